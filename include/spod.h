@@ -1,0 +1,191 @@
+/*
+ * spod.h - C ABI of the MI355X (gfx950) SPOD library, libspod.so.
+ *
+ * Spectral proper orthogonal decomposition of a real snapshot matrix
+ * Q in R^{M x N_t} (M = nspace * nvar degrees of freedom), following the
+ * discrete SPOD of Sec. 2.3 of Rogowski et al., "Unlocking massively parallel
+ * spectral proper orthogonal decompositions in the PySPOD package":
+ *
+ *   1. remove the long-time mean of every degree of freedom (Sec. 2.1, 2.3);
+ *   2. split time into L blocks of N_f snapshots overlapping by N_overlap
+ *      (eq. (blocks)), window them and take the DFT of every block in time
+ *      (eq. (blocks-ft)), regrouped per frequency (eq. (blocks-k));
+ *   3. form the weighted inner-product matrix M_k = Qhat_k^* W Qhat_k of the
+ *      method of snapshots (eq. (spod-discrete-snapshots));
+ *   4. solve M_k Psi_k = Psi_k Lambda_k for every frequency;
+ *   5. build the modes Phi_k = Qhat_k Psi_k Lambda_k^{-1/2}.
+ *
+ * Conventions (where the paper is silent; all are fixed by this library):
+ *   - DOF index m = v * nspace + s; q is row-major [M][nt] (time contiguous).
+ *   - nblocks L = floor((nt - noverlap) / (nfft - noverlap)); block l covers
+ *     snapshots [l*s, l*s + nfft), s = nfft - noverlap; later snapshots only
+ *     enter the mean.
+ *   - nfreq K = nfft/2 + 1 one-sided bins k = 0..nfft/2, DFT sign e^{-2 pi i kn/N}.
+ *   - Qhat is scaled by kappa = 1/sqrt((L-1) * sum_n w[n]^2): this folds the
+ *     1/(L-1) of eq. (csd-discrete) into Qhat so that the eigenvalues are those
+ *     of Chat_k W and the modes satisfy Phi_k^* W Phi_k = I.
+ *   - Eigenvalues descending; each eigenvector's entry of largest modulus
+ *     (lowest index on ties) is real and positive.
+ *   - Complex arrays are interleaved (re, im).  qhat and phi are complex128
+ *     under SPOD_PREC_FP64 and complex64 otherwise; gram, psi and lam are
+ *     always float64.
+ *
+ * Ownership and threading:
+ *   - The caller allocates every device buffer, including the workspace
+ *     (size from spod_plan_query).  The plan owns only its device copies of
+ *     the window, the weights and the twiddle tables, made synchronously in
+ *     spod_plan_create on the current device and freed by spod_plan_destroy.
+ *   - Host arrays passed in are read during the call only.
+ *   - Options and precision may be changed only before the first stage call;
+ *     after that the plan is read-only and may be shared by concurrent streams,
+ *     each with its own workspace.
+ *   - Every stage call is asynchronous on `stream` (a hipStream_t; NULL is the
+ *     default stream): it validates synchronously, enqueues, and returns.
+ *
+ * Errors: a negative spod_status is returned synchronously and nothing is
+ * enqueued.  Launch failures return SPOD_ERR_HIP.  Device-side numeric
+ * outcomes (Jacobi convergence, valid-mode counts) are written to the `info`
+ * and `n_valid` arrays, readable after the stream is synchronised.
+ * spod_last_error() returns a thread-local description of the last failure.
+ * Nothing throws across this interface.
+ */
+#ifndef SPOD_H
+#define SPOD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct spod_plan_s* spod_plan;
+typedef void* spod_stream; /* a hipStream_t */
+
+typedef enum {
+  SPOD_OK = 0,
+  SPOD_ERR_INVALID_ARG = -1, /* bad size, pointer, dtype, window or weights        */
+  SPOD_ERR_UNSUPPORTED = -2, /* valid SPOD but not implemented here (e.g. nfft)    */
+  SPOD_ERR_ALLOC = -3,       /* device or host allocation failed                   */
+  SPOD_ERR_HIP = -4,         /* HIP runtime error (no device, launch failure, ...) */
+  SPOD_ERR_NUMERIC = -5,     /* non-finite values where finite ones are required   */
+  SPOD_ERR_WORKSPACE = -6    /* workspace missing or smaller than required         */
+} spod_status;
+
+typedef enum { SPOD_F32 = 0, SPOD_F64 = 1 } spod_dtype; /* stored type of q and g_q */
+
+typedef enum {
+  SPOD_PREC_FP64 = 0,   /* FP64 transform, Gram and modes; complex128 qhat/phi            */
+  SPOD_PREC_FP32 = 1,   /* FP32 transform; Gram on FP32 MFMA, each 4-wide partial sum
+                           added into FP64; FP32 modes; complex64 qhat/phi               */
+  SPOD_PREC_BF16X4 = 2, /* FP32 transform; Gram on BF16 MFMA with a two-term split
+                           y = hi + lo and all four products (hi hi, hi lo, lo hi, lo lo),
+                           FP32 partial sums added into FP64; FP32 modes; complex64       */
+  SPOD_PREC_FP16X4 = 3  /* as BF16X4 with FP16 operands scaled per frequency            */
+} spod_precision;
+
+typedef enum {
+  SPOD_OPT_MAX_SWEEPS = 0, /* Jacobi sweep cap (default 40; 0 forces non-convergence)   */
+  SPOD_OPT_GRAM_SPLIT = 1, /* slices of M per frequency in the Gram (0 = automatic)     */
+  SPOD_OPT_FFT_TILE = 2    /* degrees of freedom per transform workgroup (0 = automatic) */
+} spod_option;
+
+/* Create a plan.  Follows the problem statement of Sec. 2.3: Q is M x N_t with
+ * M = nspace * nvar (eq. (data-matrix)); blocks of nfft snapshots overlapping by
+ * noverlap (eq. (blocks)).
+ *   window  : host[nfft] or NULL for the periodic Hann window
+ *             w[n] = 1/2 - 1/2 cos(2 pi n / nfft); finite, sum w^2 > 0.
+ *   weights : host[nspace*nvar] diagonal of W (the spatial weighting of the
+ *             inner product, eq. (innerprod_spacetime)) or NULL for 1/M each;
+ *             finite, >= 0, not all zero.
+ * Returns SPOD_ERR_INVALID_ARG for nspace, nvar < 1; nfft < 2; noverlap outside
+ * [0, nfft); nt < nfft; L < 2; a bad window or weights; out == NULL.
+ * Returns SPOD_ERR_UNSUPPORTED for nfft not a power of two in [8, 1024].
+ * Validation happens before any HIP call. */
+spod_status spod_plan_create(int64_t nspace, int64_t nvar, int64_t nt, int64_t nfft,
+                             int64_t noverlap, const double* window, const double* weights,
+                             spod_plan* out);
+
+/* Shape of a problem without creating a plan (host only, no HIP call). */
+spod_status spod_shape(int64_t nt, int64_t nfft, int64_t noverlap, int64_t* nblocks,
+                       int64_t* nfreq);
+
+/* Arithmetic used by the stages (default SPOD_PREC_FP64).  Only before the first
+ * stage call; SPOD_ERR_INVALID_ARG afterwards or for an unknown value. */
+spod_status spod_plan_set_precision(spod_plan plan, spod_precision prec);
+
+/* Tuning / test options (see spod_option); same timing rule as the precision. */
+spod_status spod_plan_set_option(spod_plan plan, spod_option opt, int64_t value);
+
+/* nblocks L, nfreq K and the workspace size (bytes) that every stage call of
+ * this plan accepts.  Any output pointer may be NULL. */
+spod_status spod_plan_query(spod_plan plan, int64_t* nblocks, int64_t* nfreq,
+                            size_t* workspace_bytes);
+
+/* Steps 1-2 (Sec. 2.3; eqs. (blocks), (blocks-ft), (blocks-k); step 2 of the
+ * algorithm of Sec. 3.1): temporal mean, windowed DFT of every block.
+ *   q     : device [M][nt] of `dtype`.
+ *   qhat  : device [K][L][M] complex (complex128 for SPOD_PREC_FP64, else
+ *           complex64); qhat[k][l][m] = kappa * sum_n w[n](q[m][l s + n] - mean[m])
+ *           e^{-2 pi i k n / nfft}.
+ *   mean  : device [M] float64 or NULL; the long-time mean, accumulated in FP64.
+ *   ws    : device workspace of ws_bytes >= spod_plan_query's size. */
+spod_status spod_blocks_fft(spod_plan plan, const void* q, spod_dtype dtype, void* qhat,
+                            double* mean, void* ws, size_t ws_bytes, spod_stream stream);
+
+/* Steps 3-4 (eq. (spod-discrete-snapshots); Sec. 3.1 steps 3-4): the weighted
+ * inner product of the method of snapshots for every frequency,
+ *   gram[k][i][j] = sum_m conj(qhat[k][i][m]) W_m qhat[k][j][m]
+ * (complex128 [K][L][L], Hermitian).  The sum over m, which the paper reduces
+ * across MPI ranks, is split across workgroups and combined in FP64. */
+spod_status spod_csd(spod_plan plan, const void* qhat, void* gram, void* ws, size_t ws_bytes,
+                     spod_stream stream);
+
+/* Step 5 (eq. (spod-discrete-snapshots); Sec. 3.1 step 5): eigendecomposition
+ * of every Hermitian gram[k] by cyclic Jacobi in FP64.
+ *   lam  : device [K][L] float64, descending.
+ *   psi  : device [K][L][L] complex128; psi[k][i][j] = component i of
+ *          eigenvector j (unit 2-norm, phase convention above).
+ *   info : device [K] int32 or NULL: > 0 converged, the number of sweeps
+ *          used (the last one made no rotation); <= 0 not converged after
+ *          -info sweeps (the cap set with SPOD_OPT_MAX_SWEEPS was reached). */
+spod_status spod_eig(spod_plan plan, const void* gram, double* lam, void* psi, int32_t* info,
+                     void* ws, size_t ws_bytes, spod_stream stream);
+
+/* Modes (eq. (spod-discrete-snapshots)): for j < n_modes (1 <= n_modes <= L)
+ *   phi[k][j][m] = sum_l qhat[k][l][m] psi[k][l][j] / sqrt(lam[k][j])
+ * when lam[k][0] > 0 and lam[k][j] > eps * lam[k][0] (eps = 1e-12 for
+ * SPOD_PREC_FP64, 1e-6 otherwise); otherwise phi[k][j][:] = 0.
+ *   phi     : device [K][n_modes][M], complex type of qhat.
+ *   n_valid : device [K] int32 or NULL: number of valid modes per frequency. */
+spod_status spod_modes(spod_plan plan, const void* qhat, const double* lam, const void* psi,
+                       int64_t n_modes, void* phi, int32_t* n_valid, void* ws, size_t ws_bytes,
+                       spod_stream stream);
+
+/* Adjoint of steps 1-5 (not in the paper): given the gradients of a real loss
+ * with respect to lam (g_lam, device [K][L] float64, or NULL) and phi (g_phi,
+ * device [K][n_modes][M] in phi's complex type, PyTorch convention
+ * dE/dRe + i dE/dIm, or NULL), writes g_q = dE/dq (device [M][nt] of `dtype`).
+ * lam and psi are the outputs of spod_eig for the same q.  The Fourier blocks
+ * are recomputed from q rather than stored.  Eigenvector derivatives use the
+ * distinct-eigenvalue formula (pairs closer than 1e-12 relative are dropped)
+ * and assume a loss invariant to eigenvector phases. */
+spod_status spod_backward(spod_plan plan, const void* q, spod_dtype dtype, const double* lam,
+                          const void* psi, const double* g_lam, const void* g_phi,
+                          int64_t n_modes, void* g_q, void* ws, size_t ws_bytes,
+                          spod_stream stream);
+
+/* Free the plan's device copies.  NULL-safe.  Synchronises the plan's device. */
+void spod_plan_destroy(spod_plan plan);
+
+/* Static description of a status code. */
+const char* spod_status_string(spod_status status);
+
+/* Thread-local description of the last non-OK status returned on this thread. */
+const char* spod_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPOD_H */

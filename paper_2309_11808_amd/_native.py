@@ -1,0 +1,72 @@
+"""ctypes loader for libspod.so (the C ABI declared in include/spod.h).
+
+Importing this module never builds anything and never falls back to another
+implementation: if the shared library is missing the import fails with a
+message that says how to build it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libspod.so")
+
+SPOD_OK = 0
+SPOD_ERR_INVALID_ARG = -1
+SPOD_ERR_UNSUPPORTED = -2
+SPOD_ERR_ALLOC = -3
+SPOD_ERR_HIP = -4
+SPOD_ERR_NUMERIC = -5
+SPOD_ERR_WORKSPACE = -6
+
+SPOD_F32 = 0
+SPOD_F64 = 1
+
+SPOD_PREC_FP64 = 0
+SPOD_PREC_FP32 = 1
+SPOD_PREC_BF16X4 = 2
+SPOD_PREC_FP16X4 = 3
+
+SPOD_OPT_MAX_SWEEPS = 0
+SPOD_OPT_GRAM_SPLIT = 1
+SPOD_OPT_FFT_TILE = 2
+
+_i64 = C.c_int64
+_p = C.c_void_p
+_sz = C.c_size_t
+
+# name -> (restype, argtypes); exactly the functions of include/spod.h
+SIGNATURES = {
+    "spod_plan_create": (C.c_int, [_i64, _i64, _i64, _i64, _i64, _p, _p, C.POINTER(_p)]),
+    "spod_shape": (C.c_int, [_i64, _i64, _i64, C.POINTER(_i64), C.POINTER(_i64)]),
+    "spod_plan_set_precision": (C.c_int, [_p, C.c_int]),
+    "spod_plan_set_option": (C.c_int, [_p, C.c_int, _i64]),
+    "spod_plan_query": (C.c_int, [_p, C.POINTER(_i64), C.POINTER(_i64), C.POINTER(_sz)]),
+    "spod_blocks_fft": (C.c_int, [_p, _p, C.c_int, _p, _p, _p, _sz, _p]),
+    "spod_csd": (C.c_int, [_p, _p, _p, _p, _sz, _p]),
+    "spod_eig": (C.c_int, [_p, _p, _p, _p, _p, _p, _sz, _p]),
+    "spod_modes": (C.c_int, [_p, _p, _p, _p, _i64, _p, _p, _p, _sz, _p]),
+    "spod_backward": (C.c_int, [_p, _p, C.c_int, _p, _p, _p, _p, _i64, _p, _p, _sz, _p]),
+    "spod_plan_destroy": (None, [_p]),
+    "spod_status_string": (C.c_char_p, [C.c_int]),
+    "spod_last_error": (C.c_char_p, []),
+}
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(
+            f"libspod.so not found at {path}; build it with "
+            "`python -m paper_2309_11808_amd.build` (needs ROCm hipcc)")
+    lib = C.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+class SpodError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(message)
+        self.status = status

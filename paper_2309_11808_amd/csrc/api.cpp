@@ -1,0 +1,339 @@
+// extern "C" entry points of libspod: validation, plan lifetime, dispatch.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace spod {
+
+static thread_local std::string g_last_error;
+
+spod_status fail(spod_status s, const std::string& msg) {
+  g_last_error = std::string(spod_status_string(s)) + ": " + msg;
+  return s;
+}
+
+spod_status hip_fail(hipError_t e, const char* where) {
+  return fail(SPOD_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+bool is_complex128(const Plan& p) { return p.prec == SPOD_PREC_FP64; }
+
+static int64_t auto_gram_split(const Plan& p) {
+  if (p.gram_split_opt > 0) return p.gram_split_opt;
+  // enough workgroups to fill 256 CUs several times over, but keep at least
+  // ~2048 degrees of freedom per slice so the partial sums stay cheap
+  int64_t s = (2048 + p.nfreq - 1) / p.nfreq;
+  int64_t cap = p.M / 2048;
+  if (cap < 1) cap = 1;
+  if (s > cap) s = cap;
+  if (s < 1) s = 1;
+  return s;
+}
+
+static void derive(Plan& p) {
+  p.gram_dim = (int)(((2 * p.nblocks) + 15) / 16 * 16);
+  p.gram_split = (int)auto_gram_split(p);
+  p.ws_bytes = workspace_bytes(p);
+}
+
+size_t workspace_bytes(const Plan& p) {
+  size_t w = fft_workspace(p);
+  size_t a = csd_workspace(p);
+  size_t b = backward_workspace(p);
+  if (a > w) w = a;
+  if (b > w) w = b;
+  return (w + 255) / 256 * 256;
+}
+
+void freeze(Plan& p) { p.frozen = true; }
+
+static bool is_pow2(int64_t n) { return n > 0 && (n & (n - 1)) == 0; }
+
+static spod_status validate_shape(int64_t nt, int64_t nfft, int64_t noverlap, int64_t* L,
+                                  int64_t* K) {
+  if (nfft < 2) return fail(SPOD_ERR_INVALID_ARG, "nfft must be >= 2");
+  if (noverlap < 0 || noverlap >= nfft)
+    return fail(SPOD_ERR_INVALID_ARG, "noverlap must be in [0, nfft)");
+  if (nt < nfft) return fail(SPOD_ERR_INVALID_ARG, "nt must be >= nfft");
+  int64_t l = (nt - noverlap) / (nfft - noverlap);
+  if (l < 2) return fail(SPOD_ERR_INVALID_ARG, "fewer than 2 blocks (L-1 normalisation)");
+  if (L) *L = l;
+  if (K) *K = nfft / 2 + 1;
+  return SPOD_OK;
+}
+
+}  // namespace spod
+
+using namespace spod;
+
+extern "C" {
+
+const char* spod_status_string(spod_status s) {
+  switch (s) {
+    case SPOD_OK: return "SPOD_OK";
+    case SPOD_ERR_INVALID_ARG: return "SPOD_ERR_INVALID_ARG";
+    case SPOD_ERR_UNSUPPORTED: return "SPOD_ERR_UNSUPPORTED";
+    case SPOD_ERR_ALLOC: return "SPOD_ERR_ALLOC";
+    case SPOD_ERR_HIP: return "SPOD_ERR_HIP";
+    case SPOD_ERR_NUMERIC: return "SPOD_ERR_NUMERIC";
+    case SPOD_ERR_WORKSPACE: return "SPOD_ERR_WORKSPACE";
+  }
+  return "SPOD_ERR_UNKNOWN";
+}
+
+const char* spod_last_error(void) { return g_last_error.c_str(); }
+
+spod_status spod_shape(int64_t nt, int64_t nfft, int64_t noverlap, int64_t* nblocks,
+                       int64_t* nfreq) {
+  return validate_shape(nt, nfft, noverlap, nblocks, nfreq);
+}
+
+void spod_plan_destroy(spod_plan plan) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p) return;
+  int cur = 0;
+  if (hipGetDevice(&cur) == hipSuccess && cur != p->device) (void)hipSetDevice(p->device);
+  (void)hipDeviceSynchronize();
+  void* bufs[] = {p->d_window, p->d_window32, p->d_weights, p->d_sqrtw,
+                  p->d_sqrtw32, p->d_tw64, p->d_tw32};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  if (cur != p->device) (void)hipSetDevice(cur);
+  delete p;
+}
+
+spod_status spod_plan_create(int64_t nspace, int64_t nvar, int64_t nt, int64_t nfft,
+                             int64_t noverlap, const double* window, const double* weights,
+                             spod_plan* out) {
+  if (!out) return fail(SPOD_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (nspace < 1 || nvar < 1) return fail(SPOD_ERR_INVALID_ARG, "nspace and nvar must be >= 1");
+  if (nspace > (int64_t(1) << 40) / nvar) return fail(SPOD_ERR_INVALID_ARG, "M too large");
+  int64_t L = 0, K = 0;
+  spod_status st = validate_shape(nt, nfft, noverlap, &L, &K);
+  if (st != SPOD_OK) return st;
+  const int64_t M = nspace * nvar;
+
+  // host copies of window and weights, validated before any HIP call
+  std::vector<double> w(nfft), W(M);
+  double sw2 = 0.0;
+  for (int64_t n = 0; n < nfft; ++n) {
+    double v = window ? window[n]
+                      : (double)(0.5L - 0.5L * cosl(2.0L * 3.14159265358979323846264338327950288L *
+                                                    (long double)n / (long double)nfft));
+    if (!std::isfinite(v)) return fail(SPOD_ERR_INVALID_ARG, "window has a non-finite value");
+    w[n] = v;
+    sw2 += v * v;
+  }
+  if (!(sw2 > 0.0) || !std::isfinite(sw2)) return fail(SPOD_ERR_INVALID_ARG, "window energy is zero");
+  bool any = false;
+  for (int64_t m = 0; m < M; ++m) {
+    double v = weights ? weights[m] : 1.0 / (double)M;
+    if (!std::isfinite(v) || v < 0.0)
+      return fail(SPOD_ERR_INVALID_ARG, "weights must be finite and >= 0");
+    any |= v > 0.0;
+    W[m] = v;
+  }
+  if (!any) return fail(SPOD_ERR_INVALID_ARG, "weights are all zero");
+  if (!is_pow2(nfft) || nfft < 8 || nfft > 1024)
+    return fail(SPOD_ERR_UNSUPPORTED, "nfft must be a power of two in [8, 1024]");
+
+  Plan* p = new (std::nothrow) Plan();
+  if (!p) return fail(SPOD_ERR_ALLOC, "plan");
+  p->nspace = nspace;
+  p->nvar = nvar;
+  p->M = M;
+  p->nt = nt;
+  p->nfft = nfft;
+  p->noverlap = noverlap;
+  p->step = nfft - noverlap;
+  p->nblocks = L;
+  p->nfreq = K;
+  p->kappa = 1.0 / std::sqrt((double)(L - 1) * sw2);
+  derive(*p);
+
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e, "hipGetDevice");
+  }
+  // twiddles e^{-2 pi i j / N}, computed in long double and rounded once
+  std::vector<double2> tw(nfft);
+  std::vector<float2> tw32(nfft);
+  std::vector<float> w32(nfft), sq32(M);
+  std::vector<double> sq(M);
+  for (int64_t j = 0; j < nfft; ++j) {
+    long double a = 2.0L * 3.14159265358979323846264338327950288L * (long double)j / (long double)nfft;
+    tw[j] = make_double2((double)cosl(a), (double)-sinl(a));
+    tw32[j] = make_float2((float)cosl(a), (float)-sinl(a));
+    w32[j] = (float)w[j];
+  }
+  for (int64_t m = 0; m < M; ++m) {
+    sq[m] = std::sqrt(W[m]);
+    sq32[m] = (float)sq[m];
+  }
+  struct Up { void** dst; const void* src; size_t bytes; } ups[] = {
+      {(void**)&p->d_window, w.data(), sizeof(double) * nfft},
+      {(void**)&p->d_window32, w32.data(), sizeof(float) * nfft},
+      {(void**)&p->d_weights, W.data(), sizeof(double) * M},
+      {(void**)&p->d_sqrtw, sq.data(), sizeof(double) * M},
+      {(void**)&p->d_sqrtw32, sq32.data(), sizeof(float) * M},
+      {(void**)&p->d_tw64, tw.data(), sizeof(double2) * nfft},
+      {(void**)&p->d_tw32, tw32.data(), sizeof(float2) * nfft},
+  };
+  for (auto& u : ups) {
+    e = hipMalloc(u.dst, u.bytes);
+    if (e != hipSuccess) {
+      spod_plan_destroy(reinterpret_cast<spod_plan>(p));
+      return e == hipErrorOutOfMemory ? fail(SPOD_ERR_ALLOC, "plan tables")
+                                      : hip_fail(e, "hipMalloc");
+    }
+    e = hipMemcpy(*u.dst, u.src, u.bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      spod_plan_destroy(reinterpret_cast<spod_plan>(p));
+      return hip_fail(e, "hipMemcpy");
+    }
+  }
+  *out = reinterpret_cast<spod_plan>(p);
+  return SPOD_OK;
+}
+
+spod_status spod_plan_set_precision(spod_plan plan, spod_precision prec) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p) return fail(SPOD_ERR_INVALID_ARG, "plan is NULL");
+  if (p->frozen) return fail(SPOD_ERR_INVALID_ARG, "plan already used");
+  if (prec != SPOD_PREC_FP64 && prec != SPOD_PREC_FP32 && prec != SPOD_PREC_BF16X4 &&
+      prec != SPOD_PREC_FP16X4)
+    return fail(SPOD_ERR_INVALID_ARG, "unknown precision");
+  p->prec = prec;
+  derive(*p);
+  return SPOD_OK;
+}
+
+spod_status spod_plan_set_option(spod_plan plan, spod_option opt, int64_t value) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p) return fail(SPOD_ERR_INVALID_ARG, "plan is NULL");
+  if (p->frozen) return fail(SPOD_ERR_INVALID_ARG, "plan already used");
+  switch (opt) {
+    case SPOD_OPT_MAX_SWEEPS:
+      if (value < 0 || value > 1000) return fail(SPOD_ERR_INVALID_ARG, "max sweeps in [0, 1000]");
+      p->max_sweeps = (int)value;
+      break;
+    case SPOD_OPT_GRAM_SPLIT:
+      if (value < 0 || value > 65536) return fail(SPOD_ERR_INVALID_ARG, "gram split in [0, 65536]");
+      p->gram_split_opt = value;
+      break;
+    case SPOD_OPT_FFT_TILE:
+      if (value != 0 && value != 16 && value != 32 && value != 64)
+        return fail(SPOD_ERR_INVALID_ARG, "fft tile must be 0, 16, 32 or 64");
+      p->fft_tile_opt = value;
+      break;
+    default:
+      return fail(SPOD_ERR_INVALID_ARG, "unknown option");
+  }
+  derive(*p);
+  return SPOD_OK;
+}
+
+spod_status spod_plan_query(spod_plan plan, int64_t* nblocks, int64_t* nfreq,
+                            size_t* workspace) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p) return fail(SPOD_ERR_INVALID_ARG, "plan is NULL");
+  if (nblocks) *nblocks = p->nblocks;
+  if (nfreq) *nfreq = p->nfreq;
+  if (workspace) *workspace = p->ws_bytes;
+  return SPOD_OK;
+}
+
+static spod_status check_ws(const Plan& p, void* ws, size_t ws_bytes, size_t need) {
+  if (need == 0) return SPOD_OK;
+  if (!ws || ws_bytes < need)
+    return fail(SPOD_ERR_WORKSPACE, "workspace of " + std::to_string(need) + " bytes required");
+  (void)p;
+  return SPOD_OK;
+}
+
+static spod_status enter(Plan* p) {
+  if (!p) return fail(SPOD_ERR_INVALID_ARG, "plan is NULL");
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (cur != p->device) return fail(SPOD_ERR_INVALID_ARG, "plan belongs to another device");
+  freeze(*p);
+  return SPOD_OK;
+}
+
+spod_status spod_blocks_fft(spod_plan plan, const void* q, spod_dtype dtype, void* qhat,
+                            double* mean, void* ws, size_t ws_bytes, spod_stream stream) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  spod_status st = enter(p);
+  if (st != SPOD_OK) return st;
+  if (!q || !qhat) return fail(SPOD_ERR_INVALID_ARG, "q and qhat are required");
+  if (dtype != SPOD_F32 && dtype != SPOD_F64) return fail(SPOD_ERR_INVALID_ARG, "dtype");
+  if (!mean) {
+    st = check_ws(*p, ws, ws_bytes, fft_workspace(*p));
+    if (st != SPOD_OK) return st;
+  }
+  return launch_blocks_fft(*p, q, dtype, qhat, mean, ws, (hipStream_t)stream);
+}
+
+spod_status spod_csd(spod_plan plan, const void* qhat, void* gram, void* ws, size_t ws_bytes,
+                     spod_stream stream) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  spod_status st = enter(p);
+  if (st != SPOD_OK) return st;
+  if (!qhat || !gram) return fail(SPOD_ERR_INVALID_ARG, "qhat and gram are required");
+  st = check_ws(*p, ws, ws_bytes, csd_workspace(*p));
+  if (st != SPOD_OK) return st;
+  return launch_csd(*p, qhat, gram, ws, (hipStream_t)stream);
+}
+
+spod_status spod_eig(spod_plan plan, const void* gram, double* lam, void* psi, int32_t* info,
+                     void* ws, size_t ws_bytes, spod_stream stream) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  spod_status st = enter(p);
+  if (st != SPOD_OK) return st;
+  if (!gram || !lam || !psi) return fail(SPOD_ERR_INVALID_ARG, "gram, lam and psi are required");
+  (void)ws_bytes;
+  return launch_eig(*p, gram, lam, psi, info, ws, (hipStream_t)stream);
+}
+
+spod_status spod_modes(spod_plan plan, const void* qhat, const double* lam, const void* psi,
+                       int64_t n_modes, void* phi, int32_t* n_valid, void* ws, size_t ws_bytes,
+                       spod_stream stream) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  spod_status st = enter(p);
+  if (st != SPOD_OK) return st;
+  if (!qhat || !lam || !psi || !phi)
+    return fail(SPOD_ERR_INVALID_ARG, "qhat, lam, psi and phi are required");
+  if (n_modes < 1 || n_modes > p->nblocks)
+    return fail(SPOD_ERR_INVALID_ARG, "n_modes must be in [1, nblocks]");
+  (void)ws_bytes;
+  return launch_modes(*p, qhat, lam, psi, (int)n_modes, phi, n_valid, ws, (hipStream_t)stream);
+}
+
+spod_status spod_backward(spod_plan plan, const void* q, spod_dtype dtype, const double* lam,
+                          const void* psi, const double* g_lam, const void* g_phi,
+                          int64_t n_modes, void* g_q, void* ws, size_t ws_bytes,
+                          spod_stream stream) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  spod_status st = enter(p);
+  if (st != SPOD_OK) return st;
+  if (!q || !lam || !psi || !g_q)
+    return fail(SPOD_ERR_INVALID_ARG, "q, lam, psi and g_q are required");
+  if (dtype != SPOD_F32 && dtype != SPOD_F64) return fail(SPOD_ERR_INVALID_ARG, "dtype");
+  if (g_phi && (n_modes < 1 || n_modes > p->nblocks))
+    return fail(SPOD_ERR_INVALID_ARG, "n_modes must be in [1, nblocks]");
+  st = check_ws(*p, ws, ws_bytes, backward_workspace(*p));
+  if (st != SPOD_OK) return st;
+  return launch_backward(*p, q, dtype, lam, psi, g_lam, g_phi, g_phi ? (int)n_modes : 0, g_q, ws,
+                         (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,203 @@
+// Step 5 of SPOD (eq. (spod-discrete-snapshots); Sec. 3.1 step 5): the
+// eigendecomposition of every Hermitian L x L matrix M_k, in FP64.  The paper
+// solves these serially and redundantly on every rank; here one workgroup per
+// frequency runs a parallel two-sided complex Jacobi method entirely in LDS.
+//
+// Ordering: round-robin ("circle") pairing of n = L (rounded up to even)
+// indices, so each of the n-1 rounds of a sweep rotates n/2 disjoint planes at
+// once.  Plane (p, q) with a = A_pp, b = A_qq, c = A_pq = |c| e^{i phi} is
+// reduced by
+//     J = [[cs, sn e^{i phi}], [-sn e^{-i phi}, cs]],
+// where t = sn/cs is the smaller root of t^2 + 2 tau t - 1 = 0,
+// tau = (b - a) / (2|c|) (the symmetric Schur decomposition of the real
+// 2 x 2 matrix [[a, |c|], [|c|, b]]); afterwards A_pp = a - t|c|,
+// A_qq = b + t|c|, A_pq = 0.  A plane is skipped when
+// |c| <= tol sqrt(|a b|) (tol = 1e-15) or c == 0; the iteration stops after a
+// sweep without rotations.
+//
+// Output: eigenvalues in descending order (stable on ties), eigenvector j in
+// column j with its entry of largest modulus (lowest index on ties) made real
+// and positive.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace spod {
+
+constexpr int EIG_MAXN = 64;
+constexpr int EIG_LD = EIG_MAXN + 1;
+
+struct Rot {
+  double cs, sn, er, ei, tr, a, b;
+  int p, q, on;
+};
+
+__global__ __launch_bounds__(256) void jacobi_kernel(const double2* __restrict__ gram,
+                                                     double* __restrict__ lam,
+                                                     double2* __restrict__ psi,
+                                                     int32_t* __restrict__ info, int L,
+                                                     int max_sweeps) {
+  __shared__ double2 A[EIG_MAXN * EIG_LD];
+  __shared__ double2 V[EIG_MAXN * EIG_LD];
+  __shared__ Rot rot[EIG_MAXN / 2];
+  __shared__ int any_rot;
+  __shared__ double lsh[EIG_MAXN];
+  __shared__ int rank_of[EIG_MAXN];
+  __shared__ double2 phase[EIG_MAXN];
+  __shared__ int pivot[EIG_MAXN];
+
+  const int k = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int n = (L + 1) & ~1;             // even, includes a dummy index when L is odd
+  const int half = n / 2;
+  const double2* G = gram + (int64_t)k * L * L;
+
+  for (int idx = tid; idx < n * n; idx += blockDim.x) {
+    const int i = idx / n, j = idx % n;
+    double2 g = make_double2(0.0, 0.0);
+    if (i < L && j < L) g = G[i * L + j];
+    if (i == j) g.y = 0.0;
+    A[i * EIG_LD + j] = g;
+    V[i * EIG_LD + j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+
+  const double tol = 1e-15;
+  int sweep = 0;
+  bool converged = false;
+  for (sweep = 1; sweep <= max_sweeps; ++sweep) {
+    if (tid == 0) any_rot = 0;
+    __syncthreads();
+    for (int round = 0; round < n - 1; ++round) {
+      if (tid < half) {
+        // circle method: slot 0 fixed, slots 1..n-1 rotate by `round`
+        const int s0 = tid, s1 = n - 1 - tid;
+        const int x0 = s0 == 0 ? 0 : 1 + (s0 - 1 + round) % (n - 1);
+        const int x1 = s1 == 0 ? 0 : 1 + (s1 - 1 + round) % (n - 1);
+        const int p = x0 < x1 ? x0 : x1, q = x0 < x1 ? x1 : x0;
+        Rot r;
+        r.p = p;
+        r.q = q;
+        r.on = 0;
+        if (q < L) {
+          const double a = A[p * EIG_LD + p].x, b = A[q * EIG_LD + q].x;
+          const double2 c = A[p * EIG_LD + q];
+          const double ac = hypot(c.x, c.y);
+          if (ac > 0.0 && ac > tol * sqrt(fabs(a * b))) {
+            const double tau = (b - a) / (2.0 * ac);
+            double t;
+            if (fabs(tau) > 1e150) t = 0.5 / tau;
+            else t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            const double cs = 1.0 / sqrt(1.0 + t * t);
+            r.cs = cs;
+            r.sn = t * cs;
+            r.er = c.x / ac;
+            r.ei = c.y / ac;
+            r.tr = t * ac;
+            r.a = a;
+            r.b = b;
+            r.on = 1;
+            any_rot = 1;
+          }
+        }
+        rot[tid] = r;
+      }
+      __syncthreads();
+      // rows: A <- J^H A  (row p' = cs A_p - sn e A_q ; row q' = sn conj(e) A_p + cs A_q)
+      for (int idx = tid; idx < half * n; idx += blockDim.x) {
+        const Rot& r = rot[idx / n];
+        if (!r.on) continue;
+        const int c = idx % n;
+        const double2 ap = A[r.p * EIG_LD + c], aq = A[r.q * EIG_LD + c];
+        const double2 e = make_double2(r.er, r.ei);
+        const double2 eaq = cmul(e, aq);          // e * A_q
+        const double2 ecap = cmulc(ap, e);        // conj(e) * A_p
+        A[r.p * EIG_LD + c] = make_double2(r.cs * ap.x - r.sn * eaq.x, r.cs * ap.y - r.sn * eaq.y);
+        A[r.q * EIG_LD + c] = make_double2(r.sn * ecap.x + r.cs * aq.x, r.sn * ecap.y + r.cs * aq.y);
+      }
+      __syncthreads();
+      // columns: A <- A J and V <- V J
+      //   (col p' = cs A_p - sn conj(e) A_q ; col q' = sn e A_p + cs A_q)
+      for (int idx = tid; idx < 2 * half * n; idx += blockDim.x) {
+        const int which = idx / (half * n);
+        const int rem = idx % (half * n);
+        const Rot& r = rot[rem / n];
+        if (!r.on) continue;
+        const int row = rem % n;
+        double2* X = which == 0 ? A : V;
+        const double2 xp = X[row * EIG_LD + r.p], xq = X[row * EIG_LD + r.q];
+        const double2 e = make_double2(r.er, r.ei);
+        const double2 ecxq = cmulc(xq, e);        // conj(e) * X_q
+        const double2 exp_ = cmul(e, xp);         // e * X_p
+        X[row * EIG_LD + r.p] = make_double2(r.cs * xp.x - r.sn * ecxq.x, r.cs * xp.y - r.sn * ecxq.y);
+        X[row * EIG_LD + r.q] = make_double2(r.sn * exp_.x + r.cs * xq.x, r.sn * exp_.y + r.cs * xq.y);
+      }
+      __syncthreads();
+      if (tid < half) {
+        const Rot& r = rot[tid];
+        if (r.on) {
+          A[r.p * EIG_LD + r.q] = make_double2(0.0, 0.0);
+          A[r.q * EIG_LD + r.p] = make_double2(0.0, 0.0);
+          A[r.p * EIG_LD + r.p] = make_double2(r.a - r.tr, 0.0);
+          A[r.q * EIG_LD + r.q] = make_double2(r.b + r.tr, 0.0);
+        }
+      }
+      __syncthreads();
+    }
+    if (!any_rot) {
+      converged = true;
+      break;
+    }
+    __syncthreads();
+  }
+
+  // eigenvalues, ranks (descending, stable), phases
+  for (int i = tid; i < L; i += blockDim.x) lsh[i] = A[i * EIG_LD + i].x;
+  __syncthreads();
+  for (int i = tid; i < L; i += blockDim.x) {
+    const double li = lsh[i];
+    int r = 0;
+    for (int j = 0; j < L; ++j) {
+      const double lj = lsh[j];
+      r += (lj > li) || (lj == li && j < i);
+    }
+    rank_of[i] = r;
+    int piv = 0;
+    double best = -1.0;
+    for (int row = 0; row < L; ++row) {
+      const double2 v = V[row * EIG_LD + i];
+      const double m2 = v.x * v.x + v.y * v.y;
+      if (m2 > best) {
+        best = m2;
+        piv = row;
+      }
+    }
+    const double2 v = V[piv * EIG_LD + i];
+    const double mag = hypot(v.x, v.y);
+    phase[i] = mag > 0.0 ? make_double2(v.x / mag, -v.y / mag) : make_double2(1.0, 0.0);
+    pivot[i] = piv;
+  }
+  __syncthreads();
+  for (int i = tid; i < L; i += blockDim.x) lam[(int64_t)k * L + rank_of[i]] = lsh[i];
+  for (int idx = tid; idx < L * L; idx += blockDim.x) {
+    const int row = idx / L, i = idx % L;
+    const double2 v = V[row * EIG_LD + i];
+    // the pivot entry is written as exactly |v| (real, positive)
+    psi[((int64_t)k * L + row) * L + rank_of[i]] =
+        row == pivot[i] ? make_double2(hypot(v.x, v.y), 0.0) : cmul(v, phase[i]);
+  }
+  if (tid == 0 && info) info[k] = converged ? sweep : -(sweep - 1);
+}
+
+spod_status launch_eig(const Plan& p, const void* gram, double* lam, void* psi, int32_t* info,
+                       void* ws, hipStream_t st) {
+  (void)ws;
+  if (p.nblocks > EIG_MAXN) return fail(SPOD_ERR_UNSUPPORTED, "nblocks > 64");
+  hipLaunchKernelGGL(jacobi_kernel, dim3((unsigned)p.nfreq), dim3(256), 0, st,
+                     static_cast<const double2*>(gram), lam, static_cast<double2*>(psi), info,
+                     (int)p.nblocks, p.max_sweeps);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SPOD_OK : hip_fail(e, "jacobi_kernel");
+}
+
+}  // namespace spod

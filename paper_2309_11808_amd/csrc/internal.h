@@ -1,0 +1,98 @@
+// Internal declarations shared by the libspod sources (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "spod.h"
+
+namespace spod {
+
+// --------------------------------------------------------------------------
+// plan
+// --------------------------------------------------------------------------
+struct Plan {
+  int64_t nspace = 0, nvar = 0, M = 0, nt = 0, nfft = 0, noverlap = 0, step = 0;
+  int64_t nblocks = 0, nfreq = 0;
+  spod_precision prec = SPOD_PREC_FP64;
+  int device = 0;
+  bool frozen = false;  // set by the first stage call
+
+  double kappa = 0.0;   // 1/sqrt((L-1) sum w^2)
+
+  // options
+  int max_sweeps = 40;
+  int64_t gram_split_opt = 0;
+  int64_t fft_tile_opt = 0;
+
+  // derived launch shapes (fixed when frozen)
+  int gram_split = 1;       // slices of M per frequency
+  int gram_dim = 0;         // padded realified size (multiple of 16) >= 2L
+  size_t ws_bytes = 0;
+
+  // device copies owned by the plan
+  double* d_window = nullptr;  // [nfft]
+  float* d_window32 = nullptr; // [nfft]
+  double* d_weights = nullptr; // [M]
+  double* d_sqrtw = nullptr;   // [M]
+  float* d_sqrtw32 = nullptr;  // [M]
+  double2* d_tw64 = nullptr;   // [nfft] e^{-2 pi i j / nfft}
+  float2* d_tw32 = nullptr;    // [nfft]
+};
+
+bool is_complex128(const Plan& p);
+size_t workspace_bytes(const Plan& p);
+void freeze(Plan& p);
+
+// error reporting (thread local message)
+spod_status fail(spod_status s, const std::string& msg);
+spod_status hip_fail(hipError_t e, const char* where);
+
+// --------------------------------------------------------------------------
+// stage launchers (each returns SPOD_OK or an error, never throws)
+// --------------------------------------------------------------------------
+spod_status launch_blocks_fft(const Plan& p, const void* q, spod_dtype dtype, void* qhat,
+                              double* mean, void* ws, hipStream_t st);
+spod_status launch_csd(const Plan& p, const void* qhat, void* gram, void* ws, hipStream_t st);
+spod_status launch_eig(const Plan& p, const void* gram, double* lam, void* psi, int32_t* info,
+                       void* ws, hipStream_t st);
+spod_status launch_modes(const Plan& p, const void* qhat, const double* lam, const void* psi,
+                         int n_modes, void* phi, int32_t* n_valid, void* ws, hipStream_t st);
+spod_status launch_backward(const Plan& p, const void* q, spod_dtype dtype, const double* lam,
+                            const void* psi, const double* g_lam, const void* g_phi, int n_modes,
+                            void* g_q, void* ws, hipStream_t st);
+
+// workspace sizes of the individual stages
+size_t fft_workspace(const Plan& p);  // only used when the caller passes no mean buffer
+size_t csd_workspace(const Plan& p);
+size_t backward_workspace(const Plan& p);
+
+// --------------------------------------------------------------------------
+// small device helpers
+// --------------------------------------------------------------------------
+template <typename T> struct cpx;
+template <> struct cpx<float> { using type = float2; };
+template <> struct cpx<double> { using type = double2; };
+template <typename T> using cpx_t = typename cpx<T>::type;
+
+template <typename C>
+__device__ __forceinline__ C cadd(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
+template <typename C>
+__device__ __forceinline__ C csub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
+template <typename C>
+__device__ __forceinline__ C cmul(C a, C b) {
+  return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// a * conj(b)
+template <typename C>
+__device__ __forceinline__ C cmulc(C a, C b) {
+  return C{a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+// multiply by -i
+template <typename C>
+__device__ __forceinline__ C cmul_mi(C a) { return C{a.y, -a.x}; }
+
+}  // namespace spod

@@ -1,0 +1,193 @@
+"""Thin Python binding of libspod (include/spod.h).
+
+Argument marshalling only: every step of the SPOD path runs in the library's
+HIP kernels.  PyTorch provides device memory (output tensors are allocated
+with torch.empty when not given) and the current HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _native as N
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    global _lib
+    if _lib is None:
+        _lib = N.load()
+    return _lib
+
+
+PRECISIONS = {"fp64": N.SPOD_PREC_FP64, "fp32": N.SPOD_PREC_FP32, "bf16x4": N.SPOD_PREC_BF16X4,
+              "fp16x4": N.SPOD_PREC_FP16X4}
+
+
+def _check(status: int):
+    if status != N.SPOD_OK:
+        L = lib()
+        msg = L.spod_last_error().decode() or L.spod_status_string(status).decode()
+        raise N.SpodError(status, msg)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(device: torch.device):
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def shape(nt: int, nfft: int, noverlap: int):
+    """(nblocks, nfreq) for a problem, validated by the library (host only)."""
+    L, K = C.c_int64(), C.c_int64()
+    _check(lib().spod_shape(nt, nfft, noverlap, C.byref(L), C.byref(K)))
+    return L.value, K.value
+
+
+class Plan:
+    """A libspod plan: problem shape, window, weights, precision and options."""
+
+    def __init__(self, nspace: int, nvar: int, nt: int, nfft: int, noverlap: int, window=None,
+                 weights=None, precision: str = "fp64", options: Optional[dict] = None,
+                 device=None):
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
+            else torch.device(device)
+        self.nspace, self.nvar, self.nt, self.nfft, self.noverlap = nspace, nvar, nt, nfft, noverlap
+        self.M = nspace * nvar
+        self._win = None if window is None else np.ascontiguousarray(window, dtype=np.float64)
+        self._w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
+        if self._win is not None and self._win.shape != (nfft,):
+            raise ValueError("window must have nfft entries")
+        if self._w is not None and self._w.shape != (self.M,):
+            raise ValueError("weights must have nspace*nvar entries")
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().spod_plan_create(
+                nspace, nvar, nt, nfft, noverlap,
+                None if self._win is None else self._win.ctypes.data_as(C.c_void_p),
+                None if self._w is None else self._w.ctypes.data_as(C.c_void_p), C.byref(h)))
+        self._h = h
+        self.precision = precision
+        _check(lib().spod_plan_set_precision(self._h, PRECISIONS[precision]))
+        for k, v in (options or {}).items():
+            opt = {"max_sweeps": N.SPOD_OPT_MAX_SWEEPS, "gram_split": N.SPOD_OPT_GRAM_SPLIT,
+                   "fft_tile": N.SPOD_OPT_FFT_TILE}[k]
+            _check(lib().spod_plan_set_option(self._h, opt, int(v)))
+        L, K, ws = C.c_int64(), C.c_int64(), C.c_size_t()
+        _check(lib().spod_plan_query(self._h, C.byref(L), C.byref(K), C.byref(ws)))
+        self.nblocks, self.nfreq, self.workspace_bytes = L.value, K.value, ws.value
+        self.cdtype = torch.complex128 if precision == "fp64" else torch.complex64
+        self._ws = None
+
+    # -- lifetime -----------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().spod_plan_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- buffers ------------------------------------------------------------
+    def workspace(self) -> torch.Tensor:
+        if self._ws is None:
+            self._ws = torch.empty(max(1, self.workspace_bytes), dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def _dev(self, t: torch.Tensor, name: str, dtype, shape):
+        if t.device != self.device:
+            raise ValueError(f"{name} must be on {self.device}")
+        if t.dtype != dtype:
+            raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        return t
+
+    def _out(self, t, name, dtype, shape):
+        if t is None:
+            return torch.empty(shape, dtype=dtype, device=self.device)
+        return self._dev(t, name, dtype, shape)
+
+    def _q(self, q: torch.Tensor):
+        if q.dtype not in (torch.float32, torch.float64):
+            raise TypeError("q must be float32 or float64")
+        self._dev(q, "q", q.dtype, (self.M, self.nt))
+        return N.SPOD_F32 if q.dtype == torch.float32 else N.SPOD_F64
+
+    # -- stages -------------------------------------------------------------
+    def blocks_fft(self, q, qhat=None, mean=None, want_mean: bool = True):
+        dt = self._q(q)
+        qhat = self._out(qhat, "qhat", self.cdtype, (self.nfreq, self.nblocks, self.M))
+        if want_mean or mean is not None:
+            mean = self._out(mean, "mean", torch.float64, (self.M,))
+        ws = self.workspace()
+        _check(lib().spod_blocks_fft(self._h, _ptr(q), dt, _ptr(qhat), _ptr(mean), _ptr(ws),
+                                     ws.numel(), _stream(self.device)))
+        return qhat, mean
+
+    def csd(self, qhat, gram=None):
+        self._dev(qhat, "qhat", self.cdtype, (self.nfreq, self.nblocks, self.M))
+        gram = self._out(gram, "gram", torch.complex128, (self.nfreq, self.nblocks, self.nblocks))
+        ws = self.workspace()
+        _check(lib().spod_csd(self._h, _ptr(qhat), _ptr(gram), _ptr(ws), ws.numel(),
+                              _stream(self.device)))
+        return gram
+
+    def eig(self, gram, lam=None, psi=None, info=None):
+        L, K = self.nblocks, self.nfreq
+        self._dev(gram, "gram", torch.complex128, (K, L, L))
+        lam = self._out(lam, "lam", torch.float64, (K, L))
+        psi = self._out(psi, "psi", torch.complex128, (K, L, L))
+        info = self._out(info, "info", torch.int32, (K,))
+        ws = self.workspace()
+        _check(lib().spod_eig(self._h, _ptr(gram), _ptr(lam), _ptr(psi), _ptr(info), _ptr(ws),
+                              ws.numel(), _stream(self.device)))
+        return lam, psi, info
+
+    def modes(self, qhat, lam, psi, n_modes: int, phi=None, n_valid=None):
+        L, K = self.nblocks, self.nfreq
+        self._dev(qhat, "qhat", self.cdtype, (K, L, self.M))
+        self._dev(lam, "lam", torch.float64, (K, L))
+        self._dev(psi, "psi", torch.complex128, (K, L, L))
+        phi = self._out(phi, "phi", self.cdtype, (K, n_modes, self.M))
+        n_valid = self._out(n_valid, "n_valid", torch.int32, (K,))
+        ws = self.workspace()
+        _check(lib().spod_modes(self._h, _ptr(qhat), _ptr(lam), _ptr(psi), n_modes, _ptr(phi),
+                                _ptr(n_valid), _ptr(ws), ws.numel(), _stream(self.device)))
+        return phi, n_valid
+
+    def backward(self, q, lam, psi, g_lam=None, g_phi=None, n_modes: int = 0, g_q=None):
+        dt = self._q(q)
+        L, K = self.nblocks, self.nfreq
+        self._dev(lam, "lam", torch.float64, (K, L))
+        self._dev(psi, "psi", torch.complex128, (K, L, L))
+        if g_lam is not None:
+            self._dev(g_lam, "g_lam", torch.float64, (K, L))
+        if g_phi is not None:
+            self._dev(g_phi, "g_phi", self.cdtype, (K, n_modes, self.M))
+        g_q = self._out(g_q, "g_q", q.dtype, (self.M, self.nt))
+        ws = self.workspace()
+        _check(lib().spod_backward(self._h, _ptr(q), dt, _ptr(lam), _ptr(psi), _ptr(g_lam),
+                                   _ptr(g_phi), n_modes, _ptr(g_q), _ptr(ws), ws.numel(),
+                                   _stream(self.device)))
+        return g_q
+
+    def forward(self, q, n_modes: int = 5):
+        """All stages: returns dict(mean, qhat, gram, lam, psi, info, phi, n_valid)."""
+        qhat, mean = self.blocks_fft(q)
+        gram = self.csd(qhat)
+        lam, psi, info = self.eig(gram)
+        phi, n_valid = self.modes(qhat, lam, psi, n_modes)
+        return {"mean": mean, "qhat": qhat, "gram": gram, "lam": lam, "psi": psi, "info": info,
+                "phi": phi, "n_valid": n_valid}

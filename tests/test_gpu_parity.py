@@ -1,0 +1,302 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle, stage by
+stage and end to end, on seeded inputs (MI355X only)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from synth import fields
+from tests import parity as PT
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible: the gpu tests need an MI355X")
+    import paper_2309_11808_amd  # noqa: F401  (fails loudly when libspod.so is missing)
+    yield
+
+
+def _plan(prob, precision="fp64", window=None, **opt):
+    from paper_2309_11808_amd import Plan
+    return Plan(prob.nspace, prob.nvar, prob.nt, prob.nfft, prob.noverlap, window=window,
+                weights=prob.weights, precision=precision, options=opt or None)
+
+
+def _dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x)).cuda()
+
+
+def _rand_problem(M, nt, nfft, nov, seed, dtype=torch.float64, offset=0.0):
+    p = fields.random_rows(M, nt, nfft, nov, seed=seed, offset=offset, dtype=dtype)
+    return p
+
+
+# ---------------------------------------------------------------------------
+# stage 1-2: mean and Fourier blocks
+# ---------------------------------------------------------------------------
+FFT_CASES = [
+    # nfft, noverlap, M, extra samples, input dtype, offset
+    (8, 4, 37, 3, torch.float64, 0.0),
+    (16, 8, 65, 0, torch.float64, 5.0),
+    (32, 0, 33, 7, torch.float64, 0.0),
+    (64, 32, 129, 11, torch.float64, 100.0),
+    (64, 48, 31, 5, torch.float64, 0.0),
+    (128, 64, 70, 0, torch.float32, 3.0),
+    (128, 96, 17, 9, torch.float64, 0.0),
+    (256, 128, 97, 13, torch.float32, 0.0),
+    (256, 0, 40, 1, torch.float64, 0.0),
+    (512, 256, 67, 100, torch.float32, 10.0),
+    (512, 128, 33, 0, torch.float64, 0.0),
+    (1024, 512, 35, 17, torch.float64, 1.0),
+    (1024, 512, 19, 0, torch.float32, 0.0),
+]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x4"])
+@pytest.mark.parametrize("nfft,nov,M,extra,dtype,offset", FFT_CASES)
+def test_blocks_fft_matches_oracle(prec, nfft, nov, M, extra, dtype, offset):
+    L = 3 + (nfft % 5)
+    nt = (L - 1) * (nfft - nov) + nfft + extra
+    p = _rand_problem(M, nt, nfft, nov, seed=nfft + M, dtype=dtype, offset=offset)
+    rng = np.random.Generator(np.random.PCG64(nfft))
+    window = None if nfft % 3 else rng.uniform(0.1, 1.0, nfft)      # some custom windows
+    plan = _plan(p, prec, window=window)
+    qhat, mean = plan.blocks_fft(p.q.cuda())
+    torch.cuda.synchronize()
+    q64 = p.q.numpy().astype(np.float64)
+    ora = O.fourier_blocks(q64, nfft, nov, window)
+    np.testing.assert_allclose(mean.cpu().numpy(), O.temporal_mean(q64), rtol=1e-14,
+                               atol=1e-15 * (1 + abs(offset)))
+    rtol = 2e-13 if prec == "fp64" else 4e-6
+    PT.check_qhat(qhat, ora, rtol)
+
+
+def test_blocks_fft_without_mean_buffer_uses_workspace():
+    p = _rand_problem(50, 600, 64, 32, seed=3)
+    plan = _plan(p)
+    qhat, _ = plan.blocks_fft(p.q.cuda(), want_mean=False)
+    torch.cuda.synchronize()
+    PT.check_qhat(qhat, O.fourier_blocks(p.q.numpy(), 64, 32), 2e-13)
+
+
+# ---------------------------------------------------------------------------
+# stages 3-4: weighted Gram (fed with the oracle's qhat)
+# ---------------------------------------------------------------------------
+GRAM_TOL = {"fp64": 1e-13, "fp32": 3e-6, "bf16x4": 3e-5, "fp16x4": 2e-6}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x4", "fp16x4"])
+@pytest.mark.parametrize("L,M", [(2, 1), (7, 300), (15, 1024), (16, 77), (31, 5000), (32, 2049),
+                                 (33, 130), (47, 700), (63, 257), (64, 64)])
+def test_csd_matches_oracle(prec, L, M):
+    nfft, nov = 16, 8
+    nt = (L - 1) * 8 + 16
+    p = _rand_problem(M, nt, nfft, nov, seed=L * 7 + M)
+    plan = _plan(p, prec, gram_split=3 if M > 1000 else 0)
+    qh = O.fourier_blocks(p.q.numpy(), nfft, nov)
+    if prec != "fp64":
+        qh = qh.astype(np.complex64)
+    gram = plan.csd(_dev(np.ascontiguousarray(qh)))
+    torch.cuda.synchronize()
+    ora = O.gram(qh.astype(np.complex128), p.weights)
+    PT.check_gram(gram, ora, GRAM_TOL[prec])
+
+
+# ---------------------------------------------------------------------------
+# stage 5: eigendecomposition (fed with the oracle's Gram)
+# ---------------------------------------------------------------------------
+def _herm_batch(L, K, seed, kind):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for k in range(K):
+        if kind == "psd":
+            B = rng.standard_normal((L, 2 * L)) + 1j * rng.standard_normal((L, 2 * L))
+            out.append(B @ B.conj().T)
+        elif kind == "lowrank":
+            r = max(1, L // 4)
+            B = rng.standard_normal((L, r)) + 1j * rng.standard_normal((L, r))
+            out.append(B @ B.conj().T)
+        elif kind == "graded":
+            U, _ = np.linalg.qr(rng.standard_normal((L, L)) + 1j * rng.standard_normal((L, L)))
+            out.append(U @ np.diag(10.0 ** np.linspace(0, -10, L)) @ U.conj().T)
+        elif kind == "degenerate":
+            U, _ = np.linalg.qr(rng.standard_normal((L, L)) + 1j * rng.standard_normal((L, L)))
+            d = np.repeat(np.arange(L // 2 + 1, 0, -1), 2)[:L].astype(float)
+            out.append(U @ np.diag(d) @ U.conj().T)
+        elif kind == "diagonal":
+            out.append(np.diag(rng.uniform(0, 1, L)).astype(complex))
+        elif kind == "zero":
+            out.append(np.zeros((L, L), complex))
+    A = np.stack(out)
+    return 0.5 * (A + np.conj(np.transpose(A, (0, 2, 1))))
+
+
+@pytest.mark.parametrize("L", [2, 3, 8, 15, 31, 32, 33, 63, 64])
+@pytest.mark.parametrize("kind", ["psd", "lowrank", "graded", "degenerate", "diagonal", "zero"])
+def test_eig_matches_oracle(L, kind):
+    nfft = 16
+    nt = (L - 1) * 8 + 16
+    p = _rand_problem(4, nt, nfft, 8, seed=1)
+    plan = _plan(p)
+    assert plan.nblocks == L
+    K = plan.nfreq
+    A = _herm_batch(L, K, seed=L, kind=kind)
+    lam, psi, info = plan.eig(_dev(A))
+    torch.cuda.synchronize()
+    lo, Vo, sw = O.jacobi_eigh(A)
+    lo, psio = O.sort_and_phase(lo, Vo)
+    info = info.cpu().numpy()
+    assert (info > 0).all(), info
+    PT.check_eig(lam, lo, rtol=1e-12, floor_rel=1e-14)
+    lg, pg = lam.cpu().numpy(), psi.cpu().numpy()
+    nrm = np.linalg.norm(A, axis=(1, 2))
+    for k in range(K):
+        # residual and orthonormality of the GPU eigenvectors
+        assert np.abs(A[k] @ pg[k] - pg[k] * lg[k]).max() <= 1e-13 * max(nrm[k], 1e-300) + 1e-300
+        assert np.abs(pg[k].conj().T @ pg[k] - np.eye(L)).max() < 1e-13
+        for j in range(L):
+            if kind in ("zero",) or not PT.separated(lo[k], j, 1e-6):
+                continue
+            np.testing.assert_allclose(pg[k][:, j], psio[k][:, j], atol=1e-10)
+            piv = np.argmax(np.abs(pg[k][:, j]))
+            assert pg[k][piv, j].imag == 0 and pg[k][piv, j].real > 0
+
+
+def test_eig_sweep_cap_reports_non_convergence():
+    L = 15
+    p = _rand_problem(4, (L - 1) * 8 + 16, 16, 8, seed=1)
+    A = _herm_batch(L, 9, seed=2, kind="psd")
+    plan0 = _plan(p, max_sweeps=0)
+    _, _, info0 = plan0.eig(_dev(A))
+    plan1 = _plan(p, max_sweeps=1)
+    _, _, info1 = plan1.eig(_dev(A))
+    torch.cuda.synchronize()
+    assert (info0.cpu().numpy() == 0).all()
+    assert (info1.cpu().numpy() == -1).all()
+
+
+# ---------------------------------------------------------------------------
+# modes (fed with the oracle's qhat, lambda, psi)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", ["fp64", "bf16x4"])
+@pytest.mark.parametrize("n_modes", [1, 5, 15])
+def test_modes_match_oracle(prec, n_modes):
+    p = _rand_problem(301, 1024, 128, 64, seed=5)
+    out = O.spod(p.q.numpy(), 128, 64, weights=p.weights, n_modes=n_modes,
+                 eps=1e-12 if prec == "fp64" else 1e-6)
+    plan = _plan(p, prec)
+    qh = out["qhat"] if prec == "fp64" else out["qhat"].astype(np.complex64)
+    phi, nv = plan.modes(_dev(np.ascontiguousarray(qh)), _dev(out["lam"]), _dev(out["psi"]), n_modes)
+    torch.cuda.synchronize()
+    assert (nv.cpu().numpy() == out["n_valid"]).all()
+    ora = O.modes(qh.astype(np.complex128), out["lam"], out["psi"], n_modes,
+                  eps=1e-12 if prec == "fp64" else 1e-6)[0]
+    tol = 1e-13 if prec == "fp64" else 2e-6
+    g = phi.cpu().numpy()
+    scale = np.abs(ora).max(axis=2, keepdims=True) + 1e-300
+    err = (np.abs(g - ora) / scale).max()
+    assert err <= tol, err
+
+
+def test_modes_rank_deficient_are_zero():
+    p = fields.planted(nspace=4, nt=1024, sigma=0.0, seed=2)
+    out = O.spod(p.q.numpy(), 128, 64, weights=p.weights, n_modes=6)
+    plan = _plan(p)
+    phi, nv = plan.modes(_dev(out["qhat"]), _dev(out["lam"]), _dev(out["psi"]), 6)
+    torch.cuda.synchronize()
+    nv = nv.cpu().numpy()
+    assert (nv == out["n_valid"]).all() and nv.max() <= 4
+    PT.check_invalid_modes_zero(phi, nv)
+
+
+# ---------------------------------------------------------------------------
+# end to end
+# ---------------------------------------------------------------------------
+def _end_to_end(p, prec, n_modes=5):
+    plan = _plan(p, prec)
+    out = plan.forward(p.q.cuda(), n_modes=n_modes)
+    torch.cuda.synchronize()
+    return plan, {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def test_planted_field_fp64_end_to_end():
+    p = fields.planted(seed=1, sigma=0.1)
+    _, g = _end_to_end(p, "fp64")
+    o = O.spod(p.q.numpy(), 128, 64, weights=p.weights, n_modes=5)
+    np.testing.assert_allclose(g["mean"], o["mean"], rtol=1e-13,
+                               atol=1e-15 * np.abs(p.q.numpy()).max())
+    PT.check_qhat(g["qhat"], o["qhat"], 2e-13)
+    PT.check_gram(g["gram"], o["gram"], 1e-12)
+    assert (g["info"] > 0).all()
+    PT.check_eig(g["lam"], o["lam"], rtol=1e-10)
+    assert (g["n_valid"] == o["n_valid"]).all()
+    s, n = PT.check_modes(g["phi"], o["phi"], o["lam"], p.weights, o["n_valid"], sin_tol=1e-9,
+                          elem_tol=1e-8, rel_gap=1e-6)
+    assert n > 100
+
+
+def test_planted_field_closed_form_on_gpu():
+    """sigma = 0: lambda_1(b) = L/(L-1) a^2 N_f / 6 at the planted bins."""
+    p = fields.planted(seed=1, sigma=0.0)
+    _, g = _end_to_end(p, "fp64", n_modes=3)
+    L = 15
+    for b, a, i in zip(p.meta["bins"], p.meta["amps"], range(3)):
+        ref = L / (L - 1) * a * a * 128 / 6.0
+        assert abs(g["lam"][b, 0] / ref - 1) < 1e-12
+        assert abs(g["lam"][b + 1, 0] / (ref / 4) - 1) < 1e-12
+        phi_i = p.meta["phi"][:, i]
+        assert abs(abs(np.vdot(phi_i, p.weights * g["phi"][b, 0])) - 1) < 1e-11
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x4", "fp16x4"])
+def test_planted_field_mixed_end_to_end(prec):
+    p = fields.planted(seed=1, sigma=0.1, dtype=torch.float32)
+    _, g = _end_to_end(p, prec)
+    o = O.spod(p.q.numpy(), 128, 64, weights=p.weights, n_modes=5, eps=1e-6)
+    PT.check_eig_mixed(g["lam"], o["lam"], p.M, n=5)
+    s, n = PT.check_modes(g["phi"], o["phi"], o["lam"], p.weights, o["n_valid"], sin_tol=1e-3,
+                          elem_tol=1e-2, rel_gap=1e-3)
+    assert n > 100
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x4"])
+def test_random_rows_with_offsets_end_to_end(prec):
+    p = _rand_problem(1031, 2 * 256 + 77, 64, 32, seed=9, offset=50.0,
+                      dtype=torch.float64 if prec == "fp64" else torch.float32)
+    _, g = _end_to_end(p, prec, n_modes=4)
+    o = O.spod(p.q.numpy(), 64, 32, weights=p.weights, n_modes=4, eps=1e-12 if prec == "fp64" else 1e-6)
+    if prec == "fp64":
+        PT.check_eig(g["lam"], o["lam"], rtol=1e-10)
+        PT.check_modes(g["phi"], o["phi"], o["lam"], p.weights, o["n_valid"], 1e-8, 1e-7, 1e-6)
+    else:
+        PT.check_eig_mixed(g["lam"], o["lam"], p.M, n=4)
+        PT.check_modes(g["phi"], o["phi"], o["lam"], p.weights, o["n_valid"], 1e-3, 1e-2, 1e-3)
+
+
+# ---------------------------------------------------------------------------
+# boundary behaviour on the device
+# ---------------------------------------------------------------------------
+def test_stage_errors_on_device():
+    import ctypes as C
+    from paper_2309_11808_amd import _native as N
+    from paper_2309_11808_amd.spod import lib
+    p = _rand_problem(100, 512, 64, 32, seed=4)
+    plan = _plan(p)
+    qh = torch.zeros(plan.nfreq, plan.nblocks, plan.M, dtype=torch.complex128, device="cuda")
+    g = torch.zeros(plan.nfreq, plan.nblocks, plan.nblocks, dtype=torch.complex128, device="cuda")
+    small = torch.empty(8, dtype=torch.uint8, device="cuda")
+    st = lib().spod_csd(plan._h, C.c_void_p(qh.data_ptr()), C.c_void_p(g.data_ptr()),
+                        C.c_void_p(small.data_ptr()), 8, None)
+    assert st == N.SPOD_ERR_WORKSPACE
+    st = lib().spod_modes(plan._h, C.c_void_p(qh.data_ptr()), C.c_void_p(qh.data_ptr()),
+                          C.c_void_p(g.data_ptr()), plan.nblocks + 1, C.c_void_p(qh.data_ptr()),
+                          None, None, 0, None)
+    assert st == N.SPOD_ERR_INVALID_ARG
+    # precision and options are frozen after the first stage call
+    assert lib().spod_plan_set_precision(plan._h, N.SPOD_PREC_FP32) == N.SPOD_ERR_INVALID_ARG
+    assert math.isfinite(plan.workspace_bytes)
