@@ -87,6 +87,25 @@ __device__ __forceinline__ void dft_r(C* x) {
   else dft8(x);
 }
 
+// LDS layout of one transform: element i at pad(i) = i + i/8, which spreads the
+// stride-8 writes of the first radix-8 stage over all banks; rows (one per
+// transform) are LDP = pad(N) + 1 elements apart so that reading the same
+// frequency of consecutive rows also spreads over the banks.
+__device__ __forceinline__ int pad8(int i) { return i + (i >> 3); }
+
+// Exchange barrier: when a transform lives inside one wavefront (P <= 64) its
+// lanes only need a wavefront-level barrier; otherwise the workgroup's.
+template <bool WAVE>
+__device__ __forceinline__ void xbarrier() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 // One Stockham stage of radix RS after NS points have been combined.  Lane j
 // handles butterflies b = j + u*P (u < 8/RS) over elements b + q*(NF/RS).
 template <int NF, int NS, int RS, typename C>
@@ -112,14 +131,14 @@ __device__ __forceinline__ void stockham_stage(C (&v)[8], C* buf, int j, const C
     } else {
       const int base = (b / NS) * NS * RS + kk;
 #pragma unroll
-      for (int q = 0; q < RS; ++q) buf[base + q * NS] = x[q];
+      for (int q = 0; q < RS; ++q) buf[pad8(base + q * NS)] = x[q];
     }
   }
   if constexpr (!LAST) {
-    __syncthreads();
+    xbarrier<(P <= 64)>();
 #pragma unroll
-    for (int r = 0; r < 8; ++r) v[r] = buf[j + r * P];
-    __syncthreads();
+    for (int r = 0; r < 8; ++r) v[r] = buf[pad8(j + r * P)];
+    xbarrier<(P <= 64)>();
   }
 }
 
@@ -133,58 +152,123 @@ __device__ __forceinline__ void stockham(C (&v)[8], C* buf, int j, const C* __re
   }
 }
 
+// Bins whose window DFT What_k is non-zero, for the single-pass mean removal.
+struct MeanBins {
+  int n;
+  int k[4];
+  double wr[4], wi[4];
+};
+
+// Sum over the P lanes of one transform (P a power of two <= 64).
+template <int P>
+__device__ __forceinline__ double group_sum(double x) {
+  static_assert(P <= 64, "a transform must fit in one wavefront");
+#pragma unroll
+  for (int o = P / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, P);
+  return x;
+}
+
 // ---------------------------------------------------------------------------
 // windowed block transform
 // ---------------------------------------------------------------------------
-// SHIFT = hop / P when the hop between blocks is a whole number of lane
-// strides (e.g. 4 for 50% overlap): the raw samples of elements SHIFT..7 of
-// block l are elements 0..7-SHIFT of block l+1 and stay in registers.
-// SHIFT = 8 reloads every block.
-template <int NF, typename TC, typename TIN, int NPAIR, int SHIFT>
+// A workgroup owns a tile of T = 2*NPAIR degrees of freedom and the blocks
+// [l0, l1).  SHIFT = hop / P when the hop between blocks is a whole number of
+// lane strides (e.g. 4 for 50% overlap): the raw samples of elements
+// SHIFT..7 of block l are elements 0..7-SHIFT of block l+1 and stay in
+// registers, and only SHIFT new samples per lane are loaded (prefetched one
+// block ahead).  SHIFT = 0 means "not a whole number": every block is loaded
+// in full.
+//
+// FUSED: the temporal mean is removed in the same pass.  The workgroup covers
+// all L blocks; it transforms w (x - mu0) with mu0 the mean of the first block,
+// accumulates sum(x - mu0) over every sample (blocks and the dropped tail) in
+// FP64, and at the end subtracts kappa (mu - mu0) What_k from the bins where
+// What_k != 0 (the DFT is linear: DFT(w (x - mu)) = DFT(w (x - mu0)) -
+// (mu - mu0) What).  mu0 keeps the transform's input of the order of the
+// fluctuations, so the FP32 transform does not lose the precision a large
+// mean would cost.  Not FUSED: mean[] was computed by mean_kernel.
+template <int NF, typename TC, typename TIN, int NPAIR, int SHIFT, bool FUSED>
 __global__ __launch_bounds__(NPAIR*(NF / 8)) void blocks_fft_kernel(
-    const TIN* __restrict__ q, const double* __restrict__ mean, const double* __restrict__ window,
+    const TIN* __restrict__ q, double* __restrict__ mean, const double* __restrict__ window,
     const cpx_t<TC>* __restrict__ tw, cpx_t<TC>* __restrict__ qhat, int64_t M, int64_t nt,
-    int step, int L, int bpw, TC kappa) {
+    int step, int L, int bpw, TC kappa, MeanBins mb) {
   using C = cpx_t<TC>;
   constexpr int P = NF / 8;              // lanes per transform
   constexpr int T = 2 * NPAIR;           // degrees of freedom per tile
   constexpr int NTH = NPAIR * P;
-  constexpr int LD = NF + 1;             // padded LDS row (bank spread for the [k][m] reads)
+  constexpr int LDP = NF + NF / 8 + 1;   // padded LDS row
   constexpr int K = NF / 2 + 1;
-  __shared__ C lds[NPAIR * LD];
+  constexpr int NEWR = SHIFT == 0 ? 8 : SHIFT;   // freshly loaded elements per block (after the first)
+  static_assert(!FUSED || SHIFT > 0, "the fused mean needs a whole-stride hop");
+  // complex64: the twiddle table is copied to LDS (4 KB at N = 512), so
+  // twiddle reads do not share the vector-memory counter with the prefetch
+  constexpr bool TWL = sizeof(TC) == 4;
+  __shared__ C lds[NPAIR * LDP];
+  __shared__ C twl[TWL ? NF : 1];
+  __shared__ double corr[FUSED ? T : 1];
 
   const int tid = threadIdx.x;
   const int f = tid / P;                 // transform (pair) index in the tile
   const int j = tid % P;                 // lane within the transform
   const int64_t m0 = (int64_t)blockIdx.x * T;
-  const int64_t ma = m0 + 2 * f, mb = ma + 1;
-  const bool va = ma < M, vb = mb < M;
-  const double mua = va ? mean[ma] : 0.0, mub = vb ? mean[mb] : 0.0;
+  const int64_t ma = m0 + 2 * f, mb_ = ma + 1;
+  const bool va = ma < M, vb = mb_ < M;
   const TIN* ra = q + (va ? ma : 0) * nt;
-  const TIN* rb = q + (vb ? mb : 0) * nt;
-  C* buf = lds + f * LD;
+  const TIN* rb = q + (vb ? mb_ : 0) * nt;
+  C* buf = lds + f * LDP;
 
   TC w[8];
 #pragma unroll
   for (int r = 0; r < 8; ++r) w[r] = (TC)window[j + r * P];
+  const C* twp = tw;
+  if constexpr (TWL) {
+    for (int i = tid; i < NF; i += NTH) twl[i] = tw[i];
+    twp = twl;
+    __syncthreads();
+  }
 
   const int l0 = blockIdx.y * bpw;
   const int l1 = min(L, l0 + bpw);
-  TIN xa[8], xb[8];
-  for (int l = l0; l < l1; ++l) {
-    const int64_t t0 = (int64_t)l * step;
-    const bool first = (l == l0);
+  TIN xa[8], xb[8], na[8], nb[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const int64_t t = (int64_t)l0 * step + j + r * P;
+    xa[r] = va ? ra[t] : (TIN)0;
+    xb[r] = vb ? rb[t] : (TIN)0;
+  }
+  double mua, mub;
+  double sa = 0.0, sb = 0.0;             // FUSED: sums of (x - mu0) over this lane's samples
+  if constexpr (FUSED) {
+    double pa = 0.0, pb = 0.0;
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
-      if (!first && r + SHIFT < 8) {
-        xa[r] = xa[r + SHIFT];
-        xb[r] = xb[r + SHIFT];
-      } else {
-        const int64_t t = t0 + j + r * P;
-        xa[r] = va ? ra[t] : (TIN)0;
-        xb[r] = vb ? rb[t] : (TIN)0;
-      }
+      pa += (double)xa[r];
+      pb += (double)xb[r];
     }
+    mua = group_sum<P>(pa) / NF;
+    mub = group_sum<P>(pb) / NF;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      sa += (double)xa[r] - mua;
+      sb += (double)xb[r] - mub;
+    }
+  } else {
+    mua = va ? mean[ma] : 0.0;
+    mub = vb ? mean[mb_] : 0.0;
+  }
+
+  for (int l = l0; l < l1; ++l) {
+    // prefetch the samples block l+1 needs that block l does not hold; the
+    // last block re-reads its own (in-range) samples so the loads stay
+    // unconditional and in flight during the transform
+    const bool more = l + 1 < l1;
+    const int64_t tn = (int64_t)(more ? l + 1 : l) * step + j;
+#pragma unroll
+    for (int r = 8 - NEWR; r < 8; ++r) {
+      na[r] = ra[tn + r * P];
+      nb[r] = rb[tn + r * P];
+    }
+    __builtin_amdgcn_sched_barrier(0);
 
     C v[8];
 #pragma unroll
@@ -193,9 +277,9 @@ __global__ __launch_bounds__(NPAIR*(NF / 8)) void blocks_fft_kernel(
       const TC b = (TC)((double)xb[r] - mub);
       v[r] = C{a * w[r], b * w[r]};
     }
-    stockham<NF, 1>(v, buf, j, tw);
+    stockham<NF, 1>(v, buf, j, twp);
 #pragma unroll
-    for (int r = 0; r < 8; ++r) buf[j + r * P] = v[r];
+    for (int r = 0; r < 8; ++r) buf[pad8(j + r * P)] = v[r];
     __syncthreads();
 
     // separate the two real spectra and write qhat[k][l][m0 .. m0+T)
@@ -203,71 +287,160 @@ __global__ __launch_bounds__(NPAIR*(NF / 8)) void blocks_fft_kernel(
     for (int idx = tid; idx < K * T; idx += NTH) {
       const int d = idx % T;
       const int k = idx / T;
-      const C* row = lds + (d >> 1) * LD;
-      const C A = row[k];
-      const C Bc = row[(NF - k) & (NF - 1)];
+      const C* row = lds + (d >> 1) * LDP;
+      const C A = row[pad8(k)];
+      const C Bc = row[pad8((NF - k) & (NF - 1))];
       const C B = C{Bc.x, -Bc.y};
-      C X;
-      if ((d & 1) == 0) {
-        X = cadd(A, B);
-      } else {
-        X = cmul_mi(csub(A, B));
-      }
-      const TC s = (TC)0.5 * kappa;
+      const C X = (d & 1) == 0 ? cadd(A, B) : cmul_mi(csub(A, B));
+      const TC sc = (TC)0.5 * kappa;
       const int64_t m = m0 + d;
-      if (m < M) out[(int64_t)k * L * M + m] = C{X.x * s, X.y * s};
+      if (m < M) out[(int64_t)k * L * M + m] = C{X.x * sc, X.y * sc};
     }
     __syncthreads();
+
+    if (more) {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        if (r < 8 - NEWR) {
+          xa[r] = xa[r + NEWR];
+          xb[r] = xb[r + NEWR];
+        } else {
+          xa[r] = va ? na[r] : (TIN)0;
+          xb[r] = vb ? nb[r] : (TIN)0;
+          if constexpr (FUSED) {
+            sa += (double)xa[r] - mua;
+            sb += (double)xb[r] - mub;
+          }
+        }
+      }
+    }
+  }
+
+  if constexpr (FUSED) {
+    // snapshots after the last block only enter the mean
+    for (int64_t t = (int64_t)(L - 1) * step + NF + j; t < nt; t += P) {
+      if (va) sa += (double)ra[t] - mua;
+      if (vb) sb += (double)rb[t] - mub;
+    }
+    sa = group_sum<P>(sa);
+    sb = group_sum<P>(sb);
+    const double da = sa / (double)nt, db = sb / (double)nt;   // mu - mu0
+    if (j == 0) {
+      if (va) mean[ma] = mua + da;
+      if (vb) mean[mb_] = mub + db;
+      corr[2 * f] = da * (double)kappa;
+      corr[2 * f + 1] = db * (double)kappa;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < mb.n * L * T; idx += NTH) {
+      const int d = idx % T;
+      const int l = (idx / T) % L;
+      const int s = idx / (T * L);
+      const int64_t m = m0 + d;
+      if (m >= M) continue;
+      C* o = qhat + ((int64_t)mb.k[s] * L + l) * M + m;
+      const C raw = *o;
+      const double c = corr[d];
+      *o = C{(TC)((double)raw.x - c * mb.wr[s]), (TC)((double)raw.y - c * mb.wi[s])};
+    }
   }
 }
 
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
-template <int NF, typename TC, typename TIN>
-static spod_status launch_fft_nf(const Plan& p, const TIN* q, const double* mean, void* qhat,
-                                 hipStream_t st) {
+// Transforms per workgroup: at least a full wavefront of lanes, at most 512
+// threads by default (more threads cap the registers per lane at 128).
+template <int NF, int BASE>
+struct FftShape {
+  static constexpr int P = NF / 8;
+  static constexpr int NPAIR0 = (BASE * P < 64) ? (64 / P) : BASE;
+  static constexpr int NPAIR = (NPAIR0 * P > 1024) ? (1024 / P) : NPAIR0;
+  static constexpr int T = 2 * NPAIR;
+};
+
+template <int NF, typename TC, typename TIN, int NPAIR, int SHIFT, bool FUSED>
+static void launch_fft_kernel(const Plan& p, dim3 grid, const TIN* q, double* mean, const void* tw,
+                              void* qhat, int bpw, const MeanBins& mb, hipStream_t st) {
   using C = cpx_t<TC>;
   constexpr int P = NF / 8;
-  constexpr int BASE = sizeof(TC) == 4 ? 16 : 8;          // pairs per tile
-  constexpr int NPAIR0 = (BASE * P < 64) ? (64 / P) : BASE;
-  constexpr int NPAIR = (NPAIR0 * P > 1024) ? (1024 / P) : NPAIR0;
-  constexpr int T = 2 * NPAIR;
+  hipLaunchKernelGGL((blocks_fft_kernel<NF, TC, TIN, NPAIR, SHIFT, FUSED>), grid, dim3(NPAIR * P), 0,
+                     st, q, mean, p.d_window, static_cast<const C*>(tw), static_cast<C*>(qhat),
+                     (int64_t)p.M, (int64_t)p.nt, (int)p.step, (int)p.nblocks, bpw, (TC)p.kappa, mb);
+}
+
+template <int NF, typename TC, typename TIN, int BASE>
+static spod_status launch_fft_shape(const Plan& p, const TIN* q, double* mean, void* qhat,
+                                    hipStream_t st, bool fused) {
+  using S = FftShape<NF, BASE>;
+  constexpr int P = S::P, NPAIR = S::NPAIR, T = S::T;
   const int64_t ntiles = (p.M + T - 1) / T;
-  const int L = (int)p.nblocks;
-  // split the blocks over workgroups only when the tiles alone cannot fill the GPU
-  int64_t chunks = 1;
-  if (ntiles < 4096) chunks = (4096 + ntiles - 1) / ntiles;
-  if (chunks > L) chunks = L;
-  const int bpw = (int)((L + chunks - 1) / chunks);
-  chunks = (L + bpw - 1) / bpw;
   if (ntiles > 0x7fffffff) return fail(SPOD_ERR_UNSUPPORTED, "too many tiles");
-  dim3 grid((unsigned)ntiles, (unsigned)chunks);
-  const C* tw = reinterpret_cast<const C*>(sizeof(TC) == 4 ? (const void*)p.d_tw32 : (const void*)p.d_tw64);
-  if (p.step * 2 == NF)
-    hipLaunchKernelGGL((blocks_fft_kernel<NF, TC, TIN, NPAIR, 4>), grid, dim3(NPAIR * P), 0, st, q,
-                       mean, p.d_window, tw, reinterpret_cast<C*>(qhat), (int64_t)p.M,
-                       (int64_t)p.nt, (int)p.step, L, bpw, (TC)p.kappa);
-  else
-    hipLaunchKernelGGL((blocks_fft_kernel<NF, TC, TIN, NPAIR, 8>), grid, dim3(NPAIR * P), 0, st, q,
-                       mean, p.d_window, tw, reinterpret_cast<C*>(qhat), (int64_t)p.M,
-                       (int64_t)p.nt, (int)p.step, L, bpw, (TC)p.kappa);
+  const int L = (int)p.nblocks;
+  const void* tw = sizeof(TC) == 4 ? (const void*)p.d_tw32 : (const void*)p.d_tw64;
+  MeanBins mb{};
+  mb.n = fused ? p.n_mean_bins : 0;
+  for (int i = 0; i < mb.n; ++i) {
+    mb.k[i] = p.mean_bin[i];
+    mb.wr[i] = p.what_re[i];
+    mb.wi[i] = p.what_im[i];
+  }
+  const int shift = (p.step % P == 0) ? (int)(p.step / P) : 0;
+  if (fused) {
+    if constexpr (P <= 64) {
+      dim3 grid((unsigned)ntiles, 1);
+      switch (shift) {
+        case 2: launch_fft_kernel<NF, TC, TIN, NPAIR, 2, true>(p, grid, q, mean, tw, qhat, L, mb, st); break;
+        case 4: launch_fft_kernel<NF, TC, TIN, NPAIR, 4, true>(p, grid, q, mean, tw, qhat, L, mb, st); break;
+        case 8: launch_fft_kernel<NF, TC, TIN, NPAIR, 8, true>(p, grid, q, mean, tw, qhat, L, mb, st); break;
+        default: return fail(SPOD_ERR_UNSUPPORTED, "fused transform needs hop = N/4, N/2 or N");
+      }
+    } else {
+      return fail(SPOD_ERR_UNSUPPORTED, "fused transform needs nfft <= 512");
+    }
+  } else {
+    // split the blocks over workgroups only when the tiles alone cannot fill the GPU
+    int64_t chunks = 1;
+    if (ntiles < 4096) chunks = (4096 + ntiles - 1) / ntiles;
+    if (chunks > L) chunks = L;
+    const int bpw = (int)((L + chunks - 1) / chunks);
+    chunks = (L + bpw - 1) / bpw;
+    dim3 grid((unsigned)ntiles, (unsigned)chunks);
+    if (shift == 4)
+      launch_fft_kernel<NF, TC, TIN, NPAIR, 4, false>(p, grid, q, mean, tw, qhat, bpw, mb, st);
+    else
+      launch_fft_kernel<NF, TC, TIN, NPAIR, 0, false>(p, grid, q, mean, tw, qhat, bpw, mb, st);
+  }
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SPOD_OK : hip_fail(e, "blocks_fft_kernel");
 }
 
+template <int NF, typename TC, typename TIN>
+static spod_status launch_fft_nf(const Plan& p, const TIN* q, double* mean, void* qhat,
+                                 hipStream_t st, bool fused) {
+  // Tile of 32 degrees of freedom (16 transforms; 1024 threads at N = 512):
+  // every frequency row is written in runs of 256 bytes, which the HBM takes
+  // markedly better than 128-byte runs.  Default for complex64; complex128
+  // keeps 16 (its runs are 256 bytes already, and 1024 threads would leave
+  // it 128 registers per lane).  SPOD_OPT_FFT_TILE = 16 or 32 overrides.
+  const bool wide = p.fft_tile_opt == 32 || (p.fft_tile_opt == 0 && sizeof(TC) == 4);
+  if (wide && FftShape<NF, 16>::NPAIR != FftShape<NF, 8>::NPAIR)
+    return launch_fft_shape<NF, TC, TIN, 16>(p, q, mean, qhat, st, fused);
+  return launch_fft_shape<NF, TC, TIN, 8>(p, q, mean, qhat, st, fused);
+}
+
 template <typename TC, typename TIN>
-static spod_status launch_fft_t(const Plan& p, const TIN* q, const double* mean, void* qhat,
-                                hipStream_t st) {
+static spod_status launch_fft_t(const Plan& p, const TIN* q, double* mean, void* qhat,
+                                hipStream_t st, bool fused) {
   switch (p.nfft) {
-    case 8: return launch_fft_nf<8, TC, TIN>(p, q, mean, qhat, st);
-    case 16: return launch_fft_nf<16, TC, TIN>(p, q, mean, qhat, st);
-    case 32: return launch_fft_nf<32, TC, TIN>(p, q, mean, qhat, st);
-    case 64: return launch_fft_nf<64, TC, TIN>(p, q, mean, qhat, st);
-    case 128: return launch_fft_nf<128, TC, TIN>(p, q, mean, qhat, st);
-    case 256: return launch_fft_nf<256, TC, TIN>(p, q, mean, qhat, st);
-    case 512: return launch_fft_nf<512, TC, TIN>(p, q, mean, qhat, st);
-    case 1024: return launch_fft_nf<1024, TC, TIN>(p, q, mean, qhat, st);
+    case 8: return launch_fft_nf<8, TC, TIN>(p, q, mean, qhat, st, fused);
+    case 16: return launch_fft_nf<16, TC, TIN>(p, q, mean, qhat, st, fused);
+    case 32: return launch_fft_nf<32, TC, TIN>(p, q, mean, qhat, st, fused);
+    case 64: return launch_fft_nf<64, TC, TIN>(p, q, mean, qhat, st, fused);
+    case 128: return launch_fft_nf<128, TC, TIN>(p, q, mean, qhat, st, fused);
+    case 256: return launch_fft_nf<256, TC, TIN>(p, q, mean, qhat, st, fused);
+    case 512: return launch_fft_nf<512, TC, TIN>(p, q, mean, qhat, st, fused);
+    case 1024: return launch_fft_nf<1024, TC, TIN>(p, q, mean, qhat, st, fused);
   }
   return fail(SPOD_ERR_UNSUPPORTED, "nfft");
 }
@@ -278,24 +451,30 @@ spod_status launch_blocks_fft(const Plan& p, const void* q, spod_dtype dtype, vo
                               double* mean, void* ws, hipStream_t st) {
   // the mean goes to the caller's buffer, or to the start of the workspace
   double* mu = mean ? mean : static_cast<double*>(ws);
-  const int64_t mgrid = (p.M + 3) / 4;
-  if (dtype == SPOD_F32)
-    hipLaunchKernelGGL(mean_kernel<float>, dim3((unsigned)mgrid), dim3(256), 0, st,
-                       (const float*)q, mu, (int64_t)p.M, (int64_t)p.nt);
-  else
-    hipLaunchKernelGGL(mean_kernel<double>, dim3((unsigned)mgrid), dim3(256), 0, st,
-                       (const double*)q, mu, (int64_t)p.M, (int64_t)p.nt);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return hip_fail(e, "mean_kernel");
-  spod_status s;
+  // single pass when the window's DFT has few non-zero bins and the hop is a
+  // whole number of lane strides; otherwise a separate FP64 mean pass first
+  const int P = (int)(p.nfft / 8);
+  const int shift = (p.step % P == 0) ? (int)(p.step / P) : 0;
+  // (the per-transform sums are wavefront shuffles: one transform must fit in
+  // one wavefront, P <= 64)
+  const bool fused = p.n_mean_bins >= 0 && P <= 64 && (shift == 2 || shift == 4 || shift == 8);
+  if (!fused) {
+    const int64_t mgrid = (p.M + 3) / 4;
+    if (dtype == SPOD_F32)
+      hipLaunchKernelGGL(mean_kernel<float>, dim3((unsigned)mgrid), dim3(256), 0, st,
+                         (const float*)q, mu, (int64_t)p.M, (int64_t)p.nt);
+    else
+      hipLaunchKernelGGL(mean_kernel<double>, dim3((unsigned)mgrid), dim3(256), 0, st,
+                         (const double*)q, mu, (int64_t)p.M, (int64_t)p.nt);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "mean_kernel");
+  }
   const bool c128 = is_complex128(p);
   if (dtype == SPOD_F32)
-    s = c128 ? launch_fft_t<double, float>(p, (const float*)q, mu, qhat, st)
-             : launch_fft_t<float, float>(p, (const float*)q, mu, qhat, st);
-  else
-    s = c128 ? launch_fft_t<double, double>(p, (const double*)q, mu, qhat, st)
-             : launch_fft_t<float, double>(p, (const double*)q, mu, qhat, st);
-  return s;
+    return c128 ? launch_fft_t<double, float>(p, (const float*)q, mu, qhat, st, fused)
+                : launch_fft_t<float, float>(p, (const float*)q, mu, qhat, st, fused);
+  return c128 ? launch_fft_t<double, double>(p, (const double*)q, mu, qhat, st, fused)
+              : launch_fft_t<float, double>(p, (const double*)q, mu, qhat, st, fused);
 }
 
 }  // namespace spod

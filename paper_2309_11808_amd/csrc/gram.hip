@@ -1,29 +1,29 @@
 // Steps 3-4 of SPOD (eq. (spod-discrete-snapshots); Sec. 3.1 steps 3-4): the
 // weighted inner product M_k = Qhat_k^* W Qhat_k for every frequency.
 //
-// Realified form.  With Y = sqrt(W) [Re Qhat_k^T ; Im Qhat_k^T] (2L rows, M
-// columns), P = Y Y^T is a real symmetric (2L x 2L) matrix and
-//   M_k[i][j] = (P[i][j] + P[L+i][L+j]) + i (P[i][L+j] - P[L+i][j]).
-// P is a single SYRK with a long contraction over the degrees of freedom, run
-// on MFMA in 16x16 output tiles (upper triangle of tiles only).  The paper
-// reduces this sum over space across MPI ranks; here the M axis is split into
-// S slices, one workgroup per (slice, frequency), and the S partial P's are
-// combined in FP64 by a second kernel.
+// Complex form.  With A = sqrt(W) Re(Qhat_k) and B = sqrt(W) Im(Qhat_k),
+//   Re M_k = A A^T + B B^T,   Im M_k = A B^T - B A^T,
+// four real products with a long contraction over the degrees of freedom, run
+// on MFMA in 16 x 16 blocks of M_k (upper blocks only; M_k is Hermitian).  The
+// paper reduces this sum over space across MPI ranks; here the M axis is split
+// into S slices, one workgroup per (slice, frequency), each of its four waves
+// streaming its own part of the slice, and the S partial Grams are combined in
+// FP64 by a second kernel.
 //
 // Arithmetic per precision:
 //   FP64    v_mfma_f64_16x16x4f64, FP64 accumulation.
-//   FP32    v_mfma_f32_16x16x4f32 started from zero at every 4-wide step and
-//           added into FP64 registers at once.
+//   FP32    v_mfma_f32_16x16x4f32; the two products of one 4-wide step start
+//           from zero and are added into FP64 registers at once.
 //   BF16X4  y = hi + lo with hi = bf16(y), lo = bf16(y - hi) (round to nearest
 //           even) and all four products hi hi^T + hi lo^T + lo hi^T + lo lo^T
 //           on v_mfma_f32_16x16x32_bf16: the exact product of the 16-bit
 //           representation.  Dropping lo lo^T (the common three-product
 //           scheme) is not used: on a Gram matrix it is a one-signed bias of
 //           the diagonal (sum of lo^2) that shifts every small eigenvalue.
-//           The dominant hi hi^T product starts from zero at every 32-wide
-//           step and is added into FP64 at once, so each FP32 rounding only
-//           sees 32 products; the three small correction products share one
-//           FP32 accumulator flushed every 16 steps.
+//           The dominant hi hi^T products start from zero at every 32-wide
+//           step and are added into FP64 at once, so each FP32 rounding only
+//           sees 64 products; the small correction products share one FP32
+//           accumulator flushed every 16 steps.
 //   FP16X4  the same with FP16 operands, y scaled per frequency by a power of
 //           two so that max |y| lies in [2^14, 2^15) (gram_scale_kernel).
 #include <hip/hip_runtime.h>
@@ -43,31 +43,27 @@ enum GramMode { G_F64 = 0, G_F32 = 1, G_BF16X4 = 2, G_FP16X4 = 3 };
 
 template <int MODE> struct GramCfg;
 template <> struct GramCfg<G_F64> {
-  using TL = double;            // LDS element
-  using C = double2;            // qhat element
-  static constexpr int KS = 4;  // contraction per MFMA
-  static constexpr int MC = 64; // degrees of freedom per LDS chunk
+  using T = double;               // arithmetic type of the operands
+  using C = double2;              // qhat element
+  static constexpr int DPL = 4;   // consecutive degrees of freedom loaded per lane
   using ACC = v4d;
 };
 template <> struct GramCfg<G_F32> {
-  using TL = float;
+  using T = float;
   using C = float2;
-  static constexpr int KS = 4;
-  static constexpr int MC = 128;
+  static constexpr int DPL = 4;
   using ACC = v4f;
 };
 template <> struct GramCfg<G_BF16X4> {
-  using TL = float;
+  using T = float;
   using C = float2;
-  static constexpr int KS = 32;
-  static constexpr int MC = 128;
+  static constexpr int DPL = 8;
   using ACC = v4f;
 };
 template <> struct GramCfg<G_FP16X4> {
-  using TL = float;
+  using T = float;
   using C = float2;
-  static constexpr int KS = 32;
-  static constexpr int MC = 128;
+  static constexpr int DPL = 8;
   using ACC = v4f;
 };
 
@@ -90,162 +86,423 @@ __device__ __forceinline__ void split_f16(const float* y, float s, v8h& hi, v8h&
   }
 }
 
-// NTI = tiles of 16 per side (2L <= 16*NTI); NP = NTI(NTI+1)/2 upper tile
-// pairs, processed in groups of at most PG = 10 (grid z), so each lane holds
-// at most 10 accumulator tiles.  The four waves of a workgroup split the
-// contraction and are summed through LDS at the end.
-constexpr int PG = 10;
+template <typename V>
+__device__ __forceinline__ V negate(V x) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) x[e] = -x[e];
+  return x;
+}
 
-template <int MODE, int NTI, int G>
-__device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __restrict__ qhat,
-                                          const typename GramCfg<MODE>::TL* __restrict__ sqrtw,
-                                          float scale, double* __restrict__ part, int64_t M,
-                                          int L, int S, typename GramCfg<MODE>::TL* Y) {
+// Complex form.  With A = sqrt(W) Re(qhat_k) and B = sqrt(W) Im(qhat_k) as
+// [L rows = blocks][M columns = degrees of freedom],
+//   Re M_k = A A^T + B B^T,   Im M_k = A B^T - B A^T.
+// The L rows are cut into NT tiles of 16; tile pairs (a <= b) give 16 x 16
+// blocks of M_k (the lower blocks follow from Hermitian symmetry).  Every lane
+// loads its MFMA fragments straight from HBM: lane l owns row 16a + l%16 and
+// DPL consecutive degrees of freedom starting at (l/16)*DPL of the current
+// group of 4*DPL; the contraction index is permuted accordingly (any fixed
+// permutation of the summation order gives the same sum), so each lane reads
+// one contiguous run of DPL complex values per tile.  A group is a
+// 16 x 16 x 16 (FP64/FP32, four 4-wide MFMA steps) or 16 x 16 x 32
+// (BF16/FP16, one MFMA step) product per real term.
+constexpr int PG = 3;   // tile pairs per wave (grid z splits larger sets)
+
+template <int NT, int P0, int NPG>
+__host__ __device__ constexpr unsigned tiles_needed() {
+  unsigned mask = 0;
+  int pi = 0;
+  for (int a = 0; a < NT; ++a)
+    for (int b = a; b < NT; ++b, ++pi)
+      if (pi >= P0 && pi < P0 + NPG) mask |= (1u << a) | (1u << b);
+  return mask;
+}
+
+template <int MODE, int NT>
+struct Raw {
   using Cfg = GramCfg<MODE>;
-  using TL = typename Cfg::TL;
+  typename Cfg::C x[NT][Cfg::DPL];
+  typename Cfg::T w[Cfg::DPL];
+};
+
+// Full group: every lane's run [m, m + DPL) lies inside [0, M) and rows are
+// 16-byte aligned.  Branch-free 16-byte loads (rows >= L read row L-1; the
+// caller masks them when it forms the operands, never by writing registers a
+// load may still be filling), so the next group's loads stay in flight while
+// the current one is multiplied.
+template <int MODE, int NT, unsigned NEED>
+__device__ __forceinline__ void gram_load_full(Raw<MODE, NT>& r, const typename GramCfg<MODE>::C* __restrict__ qk,
+                                               const typename GramCfg<MODE>::T* __restrict__ sqrtw,
+                                               int64_t m, int64_t M, int L, int r16) {
+  using Cfg = GramCfg<MODE>;
+  using C = typename Cfg::C;
+  using T = typename Cfg::T;
+  constexpr int DPL = Cfg::DPL;
+  constexpr int NV = (int)(sizeof(C) * DPL / 16);
+#pragma unroll
+  for (int a = 0; a < NT; ++a) {
+    if (!((NEED >> a) & 1u)) continue;
+    const int row = 16 * a + r16;
+    const int rc = row < L ? row : L - 1;
+    const v4f* src = reinterpret_cast<const v4f*>(qk + (int64_t)rc * M + m);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const v4f f = __builtin_nontemporal_load(src + v);
+      if constexpr (sizeof(C) == 8) {
+        r.x[a][2 * v] = C{f[0], f[1]};
+        r.x[a][2 * v + 1] = C{f[2], f[3]};
+      } else {
+        double2 d;
+        __builtin_memcpy(&d, &f, 16);
+        r.x[a][v] = d;
+      }
+    }
+  }
+  constexpr int NW = (int)(sizeof(T) * DPL / 16);
+  const v4f* wsrc = reinterpret_cast<const v4f*>(sqrtw + m);
+#pragma unroll
+  for (int v = 0; v < NW; ++v) {
+    const v4f f = wsrc[v];
+    __builtin_memcpy(&r.w[v * (16 / (int)sizeof(T))], &f, 16);
+  }
+}
+
+// Any group (ragged end, unaligned rows): element-wise loads with bounds checks.
+template <int MODE, int NT, unsigned NEED>
+__device__ __forceinline__ void gram_load_any(Raw<MODE, NT>& r, const typename GramCfg<MODE>::C* __restrict__ qk,
+                                              const typename GramCfg<MODE>::T* __restrict__ sqrtw,
+                                              int64_t m, int64_t M, int L, int r16) {
+  using Cfg = GramCfg<MODE>;
+  using C = typename Cfg::C;
+  using T = typename Cfg::T;
+  constexpr int DPL = Cfg::DPL;
+#pragma unroll
+  for (int a = 0; a < NT; ++a) {
+    if (!((NEED >> a) & 1u)) continue;
+    const int row = 16 * a + r16;
+#pragma unroll
+    for (int e = 0; e < DPL; ++e)
+      r.x[a][e] = (row < L && m + e < M) ? qk[(int64_t)row * M + m + e] : C{0, 0};
+  }
+#pragma unroll
+  for (int e = 0; e < DPL; ++e) r.w[e] = (m + e < M) ? sqrtw[m + e] : (T)0;
+}
+
+// LDS staging of the contraction.  A chunk is 1 KB of every row of qhat_k
+// (CD = 1024 / sizeof(C) degrees of freedom) plus the matching weights.  The
+// workgroup loads it with fully coalesced 16-byte global-to-LDS loads (lane i
+// of an instruction fills bytes [16 i, 16 i + 16) of one row), two chunks in
+// flight, and every wave then multiplies its quarter of the chunk.  Rows are
+// RSB = 1040 bytes apart in LDS, so the 16 lanes of one fragment read (16
+// rows, same column) fall in distinct banks.  Each wave issues exactly NI load
+// instructions per chunk (slots past the real rows re-read a valid row into a
+// spare LDS slot), so the wait for a chunk is the constant vmcnt(NI).
+template <int NT>
+struct GramStage {
+  static constexpr int RSB = 1040;                  // LDS row stride (bytes)
+  static constexpr int ROWS = 16 * NT + 2;          // tile rows, weight row, spare row
+  static constexpr int BYTES = ROWS * RSB;          // one stage
+  static constexpr int NI = (16 * NT + 1 + 3) / 4;  // load instructions per wave per chunk
+};
+
+template <int NT>
+__device__ __forceinline__ void stage_issue(char* stage, const char* __restrict__ qrows, int64_t rowb,
+                                            const char* __restrict__ wrow, int L, int wave, int lane) {
+  using GS = GramStage<NT>;
+#pragma unroll
+  for (int i = 0; i < GS::NI; ++i) {
+    const int slot = wave + 4 * i;                   // 0 .. 16 NT  (16 NT = weights)
+    const char* src;
+    int dst;
+    if (slot < 16 * NT) {
+      const int row = slot < L ? slot : L - 1;        // padded rows re-read a real row
+      src = qrows + (int64_t)row * rowb;
+      dst = slot;
+    } else if (slot == 16 * NT) {
+      src = wrow;
+      dst = slot;
+    } else {
+      src = wrow;                                     // spare slot: harmless duplicate
+      dst = 16 * NT + 1;
+    }
+    // the weight row holds 512 bytes: lanes 32..63 re-read the first half
+    const int off = (slot >= 16 * NT) ? 16 * (lane & 31) : 16 * lane;
+    __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)(src + off),
+                                     (void __attribute__((address_space(3)))*)(stage + dst * GS::RSB),
+                                     16, 0, 0);
+  }
+}
+
+template <int MODE, int NT, int G>
+__device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __restrict__ qhat,
+                                          const typename GramCfg<MODE>::T* __restrict__ sqrtw,
+                                          float scale, double* __restrict__ part, int64_t M,
+                                          int L, int S, bool vec, double* red, char* lds) {
+  using Cfg = GramCfg<MODE>;
+  using T = typename Cfg::T;
   using C = typename Cfg::C;
   using ACC = typename Cfg::ACC;
-  constexpr int KS = Cfg::KS, MC = Cfg::MC;
-  constexpr int D = 16 * NTI;
-  constexpr int NP = NTI * (NTI + 1) / 2;
+  using GS = GramStage<NT>;
+  constexpr int DPL = Cfg::DPL;
+  constexpr int GDOF = 4 * DPL;                             // degrees of freedom per group
+  constexpr int CD = 1024 / (int)sizeof(C);                 // degrees of freedom per chunk
+  constexpr int GPW = CD / GDOF / 4;                        // groups per wave per chunk
+  constexpr int D = 16 * NT;
+  constexpr int NP = NT * (NT + 1) / 2;
   constexpr int P0 = G * PG;
-  constexpr int NPG = (NP - P0) < PG ? (NP - P0) : PG;   // pairs in this group
-  constexpr int LDY = MC + (sizeof(TL) == 8 ? 4 : 8);
-  constexpr bool FLUSH = MODE == G_BF16X4 || MODE == G_FP16X4;  // correction accumulator
-  constexpr int NSTEP = MC / KS;
-  static_assert(NSTEP % 4 == 0, "chunk must split over four waves");
-  constexpr int SPW = NSTEP / 4;                             // steps per wave per chunk
+  constexpr int NPG = (NP - P0) < PG ? (NP - P0) : PG;
+  constexpr unsigned NEED = tiles_needed<NT, P0, NPG>();
+  constexpr bool SPLIT = MODE == G_BF16X4 || MODE == G_FP16X4;
+  static_assert(CD * (int)sizeof(T) <= 512, "weights of a chunk must fit the 512-byte weight row");
+  static_assert(GPW >= 1, "a chunk must give every wave a group");
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
   const int lane = tid & 63;
+  const int r16 = lane & 15;
+  const int g4 = lane >> 4;
   const int s = blockIdx.x;
   const int k = blockIdx.y;
+  const C* qk = qhat + (int64_t)k * L * M;
 
-  const int64_t nchunks = (M + MC - 1) / MC;
-  const int64_t c0 = nchunks * s / S, c1 = nchunks * (s + 1) / S;
+  // full chunks are split over the S slices; the ragged remainder (or all of
+  // it, when 16-byte loads are not possible) goes to the last slice
+  const int64_t nchunk = vec ? M / CD : 0;
+  const int64_t c0 = nchunk * s / S, c1 = nchunk * (s + 1) / S;
 
-  for (int idx = tid; idx < (D - 2 * L) * LDY; idx += 256) Y[2 * L * LDY + idx] = (TL)0;
-
-  ACC acc[NPG];
-  double acc64[NPG][4];
+  ACC accR[NPG], accI[NPG];          // FP64: running sums; split modes: correction terms
+  double sR[NPG][4], sI[NPG][4];     // FP64 sums of the FP32 partials (not FP64 mode)
 #pragma unroll
   for (int i = 0; i < NPG; ++i) {
-    acc[i] = ACC{0, 0, 0, 0};
+    accR[i] = ACC{0, 0, 0, 0};
+    accI[i] = ACC{0, 0, 0, 0};
 #pragma unroll
-    for (int v = 0; v < 4; ++v) acc64[i][v] = 0.0;
+    for (int v = 0; v < 4; ++v) sR[i][v] = sI[i][v] = 0.0;
   }
 
-  const C* base = qhat + (int64_t)k * L * M;
   int since_flush = 0;
-  for (int64_t c = c0; c < c1; ++c) {
-    const int64_t m0 = c * MC;
-    __syncthreads();
-    for (int idx = tid; idx < L * MC; idx += 256) {
-      const int l = idx / MC, mm = idx % MC;
-      const int64_t m = m0 + mm;
-      TL re = 0, im = 0;
-      if (m < M) {
-        const C z = base[(int64_t)l * M + m];
-        const TL w = sqrtw[m];
-        re = z.x * w;
-        im = z.y * w;
-      }
-      Y[l * LDY + mm] = re;
-      Y[(L + l) * LDY + mm] = im;
-    }
-    __syncthreads();
-
-#pragma unroll 1
-    for (int st = 0; st < SPW; ++st) {
-      const int kk0 = (wave * SPW + st) * KS;
-      if constexpr (MODE == G_F64 || MODE == G_F32) {
-        TL fr[NTI];
+  auto compute = [&](const Raw<MODE, NT>& cur) {
+    if constexpr (!SPLIT) {
+      // four 4-wide MFMA steps; step t uses element t of every lane's run
 #pragma unroll
-        for (int a = 0; a < NTI; ++a) fr[a] = Y[(16 * a + (lane & 15)) * LDY + kk0 + (lane >> 4)];
+      for (int t = 0; t < 4; ++t) {
+        T fa[NT], fb[NT];
+#pragma unroll
+        for (int a = 0; a < NT; ++a) {
+          const bool live = 16 * a + r16 < L;
+          fa[a] = live ? cur.x[a][t].x * cur.w[t] : (T)0;
+          fb[a] = live ? cur.x[a][t].y * cur.w[t] : (T)0;
+        }
         int pi = 0;
 #pragma unroll
-        for (int a = 0; a < NTI; ++a) {
+        for (int a = 0; a < NT; ++a) {
 #pragma unroll
-          for (int b = a; b < NTI; ++b, ++pi) {
-            if (pi >= P0 && pi < P0 + NPG) {
-              if constexpr (MODE == G_F64) {
-                acc[pi - P0] = __builtin_amdgcn_mfma_f64_16x16x4f64(fr[a], fr[b], acc[pi - P0], 0, 0, 0);
-              } else {
-                const ACC t = __builtin_amdgcn_mfma_f32_16x16x4f32(fr[a], fr[b], ACC{0, 0, 0, 0}, 0, 0, 0);
+          for (int b = a; b < NT; ++b, ++pi) {
+            if (pi < P0 || pi >= P0 + NPG) continue;
+            const int i = pi - P0;
+            if constexpr (MODE == G_F64) {
+              accR[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fa[b], accR[i], 0, 0, 0);
+              accR[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[a], fb[b], accR[i], 0, 0, 0);
+              accI[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], accI[i], 0, 0, 0);
+              accI[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(-fb[a], fa[b], accI[i], 0, 0, 0);
+            } else {
+              ACC tr = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[a], fa[b], ACC{0, 0, 0, 0}, 0, 0, 0);
+              tr = __builtin_amdgcn_mfma_f32_16x16x4f32(fb[a], fb[b], tr, 0, 0, 0);
+              ACC ti = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[a], fb[b], ACC{0, 0, 0, 0}, 0, 0, 0);
+              ti = __builtin_amdgcn_mfma_f32_16x16x4f32(-fb[a], fa[b], ti, 0, 0, 0);
 #pragma unroll
-                for (int v = 0; v < 4; ++v) acc64[pi - P0][v] += (double)t[v];
+              for (int v = 0; v < 4; ++v) {
+                sR[i][v] += (double)tr[v];
+                sI[i][v] += (double)ti[v];
               }
             }
           }
         }
-      } else {
-        using FR = typename std::conditional<MODE == G_BF16X4, v8bf, v8h>::type;
-        FR hi[NTI], lo[NTI];
+      }
+    } else {
+      using FR = typename std::conditional<MODE == G_BF16X4, v8bf, v8h>::type;
+      FR ah[NT], al[NT], bh[NT], bl[NT];
 #pragma unroll
-        for (int a = 0; a < NTI; ++a) {
-          const TL* src = &Y[(16 * a + (lane & 15)) * LDY + kk0 + 8 * (lane >> 4)];
-          float y[8];
+      for (int a = 0; a < NT; ++a) {
+        if (!((NEED >> a) & 1u)) continue;
+        float ya[8], yb[8];
+        const bool live = 16 * a + r16 < L;
 #pragma unroll
-          for (int e = 0; e < 8; ++e) y[e] = src[e];
-          if constexpr (MODE == G_BF16X4) split_bf16(y, hi[a], lo[a]);
-          else split_f16(y, scale, hi[a], lo[a]);
+        for (int e = 0; e < 8; ++e) {
+          ya[e] = live ? cur.x[a][e].x * cur.w[e] : 0.0f;
+          yb[e] = live ? cur.x[a][e].y * cur.w[e] : 0.0f;
         }
-        int pi = 0;
+        if constexpr (MODE == G_BF16X4) {
+          split_bf16(ya, ah[a], al[a]);
+          split_bf16(yb, bh[a], bl[a]);
+        } else {
+          split_f16(ya, scale, ah[a], al[a]);
+          split_f16(yb, scale, bh[a], bl[a]);
+        }
+      }
+      int pi = 0;
 #pragma unroll
-        for (int a = 0; a < NTI; ++a) {
+      for (int a = 0; a < NT; ++a) {
 #pragma unroll
-          for (int b = a; b < NTI; ++b, ++pi) {
-            if (pi >= P0 && pi < P0 + NPG) {
-              ACC& x = acc[pi - P0];
-              ACC t;
-              if constexpr (MODE == G_BF16X4) {
-                t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi[a], hi[b], ACC{0, 0, 0, 0}, 0, 0, 0);
-                x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi[a], lo[b], x, 0, 0, 0);
-                x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lo[a], hi[b], x, 0, 0, 0);
-                x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lo[a], lo[b], x, 0, 0, 0);
-              } else {
-                t = __builtin_amdgcn_mfma_f32_16x16x32_f16(hi[a], hi[b], ACC{0, 0, 0, 0}, 0, 0, 0);
-                x = __builtin_amdgcn_mfma_f32_16x16x32_f16(hi[a], lo[b], x, 0, 0, 0);
-                x = __builtin_amdgcn_mfma_f32_16x16x32_f16(lo[a], hi[b], x, 0, 0, 0);
-                x = __builtin_amdgcn_mfma_f32_16x16x32_f16(lo[a], lo[b], x, 0, 0, 0);
-              }
+        for (int b = a; b < NT; ++b, ++pi) {
+          if (pi < P0 || pi >= P0 + NPG) continue;
+          const int i = pi - P0;
+          const FR nbh = negate(bh[a]), nbl = negate(bl[a]);
+          ACC tr, ti;
+          if constexpr (MODE == G_BF16X4) {
+            tr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], ah[b], ACC{0, 0, 0, 0}, 0, 0, 0);
+            tr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh[a], bh[b], tr, 0, 0, 0);
+            ti = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], ACC{0, 0, 0, 0}, 0, 0, 0);
+            ti = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nbh, ah[b], ti, 0, 0, 0);
+            accR[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], al[b], accR[i], 0, 0, 0);
+            accR[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], ah[b], accR[i], 0, 0, 0);
+            accR[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], al[b], accR[i], 0, 0, 0);
+            accR[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh[a], bl[b], accR[i], 0, 0, 0);
+            accR[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bl[a], bh[b], accR[i], 0, 0, 0);
+            accR[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bl[a], bl[b], accR[i], 0, 0, 0);
+            accI[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], accI[i], 0, 0, 0);
+            accI[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], accI[i], 0, 0, 0);
+            accI[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bl[b], accI[i], 0, 0, 0);
+            accI[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nbh, al[b], accI[i], 0, 0, 0);
+            accI[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nbl, ah[b], accI[i], 0, 0, 0);
+            accI[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nbl, al[b], accI[i], 0, 0, 0);
+          } else {
+            tr = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[a], ah[b], ACC{0, 0, 0, 0}, 0, 0, 0);
+            tr = __builtin_amdgcn_mfma_f32_16x16x32_f16(bh[a], bh[b], tr, 0, 0, 0);
+            ti = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[a], bh[b], ACC{0, 0, 0, 0}, 0, 0, 0);
+            ti = __builtin_amdgcn_mfma_f32_16x16x32_f16(nbh, ah[b], ti, 0, 0, 0);
+            accR[i] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[a], al[b], accR[i], 0, 0, 0);
+            accR[i] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[a], ah[b], accR[i], 0, 0, 0);
+            accR[i] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[a], al[b], accR[i], 0, 0, 0);
+            accR[i] = __builtin_amdgcn_mfma_f32_16x16x32_f16(bh[a], bl[b], accR[i], 0, 0, 0);
+            accR[i] = __builtin_amdgcn_mfma_f32_16x16x32_f16(bl[a], bh[b], accR[i], 0, 0, 0);
+            accR[i] = __builtin_amdgcn_mfma_f32_16x16x32_f16(bl[a], bl[b], accR[i], 0, 0, 0);
+            accI[i] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[a], bl[b], accI[i], 0, 0, 0);
+            accI[i] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[a], bh[b], accI[i], 0, 0, 0);
+            accI[i] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[a], bl[b], accI[i], 0, 0, 0);
+            accI[i] = __builtin_amdgcn_mfma_f32_16x16x32_f16(nbh, al[b], accI[i], 0, 0, 0);
+            accI[i] = __builtin_amdgcn_mfma_f32_16x16x32_f16(nbl, ah[b], accI[i], 0, 0, 0);
+            accI[i] = __builtin_amdgcn_mfma_f32_16x16x32_f16(nbl, al[b], accI[i], 0, 0, 0);
+          }
 #pragma unroll
-              for (int v = 0; v < 4; ++v) acc64[pi - P0][v] += (double)t[v];
-            }
+          for (int v = 0; v < 4; ++v) {
+            sR[i][v] += (double)tr[v];
+            sI[i][v] += (double)ti[v];
           }
         }
       }
-    }
-    if constexpr (FLUSH) {
       if (++since_flush == 16) {
         since_flush = 0;
 #pragma unroll
         for (int i = 0; i < NPG; ++i) {
 #pragma unroll
-          for (int v = 0; v < 4; ++v) acc64[i][v] += (double)acc[i][v];
-          acc[i] = ACC{0, 0, 0, 0};
+          for (int v = 0; v < 4; ++v) {
+            sR[i][v] += (double)accR[i][v];
+            sI[i][v] += (double)accI[i][v];
+          }
+          accR[i] = ACC{0, 0, 0, 0};
+          accI[i] = ACC{0, 0, 0, 0};
         }
       }
     }
+  };
+
+  const char* qb = reinterpret_cast<const char*>(qk);
+  const char* wb = reinterpret_cast<const char*>(sqrtw);
+  const int64_t rowb = M * (int64_t)sizeof(C);
+  if (c0 < c1) stage_issue<NT>(lds, qb + c0 * 1024, rowb, wb + c0 * CD * (int64_t)sizeof(T), L, wave, lane);
+#pragma unroll 1
+  for (int64_t c = c0; c < c1; ++c) {
+    char* cur = lds + ((c - c0) & 1) * GS::BYTES;
+    char* nxt = lds + (((c - c0) & 1) ^ 1) * GS::BYTES;
+    // prefetch the next chunk (the last one re-reads itself into the free stage)
+    const int64_t cn = c + 1 < c1 ? c + 1 : c;
+    stage_issue<NT>(nxt, qb + cn * 1024, rowb, wb + cn * CD * (int64_t)sizeof(T), L, wave, lane);
+    // wait for this wave's loads of chunk c (the NI of chunk c+1 stay in
+    // flight), then for everybody's.  A bare s_barrier: __syncthreads() would
+    // add a release fence that drains the prefetch as well.
+    __builtin_amdgcn_s_waitcnt((GS::NI & 15) | ((GS::NI >> 4) << 14) | (7 << 4) | (15 << 8));
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int gw = 0; gw < GPW; ++gw) {
+      const int base = (wave * GPW + gw) * GDOF + g4 * DPL;   // this lane's run within the chunk
+      Raw<MODE, NT> r;
+#pragma unroll
+      for (int a = 0; a < NT; ++a) {
+        if (!((NEED >> a) & 1u)) continue;
+        const v4f* src = reinterpret_cast<const v4f*>(cur + (16 * a + r16) * GS::RSB + base * (int)sizeof(C));
+        constexpr int NV = (int)(sizeof(C) * DPL / 16);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const v4f f = src[v];
+          if constexpr (sizeof(C) == 8) {
+            r.x[a][2 * v] = C{f[0], f[1]};
+            r.x[a][2 * v + 1] = C{f[2], f[3]};
+          } else {
+            double2 d;
+            __builtin_memcpy(&d, &f, 16);
+            r.x[a][v] = d;
+          }
+        }
+      }
+      const v4f* wsrc = reinterpret_cast<const v4f*>(cur + 16 * NT * GS::RSB + base * (int)sizeof(T));
+      constexpr int NW = (int)(sizeof(T) * DPL / 16);
+#pragma unroll
+      for (int v = 0; v < NW; ++v) {
+        const v4f f = wsrc[v];
+        __builtin_memcpy(&r.w[v * (16 / (int)sizeof(T))], &f, 16);
+      }
+      compute(r);
+    }
+    // every wave's LDS reads of `cur` are done before anyone refills it
+    __builtin_amdgcn_s_waitcnt(15 | (3 << 14) | (7 << 4) | (0 << 8));
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_sched_barrier(0);
   }
+  // remaining degrees of freedom (ragged end, or everything when unaligned)
+  if (s == S - 1) {
+    const int64_t m_rem = nchunk * CD;
+    const int64_t ng = (M - m_rem + GDOF - 1) / GDOF;
+#pragma unroll 1
+    for (int64_t g = wave; g < ng; g += 4) {
+      Raw<MODE, NT> r;
+      gram_load_any<MODE, NT, NEED>(r, qk, sqrtw, m_rem + g * GDOF + g4 * DPL, M, L, r16);
+      compute(r);
+    }
+  }
+  if constexpr (MODE == G_F64) {
 #pragma unroll
-  for (int i = 0; i < NPG; ++i) {
+    for (int i = 0; i < NPG; ++i)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) acc64[i][v] += (double)acc[i][v];
+      for (int v = 0; v < 4; ++v) {
+        sR[i][v] = accR[i][v];
+        sI[i][v] = accI[i][v];
+      }
+  } else if constexpr (SPLIT) {
+#pragma unroll
+    for (int i = 0; i < NPG; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        sR[i][v] += (double)accR[i][v];
+        sI[i][v] += (double)accI[i][v];
+      }
   }
   if constexpr (MODE == G_FP16X4) {
     const double inv = 1.0 / ((double)scale * (double)scale);
 #pragma unroll
     for (int i = 0; i < NPG; ++i)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) acc64[i][v] *= inv;
+      for (int v = 0; v < 4; ++v) {
+        sR[i][v] *= inv;
+        sI[i][v] *= inv;
+      }
   }
 
-  // sum the four waves in LDS (the tile buffer is free now), one wave at a time
-  double* red = reinterpret_cast<double*>(Y);
-  static_assert(sizeof(TL) * D * LDY >= sizeof(double) * NPG * 4 * 64, "reduction buffer");
+  // the stages are reused for the reduction: drain the last (re-read)
+  // prefetch of every wave first
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
+  // sum the four waves through LDS, one wave at a time
 #pragma unroll 1
   for (int w = 0; w < 4; ++w) {
     if (wave == w) {
@@ -253,74 +510,74 @@ __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __res
       for (int i = 0; i < NPG; ++i)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          double* r = &red[(i * 4 + v) * 64 + lane];
-          *r = (w == 0) ? acc64[i][v] : *r + acc64[i][v];
+          double* rr = &red[((2 * i) * 4 + v) * 64 + lane];
+          double* ri = &red[((2 * i + 1) * 4 + v) * 64 + lane];
+          *rr = (w == 0) ? sR[i][v] : *rr + sR[i][v];
+          *ri = (w == 0) ? sI[i][v] : *ri + sI[i][v];
         }
     }
     __syncthreads();
   }
   // element (lane, v) of a 16x16 result tile sits in column lane%16 and row
   // 4*(lane/16)+v for the FP32-accumulating instructions, but row lane/16+4*v
-  // for v_mfma_f64_16x16x4f64
-  double* out = part + ((int64_t)k * S + s) * D * D;
+  // for v_mfma_f64_16x16x4f64.  Partials are stored as complex [D][D].
+  double2* out = reinterpret_cast<double2*>(part) + ((int64_t)k * S + s) * D * D;
   for (int idx = tid; idx < NPG * 4 * 64; idx += 256) {
     const int ln = idx & 63;
     const int v = (idx >> 6) & 3;
-    const int pi = P0 + (idx >> 8);
-    int a = 0, rem = pi;
-    while (rem >= NTI - a) {
-      rem -= NTI - a;
+    const int i = idx >> 8;
+    int a = 0, rem = P0 + i;
+    while (rem >= NT - a) {
+      rem -= NT - a;
       ++a;
     }
     const int b = a + rem;
     const int r = (MODE == G_F64) ? (ln >> 4) + 4 * v : 4 * (ln >> 4) + v;
-    out[(16 * a + r) * D + 16 * b + (ln & 15)] = red[idx];
+    out[(16 * a + r) * D + 16 * b + (ln & 15)] =
+        make_double2(red[((2 * i) * 4 + v) * 64 + ln], red[((2 * i + 1) * 4 + v) * 64 + ln]);
   }
 }
 
-template <int MODE, int NTI>
-__global__ __launch_bounds__(256) void gram_kernel(const typename GramCfg<MODE>::C* __restrict__ qhat,
-                                                   const void* __restrict__ sqrtw_v,
-                                                   const float* __restrict__ fscale,
-                                                   double* __restrict__ part, int64_t M, int L,
-                                                   int S) {
-  using Cfg = GramCfg<MODE>;
-  using TL = typename Cfg::TL;
-  constexpr int D = 16 * NTI;
-  constexpr int LDY = Cfg::MC + (sizeof(TL) == 8 ? 4 : 8);
-  constexpr int NP = NTI * (NTI + 1) / 2;
+template <int MODE, int NT>
+__global__ __launch_bounds__(256, 2) void gram_kernel(const typename GramCfg<MODE>::C* __restrict__ qhat,
+                                                      const void* __restrict__ sqrtw_v,
+                                                      const float* __restrict__ fscale,
+                                                      double* __restrict__ part, int64_t M, int L,
+                                                      int S, int vec) {
+  using T = typename GramCfg<MODE>::T;
+  constexpr int NP = NT * (NT + 1) / 2;
   constexpr int NG = (NP + PG - 1) / PG;
-  __shared__ TL Y[D * LDY];
-  const TL* sqrtw = static_cast<const TL*>(sqrtw_v);
+  extern __shared__ __attribute__((aligned(16))) char gram_lds[];   // 2 stages
+  double* red = reinterpret_cast<double*>(gram_lds);                // reused after the loop
+  const T* sqrtw = static_cast<const T*>(sqrtw_v);
   const float scale = (MODE == G_FP16X4) ? fscale[blockIdx.y] : 1.0f;
   switch (blockIdx.z) {
-    case 0: gram_body<MODE, NTI, 0>(qhat, sqrtw, scale, part, M, L, S, Y); break;
-    case 1: if constexpr (NG > 1) gram_body<MODE, NTI, 1>(qhat, sqrtw, scale, part, M, L, S, Y); break;
-    case 2: if constexpr (NG > 2) gram_body<MODE, NTI, 2>(qhat, sqrtw, scale, part, M, L, S, Y); break;
-    case 3: if constexpr (NG > 3) gram_body<MODE, NTI, 3>(qhat, sqrtw, scale, part, M, L, S, Y); break;
+    case 0: gram_body<MODE, NT, 0>(qhat, sqrtw, scale, part, M, L, S, vec != 0, red, gram_lds); break;
+    case 1: if constexpr (NG > 1) gram_body<MODE, NT, 1>(qhat, sqrtw, scale, part, M, L, S, vec != 0, red, gram_lds); break;
+    case 2: if constexpr (NG > 2) gram_body<MODE, NT, 2>(qhat, sqrtw, scale, part, M, L, S, vec != 0, red, gram_lds); break;
+    case 3: if constexpr (NG > 3) gram_body<MODE, NT, 3>(qhat, sqrtw, scale, part, M, L, S, vec != 0, red, gram_lds); break;
     default: break;
   }
 }
 
-// Sum the S slices of P in FP64 and assemble the complex Hermitian M_k.
-__global__ __launch_bounds__(256) void gram_combine_kernel(const double* __restrict__ part,
+// Sum the S partial Grams in FP64.  Each partial holds the 16 x 16 blocks
+// (a, b) with a <= b; an entry (i, j) of a lower block is conj of (j, i).
+__global__ __launch_bounds__(256) void gram_combine_kernel(const double2* __restrict__ part,
                                                            double2* __restrict__ gram, int L, int D,
                                                            int S) {
   const int k = blockIdx.x;
-  const double* pk = part + (int64_t)k * S * D * D;
+  const double2* pk = part + (int64_t)k * S * D * D;
   for (int idx = threadIdx.x; idx < L * L; idx += blockDim.x) {
     const int i = idx / L, j = idx % L;
-    // P is stored on upper tiles (tile(row) <= tile(col)); mirror otherwise
-    auto at = [&](const double* P, int r, int c) {
-      return ((r >> 4) <= (c >> 4)) ? P[r * D + c] : P[c * D + r];
-    };
+    const bool up = (i >> 4) <= (j >> 4);
+    const int off = up ? i * D + j : j * D + i;
     double re = 0.0, im = 0.0;
     for (int s = 0; s < S; ++s) {
-      const double* P = pk + (int64_t)s * D * D;
-      re += at(P, i, j) + at(P, L + i, L + j);
-      im += at(P, i, L + j) - at(P, L + i, j);
+      const double2 v = pk[(int64_t)s * D * D + off];
+      re += v.x;
+      im += v.y;
     }
-    gram[((int64_t)k * L + i) * L + j] = make_double2(re, im);
+    gram[((int64_t)k * L + i) * L + j] = make_double2(re, up ? im : -im);
   }
 }
 
@@ -356,7 +613,7 @@ __global__ __launch_bounds__(256) void gram_scale_kernel(const float2* __restric
 // ---------------------------------------------------------------------------
 size_t csd_workspace(const Plan& p) {
   const size_t D = (size_t)p.gram_dim;
-  size_t b = sizeof(double) * (size_t)p.nfreq * (size_t)p.gram_split * D * D;
+  size_t b = sizeof(double2) * (size_t)p.nfreq * (size_t)p.gram_split * D * D;
   if (p.prec == SPOD_PREC_FP16X4) b += sizeof(float) * (size_t)p.nfreq + 256;
   return b;
 }
@@ -367,9 +624,16 @@ static void launch_gram_nti(const Plan& p, const void* qhat, const void* sqrtw, 
   using C = typename GramCfg<MODE>::C;
   constexpr int NP = NTI * (NTI + 1) / 2;
   dim3 grid((unsigned)p.gram_split, (unsigned)p.nfreq, (unsigned)((NP + PG - 1) / PG));
-  hipLaunchKernelGGL((gram_kernel<MODE, NTI>), grid, dim3(256), 0, st,
+  // 16-byte loads need 16-byte aligned rows (an aligned base and, for
+  // complex64, an even M) and 16-byte aligned weights
+  const bool vec = ((uintptr_t)qhat % 16 == 0) && (sizeof(C) == 16 || p.M % 2 == 0) &&
+                   ((uintptr_t)sqrtw % 16 == 0);
+  const size_t lds = 2 * (size_t)GramStage<NTI>::BYTES;
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gram_kernel<MODE, NTI>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL((gram_kernel<MODE, NTI>), grid, dim3(256), lds, st,
                      static_cast<const C*>(qhat), sqrtw, fs, part, (int64_t)p.M, (int)p.nblocks,
-                     p.gram_split);
+                     p.gram_split, (int)vec);
 }
 
 template <int MODE>
@@ -380,10 +644,6 @@ static spod_status launch_gram_mode(const Plan& p, const void* qhat, const void*
     case 2: launch_gram_nti<MODE, 2>(p, qhat, sqrtw, fs, part, st); break;
     case 3: launch_gram_nti<MODE, 3>(p, qhat, sqrtw, fs, part, st); break;
     case 4: launch_gram_nti<MODE, 4>(p, qhat, sqrtw, fs, part, st); break;
-    case 5: launch_gram_nti<MODE, 5>(p, qhat, sqrtw, fs, part, st); break;
-    case 6: launch_gram_nti<MODE, 6>(p, qhat, sqrtw, fs, part, st); break;
-    case 7: launch_gram_nti<MODE, 7>(p, qhat, sqrtw, fs, part, st); break;
-    case 8: launch_gram_nti<MODE, 8>(p, qhat, sqrtw, fs, part, st); break;
     default: return fail(SPOD_ERR_UNSUPPORTED, "nblocks > 64");
   }
   hipError_t e = hipGetLastError();
@@ -395,7 +655,7 @@ spod_status launch_csd(const Plan& p, const void* qhat, void* gram, void* ws, hi
   double* part = static_cast<double*>(ws);
   const size_t D = (size_t)p.gram_dim;
   float* fs = reinterpret_cast<float*>(
-      static_cast<char*>(ws) + sizeof(double) * (size_t)p.nfreq * (size_t)p.gram_split * D * D);
+      static_cast<char*>(ws) + sizeof(double2) * (size_t)p.nfreq * (size_t)p.gram_split * D * D);
   spod_status s;
   switch (p.prec) {
     case SPOD_PREC_FP64: s = launch_gram_mode<G_F64>(p, qhat, p.d_sqrtw, nullptr, part, st); break;
@@ -410,8 +670,9 @@ spod_status launch_csd(const Plan& p, const void* qhat, void* gram, void* ws, hi
     default: return fail(SPOD_ERR_INVALID_ARG, "precision");
   }
   if (s != SPOD_OK) return s;
-  hipLaunchKernelGGL(gram_combine_kernel, dim3((unsigned)p.nfreq), dim3(256), 0, st, part,
-                     static_cast<double2*>(gram), (int)p.nblocks, (int)D, p.gram_split);
+  hipLaunchKernelGGL(gram_combine_kernel, dim3((unsigned)p.nfreq), dim3(256), 0, st,
+                     reinterpret_cast<const double2*>(part), static_cast<double2*>(gram),
+                     (int)p.nblocks, (int)D, p.gram_split);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SPOD_OK : hip_fail(e, "gram_combine_kernel");
 }

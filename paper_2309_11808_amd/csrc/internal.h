@@ -23,6 +23,16 @@ struct Plan {
 
   double kappa = 0.0;   // 1/sqrt((L-1) sum w^2)
 
+  // Bins where the window's own DFT  What_k = sum_n w[n] e^{-2 pi i k n / N}
+  // is not zero (k = 0, 1 for the periodic Hann window).  When there are at
+  // most SPOD_MAX_MEAN_BINS of them, the transform removes the mean in the
+  // same pass over q (see fft.hip); otherwise it runs a separate mean pass.
+  static constexpr int SPOD_MAX_MEAN_BINS = 4;
+  int n_mean_bins = -1;                    // -1: too many, use the separate pass
+  int mean_bin[SPOD_MAX_MEAN_BINS] = {0, 0, 0, 0};
+  double what_re[SPOD_MAX_MEAN_BINS] = {0, 0, 0, 0};
+  double what_im[SPOD_MAX_MEAN_BINS] = {0, 0, 0, 0};
+
   // options
   int max_sweeps = 40;
   int64_t gram_split_opt = 0;
@@ -30,7 +40,7 @@ struct Plan {
 
   // derived launch shapes (fixed when frozen)
   int gram_split = 1;       // slices of M per frequency
-  int gram_dim = 0;         // padded realified size (multiple of 16) >= 2L
+  int gram_dim = 0;         // L rounded up to a multiple of 16 (Gram tile size)
   size_t ws_bytes = 0;
 
   // device copies owned by the plan

@@ -23,7 +23,8 @@ __global__ __launch_bounds__(256) void modes_kernel(const cpx_t<TC>* __restrict_
                                                     int32_t* __restrict__ n_valid, int64_t M, int L,
                                                     int n_modes, double eps) {
   using C = cpx_t<TC>;
-  __shared__ C coef[MODES_MAXL * MODES_MAXL];
+  extern __shared__ char modes_lds[];
+  C* coef = reinterpret_cast<C*>(modes_lds);   // [L][n_modes]
   const int k = blockIdx.y;
   const int tid = threadIdx.x;
   const double* lk = lam + (int64_t)k * L;
@@ -73,13 +74,14 @@ spod_status launch_modes(const Plan& p, const void* qhat, const double* lam, con
   (void)ws;
   if (p.nblocks > MODES_MAXL) return fail(SPOD_ERR_UNSUPPORTED, "nblocks > 64");
   dim3 grid((unsigned)((p.M + 255) / 256), (unsigned)p.nfreq);
+  const size_t lds = (is_complex128(p) ? 16 : 8) * (size_t)p.nblocks * (size_t)n_modes;
   if (is_complex128(p))
-    hipLaunchKernelGGL(modes_kernel<double>, grid, dim3(256), 0, st,
+    hipLaunchKernelGGL(modes_kernel<double>, grid, dim3(256), lds, st,
                        static_cast<const double2*>(qhat), lam, static_cast<const double2*>(psi),
                        static_cast<double2*>(phi), n_valid, (int64_t)p.M, (int)p.nblocks, n_modes,
                        1e-12);
   else
-    hipLaunchKernelGGL(modes_kernel<float>, grid, dim3(256), 0, st,
+    hipLaunchKernelGGL(modes_kernel<float>, grid, dim3(256), lds, st,
                        static_cast<const float2*>(qhat), lam, static_cast<const double2*>(psi),
                        static_cast<float2*>(phi), n_valid, (int64_t)p.M, (int)p.nblocks, n_modes,
                        1e-6);

@@ -40,31 +40,40 @@ def _rand_problem(M, nt, nfft, nov, seed, dtype=torch.float64, offset=0.0):
 # stage 1-2: mean and Fourier blocks
 # ---------------------------------------------------------------------------
 FFT_CASES = [
-    # nfft, noverlap, M, extra samples, input dtype, offset
-    (8, 4, 37, 3, torch.float64, 0.0),
-    (16, 8, 65, 0, torch.float64, 5.0),
-    (32, 0, 33, 7, torch.float64, 0.0),
-    (64, 32, 129, 11, torch.float64, 100.0),
-    (64, 48, 31, 5, torch.float64, 0.0),
-    (128, 64, 70, 0, torch.float32, 3.0),
-    (128, 96, 17, 9, torch.float64, 0.0),
-    (256, 128, 97, 13, torch.float32, 0.0),
-    (256, 0, 40, 1, torch.float64, 0.0),
-    (512, 256, 67, 100, torch.float32, 10.0),
-    (512, 128, 33, 0, torch.float64, 0.0),
-    (1024, 512, 35, 17, torch.float64, 1.0),
-    (1024, 512, 19, 0, torch.float32, 0.0),
+    # nfft, noverlap, M, extra samples, input dtype, offset, window
+    (8, 4, 37, 3, torch.float64, 0.0, "hann"),
+    (16, 8, 65, 0, torch.float64, 5.0, "random"),
+    (32, 0, 33, 7, torch.float64, 0.0, "hamming"),
+    (64, 32, 129, 11, torch.float64, 100.0, "hann"),
+    (64, 48, 31, 5, torch.float64, 0.0, "hann"),
+    (128, 64, 70, 0, torch.float32, 3.0, "random"),
+    (128, 96, 17, 9, torch.float64, 0.0, "hamming"),
+    (256, 128, 97, 13, torch.float32, 0.0, "hann"),
+    (256, 0, 40, 1, torch.float64, 0.0, "hann"),
+    (512, 256, 67, 100, torch.float32, 10.0, "hann"),
+    (512, 256, 45, 3, torch.float32, 0.0, "random"),
+    (512, 128, 33, 0, torch.float64, 0.0, "hann"),
+    (1024, 512, 35, 17, torch.float64, 1.0, "hamming"),
+    (1024, 512, 19, 0, torch.float32, 0.0, "hann"),
 ]
 
 
+def _window(kind, nfft, seed):
+    if kind == "hann":
+        return None
+    if kind == "hamming":                      # two non-zero DFT bins: single-pass mean
+        return 0.54 - 0.46 * np.cos(2 * np.pi * np.arange(nfft) / nfft)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.uniform(0.1, 1.0, nfft)         # every bin non-zero: separate mean pass
+
+
 @pytest.mark.parametrize("prec", ["fp64", "bf16x4"])
-@pytest.mark.parametrize("nfft,nov,M,extra,dtype,offset", FFT_CASES)
-def test_blocks_fft_matches_oracle(prec, nfft, nov, M, extra, dtype, offset):
+@pytest.mark.parametrize("nfft,nov,M,extra,dtype,offset,wkind", FFT_CASES)
+def test_blocks_fft_matches_oracle(prec, nfft, nov, M, extra, dtype, offset, wkind):
     L = 3 + (nfft % 5)
     nt = (L - 1) * (nfft - nov) + nfft + extra
     p = _rand_problem(M, nt, nfft, nov, seed=nfft + M, dtype=dtype, offset=offset)
-    rng = np.random.Generator(np.random.PCG64(nfft))
-    window = None if nfft % 3 else rng.uniform(0.1, 1.0, nfft)      # some custom windows
+    window = _window(wkind, nfft, nfft)
     plan = _plan(p, prec, window=window)
     qhat, mean = plan.blocks_fft(p.q.cuda())
     torch.cuda.synchronize()
