@@ -162,17 +162,42 @@ spod_status spod_modes(spod_plan plan, const void* qhat, const double* lam, cons
                        int64_t n_modes, void* phi, int32_t* n_valid, void* ws, size_t ws_bytes,
                        spod_stream stream);
 
-/* Adjoint of steps 1-5 (not in the paper): given the gradients of a real loss
- * with respect to lam (g_lam, device [K][L] float64, or NULL) and phi (g_phi,
- * device [K][n_modes][M] in phi's complex type, PyTorch convention
- * dE/dRe + i dE/dIm, or NULL), writes g_q = dE/dq (device [M][nt] of `dtype`).
- * lam and psi are the outputs of spod_eig for the same q.  The Fourier blocks
- * are recomputed from q rather than stored.  Eigenvector derivatives use the
- * distinct-eigenvalue formula (pairs closer than 1e-12 relative are dropped)
- * and assume a loss invariant to eigenvector phases. */
-spod_status spod_backward(spod_plan plan, const void* q, spod_dtype dtype, const double* lam,
-                          const void* psi, const double* g_lam, const void* g_phi,
-                          int64_t n_modes, void* g_q, void* ws, size_t ws_bytes,
+/* Adjoint of steps 1-5 (not in the paper): the gradient of a real loss E with
+ * respect to the raw data q, given the gradients with respect to the outputs
+ * of spod_eig and spod_modes.  Complex gradients follow the convention
+ * dE/dRe + i dE/dIm.
+ *   q      : device [M][nt] of `dtype`; only read when qhat is NULL.
+ *   dtype  : SPOD_F32 or SPOD_F64; the type of q and of g_q.
+ *   qhat   : device [K][L][M], the output of spod_blocks_fft for the same q,
+ *            or NULL: the Fourier blocks are then recomputed from q (at the
+ *            selected bins only) into g_qhat, so nothing of size K*L*M needs
+ *            to be kept from the forward pass.
+ *   lam, psi : the outputs of spod_eig for the same q.
+ *   g_lam  : device [n_bins][L] float64 (dE/dlam at the selected bins) or NULL
+ *            (zero).
+ *   g_phi  : device [n_bins][n_modes][M] in phi's complex type (dE/dphi at the
+ *            selected bins), or NULL (zero; n_modes is then ignored).
+ *   bins   : host [n_bins] strictly increasing frequencies in [0, K): row s of
+ *            g_lam, g_phi and g_qhat belongs to frequency bins[s], and the
+ *            gradients at every other frequency are zero.  Copied during the
+ *            call.  NULL means all K frequencies in order (n_bins ignored).
+ *   g_qhat : device [n_bins][L][M] scratch of qhat's complex type (n_bins = K
+ *            when bins is NULL): receives dE/dqhat at the selected bins.  With
+ *            bins == NULL it may be the same buffer as qhat (qhat is then
+ *            overwritten); with a selection it must not overlap qhat.
+ *   g_q    : device [M][nt] of `dtype`: receives dE/dq (every entry written).
+ * The chain, per selected frequency: modes adjoint (Phi = Qhat Psi
+ * Lambda^{-1/2}); derivative of the phase convention of spod_eig; eigenvector
+ * and eigenvalue adjoint of M_k (distinct-eigenvalue formula: pairs closer
+ * than 1e-12 of the largest eigenvalue contribute nothing); Gram adjoint
+ * 2 W Qhat G; then the adjoint of the windowed one-sided DFT, the overlap-add
+ * of the blocks and the mean removal.  Modes that spod_modes zero-fills are
+ * constants here.  Returns SPOD_ERR_UNSUPPORTED when nfft < 16, when the hop
+ * nfft - noverlap is not nfft/4, nfft/2 or nfft, or when nblocks > 64. */
+spod_status spod_backward(spod_plan plan, const void* q, spod_dtype dtype, const void* qhat,
+                          const double* lam, const void* psi, const double* g_lam,
+                          const void* g_phi, int64_t n_modes, const int32_t* bins,
+                          int64_t n_bins, void* g_qhat, void* g_q, void* ws, size_t ws_bytes,
                           spod_stream stream);
 
 /* Free the plan's device copies.  NULL-safe.  Synchronises the plan's device. */

@@ -46,7 +46,8 @@ SIGNATURES = {
     "spod_csd": (C.c_int, [_p, _p, _p, _p, _sz, _p]),
     "spod_eig": (C.c_int, [_p, _p, _p, _p, _p, _p, _sz, _p]),
     "spod_modes": (C.c_int, [_p, _p, _p, _p, _i64, _p, _p, _p, _sz, _p]),
-    "spod_backward": (C.c_int, [_p, _p, C.c_int, _p, _p, _p, _p, _i64, _p, _p, _sz, _p]),
+    "spod_backward": (C.c_int, [_p, _p, C.c_int, _p, _p, _p, _p, _p, _i64, _p, _i64, _p, _p, _p,
+                                _sz, _p]),
     "spod_plan_destroy": (None, [_p]),
     "spod_status_string": (C.c_char_p, [C.c_int]),
     "spod_last_error": (C.c_char_p, []),

@@ -104,7 +104,7 @@ void spod_plan_destroy(spod_plan plan) {
   if (hipGetDevice(&cur) == hipSuccess && cur != p->device) (void)hipSetDevice(p->device);
   (void)hipDeviceSynchronize();
   void* bufs[] = {p->d_window, p->d_window32, p->d_weights, p->d_sqrtw,
-                  p->d_sqrtw32, p->d_tw64, p->d_tw32};
+                  p->d_sqrtw32, p->d_tw64, p->d_tw32, p->d_what};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (cur != p->device) (void)hipSetDevice(cur);
@@ -159,13 +159,14 @@ spod_status spod_plan_create(int64_t nspace, int64_t nvar, int64_t nt, int64_t n
   p->nblocks = L;
   p->nfreq = K;
   p->kappa = 1.0 / std::sqrt((double)(L - 1) * sw2);
+  // DFT of the window at every one-sided bin, What_k = sum_n w[n] e^{-2 pi i k n / N},
+  // in long double with exact integer reduction of k*n mod N
+  std::vector<double2> what(K);
   {
-    // DFT of the window at the one-sided bins, in long double with exact
-    // integer reduction of k*n mod N
     long double sabs = 0.0L;
     for (int64_t n = 0; n < nfft; ++n) sabs += fabsl((long double)w[n]);
     int cnt = 0;
-    for (int64_t k = 0; k < K && cnt >= 0; ++k) {
+    for (int64_t k = 0; k < K; ++k) {
       long double re = 0.0L, im = 0.0L;
       for (int64_t n = 0; n < nfft; ++n) {
         const long double a = 2.0L * 3.14159265358979323846264338327950288L *
@@ -173,15 +174,16 @@ spod_status spod_plan_create(int64_t nspace, int64_t nvar, int64_t nt, int64_t n
         re += (long double)w[n] * cosl(a);
         im -= (long double)w[n] * sinl(a);
       }
-      if (sqrtl(re * re + im * im) > 1e-12L * sabs) {
+      what[k] = make_double2((double)re, (double)im);
+      if (cnt >= 0 && sqrtl(re * re + im * im) > 1e-12L * sabs) {
         if (cnt == Plan::SPOD_MAX_MEAN_BINS) {
           cnt = -1;
-          break;
+        } else {
+          p->mean_bin[cnt] = (int)k;
+          p->what_re[cnt] = (double)re;
+          p->what_im[cnt] = (double)im;
+          ++cnt;
         }
-        p->mean_bin[cnt] = (int)k;
-        p->what_re[cnt] = (double)re;
-        p->what_im[cnt] = (double)im;
-        ++cnt;
       }
     }
     p->n_mean_bins = cnt;
@@ -216,6 +218,7 @@ spod_status spod_plan_create(int64_t nspace, int64_t nvar, int64_t nt, int64_t n
       {(void**)&p->d_sqrtw32, sq32.data(), sizeof(float) * M},
       {(void**)&p->d_tw64, tw.data(), sizeof(double2) * nfft},
       {(void**)&p->d_tw32, tw32.data(), sizeof(float2) * nfft},
+      {(void**)&p->d_what, what.data(), sizeof(double2) * K},
   };
   for (auto& u : ups) {
     e = hipMalloc(u.dst, u.bytes);
@@ -348,21 +351,39 @@ spod_status spod_modes(spod_plan plan, const void* qhat, const double* lam, cons
   return launch_modes(*p, qhat, lam, psi, (int)n_modes, phi, n_valid, ws, (hipStream_t)stream);
 }
 
-spod_status spod_backward(spod_plan plan, const void* q, spod_dtype dtype, const double* lam,
-                          const void* psi, const double* g_lam, const void* g_phi,
-                          int64_t n_modes, void* g_q, void* ws, size_t ws_bytes,
+spod_status spod_backward(spod_plan plan, const void* q, spod_dtype dtype, const void* qhat,
+                          const double* lam, const void* psi, const double* g_lam,
+                          const void* g_phi, int64_t n_modes, const int32_t* bins,
+                          int64_t n_bins, void* g_qhat, void* g_q, void* ws, size_t ws_bytes,
                           spod_stream stream) {
   Plan* p = reinterpret_cast<Plan*>(plan);
-  spod_status st = enter(p);
-  if (st != SPOD_OK) return st;
-  if (!q || !lam || !psi || !g_q)
-    return fail(SPOD_ERR_INVALID_ARG, "q, lam, psi and g_q are required");
+  if (!p) return fail(SPOD_ERR_INVALID_ARG, "plan is NULL");
+  if (!lam || !psi || !g_qhat || !g_q)
+    return fail(SPOD_ERR_INVALID_ARG, "lam, psi, g_qhat and g_q are required");
+  if (!qhat && !q) return fail(SPOD_ERR_INVALID_ARG, "q is required when qhat is NULL");
   if (dtype != SPOD_F32 && dtype != SPOD_F64) return fail(SPOD_ERR_INVALID_ARG, "dtype");
   if (g_phi && (n_modes < 1 || n_modes > p->nblocks))
     return fail(SPOD_ERR_INVALID_ARG, "n_modes must be in [1, nblocks]");
+  if (bins) {
+    if (n_bins < 1 || n_bins > p->nfreq)
+      return fail(SPOD_ERR_INVALID_ARG, "n_bins must be in [1, nfreq]");
+    for (int64_t i = 0; i < n_bins; ++i) {
+      if (bins[i] < 0 || bins[i] >= p->nfreq || (i > 0 && bins[i] <= bins[i - 1]))
+        return fail(SPOD_ERR_INVALID_ARG, "bins must be strictly increasing in [0, nfreq)");
+    }
+    if (qhat && qhat == g_qhat)
+      return fail(SPOD_ERR_INVALID_ARG, "g_qhat may alias qhat only without a bin selection");
+  }
+  if (p->nfft < 16) return fail(SPOD_ERR_UNSUPPORTED, "backward needs nfft >= 16");
+  if (p->step != p->nfft && p->step != p->nfft / 2 && p->step != p->nfft / 4)
+    return fail(SPOD_ERR_UNSUPPORTED, "backward needs a hop of nfft/4, nfft/2 or nfft");
+  if (p->nblocks > 64) return fail(SPOD_ERR_UNSUPPORTED, "nblocks > 64");
+  spod_status st = enter(p);
+  if (st != SPOD_OK) return st;
   st = check_ws(*p, ws, ws_bytes, backward_workspace(*p));
   if (st != SPOD_OK) return st;
-  return launch_backward(*p, q, dtype, lam, psi, g_lam, g_phi, g_phi ? (int)n_modes : 0, g_q, ws,
+  return launch_backward(*p, q, dtype, qhat, lam, psi, g_lam, g_phi, g_phi ? (int)n_modes : 0,
+                         bins, bins ? (int)n_bins : (int)p->nfreq, g_qhat, g_q, ws,
                          (hipStream_t)stream);
 }
 

@@ -16,6 +16,7 @@
 // of T complex values.
 #include <hip/hip_runtime.h>
 
+#include "fft_core.h"
 #include "internal.h"
 
 namespace spod {
@@ -35,121 +36,6 @@ __global__ __launch_bounds__(256) void mean_kernel(const TIN* __restrict__ q, do
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
   if (lane == 0) mean[m] = s / (double)nt;
-}
-
-// ---------------------------------------------------------------------------
-// in-register DFTs of size 2, 4 and 8 (natural order in and out)
-// ---------------------------------------------------------------------------
-template <typename C>
-__device__ __forceinline__ void dft2(C* x) {
-  C a = x[0], b = x[1];
-  x[0] = cadd(a, b);
-  x[1] = csub(a, b);
-}
-
-template <typename C>
-__device__ __forceinline__ void dft4(C* x) {
-  C c0 = cadd(x[0], x[2]), d0 = csub(x[0], x[2]);
-  C c1 = cadd(x[1], x[3]), d1 = cmul_mi(csub(x[1], x[3]));
-  x[0] = cadd(c0, c1);
-  x[2] = csub(c0, c1);
-  x[1] = cadd(d0, d1);
-  x[3] = csub(d0, d1);
-}
-
-template <typename C>
-__device__ __forceinline__ void dft8(C* x) {
-  using T = decltype(x[0].x);
-  const T h = (T)0.70710678118654752440084436210484903928;
-  // decimation in frequency: a = x[q] + x[q+4], b = (x[q] - x[q+4]) w8^q
-  C a[4], b[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    a[q] = cadd(x[q], x[q + 4]);
-    b[q] = csub(x[q], x[q + 4]);
-  }
-  b[1] = C{h * (b[1].x + b[1].y), h * (b[1].y - b[1].x)};    // * (1 - i)/sqrt2
-  b[2] = cmul_mi(b[2]);                                      // * -i
-  b[3] = C{h * (b[3].y - b[3].x), -h * (b[3].x + b[3].y)};   // * (-1 - i)/sqrt2
-  dft4(a);
-  dft4(b);
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    x[2 * k] = a[k];
-    x[2 * k + 1] = b[k];
-  }
-}
-
-template <int RS, typename C>
-__device__ __forceinline__ void dft_r(C* x) {
-  if constexpr (RS == 2) dft2(x);
-  else if constexpr (RS == 4) dft4(x);
-  else dft8(x);
-}
-
-// LDS layout of one transform: element i at pad(i) = i + i/8, which spreads the
-// stride-8 writes of the first radix-8 stage over all banks; rows (one per
-// transform) are LDP = pad(N) + 1 elements apart so that reading the same
-// frequency of consecutive rows also spreads over the banks.
-__device__ __forceinline__ int pad8(int i) { return i + (i >> 3); }
-
-// Exchange barrier: when a transform lives inside one wavefront (P <= 64) its
-// lanes only need a wavefront-level barrier; otherwise the workgroup's.
-template <bool WAVE>
-__device__ __forceinline__ void xbarrier() {
-  if constexpr (WAVE) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  } else {
-    __syncthreads();
-  }
-}
-
-// One Stockham stage of radix RS after NS points have been combined.  Lane j
-// handles butterflies b = j + u*P (u < 8/RS) over elements b + q*(NF/RS).
-template <int NF, int NS, int RS, typename C>
-__device__ __forceinline__ void stockham_stage(C (&v)[8], C* buf, int j, const C* __restrict__ tw) {
-  constexpr int P = NF / 8;
-  constexpr int U = 8 / RS;
-  constexpr bool LAST = (NS * RS == NF);
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int b = j + u * P;
-    const int kk = b % NS;
-    C x[RS];
-#pragma unroll
-    for (int q = 0; q < RS; ++q) x[q] = v[q * U + u];
-    if constexpr (NS > 1) {
-#pragma unroll
-      for (int q = 1; q < RS; ++q) x[q] = cmul(x[q], tw[q * kk * (NF / (NS * RS))]);
-    }
-    dft_r<RS>(x);
-    if constexpr (LAST) {
-#pragma unroll
-      for (int q = 0; q < RS; ++q) v[q * U + u] = x[q];
-    } else {
-      const int base = (b / NS) * NS * RS + kk;
-#pragma unroll
-      for (int q = 0; q < RS; ++q) buf[pad8(base + q * NS)] = x[q];
-    }
-  }
-  if constexpr (!LAST) {
-    xbarrier<(P <= 64)>();
-#pragma unroll
-    for (int r = 0; r < 8; ++r) v[r] = buf[pad8(j + r * P)];
-    xbarrier<(P <= 64)>();
-  }
-}
-
-template <int NF, int NS, typename C>
-__device__ __forceinline__ void stockham(C (&v)[8], C* buf, int j, const C* __restrict__ tw) {
-  if constexpr (NS < NF) {
-    constexpr int REM = NF / NS;
-    constexpr int RS = REM >= 8 ? 8 : REM;
-    stockham_stage<NF, NS, RS>(v, buf, j, tw);
-    stockham<NF, NS * RS>(v, buf, j, tw);
-  }
 }
 
 // Bins whose window DFT What_k is non-zero, for the single-pass mean removal.
@@ -191,7 +77,7 @@ template <int NF, typename TC, typename TIN, int NPAIR, int SHIFT, bool FUSED>
 __global__ __launch_bounds__(NPAIR*(NF / 8)) void blocks_fft_kernel(
     const TIN* __restrict__ q, double* __restrict__ mean, const double* __restrict__ window,
     const cpx_t<TC>* __restrict__ tw, cpx_t<TC>* __restrict__ qhat, int64_t M, int64_t nt,
-    int step, int L, int bpw, TC kappa, MeanBins mb) {
+    int step, int L, int bpw, TC kappa, MeanBins mb, const int* __restrict__ sel, int nsel) {
   using C = cpx_t<TC>;
   constexpr int P = NF / 8;              // lanes per transform
   constexpr int T = 2 * NPAIR;           // degrees of freedom per tile
@@ -206,6 +92,7 @@ __global__ __launch_bounds__(NPAIR*(NF / 8)) void blocks_fft_kernel(
   __shared__ C lds[NPAIR * LDP];
   __shared__ C twl[TWL ? NF : 1];
   __shared__ double corr[FUSED ? T : 1];
+  __shared__ int ksel[K];                // output row s holds frequency ksel[s] (sel != NULL)
 
   const int tid = threadIdx.x;
   const int f = tid / P;                 // transform (pair) index in the tile
@@ -216,6 +103,8 @@ __global__ __launch_bounds__(NPAIR*(NF / 8)) void blocks_fft_kernel(
   const TIN* ra = q + (va ? ma : 0) * nt;
   const TIN* rb = q + (vb ? mb_ : 0) * nt;
   C* buf = lds + f * LDP;
+  if (sel)
+    for (int i = tid; i < nsel; i += NTH) ksel[i] = sel[i];
 
   TC w[8];
 #pragma unroll
@@ -282,11 +171,13 @@ __global__ __launch_bounds__(NPAIR*(NF / 8)) void blocks_fft_kernel(
     for (int r = 0; r < 8; ++r) buf[pad8(j + r * P)] = v[r];
     __syncthreads();
 
-    // separate the two real spectra and write qhat[k][l][m0 .. m0+T)
+    // separate the two real spectra and write qhat[s][l][m0 .. m0+T), where
+    // output row s holds frequency k = s (or ksel[s] for a bin selection)
     C* out = qhat + (int64_t)l * M;
-    for (int idx = tid; idx < K * T; idx += NTH) {
+    for (int idx = tid; idx < nsel * T; idx += NTH) {
       const int d = idx % T;
-      const int k = idx / T;
+      const int s = idx / T;
+      const int k = sel ? ksel[s] : s;
       const C* row = lds + (d >> 1) * LDP;
       const C A = row[pad8(k)];
       const C Bc = row[pad8((NF - k) & (NF - 1))];
@@ -294,7 +185,7 @@ __global__ __launch_bounds__(NPAIR*(NF / 8)) void blocks_fft_kernel(
       const C X = (d & 1) == 0 ? cadd(A, B) : cmul_mi(csub(A, B));
       const TC sc = (TC)0.5 * kappa;
       const int64_t m = m0 + d;
-      if (m < M) out[(int64_t)k * L * M + m] = C{X.x * sc, X.y * sc};
+      if (m < M) out[(int64_t)s * L * M + m] = C{X.x * sc, X.y * sc};
     }
     __syncthreads();
 
@@ -349,29 +240,21 @@ __global__ __launch_bounds__(NPAIR*(NF / 8)) void blocks_fft_kernel(
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
-// Transforms per workgroup: at least a full wavefront of lanes, at most 512
-// threads by default (more threads cap the registers per lane at 128).
-template <int NF, int BASE>
-struct FftShape {
-  static constexpr int P = NF / 8;
-  static constexpr int NPAIR0 = (BASE * P < 64) ? (64 / P) : BASE;
-  static constexpr int NPAIR = (NPAIR0 * P > 1024) ? (1024 / P) : NPAIR0;
-  static constexpr int T = 2 * NPAIR;
-};
-
 template <int NF, typename TC, typename TIN, int NPAIR, int SHIFT, bool FUSED>
 static void launch_fft_kernel(const Plan& p, dim3 grid, const TIN* q, double* mean, const void* tw,
-                              void* qhat, int bpw, const MeanBins& mb, hipStream_t st) {
+                              void* qhat, int bpw, const MeanBins& mb, const FftSel& fs,
+                              hipStream_t st) {
   using C = cpx_t<TC>;
   constexpr int P = NF / 8;
   hipLaunchKernelGGL((blocks_fft_kernel<NF, TC, TIN, NPAIR, SHIFT, FUSED>), grid, dim3(NPAIR * P), 0,
                      st, q, mean, p.d_window, static_cast<const C*>(tw), static_cast<C*>(qhat),
-                     (int64_t)p.M, (int64_t)p.nt, (int)p.step, (int)p.nblocks, bpw, (TC)p.kappa, mb);
+                     (int64_t)p.M, (int64_t)p.nt, (int)p.step, (int)p.nblocks, bpw, (TC)p.kappa, mb,
+                     fs.d_sel, fs.d_sel ? fs.nsel : (int)p.nfreq);
 }
 
 template <int NF, typename TC, typename TIN, int BASE>
 static spod_status launch_fft_shape(const Plan& p, const TIN* q, double* mean, void* qhat,
-                                    hipStream_t st, bool fused) {
+                                    hipStream_t st, bool fused, const FftSel& fs) {
   using S = FftShape<NF, BASE>;
   constexpr int P = S::P, NPAIR = S::NPAIR, T = S::T;
   const int64_t ntiles = (p.M + T - 1) / T;
@@ -379,20 +262,25 @@ static spod_status launch_fft_shape(const Plan& p, const TIN* q, double* mean, v
   const int L = (int)p.nblocks;
   const void* tw = sizeof(TC) == 4 ? (const void*)p.d_tw32 : (const void*)p.d_tw64;
   MeanBins mb{};
-  mb.n = fused ? p.n_mean_bins : 0;
-  for (int i = 0; i < mb.n; ++i) {
-    mb.k[i] = p.mean_bin[i];
-    mb.wr[i] = p.what_re[i];
-    mb.wi[i] = p.what_im[i];
+  // the correction is applied to the output row of each mean bin (bins outside
+  // a selection are not written at all)
+  mb.n = 0;
+  for (int i = 0; fused && i < p.n_mean_bins; ++i) {
+    const int row = fs.d_sel ? fs.h_slot[p.mean_bin[i]] : p.mean_bin[i];
+    if (row < 0) continue;
+    mb.k[mb.n] = row;
+    mb.wr[mb.n] = p.what_re[i];
+    mb.wi[mb.n] = p.what_im[i];
+    ++mb.n;
   }
   const int shift = (p.step % P == 0) ? (int)(p.step / P) : 0;
   if (fused) {
     if constexpr (P <= 64) {
       dim3 grid((unsigned)ntiles, 1);
       switch (shift) {
-        case 2: launch_fft_kernel<NF, TC, TIN, NPAIR, 2, true>(p, grid, q, mean, tw, qhat, L, mb, st); break;
-        case 4: launch_fft_kernel<NF, TC, TIN, NPAIR, 4, true>(p, grid, q, mean, tw, qhat, L, mb, st); break;
-        case 8: launch_fft_kernel<NF, TC, TIN, NPAIR, 8, true>(p, grid, q, mean, tw, qhat, L, mb, st); break;
+        case 2: launch_fft_kernel<NF, TC, TIN, NPAIR, 2, true>(p, grid, q, mean, tw, qhat, L, mb, fs, st); break;
+        case 4: launch_fft_kernel<NF, TC, TIN, NPAIR, 4, true>(p, grid, q, mean, tw, qhat, L, mb, fs, st); break;
+        case 8: launch_fft_kernel<NF, TC, TIN, NPAIR, 8, true>(p, grid, q, mean, tw, qhat, L, mb, fs, st); break;
         default: return fail(SPOD_ERR_UNSUPPORTED, "fused transform needs hop = N/4, N/2 or N");
       }
     } else {
@@ -407,9 +295,9 @@ static spod_status launch_fft_shape(const Plan& p, const TIN* q, double* mean, v
     chunks = (L + bpw - 1) / bpw;
     dim3 grid((unsigned)ntiles, (unsigned)chunks);
     if (shift == 4)
-      launch_fft_kernel<NF, TC, TIN, NPAIR, 4, false>(p, grid, q, mean, tw, qhat, bpw, mb, st);
+      launch_fft_kernel<NF, TC, TIN, NPAIR, 4, false>(p, grid, q, mean, tw, qhat, bpw, mb, fs, st);
     else
-      launch_fft_kernel<NF, TC, TIN, NPAIR, 0, false>(p, grid, q, mean, tw, qhat, bpw, mb, st);
+      launch_fft_kernel<NF, TC, TIN, NPAIR, 0, false>(p, grid, q, mean, tw, qhat, bpw, mb, fs, st);
   }
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SPOD_OK : hip_fail(e, "blocks_fft_kernel");
@@ -417,7 +305,7 @@ static spod_status launch_fft_shape(const Plan& p, const TIN* q, double* mean, v
 
 template <int NF, typename TC, typename TIN>
 static spod_status launch_fft_nf(const Plan& p, const TIN* q, double* mean, void* qhat,
-                                 hipStream_t st, bool fused) {
+                                 hipStream_t st, bool fused, const FftSel& fs) {
   // Tile of 32 degrees of freedom (16 transforms; 1024 threads at N = 512):
   // every frequency row is written in runs of 256 bytes, which the HBM takes
   // markedly better than 128-byte runs.  Default for complex64; complex128
@@ -425,22 +313,22 @@ static spod_status launch_fft_nf(const Plan& p, const TIN* q, double* mean, void
   // it 128 registers per lane).  SPOD_OPT_FFT_TILE = 16 or 32 overrides.
   const bool wide = p.fft_tile_opt == 32 || (p.fft_tile_opt == 0 && sizeof(TC) == 4);
   if (wide && FftShape<NF, 16>::NPAIR != FftShape<NF, 8>::NPAIR)
-    return launch_fft_shape<NF, TC, TIN, 16>(p, q, mean, qhat, st, fused);
-  return launch_fft_shape<NF, TC, TIN, 8>(p, q, mean, qhat, st, fused);
+    return launch_fft_shape<NF, TC, TIN, 16>(p, q, mean, qhat, st, fused, fs);
+  return launch_fft_shape<NF, TC, TIN, 8>(p, q, mean, qhat, st, fused, fs);
 }
 
 template <typename TC, typename TIN>
 static spod_status launch_fft_t(const Plan& p, const TIN* q, double* mean, void* qhat,
-                                hipStream_t st, bool fused) {
+                                hipStream_t st, bool fused, const FftSel& fs) {
   switch (p.nfft) {
-    case 8: return launch_fft_nf<8, TC, TIN>(p, q, mean, qhat, st, fused);
-    case 16: return launch_fft_nf<16, TC, TIN>(p, q, mean, qhat, st, fused);
-    case 32: return launch_fft_nf<32, TC, TIN>(p, q, mean, qhat, st, fused);
-    case 64: return launch_fft_nf<64, TC, TIN>(p, q, mean, qhat, st, fused);
-    case 128: return launch_fft_nf<128, TC, TIN>(p, q, mean, qhat, st, fused);
-    case 256: return launch_fft_nf<256, TC, TIN>(p, q, mean, qhat, st, fused);
-    case 512: return launch_fft_nf<512, TC, TIN>(p, q, mean, qhat, st, fused);
-    case 1024: return launch_fft_nf<1024, TC, TIN>(p, q, mean, qhat, st, fused);
+    case 8: return launch_fft_nf<8, TC, TIN>(p, q, mean, qhat, st, fused, fs);
+    case 16: return launch_fft_nf<16, TC, TIN>(p, q, mean, qhat, st, fused, fs);
+    case 32: return launch_fft_nf<32, TC, TIN>(p, q, mean, qhat, st, fused, fs);
+    case 64: return launch_fft_nf<64, TC, TIN>(p, q, mean, qhat, st, fused, fs);
+    case 128: return launch_fft_nf<128, TC, TIN>(p, q, mean, qhat, st, fused, fs);
+    case 256: return launch_fft_nf<256, TC, TIN>(p, q, mean, qhat, st, fused, fs);
+    case 512: return launch_fft_nf<512, TC, TIN>(p, q, mean, qhat, st, fused, fs);
+    case 1024: return launch_fft_nf<1024, TC, TIN>(p, q, mean, qhat, st, fused, fs);
   }
   return fail(SPOD_ERR_UNSUPPORTED, "nfft");
 }
@@ -448,7 +336,7 @@ static spod_status launch_fft_t(const Plan& p, const TIN* q, double* mean, void*
 size_t fft_workspace(const Plan& p) { return sizeof(double) * (size_t)p.M; }
 
 spod_status launch_blocks_fft(const Plan& p, const void* q, spod_dtype dtype, void* qhat,
-                              double* mean, void* ws, hipStream_t st) {
+                              double* mean, void* ws, hipStream_t st, const FftSel& fs) {
   // the mean goes to the caller's buffer, or to the start of the workspace
   double* mu = mean ? mean : static_cast<double*>(ws);
   // single pass when the window's DFT has few non-zero bins and the hop is a
@@ -471,10 +359,10 @@ spod_status launch_blocks_fft(const Plan& p, const void* q, spod_dtype dtype, vo
   }
   const bool c128 = is_complex128(p);
   if (dtype == SPOD_F32)
-    return c128 ? launch_fft_t<double, float>(p, (const float*)q, mu, qhat, st, fused)
-                : launch_fft_t<float, float>(p, (const float*)q, mu, qhat, st, fused);
-  return c128 ? launch_fft_t<double, double>(p, (const double*)q, mu, qhat, st, fused)
-              : launch_fft_t<float, double>(p, (const double*)q, mu, qhat, st, fused);
+    return c128 ? launch_fft_t<double, float>(p, (const float*)q, mu, qhat, st, fused, fs)
+                : launch_fft_t<float, float>(p, (const float*)q, mu, qhat, st, fused, fs);
+  return c128 ? launch_fft_t<double, double>(p, (const double*)q, mu, qhat, st, fused, fs)
+              : launch_fft_t<float, double>(p, (const double*)q, mu, qhat, st, fused, fs);
 }
 
 }  // namespace spod

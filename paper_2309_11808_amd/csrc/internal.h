@@ -48,6 +48,7 @@ struct Plan {
   float* d_window32 = nullptr; // [nfft]
   double* d_weights = nullptr; // [M]
   double* d_sqrtw = nullptr;   // [M]
+  double2* d_what = nullptr;   // [K] DFT of the window, What_k
   float* d_sqrtw32 = nullptr;  // [M]
   double2* d_tw64 = nullptr;   // [nfft] e^{-2 pi i j / nfft}
   float2* d_tw32 = nullptr;    // [nfft]
@@ -64,16 +65,26 @@ spod_status hip_fail(hipError_t e, const char* where);
 // --------------------------------------------------------------------------
 // stage launchers (each returns SPOD_OK or an error, never throws)
 // --------------------------------------------------------------------------
+// Optional frequency selection of the block transform: output row s holds
+// frequency d_sel[s] (device table, nsel rows); h_slot[k] (host, nfreq
+// entries) is the row of frequency k or -1.  d_sel == NULL: all frequencies.
+struct FftSel {
+  const int* d_sel = nullptr;
+  int nsel = 0;
+  const int* h_slot = nullptr;
+};
+
 spod_status launch_blocks_fft(const Plan& p, const void* q, spod_dtype dtype, void* qhat,
-                              double* mean, void* ws, hipStream_t st);
+                              double* mean, void* ws, hipStream_t st, const FftSel& fs = FftSel{});
 spod_status launch_csd(const Plan& p, const void* qhat, void* gram, void* ws, hipStream_t st);
 spod_status launch_eig(const Plan& p, const void* gram, double* lam, void* psi, int32_t* info,
                        void* ws, hipStream_t st);
 spod_status launch_modes(const Plan& p, const void* qhat, const double* lam, const void* psi,
                          int n_modes, void* phi, int32_t* n_valid, void* ws, hipStream_t st);
-spod_status launch_backward(const Plan& p, const void* q, spod_dtype dtype, const double* lam,
-                            const void* psi, const double* g_lam, const void* g_phi, int n_modes,
-                            void* g_q, void* ws, hipStream_t st);
+spod_status launch_backward(const Plan& p, const void* q, spod_dtype dtype, const void* qhat,
+                            const double* lam, const void* psi, const double* g_lam,
+                            const void* g_phi, int n_modes, const int32_t* bins, int n_bins,
+                            void* g_qhat, void* g_q, void* ws, hipStream_t st);
 
 // workspace sizes of the individual stages
 size_t fft_workspace(const Plan& p);  // only used when the caller passes no mean buffer

@@ -167,20 +167,35 @@ class Plan:
                                 _ptr(n_valid), _ptr(ws), ws.numel(), _stream(self.device)))
         return phi, n_valid
 
-    def backward(self, q, lam, psi, g_lam=None, g_phi=None, n_modes: int = 0, g_q=None):
+    def backward(self, q, lam, psi, g_lam=None, g_phi=None, n_modes: int = 0, bins=None,
+                 qhat=None, g_qhat=None, g_q=None):
+        """dE/dq from dE/dlam and dE/dphi (spod_backward).
+
+        bins: optional increasing frequencies; g_lam [nb, L] and g_phi [nb, n, M]
+        then hold only those rows.  qhat: the forward's Fourier blocks, or None
+        to recompute them (selected bins only) into g_qhat."""
         dt = self._q(q)
         L, K = self.nblocks, self.nfreq
         self._dev(lam, "lam", torch.float64, (K, L))
         self._dev(psi, "psi", torch.complex128, (K, L, L))
+        sel = None
+        nb = K
+        if bins is not None:
+            sel = np.ascontiguousarray(np.asarray(bins, dtype=np.int32).reshape(-1))
+            nb = int(sel.size)
         if g_lam is not None:
-            self._dev(g_lam, "g_lam", torch.float64, (K, L))
+            self._dev(g_lam, "g_lam", torch.float64, (nb, L))
         if g_phi is not None:
-            self._dev(g_phi, "g_phi", self.cdtype, (K, n_modes, self.M))
+            self._dev(g_phi, "g_phi", self.cdtype, (nb, n_modes, self.M))
+        if qhat is not None:
+            self._dev(qhat, "qhat", self.cdtype, (K, L, self.M))
+        g_qhat = self._out(g_qhat, "g_qhat", self.cdtype, (nb, L, self.M))
         g_q = self._out(g_q, "g_q", q.dtype, (self.M, self.nt))
         ws = self.workspace()
-        _check(lib().spod_backward(self._h, _ptr(q), dt, _ptr(lam), _ptr(psi), _ptr(g_lam),
-                                   _ptr(g_phi), n_modes, _ptr(g_q), _ptr(ws), ws.numel(),
-                                   _stream(self.device)))
+        _check(lib().spod_backward(
+            self._h, _ptr(q), dt, _ptr(qhat), _ptr(lam), _ptr(psi), _ptr(g_lam), _ptr(g_phi),
+            n_modes, None if sel is None else sel.ctypes.data_as(C.c_void_p), nb, _ptr(g_qhat),
+            _ptr(g_q), _ptr(ws), ws.numel(), _stream(self.device)))
         return g_q
 
     def forward(self, q, n_modes: int = 5):

@@ -114,8 +114,8 @@ def test_null_plan_is_rejected_by_every_stage(lib):
     assert lib.spod_csd(None, None, None, None, 0, None) == N.SPOD_ERR_INVALID_ARG
     assert lib.spod_eig(None, None, None, None, None, None, 0, None) == N.SPOD_ERR_INVALID_ARG
     assert lib.spod_modes(None, None, None, None, 1, None, None, None, 0, None) == N.SPOD_ERR_INVALID_ARG
-    assert lib.spod_backward(None, None, 0, None, None, None, None, 1, None, None, 0,
-                             None) == N.SPOD_ERR_INVALID_ARG
+    assert lib.spod_backward(None, None, 0, None, None, None, None, None, 1, None, 0, None,
+                             None, None, 0, None) == N.SPOD_ERR_INVALID_ARG
 
 
 def test_valid_plan_without_gpu_reports_hip_error_or_succeeds(lib):
