@@ -1,7 +1,7 @@
 """Throughput of the SPOD hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 3] [--precision bf16x4]
-                    [--workload era|jet] [--no-fp64] [--no-cpu]
+                    [--workload era|jet] [--no-fp64] [--no-cpu] [--no-diff] [--no-batch]
 
 A step is one pass of the whole path over the resident input: temporal mean +
 windowed block FFT (spod_blocks_fft), weighted Gram (spod_csd), batched
@@ -17,6 +17,17 @@ float32 snapshots (34.4 GB), N_f = 512 with 50% overlap (31 blocks, 257
 frequencies), cos(latitude) weights; red noise plus 6 planted modes, generated
 on the device from a seed.  Prints one JSON line on stdout; progress goes to
 stderr.
+
+Two more measurements ride on the same line (skipped with --no-diff and
+--no-batch):
+  * differentiation: the jet-like field (256 x 128 x 3, N_t = 4096 float32,
+    N_f = 256, 31 blocks, 129 bins); forward pass and spod_backward for a loss
+    on 8 separated bins (3 eigenvalues and the leading mode), Fourier blocks
+    recomputed; reported as forward ms, backward ms and (fwd + bwd) / fwd, on
+    the FP64 and the mixed path;
+  * batching: 64 uneven problems from the batch generator (seed 4), the mixed
+    path, grouped launches replayed from a hipGraph with the autotuned Gram
+    split, against one launch per problem and stage.
 """
 from __future__ import annotations
 
@@ -148,6 +159,124 @@ def cpu_baseline(p, seconds_target=20.0):
                       f"frequencies, 5 modes; {dt:.1f} s"}
 
 
+def _separated_bins(lam, count, top=4, gap=1e-3):
+    import numpy as np
+    good = []
+    for k in range(lam.shape[0]):
+        l = lam[k, :top]
+        if l[-1] <= 0:
+            continue
+        d = np.abs(l[:, None] - l[None, :]) - gap * np.maximum(l[:, None], l[None, :])
+        d[np.diag_indices(len(l))] = 1.0
+        if d.min() >= 0:
+            good.append(k)
+    pick = np.unique(np.linspace(0, len(good) - 1, min(count, len(good))).round().astype(int))
+    return [good[i] for i in pick]
+
+
+def _time(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def bench_differentiation(steps, warmup, n_modes=5):
+    """Forward and backward times on the jet-like differentiation workload."""
+    import numpy as np
+    import torch
+    from synth import fields
+    from paper_2309_11808_amd import Plan
+    p = fields.jet_like(seed=2, device="cuda", dtype=torch.float32)
+    out = {"workload": "jet-like 256x128x3, nt=4096 float32, nfft=256, 50% overlap; loss on 8 "
+                       "bins: 3 leading eigenvalues + the leading mode; blocks recomputed"}
+    for precision in ("fp64", "bf16x4"):
+        plan = Plan(p.nspace, p.nvar, p.nt, p.nfft, p.noverlap, weights=p.weights,
+                    precision=precision)
+        K, L, M = plan.nfreq, plan.nblocks, plan.M
+        dev = plan.device
+        qhat = torch.empty(K, L, M, dtype=plan.cdtype, device=dev)
+        mean = torch.empty(M, dtype=torch.float64, device=dev)
+        gram = torch.empty(K, L, L, dtype=torch.complex128, device=dev)
+        lam = torch.empty(K, L, dtype=torch.float64, device=dev)
+        psi = torch.empty(K, L, L, dtype=torch.complex128, device=dev)
+        info = torch.empty(K, dtype=torch.int32, device=dev)
+        phi = torch.empty(K, n_modes, M, dtype=plan.cdtype, device=dev)
+        nval = torch.empty(K, dtype=torch.int32, device=dev)
+        plan.workspace()
+
+        def fwd():
+            plan.blocks_fft(p.q, qhat=qhat, mean=mean)
+            plan.csd(qhat, gram=gram)
+            plan.eig(gram, lam=lam, psi=psi, info=info)
+            plan.modes(qhat, lam, psi, n_modes, phi=phi, n_valid=nval)
+
+        fwd()
+        torch.cuda.synchronize()
+        bins = _separated_bins(lam.cpu().numpy(), 8)
+        nb = len(bins)
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(5)
+        g_lam = torch.zeros(nb, L, dtype=torch.float64, device=dev)
+        g_lam[:, :3] = 1.0
+        g_phi = torch.zeros(nb, n_modes, M, dtype=plan.cdtype, device=dev)
+        g_phi[:, 0] = torch.randn(nb, M, generator=gen, dtype=plan.cdtype, device=dev)
+        g_qhat = torch.empty(nb, L, M, dtype=plan.cdtype, device=dev)
+        g_q = torch.empty_like(p.q)
+
+        def bwd():
+            plan.backward(p.q, lam, psi, g_lam=g_lam, g_phi=g_phi, n_modes=n_modes, bins=bins,
+                          g_qhat=g_qhat, g_q=g_q)
+
+        t_f = _time(fwd, steps, warmup)
+        t_b = _time(bwd, steps, warmup)
+        out[precision] = {"fwd_ms": round(t_f, 4), "bwd_ms": round(t_b, 4),
+                          "fwd_plus_bwd_over_fwd": round((t_f + t_b) / t_f, 3), "bins": bins}
+        del qhat, phi, g_qhat, g_q
+        plan.close()
+        torch.cuda.empty_cache()
+    del p
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_batching(steps, warmup, precision="bf16x4", n_modes=5):
+    """64 uneven problems: grouped launches + graph vs one launch per problem."""
+    import torch
+    from synth import fields
+    from paper_2309_11808_amd import Batch
+    specs = fields.batch_specs(seed=4, count=64)
+    probs = [fields.batch_problem(s, dtype=torch.float32, device="cuda") for s in specs]
+    qs = [pb.q for pb in probs]
+    descs = [{"nspace": pb.nspace, "nvar": pb.nvar, "nt": pb.nt, "nfft": pb.nfft,
+              "noverlap": pb.noverlap, "weights": pb.weights} for pb in probs]
+    in_bytes = sum(q.numel() * q.element_size() for q in qs)
+    res = {"workload": "64 uneven problems (seed 4): nspace 1e3-2e5 log-uniform, nvar 1-3, "
+                       "nfft 64/128/256, nt 512-4096, 50% overlap, float32",
+           "problems": len(probs), "input_bytes": in_bytes, "precision": precision}
+    for name, grouped in (("grouped_graph", True), ("per_problem", False)):
+        b = Batch(descs, precision=precision, n_modes=n_modes, grouped=grouped, graph=grouped)
+        if grouped:
+            res["gram_target"] = b.autotune(qs)
+        t = _time(lambda: b.forward(qs), steps, warmup)
+        res[name] = {"ms": round(t, 3), "input_GBps": round(in_bytes / (t * 1e-3) / 1e9, 2)}
+        b.close()
+        del b
+        torch.cuda.empty_cache()
+    res["speedup"] = round(res["per_problem"]["ms"] / res["grouped_graph"]["ms"], 3)
+    del probs, qs
+    torch.cuda.empty_cache()
+    return res
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -157,6 +286,8 @@ def main(argv=None):
     ap.add_argument("--workload", default="era")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-diff", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {a.gpus} is not supported "
@@ -220,6 +351,16 @@ def main(argv=None):
         log("timing the FP64 CPU oracle on a sample")
         result["cpu_baseline"] = cpu_baseline(p)
         log(f"cpu baseline {result['cpu_baseline']}")
+    del p
+    torch.cuda.empty_cache()
+    if not a.no_diff:
+        log("differentiation workload")
+        result["differentiation"] = bench_differentiation(max(3, a.steps // 2), 1)
+        log(f"differentiation {result['differentiation']}")
+    if not a.no_batch:
+        log("batching workload")
+        result["batching"] = bench_batching(max(3, a.steps // 2), 1)
+        log(f"batching {result['batching']}")
     print(json.dumps(result), flush=True)
     return 0
 

@@ -200,6 +200,76 @@ spod_status spod_backward(spod_plan plan, const void* q, spod_dtype dtype, const
                           int64_t n_bins, void* g_qhat, void* g_q, void* ws, size_t ws_bytes,
                           spod_stream stream);
 
+/* ------------------------------------------------------------------------
+ * Batches: many independent problems of uneven shapes (not in the paper; the
+ * paper runs one problem per job).  A batch owns one plan per problem, all
+ * with the same precision.  A forward pass enqueues the five steps for every
+ * problem with one launch per step and shape group (problems that share N_f
+ * for the transform, ceil(L/16) for the Gram; all problems for the mean-free
+ * bookkeeping, eigensolve and modes): workgroup b of a grouped launch finds
+ * its problem in a device work table.  By default the launches are captured
+ * once into a hipGraph and replayed.
+ * ------------------------------------------------------------------------ */
+typedef struct spod_batch_s* spod_batch;
+
+typedef struct {
+  int64_t nspace, nvar, nt, nfft, noverlap;
+  const double* window;   /* host [nfft], copied; NULL = periodic Hann            */
+  const double* weights;  /* host [nspace*nvar], copied; NULL = 1/M for every DOF */
+} spod_problem;
+
+typedef struct {
+  int64_t M, nblocks, nfreq, n_modes; /* n_modes = min(requested, nblocks) */
+  /* byte offsets of this problem's results in the output buffer `out`:
+   * mean [M] f64, lam [K][L] f64, psi [K][L][L] c128, info [K] int32,
+   * phi [K][n_modes][M] (c128 under SPOD_PREC_FP64, else c64), n_valid [K] int32 */
+  size_t mean, lam, psi, info, phi, n_valid;
+} spod_batch_item;
+
+typedef enum {
+  SPOD_BATCH_GROUPED = 0,    /* 1 (default): grouped launches; 0: one launch per problem and step */
+  SPOD_BATCH_GRAPH = 1,      /* 1 (default): capture into a hipGraph on first use and replay      */
+  SPOD_BATCH_GRAM_TARGET = 2 /* Gram workgroups aimed at per problem (default 8192, >= 64)       */
+} spod_batch_option;
+
+/* Create plans for problems[0..n) on the current device (n >= 1).  Every
+ * problem is validated as in spod_plan_create; the first failure is returned
+ * and nothing is kept. */
+spod_status spod_batch_create(const spod_problem* problems, int64_t n, spod_precision precision,
+                              int64_t n_modes, spod_batch* out);
+
+/* Options, before the first forward pass or autotune. */
+spod_status spod_batch_set_option(spod_batch batch, spod_batch_option opt, int64_t value);
+
+/* Bytes of the device workspace (Fourier blocks, Gram partials and Grams of
+ * every problem) and of the output buffer. */
+spod_status spod_batch_query(spod_batch batch, size_t* workspace_bytes, size_t* output_bytes);
+
+/* Shape and result offsets of problem i. */
+spod_status spod_batch_item_info(spod_batch batch, int64_t i, spod_batch_item* item);
+
+/* Forward pass of every problem.  q: host array of n device pointers, problem
+ * i's snapshots [M_i][nt_i] of `dtype` (one dtype for the batch).  out, ws:
+ * device buffers of the queried sizes, 256-byte aligned.  When q, out or ws
+ * differ from the previous call the work tables are rebuilt (a synchronous
+ * copy) and the graph is captured again.  Calls on one batch must not
+ * overlap. */
+spod_status spod_batch_forward(spod_batch batch, const void* const* q, spod_dtype dtype,
+                               void* out, void* ws, size_t ws_bytes, spod_stream stream);
+
+/* Choose SPOD_BATCH_GRAM_TARGET by timing one grouped forward pass per
+ * candidate (2048, 4096, 8192, 16384 workgroups per problem) on these
+ * buffers.  With cache_path != NULL the choice is read from (when its key,
+ * a hash of the problem shapes and precision, is present) or appended to that
+ * JSON-lines file.  Synchronises the stream.  *chosen (nullable) receives the
+ * target. */
+spod_status spod_batch_autotune(spod_batch batch, const void* const* q, spod_dtype dtype,
+                                void* out, void* ws, size_t ws_bytes, spod_stream stream,
+                                const char* cache_path, int64_t* chosen);
+
+/* Free the batch and its plans (NULL-safe; synchronises the device). */
+void spod_batch_destroy(spod_batch batch);
+
 /* Free the plan's device copies.  NULL-safe.  Synchronises the plan's device. */
 void spod_plan_destroy(spod_plan plan);
 

@@ -31,6 +31,23 @@ SPOD_OPT_MAX_SWEEPS = 0
 SPOD_OPT_GRAM_SPLIT = 1
 SPOD_OPT_FFT_TILE = 2
 
+SPOD_BATCH_GROUPED = 0
+SPOD_BATCH_GRAPH = 1
+SPOD_BATCH_GRAM_TARGET = 2
+
+
+class SpodProblem(C.Structure):
+    _fields_ = [("nspace", C.c_int64), ("nvar", C.c_int64), ("nt", C.c_int64),
+                ("nfft", C.c_int64), ("noverlap", C.c_int64), ("window", C.c_void_p),
+                ("weights", C.c_void_p)]
+
+
+class SpodBatchItem(C.Structure):
+    _fields_ = [("M", C.c_int64), ("nblocks", C.c_int64), ("nfreq", C.c_int64),
+                ("n_modes", C.c_int64), ("mean", C.c_size_t), ("lam", C.c_size_t),
+                ("psi", C.c_size_t), ("info", C.c_size_t), ("phi", C.c_size_t),
+                ("n_valid", C.c_size_t)]
+
 _i64 = C.c_int64
 _p = C.c_void_p
 _sz = C.c_size_t
@@ -49,6 +66,14 @@ SIGNATURES = {
     "spod_backward": (C.c_int, [_p, _p, C.c_int, _p, _p, _p, _p, _p, _i64, _p, _i64, _p, _p, _p,
                                 _sz, _p]),
     "spod_plan_destroy": (None, [_p]),
+    "spod_batch_create": (C.c_int, [C.POINTER(SpodProblem), _i64, C.c_int, _i64, C.POINTER(_p)]),
+    "spod_batch_set_option": (C.c_int, [_p, C.c_int, _i64]),
+    "spod_batch_query": (C.c_int, [_p, C.POINTER(_sz), C.POINTER(_sz)]),
+    "spod_batch_item_info": (C.c_int, [_p, _i64, C.POINTER(SpodBatchItem)]),
+    "spod_batch_forward": (C.c_int, [_p, C.POINTER(_p), C.c_int, _p, _p, _sz, _p]),
+    "spod_batch_autotune": (C.c_int, [_p, C.POINTER(_p), C.c_int, _p, _p, _sz, _p, C.c_char_p,
+                                      C.POINTER(_i64)]),
+    "spod_batch_destroy": (None, [_p]),
     "spod_status_string": (C.c_char_p, [C.c_int]),
     "spod_last_error": (C.c_char_p, []),
 }

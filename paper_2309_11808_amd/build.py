@@ -23,7 +23,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libspod.so")
 ARCH = "gfx950"
 
-SOURCES = ["api.cpp", "fft.hip", "gram.hip", "eig.hip", "modes.hip", "backward.hip"]
+SOURCES = ["api.cpp", "batch.cpp", "fft.hip", "gram.hip", "eig.hip", "modes.hip",
+           "backward.hip"]
 
 # Packed FP32 instructions are kept out of all device code (the compiler would
 # otherwise form v_pk_* FP32 ops from ordinary float code).

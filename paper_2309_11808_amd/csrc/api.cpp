@@ -24,19 +24,29 @@ spod_status hip_fail(hipError_t e, const char* where) {
 
 bool is_complex128(const Plan& p) { return p.prec == SPOD_PREC_FP64; }
 
-static int64_t auto_gram_split(const Plan& p) {
-  if (p.gram_split_opt > 0) return p.gram_split_opt;
-  // about 8192 workgroups (measured best on the 1M-DOF workload: 32 slices x
-  // 257 frequencies), but keep at least ~4 chunks of degrees of freedom per
-  // slice so the partial sums stay cheap
+int64_t gram_split_for(const Plan& p, int64_t target) {
+  // about `target` workgroups (8192 measured best on the 1M-DOF workload: 32
+  // slices x 257 frequencies), but keep at least ~4 chunks of degrees of
+  // freedom per slice so the partial sums stay cheap
   const int64_t nt = (p.nblocks + 15) / 16;
   const int64_t ng = (nt * (nt + 1) / 2 + 2) / 3;
-  int64_t s = (8192 + p.nfreq * ng - 1) / (p.nfreq * ng);
+  int64_t s = (target + p.nfreq * ng - 1) / (p.nfreq * ng);
   int64_t cap = p.M / 512;
   if (cap < 1) cap = 1;
   if (s > cap) s = cap;
   if (s < 1) s = 1;
   return s;
+}
+
+static int64_t auto_gram_split(const Plan& p) {
+  if (p.gram_split_opt > 0) return p.gram_split_opt;
+  return gram_split_for(p, 8192);
+}
+
+void plan_set_gram_split(Plan& p, int64_t s) {
+  p.gram_split_opt = s;
+  p.gram_split = (int)s;
+  p.ws_bytes = workspace_bytes(p);
 }
 
 static void derive(Plan& p) {

@@ -1,0 +1,625 @@
+// Batches of independent SPOD problems: grouped launches, hipGraph replay and
+// a Gram-split autotuner.  The per-problem arithmetic is the single-problem
+// path's; only the mapping of workgroups to problems differs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cinttypes>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <new>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace spod {
+namespace {
+
+size_t up256(size_t x) { return (x + 255) / 256 * 256; }
+
+struct ProblemSlots {
+  Plan* plan = nullptr;
+  int n_modes = 0;
+  size_t ws_qhat = 0, ws_gram = 0, ws_part = 0;                        // workspace offsets
+  size_t o_mean = 0, o_lam = 0, o_psi = 0, o_info = 0, o_phi = 0, o_nvalid = 0;  // output offsets
+};
+
+struct Group {
+  int key = 0;               // nfft (transform) or ceil(L/16) (Gram)
+  size_t off = 0;            // byte offset of the item array in the table
+  int n = 0, wgs = 0;
+};
+
+}  // namespace
+
+struct Batch {
+  std::vector<ProblemSlots> pb;
+  spod_precision prec = SPOD_PREC_FP64;
+  int device = 0;
+  bool grouped = true, use_graph = true, started = false;
+  int64_t gram_target = 8192;
+  size_t ws_bytes = 0, out_bytes = 0;
+
+  // work tables (device) and the pointers they were built for
+  void* d_table = nullptr;
+  size_t table_cap = 0;
+  std::vector<const void*> q_built;
+  void* out_built = nullptr;
+  void* ws_built = nullptr;
+  spod_dtype dtype_built = SPOD_F32;
+  int64_t target_built = -1;
+  bool tables_ok = false;
+  std::vector<Group> fft_groups, gram_groups;
+  std::vector<int> fft_fallback;                 // problems launched on their own
+  Group scale_g, comb_g, eig_g, modes_g;
+  size_t modes_lds = 0;
+
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+bool c128(const Batch& b) { return b.prec == SPOD_PREC_FP64; }
+size_t csize(const Batch& b) { return c128(b) ? 16 : 8; }
+
+// The workspace is laid out for the largest Gram split any target may choose.
+void layout(Batch& b) {
+  const int64_t tmax = std::max<int64_t>(b.gram_target, 16384);
+  size_t ws = 0, out = 0;
+  for (auto& s : b.pb) {
+    const Plan& p = *s.plan;
+    const size_t K = p.nfreq, L = p.nblocks, M = p.M;
+    s.ws_qhat = ws;
+    ws += up256(csize(b) * K * L * M);
+    s.ws_gram = ws;
+    ws += up256(16 * K * L * L);
+    s.ws_part = ws;
+    const size_t D = (size_t)p.gram_dim;
+    const size_t smax = (size_t)gram_split_for(p, tmax);
+    ws += up256(16 * K * smax * D * D + sizeof(float) * K + 256);
+    s.o_mean = out;
+    out += up256(8 * M);
+    s.o_lam = out;
+    out += up256(8 * K * L);
+    s.o_psi = out;
+    out += up256(16 * K * L * L);
+    s.o_info = out;
+    out += up256(4 * K);
+    s.o_phi = out;
+    out += up256(csize(b) * K * (size_t)s.n_modes * M);
+    s.o_nvalid = out;
+    out += up256(4 * K);
+  }
+  b.ws_bytes = std::max<size_t>(ws, 256);
+  b.out_bytes = std::max<size_t>(out, 256);
+}
+
+void drop_graph(Batch& b) {
+  if (b.exec) (void)hipGraphExecDestroy(b.exec);
+  b.exec = nullptr;
+}
+
+void apply_target(Batch& b) {
+  for (auto& s : b.pb) plan_set_gram_split(*s.plan, gram_split_for(*s.plan, b.gram_target));
+}
+
+bool fused_ok(const Plan& p) {
+  return p.n_mean_bins >= 0 && p.nfft >= 16 && p.nfft <= 512 && p.step * 2 == p.nfft;
+}
+
+template <typename It>
+void put(std::vector<char>& host, Group& g, const std::vector<It>& items) {
+  while (host.size() % 64) host.push_back(0);
+  g.off = host.size();
+  g.n = (int)items.size();
+  const char* src = reinterpret_cast<const char*>(items.data());
+  host.insert(host.end(), src, src + sizeof(It) * items.size());
+}
+
+spod_status build_tables(Batch& b, const void* const* q, spod_dtype dtype, char* out, char* ws) {
+  std::vector<char> host;
+  const bool half = b.prec == SPOD_PREC_FP16X4;
+  // transform: grouped by nfft
+  std::map<int, std::vector<FftItem>> fft;
+  b.fft_fallback.clear();
+  for (size_t i = 0; i < b.pb.size(); ++i) {
+    const ProblemSlots& s = b.pb[i];
+    const Plan& p = *s.plan;
+    if (!fused_ok(p)) {
+      b.fft_fallback.push_back((int)i);
+      continue;
+    }
+    FftItem it{};
+    it.q = q[i];
+    it.mean = reinterpret_cast<double*>(out + s.o_mean);
+    it.window = p.d_window;
+    it.tw = c128(b) ? (const void*)p.d_tw64 : (const void*)p.d_tw32;
+    it.qhat = ws + s.ws_qhat;
+    it.M = p.M;
+    it.nt = p.nt;
+    it.step = (int)p.step;
+    it.L = (int)p.nblocks;
+    it.kappa = p.kappa;
+    it.mb.n = p.n_mean_bins;
+    for (int j = 0; j < p.n_mean_bins; ++j) {
+      it.mb.k[j] = p.mean_bin[j];
+      it.mb.wr[j] = p.what_re[j];
+      it.mb.wi[j] = p.what_im[j];
+    }
+    fft[(int)p.nfft].push_back(it);
+  }
+  b.fft_groups.clear();
+  for (auto& kv : fft) {
+    Group g;
+    g.key = kv.first;
+    const int T = fft_group_tile(kv.first, b.prec);
+    int64_t start = 0;
+    for (auto& it : kv.second) {
+      it.start = (int)start;
+      start += (it.M + T - 1) / T;
+    }
+    if (start > 0x7fffffff) return fail(SPOD_ERR_UNSUPPORTED, "batch too large for one launch");
+    g.wgs = (int)start;
+    put(host, g, kv.second);
+    b.fft_groups.push_back(g);
+  }
+  // Gram: grouped by ceil(L / 16)
+  std::map<int, std::vector<GramItem>> gram;
+  for (auto& s : b.pb) {
+    const Plan& p = *s.plan;
+    GramItem it{};
+    it.qhat = ws + s.ws_qhat;
+    it.sqrtw = c128(b) ? (const void*)p.d_sqrtw : (const void*)p.d_sqrtw32;
+    const size_t D = (size_t)p.gram_dim;
+    it.part = reinterpret_cast<double*>(ws + s.ws_part);
+    it.fscale = half ? reinterpret_cast<const float*>(ws + s.ws_part + 16 * (size_t)p.nfreq *
+                                                          (size_t)p.gram_split * D * D)
+                     : nullptr;
+    it.M = p.M;
+    it.L = (int)p.nblocks;
+    it.S = p.gram_split;
+    it.K = (int)p.nfreq;
+    const bool aligned = ((uintptr_t)it.qhat % 16 == 0) && ((uintptr_t)it.sqrtw % 16 == 0);
+    it.vec = aligned && (c128(b) || p.M % 2 == 0);
+    gram[p.gram_dim / 16].push_back(it);
+  }
+  b.gram_groups.clear();
+  for (auto& kv : gram) {
+    Group g;
+    g.key = kv.first;
+    const int ng = gram_groups(kv.first);
+    int64_t start = 0;
+    for (auto& it : kv.second) {
+      it.start = (int)start;
+      start += (int64_t)ng * it.S * it.K;
+    }
+    if (start > 0x7fffffff) return fail(SPOD_ERR_UNSUPPORTED, "batch too large for one launch");
+    g.wgs = (int)start;
+    put(host, g, kv.second);
+    b.gram_groups.push_back(g);
+  }
+  // FP16 scales, combine, eigensolve, modes: one group each
+  std::vector<CombineItem> sc, cb;
+  std::vector<EigItem> eg;
+  std::vector<ModesItem> md;
+  int64_t s_sc = 0, s_cb = 0, s_eg = 0, s_md = 0;
+  b.modes_lds = 0;
+  for (auto& s : b.pb) {
+    const Plan& p = *s.plan;
+    const size_t D = (size_t)p.gram_dim;
+    const int K = (int)p.nfreq, L = (int)p.nblocks;
+    if (half) {
+      CombineItem it{};
+      it.part = ws + s.ws_qhat;
+      it.gram = ws + s.ws_part + 16 * (size_t)K * (size_t)p.gram_split * D * D;
+      it.sqrtw = p.d_sqrtw32;
+      it.M = p.M;
+      it.L = L;
+      it.start = (int)s_sc;
+      s_sc += K;
+      sc.push_back(it);
+    }
+    CombineItem c{};
+    c.part = ws + s.ws_part;
+    c.gram = ws + s.ws_gram;
+    c.L = L;
+    c.D = (int)D;
+    c.S = p.gram_split;
+    c.start = (int)s_cb;
+    s_cb += K;
+    cb.push_back(c);
+    EigItem e{};
+    e.gram = ws + s.ws_gram;
+    e.lam = reinterpret_cast<double*>(out + s.o_lam);
+    e.psi = out + s.o_psi;
+    e.info = reinterpret_cast<int32_t*>(out + s.o_info);
+    e.L = L;
+    e.start = (int)s_eg;
+    s_eg += K;
+    eg.push_back(e);
+    ModesItem m{};
+    m.qhat = ws + s.ws_qhat;
+    m.lam = e.lam;
+    m.psi = e.psi;
+    m.phi = out + s.o_phi;
+    m.n_valid = reinterpret_cast<int32_t*>(out + s.o_nvalid);
+    m.M = p.M;
+    m.L = L;
+    m.n_modes = s.n_modes;
+    m.tiles = (int)((p.M + 255) / 256);
+    m.eps = c128(b) ? 1e-12 : 1e-6;
+    m.start = (int)s_md;
+    s_md += (int64_t)K * m.tiles;
+    md.push_back(m);
+    b.modes_lds = std::max(b.modes_lds, csize(b) * (size_t)L * (size_t)s.n_modes);
+  }
+  if (s_md > 0x7fffffff) return fail(SPOD_ERR_UNSUPPORTED, "batch too large for one launch");
+  b.scale_g = Group{};
+  if (half) {
+    put(host, b.scale_g, sc);
+    b.scale_g.wgs = (int)s_sc;
+  }
+  put(host, b.comb_g, cb);
+  b.comb_g.wgs = (int)s_cb;
+  put(host, b.eig_g, eg);
+  b.eig_g.wgs = (int)s_eg;
+  put(host, b.modes_g, md);
+  b.modes_g.wgs = (int)s_md;
+
+  if (host.size() > b.table_cap) {
+    if (b.d_table) (void)hipFree(b.d_table);
+    b.d_table = nullptr;
+    b.table_cap = 0;
+    hipError_t e = hipMalloc(&b.d_table, host.size());
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? fail(SPOD_ERR_ALLOC, "batch tables")
+                                                         : hip_fail(e, "hipMalloc");
+    b.table_cap = host.size();
+  }
+  hipError_t e = hipMemcpy(b.d_table, host.data(), host.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+  return SPOD_OK;
+}
+
+template <typename It>
+const It* at(const Batch& b, const Group& g) {
+  return reinterpret_cast<const It*>(static_cast<const char*>(b.d_table) + g.off);
+}
+
+// Enqueue the whole forward pass on `st`.
+spod_status record(Batch& b, const void* const* q, spod_dtype dtype, char* out, char* ws,
+                   hipStream_t st) {
+  spod_status r = SPOD_OK;
+  if (!b.grouped) {
+    for (size_t i = 0; i < b.pb.size() && r == SPOD_OK; ++i) {
+      const ProblemSlots& s = b.pb[i];
+      const Plan& p = *s.plan;
+      void* qh = ws + s.ws_qhat;
+      double* lam = reinterpret_cast<double*>(out + s.o_lam);
+      r = launch_blocks_fft(p, q[i], dtype, qh, reinterpret_cast<double*>(out + s.o_mean), nullptr,
+                            st);
+      if (r == SPOD_OK) r = launch_csd(p, qh, ws + s.ws_gram, ws + s.ws_part, st);
+      if (r == SPOD_OK)
+        r = launch_eig(p, ws + s.ws_gram, lam, out + s.o_psi,
+                       reinterpret_cast<int32_t*>(out + s.o_info), nullptr, st);
+      if (r == SPOD_OK)
+        r = launch_modes(p, qh, lam, out + s.o_psi, s.n_modes, out + s.o_phi,
+                         reinterpret_cast<int32_t*>(out + s.o_nvalid), nullptr, st);
+    }
+    return r;
+  }
+  for (int i : b.fft_fallback) {
+    const ProblemSlots& s = b.pb[i];
+    r = launch_blocks_fft(*s.plan, q[i], dtype, ws + s.ws_qhat,
+                          reinterpret_cast<double*>(out + s.o_mean), nullptr, st);
+    if (r != SPOD_OK) return r;
+  }
+  for (const Group& g : b.fft_groups) {
+    r = launch_fft_group(g.key, b.prec, dtype, 4, at<FftItem>(b, g), g.n, g.wgs, st);
+    if (r != SPOD_OK) return r;
+  }
+  if (b.prec == SPOD_PREC_FP16X4) {
+    r = launch_gram_scale_group(at<CombineItem>(b, b.scale_g), b.scale_g.n, b.scale_g.wgs, st);
+    if (r != SPOD_OK) return r;
+  }
+  for (const Group& g : b.gram_groups) {
+    r = launch_gram_group(b.prec, g.key, at<GramItem>(b, g), g.n, g.wgs, st);
+    if (r != SPOD_OK) return r;
+  }
+  r = launch_gram_combine_group(at<CombineItem>(b, b.comb_g), b.comb_g.n, b.comb_g.wgs, st);
+  if (r != SPOD_OK) return r;
+  r = launch_eig_group(at<EigItem>(b, b.eig_g), b.eig_g.n, b.eig_g.wgs, b.pb[0].plan->max_sweeps,
+                       st);
+  if (r != SPOD_OK) return r;
+  return launch_modes_group(c128(b), at<ModesItem>(b, b.modes_g), b.modes_g.n, b.modes_g.wgs,
+                            b.modes_lds, st);
+}
+
+spod_status prepare(Batch& b, const void* const* q, spod_dtype dtype, void* out, void* ws) {
+  bool same = b.tables_ok && out == b.out_built && ws == b.ws_built && dtype == b.dtype_built &&
+              b.target_built == b.gram_target;
+  for (size_t i = 0; same && i < b.pb.size(); ++i) same = q[i] == b.q_built[i];
+  if (same) return SPOD_OK;
+  drop_graph(b);
+  b.tables_ok = false;
+  apply_target(b);
+  spod_status r = build_tables(b, q, dtype, static_cast<char*>(out), static_cast<char*>(ws));
+  if (r != SPOD_OK) return r;
+  b.q_built.assign(q, q + b.pb.size());
+  b.out_built = out;
+  b.ws_built = ws;
+  b.dtype_built = dtype;
+  b.target_built = b.gram_target;
+  b.tables_ok = true;
+  return SPOD_OK;
+}
+
+spod_status run(Batch& b, const void* const* q, spod_dtype dtype, void* out, void* ws,
+                hipStream_t st, bool graph) {
+  spod_status r = prepare(b, q, dtype, out, ws);
+  if (r != SPOD_OK) return r;
+  char* o = static_cast<char*>(out);
+  char* w = static_cast<char*>(ws);
+  if (!graph) return record(b, q, dtype, o, w, st);
+  if (!b.exec) {
+    hipError_t e = hipStreamBeginCapture(b.cap_stream, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    r = record(b, q, dtype, o, w, b.cap_stream);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(b.cap_stream, &g);
+    if (r != SPOD_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return r;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&b.exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      b.exec = nullptr;
+      return hip_fail(e, "hipGraphInstantiate");
+    }
+  }
+  hipError_t e = hipGraphLaunch(b.exec, st);
+  return e == hipSuccess ? SPOD_OK : hip_fail(e, "hipGraphLaunch");
+}
+
+spod_status check_call(Batch* b, const void* const* q, spod_dtype dtype, void* out, void* ws,
+                       size_t ws_bytes) {
+  if (!b) return fail(SPOD_ERR_INVALID_ARG, "batch is NULL");
+  if (!q || !out || !ws) return fail(SPOD_ERR_INVALID_ARG, "q, out and ws are required");
+  if (dtype != SPOD_F32 && dtype != SPOD_F64) return fail(SPOD_ERR_INVALID_ARG, "dtype");
+  for (size_t i = 0; i < b->pb.size(); ++i)
+    if (!q[i]) return fail(SPOD_ERR_INVALID_ARG, "q[" + std::to_string(i) + "] is NULL");
+  if ((uintptr_t)out % 256 || (uintptr_t)ws % 256)
+    return fail(SPOD_ERR_INVALID_ARG, "out and ws must be 256-byte aligned");
+  if (ws_bytes < b->ws_bytes)
+    return fail(SPOD_ERR_WORKSPACE, "workspace of " + std::to_string(b->ws_bytes) + " bytes required");
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (cur != b->device) return fail(SPOD_ERR_INVALID_ARG, "batch belongs to another device");
+  if (!b->started) {
+    b->started = true;
+    for (auto& s : b->pb) freeze(*s.plan);
+  }
+  return SPOD_OK;
+}
+
+// FNV-1a over the shapes, precision and n_modes: the autotune cache key
+std::string batch_key(const Batch& b) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](int64_t v) {
+    for (int i = 0; i < 8; ++i) {
+      h ^= (uint64_t)((v >> (8 * i)) & 0xff);
+      h *= 1099511628211ull;
+    }
+  };
+  mix((int64_t)b.prec);
+  for (auto& s : b.pb) {
+    mix(s.plan->M);
+    mix(s.plan->nt);
+    mix(s.plan->nfft);
+    mix(s.plan->noverlap);
+    mix(s.n_modes);
+  }
+  char buf[32];
+  std::snprintf(buf, sizeof buf, "%016" PRIx64, h);
+  return buf;
+}
+
+int64_t cache_lookup(const char* path, const std::string& key) {
+  std::ifstream f(path);
+  std::string line;
+  int64_t found = 0;
+  const std::string kk = "\"key\": \"" + key + "\"";
+  while (std::getline(f, line)) {
+    if (line.find(kk) == std::string::npos) continue;
+    const size_t p = line.find("\"gram_target\": ");
+    if (p != std::string::npos) found = std::strtoll(line.c_str() + p + 15, nullptr, 10);
+  }
+  return found;
+}
+
+}  // namespace
+}  // namespace spod
+
+using namespace spod;
+
+extern "C" {
+
+spod_status spod_batch_create(const spod_problem* problems, int64_t n, spod_precision precision,
+                              int64_t n_modes, spod_batch* out) {
+  if (!out) return fail(SPOD_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!problems || n < 1) return fail(SPOD_ERR_INVALID_ARG, "need at least one problem");
+  if (n > 65536) return fail(SPOD_ERR_INVALID_ARG, "at most 65536 problems");
+  if (n_modes < 1) return fail(SPOD_ERR_INVALID_ARG, "n_modes must be >= 1");
+  if (precision != SPOD_PREC_FP64 && precision != SPOD_PREC_FP32 &&
+      precision != SPOD_PREC_BF16X4 && precision != SPOD_PREC_FP16X4)
+    return fail(SPOD_ERR_INVALID_ARG, "unknown precision");
+  Batch* b = new (std::nothrow) Batch();
+  if (!b) return fail(SPOD_ERR_ALLOC, "batch");
+  b->prec = precision;
+  b->pb.resize((size_t)n);
+  spod_status st = SPOD_OK;
+  for (int64_t i = 0; i < n && st == SPOD_OK; ++i) {
+    const spod_problem& d = problems[i];
+    spod_plan h = nullptr;
+    st = spod_plan_create(d.nspace, d.nvar, d.nt, d.nfft, d.noverlap, d.window, d.weights, &h);
+    if (st != SPOD_OK) {
+      fail(st, "problem " + std::to_string(i) + ": " + spod_last_error());
+      break;
+    }
+    b->pb[i].plan = reinterpret_cast<Plan*>(h);
+    st = spod_plan_set_precision(h, precision);
+    if (b->pb[i].plan->nblocks > 64) st = fail(SPOD_ERR_UNSUPPORTED, "nblocks > 64");
+    b->pb[i].n_modes = (int)std::min<int64_t>(n_modes, b->pb[i].plan->nblocks);
+  }
+  if (st == SPOD_OK) {
+    hipError_t e = hipGetDevice(&b->device);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) st = hip_fail(e, "batch stream");
+  }
+  if (st != SPOD_OK) {
+    const std::string msg = spod_last_error();
+    spod_batch_destroy(reinterpret_cast<spod_batch>(b));
+    fail(st, msg.substr(msg.find(": ") == std::string::npos ? 0 : msg.find(": ") + 2));
+    return st;
+  }
+  apply_target(*b);
+  layout(*b);
+  *out = reinterpret_cast<spod_batch>(b);
+  return SPOD_OK;
+}
+
+spod_status spod_batch_set_option(spod_batch batch, spod_batch_option opt, int64_t value) {
+  Batch* b = reinterpret_cast<Batch*>(batch);
+  if (!b) return fail(SPOD_ERR_INVALID_ARG, "batch is NULL");
+  if (b->started) return fail(SPOD_ERR_INVALID_ARG, "batch already used");
+  switch (opt) {
+    case SPOD_BATCH_GROUPED:
+      if (value != 0 && value != 1) return fail(SPOD_ERR_INVALID_ARG, "grouped is 0 or 1");
+      b->grouped = value != 0;
+      break;
+    case SPOD_BATCH_GRAPH:
+      if (value != 0 && value != 1) return fail(SPOD_ERR_INVALID_ARG, "graph is 0 or 1");
+      b->use_graph = value != 0;
+      break;
+    case SPOD_BATCH_GRAM_TARGET:
+      if (value < 64 || value > (int64_t(1) << 24))
+        return fail(SPOD_ERR_INVALID_ARG, "gram target in [64, 2^24]");
+      b->gram_target = value;
+      apply_target(*b);
+      layout(*b);
+      break;
+    default:
+      return fail(SPOD_ERR_INVALID_ARG, "unknown option");
+  }
+  return SPOD_OK;
+}
+
+spod_status spod_batch_query(spod_batch batch, size_t* workspace_bytes, size_t* output_bytes) {
+  Batch* b = reinterpret_cast<Batch*>(batch);
+  if (!b) return fail(SPOD_ERR_INVALID_ARG, "batch is NULL");
+  if (workspace_bytes) *workspace_bytes = b->ws_bytes;
+  if (output_bytes) *output_bytes = b->out_bytes;
+  return SPOD_OK;
+}
+
+spod_status spod_batch_item_info(spod_batch batch, int64_t i, spod_batch_item* item) {
+  Batch* b = reinterpret_cast<Batch*>(batch);
+  if (!b) return fail(SPOD_ERR_INVALID_ARG, "batch is NULL");
+  if (!item || i < 0 || i >= (int64_t)b->pb.size())
+    return fail(SPOD_ERR_INVALID_ARG, "item index out of range");
+  const ProblemSlots& s = b->pb[(size_t)i];
+  item->M = s.plan->M;
+  item->nblocks = s.plan->nblocks;
+  item->nfreq = s.plan->nfreq;
+  item->n_modes = s.n_modes;
+  item->mean = s.o_mean;
+  item->lam = s.o_lam;
+  item->psi = s.o_psi;
+  item->info = s.o_info;
+  item->phi = s.o_phi;
+  item->n_valid = s.o_nvalid;
+  return SPOD_OK;
+}
+
+spod_status spod_batch_forward(spod_batch batch, const void* const* q, spod_dtype dtype,
+                               void* out, void* ws, size_t ws_bytes, spod_stream stream) {
+  Batch* b = reinterpret_cast<Batch*>(batch);
+  spod_status st = check_call(b, q, dtype, out, ws, ws_bytes);
+  if (st != SPOD_OK) return st;
+  return run(*b, q, dtype, out, ws, (hipStream_t)stream, b->use_graph);
+}
+
+spod_status spod_batch_autotune(spod_batch batch, const void* const* q, spod_dtype dtype,
+                                void* out, void* ws, size_t ws_bytes, spod_stream stream,
+                                const char* cache_path, int64_t* chosen) {
+  Batch* b = reinterpret_cast<Batch*>(batch);
+  spod_status st = check_call(b, q, dtype, out, ws, ws_bytes);
+  if (st != SPOD_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const std::string key = batch_key(*b);
+  int64_t best = cache_path ? cache_lookup(cache_path, key) : 0;
+  const int64_t cands[] = {2048, 4096, 8192, 16384};
+  float ms[4] = {0, 0, 0, 0};
+  if (best <= 0) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    float best_ms = 0.0f;
+    for (int c = 0; c < 4 && st == SPOD_OK; ++c) {
+      b->gram_target = cands[c];
+      // one untimed pass (builds the tables), then one timed pass, without a graph
+      st = run(*b, q, dtype, out, ws, s, false);
+      if (st == SPOD_OK) e = hipEventRecord(e0, s);
+      if (st == SPOD_OK && e == hipSuccess) st = run(*b, q, dtype, out, ws, s, false);
+      if (st == SPOD_OK && e == hipSuccess) e = hipEventRecord(e1, s);
+      if (st == SPOD_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+      if (st == SPOD_OK && e == hipSuccess) e = hipEventElapsedTime(&ms[c], e0, e1);
+      if (st == SPOD_OK && e != hipSuccess) st = hip_fail(e, "autotune timing");
+      if (st == SPOD_OK && (best <= 0 || ms[c] < best_ms)) {
+        best = cands[c];
+        best_ms = ms[c];
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != SPOD_OK) return st;
+    if (cache_path) {
+      std::ofstream f(cache_path, std::ios::app);
+      f << "{\"key\": \"" << key << "\", \"gram_target\": " << best << ", \"ms\": {";
+      for (int c = 0; c < 4; ++c) f << (c ? ", " : "") << "\"" << cands[c] << "\": " << ms[c];
+      f << "}}\n";
+    }
+  }
+  b->gram_target = best;
+  drop_graph(*b);
+  b->tables_ok = false;
+  if (chosen) *chosen = best;
+  return SPOD_OK;
+}
+
+void spod_batch_destroy(spod_batch batch) {
+  Batch* b = reinterpret_cast<Batch*>(batch);
+  if (!b) return;
+  int cur = 0;
+  const bool have = hipGetDevice(&cur) == hipSuccess;
+  if (have && cur != b->device) (void)hipSetDevice(b->device);
+  (void)hipDeviceSynchronize();
+  drop_graph(*b);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  if (b->d_table) (void)hipFree(b->d_table);
+  for (auto& s : b->pb)
+    if (s.plan) spod_plan_destroy(reinterpret_cast<spod_plan>(s.plan));
+  if (have && cur != b->device) (void)hipSetDevice(cur);
+  delete b;
+}
+
+}  // extern "C"

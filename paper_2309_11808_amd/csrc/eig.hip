@@ -32,11 +32,10 @@ struct Rot {
   int p, q, on;
 };
 
-__global__ __launch_bounds__(256) void jacobi_kernel(const double2* __restrict__ gram,
-                                                     double* __restrict__ lam,
-                                                     double2* __restrict__ psi,
-                                                     int32_t* __restrict__ info, int L,
-                                                     int max_sweeps) {
+__device__ __forceinline__ void jacobi_body(const double2* __restrict__ gram,
+                                            double* __restrict__ lam, double2* __restrict__ psi,
+                                            int32_t* __restrict__ info, int L, int max_sweeps,
+                                            int k) {
   __shared__ double2 A[EIG_MAXN * EIG_LD];
   __shared__ double2 V[EIG_MAXN * EIG_LD];
   __shared__ Rot rot[EIG_MAXN / 2];
@@ -46,7 +45,6 @@ __global__ __launch_bounds__(256) void jacobi_kernel(const double2* __restrict__
   __shared__ double2 phase[EIG_MAXN];
   __shared__ int pivot[EIG_MAXN];
 
-  const int k = blockIdx.x;
   const int tid = threadIdx.x;
   const int n = (L + 1) & ~1;             // even, includes a dummy index when L is odd
   const int half = n / 2;
@@ -189,6 +187,21 @@ __global__ __launch_bounds__(256) void jacobi_kernel(const double2* __restrict__
   if (tid == 0 && info) info[k] = converged ? sweep : -(sweep - 1);
 }
 
+__global__ __launch_bounds__(256) void jacobi_kernel(const double2* __restrict__ gram,
+                                                     double* __restrict__ lam,
+                                                     double2* __restrict__ psi,
+                                                     int32_t* __restrict__ info, int L,
+                                                     int max_sweeps) {
+  jacobi_body(gram, lam, psi, info, L, max_sweeps, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void jacobi_batch_kernel(const EigItem* __restrict__ items, int n,
+                                                           int max_sweeps) {
+  const EigItem& it = items[find_item(items, n, (int)blockIdx.x)];
+  jacobi_body(static_cast<const double2*>(it.gram), it.lam, static_cast<double2*>(it.psi), it.info,
+              it.L, max_sweeps, (int)blockIdx.x - it.start);
+}
+
 spod_status launch_eig(const Plan& p, const void* gram, double* lam, void* psi, int32_t* info,
                        void* ws, hipStream_t st) {
   (void)ws;
@@ -198,6 +211,14 @@ spod_status launch_eig(const Plan& p, const void* gram, double* lam, void* psi, 
                      (int)p.nblocks, p.max_sweeps);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SPOD_OK : hip_fail(e, "jacobi_kernel");
+}
+
+spod_status launch_eig_group(const EigItem* d_items, int n, int wgs, int max_sweeps,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(jacobi_batch_kernel, dim3((unsigned)wgs), dim3(256), 0, st, d_items, n,
+                     max_sweeps);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SPOD_OK : hip_fail(e, "jacobi_batch_kernel");
 }
 
 }  // namespace spod

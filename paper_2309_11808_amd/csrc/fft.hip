@@ -38,13 +38,6 @@ __global__ __launch_bounds__(256) void mean_kernel(const TIN* __restrict__ q, do
   if (lane == 0) mean[m] = s / (double)nt;
 }
 
-// Bins whose window DFT What_k is non-zero, for the single-pass mean removal.
-struct MeanBins {
-  int n;
-  int k[4];
-  double wr[4], wi[4];
-};
-
 // Sum over the P lanes of one transform (P a power of two <= 64).
 template <int P>
 __device__ __forceinline__ double group_sum(double x) {
@@ -74,10 +67,11 @@ __device__ __forceinline__ double group_sum(double x) {
 // fluctuations, so the FP32 transform does not lose the precision a large
 // mean would cost.  Not FUSED: mean[] was computed by mean_kernel.
 template <int NF, typename TC, typename TIN, int NPAIR, int SHIFT, bool FUSED>
-__global__ __launch_bounds__(NPAIR*(NF / 8)) void blocks_fft_kernel(
+__device__ __forceinline__ void blocks_fft_body(
     const TIN* __restrict__ q, double* __restrict__ mean, const double* __restrict__ window,
     const cpx_t<TC>* __restrict__ tw, cpx_t<TC>* __restrict__ qhat, int64_t M, int64_t nt,
-    int step, int L, int bpw, TC kappa, MeanBins mb, const int* __restrict__ sel, int nsel) {
+    int step, int L, int bpw, TC kappa, const MeanBins& mb, const int* __restrict__ sel, int nsel,
+    int64_t tile, int chunk) {
   using C = cpx_t<TC>;
   constexpr int P = NF / 8;              // lanes per transform
   constexpr int T = 2 * NPAIR;           // degrees of freedom per tile
@@ -97,7 +91,7 @@ __global__ __launch_bounds__(NPAIR*(NF / 8)) void blocks_fft_kernel(
   const int tid = threadIdx.x;
   const int f = tid / P;                 // transform (pair) index in the tile
   const int j = tid % P;                 // lane within the transform
-  const int64_t m0 = (int64_t)blockIdx.x * T;
+  const int64_t m0 = tile * T;
   const int64_t ma = m0 + 2 * f, mb_ = ma + 1;
   const bool va = ma < M, vb = mb_ < M;
   const TIN* ra = q + (va ? ma : 0) * nt;
@@ -116,7 +110,7 @@ __global__ __launch_bounds__(NPAIR*(NF / 8)) void blocks_fft_kernel(
     __syncthreads();
   }
 
-  const int l0 = blockIdx.y * bpw;
+  const int l0 = chunk * bpw;
   const int l1 = min(L, l0 + bpw);
   TIN xa[8], xb[8], na[8], nb[8];
 #pragma unroll
@@ -237,6 +231,28 @@ __global__ __launch_bounds__(NPAIR*(NF / 8)) void blocks_fft_kernel(
   }
 }
 
+template <int NF, typename TC, typename TIN, int NPAIR, int SHIFT, bool FUSED>
+__global__ __launch_bounds__(NPAIR*(NF / 8)) void blocks_fft_kernel(
+    const TIN* __restrict__ q, double* __restrict__ mean, const double* __restrict__ window,
+    const cpx_t<TC>* __restrict__ tw, cpx_t<TC>* __restrict__ qhat, int64_t M, int64_t nt,
+    int step, int L, int bpw, TC kappa, MeanBins mb, const int* __restrict__ sel, int nsel) {
+  blocks_fft_body<NF, TC, TIN, NPAIR, SHIFT, FUSED>(q, mean, window, tw, qhat, M, nt, step, L, bpw,
+                                                    kappa, mb, sel, nsel, blockIdx.x, blockIdx.y);
+}
+
+// Grouped launch over the problems of a batch that share N_f, precision, input
+// type and hop: workgroup b belongs to the last item whose first workgroup is
+// <= b, and transforms that item's tile b - start (all blocks, fused mean).
+template <int NF, typename TC, typename TIN, int NPAIR, int SHIFT>
+__global__ __launch_bounds__(NPAIR*(NF / 8)) void blocks_fft_batch_kernel(const FftItem* __restrict__ items,
+                                                                          int n) {
+  const FftItem& it = items[find_item(items, n, (int)blockIdx.x)];
+  blocks_fft_body<NF, TC, TIN, NPAIR, SHIFT, true>(
+      static_cast<const TIN*>(it.q), it.mean, it.window, static_cast<const cpx_t<TC>*>(it.tw),
+      static_cast<cpx_t<TC>*>(it.qhat), it.M, it.nt, it.step, it.L, it.L, (TC)it.kappa, it.mb,
+      nullptr, NF / 2 + 1, (int64_t)blockIdx.x - it.start, 0);
+}
+
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
@@ -331,6 +347,61 @@ static spod_status launch_fft_t(const Plan& p, const TIN* q, double* mean, void*
     case 1024: return launch_fft_nf<1024, TC, TIN>(p, q, mean, qhat, st, fused, fs);
   }
   return fail(SPOD_ERR_UNSUPPORTED, "nfft");
+}
+
+// ---------------------------------------------------------------------------
+// grouped launch for a batch: fused mean, hop N/2, nfft <= 512, the default
+// tile of the single-problem path (so results are bit-identical to it)
+// ---------------------------------------------------------------------------
+template <int NF, typename TC>
+struct GroupShape {
+  static constexpr int BASE =
+      (sizeof(TC) == 4 && FftShape<NF, 16>::NPAIR != FftShape<NF, 8>::NPAIR) ? 16 : 8;
+  using S = FftShape<NF, BASE>;
+};
+
+template <int NF, typename TC, typename TIN>
+static spod_status fft_group_nf(const FftItem* d, int n, int wgs, hipStream_t st) {
+  using S = typename GroupShape<NF, TC>::S;
+  hipLaunchKernelGGL((blocks_fft_batch_kernel<NF, TC, TIN, S::NPAIR, 4>), dim3((unsigned)wgs),
+                     dim3(S::NPAIR * S::P), 0, st, d, n);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SPOD_OK : hip_fail(e, "blocks_fft_batch_kernel");
+}
+
+template <typename TC, typename TIN>
+static spod_status fft_group_t(int nfft, const FftItem* d, int n, int wgs, hipStream_t st) {
+  switch (nfft) {
+    case 16: return fft_group_nf<16, TC, TIN>(d, n, wgs, st);
+    case 32: return fft_group_nf<32, TC, TIN>(d, n, wgs, st);
+    case 64: return fft_group_nf<64, TC, TIN>(d, n, wgs, st);
+    case 128: return fft_group_nf<128, TC, TIN>(d, n, wgs, st);
+    case 256: return fft_group_nf<256, TC, TIN>(d, n, wgs, st);
+    case 512: return fft_group_nf<512, TC, TIN>(d, n, wgs, st);
+  }
+  return fail(SPOD_ERR_UNSUPPORTED, "grouped transform: nfft");
+}
+
+int fft_group_tile(int nfft, spod_precision prec) {
+  const bool c128 = prec == SPOD_PREC_FP64;
+  switch (nfft) {
+#define SPOD_TILE(NF) \
+    case NF: return c128 ? GroupShape<NF, double>::S::T : GroupShape<NF, float>::S::T;
+    SPOD_TILE(16) SPOD_TILE(32) SPOD_TILE(64) SPOD_TILE(128) SPOD_TILE(256) SPOD_TILE(512)
+#undef SPOD_TILE
+  }
+  return 0;
+}
+
+spod_status launch_fft_group(int nfft, spod_precision prec, spod_dtype dtype, int shift,
+                             const FftItem* d_items, int n, int wgs, hipStream_t st) {
+  if (shift != 4) return fail(SPOD_ERR_UNSUPPORTED, "grouped transform: hop must be nfft/2");
+  const bool c128 = prec == SPOD_PREC_FP64;
+  if (dtype == SPOD_F32)
+    return c128 ? fft_group_t<double, float>(nfft, d_items, n, wgs, st)
+                : fft_group_t<float, float>(nfft, d_items, n, wgs, st);
+  return c128 ? fft_group_t<double, double>(nfft, d_items, n, wgs, st)
+              : fft_group_t<float, double>(nfft, d_items, n, wgs, st);
 }
 
 size_t fft_workspace(const Plan& p) { return sizeof(double) * (size_t)p.M; }

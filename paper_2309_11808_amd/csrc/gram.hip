@@ -236,7 +236,8 @@ template <int MODE, int NT, int G>
 __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __restrict__ qhat,
                                           const typename GramCfg<MODE>::T* __restrict__ sqrtw,
                                           float scale, double* __restrict__ part, int64_t M,
-                                          int L, int S, bool vec, double* red, char* lds) {
+                                          int L, int S, bool vec, double* red, char* lds, int s,
+                                          int k) {
   using Cfg = GramCfg<MODE>;
   using T = typename Cfg::T;
   using C = typename Cfg::C;
@@ -260,8 +261,6 @@ __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __res
   const int lane = tid & 63;
   const int r16 = lane & 15;
   const int g4 = lane >> 4;
-  const int s = blockIdx.x;
-  const int k = blockIdx.y;
   const C* qk = qhat + (int64_t)k * L * M;
 
   // full chunks are split over the S slices; the ragged remainder (or all of
@@ -552,20 +551,47 @@ __global__ __launch_bounds__(256, 2) void gram_kernel(const typename GramCfg<MOD
   const T* sqrtw = static_cast<const T*>(sqrtw_v);
   const float scale = (MODE == G_FP16X4) ? fscale[blockIdx.y] : 1.0f;
   switch (blockIdx.z) {
-    case 0: gram_body<MODE, NT, 0>(qhat, sqrtw, scale, part, M, L, S, vec != 0, red, gram_lds); break;
-    case 1: if constexpr (NG > 1) gram_body<MODE, NT, 1>(qhat, sqrtw, scale, part, M, L, S, vec != 0, red, gram_lds); break;
-    case 2: if constexpr (NG > 2) gram_body<MODE, NT, 2>(qhat, sqrtw, scale, part, M, L, S, vec != 0, red, gram_lds); break;
-    case 3: if constexpr (NG > 3) gram_body<MODE, NT, 3>(qhat, sqrtw, scale, part, M, L, S, vec != 0, red, gram_lds); break;
+    case 0: gram_body<MODE, NT, 0>(qhat, sqrtw, scale, part, M, L, S, vec != 0, red, gram_lds, blockIdx.x, blockIdx.y); break;
+    case 1: if constexpr (NG > 1) gram_body<MODE, NT, 1>(qhat, sqrtw, scale, part, M, L, S, vec != 0, red, gram_lds, blockIdx.x, blockIdx.y); break;
+    case 2: if constexpr (NG > 2) gram_body<MODE, NT, 2>(qhat, sqrtw, scale, part, M, L, S, vec != 0, red, gram_lds, blockIdx.x, blockIdx.y); break;
+    case 3: if constexpr (NG > 3) gram_body<MODE, NT, 3>(qhat, sqrtw, scale, part, M, L, S, vec != 0, red, gram_lds, blockIdx.x, blockIdx.y); break;
+    default: break;
+  }
+}
+
+// Grouped launch over a batch: workgroup b -> item, then (pair group, slice,
+// frequency) = the item's local index in that order.
+template <int MODE, int NT>
+__global__ __launch_bounds__(256, 2) void gram_batch_kernel(const GramItem* __restrict__ items, int n) {
+  using T = typename GramCfg<MODE>::T;
+  using C = typename GramCfg<MODE>::C;
+  constexpr int NP = NT * (NT + 1) / 2;
+  constexpr int NG = (NP + PG - 1) / PG;
+  extern __shared__ __attribute__((aligned(16))) char gram_lds[];
+  double* red = reinterpret_cast<double*>(gram_lds);
+  const GramItem& it = items[find_item(items, n, (int)blockIdx.x)];
+  const int local = (int)blockIdx.x - it.start;
+  const int g = local % NG;
+  const int s = (local / NG) % it.S;
+  const int k = local / (NG * it.S);
+  const C* qhat = static_cast<const C*>(it.qhat);
+  const T* sqrtw = static_cast<const T*>(it.sqrtw);
+  const float scale = (MODE == G_FP16X4) ? it.fscale[k] : 1.0f;
+  const bool vec = it.vec != 0;
+  switch (g) {
+    case 0: gram_body<MODE, NT, 0>(qhat, sqrtw, scale, it.part, it.M, it.L, it.S, vec, red, gram_lds, s, k); break;
+    case 1: if constexpr (NG > 1) gram_body<MODE, NT, 1>(qhat, sqrtw, scale, it.part, it.M, it.L, it.S, vec, red, gram_lds, s, k); break;
+    case 2: if constexpr (NG > 2) gram_body<MODE, NT, 2>(qhat, sqrtw, scale, it.part, it.M, it.L, it.S, vec, red, gram_lds, s, k); break;
+    case 3: if constexpr (NG > 3) gram_body<MODE, NT, 3>(qhat, sqrtw, scale, it.part, it.M, it.L, it.S, vec, red, gram_lds, s, k); break;
     default: break;
   }
 }
 
 // Sum the S partial Grams in FP64.  Each partial holds the 16 x 16 blocks
 // (a, b) with a <= b; an entry (i, j) of a lower block is conj of (j, i).
-__global__ __launch_bounds__(256) void gram_combine_kernel(const double2* __restrict__ part,
-                                                           double2* __restrict__ gram, int L, int D,
-                                                           int S) {
-  const int k = blockIdx.x;
+__device__ __forceinline__ void gram_combine_body(const double2* __restrict__ part,
+                                                  double2* __restrict__ gram, int L, int D, int S,
+                                                  int k) {
   const double2* pk = part + (int64_t)k * S * D * D;
   for (int idx = threadIdx.x; idx < L * L; idx += blockDim.x) {
     const int i = idx / L, j = idx % L;
@@ -581,13 +607,25 @@ __global__ __launch_bounds__(256) void gram_combine_kernel(const double2* __rest
   }
 }
 
+__global__ __launch_bounds__(256) void gram_combine_kernel(const double2* __restrict__ part,
+                                                           double2* __restrict__ gram, int L, int D,
+                                                           int S) {
+  gram_combine_body(part, gram, L, D, S, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void gram_combine_batch_kernel(const CombineItem* __restrict__ items,
+                                                                 int n) {
+  const CombineItem& it = items[find_item(items, n, (int)blockIdx.x)];
+  gram_combine_body(static_cast<const double2*>(it.part), static_cast<double2*>(it.gram), it.L,
+                    it.D, it.S, (int)blockIdx.x - it.start);
+}
+
 // Per-frequency power-of-two scale for the FP16 operands: 2^(15 - e) with e
 // the exponent of max_m,l |sqrt(W_m) qhat[k][l][m]| (real or imaginary part),
 // so the largest scaled value lies in [2^14, 2^15) < 65504.
-__global__ __launch_bounds__(256) void gram_scale_kernel(const float2* __restrict__ qhat,
-                                                         const float* __restrict__ sqrtw,
-                                                         float* __restrict__ scale, int64_t M, int L) {
-  const int k = blockIdx.x;
+__device__ __forceinline__ void gram_scale_body(const float2* __restrict__ qhat,
+                                                const float* __restrict__ sqrtw,
+                                                float* __restrict__ scale, int64_t M, int L, int k) {
   const float2* base = qhat + (int64_t)k * L * M;
   float mx = 0.0f;
   for (int64_t idx = threadIdx.x; idx < (int64_t)L * M; idx += 256) {
@@ -608,6 +646,19 @@ __global__ __launch_bounds__(256) void gram_scale_kernel(const float2* __restric
     if (m > 0.0f) (void)frexpf(m, &e);
     scale[k] = ldexpf(1.0f, 15 - e);
   }
+}
+
+__global__ __launch_bounds__(256) void gram_scale_kernel(const float2* __restrict__ qhat,
+                                                         const float* __restrict__ sqrtw,
+                                                         float* __restrict__ scale, int64_t M, int L) {
+  gram_scale_body(qhat, sqrtw, scale, M, L, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void gram_scale_batch_kernel(const CombineItem* __restrict__ items,
+                                                               int n) {
+  const CombineItem& it = items[find_item(items, n, (int)blockIdx.x)];
+  gram_scale_body(static_cast<const float2*>(it.part), static_cast<const float*>(it.sqrtw),
+                  static_cast<float*>(it.gram), it.M, it.L, (int)blockIdx.x - it.start);
 }
 
 // ---------------------------------------------------------------------------
@@ -675,6 +726,58 @@ spod_status launch_csd(const Plan& p, const void* qhat, void* gram, void* ws, hi
                      (int)p.nblocks, (int)D, p.gram_split);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SPOD_OK : hip_fail(e, "gram_combine_kernel");
+}
+
+// ---------------------------------------------------------------------------
+// grouped launches for a batch
+// ---------------------------------------------------------------------------
+int gram_groups(int nt16) {
+  const int np = nt16 * (nt16 + 1) / 2;
+  return (np + PG - 1) / PG;
+}
+
+template <int MODE, int NTI>
+static spod_status gram_group_nti(const GramItem* d, int n, int wgs, hipStream_t st) {
+  const size_t lds = 2 * (size_t)GramStage<NTI>::BYTES;
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gram_batch_kernel<MODE, NTI>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL((gram_batch_kernel<MODE, NTI>), dim3((unsigned)wgs), dim3(256), lds, st, d, n);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SPOD_OK : hip_fail(e, "gram_batch_kernel");
+}
+
+template <int MODE>
+static spod_status gram_group_mode(int nt16, const GramItem* d, int n, int wgs, hipStream_t st) {
+  switch (nt16) {
+    case 1: return gram_group_nti<MODE, 1>(d, n, wgs, st);
+    case 2: return gram_group_nti<MODE, 2>(d, n, wgs, st);
+    case 3: return gram_group_nti<MODE, 3>(d, n, wgs, st);
+    case 4: return gram_group_nti<MODE, 4>(d, n, wgs, st);
+  }
+  return fail(SPOD_ERR_UNSUPPORTED, "nblocks > 64");
+}
+
+spod_status launch_gram_group(spod_precision prec, int nt16, const GramItem* d_items, int n,
+                              int wgs, hipStream_t st) {
+  switch (prec) {
+    case SPOD_PREC_FP64: return gram_group_mode<G_F64>(nt16, d_items, n, wgs, st);
+    case SPOD_PREC_FP32: return gram_group_mode<G_F32>(nt16, d_items, n, wgs, st);
+    case SPOD_PREC_BF16X4: return gram_group_mode<G_BF16X4>(nt16, d_items, n, wgs, st);
+    case SPOD_PREC_FP16X4: return gram_group_mode<G_FP16X4>(nt16, d_items, n, wgs, st);
+  }
+  return fail(SPOD_ERR_INVALID_ARG, "precision");
+}
+
+spod_status launch_gram_scale_group(const CombineItem* d_items, int n, int wgs, hipStream_t st) {
+  hipLaunchKernelGGL(gram_scale_batch_kernel, dim3((unsigned)wgs), dim3(256), 0, st, d_items, n);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SPOD_OK : hip_fail(e, "gram_scale_batch_kernel");
+}
+
+spod_status launch_gram_combine_group(const CombineItem* d_items, int n, int wgs, hipStream_t st) {
+  hipLaunchKernelGGL(gram_combine_batch_kernel, dim3((unsigned)wgs), dim3(256), 0, st, d_items, n);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SPOD_OK : hip_fail(e, "gram_combine_batch_kernel");
 }
 
 }  // namespace spod

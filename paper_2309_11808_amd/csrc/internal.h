@@ -55,6 +55,8 @@ struct Plan {
 };
 
 bool is_complex128(const Plan& p);
+int64_t gram_split_for(const Plan& p, int64_t target);   // slices for ~target workgroups
+void plan_set_gram_split(Plan& p, int64_t s);            // internal: owner of the plan only
 size_t workspace_bytes(const Plan& p);
 void freeze(Plan& p);
 
@@ -90,6 +92,97 @@ spod_status launch_backward(const Plan& p, const void* q, spod_dtype dtype, cons
 size_t fft_workspace(const Plan& p);  // only used when the caller passes no mean buffer
 size_t csd_workspace(const Plan& p);
 size_t backward_workspace(const Plan& p);
+
+// --------------------------------------------------------------------------
+// grouped (batched) launches: one launch covers the workgroups of several
+// problems; item i owns workgroups [start_i, start_{i+1}) of the grid
+// --------------------------------------------------------------------------
+// Bins whose window DFT What_k is non-zero, for the single-pass mean removal.
+struct MeanBins {
+  int n;
+  int k[4];
+  double wr[4], wi[4];
+};
+
+struct FftItem {                 // blocks_fft, fused mean, all blocks per tile
+  const void* q;
+  double* mean;
+  const double* window;
+  const void* tw;
+  void* qhat;
+  int64_t M, nt;
+  int step, L;
+  double kappa;
+  MeanBins mb;
+  int start;
+};
+
+struct GramItem {                // gram partials, work unit = (group, slice, k)
+  const void* qhat;
+  const void* sqrtw;
+  const float* fscale;
+  double* part;
+  int64_t M;
+  int L, S, K, vec;
+  int start;
+};
+
+struct CombineItem {             // gram_combine / gram_scale, work unit = k
+  const void* part;              // combine: partials; scale: qhat
+  void* gram;                    // combine: gram; scale: float scales
+  const void* sqrtw;             // scale only
+  int64_t M;
+  int L, D, S;
+  int start;
+};
+
+struct EigItem {                 // jacobi, work unit = k
+  const void* gram;
+  double* lam;
+  void* psi;
+  int32_t* info;
+  int L;
+  int start;
+};
+
+struct ModesItem {               // modes, work unit = (k, tile of 256 DOFs)
+  const void* qhat;
+  const double* lam;
+  const void* psi;
+  void* phi;
+  int32_t* n_valid;
+  int64_t M;
+  int L, n_modes, tiles;
+  double eps;
+  int start;
+};
+
+// index of the item that owns workgroup b (items sorted by start, start_0 = 0)
+template <typename It>
+__device__ __forceinline__ int find_item(const It* __restrict__ items, int n, int b) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].start <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// grouped stage launchers (items already in device memory; `wgs` = total
+// workgroups).  Each returns SPOD_OK or an error.
+spod_status launch_fft_group(int nfft, spod_precision prec, spod_dtype dtype, int shift,
+                             const FftItem* d_items, int n, int wgs, hipStream_t st);
+int fft_group_tile(int nfft, spod_precision prec);   // degrees of freedom per tile
+spod_status launch_gram_group(spod_precision prec, int nt16, const GramItem* d_items, int n,
+                              int wgs, hipStream_t st);
+int gram_groups(int nt16);                           // pair groups per (slice, k)
+spod_status launch_gram_scale_group(const CombineItem* d_items, int n, int wgs, hipStream_t st);
+spod_status launch_gram_combine_group(const CombineItem* d_items, int n, int wgs, hipStream_t st);
+spod_status launch_eig_group(const EigItem* d_items, int n, int wgs, int max_sweeps,
+                             hipStream_t st);
+spod_status launch_modes_group(bool c128, const ModesItem* d_items, int n, int wgs,
+                               size_t lds_bytes, hipStream_t st);
 
 // --------------------------------------------------------------------------
 // small device helpers

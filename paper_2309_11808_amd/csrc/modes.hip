@@ -16,16 +16,15 @@ constexpr int MODES_MAXL = 64;
 constexpr int MODES_GROUP = 8;
 
 template <typename TC>
-__global__ __launch_bounds__(256) void modes_kernel(const cpx_t<TC>* __restrict__ qhat,
-                                                    const double* __restrict__ lam,
-                                                    const double2* __restrict__ psi,
-                                                    cpx_t<TC>* __restrict__ phi,
-                                                    int32_t* __restrict__ n_valid, int64_t M, int L,
-                                                    int n_modes, double eps) {
+__device__ __forceinline__ void modes_body(const cpx_t<TC>* __restrict__ qhat,
+                                           const double* __restrict__ lam,
+                                           const double2* __restrict__ psi,
+                                           cpx_t<TC>* __restrict__ phi,
+                                           int32_t* __restrict__ n_valid, int64_t M, int L,
+                                           int n_modes, double eps, int64_t bx, int k) {
   using C = cpx_t<TC>;
   extern __shared__ char modes_lds[];
   C* coef = reinterpret_cast<C*>(modes_lds);   // [L][n_modes]
-  const int k = blockIdx.y;
   const int tid = threadIdx.x;
   const double* lk = lam + (int64_t)k * L;
   const double l0 = lk[0];
@@ -37,13 +36,13 @@ __global__ __launch_bounds__(256) void modes_kernel(const cpx_t<TC>* __restrict_
     const double2 ps = psi[((int64_t)k * L + l) * L + j];
     coef[idx] = C{(TC)(ps.x * s), (TC)(ps.y * s)};
   }
-  if (blockIdx.x == 0 && tid == 0 && n_valid) {
+  if (bx == 0 && tid == 0 && n_valid) {
     int c = 0;
     for (int j = 0; j < n_modes; ++j) c += (l0 > 0.0 && lk[j] > eps * l0);
     n_valid[k] = c;
   }
   __syncthreads();
-  const int64_t m = (int64_t)blockIdx.x * blockDim.x + tid;
+  const int64_t m = bx * blockDim.x + tid;
   if (m >= M) return;
   const C* src = qhat + (int64_t)k * L * M + m;
   C* dst = phi + (int64_t)k * n_modes * M + m;
@@ -69,6 +68,25 @@ __global__ __launch_bounds__(256) void modes_kernel(const cpx_t<TC>* __restrict_
   }
 }
 
+template <typename TC>
+__global__ __launch_bounds__(256) void modes_kernel(const cpx_t<TC>* __restrict__ qhat,
+                                                    const double* __restrict__ lam,
+                                                    const double2* __restrict__ psi,
+                                                    cpx_t<TC>* __restrict__ phi,
+                                                    int32_t* __restrict__ n_valid, int64_t M, int L,
+                                                    int n_modes, double eps) {
+  modes_body<TC>(qhat, lam, psi, phi, n_valid, M, L, n_modes, eps, blockIdx.x, blockIdx.y);
+}
+
+template <typename TC>
+__global__ __launch_bounds__(256) void modes_batch_kernel(const ModesItem* __restrict__ items, int n) {
+  const ModesItem& it = items[find_item(items, n, (int)blockIdx.x)];
+  const int local = (int)blockIdx.x - it.start;
+  modes_body<TC>(static_cast<const cpx_t<TC>*>(it.qhat), it.lam, static_cast<const double2*>(it.psi),
+                 static_cast<cpx_t<TC>*>(it.phi), it.n_valid, it.M, it.L, it.n_modes, it.eps,
+                 local % it.tiles, local / it.tiles);
+}
+
 spod_status launch_modes(const Plan& p, const void* qhat, const double* lam, const void* psi,
                          int n_modes, void* phi, int32_t* n_valid, void* ws, hipStream_t st) {
   (void)ws;
@@ -87,6 +105,18 @@ spod_status launch_modes(const Plan& p, const void* qhat, const double* lam, con
                        1e-6);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SPOD_OK : hip_fail(e, "modes_kernel");
+}
+
+spod_status launch_modes_group(bool c128, const ModesItem* d_items, int n, int wgs,
+                               size_t lds_bytes, hipStream_t st) {
+  if (c128)
+    hipLaunchKernelGGL(modes_batch_kernel<double>, dim3((unsigned)wgs), dim3(256), lds_bytes, st,
+                       d_items, n);
+  else
+    hipLaunchKernelGGL(modes_batch_kernel<float>, dim3((unsigned)wgs), dim3(256), lds_bytes, st,
+                       d_items, n);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SPOD_OK : hip_fail(e, "modes_batch_kernel");
 }
 
 }  // namespace spod

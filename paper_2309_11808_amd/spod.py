@@ -206,3 +206,111 @@ class Plan:
         phi, n_valid = self.modes(qhat, lam, psi, n_modes)
         return {"mean": mean, "qhat": qhat, "gram": gram, "lam": lam, "psi": psi, "info": info,
                 "phi": phi, "n_valid": n_valid}
+
+
+class Batch:
+    """Many independent problems run with grouped launches (spod_batch_*).
+
+    problems: sequence of dicts with nspace, nvar, nt, nfft, noverlap and
+    optional window / weights.  forward(qs) returns, per problem, a dict of
+    tensors viewing the batch's output buffer (mean, lam, psi, info, phi,
+    n_valid); they are overwritten by the next forward call."""
+
+    def __init__(self, problems, precision: str = "fp64", n_modes: int = 5, grouped: bool = True,
+                 graph: bool = True, gram_target: Optional[int] = None, device=None):
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
+            else torch.device(device)
+        self.precision = precision
+        self.cdtype = torch.complex128 if precision == "fp64" else torch.complex64
+        keep = []
+        arr = (N.SpodProblem * len(problems))()
+        for i, d in enumerate(problems):
+            win = d.get("window")
+            w = d.get("weights")
+            win = None if win is None else np.ascontiguousarray(win, dtype=np.float64)
+            w = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+            keep += [win, w]
+            arr[i] = N.SpodProblem(d["nspace"], d["nvar"], d["nt"], d["nfft"], d["noverlap"],
+                                   None if win is None else win.ctypes.data,
+                                   None if w is None else w.ctypes.data)
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().spod_batch_create(arr, len(problems), PRECISIONS[precision], n_modes,
+                                           C.byref(h)))
+        self._h = h
+        for opt, v in ((N.SPOD_BATCH_GROUPED, grouped), (N.SPOD_BATCH_GRAPH, graph),
+                       (N.SPOD_BATCH_GRAM_TARGET, gram_target)):
+            if v is not None:
+                _check(lib().spod_batch_set_option(self._h, opt, int(v)))
+        ws, out = C.c_size_t(), C.c_size_t()
+        _check(lib().spod_batch_query(self._h, C.byref(ws), C.byref(out)))
+        self.workspace_bytes, self.output_bytes = ws.value, out.value
+        self.items = []
+        for i in range(len(problems)):
+            it = N.SpodBatchItem()
+            _check(lib().spod_batch_item_info(self._h, i, C.byref(it)))
+            self.items.append(it)
+        self._ws = None
+        self._out = None
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().spod_batch_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def buffers(self):
+        if self._ws is None:
+            self._ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+            self._out = torch.empty(self.output_bytes, dtype=torch.uint8, device=self.device)
+        return self._ws, self._out
+
+    def _qptrs(self, qs):
+        if len(qs) != len(self.items):
+            raise ValueError(f"expected {len(self.items)} inputs")
+        dt = qs[0].dtype
+        for q, it in zip(qs, self.items):
+            if q.dtype != dt or q.device != self.device or not q.is_contiguous():
+                raise ValueError("inputs must share a dtype and be contiguous on the batch's device")
+            if q.dim() != 2 or q.shape[0] != it.M:
+                raise ValueError("input rows do not match the problem's M")
+        ptrs = (C.c_void_p * len(qs))(*[q.data_ptr() for q in qs])
+        return ptrs, (N.SPOD_F32 if dt == torch.float32 else N.SPOD_F64)
+
+    def _view(self, off, dtype, shape):
+        n = int(np.prod(shape)) * torch.empty(0, dtype=dtype).element_size()
+        return self._out[off:off + n].view(dtype).view(*shape)
+
+    def results(self):
+        out = []
+        for it in self.items:
+            K, L, M, n = it.nfreq, it.nblocks, it.M, it.n_modes
+            out.append({"mean": self._view(it.mean, torch.float64, (M,)),
+                        "lam": self._view(it.lam, torch.float64, (K, L)),
+                        "psi": self._view(it.psi, torch.complex128, (K, L, L)),
+                        "info": self._view(it.info, torch.int32, (K,)),
+                        "phi": self._view(it.phi, self.cdtype, (K, n, M)),
+                        "n_valid": self._view(it.n_valid, torch.int32, (K,))})
+        return out
+
+    def forward(self, qs):
+        ptrs, dt = self._qptrs(qs)
+        ws, out = self.buffers()
+        _check(lib().spod_batch_forward(self._h, ptrs, dt, _ptr(out), _ptr(ws), ws.numel(),
+                                        _stream(self.device)))
+        return self.results()
+
+    def autotune(self, qs, cache_path: Optional[str] = None) -> int:
+        ptrs, dt = self._qptrs(qs)
+        ws, out = self.buffers()
+        chosen = C.c_int64()
+        _check(lib().spod_batch_autotune(self._h, ptrs, dt, _ptr(out), _ptr(ws), ws.numel(),
+                                         _stream(self.device),
+                                         None if cache_path is None else cache_path.encode(),
+                                         C.byref(chosen)))
+        return chosen.value

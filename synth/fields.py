@@ -136,6 +136,11 @@ class _RedNoise:
             a = self.rho * a + self.c * eta[i]
             out[i] = a
         self.state = a
+        if self.ny == 1:
+            # a line: the 1-D transform (the GPU FFT library rejects a 2-D
+            # transform with a dimension of length one)
+            spec = torch.fft.rfft(out, dim=-1) * self.h[0]
+            return torch.fft.irfft(spec, n=self.nx, dim=-1)
         spec = torch.fft.rfft2(out) * self.h
         return torch.fft.irfft2(spec, s=(self.ny, self.nx))
 

@@ -127,3 +127,26 @@ def test_valid_plan_without_gpu_reports_hip_error_or_succeeds(lib):
         lib.spod_plan_destroy(h)
     else:
         assert st == N.SPOD_ERR_HIP
+
+
+def test_batch_entry_points_reject_null_and_bad_problems(lib):
+    out = C.c_void_p()
+    assert lib.spod_batch_create(None, 1, 0, 5, C.byref(out)) == N.SPOD_ERR_INVALID_ARG
+    probs = (N.SpodProblem * 1)(N.SpodProblem(16, 1, 256, 64, 32, None, None))
+    assert lib.spod_batch_create(probs, 1, 0, 5, None) == N.SPOD_ERR_INVALID_ARG
+    assert lib.spod_batch_create(probs, 0, 0, 5, C.byref(out)) == N.SPOD_ERR_INVALID_ARG
+    assert lib.spod_batch_create(probs, 1, 0, 0, C.byref(out)) == N.SPOD_ERR_INVALID_ARG
+    assert lib.spod_batch_create(probs, 1, 9, 5, C.byref(out)) == N.SPOD_ERR_INVALID_ARG
+    # problem validation happens before any HIP call, with the problem's index
+    bad = (N.SpodProblem * 2)(N.SpodProblem(16, 1, 256, 64, 32, None, None),
+                              N.SpodProblem(16, 1, 256, 48, 24, None, None))
+    st = lib.spod_batch_create(bad, 2, 0, 5, C.byref(out))
+    assert st in (N.SPOD_ERR_UNSUPPORTED, N.SPOD_ERR_HIP)   # HIP: no device to create plan 0
+    assert out.value is None
+    assert lib.spod_batch_set_option(None, 0, 1) == N.SPOD_ERR_INVALID_ARG
+    assert lib.spod_batch_query(None, None, None) == N.SPOD_ERR_INVALID_ARG
+    assert lib.spod_batch_item_info(None, 0, None) == N.SPOD_ERR_INVALID_ARG
+    assert lib.spod_batch_forward(None, None, 0, None, None, 0, None) == N.SPOD_ERR_INVALID_ARG
+    assert lib.spod_batch_autotune(None, None, 0, None, None, 0, None, None,
+                                   None) == N.SPOD_ERR_INVALID_ARG
+    lib.spod_batch_destroy(None)

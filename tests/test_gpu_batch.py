@@ -1,0 +1,192 @@
+"""Batches of uneven problems (spod_batch_*), MI355X only.
+
+A batch runs the single-problem kernels through grouped launches, so every
+problem's results must be bit-identical to the single-problem path with the
+same Gram split; the small problems are also checked against the FP64 oracle.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from synth import fields
+from tests import parity as PT
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("mean", "lam", "psi", "info", "phi", "n_valid")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible: the gpu tests need an MI355X")
+    import paper_2309_11808_amd  # noqa: F401
+    yield
+
+
+def _small_specs(count, seed, max_space=3000):
+    """The batch generator's shape mix with nspace scaled down."""
+    specs = fields.batch_specs(seed=seed, count=count)
+    out = []
+    for s in specs:
+        s = dict(s)
+        s["nspace"] = 50 + s["nspace"] % max_space
+        out.append(s)
+    return out
+
+
+def _problems(specs, dtype=torch.float32):
+    return [fields.batch_problem(s, dtype=dtype, device="cuda") for s in specs]
+
+
+def _desc(p, window=None):
+    return {"nspace": p.nspace, "nvar": p.nvar, "nt": p.nt, "nfft": p.nfft,
+            "noverlap": p.noverlap, "weights": p.weights, "window": window}
+
+
+def _single(p, precision, n_modes, window=None):
+    from paper_2309_11808_amd import Plan
+    plan = Plan(p.nspace, p.nvar, p.nt, p.nfft, p.noverlap, window=window, weights=p.weights,
+                precision=precision)
+    out = plan.forward(p.q, min(n_modes, plan.nblocks))
+    torch.cuda.synchronize()
+    res = {k: out[k].clone() for k in KEYS}
+    plan.close()
+    return res
+
+
+def _same(a, b, what):
+    for k in KEYS:
+        x, y = a[k], b[k]
+        assert x.shape == y.shape, (what, k, x.shape, y.shape)
+        assert torch.equal(x, y), f"{what}: {k} differs"
+
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16x4", "fp16x4", "fp32"])
+def test_batch_bit_identical_to_single_path(precision):
+    from paper_2309_11808_amd import Batch
+    specs = _small_specs(16, seed=4)
+    probs = _problems(specs)
+    n_modes = 5
+    ref = [_single(p, precision, n_modes) for p in probs]
+    for grouped, graph in ((True, True), (True, False), (False, False), (False, True)):
+        b = Batch([_desc(p) for p in probs], precision=precision, n_modes=n_modes,
+                  grouped=grouped, graph=graph)
+        res = b.forward([p.q for p in probs])
+        torch.cuda.synchronize()
+        for i, (r, s) in enumerate(zip(res, ref)):
+            _same(r, s, f"{precision} grouped={grouped} graph={graph} problem {i}")
+        b.close()
+
+
+def test_batch_small_problems_match_oracle():
+    from paper_2309_11808_amd import Batch
+    specs = _small_specs(8, seed=11, max_space=400)
+    probs = _problems(specs, dtype=torch.float64)
+    b = Batch([_desc(p) for p in probs], precision="fp64", n_modes=3)
+    res = b.forward([p.q for p in probs])
+    torch.cuda.synchronize()
+    for p, r in zip(probs, res):
+        ref = O.spod(p.q.cpu().numpy(), p.nfft, p.noverlap, weights=p.weights, n_modes=3)
+        PT.check_eig(r["lam"], ref["lam"], rtol=1e-10, floor_rel=1e-13)
+        np.testing.assert_allclose(r["mean"].cpu().numpy(), ref["mean"], rtol=0,
+                                   atol=1e-14 * float(np.abs(p.q.cpu().numpy()).max()))
+        PT.check_modes(r["phi"], ref["phi"], ref["lam"], p.weights, r["n_valid"].cpu().numpy(),
+                       sin_tol=1e-8, elem_tol=1e-6, rel_gap=1e-6)
+    b.close()
+
+
+def test_batch_graph_replays_and_new_buffers():
+    from paper_2309_11808_amd import Batch
+    specs = _small_specs(10, seed=5)
+    probs = _problems(specs)
+    b = Batch([_desc(p) for p in probs], precision="bf16x4", n_modes=4)
+    first = [{k: v.clone() for k, v in r.items()} for r in b.forward([p.q for p in probs])]
+    torch.cuda.synchronize()
+    for rep in range(3):
+        # unrelated eager work between replays
+        junk = torch.randn(1 << 20, device="cuda").sum()
+        res = b.forward([p.q for p in probs])
+        torch.cuda.synchronize()
+        assert torch.isfinite(junk)
+        for i, (r, f) in enumerate(zip(res, first)):
+            _same(r, f, f"replay {rep} problem {i}")
+    # new input buffers (same values): tables rebuilt, graph recaptured
+    qs2 = [p.q.clone() for p in probs]
+    res = b.forward(qs2)
+    torch.cuda.synchronize()
+    for i, (r, f) in enumerate(zip(res, first)):
+        _same(r, f, f"new buffers problem {i}")
+    # new values in the same buffers: the graph sees them
+    for q in qs2:
+        q.mul_(2.0)
+    res = b.forward(qs2)
+    torch.cuda.synchronize()
+    for i, (r, f) in enumerate(zip(res, first)):
+        torch.testing.assert_close(r["lam"], 4.0 * f["lam"], rtol=1e-5, atol=1e-6 * float(f["lam"].max()))
+    b.close()
+
+
+def test_batch_windows_and_overlaps_fall_back_per_problem():
+    """Problems the grouped transform does not take (a window with every DFT
+    bin non-zero, 75% overlap) run their own transform inside the batch."""
+    from paper_2309_11808_amd import Batch
+    rng = np.random.Generator(np.random.PCG64(3))
+    probs, descs, wins = [], [], []
+    for i, (nfft, nov) in enumerate(((64, 32), (128, 96), (32, 16), (256, 128))):
+        p = fields.random_rows(97 + 31 * i, 12 * nfft, nfft, nov, seed=i, dtype=torch.float32)
+        p.q = p.q.cuda()
+        win = rng.uniform(0.2, 1.0, nfft) if i % 2 == 0 else None
+        probs.append(p)
+        wins.append(win)
+        descs.append(_desc(p, win))
+    b = Batch(descs, precision="fp64", n_modes=2)
+    res = b.forward([p.q for p in probs])
+    torch.cuda.synchronize()
+    for p, r, w in zip(probs, res, wins):
+        _same(r, _single(p, "fp64", 2, w), "fallback")
+    b.close()
+
+
+def test_batch_autotune_and_cache(tmp_path):
+    from paper_2309_11808_amd import Batch
+    specs = _small_specs(6, seed=6)
+    probs = _problems(specs)
+    cache = str(tmp_path / "tune.jsonl")
+    b = Batch([_desc(p) for p in probs], precision="bf16x4", n_modes=3)
+    t = b.autotune([p.q for p in probs], cache_path=cache)
+    assert t in (2048, 4096, 8192, 16384)
+    lines = open(cache).read().strip().splitlines()
+    assert len(lines) == 1 and json.loads(lines[0])["gram_target"] == t
+    res = b.forward([p.q for p in probs])
+    torch.cuda.synchronize()
+    # the tuned split only changes the order of the Gram sums
+    for p, r in zip(probs, res):
+        s = _single(p, "bf16x4", 3)
+        PT.check_eig_mixed(r["lam"], s["lam"], p.M, n=3, rtol=1e-5)
+    b.close()
+    # a second batch of the same shapes takes the cached choice without timing
+    b2 = Batch([_desc(p) for p in probs], precision="bf16x4", n_modes=3)
+    assert b2.autotune([p.q for p in probs], cache_path=cache) == t
+    assert len(open(cache).read().strip().splitlines()) == 1
+    b2.close()
+    os.remove(cache)
+
+
+def test_batch_rejects_bad_arguments():
+    from paper_2309_11808_amd import Batch, SpodError
+    with pytest.raises(SpodError) as ei:
+        Batch([{"nspace": 10, "nvar": 1, "nt": 100, "nfft": 48, "noverlap": 24}])
+    assert ei.value.status == -2
+    with pytest.raises(SpodError) as ei:
+        Batch([{"nspace": 10, "nvar": 1, "nt": 100, "nfft": 32, "noverlap": 32}])
+    assert ei.value.status == -1
+    p = fields.random_rows(40, 256, 32, 16, seed=1, dtype=torch.float32)
+    b = Batch([_desc(p)], precision="fp32")
+    with pytest.raises(ValueError):
+        b.forward([p.q.cuda()[:20]])
+    b.close()
