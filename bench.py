@@ -288,6 +288,11 @@ def main(argv=None):
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-diff", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-main", action="store_true",
+                    help="skip the main workload (profiling the other sections alone)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy 1 GiB device to device 3 times (a kernel of known traffic "
+                         "for scaling hardware byte counters)")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {a.gpus} is not supported "
@@ -302,6 +307,22 @@ def main(argv=None):
         return 2
     P.lib()                                   # fails loudly without libspod.so
     torch.cuda.set_device(0)
+    if a.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copied 1 GiB device to device 3 times")
+        del src, dst
+    if a.no_main:
+        result = {"metric": METRIC, "value": None, "unit": "GB/s", "n_gpus": 1}
+        if not a.no_diff:
+            result["differentiation"] = bench_differentiation(max(3, a.steps // 2), 1)
+        if not a.no_batch:
+            result["batching"] = bench_batching(max(3, a.steps // 2), 1)
+        print(json.dumps(result), flush=True)
+        return 0
     log(f"generating workload {a.workload} on the device")
     t = time.perf_counter()
     p, desc = workload(a.workload, "cuda")

@@ -192,11 +192,10 @@ spod_status build_tables(Batch& b, const void* const* q, spod_dtype dtype, char*
   for (auto& kv : gram) {
     Group g;
     g.key = kv.first;
-    const int ng = gram_groups(kv.first);
     int64_t start = 0;
     for (auto& it : kv.second) {
       it.start = (int)start;
-      start += (int64_t)ng * it.S * it.K;
+      start += gram_group_wgs(kv.first, it.S, it.K);
     }
     if (start > 0x7fffffff) return fail(SPOD_ERR_UNSUPPORTED, "batch too large for one launch");
     g.wgs = (int)start;

@@ -458,12 +458,14 @@ __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __res
     __builtin_amdgcn_s_barrier();
     __builtin_amdgcn_sched_barrier(0);
   }
-  // remaining degrees of freedom (ragged end, or everything when unaligned)
-  if (s == S - 1) {
+  // remaining degrees of freedom (ragged end, or everything when rows are not
+  // 16-byte aligned), split over the S slices like the chunks
+  {
     const int64_t m_rem = nchunk * CD;
     const int64_t ng = (M - m_rem + GDOF - 1) / GDOF;
+    const int64_t g0 = ng * s / S, g1 = ng * (s + 1) / S;
 #pragma unroll 1
-    for (int64_t g = wave; g < ng; g += 4) {
+    for (int64_t g = g0 + wave; g < g1; g += 4) {
       Raw<MODE, NT> r;
       gram_load_any<MODE, NT, NEED>(r, qk, sqrtw, m_rem + g * GDOF + g4 * DPL, M, L, r16);
       compute(r);
@@ -537,54 +539,67 @@ __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __res
   }
 }
 
+// Work units: (pair group g, slice s, frequency k).  The NG groups of one
+// (s, k) stream the same rows, so they are given workgroup ids that are equal
+// modulo 8 and 8 apart: consecutive ids go to the 8 XCDs in turn, so the
+// groups run on one XCD at the same time and share its L2.  A grid covers
+// units_padded(S K) workgroups; ids past S K units return at once.
+__host__ __device__ constexpr int64_t gram_units_padded(int64_t sk, int ng) {
+  return (sk + 7) / 8 * 8 * ng;
+}
+
+template <int MODE, int NT>
+__device__ __forceinline__ void gram_unit(const typename GramCfg<MODE>::C* __restrict__ qhat,
+                                          const typename GramCfg<MODE>::T* __restrict__ sqrtw,
+                                          const float* __restrict__ fscale, double* __restrict__ part,
+                                          int64_t M, int L, int S, int K, bool vec, int64_t local,
+                                          char* lds) {
+  constexpr int NP = NT * (NT + 1) / 2;
+  constexpr int NG = (NP + PG - 1) / PG;
+  const int64_t blk = local / (8 * NG);
+  const int r = (int)(local % (8 * NG));
+  const int g = r / 8;
+  const int64_t su = blk * 8 + (r % 8);
+  if (su >= (int64_t)S * K) return;
+  const int s = (int)(su % S);
+  const int k = (int)(su / S);
+  double* red = reinterpret_cast<double*>(lds);                      // reused after the loop
+  const float scale = (MODE == G_FP16X4) ? fscale[k] : 1.0f;
+  switch (g) {
+    case 0: gram_body<MODE, NT, 0>(qhat, sqrtw, scale, part, M, L, S, vec, red, lds, s, k); break;
+    case 1: if constexpr (NG > 1) gram_body<MODE, NT, 1>(qhat, sqrtw, scale, part, M, L, S, vec, red, lds, s, k); break;
+    case 2: if constexpr (NG > 2) gram_body<MODE, NT, 2>(qhat, sqrtw, scale, part, M, L, S, vec, red, lds, s, k); break;
+    case 3: if constexpr (NG > 3) gram_body<MODE, NT, 3>(qhat, sqrtw, scale, part, M, L, S, vec, red, lds, s, k); break;
+    default: break;
+  }
+}
+
 template <int MODE, int NT>
 __global__ __launch_bounds__(256, 2) void gram_kernel(const typename GramCfg<MODE>::C* __restrict__ qhat,
                                                       const void* __restrict__ sqrtw_v,
                                                       const float* __restrict__ fscale,
                                                       double* __restrict__ part, int64_t M, int L,
-                                                      int S, int vec) {
+                                                      int S, int K, int vec) {
   using T = typename GramCfg<MODE>::T;
-  constexpr int NP = NT * (NT + 1) / 2;
-  constexpr int NG = (NP + PG - 1) / PG;
   extern __shared__ __attribute__((aligned(16))) char gram_lds[];   // 2 stages
-  double* red = reinterpret_cast<double*>(gram_lds);                // reused after the loop
-  const T* sqrtw = static_cast<const T*>(sqrtw_v);
-  const float scale = (MODE == G_FP16X4) ? fscale[blockIdx.y] : 1.0f;
-  switch (blockIdx.z) {
-    case 0: gram_body<MODE, NT, 0>(qhat, sqrtw, scale, part, M, L, S, vec != 0, red, gram_lds, blockIdx.x, blockIdx.y); break;
-    case 1: if constexpr (NG > 1) gram_body<MODE, NT, 1>(qhat, sqrtw, scale, part, M, L, S, vec != 0, red, gram_lds, blockIdx.x, blockIdx.y); break;
-    case 2: if constexpr (NG > 2) gram_body<MODE, NT, 2>(qhat, sqrtw, scale, part, M, L, S, vec != 0, red, gram_lds, blockIdx.x, blockIdx.y); break;
-    case 3: if constexpr (NG > 3) gram_body<MODE, NT, 3>(qhat, sqrtw, scale, part, M, L, S, vec != 0, red, gram_lds, blockIdx.x, blockIdx.y); break;
-    default: break;
-  }
+  gram_unit<MODE, NT>(qhat, static_cast<const T*>(sqrtw_v), fscale, part, M, L, S, K, vec != 0,
+                      blockIdx.x, gram_lds);
 }
 
 // Grouped launch over a batch: workgroup b -> item, then (pair group, slice,
 // frequency) = the item's local index in that order.
+// Grouped launch over a batch: workgroup b -> item, then the item's local
+// index -> work unit as in gram_kernel (every item's range is a multiple of 8
+// workgroups, so the XCD of a workgroup is the same as in a launch of its own).
 template <int MODE, int NT>
 __global__ __launch_bounds__(256, 2) void gram_batch_kernel(const GramItem* __restrict__ items, int n) {
   using T = typename GramCfg<MODE>::T;
   using C = typename GramCfg<MODE>::C;
-  constexpr int NP = NT * (NT + 1) / 2;
-  constexpr int NG = (NP + PG - 1) / PG;
   extern __shared__ __attribute__((aligned(16))) char gram_lds[];
-  double* red = reinterpret_cast<double*>(gram_lds);
   const GramItem& it = items[find_item(items, n, (int)blockIdx.x)];
-  const int local = (int)blockIdx.x - it.start;
-  const int g = local % NG;
-  const int s = (local / NG) % it.S;
-  const int k = local / (NG * it.S);
-  const C* qhat = static_cast<const C*>(it.qhat);
-  const T* sqrtw = static_cast<const T*>(it.sqrtw);
-  const float scale = (MODE == G_FP16X4) ? it.fscale[k] : 1.0f;
-  const bool vec = it.vec != 0;
-  switch (g) {
-    case 0: gram_body<MODE, NT, 0>(qhat, sqrtw, scale, it.part, it.M, it.L, it.S, vec, red, gram_lds, s, k); break;
-    case 1: if constexpr (NG > 1) gram_body<MODE, NT, 1>(qhat, sqrtw, scale, it.part, it.M, it.L, it.S, vec, red, gram_lds, s, k); break;
-    case 2: if constexpr (NG > 2) gram_body<MODE, NT, 2>(qhat, sqrtw, scale, it.part, it.M, it.L, it.S, vec, red, gram_lds, s, k); break;
-    case 3: if constexpr (NG > 3) gram_body<MODE, NT, 3>(qhat, sqrtw, scale, it.part, it.M, it.L, it.S, vec, red, gram_lds, s, k); break;
-    default: break;
-  }
+  gram_unit<MODE, NT>(static_cast<const C*>(it.qhat), static_cast<const T*>(it.sqrtw), it.fscale,
+                      it.part, it.M, it.L, it.S, it.K, it.vec != 0,
+                      (int64_t)blockIdx.x - it.start, gram_lds);
 }
 
 // Sum the S partial Grams in FP64.  Each partial holds the 16 x 16 blocks
@@ -674,7 +689,7 @@ static void launch_gram_nti(const Plan& p, const void* qhat, const void* sqrtw, 
                             double* part, hipStream_t st) {
   using C = typename GramCfg<MODE>::C;
   constexpr int NP = NTI * (NTI + 1) / 2;
-  dim3 grid((unsigned)p.gram_split, (unsigned)p.nfreq, (unsigned)((NP + PG - 1) / PG));
+  dim3 grid((unsigned)gram_units_padded((int64_t)p.gram_split * p.nfreq, (NP + PG - 1) / PG));
   // 16-byte loads need 16-byte aligned rows (an aligned base and, for
   // complex64, an even M) and 16-byte aligned weights
   const bool vec = ((uintptr_t)qhat % 16 == 0) && (sizeof(C) == 16 || p.M % 2 == 0) &&
@@ -684,7 +699,7 @@ static void launch_gram_nti(const Plan& p, const void* qhat, const void* sqrtw, 
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL((gram_kernel<MODE, NTI>), grid, dim3(256), lds, st,
                      static_cast<const C*>(qhat), sqrtw, fs, part, (int64_t)p.M, (int)p.nblocks,
-                     p.gram_split, (int)vec);
+                     p.gram_split, (int)p.nfreq, (int)vec);
 }
 
 template <int MODE>
@@ -734,6 +749,10 @@ spod_status launch_csd(const Plan& p, const void* qhat, void* gram, void* ws, hi
 int gram_groups(int nt16) {
   const int np = nt16 * (nt16 + 1) / 2;
   return (np + PG - 1) / PG;
+}
+
+int64_t gram_group_wgs(int nt16, int64_t S, int64_t K) {
+  return gram_units_padded(S * K, gram_groups(nt16));
 }
 
 template <int MODE, int NTI>

@@ -177,6 +177,7 @@ int fft_group_tile(int nfft, spod_precision prec);   // degrees of freedom per t
 spod_status launch_gram_group(spod_precision prec, int nt16, const GramItem* d_items, int n,
                               int wgs, hipStream_t st);
 int gram_groups(int nt16);                           // pair groups per (slice, k)
+int64_t gram_group_wgs(int nt16, int64_t S, int64_t K);   // workgroups of one problem
 spod_status launch_gram_scale_group(const CombineItem* d_items, int n, int wgs, hipStream_t st);
 spod_status launch_gram_combine_group(const CombineItem* d_items, int n, int wgs, hipStream_t st);
 spod_status launch_eig_group(const EigItem* d_items, int n, int wgs, int max_sweeps,

@@ -142,6 +142,7 @@ def test_gradient_planted_fp64(selected, keep_qhat, phase):
     ref = _reference(p, loss, bins, None, 5)
     g = _gpu_grad(p, loss, bins, None, 5, keep_qhat=keep_qhat)
     err = _rel(g, ref)
+    print(f"planted fp64 selected={selected} keep={keep_qhat} phase={phase}: {err:.2e}")
     assert err <= TOL_FP64, f"gradient error {err:.2e}"
 
 
@@ -184,13 +185,17 @@ def test_gradient_variants_fp64(nfft, nov, M, extra, dtype, wkind):
     # float32 inputs: g_q is returned in float32
     tol = TOL_FP64 if dtype == torch.float64 else 2e-7
     err = _rel(g, ref)
+    print(f"variant nfft={nfft} nov={nov} M={M} {wkind}: {err:.2e}")
     assert err <= tol, f"gradient error {err:.2e}"
 
 
 # ---------------------------------------------------------------------------
 # mixed-precision plans (complex64 blocks, FP32 transforms)
 # ---------------------------------------------------------------------------
-MIXED_TOL = {"fp32": 2e-4, "bf16x4": 2e-4, "fp16x4": 2e-4}
+# the mixed plans' eigenvector error (about 1e-6 relative to lambda_1 from the
+# split Gram) is amplified by lambda_1 / gap <= 100 at the loss's bins (gap
+# 1e-2); measured 3e-6 to 1e-5
+MIXED_TOL = {"fp32": 1e-4, "bf16x4": 1e-4, "fp16x4": 1e-4}
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16x4", "fp16x4"])
@@ -203,6 +208,7 @@ def test_gradient_planted_mixed(precision):
     ref = _reference(p32, loss, F8, None, 5)
     g = _gpu_grad(p32, loss, F8, None, 5, precision=precision)
     err = _rel(g, ref)
+    print(f"planted {precision}: {err:.2e}")
     assert err <= MIXED_TOL[precision], f"{precision} gradient error {err:.2e}"
 
 
@@ -322,6 +328,7 @@ def test_energy_gradient_full_size(jet64):
     ref = _energy_gradient_rows(q[rows].cpu().numpy(), p.weights[rows], p.nfft, p.noverlap,
                                 O.hann_periodic(p.nfft))
     err = _rel(g[rows].cpu().numpy(), ref)
+    print(f"energy gradient full size: {err:.2e}")
     assert err <= 1e-12, f"energy gradient error {err:.2e}"
     plan.close()
 
