@@ -53,9 +53,9 @@ struct Batch {
   spod_dtype dtype_built = SPOD_F32;
   int64_t target_built = -1;
   bool tables_ok = false;
-  std::vector<Group> fft_groups, gram_groups;
+  std::vector<Group> fft_groups, gram_groups, eig_groups;   // eig: by L bucket (16, 32, 64)
   std::vector<int> fft_fallback;                 // problems launched on their own
-  Group scale_g, comb_g, eig_g, modes_g;
+  Group scale_g, comb_g, modes_g;
   size_t modes_lds = 0;
 
   hipStream_t cap_stream = nullptr;
@@ -204,9 +204,10 @@ spod_status build_tables(Batch& b, const void* const* q, spod_dtype dtype, char*
   }
   // FP16 scales, combine, eigensolve, modes: one group each
   std::vector<CombineItem> sc, cb;
-  std::vector<EigItem> eg;
+  std::map<int, std::vector<EigItem>> eg;
+  std::map<int, int64_t> s_eg;
   std::vector<ModesItem> md;
-  int64_t s_sc = 0, s_cb = 0, s_eg = 0, s_md = 0;
+  int64_t s_sc = 0, s_cb = 0, s_md = 0;
   b.modes_lds = 0;
   for (auto& s : b.pb) {
     const Plan& p = *s.plan;
@@ -238,9 +239,10 @@ spod_status build_tables(Batch& b, const void* const* q, spod_dtype dtype, char*
     e.psi = out + s.o_psi;
     e.info = reinterpret_cast<int32_t*>(out + s.o_info);
     e.L = L;
-    e.start = (int)s_eg;
-    s_eg += K;
-    eg.push_back(e);
+    const int lb = L <= 16 ? 16 : (L <= 32 ? 32 : 64);
+    e.start = (int)s_eg[lb];
+    s_eg[lb] += K;
+    eg[lb].push_back(e);
     ModesItem m{};
     m.qhat = ws + s.ws_qhat;
     m.lam = e.lam;
@@ -250,7 +252,9 @@ spod_status build_tables(Batch& b, const void* const* q, spod_dtype dtype, char*
     m.M = p.M;
     m.L = L;
     m.n_modes = s.n_modes;
-    m.tiles = (int)((p.M + 255) / 256);
+    // the same choice as the single-problem launch (so results are identical)
+    m.pair = !c128(b) && p.M % 2 == 0 && (uintptr_t)m.qhat % 16 == 0 && (uintptr_t)m.phi % 16 == 0;
+    m.tiles = (int)(((m.pair ? p.M / 2 : p.M) + 255) / 256);
     m.eps = c128(b) ? 1e-12 : 1e-6;
     m.start = (int)s_md;
     s_md += (int64_t)K * m.tiles;
@@ -265,8 +269,14 @@ spod_status build_tables(Batch& b, const void* const* q, spod_dtype dtype, char*
   }
   put(host, b.comb_g, cb);
   b.comb_g.wgs = (int)s_cb;
-  put(host, b.eig_g, eg);
-  b.eig_g.wgs = (int)s_eg;
+  b.eig_groups.clear();
+  for (auto& kv : eg) {
+    Group g;
+    g.key = kv.first;
+    put(host, g, kv.second);
+    g.wgs = (int)s_eg[kv.first];
+    b.eig_groups.push_back(g);
+  }
   put(host, b.modes_g, md);
   b.modes_g.wgs = (int)s_md;
 
@@ -331,9 +341,11 @@ spod_status record(Batch& b, const void* const* q, spod_dtype dtype, char* out, 
   }
   r = launch_gram_combine_group(at<CombineItem>(b, b.comb_g), b.comb_g.n, b.comb_g.wgs, st);
   if (r != SPOD_OK) return r;
-  r = launch_eig_group(at<EigItem>(b, b.eig_g), b.eig_g.n, b.eig_g.wgs, b.pb[0].plan->max_sweeps,
-                       st);
-  if (r != SPOD_OK) return r;
+  for (const Group& g : b.eig_groups) {
+    r = launch_eig_group(at<EigItem>(b, g), g.n, g.wgs, b.pb[0].plan->max_sweeps,
+                         eig_group_lds(g.key), st);
+    if (r != SPOD_OK) return r;
+  }
   return launch_modes_group(c128(b), at<ModesItem>(b, b.modes_g), b.modes_g.n, b.modes_g.wgs,
                             b.modes_lds, st);
 }

@@ -25,7 +25,12 @@
 namespace spod {
 
 constexpr int EIG_MAXN = 64;
-constexpr int EIG_LD = EIG_MAXN + 1;
+
+// LDS of one eigenproblem: A and V with rows of n + 1 entries (n = L rounded
+// up to even), sized at launch so that small problems share a CU.
+__host__ __device__ constexpr size_t eig_lds_bytes(int L) {
+  return 2 * sizeof(double2) * (size_t)((L + 1) & ~1) * (size_t)(((L + 1) & ~1) + 1);
+}
 
 struct Rot {
   double cs, sn, er, ei, tr, a, b;
@@ -36,8 +41,7 @@ __device__ __forceinline__ void jacobi_body(const double2* __restrict__ gram,
                                             double* __restrict__ lam, double2* __restrict__ psi,
                                             int32_t* __restrict__ info, int L, int max_sweeps,
                                             int k) {
-  __shared__ double2 A[EIG_MAXN * EIG_LD];
-  __shared__ double2 V[EIG_MAXN * EIG_LD];
+  extern __shared__ double2 eig_dyn[];
   __shared__ Rot rot[EIG_MAXN / 2];
   __shared__ int any_rot;
   __shared__ double lsh[EIG_MAXN];
@@ -48,6 +52,9 @@ __device__ __forceinline__ void jacobi_body(const double2* __restrict__ gram,
   const int tid = threadIdx.x;
   const int n = (L + 1) & ~1;             // even, includes a dummy index when L is odd
   const int half = n / 2;
+  const int EIG_LD = n + 1;
+  double2* A = eig_dyn;                   // [n][n + 1]
+  double2* V = eig_dyn + n * EIG_LD;      // [n][n + 1]
   const double2* G = gram + (int64_t)k * L * L;
 
   for (int idx = tid; idx < n * n; idx += blockDim.x) {
@@ -202,11 +209,30 @@ __global__ __launch_bounds__(256) void jacobi_batch_kernel(const EigItem* __rest
               it.L, max_sweeps, (int)blockIdx.x - it.start);
 }
 
+static bool eig_attr_done = false;
+
+static hipError_t eig_attr() {
+  if (eig_attr_done) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_kernel),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)eig_lds_bytes(EIG_MAXN));
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_batch_kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)eig_lds_bytes(EIG_MAXN));
+  if (e == hipSuccess) eig_attr_done = true;
+  return e;
+}
+
+size_t eig_group_lds(int L) { return eig_lds_bytes(L); }
+
 spod_status launch_eig(const Plan& p, const void* gram, double* lam, void* psi, int32_t* info,
                        void* ws, hipStream_t st) {
   (void)ws;
   if (p.nblocks > EIG_MAXN) return fail(SPOD_ERR_UNSUPPORTED, "nblocks > 64");
-  hipLaunchKernelGGL(jacobi_kernel, dim3((unsigned)p.nfreq), dim3(256), 0, st,
+  hipError_t ea = eig_attr();
+  if (ea != hipSuccess) return hip_fail(ea, "hipFuncSetAttribute");
+  hipLaunchKernelGGL(jacobi_kernel, dim3((unsigned)p.nfreq), dim3(256),
+                     eig_lds_bytes((int)p.nblocks), st,
                      static_cast<const double2*>(gram), lam, static_cast<double2*>(psi), info,
                      (int)p.nblocks, p.max_sweeps);
   hipError_t e = hipGetLastError();
@@ -214,8 +240,10 @@ spod_status launch_eig(const Plan& p, const void* gram, double* lam, void* psi, 
 }
 
 spod_status launch_eig_group(const EigItem* d_items, int n, int wgs, int max_sweeps,
-                             hipStream_t st) {
-  hipLaunchKernelGGL(jacobi_batch_kernel, dim3((unsigned)wgs), dim3(256), 0, st, d_items, n,
+                             size_t lds_bytes, hipStream_t st) {
+  hipError_t ea = eig_attr();
+  if (ea != hipSuccess) return hip_fail(ea, "hipFuncSetAttribute");
+  hipLaunchKernelGGL(jacobi_batch_kernel, dim3((unsigned)wgs), dim3(256), lds_bytes, st, d_items, n,
                      max_sweeps);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SPOD_OK : hip_fail(e, "jacobi_batch_kernel");

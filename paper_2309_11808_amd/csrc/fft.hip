@@ -38,6 +38,21 @@ __global__ __launch_bounds__(256) void mean_kernel(const TIN* __restrict__ q, do
   if (lane == 0) mean[m] = s / (double)nt;
 }
 
+// Streaming stores of two adjacent complex values (16-byte aligned address):
+// the blocks are written once and read by a later kernel, so they bypass the
+// caches on the way out.
+__device__ __forceinline__ void store_pair(float2* o, float2 a, float2 b) {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  const v4 v = {a.x, a.y, b.x, b.y};
+  __builtin_nontemporal_store(v, reinterpret_cast<v4*>(o));
+}
+__device__ __forceinline__ void store_pair(double2* o, double2 a, double2 b) {
+  typedef double v2 __attribute__((ext_vector_type(2)));
+  const v2 va = {a.x, a.y}, vb = {b.x, b.y};
+  __builtin_nontemporal_store(va, reinterpret_cast<v2*>(o));
+  __builtin_nontemporal_store(vb, reinterpret_cast<v2*>(o) + 1);
+}
+
 // Sum over the P lanes of one transform (P a power of two <= 64).
 template <int P>
 __device__ __forceinline__ double group_sum(double x) {
@@ -97,6 +112,8 @@ __device__ __forceinline__ void blocks_fft_body(
   const TIN* ra = q + (va ? ma : 0) * nt;
   const TIN* rb = q + (vb ? mb_ : 0) * nt;
   C* buf = lds + f * LDP;
+  // two adjacent complex values per 16-byte aligned store (complex64 needs an even M)
+  const bool pair_ok = ((uintptr_t)qhat % 16 == 0) && (sizeof(TC) == 8 || (M & 1) == 0);
   if (sel)
     for (int i = tid; i < nsel; i += NTH) ksel[i] = sel[i];
 
@@ -165,40 +182,59 @@ __device__ __forceinline__ void blocks_fft_body(
     for (int r = 0; r < 8; ++r) buf[pad8(j + r * P)] = v[r];
     __syncthreads();
 
-    // separate the two real spectra and write qhat[s][l][m0 .. m0+T), where
-    // output row s holds frequency k = s (or ksel[s] for a bin selection)
-    C* out = qhat + (int64_t)l * M;
-    for (int idx = tid; idx < nsel * T; idx += NTH) {
-      const int d = idx % T;
-      const int s = idx / T;
-      const int k = sel ? ksel[s] : s;
-      const C* row = lds + (d >> 1) * LDP;
-      const C A = row[pad8(k)];
-      const C Bc = row[pad8((NF - k) & (NF - 1))];
-      const C B = C{Bc.x, -Bc.y};
-      const C X = (d & 1) == 0 ? cadd(A, B) : cmul_mi(csub(A, B));
-      const TC sc = (TC)0.5 * kappa;
-      const int64_t m = m0 + d;
-      if (m < M) out[(int64_t)s * L * M + m] = C{X.x * sc, X.y * sc};
-    }
-    __syncthreads();
-
-    if (more) {
+    // take in the prefetched samples of block l+1 now, before this block's
+    // stores are issued: the vector-memory counter also counts stores, so a
+    // wait placed after the store loop would wait for every store as well.
+    // The shift is unconditional (after the last block the registers are
+    // dead): loads used only under a branch get sunk into it, past the
+    // transform, which would undo the prefetch.
 #pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        if (r < 8 - NEWR) {
-          xa[r] = xa[r + NEWR];
-          xb[r] = xb[r + NEWR];
-        } else {
-          xa[r] = va ? na[r] : (TIN)0;
-          xb[r] = vb ? nb[r] : (TIN)0;
-          if constexpr (FUSED) {
-            sa += (double)xa[r] - mua;
-            sb += (double)xb[r] - mub;
-          }
+    for (int r = 0; r < 8; ++r) {
+      if (r < 8 - NEWR) {
+        xa[r] = xa[r + NEWR];
+        xb[r] = xb[r + NEWR];
+      } else {
+        xa[r] = va ? na[r] : (TIN)0;
+        xb[r] = vb ? nb[r] : (TIN)0;
+        if constexpr (FUSED) {
+          sa += more ? (double)xa[r] - mua : 0.0;
+          sb += more ? (double)xb[r] - mub : 0.0;
         }
       }
     }
+    // an empty asm that reads the new samples pins their arrival (the wait
+    // on the prefetch) here, ahead of the store loop
+#pragma unroll
+    for (int r = 8 - NEWR; r < 8; ++r) asm volatile("" ::"v"(xa[r]), "v"(xb[r]));
+
+    // separate the two real spectra and write qhat[s][l][m0 .. m0+T), where
+    // output row s holds frequency k = s (or ksel[s] for a bin selection).
+    // One thread per (row, pair): X_a = (A + conj B) / 2 and
+    // X_b = (A - conj B) / (2i) come from the same two LDS reads, and the two
+    // adjacent degrees of freedom are written with one 16-byte streaming store.
+    C* out = qhat + (int64_t)l * M;
+    const TC sc = (TC)0.5 * kappa;
+    for (int idx = tid; idx < nsel * NPAIR; idx += NTH) {
+      const int f2 = idx % NPAIR;
+      const int s = idx / NPAIR;
+      const int k = sel ? ksel[s] : s;
+      const C* row = lds + f2 * LDP;
+      const C A = row[pad8(k)];
+      const C Bc = row[pad8((NF - k) & (NF - 1))];
+      const C Xa = C{(A.x + Bc.x) * sc, (A.y - Bc.y) * sc};
+      const TC dx = A.x - Bc.x, dy = A.y + Bc.y;
+      const C Xb = C{dy * sc, -(dx * sc)};
+      const int64_t m = m0 + 2 * f2;
+      C* o = out + (int64_t)s * L * M + m;
+      if (pair_ok && m + 1 < M) {
+        store_pair(o, Xa, Xb);
+      } else {
+        if (m < M) o[0] = Xa;
+        if (m + 1 < M) o[1] = Xb;
+      }
+    }
+    __syncthreads();
+
   }
 
   if constexpr (FUSED) {
@@ -322,12 +358,11 @@ static spod_status launch_fft_shape(const Plan& p, const TIN* q, double* mean, v
 template <int NF, typename TC, typename TIN>
 static spod_status launch_fft_nf(const Plan& p, const TIN* q, double* mean, void* qhat,
                                  hipStream_t st, bool fused, const FftSel& fs) {
-  // Tile of 32 degrees of freedom (16 transforms; 1024 threads at N = 512):
-  // every frequency row is written in runs of 256 bytes, which the HBM takes
-  // markedly better than 128-byte runs.  Default for complex64; complex128
-  // keeps 16 (its runs are 256 bytes already, and 1024 threads would leave
-  // it 128 registers per lane).  SPOD_OPT_FFT_TILE = 16 or 32 overrides.
-  const bool wide = p.fft_tile_opt == 32 || (p.fft_tile_opt == 0 && sizeof(TC) == 4);
+  // Tile of 16 degrees of freedom (8 transforms; 512 threads at N = 512) by
+  // default: two workgroups share a CU, so one's stores overlap the other's
+  // transform (measured faster than 32 at N = 512 for both complex types).
+  // SPOD_OPT_FFT_TILE = 32 selects the wide tile.
+  const bool wide = p.fft_tile_opt == 32;
   if (wide && FftShape<NF, 16>::NPAIR != FftShape<NF, 8>::NPAIR)
     return launch_fft_shape<NF, TC, TIN, 16>(p, q, mean, qhat, st, fused, fs);
   return launch_fft_shape<NF, TC, TIN, 8>(p, q, mean, qhat, st, fused, fs);
@@ -355,9 +390,7 @@ static spod_status launch_fft_t(const Plan& p, const TIN* q, double* mean, void*
 // ---------------------------------------------------------------------------
 template <int NF, typename TC>
 struct GroupShape {
-  static constexpr int BASE =
-      (sizeof(TC) == 4 && FftShape<NF, 16>::NPAIR != FftShape<NF, 8>::NPAIR) ? 16 : 8;
-  using S = FftShape<NF, BASE>;
+  using S = FftShape<NF, 8>;
 };
 
 template <int NF, typename TC, typename TIN>

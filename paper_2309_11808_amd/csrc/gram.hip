@@ -11,7 +11,10 @@
 // FP64 by a second kernel.
 //
 // Arithmetic per precision:
-//   FP64    v_mfma_f64_16x16x4f64, FP64 accumulation.
+//   FP64    v_mfma_f64_16x16x4f64, FP64 accumulation, three real products
+//           per complex one: T1 = A_a A_b^T, T2 = B_a B_b^T and
+//           T3 = (A_a - B_a)(A_b + B_b)^T give Re = T1 + T2 and
+//           Im = T3 - T1 + T2 (this path is bound by FP64 MFMA issue).
 //   FP32    v_mfma_f32_16x16x4f32; the two products of one 4-wide step start
 //           from zero and are added into FP64 registers at once.
 //   BF16X4  y = hi + lo with hi = bf16(y), lo = bf16(y - hi) (round to nearest
@@ -269,7 +272,10 @@ __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __res
   const int64_t c0 = nchunk * s / S, c1 = nchunk * (s + 1) / S;
 
   ACC accR[NPG], accI[NPG];          // FP64: running sums; split modes: correction terms
+  ACC accG[MODE == G_F64 ? NPG : 1]; // FP64: the third product of the 3-multiplication form
   double sR[NPG][4], sI[NPG][4];     // FP64 sums of the FP32 partials (not FP64 mode)
+#pragma unroll
+  for (int i = 0; i < (MODE == G_F64 ? NPG : 1); ++i) accG[i] = ACC{0, 0, 0, 0};
 #pragma unroll
   for (int i = 0; i < NPG; ++i) {
     accR[i] = ACC{0, 0, 0, 0};
@@ -284,12 +290,14 @@ __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __res
       // four 4-wide MFMA steps; step t uses element t of every lane's run
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        T fa[NT], fb[NT];
+        T fa[NT], fb[NT], fd[NT], fs[NT];
 #pragma unroll
         for (int a = 0; a < NT; ++a) {
           const bool live = 16 * a + r16 < L;
           fa[a] = live ? cur.x[a][t].x * cur.w[t] : (T)0;
           fb[a] = live ? cur.x[a][t].y * cur.w[t] : (T)0;
+          fd[a] = fa[a] - fb[a];
+          fs[a] = fa[a] + fb[a];
         }
         int pi = 0;
 #pragma unroll
@@ -299,10 +307,12 @@ __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __res
             if (pi < P0 || pi >= P0 + NPG) continue;
             const int i = pi - P0;
             if constexpr (MODE == G_F64) {
+              // three real products per complex one: T1 = A_a A_b^T,
+              // T2 = B_a B_b^T, T3 = (A_a - B_a)(A_b + B_b)^T; at the end
+              // Re = T1 + T2 and Im = T3 - T1 + T2 (= A_a B_b^T - B_a A_b^T)
               accR[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fa[b], accR[i], 0, 0, 0);
-              accR[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[a], fb[b], accR[i], 0, 0, 0);
-              accI[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], accI[i], 0, 0, 0);
-              accI[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(-fb[a], fa[b], accI[i], 0, 0, 0);
+              accI[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[a], fb[b], accI[i], 0, 0, 0);
+              accG[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(fd[a], fs[b], accG[i], 0, 0, 0);
             } else {
               ACC tr = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[a], fa[b], ACC{0, 0, 0, 0}, 0, 0, 0);
               tr = __builtin_amdgcn_mfma_f32_16x16x4f32(fb[a], fb[b], tr, 0, 0, 0);
@@ -476,8 +486,8 @@ __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __res
     for (int i = 0; i < NPG; ++i)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        sR[i][v] = accR[i][v];
-        sI[i][v] = accI[i][v];
+        sR[i][v] = accR[i][v] + accI[i][v];
+        sI[i][v] = (accG[i][v] - accR[i][v]) + accI[i][v];
       }
   } else if constexpr (SPLIT) {
 #pragma unroll

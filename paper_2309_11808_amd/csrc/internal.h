@@ -153,6 +153,7 @@ struct ModesItem {               // modes, work unit = (k, tile of 256 DOFs)
   int32_t* n_valid;
   int64_t M;
   int L, n_modes, tiles;
+  int pair;                      // two DOFs per thread (complex64, even M, aligned)
   double eps;
   int start;
 };
@@ -181,7 +182,8 @@ int64_t gram_group_wgs(int nt16, int64_t S, int64_t K);   // workgroups of one p
 spod_status launch_gram_scale_group(const CombineItem* d_items, int n, int wgs, hipStream_t st);
 spod_status launch_gram_combine_group(const CombineItem* d_items, int n, int wgs, hipStream_t st);
 spod_status launch_eig_group(const EigItem* d_items, int n, int wgs, int max_sweeps,
-                             hipStream_t st);
+                             size_t lds_bytes, hipStream_t st);
+size_t eig_group_lds(int L);                         // dynamic LDS of one eigenproblem
 spod_status launch_modes_group(bool c128, const ModesItem* d_items, int n, int wgs,
                                size_t lds_bytes, hipStream_t st);
 

@@ -15,7 +15,10 @@ namespace spod {
 constexpr int MODES_MAXL = 64;
 constexpr int MODES_GROUP = 8;
 
-template <typename TC>
+// Pairs of degrees of freedom as one 16-byte vector (complex64 only).
+typedef float modes_v4 __attribute__((ext_vector_type(4)));
+
+template <typename TC, bool PAIR>
 __device__ __forceinline__ void modes_body(const cpx_t<TC>* __restrict__ qhat,
                                            const double* __restrict__ lam,
                                            const double2* __restrict__ psi,
@@ -23,6 +26,7 @@ __device__ __forceinline__ void modes_body(const cpx_t<TC>* __restrict__ qhat,
                                            int32_t* __restrict__ n_valid, int64_t M, int L,
                                            int n_modes, double eps, int64_t bx, int k) {
   using C = cpx_t<TC>;
+  static_assert(!PAIR || sizeof(TC) == 4, "pairs are 16-byte complex64 vectors");
   extern __shared__ char modes_lds[];
   C* coef = reinterpret_cast<C*>(modes_lds);   // [L][n_modes]
   const int tid = threadIdx.x;
@@ -42,67 +46,107 @@ __device__ __forceinline__ void modes_body(const cpx_t<TC>* __restrict__ qhat,
     n_valid[k] = c;
   }
   __syncthreads();
-  const int64_t m = bx * blockDim.x + tid;
+  constexpr int DPT = PAIR ? 2 : 1;            // degrees of freedom per thread
+  const int64_t m = (bx * blockDim.x + tid) * DPT;
   if (m >= M) return;
   const C* src = qhat + (int64_t)k * L * M + m;
   C* dst = phi + (int64_t)k * n_modes * M + m;
   for (int j0 = 0; j0 < n_modes; j0 += MODES_GROUP) {
-    C acc[MODES_GROUP];
+    C acc[DPT][MODES_GROUP];
 #pragma unroll
-    for (int j = 0; j < MODES_GROUP; ++j) acc[j] = C{0, 0};
+    for (int d = 0; d < DPT; ++d)
+#pragma unroll
+      for (int j = 0; j < MODES_GROUP; ++j) acc[d][j] = C{0, 0};
     for (int l = 0; l < L; ++l) {
-      const C x = src[(int64_t)l * M];
+      C x[DPT];
+      if constexpr (PAIR) {
+        const modes_v4 v = __builtin_nontemporal_load(reinterpret_cast<const modes_v4*>(src + (int64_t)l * M));
+        x[0] = C{v[0], v[1]};
+        x[1] = C{v[2], v[3]};
+      } else {
+        x[0] = src[(int64_t)l * M];
+      }
       const C* cl = coef + l * n_modes + j0;
 #pragma unroll
       for (int j = 0; j < MODES_GROUP; ++j) {
         if (j0 + j < n_modes) {
           const C c = cl[j];
-          acc[j].x += x.x * c.x - x.y * c.y;
-          acc[j].y += x.x * c.y + x.y * c.x;
+#pragma unroll
+          for (int d = 0; d < DPT; ++d) {
+            acc[d][j].x += x[d].x * c.x - x[d].y * c.y;
+            acc[d][j].y += x[d].x * c.y + x[d].y * c.x;
+          }
         }
       }
     }
 #pragma unroll
-    for (int j = 0; j < MODES_GROUP; ++j)
-      if (j0 + j < n_modes) dst[(int64_t)(j0 + j) * M] = acc[j];
+    for (int j = 0; j < MODES_GROUP; ++j) {
+      if (j0 + j < n_modes) {
+        if constexpr (PAIR) {
+          const modes_v4 v = {acc[0][j].x, acc[0][j].y, acc[1][j].x, acc[1][j].y};
+          __builtin_nontemporal_store(v, reinterpret_cast<modes_v4*>(dst + (int64_t)(j0 + j) * M));
+        } else {
+          dst[(int64_t)(j0 + j) * M] = acc[0][j];
+        }
+      }
+    }
   }
 }
 
-template <typename TC>
+template <typename TC, bool PAIR>
 __global__ __launch_bounds__(256) void modes_kernel(const cpx_t<TC>* __restrict__ qhat,
                                                     const double* __restrict__ lam,
                                                     const double2* __restrict__ psi,
                                                     cpx_t<TC>* __restrict__ phi,
                                                     int32_t* __restrict__ n_valid, int64_t M, int L,
                                                     int n_modes, double eps) {
-  modes_body<TC>(qhat, lam, psi, phi, n_valid, M, L, n_modes, eps, blockIdx.x, blockIdx.y);
+  modes_body<TC, PAIR>(qhat, lam, psi, phi, n_valid, M, L, n_modes, eps, blockIdx.x, blockIdx.y);
 }
 
 template <typename TC>
 __global__ __launch_bounds__(256) void modes_batch_kernel(const ModesItem* __restrict__ items, int n) {
   const ModesItem& it = items[find_item(items, n, (int)blockIdx.x)];
   const int local = (int)blockIdx.x - it.start;
-  modes_body<TC>(static_cast<const cpx_t<TC>*>(it.qhat), it.lam, static_cast<const double2*>(it.psi),
-                 static_cast<cpx_t<TC>*>(it.phi), it.n_valid, it.M, it.L, it.n_modes, it.eps,
-                 local % it.tiles, local / it.tiles);
+  if constexpr (sizeof(TC) == 4) {
+    if (it.pair) {
+      modes_body<TC, true>(static_cast<const cpx_t<TC>*>(it.qhat), it.lam,
+                           static_cast<const double2*>(it.psi), static_cast<cpx_t<TC>*>(it.phi),
+                           it.n_valid, it.M, it.L, it.n_modes, it.eps, local % it.tiles,
+                           local / it.tiles);
+      return;
+    }
+  }
+  modes_body<TC, false>(static_cast<const cpx_t<TC>*>(it.qhat), it.lam,
+                        static_cast<const double2*>(it.psi), static_cast<cpx_t<TC>*>(it.phi),
+                        it.n_valid, it.M, it.L, it.n_modes, it.eps, local % it.tiles,
+                        local / it.tiles);
 }
 
 spod_status launch_modes(const Plan& p, const void* qhat, const double* lam, const void* psi,
                          int n_modes, void* phi, int32_t* n_valid, void* ws, hipStream_t st) {
   (void)ws;
   if (p.nblocks > MODES_MAXL) return fail(SPOD_ERR_UNSUPPORTED, "nblocks > 64");
-  dim3 grid((unsigned)((p.M + 255) / 256), (unsigned)p.nfreq);
   const size_t lds = (is_complex128(p) ? 16 : 8) * (size_t)p.nblocks * (size_t)n_modes;
-  if (is_complex128(p))
-    hipLaunchKernelGGL(modes_kernel<double>, grid, dim3(256), lds, st,
+  if (is_complex128(p)) {
+    dim3 grid((unsigned)((p.M + 255) / 256), (unsigned)p.nfreq);
+    hipLaunchKernelGGL((modes_kernel<double, false>), grid, dim3(256), lds, st,
                        static_cast<const double2*>(qhat), lam, static_cast<const double2*>(psi),
                        static_cast<double2*>(phi), n_valid, (int64_t)p.M, (int)p.nblocks, n_modes,
                        1e-12);
-  else
-    hipLaunchKernelGGL(modes_kernel<float>, grid, dim3(256), lds, st,
+  } else if (p.M % 2 == 0 && (uintptr_t)qhat % 16 == 0 && (uintptr_t)phi % 16 == 0) {
+    // two degrees of freedom per thread, 16-byte loads and stores
+    dim3 grid((unsigned)((p.M / 2 + 255) / 256), (unsigned)p.nfreq);
+    hipLaunchKernelGGL((modes_kernel<float, true>), grid, dim3(256), lds, st,
                        static_cast<const float2*>(qhat), lam, static_cast<const double2*>(psi),
                        static_cast<float2*>(phi), n_valid, (int64_t)p.M, (int)p.nblocks, n_modes,
                        1e-6);
+  } else {
+    dim3 grid((unsigned)((p.M + 255) / 256), (unsigned)p.nfreq);
+    hipLaunchKernelGGL((modes_kernel<float, false>), grid, dim3(256), lds, st,
+                       static_cast<const float2*>(qhat), lam, static_cast<const double2*>(psi),
+                       static_cast<float2*>(phi), n_valid, (int64_t)p.M, (int)p.nblocks, n_modes,
+                       1e-6);
+  }
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SPOD_OK : hip_fail(e, "modes_kernel");
 }

@@ -361,3 +361,48 @@ def test_directional_derivative_full_size(jet64):
     print(f"directional derivative: fd {fd!r} adjoint {dd!r} rel {abs(fd - dd) / abs(dd):.2e}")
     assert abs(fd - dd) <= 1e-5 * abs(dd), (fd, dd)
     plan.close()
+
+
+def test_central_differences_64_entries_full_size(jet64):
+    """dE/dq at 64 seeded entries against (E(q + h e) - E(q - h e)) / 2h,
+    h = 1e-4, with the FP64 GPU forward, for the 8-bin loss."""
+    from paper_2309_11808_amd import spod
+    p, q = jet64
+    plan = _plan(p)
+    out = _forward(plan, q, 5)
+    lam = out["lam"].cpu().numpy()
+    del out
+    F8 = _separated_bins(lam, 8)
+    loss = _make_loss(p.weights, _probes(len(F8), p.M, p.weights, seed=9))
+    qg = q.clone().requires_grad_(True)
+    lam_s, phi_s = spod(qg, plan, n_modes=5, bins=F8)
+    loss(lam_s, phi_s).backward()
+    g = qg.grad.detach()
+    rng = np.random.Generator(np.random.PCG64(64))
+    ent = rng.choice(q.numel(), 64, replace=False)
+    h = 1e-4
+    qp = q.clone()
+    flat = qp.view(-1)
+    fd = np.empty(64)
+    with torch.no_grad():
+        for n, e in enumerate(ent):
+            x0 = float(flat[e])
+            flat[e] = x0 + h
+            ep = float(loss(*spod(qp, plan, n_modes=5, bins=F8)))
+            flat[e] = x0 - h
+            em = float(loss(*spod(qp, plan, n_modes=5, bins=F8)))
+            flat[e] = x0
+            fd[n] = (ep - em) / (2 * h)
+    with torch.no_grad():
+        E0 = float(loss(*spod(q, plan, n_modes=5, bins=F8)))
+    ga = g.view(-1)[torch.as_tensor(ent, device="cuda")].cpu().numpy()
+    err = np.abs(fd - ga)
+    # a central difference resolves dE only to the rounding of E itself,
+    # about eps |E| / h, besides its O(h^2) truncation
+    noise = 10.0 * np.finfo(np.float64).eps * abs(E0) / h
+    agg = float(np.linalg.norm(fd - ga) / np.linalg.norm(ga))
+    print(f"central differences: E {E0:.4e}, rounding floor {noise:.1e}, max |fd - g| "
+          f"{err.max():.2e}, max |g| {np.abs(ga).max():.2e}, aggregate rel {agg:.2e}")
+    assert np.all(err <= 1e-4 * np.abs(ga) + noise)
+    assert agg <= 1e-4
+    plan.close()

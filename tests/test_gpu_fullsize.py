@@ -1,0 +1,136 @@
+"""Parity at the workloads' full sizes (MI355X only).
+
+The HIP path runs the whole problem in the same configuration the benchmark
+times; the FP64 oracle (streamed over chunks of degrees of freedom, the
+paper's spatial split done sequentially) computes the outputs it can afford:
+the eigenvalues and modes of selected frequencies, the modes at sampled
+degrees of freedom, the means, and sampled Fourier blocks.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from synth import fields
+from tests import parity as PT
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible: the gpu tests need an MI355X")
+    import paper_2309_11808_amd  # noqa: F401
+    yield
+
+
+def _plan(p, precision):
+    from paper_2309_11808_amd import Plan
+    return Plan(p.nspace, p.nvar, p.nt, p.nfft, p.noverlap, weights=p.weights, precision=precision)
+
+
+def _modes_rows_error(phi_gpu, phi_ora, n_valid, lam, rel_gap):
+    """Largest relative error of the sampled rows of every valid, separated
+    mode (the phase convention makes the modes unique)."""
+    worst = 0.0
+    for k in range(phi_ora.shape[0]):
+        for j in range(min(phi_ora.shape[1], int(n_valid[k]))):
+            if not PT.separated(lam[k], j, rel_gap):
+                continue
+            o = phi_ora[k, j]
+            e = np.linalg.norm(phi_gpu[k, j] - o) / np.linalg.norm(o)
+            worst = max(worst, float(e))
+    return worst
+
+
+# ---------------------------------------------------------------------------
+# jet-like field: 256 x 128 x 3, N_t = 4096 float32, N_f = 256, 31 blocks, 129 bins
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def jet():
+    p = fields.jet_like(seed=2, device="cuda", dtype=torch.float32)
+    q_host = p.q.cpu().numpy()
+    bins = [0, 10, 20, 35, 50, 77, 100, 128]          # the 4 packet bins and 4 others
+    rng = np.random.Generator(np.random.PCG64(12))
+    rows = np.sort(rng.choice(p.M, 512, replace=False))
+    ref = O.spod_chunked(q_host, p.nfft, p.noverlap, weights=p.weights, n_modes=5,
+                         chunk=16384, bins=bins, mode_rows=rows)
+    return p, bins, rows, ref
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x4"])
+def test_jet_field_full_size(jet, precision):
+    p, bins, rows, ref = jet
+    plan = _plan(p, precision)
+    out = plan.forward(p.q, n_modes=5)
+    torch.cuda.synchronize()
+    idx = torch.as_tensor(bins, device="cuda")
+    lam = out["lam"].index_select(0, idx).cpu().numpy()
+    np.testing.assert_allclose(out["mean"].cpu().numpy(), ref["mean"], rtol=0,
+                               atol=1e-13 * float(np.abs(ref["mean"]).max()) + 1e-12)
+    if precision == "fp64":
+        err = PT.check_eig(lam, ref["lam"], rtol=1e-10, floor_rel=1e-13, n=5)
+        tol_modes, gap = 1e-7, 1e-6
+    else:
+        err = PT.check_eig_mixed(lam, ref["lam"], p.M, n=5, rtol=1e-4)
+        tol_modes, gap = 1e-3, 1e-3
+    phi = out["phi"].index_select(0, idx)[:, :, torch.as_tensor(rows, device="cuda")].cpu().numpy()
+    merr = _modes_rows_error(phi, ref["phi"], out["n_valid"].index_select(0, idx).cpu().numpy(),
+                             ref["lam"], gap)
+    print(f"jet {precision}: eigenvalue rel err {err:.2e}, sampled mode rows {merr:.2e}")
+    assert merr <= tol_modes
+    assert int(out["info"].min()) > 0
+    plan.close()
+
+
+# ---------------------------------------------------------------------------
+# ERA-like field: 1024 x 512 x 2, N_t = 8192 float32, N_f = 512, 31 blocks,
+# 257 bins, in the benchmark's launch configuration (bf16x4 and FP64 plans)
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def era():
+    p = fields.era_like(seed=3, device="cuda", dtype=torch.float32)
+    bins = [3, 100]                                    # a planted bin and a noise bin
+    rng = np.random.Generator(np.random.PCG64(13))
+    rows = np.sort(rng.choice(p.M, 256, replace=False))
+    q_host = p.q.cpu().numpy()
+    ref = O.spod_chunked(q_host, p.nfft, p.noverlap, weights=p.weights, n_modes=5,
+                         chunk=32768, bins=bins, mode_rows=rows)
+    # Fourier blocks of the sampled rows at every frequency (one by one)
+    ref["qhat_rows"] = O.fourier_blocks(q_host[rows], p.nfft, p.noverlap, O.hann_periodic(p.nfft),
+                                        ref["mean"][rows], None)
+    del q_host
+    return p, bins, rows, ref
+
+
+@pytest.mark.parametrize("precision", ["bf16x4", "fp64"])
+def test_era_field_full_size(era, precision):
+    p, bins, rows, ref = era
+    plan = _plan(p, precision)
+    out = plan.forward(p.q, n_modes=5)
+    torch.cuda.synchronize()
+    rows_d = torch.as_tensor(rows, device="cuda")
+    idx = torch.as_tensor(bins, device="cuda")
+    mean = out["mean"].index_select(0, rows_d).cpu().numpy()
+    np.testing.assert_allclose(mean, ref["mean"][rows], rtol=0,
+                               atol=1e-13 * float(np.abs(ref["mean"]).max()) + 1e-12)
+    qh = out["qhat"][:, :, rows_d].cpu().numpy()
+    qtol = 1e-12 if precision == "fp64" else 2e-6
+    qerr = PT.check_qhat(qh, ref["qhat_rows"], qtol)
+    lam = out["lam"].index_select(0, idx).cpu().numpy()
+    if precision == "fp64":
+        err = PT.check_eig(lam, ref["lam"], rtol=1e-10, floor_rel=1e-13, n=5)
+        tol_modes, gap = 1e-7, 1e-6
+    else:
+        err = PT.check_eig_mixed(lam, ref["lam"], p.M, n=5, rtol=1e-4)
+        tol_modes, gap = 1e-3, 1e-3
+    phi = out["phi"].index_select(0, idx)[:, :, rows_d].cpu().numpy()
+    merr = _modes_rows_error(phi, ref["phi"], out["n_valid"].index_select(0, idx).cpu().numpy(),
+                             ref["lam"], gap)
+    print(f"era {precision}: qhat {qerr:.2e}, eigenvalue rel err {err:.2e}, "
+          f"sampled mode rows {merr:.2e}")
+    assert merr <= tol_modes
+    del out
+    plan.close()
+    torch.cuda.empty_cache()
