@@ -25,12 +25,11 @@ spod_status hip_fail(hipError_t e, const char* where) {
 bool is_complex128(const Plan& p) { return p.prec == SPOD_PREC_FP64; }
 
 int64_t gram_split_for(const Plan& p, int64_t target) {
-  // about `target` workgroups (8192 measured best on the 1M-DOF workload: 32
-  // slices x 257 frequencies), but keep at least ~4 chunks of degrees of
-  // freedom per slice so the partial sums stay cheap
-  const int64_t nt = (p.nblocks + 15) / 16;
-  const int64_t ng = (nt * (nt + 1) / 2 + 2) / 3;
-  int64_t s = (target + p.nfreq * ng - 1) / (p.nfreq * ng);
+  // about `target` workgroups (one per slice and frequency; 8192 measured
+  // best on the 1M-DOF workload: 32 slices x 257 frequencies), but keep at
+  // least ~4 chunks of degrees of freedom per slice so the partial sums stay
+  // cheap
+  int64_t s = (target + p.nfreq - 1) / p.nfreq;
   int64_t cap = p.M / 512;
   if (cap < 1) cap = 1;
   if (s > cap) s = cap;

@@ -358,11 +358,12 @@ static spod_status launch_fft_shape(const Plan& p, const TIN* q, double* mean, v
 template <int NF, typename TC, typename TIN>
 static spod_status launch_fft_nf(const Plan& p, const TIN* q, double* mean, void* qhat,
                                  hipStream_t st, bool fused, const FftSel& fs) {
-  // Tile of 16 degrees of freedom (8 transforms; 512 threads at N = 512) by
-  // default: two workgroups share a CU, so one's stores overlap the other's
-  // transform (measured faster than 32 at N = 512 for both complex types).
-  // SPOD_OPT_FFT_TILE = 32 selects the wide tile.
-  const bool wide = p.fft_tile_opt == 32;
+  // Default tile (measured on 393,216 DOFs, 50% overlap): 16 degrees of
+  // freedom at N >= 512 (512 threads, two workgroups share a CU, so one's
+  // stores overlap the other's transform), 32 for shorter transforms (more
+  // work per workgroup; up to 18% faster at N = 128 for complex128).
+  // SPOD_OPT_FFT_TILE = 16 or 32 overrides.
+  const bool wide = p.fft_tile_opt == 32 || (p.fft_tile_opt == 0 && NF <= 256);
   if (wide && FftShape<NF, 16>::NPAIR != FftShape<NF, 8>::NPAIR)
     return launch_fft_shape<NF, TC, TIN, 16>(p, q, mean, qhat, st, fused, fs);
   return launch_fft_shape<NF, TC, TIN, 8>(p, q, mean, qhat, st, fused, fs);
@@ -390,7 +391,7 @@ static spod_status launch_fft_t(const Plan& p, const TIN* q, double* mean, void*
 // ---------------------------------------------------------------------------
 template <int NF, typename TC>
 struct GroupShape {
-  using S = FftShape<NF, 8>;
+  using S = FftShape<NF, (NF <= 256) ? 16 : 8>;   // the single-problem default tile
 };
 
 template <int NF, typename TC, typename TIN>

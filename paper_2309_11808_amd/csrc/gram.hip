@@ -6,9 +6,10 @@
 // four real products with a long contraction over the degrees of freedom, run
 // on MFMA in 16 x 16 blocks of M_k (upper blocks only; M_k is Hermitian).  The
 // paper reduces this sum over space across MPI ranks; here the M axis is split
-// into S slices, one workgroup per (slice, frequency), each of its four waves
-// streaming its own part of the slice, and the S partial Grams are combined in
-// FP64 by a second kernel.
+// into S slices, one workgroup per (slice, frequency), whose four waves share
+// LDS-staged chunks of the slice (splitting the chunk's degrees of freedom,
+// or, for L > 32, the 16 x 16 block pairs), and the S partial Grams are
+// combined in FP64 by a second kernel.
 //
 // Arithmetic per precision:
 //   FP64    v_mfma_f64_16x16x4f64, FP64 accumulation, three real products
@@ -235,7 +236,13 @@ __device__ __forceinline__ void stage_issue(char* stage, const char* __restrict_
   }
 }
 
-template <int MODE, int NT, int G>
+// G: the pair group this wave computes; WPG: waves per group (4 / number of
+// groups).  With one group (L <= 32) all four waves share the pairs and split
+// each chunk's degrees of freedom; with 2 or 4 groups (L <= 48, <= 64) each
+// wave runs its group's instantiation over the chunk that all four waves
+// loaded, so the rows are read from HBM once per workgroup.  Every
+// instantiation executes the same barriers, in the same order.
+template <int MODE, int NT, int G, int WPG>
 __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __restrict__ qhat,
                                           const typename GramCfg<MODE>::T* __restrict__ sqrtw,
                                           float scale, double* __restrict__ part, int64_t M,
@@ -249,7 +256,7 @@ __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __res
   constexpr int DPL = Cfg::DPL;
   constexpr int GDOF = 4 * DPL;                             // degrees of freedom per group
   constexpr int CD = 1024 / (int)sizeof(C);                 // degrees of freedom per chunk
-  constexpr int GPW = CD / GDOF / 4;                        // groups per wave per chunk
+  constexpr int GPW = CD / GDOF / WPG;                      // DOF groups per wave per chunk
   constexpr int D = 16 * NT;
   constexpr int NP = NT * (NT + 1) / 2;
   constexpr int P0 = G * PG;
@@ -261,6 +268,7 @@ __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __res
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
+  const int wsub = wave % WPG;          // this wave's share of the chunk within its group
   const int lane = tid & 63;
   const int r16 = lane & 15;
   const int g4 = lane >> 4;
@@ -434,7 +442,7 @@ __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __res
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int gw = 0; gw < GPW; ++gw) {
-      const int base = (wave * GPW + gw) * GDOF + g4 * DPL;   // this lane's run within the chunk
+      const int base = (wsub * GPW + gw) * GDOF + g4 * DPL;   // this lane's run within the chunk
       Raw<MODE, NT> r;
 #pragma unroll
       for (int a = 0; a < NT; ++a) {
@@ -475,7 +483,7 @@ __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __res
     const int64_t ng = (M - m_rem + GDOF - 1) / GDOF;
     const int64_t g0 = ng * s / S, g1 = ng * (s + 1) / S;
 #pragma unroll 1
-    for (int64_t g = g0 + wave; g < g1; g += 4) {
+    for (int64_t g = g0 + wsub; g < g1; g += WPG) {
       Raw<MODE, NT> r;
       gram_load_any<MODE, NT, NEED>(r, qk, sqrtw, m_rem + g * GDOF + g4 * DPL, M, L, r16);
       compute(r);
@@ -513,16 +521,18 @@ __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __res
   // prefetch of every wave first
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  // sum the four waves through LDS, one wave at a time
+  // sum the group's waves through LDS (each group has its own region), one
+  // wave at a time
+  double* rg = red + G * (PG * 2 * 4 * 64);
 #pragma unroll 1
-  for (int w = 0; w < 4; ++w) {
-    if (wave == w) {
+  for (int w = 0; w < WPG; ++w) {
+    if (wsub == w) {
 #pragma unroll
       for (int i = 0; i < NPG; ++i)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          double* rr = &red[((2 * i) * 4 + v) * 64 + lane];
-          double* ri = &red[((2 * i + 1) * 4 + v) * 64 + lane];
+          double* rr = &rg[((2 * i) * 4 + v) * 64 + lane];
+          double* ri = &rg[((2 * i + 1) * 4 + v) * 64 + lane];
           *rr = (w == 0) ? sR[i][v] : *rr + sR[i][v];
           *ri = (w == 0) ? sI[i][v] : *ri + sI[i][v];
         }
@@ -533,7 +543,7 @@ __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __res
   // 4*(lane/16)+v for the FP32-accumulating instructions, but row lane/16+4*v
   // for v_mfma_f64_16x16x4f64.  Partials are stored as complex [D][D].
   double2* out = reinterpret_cast<double2*>(part) + ((int64_t)k * S + s) * D * D;
-  for (int idx = tid; idx < NPG * 4 * 64; idx += 256) {
+  for (int idx = wsub * 64 + lane; idx < NPG * 4 * 64; idx += 64 * WPG) {
     const int ln = idx & 63;
     const int v = (idx >> 6) & 3;
     const int i = idx >> 8;
@@ -545,19 +555,12 @@ __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __res
     const int b = a + rem;
     const int r = (MODE == G_F64) ? (ln >> 4) + 4 * v : 4 * (ln >> 4) + v;
     out[(16 * a + r) * D + 16 * b + (ln & 15)] =
-        make_double2(red[((2 * i) * 4 + v) * 64 + ln], red[((2 * i + 1) * 4 + v) * 64 + ln]);
+        make_double2(rg[((2 * i) * 4 + v) * 64 + ln], rg[((2 * i + 1) * 4 + v) * 64 + ln]);
   }
 }
 
-// Work units: (pair group g, slice s, frequency k).  The NG groups of one
-// (s, k) stream the same rows, so they are given workgroup ids that are equal
-// modulo 8 and 8 apart: consecutive ids go to the 8 XCDs in turn, so the
-// groups run on one XCD at the same time and share its L2.  A grid covers
-// units_padded(S K) workgroups; ids past S K units return at once.
-__host__ __device__ constexpr int64_t gram_units_padded(int64_t sk, int ng) {
-  return (sk + 7) / 8 * 8 * ng;
-}
-
+// Work unit = (slice s, frequency k), one workgroup each; the pair groups of
+// a unit are spread over the workgroup's waves (see gram_body).
 template <int MODE, int NT>
 __device__ __forceinline__ void gram_unit(const typename GramCfg<MODE>::C* __restrict__ qhat,
                                           const typename GramCfg<MODE>::T* __restrict__ sqrtw,
@@ -566,20 +569,19 @@ __device__ __forceinline__ void gram_unit(const typename GramCfg<MODE>::C* __res
                                           char* lds) {
   constexpr int NP = NT * (NT + 1) / 2;
   constexpr int NG = (NP + PG - 1) / PG;
-  const int64_t blk = local / (8 * NG);
-  const int r = (int)(local % (8 * NG));
-  const int g = r / 8;
-  const int64_t su = blk * 8 + (r % 8);
-  if (su >= (int64_t)S * K) return;
-  const int s = (int)(su % S);
-  const int k = (int)(su / S);
+  static_assert(NG == 1 || NG == 2 || NG == 4, "pair groups must divide the 4 waves");
+  constexpr int WPG = 4 / NG;
+  if (local >= (int64_t)S * K) return;
+  const int s = (int)(local % S);
+  const int k = (int)(local / S);
   double* red = reinterpret_cast<double*>(lds);                      // reused after the loop
   const float scale = (MODE == G_FP16X4) ? fscale[k] : 1.0f;
+  const int g = (int)(threadIdx.x >> 6) / WPG;
   switch (g) {
-    case 0: gram_body<MODE, NT, 0>(qhat, sqrtw, scale, part, M, L, S, vec, red, lds, s, k); break;
-    case 1: if constexpr (NG > 1) gram_body<MODE, NT, 1>(qhat, sqrtw, scale, part, M, L, S, vec, red, lds, s, k); break;
-    case 2: if constexpr (NG > 2) gram_body<MODE, NT, 2>(qhat, sqrtw, scale, part, M, L, S, vec, red, lds, s, k); break;
-    case 3: if constexpr (NG > 3) gram_body<MODE, NT, 3>(qhat, sqrtw, scale, part, M, L, S, vec, red, lds, s, k); break;
+    case 0: gram_body<MODE, NT, 0, WPG>(qhat, sqrtw, scale, part, M, L, S, vec, red, lds, s, k); break;
+    case 1: if constexpr (NG > 1) gram_body<MODE, NT, 1, WPG>(qhat, sqrtw, scale, part, M, L, S, vec, red, lds, s, k); break;
+    case 2: if constexpr (NG > 2) gram_body<MODE, NT, 2, WPG>(qhat, sqrtw, scale, part, M, L, S, vec, red, lds, s, k); break;
+    case 3: if constexpr (NG > 3) gram_body<MODE, NT, 3, WPG>(qhat, sqrtw, scale, part, M, L, S, vec, red, lds, s, k); break;
     default: break;
   }
 }
@@ -599,8 +601,7 @@ __global__ __launch_bounds__(256, 2) void gram_kernel(const typename GramCfg<MOD
 // Grouped launch over a batch: workgroup b -> item, then (pair group, slice,
 // frequency) = the item's local index in that order.
 // Grouped launch over a batch: workgroup b -> item, then the item's local
-// index -> work unit as in gram_kernel (every item's range is a multiple of 8
-// workgroups, so the XCD of a workgroup is the same as in a launch of its own).
+// index -> work unit as in gram_kernel.
 template <int MODE, int NT>
 __global__ __launch_bounds__(256, 2) void gram_batch_kernel(const GramItem* __restrict__ items, int n) {
   using T = typename GramCfg<MODE>::T;
@@ -699,7 +700,8 @@ static void launch_gram_nti(const Plan& p, const void* qhat, const void* sqrtw, 
                             double* part, hipStream_t st) {
   using C = typename GramCfg<MODE>::C;
   constexpr int NP = NTI * (NTI + 1) / 2;
-  dim3 grid((unsigned)gram_units_padded((int64_t)p.gram_split * p.nfreq, (NP + PG - 1) / PG));
+  (void)NP;
+  dim3 grid((unsigned)((int64_t)p.gram_split * p.nfreq));
   // 16-byte loads need 16-byte aligned rows (an aligned base and, for
   // complex64, an even M) and 16-byte aligned weights
   const bool vec = ((uintptr_t)qhat % 16 == 0) && (sizeof(C) == 16 || p.M % 2 == 0) &&
@@ -762,7 +764,8 @@ int gram_groups(int nt16) {
 }
 
 int64_t gram_group_wgs(int nt16, int64_t S, int64_t K) {
-  return gram_units_padded(S * K, gram_groups(nt16));
+  (void)nt16;
+  return S * K;
 }
 
 template <int MODE, int NTI>
