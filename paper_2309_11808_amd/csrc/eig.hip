@@ -108,43 +108,63 @@ __device__ __forceinline__ void jacobi_body(const double2* __restrict__ gram,
         rot[tid] = r;
       }
       __syncthreads();
-      // rows: A <- J^H A  (row p' = cs A_p - sn e A_q ; row q' = sn conj(e) A_p + cs A_q)
-      for (int idx = tid; idx < half * n; idx += blockDim.x) {
-        const Rot& r = rot[idx / n];
-        if (!r.on) continue;
-        const int c = idx % n;
-        const double2 ap = A[r.p * EIG_LD + c], aq = A[r.q * EIG_LD + c];
-        const double2 e = make_double2(r.er, r.ei);
-        const double2 eaq = cmul(e, aq);          // e * A_q
-        const double2 ecap = cmulc(ap, e);        // conj(e) * A_p
-        A[r.p * EIG_LD + c] = make_double2(r.cs * ap.x - r.sn * eaq.x, r.cs * ap.y - r.sn * eaq.y);
-        A[r.q * EIG_LD + c] = make_double2(r.sn * ecap.x + r.cs * aq.x, r.sn * ecap.y + r.cs * aq.y);
-      }
-      __syncthreads();
-      // columns: A <- A J and V <- V J
-      //   (col p' = cs A_p - sn conj(e) A_q ; col q' = sn e A_p + cs A_q)
-      for (int idx = tid; idx < 2 * half * n; idx += blockDim.x) {
-        const int which = idx / (half * n);
-        const int rem = idx % (half * n);
-        const Rot& r = rot[rem / n];
-        if (!r.on) continue;
-        const int row = rem % n;
-        double2* X = which == 0 ? A : V;
-        const double2 xp = X[row * EIG_LD + r.p], xq = X[row * EIG_LD + r.q];
-        const double2 e = make_double2(r.er, r.ei);
-        const double2 ecxq = cmulc(xq, e);        // conj(e) * X_q
-        const double2 exp_ = cmul(e, xp);         // e * X_p
-        X[row * EIG_LD + r.p] = make_double2(r.cs * xp.x - r.sn * ecxq.x, r.cs * xp.y - r.sn * ecxq.y);
-        X[row * EIG_LD + r.q] = make_double2(r.sn * exp_.x + r.cs * xq.x, r.sn * exp_.y + r.cs * xq.y);
-      }
-      __syncthreads();
-      if (tid < half) {
-        const Rot& r = rot[tid];
-        if (r.on) {
-          A[r.p * EIG_LD + r.q] = make_double2(0.0, 0.0);
-          A[r.q * EIG_LD + r.p] = make_double2(0.0, 0.0);
-          A[r.p * EIG_LD + r.p] = make_double2(r.a - r.tr, 0.0);
-          A[r.q * EIG_LD + r.q] = make_double2(r.b + r.tr, 0.0);
+      // A <- J^H A J and V <- V J.  The planes of a round are disjoint, so the
+      // 2 x 2 block of A in the rows of plane P and the columns of plane Q
+      // depends on itself only: one thread updates it (rows, then columns:
+      //   row p' = cs A_p - sn e A_q,        row q' = sn conj(e) A_p + cs A_q,
+      //   col p' = cs A_p - sn conj(e) A_q,  col q' = sn e A_p + cs A_q),
+      // and a diagonal block (P = Q) is set to its exact result.
+      for (int idx = tid; idx < half * half + n * half; idx += blockDim.x) {
+        if (idx < half * half) {
+          const int P = idx / half, Q = idx % half;
+          const Rot& r1 = rot[P];
+          const Rot& r2 = rot[Q];
+          if (!r1.on && !r2.on) continue;
+          double2* x00 = &A[r1.p * EIG_LD + r2.p];
+          double2* x01 = &A[r1.p * EIG_LD + r2.q];
+          double2* x10 = &A[r1.q * EIG_LD + r2.p];
+          double2* x11 = &A[r1.q * EIG_LD + r2.q];
+          double2 y00 = *x00, y01 = *x01, y10 = *x10, y11 = *x11;
+          if (r1.on) {
+            const double2 e = make_double2(r1.er, r1.ei);
+            const double2 eq0 = cmul(e, y10), eq1 = cmul(e, y11);      // e * A_q
+            const double2 ep0 = cmulc(y00, e), ep1 = cmulc(y01, e);    // conj(e) * A_p
+            y00 = make_double2(r1.cs * y00.x - r1.sn * eq0.x, r1.cs * y00.y - r1.sn * eq0.y);
+            y01 = make_double2(r1.cs * y01.x - r1.sn * eq1.x, r1.cs * y01.y - r1.sn * eq1.y);
+            y10 = make_double2(r1.sn * ep0.x + r1.cs * y10.x, r1.sn * ep0.y + r1.cs * y10.y);
+            y11 = make_double2(r1.sn * ep1.x + r1.cs * y11.x, r1.sn * ep1.y + r1.cs * y11.y);
+          }
+          if (r2.on) {
+            const double2 e = make_double2(r2.er, r2.ei);
+            const double2 cq0 = cmulc(y01, e), cq1 = cmulc(y11, e);    // conj(e) * A_q
+            const double2 ep0 = cmul(e, y00), ep1 = cmul(e, y10);      // e * A_p
+            const double2 z00 = make_double2(r2.cs * y00.x - r2.sn * cq0.x, r2.cs * y00.y - r2.sn * cq0.y);
+            const double2 z10 = make_double2(r2.cs * y10.x - r2.sn * cq1.x, r2.cs * y10.y - r2.sn * cq1.y);
+            y01 = make_double2(r2.sn * ep0.x + r2.cs * y01.x, r2.sn * ep0.y + r2.cs * y01.y);
+            y11 = make_double2(r2.sn * ep1.x + r2.cs * y11.x, r2.sn * ep1.y + r2.cs * y11.y);
+            y00 = z00;
+            y10 = z10;
+          }
+          if (P == Q) {
+            y00 = make_double2(r1.a - r1.tr, 0.0);
+            y11 = make_double2(r1.b + r1.tr, 0.0);
+            y01 = y10 = make_double2(0.0, 0.0);
+          }
+          *x00 = y00;
+          *x01 = y01;
+          *x10 = y10;
+          *x11 = y11;
+        } else {
+          const int rem = idx - half * half;
+          const int row = rem / half;
+          const Rot& r = rot[rem % half];
+          if (!r.on) continue;
+          const double2 xp = V[row * EIG_LD + r.p], xq = V[row * EIG_LD + r.q];
+          const double2 e = make_double2(r.er, r.ei);
+          const double2 ecxq = cmulc(xq, e);        // conj(e) * V_q
+          const double2 exp_ = cmul(e, xp);         // e * V_p
+          V[row * EIG_LD + r.p] = make_double2(r.cs * xp.x - r.sn * ecxq.x, r.cs * xp.y - r.sn * ecxq.y);
+          V[row * EIG_LD + r.q] = make_double2(r.sn * exp_.x + r.cs * xq.x, r.sn * exp_.y + r.cs * xq.y);
         }
       }
       __syncthreads();
