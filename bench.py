@@ -45,6 +45,30 @@ METRIC = "SPOD input GB/s (FFT+CSD+eig+modes), mixed vs FP64 at eig rel err ≤1
 HBM_PEAK_GBS = 8000.0
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spod_blocks_fft_era_1024x512x2_nt8192_bf16x4_traffic.txt")
+
+
+def committed_traffic():
+    """HBM bytes per spod_blocks_fft launch from the committed FETCH_SIZE /
+    WRITE_SIZE counter runs, or None once the transform's source differs from
+    the one the counters were taken on."""
+    import hashlib
+    import re
+    try:
+        txt = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    t = re.search(r"traffic_bytes_per_launch: (\d+)", txt)
+    h = re.search(r"source_sha256 .*: ([0-9a-f]{64})", txt)
+    if not t or not h:
+        return None
+    d = hashlib.sha256()
+    for f in ("fft.hip", "fft_core.h"):
+        with open(os.path.join(ROOT, "paper_2309_11808_amd", "csrc", f), "rb") as fh:
+            d.update(fh.read())
+    return int(t.group(1)) if d.hexdigest() == h.group(1) else None
+
+
 def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
@@ -290,9 +314,6 @@ def main(argv=None):
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-main", action="store_true",
                     help="skip the main workload (profiling the other sections alone)")
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="first copy 1 GiB device to device 3 times (a kernel of known traffic "
-                         "for scaling hardware byte counters)")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {a.gpus} is not supported "
@@ -307,14 +328,6 @@ def main(argv=None):
         return 2
     P.lib()                                   # fails loudly without libspod.so
     torch.cuda.set_device(0)
-    if a.calibrate_copy:
-        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        log("copied 1 GiB device to device 3 times")
-        del src, dst
     if a.no_main:
         result = {"metric": METRIC, "value": None, "unit": "GB/s", "n_gpus": 1}
         if not a.no_diff:
@@ -356,7 +369,9 @@ def main(argv=None):
         "stages_ms": {k: round(v, 4) for k, v in mixed["stages_ms"].items()},
         "roofline": {"bound": "hbm", "kernel": "spod_blocks_fft (mean + windowed block FFT)",
                      "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": committed_traffic() if (a.workload == "era" and
+                                                        a.precision == "bf16x4") else None,
                      "algorithmic_bytes_per_launch": fft_bytes},
         "checks": {"jacobi_info_min": mixed["info_min"], "n_valid_min": mixed["n_valid_min"]},
     }

@@ -2,9 +2,11 @@
 
     python -m paper_2309_11808_amd.build [--jobs N] [--verbose]
 
-Every source under csrc/ is compiled to an object under _build/ at the
-repository root and linked into paper_2309_11808_amd/libspod.so.  The build
-always recompiles (it is the "does it build" check as well as the build).
+Every library source under csrc/ is compiled to an object under _build/ at
+the repository root and linked into paper_2309_11808_amd/libspod.so; the
+plain C caller csrc/spod_bench.cpp becomes paper_2309_11808_amd/spod_bench.
+The build always recompiles (it is the "does it build" check as well as the
+build).
 """
 from __future__ import annotations
 
@@ -69,6 +71,17 @@ def build(jobs: int = 0, verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"linking libspod.so failed:\n{r.stderr}")
     os.replace(tmp, LIB)
+    # spod_bench: a plain C-ABI caller of the library (hardware-counter runs)
+    drv = os.path.join(PKG, "spod_bench")
+    cmd = [_hipcc(), "-x", "hip"] + [c for c in COMMON if c != "-fPIC"] + [
+        os.path.join(CSRC, "spod_bench.cpp"), "-L", PKG, "-lspod", "-Wl,-rpath,$ORIGIN",
+        "-o", drv + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"building spod_bench failed:\n{r.stderr}")
+    os.replace(drv + ".tmp", drv)
     return LIB
 
 

@@ -1,0 +1,125 @@
+// spod_bench: a plain C-ABI caller of libspod, with nothing else in the
+// process (no Python, no framework), for hardware-counter runs.
+//
+//   spod_bench [nspace nvar nt nfft noverlap reps precision]
+//   defaults:   524288  2   8192 512  256      3    2 (bf16x4)
+//
+// Fills q [M][nt] float32 on the device with hashed values in [-1, 1), runs
+// spod_blocks_fft `reps` times, then copies 1 GiB device to device three
+// times with its own copy kernel (a dispatch of known traffic: 1 GiB read and
+// 1 GiB written), and prints the event timings.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+
+#include "spod.h"
+
+#define CHECK_HIP(x)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (x);                                                          \
+    if (e_ != hipSuccess) {                                                       \
+      std::fprintf(stderr, "%s failed: %s\n", #x, hipGetErrorString(e_));         \
+      return 1;                                                                   \
+    }                                                                             \
+  } while (0)
+
+#define CHECK_SPOD(x)                                                             \
+  do {                                                                            \
+    spod_status s_ = (x);                                                         \
+    if (s_ != SPOD_OK) {                                                          \
+      std::fprintf(stderr, "%s failed: %s\n", #x, spod_last_error());             \
+      return 1;                                                                   \
+    }                                                                             \
+  } while (0)
+
+__global__ void fill_kernel(float* __restrict__ q, int64_t n, uint32_t seed) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t h = (uint32_t)i * 2654435761u ^ (uint32_t)(i >> 32) * 40503u ^ seed;
+    h ^= h >> 16;
+    h *= 0x7feb352du;
+    h ^= h >> 15;
+    h *= 0x846ca68bu;
+    h ^= h >> 16;
+    q[i] = (float)(h >> 8) * (1.0f / 8388608.0f) - 1.0f;
+  }
+}
+
+__global__ void copy_kernel(const float4* __restrict__ src, float4* __restrict__ dst, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+int main(int argc, char** argv) {
+  int64_t nspace = 524288, nvar = 2, nt = 8192, nfft = 512, nov = 256, reps = 3, prec = 2;
+  int64_t* args[] = {&nspace, &nvar, &nt, &nfft, &nov, &reps, &prec};
+  for (int i = 1; i < argc && i <= 7; ++i) *args[i - 1] = std::atoll(argv[i]);
+  const int64_t M = nspace * nvar;
+
+  spod_plan plan = nullptr;
+  CHECK_SPOD(spod_plan_create(nspace, nvar, nt, nfft, nov, nullptr, nullptr, &plan));
+  CHECK_SPOD(spod_plan_set_precision(plan, (spod_precision)prec));
+  int64_t L = 0, K = 0;
+  size_t wsb = 0;
+  CHECK_SPOD(spod_plan_query(plan, &L, &K, &wsb));
+  const size_t csz = prec == SPOD_PREC_FP64 ? 16 : 8;
+  const size_t qbytes = sizeof(float) * (size_t)M * (size_t)nt;
+  const size_t hbytes = csz * (size_t)K * (size_t)L * (size_t)M;
+  std::printf("M=%lld nt=%lld nfft=%lld L=%lld K=%lld q=%.3f GB qhat=%.3f GB\n", (long long)M,
+              (long long)nt, (long long)nfft, (long long)L, (long long)K, qbytes / 1e9, hbytes / 1e9);
+  std::fflush(stdout);
+
+  float* q = nullptr;
+  void* qhat = nullptr;
+  double* mean = nullptr;
+  void* ws = nullptr;
+  CHECK_HIP(hipMalloc(&q, qbytes));
+  CHECK_HIP(hipMalloc(&qhat, hbytes));
+  CHECK_HIP(hipMalloc(&mean, sizeof(double) * (size_t)M));
+  CHECK_HIP(hipMalloc(&ws, wsb > 0 ? wsb : 256));
+  hipLaunchKernelGGL(fill_kernel, dim3(8192), dim3(256), 0, 0, q, (int64_t)(qbytes / 4), 12345u);
+  CHECK_HIP(hipGetLastError());
+  CHECK_HIP(hipDeviceSynchronize());
+
+  hipEvent_t e0, e1;
+  CHECK_HIP(hipEventCreate(&e0));
+  CHECK_HIP(hipEventCreate(&e1));
+  for (int64_t r = 0; r < reps; ++r) {
+    CHECK_HIP(hipEventRecord(e0, 0));
+    CHECK_SPOD(spod_blocks_fft(plan, q, SPOD_F32, qhat, mean, ws, wsb, nullptr));
+    CHECK_HIP(hipEventRecord(e1, 0));
+    CHECK_HIP(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
+    std::printf("spod_blocks_fft %lld: %.3f ms, %.3f TB/s of algorithmic bytes\n", (long long)r, ms,
+                (qbytes + hbytes) / (ms * 1e-3) / 1e12);
+    std::fflush(stdout);
+  }
+  const size_t cbytes = size_t(1) << 30;
+  if (qbytes >= cbytes && hbytes >= cbytes) {
+    for (int r = 0; r < 3; ++r) {
+      CHECK_HIP(hipEventRecord(e0, 0));
+      hipLaunchKernelGGL(copy_kernel, dim3(8192), dim3(256), 0, 0, reinterpret_cast<const float4*>(q),
+                         reinterpret_cast<float4*>(qhat), (int64_t)(cbytes / 16));
+      CHECK_HIP(hipGetLastError());
+      CHECK_HIP(hipEventRecord(e1, 0));
+      CHECK_HIP(hipEventSynchronize(e1));
+      float ms = 0.0f;
+      CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
+      std::printf("copy 1 GiB %d: %.3f ms, %.3f TB/s (read + write)\n", r, ms,
+                  2.0 * cbytes / (ms * 1e-3) / 1e12);
+      std::fflush(stdout);
+    }
+  }
+  CHECK_HIP(hipDeviceSynchronize());
+  spod_plan_destroy(plan);
+  CHECK_HIP(hipFree(q));
+  CHECK_HIP(hipFree(qhat));
+  CHECK_HIP(hipFree(mean));
+  CHECK_HIP(hipFree(ws));
+  std::printf("done\n");
+  return 0;
+}
