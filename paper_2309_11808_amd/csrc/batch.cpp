@@ -24,6 +24,7 @@ size_t up256(size_t x) { return (x + 255) / 256 * 256; }
 struct ProblemSlots {
   Plan* plan = nullptr;
   int n_modes = 0;
+  int64_t ldq = 0;   // row stride of the problem's blocks in the workspace (grouped launches)
   size_t ws_qhat = 0, ws_gram = 0, ws_part = 0;                        // workspace offsets
   size_t o_mean = 0, o_lam = 0, o_psi = 0, o_info = 0, o_phi = 0, o_nvalid = 0;  // output offsets
 };
@@ -74,8 +75,11 @@ void layout(Batch& b) {
   for (auto& s : b.pb) {
     const Plan& p = *s.plan;
     const size_t K = p.nfreq, L = p.nblocks, M = p.M;
+    // complex64 rows get an even stride, so they are 16-byte aligned for the
+    // grouped kernels' vector loads and stores (the pad column is never read)
+    s.ldq = c128(b) ? p.M : (p.M + 1) / 2 * 2;
     s.ws_qhat = ws;
-    ws += up256(csize(b) * K * L * M);
+    ws += up256(csize(b) * K * L * (size_t)s.ldq);
     s.ws_gram = ws;
     ws += up256(16 * K * L * L);
     s.ws_part = ws;
@@ -141,6 +145,7 @@ spod_status build_tables(Batch& b, const void* const* q, spod_dtype dtype, char*
     it.tw = c128(b) ? (const void*)p.d_tw64 : (const void*)p.d_tw32;
     it.qhat = ws + s.ws_qhat;
     it.M = p.M;
+    it.ldq = s.ldq;
     it.nt = p.nt;
     it.step = (int)p.step;
     it.L = (int)p.nblocks;
@@ -181,11 +186,12 @@ spod_status build_tables(Batch& b, const void* const* q, spod_dtype dtype, char*
                                                           (size_t)p.gram_split * D * D)
                      : nullptr;
     it.M = p.M;
+    it.ldq = s.ldq;
     it.L = (int)p.nblocks;
     it.S = p.gram_split;
     it.K = (int)p.nfreq;
     const bool aligned = ((uintptr_t)it.qhat % 16 == 0) && ((uintptr_t)it.sqrtw % 16 == 0);
-    it.vec = aligned && (c128(b) || p.M % 2 == 0);
+    it.vec = aligned && (c128(b) || s.ldq % 2 == 0);
     gram[p.gram_dim / 16].push_back(it);
   }
   b.gram_groups.clear();
@@ -219,6 +225,7 @@ spod_status build_tables(Batch& b, const void* const* q, spod_dtype dtype, char*
       it.gram = ws + s.ws_part + 16 * (size_t)K * (size_t)p.gram_split * D * D;
       it.sqrtw = p.d_sqrtw32;
       it.M = p.M;
+      it.ldq = s.ldq;
       it.L = L;
       it.start = (int)s_sc;
       s_sc += K;
@@ -250,9 +257,11 @@ spod_status build_tables(Batch& b, const void* const* q, spod_dtype dtype, char*
     m.phi = out + s.o_phi;
     m.n_valid = reinterpret_cast<int32_t*>(out + s.o_nvalid);
     m.M = p.M;
+    m.ldq = s.ldq;
     m.L = L;
     m.n_modes = s.n_modes;
-    // the same choice as the single-problem launch (so results are identical)
+    // the same choice as the single-problem launch: phi rows (stride M) must
+    // take whole pairs
     m.pair = !c128(b) && p.M % 2 == 0 && (uintptr_t)m.qhat % 16 == 0 && (uintptr_t)m.phi % 16 == 0;
     m.tiles = (int)(((m.pair ? p.M / 2 : p.M) + 255) / 256);
     m.eps = c128(b) ? 1e-12 : 1e-6;

@@ -84,9 +84,9 @@ __device__ __forceinline__ double group_sum(double x) {
 template <int NF, typename TC, typename TIN, int NPAIR, int SHIFT, bool FUSED>
 __device__ __forceinline__ void blocks_fft_body(
     const TIN* __restrict__ q, double* __restrict__ mean, const double* __restrict__ window,
-    const cpx_t<TC>* __restrict__ tw, cpx_t<TC>* __restrict__ qhat, int64_t M, int64_t nt,
-    int step, int L, int bpw, TC kappa, const MeanBins& mb, const int* __restrict__ sel, int nsel,
-    int64_t tile, int chunk) {
+    const cpx_t<TC>* __restrict__ tw, cpx_t<TC>* __restrict__ qhat, int64_t M, int64_t ldq,
+    int64_t nt, int step, int L, int bpw, TC kappa, const MeanBins& mb,
+    const int* __restrict__ sel, int nsel, int64_t tile, int chunk) {
   using C = cpx_t<TC>;
   constexpr int P = NF / 8;              // lanes per transform
   constexpr int T = 2 * NPAIR;           // degrees of freedom per tile
@@ -112,8 +112,9 @@ __device__ __forceinline__ void blocks_fft_body(
   const TIN* ra = q + (va ? ma : 0) * nt;
   const TIN* rb = q + (vb ? mb_ : 0) * nt;
   C* buf = lds + f * LDP;
-  // two adjacent complex values per 16-byte aligned store (complex64 needs an even M)
-  const bool pair_ok = ((uintptr_t)qhat % 16 == 0) && (sizeof(TC) == 8 || (M & 1) == 0);
+  // two adjacent complex values per 16-byte aligned store (complex64 needs an
+  // even row stride ldq)
+  const bool pair_ok = ((uintptr_t)qhat % 16 == 0) && (sizeof(TC) == 8 || (ldq & 1) == 0);
   if (sel)
     for (int i = tid; i < nsel; i += NTH) ksel[i] = sel[i];
 
@@ -212,7 +213,7 @@ __device__ __forceinline__ void blocks_fft_body(
     // One thread per (row, pair): X_a = (A + conj B) / 2 and
     // X_b = (A - conj B) / (2i) come from the same two LDS reads, and the two
     // adjacent degrees of freedom are written with one 16-byte streaming store.
-    C* out = qhat + (int64_t)l * M;
+    C* out = qhat + (int64_t)l * ldq;
     const TC sc = (TC)0.5 * kappa;
     for (int idx = tid; idx < nsel * NPAIR; idx += NTH) {
       const int f2 = idx % NPAIR;
@@ -225,7 +226,7 @@ __device__ __forceinline__ void blocks_fft_body(
       const TC dx = A.x - Bc.x, dy = A.y + Bc.y;
       const C Xb = C{dy * sc, -(dx * sc)};
       const int64_t m = m0 + 2 * f2;
-      C* o = out + (int64_t)s * L * M + m;
+      C* o = out + (int64_t)s * L * ldq + m;
       if (pair_ok && m + 1 < M) {
         store_pair(o, Xa, Xb);
       } else {
@@ -259,7 +260,7 @@ __device__ __forceinline__ void blocks_fft_body(
       const int s = idx / (T * L);
       const int64_t m = m0 + d;
       if (m >= M) continue;
-      C* o = qhat + ((int64_t)mb.k[s] * L + l) * M + m;
+      C* o = qhat + ((int64_t)mb.k[s] * L + l) * ldq + m;
       const C raw = *o;
       const double c = corr[d];
       *o = C{(TC)((double)raw.x - c * mb.wr[s]), (TC)((double)raw.y - c * mb.wi[s])};
@@ -272,7 +273,7 @@ __global__ __launch_bounds__(NPAIR*(NF / 8)) void blocks_fft_kernel(
     const TIN* __restrict__ q, double* __restrict__ mean, const double* __restrict__ window,
     const cpx_t<TC>* __restrict__ tw, cpx_t<TC>* __restrict__ qhat, int64_t M, int64_t nt,
     int step, int L, int bpw, TC kappa, MeanBins mb, const int* __restrict__ sel, int nsel) {
-  blocks_fft_body<NF, TC, TIN, NPAIR, SHIFT, FUSED>(q, mean, window, tw, qhat, M, nt, step, L, bpw,
+  blocks_fft_body<NF, TC, TIN, NPAIR, SHIFT, FUSED>(q, mean, window, tw, qhat, M, M, nt, step, L, bpw,
                                                     kappa, mb, sel, nsel, blockIdx.x, blockIdx.y);
 }
 
@@ -285,7 +286,7 @@ __global__ __launch_bounds__(NPAIR*(NF / 8)) void blocks_fft_batch_kernel(const 
   const FftItem& it = items[find_item(items, n, (int)blockIdx.x)];
   blocks_fft_body<NF, TC, TIN, NPAIR, SHIFT, true>(
       static_cast<const TIN*>(it.q), it.mean, it.window, static_cast<const cpx_t<TC>*>(it.tw),
-      static_cast<cpx_t<TC>*>(it.qhat), it.M, it.nt, it.step, it.L, it.L, (TC)it.kappa, it.mb,
+      static_cast<cpx_t<TC>*>(it.qhat), it.M, it.ldq, it.nt, it.step, it.L, it.L, (TC)it.kappa, it.mb,
       nullptr, NF / 2 + 1, (int64_t)blockIdx.x - it.start, 0);
 }
 

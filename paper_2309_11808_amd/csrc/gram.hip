@@ -128,53 +128,11 @@ struct Raw {
   typename Cfg::T w[Cfg::DPL];
 };
 
-// Full group: every lane's run [m, m + DPL) lies inside [0, M) and rows are
-// 16-byte aligned.  Branch-free 16-byte loads (rows >= L read row L-1; the
-// caller masks them when it forms the operands, never by writing registers a
-// load may still be filling), so the next group's loads stay in flight while
-// the current one is multiplied.
-template <int MODE, int NT, unsigned NEED>
-__device__ __forceinline__ void gram_load_full(Raw<MODE, NT>& r, const typename GramCfg<MODE>::C* __restrict__ qk,
-                                               const typename GramCfg<MODE>::T* __restrict__ sqrtw,
-                                               int64_t m, int64_t M, int L, int r16) {
-  using Cfg = GramCfg<MODE>;
-  using C = typename Cfg::C;
-  using T = typename Cfg::T;
-  constexpr int DPL = Cfg::DPL;
-  constexpr int NV = (int)(sizeof(C) * DPL / 16);
-#pragma unroll
-  for (int a = 0; a < NT; ++a) {
-    if (!((NEED >> a) & 1u)) continue;
-    const int row = 16 * a + r16;
-    const int rc = row < L ? row : L - 1;
-    const v4f* src = reinterpret_cast<const v4f*>(qk + (int64_t)rc * M + m);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const v4f f = __builtin_nontemporal_load(src + v);
-      if constexpr (sizeof(C) == 8) {
-        r.x[a][2 * v] = C{f[0], f[1]};
-        r.x[a][2 * v + 1] = C{f[2], f[3]};
-      } else {
-        double2 d;
-        __builtin_memcpy(&d, &f, 16);
-        r.x[a][v] = d;
-      }
-    }
-  }
-  constexpr int NW = (int)(sizeof(T) * DPL / 16);
-  const v4f* wsrc = reinterpret_cast<const v4f*>(sqrtw + m);
-#pragma unroll
-  for (int v = 0; v < NW; ++v) {
-    const v4f f = wsrc[v];
-    __builtin_memcpy(&r.w[v * (16 / (int)sizeof(T))], &f, 16);
-  }
-}
-
 // Any group (ragged end, unaligned rows): element-wise loads with bounds checks.
 template <int MODE, int NT, unsigned NEED>
 __device__ __forceinline__ void gram_load_any(Raw<MODE, NT>& r, const typename GramCfg<MODE>::C* __restrict__ qk,
                                               const typename GramCfg<MODE>::T* __restrict__ sqrtw,
-                                              int64_t m, int64_t M, int L, int r16) {
+                                              int64_t m, int64_t M, int64_t ldq, int L, int r16) {
   using Cfg = GramCfg<MODE>;
   using C = typename Cfg::C;
   using T = typename Cfg::T;
@@ -185,7 +143,7 @@ __device__ __forceinline__ void gram_load_any(Raw<MODE, NT>& r, const typename G
     const int row = 16 * a + r16;
 #pragma unroll
     for (int e = 0; e < DPL; ++e)
-      r.x[a][e] = (row < L && m + e < M) ? qk[(int64_t)row * M + m + e] : C{0, 0};
+      r.x[a][e] = (row < L && m + e < M) ? qk[(int64_t)row * ldq + m + e] : C{0, 0};
   }
 #pragma unroll
   for (int e = 0; e < DPL; ++e) r.w[e] = (m + e < M) ? sqrtw[m + e] : (T)0;
@@ -246,8 +204,8 @@ template <int MODE, int NT, int G, int WPG>
 __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __restrict__ qhat,
                                           const typename GramCfg<MODE>::T* __restrict__ sqrtw,
                                           float scale, double* __restrict__ part, int64_t M,
-                                          int L, int S, bool vec, double* red, char* lds, int s,
-                                          int k) {
+                                          int64_t ldq, int L, int S, bool vec, double* red, char* lds,
+                                          int s, int k) {
   using Cfg = GramCfg<MODE>;
   using T = typename Cfg::T;
   using C = typename Cfg::C;
@@ -272,7 +230,7 @@ __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __res
   const int lane = tid & 63;
   const int r16 = lane & 15;
   const int g4 = lane >> 4;
-  const C* qk = qhat + (int64_t)k * L * M;
+  const C* qk = qhat + (int64_t)k * L * ldq;
 
   // full chunks are split over the S slices; the ragged remainder (or all of
   // it, when 16-byte loads are not possible) goes to the last slice
@@ -425,7 +383,7 @@ __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __res
 
   const char* qb = reinterpret_cast<const char*>(qk);
   const char* wb = reinterpret_cast<const char*>(sqrtw);
-  const int64_t rowb = M * (int64_t)sizeof(C);
+  const int64_t rowb = ldq * (int64_t)sizeof(C);
   if (c0 < c1) stage_issue<NT>(lds, qb + c0 * 1024, rowb, wb + c0 * CD * (int64_t)sizeof(T), L, wave, lane);
 #pragma unroll 1
   for (int64_t c = c0; c < c1; ++c) {
@@ -485,7 +443,7 @@ __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __res
 #pragma unroll 1
     for (int64_t g = g0 + wsub; g < g1; g += WPG) {
       Raw<MODE, NT> r;
-      gram_load_any<MODE, NT, NEED>(r, qk, sqrtw, m_rem + g * GDOF + g4 * DPL, M, L, r16);
+      gram_load_any<MODE, NT, NEED>(r, qk, sqrtw, m_rem + g * GDOF + g4 * DPL, M, ldq, L, r16);
       compute(r);
     }
   }
@@ -565,8 +523,8 @@ template <int MODE, int NT>
 __device__ __forceinline__ void gram_unit(const typename GramCfg<MODE>::C* __restrict__ qhat,
                                           const typename GramCfg<MODE>::T* __restrict__ sqrtw,
                                           const float* __restrict__ fscale, double* __restrict__ part,
-                                          int64_t M, int L, int S, int K, bool vec, int64_t local,
-                                          char* lds) {
+                                          int64_t M, int64_t ldq, int L, int S, int K, bool vec,
+                                          int64_t local, char* lds) {
   constexpr int NP = NT * (NT + 1) / 2;
   constexpr int NG = (NP + PG - 1) / PG;
   static_assert(NG == 1 || NG == 2 || NG == 4, "pair groups must divide the 4 waves");
@@ -578,10 +536,10 @@ __device__ __forceinline__ void gram_unit(const typename GramCfg<MODE>::C* __res
   const float scale = (MODE == G_FP16X4) ? fscale[k] : 1.0f;
   const int g = (int)(threadIdx.x >> 6) / WPG;
   switch (g) {
-    case 0: gram_body<MODE, NT, 0, WPG>(qhat, sqrtw, scale, part, M, L, S, vec, red, lds, s, k); break;
-    case 1: if constexpr (NG > 1) gram_body<MODE, NT, 1, WPG>(qhat, sqrtw, scale, part, M, L, S, vec, red, lds, s, k); break;
-    case 2: if constexpr (NG > 2) gram_body<MODE, NT, 2, WPG>(qhat, sqrtw, scale, part, M, L, S, vec, red, lds, s, k); break;
-    case 3: if constexpr (NG > 3) gram_body<MODE, NT, 3, WPG>(qhat, sqrtw, scale, part, M, L, S, vec, red, lds, s, k); break;
+    case 0: gram_body<MODE, NT, 0, WPG>(qhat, sqrtw, scale, part, M, ldq, L, S, vec, red, lds, s, k); break;
+    case 1: if constexpr (NG > 1) gram_body<MODE, NT, 1, WPG>(qhat, sqrtw, scale, part, M, ldq, L, S, vec, red, lds, s, k); break;
+    case 2: if constexpr (NG > 2) gram_body<MODE, NT, 2, WPG>(qhat, sqrtw, scale, part, M, ldq, L, S, vec, red, lds, s, k); break;
+    case 3: if constexpr (NG > 3) gram_body<MODE, NT, 3, WPG>(qhat, sqrtw, scale, part, M, ldq, L, S, vec, red, lds, s, k); break;
     default: break;
   }
 }
@@ -594,7 +552,7 @@ __global__ __launch_bounds__(256, 2) void gram_kernel(const typename GramCfg<MOD
                                                       int S, int K, int vec) {
   using T = typename GramCfg<MODE>::T;
   extern __shared__ __attribute__((aligned(16))) char gram_lds[];   // 2 stages
-  gram_unit<MODE, NT>(qhat, static_cast<const T*>(sqrtw_v), fscale, part, M, L, S, K, vec != 0,
+  gram_unit<MODE, NT>(qhat, static_cast<const T*>(sqrtw_v), fscale, part, M, M, L, S, K, vec != 0,
                       blockIdx.x, gram_lds);
 }
 
@@ -609,7 +567,7 @@ __global__ __launch_bounds__(256, 2) void gram_batch_kernel(const GramItem* __re
   extern __shared__ __attribute__((aligned(16))) char gram_lds[];
   const GramItem& it = items[find_item(items, n, (int)blockIdx.x)];
   gram_unit<MODE, NT>(static_cast<const C*>(it.qhat), static_cast<const T*>(it.sqrtw), it.fscale,
-                      it.part, it.M, it.L, it.S, it.K, it.vec != 0,
+                      it.part, it.M, it.ldq, it.L, it.S, it.K, it.vec != 0,
                       (int64_t)blockIdx.x - it.start, gram_lds);
 }
 
@@ -651,12 +609,14 @@ __global__ __launch_bounds__(256) void gram_combine_batch_kernel(const CombineIt
 // so the largest scaled value lies in [2^14, 2^15) < 65504.
 __device__ __forceinline__ void gram_scale_body(const float2* __restrict__ qhat,
                                                 const float* __restrict__ sqrtw,
-                                                float* __restrict__ scale, int64_t M, int L, int k) {
-  const float2* base = qhat + (int64_t)k * L * M;
+                                                float* __restrict__ scale, int64_t M, int64_t ldq,
+                                                int L, int k) {
+  const float2* base = qhat + (int64_t)k * L * ldq;
   float mx = 0.0f;
   for (int64_t idx = threadIdx.x; idx < (int64_t)L * M; idx += 256) {
-    const float2 z = base[idx];
-    const float w = sqrtw[idx % M];
+    const int64_t l = idx / M, m = idx % M;
+    const float2 z = base[l * ldq + m];
+    const float w = sqrtw[m];
     mx = fmaxf(mx, fmaxf(fabsf(z.x * w), fabsf(z.y * w)));
   }
   __shared__ float red[256];
@@ -677,14 +637,14 @@ __device__ __forceinline__ void gram_scale_body(const float2* __restrict__ qhat,
 __global__ __launch_bounds__(256) void gram_scale_kernel(const float2* __restrict__ qhat,
                                                          const float* __restrict__ sqrtw,
                                                          float* __restrict__ scale, int64_t M, int L) {
-  gram_scale_body(qhat, sqrtw, scale, M, L, blockIdx.x);
+  gram_scale_body(qhat, sqrtw, scale, M, M, L, blockIdx.x);
 }
 
 __global__ __launch_bounds__(256) void gram_scale_batch_kernel(const CombineItem* __restrict__ items,
                                                                int n) {
   const CombineItem& it = items[find_item(items, n, (int)blockIdx.x)];
   gram_scale_body(static_cast<const float2*>(it.part), static_cast<const float*>(it.sqrtw),
-                  static_cast<float*>(it.gram), it.M, it.L, (int)blockIdx.x - it.start);
+                  static_cast<float*>(it.gram), it.M, it.ldq, it.L, (int)blockIdx.x - it.start);
 }
 
 // ---------------------------------------------------------------------------

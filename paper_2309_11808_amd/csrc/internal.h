@@ -110,19 +110,19 @@ struct FftItem {                 // blocks_fft, fused mean, all blocks per tile
   const double* window;
   const void* tw;
   void* qhat;
-  int64_t M, nt;
+  int64_t M, ldq, nt;            // ldq: row stride of qhat (>= M)
   int step, L;
   double kappa;
   MeanBins mb;
   int start;
 };
 
-struct GramItem {                // gram partials, work unit = (group, slice, k)
+struct GramItem {                // gram partials, work unit = (slice, k)
   const void* qhat;
   const void* sqrtw;
   const float* fscale;
   double* part;
-  int64_t M;
+  int64_t M, ldq;
   int L, S, K, vec;
   int start;
 };
@@ -131,7 +131,7 @@ struct CombineItem {             // gram_combine / gram_scale, work unit = k
   const void* part;              // combine: partials; scale: qhat
   void* gram;                    // combine: gram; scale: float scales
   const void* sqrtw;             // scale only
-  int64_t M;
+  int64_t M, ldq;                // scale only
   int L, D, S;
   int start;
 };
@@ -151,7 +151,7 @@ struct ModesItem {               // modes, work unit = (k, tile of 256 DOFs)
   const void* psi;
   void* phi;
   int32_t* n_valid;
-  int64_t M;
+  int64_t M, ldq;
   int L, n_modes, tiles;
   int pair;                      // two DOFs per thread (complex64, even M, aligned)
   double eps;

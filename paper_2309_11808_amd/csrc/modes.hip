@@ -23,8 +23,8 @@ __device__ __forceinline__ void modes_body(const cpx_t<TC>* __restrict__ qhat,
                                            const double* __restrict__ lam,
                                            const double2* __restrict__ psi,
                                            cpx_t<TC>* __restrict__ phi,
-                                           int32_t* __restrict__ n_valid, int64_t M, int L,
-                                           int n_modes, double eps, int64_t bx, int k) {
+                                           int32_t* __restrict__ n_valid, int64_t M, int64_t ldq,
+                                           int L, int n_modes, double eps, int64_t bx, int k) {
   using C = cpx_t<TC>;
   static_assert(!PAIR || sizeof(TC) == 4, "pairs are 16-byte complex64 vectors");
   extern __shared__ char modes_lds[];
@@ -49,7 +49,7 @@ __device__ __forceinline__ void modes_body(const cpx_t<TC>* __restrict__ qhat,
   constexpr int DPT = PAIR ? 2 : 1;            // degrees of freedom per thread
   const int64_t m = (bx * blockDim.x + tid) * DPT;
   if (m >= M) return;
-  const C* src = qhat + (int64_t)k * L * M + m;
+  const C* src = qhat + (int64_t)k * L * ldq + m;
   C* dst = phi + (int64_t)k * n_modes * M + m;
   for (int j0 = 0; j0 < n_modes; j0 += MODES_GROUP) {
     C acc[DPT][MODES_GROUP];
@@ -60,11 +60,11 @@ __device__ __forceinline__ void modes_body(const cpx_t<TC>* __restrict__ qhat,
     for (int l = 0; l < L; ++l) {
       C x[DPT];
       if constexpr (PAIR) {
-        const modes_v4 v = __builtin_nontemporal_load(reinterpret_cast<const modes_v4*>(src + (int64_t)l * M));
+        const modes_v4 v = __builtin_nontemporal_load(reinterpret_cast<const modes_v4*>(src + (int64_t)l * ldq));
         x[0] = C{v[0], v[1]};
         x[1] = C{v[2], v[3]};
       } else {
-        x[0] = src[(int64_t)l * M];
+        x[0] = src[(int64_t)l * ldq];
       }
       const C* cl = coef + l * n_modes + j0;
 #pragma unroll
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(256) void modes_kernel(const cpx_t<TC>* __restrict_
                                                     cpx_t<TC>* __restrict__ phi,
                                                     int32_t* __restrict__ n_valid, int64_t M, int L,
                                                     int n_modes, double eps) {
-  modes_body<TC, PAIR>(qhat, lam, psi, phi, n_valid, M, L, n_modes, eps, blockIdx.x, blockIdx.y);
+  modes_body<TC, PAIR>(qhat, lam, psi, phi, n_valid, M, M, L, n_modes, eps, blockIdx.x, blockIdx.y);
 }
 
 template <typename TC>
@@ -111,14 +111,14 @@ __global__ __launch_bounds__(256) void modes_batch_kernel(const ModesItem* __res
     if (it.pair) {
       modes_body<TC, true>(static_cast<const cpx_t<TC>*>(it.qhat), it.lam,
                            static_cast<const double2*>(it.psi), static_cast<cpx_t<TC>*>(it.phi),
-                           it.n_valid, it.M, it.L, it.n_modes, it.eps, local % it.tiles,
+                           it.n_valid, it.M, it.ldq, it.L, it.n_modes, it.eps, local % it.tiles,
                            local / it.tiles);
       return;
     }
   }
   modes_body<TC, false>(static_cast<const cpx_t<TC>*>(it.qhat), it.lam,
                         static_cast<const double2*>(it.psi), static_cast<cpx_t<TC>*>(it.phi),
-                        it.n_valid, it.M, it.L, it.n_modes, it.eps, local % it.tiles,
+                        it.n_valid, it.M, it.ldq, it.L, it.n_modes, it.eps, local % it.tiles,
                         local / it.tiles);
 }
 
