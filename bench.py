@@ -383,6 +383,20 @@ def main(argv=None):
                           "stages_ms": {k: round(v, 4) for k, v in fp64["stages_ms"].items()}}
         result["eig_rel_err_vs_fp64"] = err
         result["mixed_over_fp64"] = round(fp64["ms_per_step"] / mixed["ms_per_step"], 3)
+    if fp64 is not None:
+        # every precision form's time and eigenvalue error against the FP64 path
+        forms = {a.precision: {"ms_per_step": result["ms_per_step"],
+                               "eig_rel_err_vs_fp64": result["eig_rel_err_vs_fp64"]}}
+        for prec in ("fp32", "bf16x4", "fp16x4"):
+            if prec in forms:
+                continue
+            r = run_path(p, prec, max(2, a.steps // 3), 1)
+            lm = r["lam"].numpy()[:, :5]
+            forms[prec] = {"ms_per_step": round(r["ms_per_step"], 4),
+                           "eig_rel_err_vs_fp64": float(np.max(np.abs(lm - lf) / np.maximum(np.abs(lf), 1e-300)))}
+        forms["fp64"] = {"ms_per_step": result["fp64"]["ms_per_step"], "eig_rel_err_vs_fp64": 0.0}
+        result["precision_forms"] = forms
+        log(f"precision forms {forms}")
     if not a.no_cpu:
         log("timing the FP64 CPU oracle on a sample")
         result["cpu_baseline"] = cpu_baseline(p)

@@ -85,7 +85,7 @@ void layout(Batch& b) {
     s.ws_part = ws;
     const size_t D = (size_t)p.gram_dim;
     const size_t smax = (size_t)gram_split_for(p, tmax);
-    ws += up256(16 * K * smax * D * D + sizeof(float) * K + 256);
+    ws += up256(16 * K * smax * D * D + sizeof(float) * K * (1 + (size_t)gram_scale_parts()) + 256);
     s.o_mean = out;
     out += up256(8 * M);
     s.o_lam = out;
@@ -223,12 +223,13 @@ spod_status build_tables(Batch& b, const void* const* q, spod_dtype dtype, char*
       CombineItem it{};
       it.part = ws + s.ws_qhat;
       it.gram = ws + s.ws_part + 16 * (size_t)K * (size_t)p.gram_split * D * D;
+      it.aux = static_cast<float*>(it.gram) + K;
       it.sqrtw = p.d_sqrtw32;
       it.M = p.M;
       it.ldq = s.ldq;
       it.L = L;
       it.start = (int)s_sc;
-      s_sc += K;
+      s_sc += (int64_t)K * gram_scale_parts();
       sc.push_back(it);
     }
     CombineItem c{};

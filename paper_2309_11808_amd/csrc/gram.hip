@@ -606,18 +606,26 @@ __global__ __launch_bounds__(256) void gram_combine_batch_kernel(const CombineIt
 
 // Per-frequency power-of-two scale for the FP16 operands: 2^(15 - e) with e
 // the exponent of max_m,l |sqrt(W_m) qhat[k][l][m]| (real or imaginary part),
-// so the largest scaled value lies in [2^14, 2^15) < 65504.
-__device__ __forceinline__ void gram_scale_body(const float2* __restrict__ qhat,
-                                                const float* __restrict__ sqrtw,
-                                                float* __restrict__ scale, int64_t M, int64_t ldq,
-                                                int L, int k) {
+// so the largest scaled value lies in [2^14, 2^15) < 65504.  Two stages, in a
+// fixed order: workgroup (c, k) takes the maximum over every row of the c-th
+// of SCALE_PARTS ranges of degrees of freedom, then one wave per frequency
+// reduces the partial maxima.
+constexpr int SCALE_PARTS = 64;
+
+__device__ __forceinline__ void gram_scale_part_body(const float2* __restrict__ qhat,
+                                                     const float* __restrict__ sqrtw,
+                                                     float* __restrict__ pmax, int64_t M,
+                                                     int64_t ldq, int L, int k, int c) {
   const float2* base = qhat + (int64_t)k * L * ldq;
+  const int64_t m0 = M * c / SCALE_PARTS, m1 = M * (c + 1) / SCALE_PARTS;
   float mx = 0.0f;
-  for (int64_t idx = threadIdx.x; idx < (int64_t)L * M; idx += 256) {
-    const int64_t l = idx / M, m = idx % M;
-    const float2 z = base[l * ldq + m];
-    const float w = sqrtw[m];
-    mx = fmaxf(mx, fmaxf(fabsf(z.x * w), fabsf(z.y * w)));
+  for (int l = 0; l < L; ++l) {
+    const float2* row = base + (int64_t)l * ldq;
+    for (int64_t m = m0 + threadIdx.x; m < m1; m += 256) {
+      const float2 z = row[m];
+      const float w = sqrtw[m];
+      mx = fmaxf(mx, fmaxf(fabsf(z.x * w), fabsf(z.y * w)));
+    }
   }
   __shared__ float red[256];
   red[threadIdx.x] = mx;
@@ -626,32 +634,58 @@ __device__ __forceinline__ void gram_scale_body(const float2* __restrict__ qhat,
     if ((int)threadIdx.x < o) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + o]);
     __syncthreads();
   }
+  if (threadIdx.x == 0) pmax[(int64_t)k * SCALE_PARTS + c] = red[0];
+}
+
+__device__ __forceinline__ void gram_scale_final_body(const float* __restrict__ pmax,
+                                                      float* __restrict__ scale, int k) {
+  static_assert(SCALE_PARTS == 64, "one partial per lane");
+  float m = pmax[(int64_t)k * SCALE_PARTS + (threadIdx.x & 63)];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
   if (threadIdx.x == 0) {
-    const float m = red[0];
     int e = 0;
     if (m > 0.0f) (void)frexpf(m, &e);
     scale[k] = ldexpf(1.0f, 15 - e);
   }
 }
 
-__global__ __launch_bounds__(256) void gram_scale_kernel(const float2* __restrict__ qhat,
-                                                         const float* __restrict__ sqrtw,
-                                                         float* __restrict__ scale, int64_t M, int L) {
-  gram_scale_body(qhat, sqrtw, scale, M, M, L, blockIdx.x);
+__global__ __launch_bounds__(256) void gram_scale_part_kernel(const float2* __restrict__ qhat,
+                                                              const float* __restrict__ sqrtw,
+                                                              float* __restrict__ pmax, int64_t M,
+                                                              int L) {
+  gram_scale_part_body(qhat, sqrtw, pmax, M, M, L, blockIdx.y, blockIdx.x);
 }
 
-__global__ __launch_bounds__(256) void gram_scale_batch_kernel(const CombineItem* __restrict__ items,
-                                                               int n) {
+__global__ __launch_bounds__(64) void gram_scale_final_kernel(const float* __restrict__ pmax,
+                                                              float* __restrict__ scale) {
+  gram_scale_final_body(pmax, scale, blockIdx.x);
+}
+
+// grouped: stage 1 units = (k, c) per item (c fastest), stage 2 units = k
+__global__ __launch_bounds__(256) void gram_scale_part_batch_kernel(const CombineItem* __restrict__ items,
+                                                                    int n) {
   const CombineItem& it = items[find_item(items, n, (int)blockIdx.x)];
-  gram_scale_body(static_cast<const float2*>(it.part), static_cast<const float*>(it.sqrtw),
-                  static_cast<float*>(it.gram), it.M, it.ldq, it.L, (int)blockIdx.x - it.start);
+  const int local = (int)blockIdx.x - it.start;
+  gram_scale_part_body(static_cast<const float2*>(it.part), static_cast<const float*>(it.sqrtw),
+                       static_cast<float*>(it.aux), it.M, it.ldq, it.L, local / SCALE_PARTS,
+                       local % SCALE_PARTS);
+}
+
+__global__ __launch_bounds__(64) void gram_scale_final_batch_kernel(const CombineItem* __restrict__ items,
+                                                                    int n) {
+  const CombineItem& it = items[find_item(items, n, (int)blockIdx.x)];
+  const int local = (int)blockIdx.x - it.start;
+  if (local % SCALE_PARTS) return;     // one workgroup per frequency reduces
+  gram_scale_final_body(static_cast<const float*>(it.aux), static_cast<float*>(it.gram),
+                        local / SCALE_PARTS);
 }
 
 // ---------------------------------------------------------------------------
 size_t csd_workspace(const Plan& p) {
   const size_t D = (size_t)p.gram_dim;
   size_t b = sizeof(double2) * (size_t)p.nfreq * (size_t)p.gram_split * D * D;
-  if (p.prec == SPOD_PREC_FP16X4) b += sizeof(float) * (size_t)p.nfreq + 256;
+  if (p.prec == SPOD_PREC_FP16X4) b += sizeof(float) * (size_t)p.nfreq * (1 + SCALE_PARTS) + 256;
   return b;
 }
 
@@ -699,12 +733,15 @@ spod_status launch_csd(const Plan& p, const void* qhat, void* gram, void* ws, hi
     case SPOD_PREC_FP64: s = launch_gram_mode<G_F64>(p, qhat, p.d_sqrtw, nullptr, part, st); break;
     case SPOD_PREC_FP32: s = launch_gram_mode<G_F32>(p, qhat, p.d_sqrtw32, nullptr, part, st); break;
     case SPOD_PREC_BF16X4: s = launch_gram_mode<G_BF16X4>(p, qhat, p.d_sqrtw32, nullptr, part, st); break;
-    case SPOD_PREC_FP16X4:
-      hipLaunchKernelGGL(gram_scale_kernel, dim3((unsigned)p.nfreq), dim3(256), 0, st,
-                         static_cast<const float2*>(qhat), p.d_sqrtw32, fs, (int64_t)p.M,
+    case SPOD_PREC_FP16X4: {
+      float* pmax = fs + p.nfreq;            // [K][SCALE_PARTS] partial maxima
+      hipLaunchKernelGGL(gram_scale_part_kernel, dim3(SCALE_PARTS, (unsigned)p.nfreq), dim3(256), 0,
+                         st, static_cast<const float2*>(qhat), p.d_sqrtw32, pmax, (int64_t)p.M,
                          (int)p.nblocks);
+      hipLaunchKernelGGL(gram_scale_final_kernel, dim3((unsigned)p.nfreq), dim3(64), 0, st, pmax, fs);
       s = launch_gram_mode<G_FP16X4>(p, qhat, p.d_sqrtw32, fs, part, st);
       break;
+    }
     default: return fail(SPOD_ERR_INVALID_ARG, "precision");
   }
   if (s != SPOD_OK) return s;
@@ -760,8 +797,13 @@ spod_status launch_gram_group(spod_precision prec, int nt16, const GramItem* d_i
   return fail(SPOD_ERR_INVALID_ARG, "precision");
 }
 
+int gram_scale_parts() { return SCALE_PARTS; }
+
 spod_status launch_gram_scale_group(const CombineItem* d_items, int n, int wgs, hipStream_t st) {
-  hipLaunchKernelGGL(gram_scale_batch_kernel, dim3((unsigned)wgs), dim3(256), 0, st, d_items, n);
+  // wgs = sum over items of K * SCALE_PARTS; stage 2 reuses the same table
+  // and grid, and only the first workgroup of each frequency works
+  hipLaunchKernelGGL(gram_scale_part_batch_kernel, dim3((unsigned)wgs), dim3(256), 0, st, d_items, n);
+  hipLaunchKernelGGL(gram_scale_final_batch_kernel, dim3((unsigned)wgs), dim3(64), 0, st, d_items, n);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SPOD_OK : hip_fail(e, "gram_scale_batch_kernel");
 }

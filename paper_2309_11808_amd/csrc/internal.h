@@ -127,10 +127,11 @@ struct GramItem {                // gram partials, work unit = (slice, k)
   int start;
 };
 
-struct CombineItem {             // gram_combine / gram_scale, work unit = k
+struct CombineItem {             // gram_combine (unit k) / gram_scale (unit (k, part))
   const void* part;              // combine: partials; scale: qhat
-  void* gram;                    // combine: gram; scale: float scales
+  void* gram;                    // combine: gram; scale: float scales [K]
   const void* sqrtw;             // scale only
+  void* aux;                     // scale only: partial maxima [K][gram_scale_parts()]
   int64_t M, ldq;                // scale only
   int L, D, S;
   int start;
@@ -180,6 +181,7 @@ spod_status launch_gram_group(spod_precision prec, int nt16, const GramItem* d_i
 int gram_groups(int nt16);                           // pair groups per (slice, k)
 int64_t gram_group_wgs(int nt16, int64_t S, int64_t K);   // workgroups of one problem
 spod_status launch_gram_scale_group(const CombineItem* d_items, int n, int wgs, hipStream_t st);
+int gram_scale_parts();                              // FP16 scale: partial maxima per frequency
 spod_status launch_gram_combine_group(const CombineItem* d_items, int n, int wgs, hipStream_t st);
 spod_status launch_eig_group(const EigItem* d_items, int n, int wgs, int max_sweeps,
                              size_t lds_bytes, hipStream_t st);

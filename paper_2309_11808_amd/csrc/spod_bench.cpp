@@ -1,13 +1,16 @@
 // spod_bench: a plain C-ABI caller of libspod, with nothing else in the
 // process (no Python, no framework), for hardware-counter runs.
 //
-//   spod_bench [nspace nvar nt nfft noverlap reps precision]
-//   defaults:   524288  2   8192 512  256      3    2 (bf16x4)
+//   spod_bench [nspace nvar nt nfft noverlap reps precision path]
+//   defaults:   524288  2   8192 512  256      3    2 (bf16x4)  0
 //
-// Fills q [M][nt] float32 on the device with hashed values in [-1, 1), runs
-// spod_blocks_fft `reps` times, then copies 1 GiB device to device three
-// times with its own copy kernel (a dispatch of known traffic: 1 GiB read and
-// 1 GiB written), and prints the event timings.
+// Fills q [M][nt] float32 on the device with hashed values in [-1, 1).
+// path 0: runs spod_blocks_fft `reps` times, then copies 1 GiB device to
+//         device three times with its own copy kernel (a dispatch of known
+//         traffic: 1 GiB read and 1 GiB written).
+// path 1: runs the whole forward path (blocks_fft, csd, eig, modes with 5
+//         modes) `reps` times with the bf16x4 plan, then with the FP64 plan.
+// Prints the event timings.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -53,11 +56,72 @@ __global__ void copy_kernel(const float4* __restrict__ src, float4* __restrict__
     dst[i] = src[i];
 }
 
+static int run_path(int64_t nspace, int64_t nvar, int64_t nt, int64_t nfft, int64_t nov,
+                    int64_t reps, spod_precision prec, const float* q) {
+  const int64_t M = nspace * nvar, n_modes = 5;
+  spod_plan plan = nullptr;
+  CHECK_SPOD(spod_plan_create(nspace, nvar, nt, nfft, nov, nullptr, nullptr, &plan));
+  CHECK_SPOD(spod_plan_set_precision(plan, prec));
+  int64_t L = 0, K = 0;
+  size_t wsb = 0;
+  CHECK_SPOD(spod_plan_query(plan, &L, &K, &wsb));
+  const size_t csz = prec == SPOD_PREC_FP64 ? 16 : 8;
+  void *qhat = nullptr, *gram = nullptr, *psi = nullptr, *phi = nullptr, *ws = nullptr;
+  double *mean = nullptr, *lam = nullptr;
+  int32_t *info = nullptr, *nval = nullptr;
+  CHECK_HIP(hipMalloc(&qhat, csz * (size_t)(K * L * M)));
+  CHECK_HIP(hipMalloc(&phi, csz * (size_t)(K * n_modes * M)));
+  CHECK_HIP(hipMalloc(&gram, 16 * (size_t)(K * L * L)));
+  CHECK_HIP(hipMalloc(&psi, 16 * (size_t)(K * L * L)));
+  CHECK_HIP(hipMalloc(&lam, 8 * (size_t)(K * L)));
+  CHECK_HIP(hipMalloc(&mean, 8 * (size_t)M));
+  CHECK_HIP(hipMalloc(&info, 4 * (size_t)K));
+  CHECK_HIP(hipMalloc(&nval, 4 * (size_t)K));
+  CHECK_HIP(hipMalloc(&ws, wsb > 0 ? wsb : 256));
+  hipEvent_t e[5];
+  for (auto& x : e) CHECK_HIP(hipEventCreate(&x));
+  for (int64_t r = 0; r < reps; ++r) {
+    CHECK_HIP(hipEventRecord(e[0], 0));
+    CHECK_SPOD(spod_blocks_fft(plan, q, SPOD_F32, qhat, mean, ws, wsb, nullptr));
+    CHECK_HIP(hipEventRecord(e[1], 0));
+    CHECK_SPOD(spod_csd(plan, qhat, gram, ws, wsb, nullptr));
+    CHECK_HIP(hipEventRecord(e[2], 0));
+    CHECK_SPOD(spod_eig(plan, gram, lam, psi, info, ws, wsb, nullptr));
+    CHECK_HIP(hipEventRecord(e[3], 0));
+    CHECK_SPOD(spod_modes(plan, qhat, lam, psi, n_modes, phi, nval, ws, wsb, nullptr));
+    CHECK_HIP(hipEventRecord(e[4], 0));
+    CHECK_HIP(hipEventSynchronize(e[4]));
+    float ms[4];
+    for (int i = 0; i < 4; ++i) CHECK_HIP(hipEventElapsedTime(&ms[i], e[i], e[i + 1]));
+    std::printf("%s path %lld: blocks_fft %.3f ms, csd %.3f ms, eig %.3f ms, modes %.3f ms\n",
+                prec == SPOD_PREC_FP64 ? "fp64" : "mixed", (long long)r, ms[0], ms[1], ms[2], ms[3]);
+    std::fflush(stdout);
+  }
+  for (auto& x : e) CHECK_HIP(hipEventDestroy(x));
+  spod_plan_destroy(plan);
+  void* bufs[] = {qhat, gram, psi, phi, ws, mean, lam, info, nval};
+  for (void* b : bufs) CHECK_HIP(hipFree(b));
+  return 0;
+}
+
 int main(int argc, char** argv) {
-  int64_t nspace = 524288, nvar = 2, nt = 8192, nfft = 512, nov = 256, reps = 3, prec = 2;
-  int64_t* args[] = {&nspace, &nvar, &nt, &nfft, &nov, &reps, &prec};
-  for (int i = 1; i < argc && i <= 7; ++i) *args[i - 1] = std::atoll(argv[i]);
+  int64_t nspace = 524288, nvar = 2, nt = 8192, nfft = 512, nov = 256, reps = 3, prec = 2, path = 0;
+  int64_t* args[] = {&nspace, &nvar, &nt, &nfft, &nov, &reps, &prec, &path};
+  for (int i = 1; i < argc && i <= 8; ++i) *args[i - 1] = std::atoll(argv[i]);
   const int64_t M = nspace * nvar;
+  if (path == 1) {
+    float* q = nullptr;
+    const size_t qbytes = sizeof(float) * (size_t)M * (size_t)nt;
+    CHECK_HIP(hipMalloc(&q, qbytes));
+    hipLaunchKernelGGL(fill_kernel, dim3(8192), dim3(256), 0, 0, q, (int64_t)(qbytes / 4), 12345u);
+    CHECK_HIP(hipGetLastError());
+    CHECK_HIP(hipDeviceSynchronize());
+    if (run_path(nspace, nvar, nt, nfft, nov, reps, SPOD_PREC_BF16X4, q)) return 1;
+    if (run_path(nspace, nvar, nt, nfft, nov, reps, SPOD_PREC_FP64, q)) return 1;
+    CHECK_HIP(hipFree(q));
+    std::printf("done\n");
+    return 0;
+  }
 
   spod_plan plan = nullptr;
   CHECK_SPOD(spod_plan_create(nspace, nvar, nt, nfft, nov, nullptr, nullptr, &plan));
