@@ -2,6 +2,7 @@
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 3] [--precision bf16x4]
                     [--workload era|jet] [--no-fp64] [--no-cpu] [--no-diff] [--no-batch]
+                    [--no-ooc]
 
 A step is one pass of the whole path over the resident input: temporal mean +
 windowed block FFT (spod_blocks_fft), weighted Gram (spod_csd), batched
@@ -18,8 +19,12 @@ frequencies), cos(latitude) weights; red noise plus 6 planted modes, generated
 on the device from a seed.  Prints one JSON line on stdout; progress goes to
 stderr.
 
-Two more measurements ride on the same line (skipped with --no-diff and
---no-batch):
+Three more measurements ride on the same line (skipped with --no-ooc,
+--no-diff and --no-batch):
+  * out_of_core: the same field with q in pinned host memory, streamed to the
+    device in chunks of 32768 rows by spod_ooc_forward, with no chunk resident
+    (Q crosses the host link twice) and with every chunk resident (once);
+    reported against a plain pinned host -> device copy;
   * differentiation: the jet-like field (256 x 128 x 3, N_t = 4096 float32,
     N_f = 256, 31 blocks, 129 bins); forward pass and spod_backward for a loss
     on 8 separated bins (3 eigenvalues and the leading mode), Fourier blocks
@@ -301,6 +306,70 @@ def bench_batching(steps, warmup, precision="bf16x4", n_modes=5):
     return res
 
 
+PCIE_PEAK_GBS = 64.0   # PCIe 5.0 x16, one direction (the host link of one MI355X)
+
+
+def _link_copy_gbs(src_host, dst_dev, reps=3):
+    """Plain pinned host -> device copy rate (GB/s): a DMA of known size."""
+    import torch
+    best = 0.0
+    n = dst_dev.numel() * dst_dev.element_size()
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        dst_dev.copy_(src_host, non_blocking=True)
+        torch.cuda.synchronize()
+        best = max(best, n / (time.perf_counter() - t) / 1e9)
+    return best
+
+
+def bench_out_of_core(p, precision, lam_in_memory, chunk_rows=32768, reps=2):
+    """The main workload with q in pinned host memory, streamed by spod_ooc_*:
+    nothing resident (both passes read Q over the link) and every chunk
+    resident (Q crosses the link once)."""
+    import numpy as np
+    import torch
+    from paper_2309_11808_amd import OutOfCore, Plan
+    q_host = torch.empty(tuple(p.q.shape), dtype=p.q.dtype, pin_memory=True)
+    q_host.copy_(p.q)
+    torch.cuda.synchronize()
+    in_bytes = q_host.numel() * q_host.element_size()
+    piece = 1 << 28
+    dst = torch.empty(piece, dtype=torch.float32, device="cuda")
+    copy_gbs = _link_copy_gbs(q_host.view(-1)[:piece], dst)
+    del dst
+    plan = Plan(p.nspace, p.nvar, p.nt, p.nfft, p.noverlap, weights=p.weights, precision=precision)
+    phi = torch.empty((plan.nfreq, 5, plan.M), dtype=plan.cdtype, pin_memory=True)
+    res = {"workload": "the main workload with q in pinned host memory", "chunk_rows": chunk_rows,
+           "input_bytes": in_bytes, "precision": precision,
+           "h2d_copy_GBps": round(copy_gbs, 2), "link_peak_GBps": PCIE_PEAK_GBS}
+    for name, resident in (("streamed", 0), ("resident", 1 << 30)):
+        o = OutOfCore(plan, dtype=p.q.dtype, chunk_rows=chunk_rows, n_modes=5, resident=resident)
+        out = o.forward(q=q_host, phi=phi)           # warm-up (pinned staging, first launches)
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            out = o.forward(q=q_host, phi=phi)
+            ts.append(time.perf_counter() - t)
+        dt = min(ts)
+        link_in = in_bytes * (2 * o.n_chunks - o.resident) / o.n_chunks
+        lm, lr = out["lam"].cpu().numpy()[:, :5], lam_in_memory[:, :5]
+        res[name] = {"chunks": o.n_chunks, "resident": o.resident, "ms": round(dt * 1e3, 2),
+                     "input_GBps": round(in_bytes / dt / 1e9, 2),
+                     "link_in_bytes": int(link_in), "link_in_GBps": round(link_in / dt / 1e9, 2),
+                     "frac_of_h2d_copy": round(link_in / dt / 1e9 / copy_gbs, 3),
+                     "device_bytes": o.device_bytes,
+                     "eig_rel_diff_vs_in_memory": float(np.max(np.abs(lm - lr) /
+                                                               np.maximum(np.abs(lr), 1e-300)))}
+        o.close()
+        del out
+        torch.cuda.empty_cache()
+    plan.close()
+    del q_host, phi
+    return res
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -312,6 +381,7 @@ def main(argv=None):
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-diff", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-ooc", action="store_true")
     ap.add_argument("--no-main", action="store_true",
                     help="skip the main workload (profiling the other sections alone)")
     a = ap.parse_args(argv)
@@ -393,6 +463,7 @@ def main(argv=None):
             r = run_path(p, prec, max(2, a.steps // 3), 1)
             lm = r["lam"].numpy()[:, :5]
             forms[prec] = {"ms_per_step": round(r["ms_per_step"], 4),
+                           "stages_ms": {k: round(v, 4) for k, v in r["stages_ms"].items()},
                            "eig_rel_err_vs_fp64": float(np.max(np.abs(lm - lf) / np.maximum(np.abs(lf), 1e-300)))}
         forms["fp64"] = {"ms_per_step": result["fp64"]["ms_per_step"], "eig_rel_err_vs_fp64": 0.0}
         result["precision_forms"] = forms
@@ -401,6 +472,10 @@ def main(argv=None):
         log("timing the FP64 CPU oracle on a sample")
         result["cpu_baseline"] = cpu_baseline(p)
         log(f"cpu baseline {result['cpu_baseline']}")
+    if not a.no_ooc:
+        log("out-of-core workload")
+        result["out_of_core"] = bench_out_of_core(p, a.precision, mixed["lam"].numpy())
+        log(f"out of core {result['out_of_core']}")
     del p
     torch.cuda.empty_cache()
     if not a.no_diff:

@@ -69,7 +69,8 @@ typedef enum {
   SPOD_ERR_ALLOC = -3,       /* device or host allocation failed                   */
   SPOD_ERR_HIP = -4,         /* HIP runtime error (no device, launch failure, ...) */
   SPOD_ERR_NUMERIC = -5,     /* non-finite values where finite ones are required   */
-  SPOD_ERR_WORKSPACE = -6    /* workspace missing or smaller than required         */
+  SPOD_ERR_WORKSPACE = -6,   /* workspace missing or smaller than required         */
+  SPOD_ERR_IO = -7           /* a reader callback reported a failure               */
 } spod_status;
 
 typedef enum { SPOD_F32 = 0, SPOD_F64 = 1 } spod_dtype; /* stored type of q and g_q */
@@ -269,6 +270,77 @@ spod_status spod_batch_autotune(spod_batch batch, const void* const* q, spod_dty
 
 /* Free the batch and its plans (NULL-safe; synchronises the device). */
 void spod_batch_destroy(spod_batch batch);
+
+/* ---------------------------------------------------------------------------
+ * Out-of-core SPOD: the snapshot matrix stays in host memory (or behind a
+ * reader) and reaches the device in chunks of rows.  This is the spatial
+ * split of Sec. 3.1 (every process owns a slice of the degrees of freedom and
+ * its share of Qhat_k^* W Qhat_k adds up to the Gram of
+ * eq. (spod-discrete-snapshots)) run through one device, with the chunked
+ * reading of the data that Sec. 3.1 describes.
+ *
+ *   pass 1: for every chunk: copy it in, mean + blocks + DFT, add its
+ *           weighted Gram into the Gram of every frequency;
+ *   then:   the eigensolve of every frequency (spod_eig);
+ *   pass 2: for every chunk: blocks + DFT again, the modes of its rows
+ *           (eq. (discrete_modes) is row by row), copy them out.
+ *
+ * Copies run on library-owned streams (default priority) and overlap the
+ * kernels of the previous chunk: two device slots take the streamed chunks in
+ * turn.  The last `resident` chunks of pass 1 get slots of their own and stay
+ * on the device, so pass 2 reads only the other chunks again; with
+ * resident >= the number of chunks the host data crosses the link once.
+ * Results equal the in-memory path's up to the order of the Gram sums
+ * (bit-identical with one chunk).
+ * ------------------------------------------------------------------------ */
+typedef struct spod_ooc_s* spod_ooc;
+
+/* Reader: fill dst (pinned host memory, [nrows][nt] of the object's dtype,
+ * row-major) with rows [row0, row0 + nrows) of Q.  Return 0 on success; any
+ * other value stops the forward pass with SPOD_ERR_IO. */
+typedef int (*spod_read_fn)(void* user, int64_t row0, int64_t nrows, void* dst);
+
+/* Create an out-of-core driver for `plan` (which must outlive it; its
+ * precision and options are used as they are).  dtype: stored type of Q.
+ * chunk_rows: rows per chunk, rounded up to a multiple of 256 (>= 1; values
+ * >= M give one chunk).  n_modes in [1, nblocks].  resident in [0, ...):
+ * chunks kept on the device between the passes.  Allocates every device
+ * buffer and the streams now (on the plan's device, which must be current);
+ * pinned host staging buffers are allocated on the first forward pass that
+ * needs them.  SPOD_ERR_UNSUPPORTED when nblocks > 64. */
+spod_status spod_ooc_create(spod_plan plan, spod_dtype dtype, int64_t chunk_rows,
+                            int64_t n_modes, int64_t resident, spod_ooc* out);
+
+/* Chunk rows after rounding, number of chunks, chunks kept resident, bytes of
+ * device memory held by the object and of pinned host memory it may allocate
+ * (all pointers nullable). */
+spod_status spod_ooc_query(spod_ooc ooc, int64_t* chunk_rows, int64_t* n_chunks,
+                           int64_t* n_resident, size_t* device_bytes, size_t* pinned_bytes);
+
+/* One SPOD of Q.  Exactly one source:
+ *   q     : [M][nt] of dtype, row-major.  Device memory or pinned host memory
+ *           is copied from directly; other host memory is copied through
+ *           pinned staging buffers by host threads;
+ *   read  : called in row order, twice per chunk that is not resident (once
+ *           per pass), on the calling thread, with user passed through.
+ * Outputs:
+ *   mean  : [M] f64, host or device memory;
+ *   lam   : device [K][L] f64;  psi: device [K][L][L] c128;  info: device [K]
+ *           int32 (as spod_eig);
+ *   phi   : [K][n_modes][M], c128 under SPOD_PREC_FP64 else c64, host (pinned
+ *           or not) or device memory;
+ *   n_valid: device [K] int32 (as spod_modes).
+ * `stream` runs the kernels and is waited on before the first copy.  The call
+ * returns after every result is in place (it synchronises the streams).  On
+ * an error nothing is left running; the outputs are then undefined.  Calls on
+ * one object must not overlap. */
+spod_status spod_ooc_forward(spod_ooc ooc, const void* q, spod_read_fn read, void* user,
+                             double* mean, double* lam, void* psi, int32_t* info, void* phi,
+                             int32_t* n_valid, spod_stream stream);
+
+/* Free the object's device and pinned buffers, streams and events
+ * (NULL-safe; synchronises its streams). */
+void spod_ooc_destroy(spod_ooc ooc);
 
 /* Free the plan's device copies.  NULL-safe.  Synchronises the plan's device. */
 void spod_plan_destroy(spod_plan plan);

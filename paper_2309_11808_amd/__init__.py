@@ -2,6 +2,6 @@
 
 The Python layer only marshals arguments; see `spod.Plan`.
 """
-from .spod import Batch, Plan, PRECISIONS, lib, shape  # noqa: F401
+from .spod import Batch, OutOfCore, Plan, PRECISIONS, lib, shape  # noqa: F401
 from ._native import SpodError  # noqa: F401
 from .autograd import spod, SpodFunction  # noqa: F401

@@ -18,6 +18,7 @@ SPOD_ERR_ALLOC = -3
 SPOD_ERR_HIP = -4
 SPOD_ERR_NUMERIC = -5
 SPOD_ERR_WORKSPACE = -6
+SPOD_ERR_IO = -7
 
 SPOD_F32 = 0
 SPOD_F64 = 1
@@ -52,6 +53,9 @@ _i64 = C.c_int64
 _p = C.c_void_p
 _sz = C.c_size_t
 
+# int (*spod_read_fn)(void* user, int64_t row0, int64_t nrows, void* dst)
+READ_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p)
+
 # name -> (restype, argtypes); exactly the functions of include/spod.h
 SIGNATURES = {
     "spod_plan_create": (C.c_int, [_i64, _i64, _i64, _i64, _i64, _p, _p, C.POINTER(_p)]),
@@ -74,6 +78,11 @@ SIGNATURES = {
     "spod_batch_autotune": (C.c_int, [_p, C.POINTER(_p), C.c_int, _p, _p, _sz, _p, C.c_char_p,
                                       C.POINTER(_i64)]),
     "spod_batch_destroy": (None, [_p]),
+    "spod_ooc_create": (C.c_int, [_p, C.c_int, _i64, _i64, _i64, C.POINTER(_p)]),
+    "spod_ooc_query": (C.c_int, [_p, C.POINTER(_i64), C.POINTER(_i64), C.POINTER(_i64),
+                                 C.POINTER(_sz), C.POINTER(_sz)]),
+    "spod_ooc_forward": (C.c_int, [_p, _p, READ_FN, _p, _p, _p, _p, _p, _p, _p, _p]),
+    "spod_ooc_destroy": (None, [_p]),
     "spod_status_string": (C.c_char_p, [C.c_int]),
     "spod_last_error": (C.c_char_p, []),
 }

@@ -25,7 +25,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libspod.so")
 ARCH = "gfx950"
 
-SOURCES = ["api.cpp", "batch.cpp", "fft.hip", "gram.hip", "eig.hip", "modes.hip",
+SOURCES = ["api.cpp", "batch.cpp", "ooc.cpp", "fft.hip", "gram.hip", "eig.hip", "modes.hip",
            "backward.hip"]
 
 # Packed FP32 instructions are kept out of all device code (the compiler would

@@ -65,6 +65,18 @@ size_t workspace_bytes(const Plan& p) {
 
 void freeze(Plan& p) { p.frozen = true; }
 
+Plan plan_rows(const Plan& p, int64_t row0, int64_t rows) {
+  Plan c = p;
+  c.nspace = rows;
+  c.nvar = 1;
+  c.M = rows;
+  c.d_weights = p.d_weights + row0;
+  c.d_sqrtw = p.d_sqrtw + row0;
+  c.d_sqrtw32 = p.d_sqrtw32 + row0;
+  derive(c);
+  return c;
+}
+
 static bool is_pow2(int64_t n) { return n > 0 && (n & (n - 1)) == 0; }
 
 static spod_status validate_shape(int64_t nt, int64_t nfft, int64_t noverlap, int64_t* L,
@@ -95,6 +107,7 @@ const char* spod_status_string(spod_status s) {
     case SPOD_ERR_HIP: return "SPOD_ERR_HIP";
     case SPOD_ERR_NUMERIC: return "SPOD_ERR_NUMERIC";
     case SPOD_ERR_WORKSPACE: return "SPOD_ERR_WORKSPACE";
+    case SPOD_ERR_IO: return "SPOD_ERR_IO";
   }
   return "SPOD_ERR_UNKNOWN";
 }

@@ -575,7 +575,7 @@ __global__ __launch_bounds__(256, 2) void gram_batch_kernel(const GramItem* __re
 // (a, b) with a <= b; an entry (i, j) of a lower block is conj of (j, i).
 __device__ __forceinline__ void gram_combine_body(const double2* __restrict__ part,
                                                   double2* __restrict__ gram, int L, int D, int S,
-                                                  int k) {
+                                                  int k, bool acc) {
   const double2* pk = part + (int64_t)k * S * D * D;
   for (int idx = threadIdx.x; idx < L * L; idx += blockDim.x) {
     const int i = idx / L, j = idx % L;
@@ -587,21 +587,27 @@ __device__ __forceinline__ void gram_combine_body(const double2* __restrict__ pa
       re += v.x;
       im += v.y;
     }
-    gram[((int64_t)k * L + i) * L + j] = make_double2(re, up ? im : -im);
+    double2* g = gram + ((int64_t)k * L + i) * L + j;
+    if (acc) {
+      const double2 o = *g;
+      *g = make_double2(o.x + re, o.y + (up ? im : -im));
+    } else {
+      *g = make_double2(re, up ? im : -im);
+    }
   }
 }
 
 __global__ __launch_bounds__(256) void gram_combine_kernel(const double2* __restrict__ part,
                                                            double2* __restrict__ gram, int L, int D,
-                                                           int S) {
-  gram_combine_body(part, gram, L, D, S, blockIdx.x);
+                                                           int S, int acc) {
+  gram_combine_body(part, gram, L, D, S, blockIdx.x, acc != 0);
 }
 
 __global__ __launch_bounds__(256) void gram_combine_batch_kernel(const CombineItem* __restrict__ items,
                                                                  int n) {
   const CombineItem& it = items[find_item(items, n, (int)blockIdx.x)];
   gram_combine_body(static_cast<const double2*>(it.part), static_cast<double2*>(it.gram), it.L,
-                    it.D, it.S, (int)blockIdx.x - it.start);
+                    it.D, it.S, (int)blockIdx.x - it.start, false);
 }
 
 // Per-frequency power-of-two scale for the FP16 operands: 2^(15 - e) with e
@@ -722,7 +728,8 @@ static spod_status launch_gram_mode(const Plan& p, const void* qhat, const void*
   return e == hipSuccess ? SPOD_OK : hip_fail(e, "gram_kernel");
 }
 
-spod_status launch_csd(const Plan& p, const void* qhat, void* gram, void* ws, hipStream_t st) {
+spod_status launch_csd(const Plan& p, const void* qhat, void* gram, void* ws, hipStream_t st,
+                       bool accumulate) {
   if (p.nblocks > 64) return fail(SPOD_ERR_UNSUPPORTED, "nblocks > 64");
   double* part = static_cast<double*>(ws);
   const size_t D = (size_t)p.gram_dim;
@@ -747,7 +754,7 @@ spod_status launch_csd(const Plan& p, const void* qhat, void* gram, void* ws, hi
   if (s != SPOD_OK) return s;
   hipLaunchKernelGGL(gram_combine_kernel, dim3((unsigned)p.nfreq), dim3(256), 0, st,
                      reinterpret_cast<const double2*>(part), static_cast<double2*>(gram),
-                     (int)p.nblocks, (int)D, p.gram_split);
+                     (int)p.nblocks, (int)D, p.gram_split, accumulate ? 1 : 0);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SPOD_OK : hip_fail(e, "gram_combine_kernel");
 }

@@ -59,6 +59,10 @@ int64_t gram_split_for(const Plan& p, int64_t target);   // slices for ~target w
 void plan_set_gram_split(Plan& p, int64_t s);            // internal: owner of the plan only
 size_t workspace_bytes(const Plan& p);
 void freeze(Plan& p);
+// A view of rows [row0, row0 + rows) of p's degrees of freedom: the same
+// tables offset to row0, launch shapes derived for `rows` (no allocation; the
+// view must not outlive p and is never destroyed).
+Plan plan_rows(const Plan& p, int64_t row0, int64_t rows);
 
 // error reporting (thread local message)
 spod_status fail(spod_status s, const std::string& msg);
@@ -78,7 +82,9 @@ struct FftSel {
 
 spod_status launch_blocks_fft(const Plan& p, const void* q, spod_dtype dtype, void* qhat,
                               double* mean, void* ws, hipStream_t st, const FftSel& fs = FftSel{});
-spod_status launch_csd(const Plan& p, const void* qhat, void* gram, void* ws, hipStream_t st);
+// accumulate: gram += Qhat^* W Qhat instead of gram = ...
+spod_status launch_csd(const Plan& p, const void* qhat, void* gram, void* ws, hipStream_t st,
+                       bool accumulate = false);
 spod_status launch_eig(const Plan& p, const void* gram, double* lam, void* psi, int32_t* info,
                        void* ws, hipStream_t st);
 spod_status launch_modes(const Plan& p, const void* qhat, const double* lam, const void* psi,

@@ -9,7 +9,8 @@
 //         device three times with its own copy kernel (a dispatch of known
 //         traffic: 1 GiB read and 1 GiB written).
 // path 1: runs the whole forward path (blocks_fft, csd, eig, modes with 5
-//         modes) `reps` times with the bf16x4 plan, then with the FP64 plan.
+//         modes) `reps` times with the plan of `precision`, then with the
+//         FP64 plan.
 // Prints the event timings.
 #include <hip/hip_runtime.h>
 
@@ -93,8 +94,9 @@ static int run_path(int64_t nspace, int64_t nvar, int64_t nt, int64_t nfft, int6
     CHECK_HIP(hipEventSynchronize(e[4]));
     float ms[4];
     for (int i = 0; i < 4; ++i) CHECK_HIP(hipEventElapsedTime(&ms[i], e[i], e[i + 1]));
+    static const char* names[] = {"fp64", "fp32", "bf16x4", "fp16x4"};
     std::printf("%s path %lld: blocks_fft %.3f ms, csd %.3f ms, eig %.3f ms, modes %.3f ms\n",
-                prec == SPOD_PREC_FP64 ? "fp64" : "mixed", (long long)r, ms[0], ms[1], ms[2], ms[3]);
+                names[prec & 3], (long long)r, ms[0], ms[1], ms[2], ms[3]);
     std::fflush(stdout);
   }
   for (auto& x : e) CHECK_HIP(hipEventDestroy(x));
@@ -116,7 +118,7 @@ int main(int argc, char** argv) {
     hipLaunchKernelGGL(fill_kernel, dim3(8192), dim3(256), 0, 0, q, (int64_t)(qbytes / 4), 12345u);
     CHECK_HIP(hipGetLastError());
     CHECK_HIP(hipDeviceSynchronize());
-    if (run_path(nspace, nvar, nt, nfft, nov, reps, SPOD_PREC_BF16X4, q)) return 1;
+    if (run_path(nspace, nvar, nt, nfft, nov, reps, (spod_precision)prec, q)) return 1;
     if (run_path(nspace, nvar, nt, nfft, nov, reps, SPOD_PREC_FP64, q)) return 1;
     CHECK_HIP(hipFree(q));
     std::printf("done\n");

@@ -314,3 +314,122 @@ class Batch:
                                          None if cache_path is None else cache_path.encode(),
                                          C.byref(chosen)))
         return chosen.value
+
+
+def _host_or_device_ptr(t, name: str):
+    """Data pointer of a contiguous torch tensor (CPU or the device) or numpy array."""
+    if isinstance(t, np.ndarray):
+        if not t.flags["C_CONTIGUOUS"]:
+            raise ValueError(f"{name} must be C-contiguous")
+        return C.c_void_p(t.ctypes.data)
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+class OutOfCore:
+    """Out-of-core SPOD (spod_ooc_*): the snapshot matrix stays in host memory
+    and is streamed to the device in chunks of `chunk_rows` rows, twice (Gram
+    pass, modes pass); the last `resident` chunks stay on the device between
+    the passes.  The plan gives the shape, weights, window and precision and
+    must stay open while this object is used."""
+
+    def __init__(self, plan: Plan, dtype=torch.float32, chunk_rows: int = 32768, n_modes: int = 5,
+                 resident: int = 0):
+        if dtype not in (torch.float32, torch.float64):
+            raise TypeError("dtype must be float32 or float64")
+        self.plan = plan
+        self.dtype = dtype
+        self.n_modes = n_modes
+        h = C.c_void_p()
+        with torch.cuda.device(plan.device):
+            _check(lib().spod_ooc_create(plan._h, N.SPOD_F32 if dtype == torch.float32 else N.SPOD_F64,
+                                         int(chunk_rows), int(n_modes), int(resident), C.byref(h)))
+        self._h = h
+        rows, n, r, dev, pin = C.c_int64(), C.c_int64(), C.c_int64(), C.c_size_t(), C.c_size_t()
+        _check(lib().spod_ooc_query(self._h, C.byref(rows), C.byref(n), C.byref(r), C.byref(dev),
+                                    C.byref(pin)))
+        self.chunk_rows, self.n_chunks, self.resident = rows.value, n.value, r.value
+        self.device_bytes, self.pinned_bytes = dev.value, pin.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().spod_ooc_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check_q(self, q):
+        p = self.plan
+        dt = q.dtype if isinstance(q, torch.Tensor) else torch.from_numpy(q[:0]).dtype
+        if dt != self.dtype:
+            raise TypeError(f"q must be {self.dtype}, got {dt}")
+        if tuple(q.shape) != (p.M, p.nt):
+            raise ValueError(f"q must have shape {(p.M, p.nt)}, got {tuple(q.shape)}")
+        if isinstance(q, torch.Tensor) and q.is_cuda and q.device != p.device:
+            raise ValueError(f"q must be on the host or on {p.device}")
+
+    def forward(self, q=None, reader=None, phi=None, mean=None):
+        """One SPOD.  Exactly one of
+          q      : [M, nt] torch tensor (host, pinned or not, or the plan's
+                   device) or numpy array;
+          reader : reader(row0, nrows, out) fills out (a numpy array
+                   [nrows, nt] viewing pinned memory) with those rows of Q.
+        phi ([K, n_modes, M] complex, host or device) and mean ([M] float64)
+        are allocated when not given: phi in pinned host memory, mean on the
+        host.  Returns dict(mean, lam, psi, info, phi, n_valid); lam, psi,
+        info and n_valid are on the device."""
+        p = self.plan
+        if (q is None) == (reader is None):
+            raise ValueError("give exactly one of q and reader")
+        K, L, M, n = p.nfreq, p.nblocks, p.M, self.n_modes
+        if q is not None:
+            self._check_q(q)
+        if phi is None:
+            phi = torch.empty((K, n, M), dtype=p.cdtype, pin_memory=True)
+        elif tuple(phi.shape) != (K, n, M) or phi.dtype != p.cdtype:
+            raise ValueError(f"phi must be {p.cdtype} of shape {(K, n, M)}")
+        if mean is None:
+            mean = torch.empty(M, dtype=torch.float64)
+        elif tuple(mean.shape) != (M,) or mean.dtype != torch.float64:
+            raise ValueError(f"mean must be float64 of shape {(M,)}")
+        lam = torch.empty((K, L), dtype=torch.float64, device=p.device)
+        psi = torch.empty((K, L, L), dtype=torch.complex128, device=p.device)
+        info = torch.empty(K, dtype=torch.int32, device=p.device)
+        n_valid = torch.empty(K, dtype=torch.int32, device=p.device)
+
+        err = []
+        if reader is not None:
+            nt, npdt = p.nt, (np.float32 if self.dtype == torch.float32 else np.float64)
+            ct = C.c_float if self.dtype == torch.float32 else C.c_double
+
+            def _read(user, row0, nrows, dst):
+                try:
+                    buf = (ct * (nrows * nt)).from_address(dst)
+                    out = np.frombuffer(buf, dtype=npdt).reshape(nrows, nt)
+                    reader(int(row0), int(nrows), out)
+                    return 0
+                except BaseException as e:  # reported through SPOD_ERR_IO
+                    err.append(e)
+                    return 1
+            cb = N.READ_FN(_read)
+        else:
+            cb = N.READ_FN()
+        with torch.cuda.device(p.device):
+            _check_ooc(lib().spod_ooc_forward(
+                self._h, None if q is None else _host_or_device_ptr(q, "q"), cb, None,
+                _host_or_device_ptr(mean, "mean"), _ptr(lam), _ptr(psi), _ptr(info),
+                _host_or_device_ptr(phi, "phi"), _ptr(n_valid), _stream(p.device)), err)
+        return {"mean": mean, "lam": lam, "psi": psi, "info": info, "phi": phi, "n_valid": n_valid}
+
+
+def _check_ooc(status: int, err: list):
+    if status != N.SPOD_OK and err:
+        L = lib()
+        msg = L.spod_last_error().decode() or L.spod_status_string(status).decode()
+        raise N.SpodError(status, f"{msg} ({err[0]!r})") from err[0]
+    _check(status)

@@ -49,7 +49,7 @@ def test_binding_signature_table_matches_header():
 def test_status_strings(lib):
     for code, name in [(0, b"SPOD_OK"), (-1, b"SPOD_ERR_INVALID_ARG"), (-2, b"SPOD_ERR_UNSUPPORTED"),
                        (-3, b"SPOD_ERR_ALLOC"), (-4, b"SPOD_ERR_HIP"), (-5, b"SPOD_ERR_NUMERIC"),
-                       (-6, b"SPOD_ERR_WORKSPACE")]:
+                       (-6, b"SPOD_ERR_WORKSPACE"), (-7, b"SPOD_ERR_IO")]:
         assert lib.spod_status_string(code) == name
     assert lib.spod_status_string(-99) == b"SPOD_ERR_UNKNOWN"
 
@@ -150,3 +150,14 @@ def test_batch_entry_points_reject_null_and_bad_problems(lib):
     assert lib.spod_batch_autotune(None, None, 0, None, None, 0, None, None,
                                    None) == N.SPOD_ERR_INVALID_ARG
     lib.spod_batch_destroy(None)
+
+
+def test_out_of_core_entry_points_reject_null(lib):
+    out = C.c_void_p()
+    assert lib.spod_ooc_create(None, 0, 256, 1, 0, C.byref(out)) == N.SPOD_ERR_INVALID_ARG
+    assert out.value is None
+    assert lib.spod_ooc_create(None, 0, 256, 1, 0, None) == N.SPOD_ERR_INVALID_ARG
+    assert lib.spod_ooc_query(None, None, None, None, None, None) == N.SPOD_ERR_INVALID_ARG
+    assert lib.spod_ooc_forward(None, None, N.READ_FN(), None, None, None, None, None, None, None,
+                                None) == N.SPOD_ERR_INVALID_ARG
+    lib.spod_ooc_destroy(None)

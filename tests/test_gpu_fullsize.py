@@ -134,3 +134,31 @@ def test_era_field_full_size(era, precision):
     del out
     plan.close()
     torch.cuda.empty_cache()
+
+
+def test_era_field_out_of_core(era):
+    """The same workload streamed from pinned host memory in 32 chunks of
+    32768 rows with nothing kept resident: both passes read all of Q."""
+    from paper_2309_11808_amd import OutOfCore
+    p, bins, rows, ref = era
+    plan = _plan(p, "bf16x4")
+    q_host = torch.empty(tuple(p.q.shape), dtype=torch.float32, pin_memory=True)
+    q_host.copy_(p.q)
+    o = OutOfCore(plan, dtype=torch.float32, chunk_rows=32768, n_modes=5, resident=0)
+    assert o.n_chunks == 32
+    out = o.forward(q=q_host)
+    mean = out["mean"].numpy()[rows]
+    np.testing.assert_allclose(mean, ref["mean"][rows], rtol=0,
+                               atol=1e-13 * float(np.abs(ref["mean"]).max()) + 1e-12)
+    lam = out["lam"].index_select(0, torch.as_tensor(bins, device="cuda")).cpu().numpy()
+    err = PT.check_eig_mixed(lam, ref["lam"], p.M, n=5, rtol=1e-4)
+    phi = out["phi"][bins][:, :, rows].numpy()
+    n_valid = out["n_valid"].cpu().numpy()[bins]
+    merr = _modes_rows_error(phi, ref["phi"], n_valid, ref["lam"], 1e-3)
+    print(f"era out-of-core bf16x4: eigenvalue rel err {err:.2e}, sampled mode rows {merr:.2e}")
+    assert merr <= 1e-3
+    assert int(out["info"].min()) > 0
+    del out, q_host
+    o.close()
+    plan.close()
+    torch.cuda.empty_cache()
