@@ -94,6 +94,12 @@ spod_status launch_backward(const Plan& p, const void* q, spod_dtype dtype, cons
                             const void* g_phi, int n_modes, const int32_t* bins, int n_bins,
                             void* g_qhat, void* g_q, void* ws, hipStream_t st);
 
+// nrow rows of width_bytes from a packed device buffer to dst with row stride
+// dpitch_bytes (device memory, or pinned host memory through its device
+// address); 8-byte units and alignment
+spod_status launch_store_rows(const void* src, void* dst, size_t width_bytes, size_t dpitch_bytes,
+                              int64_t nrow, hipStream_t st);
+
 // workspace sizes of the individual stages
 size_t fft_workspace(const Plan& p);  // only used when the caller passes no mean buffer
 size_t csd_workspace(const Plan& p);

@@ -8,6 +8,8 @@
 // the L x n_modes coefficients psi / sqrt(lambda) sit in LDS.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "internal.h"
 
 namespace spod {
@@ -161,6 +163,43 @@ spod_status launch_modes_group(bool c128, const ModesItem* d_items, int n, int w
                        d_items, n);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SPOD_OK : hip_fail(e, "modes_batch_kernel");
+}
+
+// Rows of a packed buffer [nrow][width] to a destination with row stride
+// dpitch (units of V): the modes of one chunk of degrees of freedom into their
+// columns of phi [K][n_modes][M], in device memory or in pinned host memory
+// mapped for the device (then the stores cross the host link).
+template <typename V>
+__global__ __launch_bounds__(256) void store_rows_kernel(const V* __restrict__ src,
+                                                         V* __restrict__ dst, int64_t width,
+                                                         int64_t dpitch, int64_t nrow) {
+  const int64_t tiles = (width + 255) / 256;
+  for (int64_t t = blockIdx.x; t < tiles * nrow; t += gridDim.x) {
+    const int64_t r = t / tiles, i = (t - r * tiles) * 256 + threadIdx.x;
+    if (i < width) dst[r * dpitch + i] = src[r * width + i];
+  }
+}
+
+spod_status launch_store_rows(const void* src, void* dst, size_t width_bytes, size_t dpitch_bytes,
+                              int64_t nrow, hipStream_t st) {
+  if (width_bytes % 8 != 0 || dpitch_bytes % 8 != 0 || (uintptr_t)src % 8 != 0 ||
+      (uintptr_t)dst % 8 != 0 || dpitch_bytes < width_bytes)
+    return fail(SPOD_ERR_INVALID_ARG, "store_rows: 8-byte units and alignment required");
+  if (nrow <= 0 || width_bytes == 0) return SPOD_OK;
+  const bool v16 = width_bytes % 16 == 0 && dpitch_bytes % 16 == 0 && (uintptr_t)src % 16 == 0 &&
+                   (uintptr_t)dst % 16 == 0;
+  const int64_t unit = v16 ? 16 : 8;
+  const int64_t width = (int64_t)width_bytes / unit, dpitch = (int64_t)dpitch_bytes / unit;
+  const int64_t total = (width + 255) / 256 * nrow;
+  const unsigned grid = (unsigned)std::min<int64_t>(total, 4096);
+  if (v16)
+    hipLaunchKernelGGL(store_rows_kernel<uint4>, dim3(grid), dim3(256), 0, st,
+                       static_cast<const uint4*>(src), static_cast<uint4*>(dst), width, dpitch, nrow);
+  else
+    hipLaunchKernelGGL(store_rows_kernel<uint2>, dim3(grid), dim3(256), 0, st,
+                       static_cast<const uint2*>(src), static_cast<uint2*>(dst), width, dpitch, nrow);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SPOD_OK : hip_fail(e, "store_rows_kernel");
 }
 
 }  // namespace spod
