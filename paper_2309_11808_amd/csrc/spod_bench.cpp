@@ -11,12 +11,18 @@
 // path 1: runs the whole forward path (blocks_fft, csd, eig, modes with 5
 //         modes) `reps` times with the plan of `precision`, then with the
 //         FP64 plan.
+// path 2: out-of-core: Q copied to pinned host memory, then spod_ooc_forward
+//         with chunks of 32768 rows, `reps` times with no chunk resident and
+//         `reps` times with every chunk resident (plan of `precision`, 5
+//         modes to pinned host memory).
 // Prints the event timings.
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
+#include <vector>
 
 #include "spod.h"
 
@@ -106,11 +112,69 @@ static int run_path(int64_t nspace, int64_t nvar, int64_t nt, int64_t nfft, int6
   return 0;
 }
 
+static int run_ooc(int64_t nspace, int64_t nvar, int64_t nt, int64_t nfft, int64_t nov,
+                   int64_t reps, spod_precision prec) {
+  const int64_t M = nspace * nvar, n_modes = 5, rows = 32768;
+  const size_t qbytes = sizeof(float) * (size_t)M * (size_t)nt;
+  float* qd = nullptr;
+  float* qh = nullptr;
+  CHECK_HIP(hipMalloc(&qd, qbytes));
+  hipLaunchKernelGGL(fill_kernel, dim3(8192), dim3(256), 0, 0, qd, (int64_t)(qbytes / 4), 12345u);
+  CHECK_HIP(hipGetLastError());
+  CHECK_HIP(hipHostMalloc(reinterpret_cast<void**>(&qh), qbytes, hipHostMallocDefault));
+  CHECK_HIP(hipMemcpy(qh, qd, qbytes, hipMemcpyDeviceToHost));
+  CHECK_HIP(hipFree(qd));
+  spod_plan plan = nullptr;
+  CHECK_SPOD(spod_plan_create(nspace, nvar, nt, nfft, nov, nullptr, nullptr, &plan));
+  CHECK_SPOD(spod_plan_set_precision(plan, prec));
+  int64_t L = 0, K = 0;
+  CHECK_SPOD(spod_plan_query(plan, &L, &K, nullptr));
+  const size_t csz = prec == SPOD_PREC_FP64 ? 16 : 8;
+  void *phi = nullptr, *psi = nullptr;
+  double* lam = nullptr;
+  int32_t *info = nullptr, *nval = nullptr;
+  std::vector<double> mean((size_t)M);
+  CHECK_HIP(hipHostMalloc(&phi, csz * (size_t)(K * n_modes * M), hipHostMallocDefault));
+  CHECK_HIP(hipMalloc(&psi, 16 * (size_t)(K * L * L)));
+  CHECK_HIP(hipMalloc(&lam, 8 * (size_t)(K * L)));
+  CHECK_HIP(hipMalloc(&info, 4 * (size_t)K));
+  CHECK_HIP(hipMalloc(&nval, 4 * (size_t)K));
+  for (int64_t resident : {int64_t(0), int64_t(1) << 30}) {
+    spod_ooc o = nullptr;
+    CHECK_SPOD(spod_ooc_create(plan, SPOD_F32, rows, n_modes, resident, &o));
+    int64_t nchunks = 0, nres = 0;
+    CHECK_SPOD(spod_ooc_query(o, nullptr, &nchunks, &nres, nullptr, nullptr));
+    for (int64_t r = 0; r < reps; ++r) {
+      auto t0 = std::chrono::steady_clock::now();
+      CHECK_SPOD(spod_ooc_forward(o, qh, nullptr, nullptr, mean.data(), lam, psi, info, phi, nval,
+                                  nullptr));
+      const double s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      const double link = (double)qbytes * (double)(2 * nchunks - nres) / (double)nchunks;
+      std::printf("out-of-core %lld/%lld chunks resident, %lld: %.1f ms, Q %.2f GB/s, link in %.2f GB/s\n",
+                  (long long)nres, (long long)nchunks, (long long)r, s * 1e3, qbytes / s / 1e9,
+                  link / s / 1e9);
+      std::fflush(stdout);
+    }
+    spod_ooc_destroy(o);
+  }
+  spod_plan_destroy(plan);
+  CHECK_HIP(hipHostFree(qh));
+  CHECK_HIP(hipHostFree(phi));
+  void* bufs[] = {psi, lam, info, nval};
+  for (void* b : bufs) CHECK_HIP(hipFree(b));
+  return 0;
+}
+
 int main(int argc, char** argv) {
   int64_t nspace = 524288, nvar = 2, nt = 8192, nfft = 512, nov = 256, reps = 3, prec = 2, path = 0;
   int64_t* args[] = {&nspace, &nvar, &nt, &nfft, &nov, &reps, &prec, &path};
   for (int i = 1; i < argc && i <= 8; ++i) *args[i - 1] = std::atoll(argv[i]);
   const int64_t M = nspace * nvar;
+  if (path == 2) {
+    if (run_ooc(nspace, nvar, nt, nfft, nov, reps, (spod_precision)prec)) return 1;
+    std::printf("done\n");
+    return 0;
+  }
   if (path == 1) {
     float* q = nullptr;
     const size_t qbytes = sizeof(float) * (size_t)M * (size_t)nt;
