@@ -272,6 +272,54 @@ spod_status spod_batch_autotune(spod_batch batch, const void* const* q, spod_dty
 void spod_batch_destroy(spod_batch batch);
 
 /* ---------------------------------------------------------------------------
+ * Expansion coefficients and reconstruction (SPOD for data compression,
+ * eq. (coeffs) and eq. (SPODrec)).  Phi_r gathers the retained modes arranged
+ * by frequency as in eq. (discrete_modes): column r = i * n_r + j is mode j of
+ * frequency bins[i].  With R = n_bins * n_r retained modes:
+ *
+ *   A  = (Phi_r^* W Phi_r)^{-1} Phi_r^* W (Q - qbar 1^T)     (R x N_t)
+ *   Q~ = Re(Phi_r A) + qbar 1^T                               (M x N_t)
+ *
+ * The mean is removed before the projection and added back after it (the
+ * modes describe the fluctuations); only the one-sided frequencies are
+ * retained, so the reconstruction of real data is the real part.  Every
+ * product runs in FP64 (complex64 modes and float32 snapshots are widened
+ * as they are read); Phi_r^* W Phi_r is factored by Cholesky, so every
+ * retained mode must be valid (n_r <= n_valid at each retained bin).
+ * ------------------------------------------------------------------------ */
+
+/* Workspace bytes of spod_coeffs for R = n_bins * n_r in [1, 1024]. */
+spod_status spod_coeffs_query(spod_plan plan, int64_t n_bins, int64_t n_r, size_t* workspace);
+
+/* A = (Phi_r^* W Phi_r)^{-1} Phi_r^* W (Q - qbar 1^T)  (eq. (coeffs)).
+ *   q      : device [M][nt] of dtype (the snapshots the modes came from, or
+ *            any others of the same shape);
+ *   mean   : device [M] f64 (the long-time mean from spod_blocks_fft);
+ *   phi    : device [K][n_modes][M], complex128 under SPOD_PREC_FP64 else
+ *            complex64 (spod_modes' output);
+ *   bins   : host [n_bins], strictly increasing in [0, K), read during the call;
+ *   n_r    : modes kept per retained frequency, in [1, n_modes];
+ *   a      : device [R][nt] in phi's complex type (row r = coefficient of
+ *            column r of Phi_r over time);
+ *   info   : device [1] int32: 0, or j + 1 when pivot j of the Cholesky
+ *            factorisation is not positive (a retained mode is zero or the
+ *            retained modes are linearly dependent); a is then zero;
+ *   ws     : device workspace of spod_coeffs_query's size.
+ * Asynchronous on stream.  SPOD_ERR_UNSUPPORTED when R > 1024. */
+spod_status spod_coeffs(spod_plan plan, const void* q, spod_dtype dtype, const double* mean,
+                        const void* phi, int64_t n_modes, const int32_t* bins, int64_t n_bins,
+                        int64_t n_r, void* a, int32_t* info, void* ws, size_t ws_bytes,
+                        spod_stream stream);
+
+/* Q~ = Re(Phi_r A) + qbar 1^T  (eq. (SPODrec)).  phi, bins, n_r as in
+ * spod_coeffs; a: device [R][nt] in phi's complex type; mean: device [M] f64;
+ * q_rec: device [M][nt] of dtype.  Asynchronous on stream; needs no
+ * workspace. */
+spod_status spod_reconstruct(spod_plan plan, const void* phi, int64_t n_modes, const int32_t* bins,
+                             int64_t n_bins, int64_t n_r, const void* a, const double* mean,
+                             void* q_rec, spod_dtype dtype, spod_stream stream);
+
+/* ---------------------------------------------------------------------------
  * Out-of-core SPOD: the snapshot matrix stays in host memory (or behind a
  * reader) and reaches the device in chunks of rows.  This is the spatial
  * split of Sec. 3.1 (every process owns a slice of the degrees of freedom and

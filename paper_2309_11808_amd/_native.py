@@ -78,6 +78,9 @@ SIGNATURES = {
     "spod_batch_autotune": (C.c_int, [_p, C.POINTER(_p), C.c_int, _p, _p, _sz, _p, C.c_char_p,
                                       C.POINTER(_i64)]),
     "spod_batch_destroy": (None, [_p]),
+    "spod_coeffs_query": (C.c_int, [_p, _i64, _i64, C.POINTER(_sz)]),
+    "spod_coeffs": (C.c_int, [_p, _p, C.c_int, _p, _p, _i64, _p, _i64, _i64, _p, _p, _p, _sz, _p]),
+    "spod_reconstruct": (C.c_int, [_p, _p, _i64, _p, _i64, _i64, _p, _p, _p, C.c_int, _p]),
     "spod_ooc_create": (C.c_int, [_p, C.c_int, _i64, _i64, _i64, C.POINTER(_p)]),
     "spod_ooc_query": (C.c_int, [_p, C.POINTER(_i64), C.POINTER(_i64), C.POINTER(_i64),
                                  C.POINTER(_sz), C.POINTER(_sz)]),

@@ -409,4 +409,68 @@ spod_status spod_backward(spod_plan plan, const void* q, spod_dtype dtype, const
                          (hipStream_t)stream);
 }
 
+static spod_status coeff_sel(const Plan& p, int64_t n_modes, const int32_t* bins, int64_t n_bins,
+                             int64_t n_r, CoeffSel* cs) {
+  if (n_modes < 1 || n_modes > p.nblocks)
+    return fail(SPOD_ERR_INVALID_ARG, "n_modes must be in [1, nblocks]");
+  if (n_r < 1 || n_r > n_modes) return fail(SPOD_ERR_INVALID_ARG, "n_r must be in [1, n_modes]");
+  if (!bins) return fail(SPOD_ERR_INVALID_ARG, "bins is required");
+  if (n_bins < 1 || n_bins > p.nfreq)
+    return fail(SPOD_ERR_INVALID_ARG, "n_bins must be in [1, nfreq]");
+  for (int64_t i = 0; i < n_bins; ++i)
+    if (bins[i] < 0 || bins[i] >= p.nfreq || (i > 0 && bins[i] <= bins[i - 1]))
+      return fail(SPOD_ERR_INVALID_ARG, "bins must be strictly increasing in [0, nfreq)");
+  if (n_bins * n_r > CoeffSel::MAX_R)
+    return fail(SPOD_ERR_UNSUPPORTED, "n_bins * n_r above 1024 retained modes");
+  cs->n_bins = (int)n_bins;
+  cs->n_r = (int)n_r;
+  cs->n_modes = (int)n_modes;
+  for (int64_t i = 0; i < n_bins; ++i) cs->bin[i] = bins[i];
+  return SPOD_OK;
+}
+
+spod_status spod_coeffs_query(spod_plan plan, int64_t n_bins, int64_t n_r, size_t* workspace) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p) return fail(SPOD_ERR_INVALID_ARG, "plan is NULL");
+  if (n_bins < 1 || n_r < 1 || n_bins * n_r > CoeffSel::MAX_R)
+    return fail(SPOD_ERR_INVALID_ARG, "n_bins * n_r must be in [1, 1024]");
+  if (workspace) *workspace = coeff_layout(*p, (int)(n_bins * n_r)).bytes;
+  return SPOD_OK;
+}
+
+spod_status spod_coeffs(spod_plan plan, const void* q, spod_dtype dtype, const double* mean,
+                        const void* phi, int64_t n_modes, const int32_t* bins, int64_t n_bins,
+                        int64_t n_r, void* a, int32_t* info, void* ws, size_t ws_bytes,
+                        spod_stream stream) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p) return fail(SPOD_ERR_INVALID_ARG, "plan is NULL");
+  if (!q || !mean || !phi || !a || !info)
+    return fail(SPOD_ERR_INVALID_ARG, "q, mean, phi, a and info are required");
+  if (dtype != SPOD_F32 && dtype != SPOD_F64) return fail(SPOD_ERR_INVALID_ARG, "dtype");
+  CoeffSel cs;
+  spod_status st = coeff_sel(*p, n_modes, bins, n_bins, n_r, &cs);
+  if (st != SPOD_OK) return st;
+  st = enter(p);
+  if (st != SPOD_OK) return st;
+  st = check_ws(*p, ws, ws_bytes, coeff_layout(*p, cs.n_bins * cs.n_r).bytes);
+  if (st != SPOD_OK) return st;
+  return launch_coeffs(*p, q, dtype, mean, phi, cs, a, info, ws, (hipStream_t)stream);
+}
+
+spod_status spod_reconstruct(spod_plan plan, const void* phi, int64_t n_modes, const int32_t* bins,
+                             int64_t n_bins, int64_t n_r, const void* a, const double* mean,
+                             void* q_rec, spod_dtype dtype, spod_stream stream) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p) return fail(SPOD_ERR_INVALID_ARG, "plan is NULL");
+  if (!phi || !a || !mean || !q_rec)
+    return fail(SPOD_ERR_INVALID_ARG, "phi, a, mean and q_rec are required");
+  if (dtype != SPOD_F32 && dtype != SPOD_F64) return fail(SPOD_ERR_INVALID_ARG, "dtype");
+  CoeffSel cs;
+  spod_status st = coeff_sel(*p, n_modes, bins, n_bins, n_r, &cs);
+  if (st != SPOD_OK) return st;
+  st = enter(p);
+  if (st != SPOD_OK) return st;
+  return launch_reconstruct(*p, phi, cs, a, mean, q_rec, dtype, (hipStream_t)stream);
+}
+
 }  // extern "C"

@@ -100,6 +100,26 @@ spod_status launch_backward(const Plan& p, const void* q, spod_dtype dtype, cons
 spod_status launch_store_rows(const void* src, void* dst, size_t width_bytes, size_t dpitch_bytes,
                               int64_t nrow, hipStream_t st);
 
+// Expansion coefficients and reconstruction: the retained modes (mode j < n_r
+// of every frequency bin[i], column i * n_r + j of Phi_r) and the workspace
+// layout of one problem with R = n_bins * n_r columns.
+struct CoeffSel {
+  static constexpr int MAX_BINS = 513;
+  static constexpr int MAX_R = 1024;
+  int n_bins = 0, n_r = 0, n_modes = 0;
+  int bin[MAX_BINS] = {};
+};
+struct CoeffLayout {
+  int R = 0, S_rhs = 1, S_gram = 1;   // columns, slices of M for C and for B
+  size_t off_B = 0, off_C = 0, off_part = 0, bytes = 0;
+};
+CoeffLayout coeff_layout(const Plan& p, int R);
+spod_status launch_coeffs(const Plan& p, const void* q, spod_dtype dtype, const double* mean,
+                          const void* phi, const CoeffSel& cs, void* a, int32_t* info, void* ws,
+                          hipStream_t st);
+spod_status launch_reconstruct(const Plan& p, const void* phi, const CoeffSel& cs, const void* a,
+                               const double* mean, void* qrec, spod_dtype dtype, hipStream_t st);
+
 // workspace sizes of the individual stages
 size_t fft_workspace(const Plan& p);  // only used when the caller passes no mean buffer
 size_t csd_workspace(const Plan& p);

@@ -198,6 +198,48 @@ class Plan:
             _ptr(g_q), _ptr(ws), ws.numel(), _stream(self.device)))
         return g_q
 
+    # -- expansion coefficients and reconstruction -------------------------
+    def _bins(self, phi, bins, n_r):
+        if phi.dim() != 3 or phi.shape[0] != self.nfreq or phi.shape[2] != self.M:
+            raise ValueError(f"phi must have shape ({self.nfreq}, n_modes, {self.M})")
+        self._dev(phi, "phi", self.cdtype, tuple(phi.shape))
+        sel = np.ascontiguousarray(np.asarray(bins, dtype=np.int32))
+        if sel.ndim != 1:
+            raise ValueError("bins must be one-dimensional")
+        return sel, len(sel) * int(n_r)
+
+    def coeffs(self, q, mean, phi, bins, n_r: int, a=None, info=None):
+        """Expansion coefficients A = (Phi_r^* W Phi_r)^{-1} Phi_r^* W (Q - qbar)
+        over mode j < n_r of every frequency in bins (column i * n_r + j).
+        Returns (a [R, nt] in phi's complex type, info [1] int32)."""
+        dt = self._q(q)
+        self._dev(mean, "mean", torch.float64, (self.M,))
+        sel, R = self._bins(phi, bins, n_r)
+        a = self._out(a, "a", self.cdtype, (R, self.nt))
+        info = self._out(info, "info", torch.int32, (1,))
+        wsb = C.c_size_t()
+        _check(lib().spod_coeffs_query(self._h, len(sel), int(n_r), C.byref(wsb)))
+        ws = torch.empty(max(1, wsb.value), dtype=torch.uint8, device=self.device)
+        _check(lib().spod_coeffs(self._h, _ptr(q), dt, _ptr(mean), _ptr(phi), phi.shape[1],
+                                 sel.ctypes.data_as(C.c_void_p), len(sel), int(n_r), _ptr(a),
+                                 _ptr(info), _ptr(ws), ws.numel(), _stream(self.device)))
+        return a, info
+
+    def reconstruct(self, phi, bins, n_r: int, a, mean, q_rec=None, dtype=torch.float32):
+        """Q~ = Re(Phi_r A) + qbar 1^T, [M, nt] of dtype."""
+        sel, R = self._bins(phi, bins, n_r)
+        self._dev(a, "a", self.cdtype, (R, self.nt))
+        self._dev(mean, "mean", torch.float64, (self.M,))
+        if dtype not in (torch.float32, torch.float64):
+            raise TypeError("dtype must be float32 or float64")
+        q_rec = self._out(q_rec, "q_rec", dtype, (self.M, self.nt))
+        _check(lib().spod_reconstruct(self._h, _ptr(phi), phi.shape[1],
+                                      sel.ctypes.data_as(C.c_void_p), len(sel), int(n_r), _ptr(a),
+                                      _ptr(mean), _ptr(q_rec),
+                                      N.SPOD_F32 if dtype == torch.float32 else N.SPOD_F64,
+                                      _stream(self.device)))
+        return q_rec
+
     def forward(self, q, n_modes: int = 5):
         """All stages: returns dict(mean, qhat, gram, lam, psi, info, phi, n_valid)."""
         qhat, mean = self.blocks_fft(q)

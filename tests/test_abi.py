@@ -161,3 +161,12 @@ def test_out_of_core_entry_points_reject_null(lib):
     assert lib.spod_ooc_forward(None, None, N.READ_FN(), None, None, None, None, None, None, None,
                                 None) == N.SPOD_ERR_INVALID_ARG
     lib.spod_ooc_destroy(None)
+
+
+def test_coefficient_entry_points_reject_null(lib):
+    ws = C.c_size_t()
+    assert lib.spod_coeffs_query(None, 1, 1, C.byref(ws)) == N.SPOD_ERR_INVALID_ARG
+    assert lib.spod_coeffs(None, None, 0, None, None, 1, None, 1, 1, None, None, None, 0,
+                           None) == N.SPOD_ERR_INVALID_ARG
+    assert lib.spod_reconstruct(None, None, 1, None, 1, 1, None, None, None, 0,
+                                None) == N.SPOD_ERR_INVALID_ARG
