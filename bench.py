@@ -2,7 +2,7 @@
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 3] [--precision bf16x4]
                     [--workload era|jet] [--no-fp64] [--no-cpu] [--no-diff] [--no-batch]
-                    [--no-ooc] [--ooc-only]
+                    [--no-ooc] [--ooc-only] [--no-coeffs] [--coeffs-only]
 
 A step is one pass of the whole path over the resident input: temporal mean +
 windowed block FFT (spod_blocks_fft), weighted Gram (spod_csd), batched
@@ -19,8 +19,11 @@ frequencies), cos(latitude) weights; red noise plus 6 planted modes, generated
 on the device from a seed.  Prints one JSON line on stdout; progress goes to
 stderr.
 
-Three more measurements ride on the same line (skipped with --no-ooc,
+More measurements ride on the same line (skipped with --no-coeffs, --no-ooc,
 --no-diff and --no-batch):
+  * coefficients: expansion coefficients (spod_coeffs) of the same field over
+    the 5 leading modes of its 64 lowest frequencies (R = 320) and the
+    reconstruction from them (spod_reconstruct), against FP64 MFMA peak;
   * out_of_core: the same field with q in pinned host memory, streamed to the
     device in chunks of 32768 rows by spod_ooc_forward, with no chunk resident
     (Q crosses the host link twice) and with every chunk resident (once);
@@ -373,6 +376,59 @@ def bench_out_of_core(p, precision, lam_in_memory, chunk_rows=32768, reps=2):
     return res
 
 
+FP64_PEAK_TFLOPS = 78.6
+
+
+def bench_coeffs(p, precision, n_bins=64, n_r=5, steps=3, warmup=1):
+    """Expansion coefficients and reconstruction of the main workload over the
+    n_r leading modes of its n_bins lowest frequencies."""
+    import numpy as np
+    import torch
+    from paper_2309_11808_amd import Plan
+    plan = Plan(p.nspace, p.nvar, p.nt, p.nfft, p.noverlap, weights=p.weights, precision=precision)
+    out = plan.forward(p.q, n_modes=n_r)
+    phi, mean = out["phi"], out["mean"]
+    n_valid = int(out["n_valid"][:n_bins].min())
+    del out
+    torch.cuda.empty_cache()
+    bins = list(range(n_bins))
+    R, M, nt = n_bins * n_r, plan.M, plan.nt
+    a, info = plan.coeffs(p.q, mean, phi, bins, n_r)
+    rec = plan.reconstruct(phi, bins, n_r, a, mean, dtype=p.q.dtype)
+    t_c = _time(lambda: plan.coeffs(p.q, mean, phi, bins, n_r, a=a, info=info), steps, warmup)
+    t_r = _time(lambda: plan.reconstruct(phi, bins, n_r, a, mean, q_rec=rec), steps, warmup)
+    # property at full size: the residual of the projection is W-orthogonal to
+    # the retained modes (checked on 16 sampled time columns)
+    cols = torch.arange(0, nt, nt // 16, device=p.q.device)[:16]
+    W = torch.as_tensor(p.weights, device=p.q.device)
+    Phi = phi[bins].reshape(R, M).to(torch.complex128)
+    qs = (p.q[:, cols].double() - mean[:, None]).to(torch.complex128)
+    res = qs - torch.mm(Phi.t().contiguous(), a[:, cols].to(torch.complex128))
+    ortho = float((Phi.conj() @ (W[:, None] * res)).abs().max() /
+                  (Phi.conj() @ (W[:, None] * qs)).abs().max())
+    err = float(((rec[:, cols].double() - p.q[:, cols].double()).pow(2) * W[:, None]).sum() /
+                ((p.q[:, cols].double() - mean[:, None]).pow(2) * W[:, None]).sum())
+    f_rhs = 4.0 * R * M * nt
+    f_gram = 8.0 * R * (R + 1) / 2 * M
+    f_rec = 4.0 * R * M * nt
+    res_ = {"workload": f"the main workload's modes: {n_r} leading modes of the {n_bins} lowest "
+                        f"frequencies (R = {R}), FP64 MFMA",
+            "R": R, "precision_of_modes": precision, "retained_modes_valid": n_valid >= n_r,
+            "info": int(info.item()),
+            "coeffs_ms": round(t_c, 3), "reconstruct_ms": round(t_r, 3),
+            "coeffs_TFLOPs": round((f_rhs + f_gram) / (t_c * 1e-3) / 1e12, 2),
+            "reconstruct_TFLOPs": round(f_rec / (t_r * 1e-3) / 1e12, 2),
+            "peak_TFLOPs": FP64_PEAK_TFLOPS,
+            "coeffs_frac": round((f_rhs + f_gram) / (t_c * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4),
+            "reconstruct_frac": round(f_rec / (t_r * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4),
+            "residual_w_orthogonality": ortho,
+            "relative_w_energy_not_captured": err}
+    del a, rec, phi, mean, Phi, qs, res
+    plan.close()
+    torch.cuda.empty_cache()
+    return res_
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -385,6 +441,9 @@ def main(argv=None):
     ap.add_argument("--no-diff", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-ooc", action="store_true")
+    ap.add_argument("--no-coeffs", action="store_true")
+    ap.add_argument("--coeffs-only", action="store_true",
+                    help="generate the workload and time the coefficients and reconstruction alone")
     ap.add_argument("--ooc-only", action="store_true",
                     help="generate the workload and time the out-of-core path alone")
     ap.add_argument("--no-main", action="store_true",
@@ -416,6 +475,12 @@ def main(argv=None):
     p, desc = workload(a.workload, "cuda")
     torch.cuda.synchronize()
     log(f"generated M={p.M} nt={p.nt} in {time.perf_counter() - t:.1f} s")
+    if a.coeffs_only:
+        result = {"metric": METRIC, "value": None, "unit": "GB/s", "n_gpus": 1,
+                  "config": {"workload": desc},
+                  "coefficients": bench_coeffs(p, a.precision, steps=max(1, a.steps))}
+        print(json.dumps(result), flush=True)
+        return 0
     if a.ooc_only:
         result = {"metric": METRIC, "value": None, "unit": "GB/s", "n_gpus": 1,
                   "config": {"workload": desc},
@@ -483,6 +548,10 @@ def main(argv=None):
         log("timing the FP64 CPU oracle on a sample")
         result["cpu_baseline"] = cpu_baseline(p)
         log(f"cpu baseline {result['cpu_baseline']}")
+    if not a.no_coeffs:
+        log("expansion coefficients and reconstruction")
+        result["coefficients"] = bench_coeffs(p, a.precision)
+        log(f"coefficients {result['coefficients']}")
     if not a.no_ooc:
         log("out-of-core workload")
         result["out_of_core"] = bench_out_of_core(p, a.precision, mixed["lam"].numpy())

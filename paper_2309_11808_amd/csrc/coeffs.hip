@@ -8,9 +8,9 @@
 //   Q~    = Re(Phi_r A) + qbar 1^T                           (M x N_t)
 //
 // B, C and Q~ are long real contractions run on v_mfma_f64_16x16x4f64 in
-// 64 x 64 output tiles per workgroup (four waves of 32 x 32): 16-wide blocks of
-// the contraction are staged in LDS as [k][64] so that a wave's 16 lanes of
-// one k read 16 consecutive doubles.  Complex operands are split into real and
+// 64 x 64 output tiles per workgroup (four waves of 32 x 32): 16- or 32-wide
+// blocks of the contraction are staged in LDS as [k][64] so that a wave's 16
+// lanes of one k read 16 consecutive doubles.  Complex operands are split into real and
 // imaginary planes; complex64 modes and float32 snapshots are widened to FP64
 // as they are loaded, so every form of the plan computes in FP64.  B and C
 // contract over the M degrees of freedom, split into S slices whose partial
@@ -55,18 +55,67 @@ __device__ __forceinline__ v4d mfma(double a, double b, v4d c) {
 }
 
 // ---------------------------------------------------------------------------
-// C = Phi_r^* W (Q - qbar): partial tile of slice s.  Grid: i tiles fastest,
-// then t tiles, then slices (the i tiles of one t tile share its Q rows).
+// X = W conj(Phi_r) as two FP64 planes [M][R] (real, imaginary): a tiled
+// transpose through LDS, so that the right-hand side reads 16 contiguous rows
+// of R values per block instead of 64 mode rows far apart in memory.
 // ---------------------------------------------------------------------------
-template <typename CT, typename QT>
-__global__ __launch_bounds__(256) void coeff_rhs_kernel(const CT* __restrict__ phi,
-                                                        const QT* __restrict__ q,
-                                                        const double* __restrict__ mean,
-                                                        const double* __restrict__ w, ModeSel sel,
-                                                        double2* __restrict__ out, int64_t M,
-                                                        int64_t nt, int S) {
-  __shared__ double Ar[KB][TILE], Ai[KB][TILE], Bq[KB][TILE];
+constexpr int GM = 32;     // DOFs per gather tile
+
+template <typename CT>
+__global__ __launch_bounds__(256) void gather_weighted_kernel(const CT* __restrict__ phi,
+                                                              const double* __restrict__ w,
+                                                              ModeSel sel, double* __restrict__ Xr,
+                                                              double* __restrict__ Xi, int64_t M) {
+  __shared__ double tr[TILE][GM + 1], ti[TILE][GM + 1];
   const int R = sel.R;
+  const int Ti = (R + TILE - 1) / TILE;
+  const int i0 = (int)(blockIdx.x % Ti) * TILE;
+  const int64_t m0 = (int64_t)(blockIdx.x / Ti) * GM;
+  const int tid = threadIdx.x;
+  // read: 64 mode rows x 32 DOFs, 8 threads x 4 DOFs a row, 32 rows per pass
+  for (int rr = tid >> 3; rr < TILE; rr += 32) {
+    const int i = i0 + rr;
+    const CT* src = phi + (i < R ? sel_row(sel, i) * M : 0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = (tid & 7) * 4 + u;
+      const int64_t m = m0 + c;
+      const double2 v = (i < R && m < M) ? ld_c(src + m) : make_double2(0.0, 0.0);
+      const double wm = m < M ? w[m] : 0.0;
+      tr[rr][c] = wm * v.x;
+      ti[rr][c] = -wm * v.y;
+    }
+  }
+  __syncthreads();
+  // write: 32 DOF rows x 64 modes, 16 threads x 4 modes a row, 16 rows per pass
+  for (int cc = tid >> 4; cc < GM; cc += 16) {
+    const int64_t m = m0 + cc;
+    if (m >= M) continue;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = (tid & 15) * 4 + u;
+      if (i0 + r < R) {
+        Xr[m * R + i0 + r] = tr[r][cc];
+        Xi[m * R + i0 + r] = ti[r][cc];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// C = X^T (Q - qbar) with X = W conj(Phi_r): partial tile of slice s.  Grid:
+// i tiles fastest, then t tiles, then slices (the i tiles of one t tile share
+// its Q rows).  16-wide blocks of the contraction; the next block is loaded
+// into registers while the current one is multiplied from LDS.
+// ---------------------------------------------------------------------------
+constexpr int KR = 16;               // contraction block of the right-hand side
+
+template <typename QT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void coeff_rhs_kernel(
+    const double* __restrict__ Xr, const double* __restrict__ Xi, const QT* __restrict__ q,
+    const double* __restrict__ mean, double2* __restrict__ out, int R, int64_t M, int64_t nt,
+    int S) {
+  __shared__ double Ar[KR][TILE], Ai[KR][TILE], Bq[KR][TILE];
   const int Ti = (R + TILE - 1) / TILE;
   const int64_t Tt = (nt + TILE - 1) / TILE;
   const int64_t b = blockIdx.x;
@@ -79,11 +128,34 @@ __global__ __launch_bounds__(256) void coeff_rhs_kernel(const CT* __restrict__ p
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
 
-  // loaders: A: row tid/4, four consecutive m; B: k tid/16, four consecutive t
-  const int a_row = tid >> 2, a_m = (tid & 3) * 4;
-  const bool a_live = i0 + a_row < R;
-  const CT* a_src = phi + (a_live ? sel_row(sel, i0 + a_row) * M : 0);
-  const int b_k = tid >> 4, b_t = (tid & 15) * 4;
+  // loaders (16 threads per row of 64): row k = tid/16, four consecutive columns
+  const int ld_k = tid >> 4, ld_c4 = (tid & 15) * 4;
+  const bool i_full = i0 + TILE <= R, t_full = t0 + TILE <= nt;
+
+  double ra[4], rai[4], rb[4];
+  auto fetch = [&](int64_t m0) {
+    const int64_t m = m0 + ld_k;
+    const bool ml = m < m_end;
+    const double* xr = Xr + (ml ? m : 0) * R + i0 + ld_c4;
+    const double* xi = Xi + (ml ? m : 0) * R + i0 + ld_c4;
+    const double mu = ml ? mean[m] : 0.0;
+    const QT* qr = q + (ml ? m : 0) * nt + t0 + ld_c4;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const bool il = ml && (i_full || i0 + ld_c4 + u < R);
+      ra[u] = il ? xr[u] : 0.0;
+      rai[u] = il ? xi[u] : 0.0;
+      rb[u] = (ml && (t_full || t0 + ld_c4 + u < nt)) ? (double)qr[u] - mu : 0.0;
+    }
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      Ar[ld_k][ld_c4 + u] = ra[u];
+      Ai[ld_k][ld_c4 + u] = rai[u];
+      Bq[ld_k][ld_c4 + u] = rb[u];
+    }
+  };
 
   v4d accR[2][2], accI[2][2];
 #pragma unroll
@@ -91,32 +163,14 @@ __global__ __launch_bounds__(256) void coeff_rhs_kernel(const CT* __restrict__ p
 #pragma unroll
     for (int y = 0; y < 2; ++y) accR[x][y] = accI[x][y] = v4d{0, 0, 0, 0};
 
-  for (int64_t m0 = m_beg; m0 < m_end; m0 += KB) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int64_t m = m0 + a_m + u;
-      double2 v = make_double2(0.0, 0.0);
-      double wm = 0.0;
-      if (a_live && m < m_end) {
-        v = ld_c(a_src + m);
-        wm = w[m];
-      }
-      Ar[a_m + u][a_row] = wm * v.x;
-      Ai[a_m + u][a_row] = -wm * v.y;     // conj(phi)
-    }
-    {
-      const int64_t m = m0 + b_k;
-      const bool mlive = m < m_end;
-      const double mu = mlive ? mean[m] : 0.0;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int64_t t = t0 + b_t + u;
-        Bq[b_k][b_t + u] = (mlive && t < nt) ? (double)q[m * nt + t] - mu : 0.0;
-      }
-    }
+  if (m_beg < m_end) fetch(m_beg);
+  for (int64_t m0 = m_beg; m0 < m_end; m0 += KR) {
+    __syncthreads();                 // every wave is done with the previous block
+    stage();
     __syncthreads();
+    if (m0 + KR < m_end) fetch(m0 + KR);
 #pragma unroll
-    for (int ks = 0; ks < KB / 4; ++ks) {
+    for (int ks = 0; ks < KR / 4; ++ks) {
       const int kk = 4 * ks + (lane >> 4);
       double ar[2], ai[2], bq[2];
 #pragma unroll
@@ -133,7 +187,6 @@ __global__ __launch_bounds__(256) void coeff_rhs_kernel(const CT* __restrict__ p
           accI[x][y] = mfma(ai[x], bq[y], accI[x][y]);
         }
     }
-    __syncthreads();
   }
   double2* o = out + (int64_t)s * R * nt;
 #pragma unroll
@@ -310,45 +363,83 @@ __global__ __launch_bounds__(1024) void cholesky_kernel(double2* __restrict__ B,
     }
   }
   __syncthreads();
+  // U = L^* in the strictly upper triangle, so the back substitution reads rows
+  for (int64_t e = tid; e < (int64_t)R * R; e += blockDim.x) {
+    const int i = (int)(e / R), k = (int)(e % R);
+    if (k > i) {
+      const double2 l = B[(int64_t)k * R + i];
+      B[e] = make_double2(l.x, -l.y);
+    }
+  }
   if (tid == 0) *info = 0;
 }
 
-// A = L^{-*} L^{-1} C, one thread per column t (C overwritten), A written in
-// the output type.  With info != 0 the columns of A are zero.
+// A = L^{-*} L^{-1} C.  One workgroup per SOLVE_COLS columns of C, whose
+// unknowns live in LDS; 32 lanes share the dot product of every row (strided
+// over k, summed by shuffles).  L is read by rows: the lower triangle for the
+// forward pass, U = L^* (stored above the diagonal) for the backward pass.
+// With info != 0 the columns of A are zero.
+constexpr int SOLVE_COLS = 8;
+
 template <typename CT>
 __global__ __launch_bounds__(256) void coeff_solve_kernel(const double2* __restrict__ L,
-                                                          double2* __restrict__ C,
+                                                          const double2* __restrict__ C,
                                                           CT* __restrict__ A, int R, int64_t nt,
                                                           const int32_t* __restrict__ info) {
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (t >= nt) return;
+  extern __shared__ double2 y[];            // [R][SOLVE_COLS]
+  const int tid = threadIdx.x, col = tid >> 5, sub = tid & 31;
+  const int64_t t = (int64_t)blockIdx.x * SOLVE_COLS + col;
+  const bool live = t < nt;
   if (*info != 0) {
-    for (int i = 0; i < R; ++i) st_c(&A[(int64_t)i * nt + t], make_double2(0.0, 0.0));
+    if (live)
+      for (int i = sub; i < R; i += 32) st_c(&A[(int64_t)i * nt + t], make_double2(0.0, 0.0));
     return;
   }
-  for (int i = 0; i < R; ++i) {            // L y = c
-    double re = C[(int64_t)i * nt + t].x, im = C[(int64_t)i * nt + t].y;
-    for (int k = 0; k < i; ++k) {
-      const double2 l = L[(int64_t)i * R + k], y = C[(int64_t)k * nt + t];
-      re -= l.x * y.x - l.y * y.y;
-      im -= l.x * y.y + l.y * y.x;
+  for (int i = sub; i < R; i += 32)
+    y[i * SOLVE_COLS + col] = live ? C[(int64_t)i * nt + t] : make_double2(0.0, 0.0);
+  __syncthreads();
+  for (int i = 0; i < R; ++i) {             // L y = c
+    const double2* Li = L + (int64_t)i * R;
+    double re = 0.0, im = 0.0;
+    for (int k = sub; k < i; k += 32) {
+      const double2 l = Li[k], v = y[k * SOLVE_COLS + col];
+      re += l.x * v.x - l.y * v.y;
+      im += l.x * v.y + l.y * v.x;
     }
-    const double d = 1.0 / L[(int64_t)i * R + i].x;
-    C[(int64_t)i * nt + t] = make_double2(re * d, im * d);
-  }
-  for (int i = R - 1; i >= 0; --i) {       // L^* a = y
-    double re = C[(int64_t)i * nt + t].x, im = C[(int64_t)i * nt + t].y;
-    for (int k = i + 1; k < R; ++k) {
-      const double2 l = L[(int64_t)k * R + i], a = C[(int64_t)k * nt + t];
-      // conj(l) a
-      re -= l.x * a.x + l.y * a.y;
-      im -= l.x * a.y - l.y * a.x;
+#pragma unroll
+    for (int off = 16; off > 0; off >>= 1) {
+      re += __shfl_xor(re, off, 32);
+      im += __shfl_xor(im, off, 32);
     }
-    const double d = 1.0 / L[(int64_t)i * R + i].x;
-    const double2 a = make_double2(re * d, im * d);
-    C[(int64_t)i * nt + t] = a;
-    st_c(&A[(int64_t)i * nt + t], a);
+    if (sub == 0) {
+      const double d = 1.0 / Li[i].x;
+      const double2 c = y[i * SOLVE_COLS + col];
+      y[i * SOLVE_COLS + col] = make_double2((c.x - re) * d, (c.y - im) * d);
+    }
+    __syncthreads();
   }
+  for (int i = R - 1; i >= 0; --i) {        // L^* a = y, U = L^* row by row
+    const double2* Ui = L + (int64_t)i * R;
+    double re = 0.0, im = 0.0;
+    for (int k = i + 1 + sub; k < R; k += 32) {
+      const double2 u = Ui[k], v = y[k * SOLVE_COLS + col];
+      re += u.x * v.x - u.y * v.y;
+      im += u.x * v.y + u.y * v.x;
+    }
+#pragma unroll
+    for (int off = 16; off > 0; off >>= 1) {
+      re += __shfl_xor(re, off, 32);
+      im += __shfl_xor(im, off, 32);
+    }
+    if (sub == 0) {
+      const double d = 1.0 / Ui[i].x;
+      const double2 c = y[i * SOLVE_COLS + col];
+      y[i * SOLVE_COLS + col] = make_double2((c.x - re) * d, (c.y - im) * d);
+    }
+    __syncthreads();
+  }
+  if (live)
+    for (int i = sub; i < R; i += 32) st_c(&A[(int64_t)i * nt + t], y[i * SOLVE_COLS + col]);
 }
 
 // ---------------------------------------------------------------------------
@@ -444,8 +535,8 @@ CoeffLayout coeff_layout(const Plan& p, int R) {
   const int Ti = (R + TILE - 1) / TILE;
   const int64_t Tt = (p.nt + TILE - 1) / TILE;
   const int64_t tiles = (int64_t)Ti * Tt;
-  // about 2048 workgroups for the right-hand side, slices of >= 4096 DOFs
-  int64_t s = (2048 + tiles - 1) / tiles;
+  // about 8192 workgroups for the right-hand side, slices of >= 4096 DOFs
+  int64_t s = (8192 + tiles - 1) / tiles;
   s = std::min<int64_t>(s, std::max<int64_t>(1, p.M / 4096));
   c.S_rhs = (int)std::max<int64_t>(1, s);
   const int P = Ti * (Ti + 1) / 2;
@@ -458,7 +549,8 @@ CoeffLayout coeff_layout(const Plan& p, int R) {
   c.off_B = 0;
   c.off_C = up(sizeof(double2) * (size_t)R * R);
   c.off_part = c.off_C + up(sizeof(double2) * (size_t)R * p.nt);
-  c.bytes = c.off_part + up(std::max(rhs_part, gram_part));
+  c.off_X = c.off_part + up(std::max(rhs_part, gram_part));
+  c.bytes = c.off_X + 2 * up(sizeof(double) * (size_t)p.M * R);
   return c;
 }
 
@@ -491,30 +583,42 @@ spod_status launch_coeffs(const Plan& p, const void* q, spod_dtype dtype, const 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "mode_gram / cholesky");
 
-  // C = Phi^* W (Q - qbar)
+  // X = W conj(Phi_r) as [M][R] planes, then C = X^T (Q - qbar)
+  double* Xr = reinterpret_cast<double*>(base + c.off_X);
+  double* Xi = Xr + ((sizeof(double) * (size_t)p.M * R + 255) / 256 * 256) / sizeof(double);
+  const int64_t Tm = (p.M + GM - 1) / GM;
+  if (c128)
+    hipLaunchKernelGGL(gather_weighted_kernel<double2>, dim3((unsigned)(Ti * Tm)), dim3(256), 0, st,
+                       static_cast<const double2*>(phi), p.d_weights, sel, Xr, Xi, p.M);
+  else
+    hipLaunchKernelGGL(gather_weighted_kernel<float2>, dim3((unsigned)(Ti * Tm)), dim3(256), 0, st,
+                       static_cast<const float2*>(phi), p.d_weights, sel, Xr, Xi, p.M);
   double2* rhs = c.S_rhs > 1 ? part : Cm;
   const unsigned grid = (unsigned)((int64_t)Ti * Tt * c.S_rhs);
-#define SPOD_RHS(CT, QT)                                                                          \
-  hipLaunchKernelGGL((coeff_rhs_kernel<CT, QT>), dim3(grid), dim3(256), 0, st,                   \
-                     static_cast<const CT*>(phi), static_cast<const QT*>(q), mean, p.d_weights,   \
-                     sel, rhs, p.M, p.nt, c.S_rhs)
-  if (c128 && dtype == SPOD_F32) SPOD_RHS(double2, float);
-  else if (c128) SPOD_RHS(double2, double);
-  else if (dtype == SPOD_F32) SPOD_RHS(float2, float);
-  else SPOD_RHS(float2, double);
-#undef SPOD_RHS
+  if (dtype == SPOD_F32)
+    hipLaunchKernelGGL(coeff_rhs_kernel<float>, dim3(grid), dim3(256), 0, st, Xr, Xi,
+                       static_cast<const float*>(q), mean, rhs, R, p.M, p.nt, c.S_rhs);
+  else
+    hipLaunchKernelGGL(coeff_rhs_kernel<double>, dim3(grid), dim3(256), 0, st, Xr, Xi,
+                       static_cast<const double*>(q), mean, rhs, R, p.M, p.nt, c.S_rhs);
   if (c.S_rhs > 1) {
     const int64_t n = (int64_t)R * p.nt;
     hipLaunchKernelGGL(coeff_sum_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 8192)),
                        dim3(256), 0, st, part, Cm, n, c.S_rhs);
   }
-  const unsigned sg = (unsigned)((p.nt + 255) / 256);
-  if (c128)
-    hipLaunchKernelGGL(coeff_solve_kernel<double2>, dim3(sg), dim3(256), 0, st, B, Cm,
+  const unsigned sg = (unsigned)((p.nt + SOLVE_COLS - 1) / SOLVE_COLS);
+  const size_t lds = sizeof(double2) * (size_t)R * SOLVE_COLS;   // <= 128 KiB (R <= 1024)
+  if (c128) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&coeff_solve_kernel<double2>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(coeff_solve_kernel<double2>, dim3(sg), dim3(256), lds, st, B, Cm,
                        static_cast<double2*>(a), R, p.nt, info);
-  else
-    hipLaunchKernelGGL(coeff_solve_kernel<float2>, dim3(sg), dim3(256), 0, st, B, Cm,
+  } else {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&coeff_solve_kernel<float2>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(coeff_solve_kernel<float2>, dim3(sg), dim3(256), lds, st, B, Cm,
                        static_cast<float2*>(a), R, p.nt, info);
+  }
   e = hipGetLastError();
   return e == hipSuccess ? SPOD_OK : hip_fail(e, "coeff_rhs / solve");
 }

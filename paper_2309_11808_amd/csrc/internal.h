@@ -111,7 +111,7 @@ struct CoeffSel {
 };
 struct CoeffLayout {
   int R = 0, S_rhs = 1, S_gram = 1;   // columns, slices of M for C and for B
-  size_t off_B = 0, off_C = 0, off_part = 0, bytes = 0;
+  size_t off_B = 0, off_C = 0, off_part = 0, off_X = 0, bytes = 0;
 };
 CoeffLayout coeff_layout(const Plan& p, int R);
 spod_status launch_coeffs(const Plan& p, const void* q, spod_dtype dtype, const double* mean,
