@@ -6,6 +6,8 @@ paper's spatial split done sequentially) computes the outputs it can afford:
 the eigenvalues and modes of selected frequencies, the modes at sampled
 degrees of freedom, the means, and sampled Fourier blocks.
 """
+import time
+
 import numpy as np
 import pytest
 import torch
@@ -95,11 +97,14 @@ def era():
     rng = np.random.Generator(np.random.PCG64(13))
     rows = np.sort(rng.choice(p.M, 256, replace=False))
     q_host = p.q.cpu().numpy()
+    t = time.perf_counter()
     ref = O.spod_chunked(q_host, p.nfft, p.noverlap, weights=p.weights, n_modes=5,
                          chunk=32768, bins=bins, mode_rows=rows)
+    print(f"[era fixture] oracle bins {bins}: {time.perf_counter() - t:.0f} s", flush=True)
     # Fourier blocks of the sampled rows at every frequency (one by one)
     ref["qhat_rows"] = O.fourier_blocks(q_host[rows], p.nfft, p.noverlap, O.hann_periodic(p.nfft),
                                         ref["mean"][rows], None)
+    print("[era fixture] oracle Fourier blocks of the sampled rows done", flush=True)
     del q_host
     return p, bins, rows, ref
 
@@ -160,5 +165,67 @@ def test_era_field_out_of_core(era):
     assert int(out["info"].min()) > 0
     del out, q_host
     o.close()
+    plan.close()
+    torch.cuda.empty_cache()
+
+
+@pytest.fixture(scope="module")
+def era_modes(era):
+    """The oracle's full modes of three frequencies of the ERA-like field."""
+    p = era[0]
+    bins = [3, 8, 17]
+    q_host = p.q.cpu().numpy()
+    # the Gram pass and the modes pass separately, each printing when done
+    t = time.perf_counter()
+    ref = O.spod_chunked(q_host, p.nfft, p.noverlap, weights=p.weights, n_modes=5, chunk=32768,
+                         bins=bins, want_modes=False)
+    print(f"[era_modes fixture] oracle Gram pass: {time.perf_counter() - t:.0f} s", flush=True)
+    # the second pass of the chunked oracle: blocks again, modes row by row
+    window = O.hann_periodic(p.nfft)
+    phi = np.empty((len(bins), 5, p.M), dtype=np.complex128)
+    for c0 in range(0, p.M, 1 << 17):
+        r = slice(c0, min(p.M, c0 + (1 << 17)))
+        qh = O.fourier_blocks(q_host[r], p.nfft, p.noverlap, window, ref["mean"][r], bins)
+        phi[:, :, r], _ = O.modes(qh, ref["lam"], ref["psi"], 5, 1e-12)
+        print(f"[era_modes fixture] oracle modes to row {r.stop}: {time.perf_counter() - t:.0f} s",
+              flush=True)
+    ref["phi"] = phi
+    del q_host
+    return bins, ref
+
+
+def test_era_field_coefficients_and_reconstruction(era, era_modes):
+    """Coefficients over 15 modes (5 of 3 frequencies) of the full field, and a
+    reconstruction, by the kernels on the oracle's modes: coefficients compared
+    at 16 time columns, the reconstruction at 256 rows."""
+    from oracle import coeffs as OC
+    p, _, rows, _ = era
+    bins, ref = era_modes
+    plan = _plan(p, "fp64")
+    K, M, nt = plan.nfreq, plan.M, plan.nt
+    phi = torch.zeros((K, 5, M), dtype=torch.complex128, device="cuda")
+    phi[bins] = torch.as_tensor(ref["phi"]).cuda()
+    mean = torch.as_tensor(ref["mean"]).cuda()
+    a, info = plan.coeffs(p.q, mean, phi, bins, 5)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    cols = np.arange(0, nt, nt // 16)
+    Phi = OC.gather_modes(ref["phi"], [0, 1, 2], 5)
+    B = OC.mode_gram(Phi, p.weights)
+    rhs = OC.projection_rhs(Phi, p.weights, p.q[:, cols].cpu().double().numpy(), ref["mean"])
+    a_ref = np.linalg.solve(B, rhs)
+    err = float(np.abs(a[:, cols].cpu().numpy() - a_ref).max() / np.abs(a_ref).max())
+    print(f"era coefficients (R = 15, FP64): rel err {err:.2e} at 16 columns")
+    assert err <= 1e-12
+    # reconstruction from seeded coefficients
+    rng = np.random.Generator(np.random.PCG64(21))
+    a_in = rng.standard_normal((15, nt)) + 1j * rng.standard_normal((15, nt))
+    rec = plan.reconstruct(phi, bins, 5, torch.as_tensor(a_in).cuda(), mean, dtype=torch.float32)
+    rec_rows = rec[torch.as_tensor(rows, device="cuda")].cpu().double().numpy()
+    rec_ref = np.real(Phi[rows] @ a_in) + ref["mean"][rows, None]
+    rerr = float(np.abs(rec_rows - rec_ref).max() / np.abs(rec_ref).max())
+    print(f"era reconstruction (float32 output): rel err {rerr:.2e} at 256 rows")
+    assert rerr <= 1e-6
+    del a, rec, phi
     plan.close()
     torch.cuda.empty_cache()
