@@ -15,6 +15,10 @@
 //         with chunks of 32768 rows, `reps` times with no chunk resident and
 //         `reps` times with every chunk resident (plan of `precision`, 5
 //         modes to pinned host memory).
+// path 3: HBM reference rates of plain streaming kernels with 16-byte accesses
+//         over 16 GiB in / 32 GiB out: write only, read only, copy 1:1, and
+//         read 1 : write 2 (the transform's mix: q in, twice the bytes out)
+//         as two output streams; grids of 16384 and 65536 workgroups.
 // Prints the event timings.
 #include <hip/hip_runtime.h>
 
@@ -61,6 +65,73 @@ __global__ void copy_kernel(const float4* __restrict__ src, float4* __restrict__
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     dst[i] = src[i];
+}
+
+__global__ void write_kernel(float4* __restrict__ o, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    o[i] = make_float4((float)i, 1.f, 2.f, 3.f);
+}
+
+__global__ void read_kernel(const float4* __restrict__ a, int64_t n, float* __restrict__ sink) {
+  float s = 0.f;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float4 v = a[i];
+    s += v.x + v.y + v.z + v.w;
+  }
+  if (s == 123.456f) sink[0] = s;   // keeps the loads
+}
+
+// n float4 in, 2n float4 out as two streams: o[i] and o[n + i]
+__global__ void read1_write2_kernel(const float4* __restrict__ a, float4* __restrict__ o,
+                                    int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float4 v = a[i];
+    o[i] = v;
+    o[n + i] = make_float4(v.y, v.x, v.w, v.z);
+  }
+}
+
+static int run_rates() {
+  const int64_t n = (int64_t(16) << 30) / 16;   // 16 GiB of float4 in
+  float4 *a = nullptr, *o = nullptr;
+  float* sink = nullptr;
+  CHECK_HIP(hipMalloc(&a, 16 * (size_t)n));
+  CHECK_HIP(hipMalloc(&o, 32 * (size_t)n));
+  CHECK_HIP(hipMalloc(&sink, 64));
+  hipLaunchKernelGGL(fill_kernel, dim3(8192), dim3(256), 0, 0, reinterpret_cast<float*>(a), 4 * n,
+                     7u);
+  CHECK_HIP(hipGetLastError());
+  hipEvent_t e0, e1;
+  CHECK_HIP(hipEventCreate(&e0));
+  CHECK_HIP(hipEventCreate(&e1));
+  const char* names[] = {"write only", "read only", "copy 1:1", "read 1 : write 2"};
+  const double bytes[] = {32.0 * n, 16.0 * n, 32.0 * n, 48.0 * n};
+  for (int grid : {16384, 65536}) {
+    for (int k = 0; k < 4; ++k) {
+      float ms = 0.0f;
+      for (int r = 0; r < 3; ++r) {
+        CHECK_HIP(hipEventRecord(e0, 0));
+        if (k == 0) hipLaunchKernelGGL(write_kernel, dim3(grid), dim3(256), 0, 0, o, 2 * n);
+        if (k == 1) hipLaunchKernelGGL(read_kernel, dim3(grid), dim3(256), 0, 0, a, n, sink);
+        if (k == 2)
+          hipLaunchKernelGGL(copy_kernel, dim3(grid), dim3(256), 0, 0, a, o, n);
+        if (k == 3) hipLaunchKernelGGL(read1_write2_kernel, dim3(grid), dim3(256), 0, 0, a, o, n);
+        CHECK_HIP(hipGetLastError());
+        CHECK_HIP(hipEventRecord(e1, 0));
+        CHECK_HIP(hipEventSynchronize(e1));
+        CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
+      }
+      std::printf("grid %6d %-18s %8.3f ms %6.2f TB/s\n", grid, names[k], ms,
+                  bytes[k] / (ms * 1e-3) / 1e12);
+      std::fflush(stdout);
+    }
+  }
+  void* bufs[] = {a, o, sink};
+  for (void* b : bufs) CHECK_HIP(hipFree(b));
+  return 0;
 }
 
 static int run_path(int64_t nspace, int64_t nvar, int64_t nt, int64_t nfft, int64_t nov,
@@ -170,6 +241,11 @@ int main(int argc, char** argv) {
   int64_t* args[] = {&nspace, &nvar, &nt, &nfft, &nov, &reps, &prec, &path};
   for (int i = 1; i < argc && i <= 8; ++i) *args[i - 1] = std::atoll(argv[i]);
   const int64_t M = nspace * nvar;
+  if (path == 3) {
+    if (run_rates()) return 1;
+    std::printf("done\n");
+    return 0;
+  }
   if (path == 2) {
     if (run_ooc(nspace, nvar, nt, nfft, nov, reps, (spod_precision)prec)) return 1;
     std::printf("done\n");
