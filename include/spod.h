@@ -101,7 +101,11 @@ typedef enum {
  *             finite, >= 0, not all zero.
  * Returns SPOD_ERR_INVALID_ARG for nspace, nvar < 1; nfft < 2; noverlap outside
  * [0, nfft); nt < nfft; L < 2; a bad window or weights; out == NULL.
- * Returns SPOD_ERR_UNSUPPORTED for nfft not a power of two in [8, 1024].
+ * Returns SPOD_ERR_UNSUPPORTED for nfft outside [8, 20480].  Powers of two up
+ * to 1024 take the register-resident radix-8 transform; every other nfft (the
+ * paper's hourly records use 8760 = 2^3 3 5 73) takes a mixed-radix transform
+ * held in LDS, limited to nfft <= 10240 under SPOD_PREC_FP64 (complex128
+ * blocks) and 20480 otherwise (SPOD_ERR_UNSUPPORTED from spod_blocks_fft). */
  * Validation happens before any HIP call. */
 spod_status spod_plan_create(int64_t nspace, int64_t nvar, int64_t nt, int64_t nfft,
                              int64_t noverlap, const double* window, const double* weights,
@@ -193,8 +197,9 @@ spod_status spod_modes(spod_plan plan, const void* qhat, const double* lam, cons
  * than 1e-12 of the largest eigenvalue contribute nothing); Gram adjoint
  * 2 W Qhat G; then the adjoint of the windowed one-sided DFT, the overlap-add
  * of the blocks and the mean removal.  Modes that spod_modes zero-fills are
- * constants here.  Returns SPOD_ERR_UNSUPPORTED when nfft < 16, when the hop
- * nfft - noverlap is not nfft/4, nfft/2 or nfft, or when nblocks > 64. */
+ * constants here.  Returns SPOD_ERR_UNSUPPORTED when nfft is not a power of
+ * two in [16, 1024], when the hop nfft - noverlap is not nfft/4, nfft/2 or
+ * nfft, or when nblocks > 64. */
 spod_status spod_backward(spod_plan plan, const void* q, spod_dtype dtype, const void* qhat,
                           const double* lam, const void* psi, const double* g_lam,
                           const void* g_phi, int64_t n_modes, const int32_t* bins,

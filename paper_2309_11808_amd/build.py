@@ -26,7 +26,7 @@ LIB = os.path.join(PKG, "libspod.so")
 ARCH = "gfx950"
 
 SOURCES = ["api.cpp", "batch.cpp", "ooc.cpp", "fft.hip", "gram.hip", "eig.hip", "modes.hip",
-           "backward.hip", "coeffs.hip"]
+           "backward.hip", "coeffs.hip", "fft_general.hip"]
 
 # Packed FP32 instructions are kept out of all device code (the compiler would
 # otherwise form v_pk_* FP32 ops from ordinary float code).

@@ -166,8 +166,8 @@ spod_status spod_plan_create(int64_t nspace, int64_t nvar, int64_t nt, int64_t n
     W[m] = v;
   }
   if (!any) return fail(SPOD_ERR_INVALID_ARG, "weights are all zero");
-  if (!is_pow2(nfft) || nfft < 8 || nfft > 1024)
-    return fail(SPOD_ERR_UNSUPPORTED, "nfft must be a power of two in [8, 1024]");
+  if (nfft < 8 || nfft > SPOD_GENERAL_MAX_NFFT)
+    return fail(SPOD_ERR_UNSUPPORTED, "nfft must be in [8, 20480]");
 
   Plan* p = new (std::nothrow) Plan();
   if (!p) return fail(SPOD_ERR_ALLOC, "plan");
@@ -180,6 +180,23 @@ spod_status spod_plan_create(int64_t nspace, int64_t nvar, int64_t nt, int64_t n
   p->step = nfft - noverlap;
   p->nblocks = L;
   p->nfreq = K;
+  p->general = !(is_pow2(nfft) && nfft <= 1024);
+  {
+    int64_t n = nfft;
+    for (int64_t f : {8, 4, 2, 3, 5, 7}) {
+      while (n % f == 0 && p->radices.n < 32) {
+        p->radices.r[p->radices.n++] = (int)f;
+        n /= f;
+      }
+    }
+    for (int64_t f = 11; n > 1 && p->radices.n < 32; f += 2) {
+      while (n % f == 0 && p->radices.n < 32) {
+        p->radices.r[p->radices.n++] = (int)f;
+        n /= f;
+      }
+    }
+    if (n != 1) p->radices.n = 0;   // not reachable for nfft <= 20480 (at most 15 factors)
+  }
   p->kappa = 1.0 / std::sqrt((double)(L - 1) * sw2);
   // DFT of the window at every one-sided bin, What_k = sum_n w[n] e^{-2 pi i k n / N},
   // in long double with exact integer reduction of k*n mod N
@@ -187,14 +204,22 @@ spod_status spod_plan_create(int64_t nspace, int64_t nvar, int64_t nt, int64_t n
   {
     long double sabs = 0.0L;
     for (int64_t n = 0; n < nfft; ++n) sabs += fabsl((long double)w[n]);
+    std::vector<long double> ct(nfft), st(nfft);
+    for (int64_t t = 0; t < nfft; ++t) {
+      const long double a =
+          2.0L * 3.14159265358979323846264338327950288L * (long double)t / (long double)nfft;
+      ct[t] = cosl(a);
+      st[t] = sinl(a);
+    }
     int cnt = 0;
     for (int64_t k = 0; k < K; ++k) {
       long double re = 0.0L, im = 0.0L;
+      int64_t t = 0;                      // (k * n) mod nfft
       for (int64_t n = 0; n < nfft; ++n) {
-        const long double a = 2.0L * 3.14159265358979323846264338327950288L *
-                              (long double)((k * n) % nfft) / (long double)nfft;
-        re += (long double)w[n] * cosl(a);
-        im -= (long double)w[n] * sinl(a);
+        re += (long double)w[n] * ct[t];
+        im -= (long double)w[n] * st[t];
+        t += k;
+        if (t >= nfft) t -= nfft;
       }
       what[k] = make_double2((double)re, (double)im);
       if (cnt >= 0 && sqrtl(re * re + im * im) > 1e-12L * sabs) {
@@ -397,6 +422,7 @@ spod_status spod_backward(spod_plan plan, const void* q, spod_dtype dtype, const
       return fail(SPOD_ERR_INVALID_ARG, "g_qhat may alias qhat only without a bin selection");
   }
   if (p->nfft < 16) return fail(SPOD_ERR_UNSUPPORTED, "backward needs nfft >= 16");
+  if (p->general) return fail(SPOD_ERR_UNSUPPORTED, "backward needs a power-of-two nfft <= 1024");
   if (p->step != p->nfft && p->step != p->nfft / 2 && p->step != p->nfft / 4)
     return fail(SPOD_ERR_UNSUPPORTED, "backward needs a hop of nfft/4, nfft/2 or nfft");
   if (p->nblocks > 64) return fail(SPOD_ERR_UNSUPPORTED, "nblocks > 64");

@@ -113,7 +113,8 @@ void apply_target(Batch& b) {
 }
 
 bool fused_ok(const Plan& p) {
-  return p.n_mean_bins >= 0 && p.nfft >= 16 && p.nfft <= 512 && p.step * 2 == p.nfft;
+  return !p.general && p.n_mean_bins >= 0 && p.nfft >= 16 && p.nfft <= 512 &&
+         p.step * 2 == p.nfft;
 }
 
 template <typename It>

@@ -445,6 +445,19 @@ spod_status launch_blocks_fft(const Plan& p, const void* q, spod_dtype dtype, vo
                               double* mean, void* ws, hipStream_t st, const FftSel& fs) {
   // the mean goes to the caller's buffer, or to the start of the workspace
   double* mu = mean ? mean : static_cast<double*>(ws);
+  if (p.general) {
+    if (fs.d_sel) return fail(SPOD_ERR_UNSUPPORTED, "frequency selection needs a power-of-two nfft");
+    const int64_t mgrid = (p.M + 3) / 4;
+    if (dtype == SPOD_F32)
+      hipLaunchKernelGGL(mean_kernel<float>, dim3((unsigned)mgrid), dim3(256), 0, st,
+                         (const float*)q, mu, (int64_t)p.M, (int64_t)p.nt);
+    else
+      hipLaunchKernelGGL(mean_kernel<double>, dim3((unsigned)mgrid), dim3(256), 0, st,
+                         (const double*)q, mu, (int64_t)p.M, (int64_t)p.nt);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "mean_kernel");
+    return launch_blocks_dft_general(p, q, dtype, mu, qhat, st);
+  }
   // single pass when the window's DFT has few non-zero bins and the hop is a
   // whole number of lane strides; otherwise a separate FP64 mean pass first
   const int P = (int)(p.nfft / 8);

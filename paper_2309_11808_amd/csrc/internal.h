@@ -14,6 +14,14 @@ namespace spod {
 // --------------------------------------------------------------------------
 // plan
 // --------------------------------------------------------------------------
+// Radix factorisation of N_f for the general transform (radices 8, 4, 2, 3,
+// 5, 7, then any remaining primes in increasing order).
+struct Radices {
+  int n = 0;
+  int r[32] = {};
+};
+constexpr int SPOD_GENERAL_MAX_NFFT = 20480;   // complex64 blocks of one transform fill 160 KiB LDS
+
 struct Plan {
   int64_t nspace = 0, nvar = 0, M = 0, nt = 0, nfft = 0, noverlap = 0, step = 0;
   int64_t nblocks = 0, nfreq = 0;
@@ -32,6 +40,10 @@ struct Plan {
   int mean_bin[SPOD_MAX_MEAN_BINS] = {0, 0, 0, 0};
   double what_re[SPOD_MAX_MEAN_BINS] = {0, 0, 0, 0};
   double what_im[SPOD_MAX_MEAN_BINS] = {0, 0, 0, 0};
+
+  // N_f not a power of two in [8, 1024]: the general transform and its radices
+  bool general = false;
+  Radices radices;
 
   // options
   int max_sweeps = 40;
@@ -83,6 +95,9 @@ struct FftSel {
 spod_status launch_blocks_fft(const Plan& p, const void* q, spod_dtype dtype, void* qhat,
                               double* mean, void* ws, hipStream_t st, const FftSel& fs = FftSel{});
 // accumulate: gram += Qhat^* W Qhat instead of gram = ...
+// the transform of steps 1-2 for any N_f (mean from the FP64 mean pass)
+spod_status launch_blocks_dft_general(const Plan& p, const void* q, spod_dtype dtype,
+                                      const double* mean, void* qhat, hipStream_t st);
 spod_status launch_csd(const Plan& p, const void* qhat, void* gram, void* ws, hipStream_t st,
                        bool accumulate = false);
 spod_status launch_eig(const Plan& p, const void* gram, double* lam, void* psi, int32_t* info,

@@ -91,8 +91,7 @@ def _create(lib, nspace=16, nvar=1, nt=256, nfft=64, nov=32, window=None, weight
     (dict(weights=[1.0] * 15 + [-1.0]), N.SPOD_ERR_INVALID_ARG),
     (dict(weights=[0.0] * 16), N.SPOD_ERR_INVALID_ARG),
     (dict(weights=[1.0] * 15 + [float("inf")]), N.SPOD_ERR_INVALID_ARG),
-    (dict(nfft=48, nov=24, nt=480), N.SPOD_ERR_UNSUPPORTED),   # not a power of two
-    (dict(nfft=2048, nov=1024, nt=8192), N.SPOD_ERR_UNSUPPORTED),
+    (dict(nfft=20481, nov=0, nt=40962), N.SPOD_ERR_UNSUPPORTED),   # above the LDS transform
     (dict(nfft=4, nov=2, nt=64), N.SPOD_ERR_UNSUPPORTED),
 ])
 def test_plan_create_rejects_before_any_hip_call(lib, kw, expect):

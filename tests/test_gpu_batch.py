@@ -196,7 +196,7 @@ def test_batch_autotune_and_cache(tmp_path):
 def test_batch_rejects_bad_arguments():
     from paper_2309_11808_amd import Batch, SpodError
     with pytest.raises(SpodError) as ei:
-        Batch([{"nspace": 10, "nvar": 1, "nt": 100, "nfft": 48, "noverlap": 24}])
+        Batch([{"nspace": 10, "nvar": 1, "nt": 50000, "nfft": 24000, "noverlap": 12000}])
     assert ei.value.status == -2
     with pytest.raises(SpodError) as ei:
         Batch([{"nspace": 10, "nvar": 1, "nt": 100, "nfft": 32, "noverlap": 32}])

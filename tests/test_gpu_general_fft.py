@@ -1,0 +1,109 @@
+"""The transform for block lengths that are not powers of two (or above 1024),
+MI355X only: mixed-radix stages in LDS with a direct sum per output, against
+the FP64 oracle (whose DFT is pinned to numpy's rfft for any length).
+
+Lengths cover small primes, a large prime factor (73, as in the paper's
+8760 = 2^3 3 5 73 hourly blocks), odd N_f (K = (N_f + 1) / 2), powers of two
+above 1024, ragged M (odd: a last unpaired row) and several overlaps."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from synth import fields
+from tests import parity as PT
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible: the gpu tests need an MI355X")
+    import paper_2309_11808_amd  # noqa: F401
+    yield
+
+
+def _plan(p, precision):
+    from paper_2309_11808_amd import Plan
+    return Plan(p.nspace, p.nvar, p.nt, p.nfft, p.noverlap, weights=p.weights, precision=precision)
+
+
+CASES = [  # nfft, noverlap, M, L
+    (12, 6, 37, 6), (24, 12, 64, 5), (60, 30, 101, 4), (73, 0, 50, 3), (100, 50, 33, 4),
+    (146, 73, 20, 3), (360, 180, 17, 3), (2048, 1024, 9, 3), (730, 365, 12, 3),
+]
+
+
+@pytest.mark.parametrize("nfft,nov,M,L", CASES, ids=[f"N{c[0]}" for c in CASES])
+def test_fourier_blocks_match_oracle_fp64(nfft, nov, M, L):
+    nt = (L - 1) * (nfft - nov) + nfft + 5
+    p = fields.random_rows(M, nt, nfft, nov, seed=nfft, offset=1.5, dtype=torch.float64)
+    plan = _plan(p, "fp64")
+    assert plan.nblocks == L and plan.nfreq == nfft // 2 + 1
+    qhat, mean = plan.blocks_fft(p.q.cuda())
+    torch.cuda.synchronize()
+    ref_mean = O.temporal_mean(p.q.numpy())
+    ref = O.fourier_blocks(p.q.numpy(), nfft, nov, O.hann_periodic(nfft), ref_mean, None)
+    np.testing.assert_allclose(mean.cpu().numpy(), ref_mean, rtol=0, atol=1e-14 * 3)
+    err = PT.check_qhat(qhat.cpu().numpy(), ref, 1e-12)
+    print(f"N={nfft}: fp64 qhat rel err {err:.2e}")
+    plan.close()
+
+
+@pytest.mark.parametrize("nfft,nov,M,L", CASES[:5], ids=[f"N{c[0]}" for c in CASES[:5]])
+def test_fourier_blocks_match_oracle_complex64(nfft, nov, M, L):
+    nt = (L - 1) * (nfft - nov) + nfft + 5
+    p = fields.random_rows(M, nt, nfft, nov, seed=nfft + 1, offset=1.5, dtype=torch.float32)
+    plan = _plan(p, "bf16x4")
+    qhat, _ = plan.blocks_fft(p.q.cuda())
+    torch.cuda.synchronize()
+    q64 = p.q.double().numpy()
+    ref = O.fourier_blocks(q64, nfft, nov, O.hann_periodic(nfft), O.temporal_mean(q64), None)
+    err = PT.check_qhat(qhat.cpu().numpy(), ref, 2e-6)
+    print(f"N={nfft}: complex64 qhat rel err {err:.2e}")
+    plan.close()
+
+
+def test_hourly_year_blocks_end_to_end():
+    """N_f = 8760 (one year of hours), 50% overlap, 4 blocks: the whole path
+    against the oracle."""
+    nfft, nov, M, L = 8760, 4380, 256, 4
+    nt = (L - 1) * (nfft - nov) + nfft
+    p = fields.random_rows(M, nt, nfft, nov, seed=8760, offset=0.5, dtype=torch.float64)
+    ref = O.spod(p.q.numpy(), nfft, nov, weights=p.weights, n_modes=3)
+    plan = _plan(p, "fp64")
+    out = plan.forward(p.q.cuda(), n_modes=3)
+    torch.cuda.synchronize()
+    PT.check_eig(out["lam"], ref["lam"], rtol=1e-10, floor_rel=1e-13)
+    s, n = PT.check_modes(out["phi"], ref["phi"], ref["lam"], p.weights, ref["n_valid"],
+                          sin_tol=1e-8, elem_tol=1e-6, rel_gap=1e-6)
+    print(f"N=8760 end to end: modes compared {n}, worst sine {s:.2e}")
+    assert n > 1000
+    plan.close()
+
+
+def test_general_transform_limits():
+    from paper_2309_11808_amd import SpodError
+    p = fields.random_rows(4, 3 * 12000, 12000, 0, seed=1, dtype=torch.float64)
+    plan = _plan(p, "fp64")                     # complex128 blocks: at most 10240
+    with pytest.raises(SpodError) as ei:
+        plan.blocks_fft(p.q.cuda())
+    assert ei.value.status == -2
+    plan.close()
+    plan = _plan(p, "fp32")                     # complex64 blocks: up to 20480
+    qhat, _ = plan.blocks_fft(p.q.float().cuda())
+    torch.cuda.synchronize()
+    assert torch.isfinite(torch.view_as_real(qhat)).all()
+    plan.close()
+
+
+def test_backward_rejects_general_lengths():
+    from paper_2309_11808_amd import SpodError
+    p = fields.random_rows(16, 4 * 30 + 60, 60, 30, seed=2, dtype=torch.float64)
+    plan = _plan(p, "fp64")
+    out = plan.forward(p.q.cuda(), n_modes=2)
+    with pytest.raises(SpodError) as ei:
+        plan.backward(p.q.cuda(), out["lam"], out["psi"], g_lam=torch.ones_like(out["lam"]))
+    assert ei.value.status == -2
+    plan.close()

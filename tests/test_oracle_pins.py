@@ -58,7 +58,7 @@ def test_hann_is_scipy_periodic_hann_and_has_three_tap_spectrum():
 
 def test_dft_matrix_is_numpy_rfft():
     rng = _rng(3)
-    for n in (8, 15, 64):
+    for n in (8, 15, 64, 73, 360):
         x = rng.standard_normal((5, n))
         np.testing.assert_allclose(x @ O.dft_matrix(n), np.fft.rfft(x, axis=1), atol=1e-12)
 
