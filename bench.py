@@ -3,6 +3,7 @@
     python bench.py [--gpus 1] [--steps 10] [--warmup 3] [--precision bf16x4]
                     [--workload era|jet] [--no-fp64] [--no-cpu] [--no-diff] [--no-batch]
                     [--no-ooc] [--ooc-only] [--no-coeffs] [--coeffs-only]
+                    [--no-hourly] [--hourly-only]
 
 A step is one pass of the whole path over the resident input: temporal mean +
 windowed block FFT (spod_blocks_fft), weighted Gram (spod_csd), batched
@@ -19,8 +20,10 @@ frequencies), cos(latitude) weights; red noise plus 6 planted modes, generated
 on the device from a seed.  Prints one JSON line on stdout; progress goes to
 stderr.
 
-More measurements ride on the same line (skipped with --no-coeffs, --no-ooc,
---no-diff and --no-batch):
+More measurements ride on the same line (skipped with --no-hourly, --no-coeffs,
+--no-ooc, --no-diff and --no-batch):
+  * hourly: a block length that is not a power of two (N_f = 8760, one year of
+    hourly records, 256 x 256 grid, N_t = 39,420, L = 8), whole path;
   * coefficients: expansion coefficients (spod_coeffs) of the same field over
     the 5 leading modes of its 64 lowest frequencies (R = 320) and the
     reconstruction from them (spod_reconstruct), against FP64 MFMA peak;
@@ -379,6 +382,35 @@ def bench_out_of_core(p, precision, lam_in_memory, chunk_rows=32768, reps=2):
 FP64_PEAK_TFLOPS = 78.6
 
 
+def bench_hourly(precision, steps=3, warmup=1):
+    """A block length that is not a power of two: one year of hourly records
+    (N_f = 8760 = 2^3 3 5 73) on a 256 x 256 lat-lon grid, 4.5 years (N_t =
+    39,420 float32), 50% overlap, L = 8 blocks as in the paper's ERA5 runs."""
+    import torch
+    from synth import fields
+    nfft, nov, L = 8760, 4380, 8
+    nt = (L - 1) * (nfft - nov) + nfft
+    p = fields.era_like(seed=5, nlon=256, nlat=256, nvar=1, nt=nt, nfft=nfft, noverlap=nov,
+                        dtype=torch.float32, device="cuda")
+    r = run_path(p, precision, steps, warmup)
+    in_bytes = p.M * p.nt * 4
+    fft_ms = r["stages_ms"]["blocks_fft"]
+    alg = in_bytes + r["qhat_bytes"]
+    out = {"workload": "hourly-like: 256 x 256 x 1, N_t = 39420 float32 (4.5 years of hours), "
+                       "N_f = 8760 (one year, 2^3 3 5 73), 50% overlap, L = 8, K = 4381; "
+                       "ERA-like red noise + 6 planted modes, cos(lat) weights",
+           "precision": precision, "ms_per_step": round(r["ms_per_step"], 3),
+           "input_GBps": round(in_bytes / (r["ms_per_step"] * 1e-3) / 1e9, 2),
+           "stages_ms": {k: round(v, 3) for k, v in r["stages_ms"].items()},
+           "transform_algorithmic_GBps": round(alg / (fft_ms * 1e-3) / 1e9, 1),
+           "transform_moved_GBps": round((in_bytes * (1 + L * nfft / nt) + r["qhat_bytes"]) /
+                                         (fft_ms * 1e-3) / 1e9, 1),
+           "info_min": r["info_min"]}
+    del p
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_coeffs(p, precision, n_bins=64, n_r=5, steps=3, warmup=1):
     """Expansion coefficients and reconstruction of the main workload over the
     n_r leading modes of its n_bins lowest frequencies."""
@@ -442,6 +474,9 @@ def main(argv=None):
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-ooc", action="store_true")
     ap.add_argument("--no-coeffs", action="store_true")
+    ap.add_argument("--no-hourly", action="store_true")
+    ap.add_argument("--hourly-only", action="store_true",
+                    help="time the N_f = 8760 workload alone")
     ap.add_argument("--coeffs-only", action="store_true",
                     help="generate the workload and time the coefficients and reconstruction alone")
     ap.add_argument("--ooc-only", action="store_true",
@@ -462,6 +497,11 @@ def main(argv=None):
         return 2
     P.lib()                                   # fails loudly without libspod.so
     torch.cuda.set_device(0)
+    if a.hourly_only:
+        result = {"metric": METRIC, "value": None, "unit": "GB/s", "n_gpus": 1,
+                  "hourly": bench_hourly(a.precision, steps=max(1, a.steps))}
+        print(json.dumps(result), flush=True)
+        return 0
     if a.no_main:
         result = {"metric": METRIC, "value": None, "unit": "GB/s", "n_gpus": 1}
         if not a.no_diff:
@@ -558,6 +598,10 @@ def main(argv=None):
         log(f"out of core {result['out_of_core']}")
     del p
     torch.cuda.empty_cache()
+    if not a.no_hourly:
+        log("hourly workload (N_f = 8760)")
+        result["hourly"] = bench_hourly(a.precision)
+        log(f"hourly {result['hourly']}")
     if not a.no_diff:
         log("differentiation workload")
         result["differentiation"] = bench_differentiation(max(3, a.steps // 2), 1)

@@ -105,8 +105,9 @@ typedef enum {
  * to 1024 take the register-resident radix-8 transform; every other nfft (the
  * paper's hourly records use 8760 = 2^3 3 5 73) takes a mixed-radix transform
  * held in LDS, limited to nfft <= 10240 under SPOD_PREC_FP64 (complex128
- * blocks) and 20480 otherwise (SPOD_ERR_UNSUPPORTED from spod_blocks_fft). */
- * Validation happens before any HIP call. */
+ * blocks) and about 20400 otherwise (the block and its stage twiddles share
+ * 160 KiB of LDS), and to prime factors up to 1024 (SPOD_ERR_UNSUPPORTED from
+ * spod_blocks_fft).  Validation happens before any HIP call. */
 spod_status spod_plan_create(int64_t nspace, int64_t nvar, int64_t nt, int64_t nfft,
                              int64_t noverlap, const double* window, const double* weights,
                              spod_plan* out);

@@ -10,7 +10,10 @@
 // radix r with current length n and stride s maps
 //   y[q + s (r p + k)] = W_n^{p k} sum_j x[q + s (p + j n / r)] W_r^{j k},
 // every output a direct radix-r sum (so a prime factor such as 73 needs no
-// special case), all twiddles taken from the plan's table W_N^t.  A thread
+// special case), the W_r^t of every stage copied from the plan's table W_N^t
+// into LDS (at most the sum of the radices, 89 values for 8760).  For an odd
+// radix one work item yields the outputs k and r - k from (r - 1) / 2 terms
+// of the symmetric sums, a quarter of the multiplications.  A thread
 // computes its outputs of a stage into registers, the workgroup synchronises,
 // and the outputs overwrite the inputs in LDS.  The mean comes from the FP64
 // mean pass.  Consecutive workgroups of one XCD take consecutive pairs of the
@@ -35,14 +38,97 @@ __device__ __forceinline__ cpx_t<TC> mk(TC x, TC y) {
   return c;
 }
 
-template <typename TC, typename TIN, int MAXU>
+// One output of an even-radix stage: y[o] = W_n^{p k} sum_j x[q + s(p + j m)] W_r^{j k}
+// (four independent partial sums, t = j k mod r).
+template <typename TC>
+__device__ __forceinline__ cpx_t<TC> even_output(const cpx_t<TC>* __restrict__ X,
+                                                 const cpx_t<TC>* __restrict__ Wr,
+                                                 const cpx_t<TC>* __restrict__ tw, int o, int r,
+                                                 int s, int m, int wn, int N) {
+  using C = cpx_t<TC>;
+  const int qq = o % s, rest = o / s;
+  const int k = rest % r, pp = rest / r;
+  const int base = qq + s * pp, js = s * m;
+  TC ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
+  int j = 0, t = 0;
+  for (; j + 4 <= r; j += 4) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const C xv = X[base + (j + v) * js];
+      const C wv = Wr[t];
+      ar[v] += xv.x * wv.x - xv.y * wv.y;
+      ai[v] += xv.x * wv.y + xv.y * wv.x;
+      t += k;
+      if (t >= r) t -= r;
+    }
+  }
+  for (; j < r; ++j) {
+    const C xv = X[base + j * js];
+    const C wv = Wr[t];
+    ar[0] += xv.x * wv.x - xv.y * wv.y;
+    ai[0] += xv.x * wv.y + xv.y * wv.x;
+    t += k;
+    if (t >= r) t -= r;
+  }
+  const TC sr = (ar[0] + ar[1]) + (ar[2] + ar[3]), si = (ai[0] + ai[1]) + (ai[2] + ai[3]);
+  const C t2 = tw[(int)(((int64_t)wn * pp * k) % N)];
+  return mk<TC>(sr * t2.x - si * t2.y, sr * t2.y + si * t2.x);
+}
+
+// Work item it of an odd-radix stage: with a_j = x_j + x_{r-j}, b_j =
+// x_j - x_{r-j} and W_r^{jk} = c - i s, the outputs k and r - k share the sums
+// A = sum_{j <= (r-1)/2} a_j c and B = sum b_j s:  y_k = x_0 + A - i B,
+// y_{r-k} = x_0 + A + i B (then W_n^{p k}, W_n^{p(r-k)}).  kk = it / NB in
+// [0, (r-1)/2]; consecutive items are consecutive butterflies.
+template <typename TC>
+__device__ __forceinline__ void odd_pair(const cpx_t<TC>* __restrict__ X,
+                                         const cpx_t<TC>* __restrict__ Wr,
+                                         const cpx_t<TC>* __restrict__ tw, int it, int NB, int r,
+                                         int s, int m, int wn, int N, cpx_t<TC>& y0,
+                                         cpx_t<TC>& y1, int& o0, int& o1) {
+  using C = cpx_t<TC>;
+  const int kk = it / NB, bf = it - kk * NB;
+  const int qq = bf % s, pp = bf / s;
+  const int base = qq + s * pp, js = s * m;
+  const C x0 = X[base];
+  TC Ar = 0, Ai = 0, Br = 0, Bi = 0;
+  int t = 0;
+  for (int j = 1; 2 * j < r; ++j) {
+    t += kk;
+    if (t >= r) t -= r;
+    const C xa = X[base + j * js], xb = X[base + (r - j) * js];
+    const C w = Wr[t];
+    const TC c = w.x, sn = -w.y;
+    Ar += (xa.x + xb.x) * c;
+    Ai += (xa.y + xb.y) * c;
+    Br += (xa.x - xb.x) * sn;
+    Bi += (xa.y - xb.y) * sn;
+  }
+  const TC ykr = x0.x + Ar + Bi, yki = x0.y + Ai - Br;
+  const TC yrr = x0.x + Ar - Bi, yri = x0.y + Ai + Br;
+  const C t0 = tw[(int)(((int64_t)wn * pp * kk) % N)];
+  const C t1 = tw[(int)(((int64_t)wn * pp * (r - kk)) % N)];
+  y0 = mk<TC>(ykr * t0.x - yki * t0.y, ykr * t0.y + yki * t0.x);
+  y1 = mk<TC>(yrr * t1.x - yri * t1.y, yrr * t1.y + yri * t1.x);
+  o0 = qq + s * (r * pp + kk);
+  o1 = kk > 0 ? qq + s * (r * pp + r - kk) : -1;
+}
+
+// PP: two LDS buffers, every stage reads one and writes the other (no
+// staging registers).  Otherwise one buffer: a thread computes its outputs of
+// a stage into registers (MAXU outputs of an even-radix stage, MAXI pairs of
+// an odd one, (N / r)(r + 1) / 2 <= 2N / 3 items), the workgroup synchronises,
+// and the outputs overwrite the inputs.
+template <typename TC, typename TIN, bool PP, int MAXU, int MAXI = (2 * MAXU + 2) / 3>
 __global__ __launch_bounds__(GEN_THREADS) void blocks_dft_general_kernel(
     const TIN* __restrict__ q, const double* __restrict__ mean, const double* __restrict__ window,
     const cpx_t<TC>* __restrict__ tw, cpx_t<TC>* __restrict__ qhat, int64_t M, int64_t nt, int N,
     int step, int L, int K, TC kappa, Radices rad, int64_t per_xcd) {
   using C = cpx_t<TC>;
   extern __shared__ unsigned char smem[];
-  C* T = reinterpret_cast<C*>(smem);
+  C* X = reinterpret_cast<C*>(smem);
+  C* Y = PP ? X + N : X;
+  C* Wt = X + (PP ? 2 * N : N);  // per stage: W_r^t, t < r, stage after stage
   const int64_t b = blockIdx.x;
   const int64_t x = b >> 3, xcd = b & 7;
   const int64_t l = x / per_xcd;
@@ -53,6 +139,14 @@ __global__ __launch_bounds__(GEN_THREADS) void blocks_dft_general_kernel(
   const bool two = m0 + 1 < M;
   const int tid = threadIdx.x;
 
+  {
+    int off = 0;
+    for (int st = 0; st < rad.n; ++st) {
+      const int r = rad.r[st];
+      for (int t = tid; t < r; t += GEN_THREADS) Wt[off + t] = tw[(N / r) * t];
+      off += r;
+    }
+  }
   // windowed, mean-free samples of both rows as one complex sequence
   {
     const double mu0 = mean[m0], mu1 = two ? mean[m0 + 1] : 0.0;
@@ -62,56 +156,80 @@ __global__ __launch_bounds__(GEN_THREADS) void blocks_dft_general_kernel(
       const double w = window[n];
       const double a = ((double)r0[n] - mu0) * w;
       const double c = two ? ((double)r1[n] - mu1) * w : 0.0;
-      T[n] = mk<TC>((TC)a, (TC)c);
+      X[n] = mk<TC>((TC)a, (TC)c);
     }
   }
   __syncthreads();
 
-  int n = N, s = 1;
+  int n = N, s = 1, off = 0;
   for (int st = 0; st < rad.n; ++st) {
     const int r = rad.r[st];
     const int m = n / r;
-    const int wr = N / r;          // W_r = W_N^(N/r)
     const int wn = N / n;          // W_n = W_N^(N/n)
-    C y[MAXU];
-#pragma unroll
-    for (int u = 0; u < MAXU; ++u) {
-      const int o = tid + u * GEN_THREADS;
-      if (o < N) {
-        const int qq = o % s, rest = o / s;
-        const int k = rest % r, pp = rest / r;
-        const int base = qq + s * pp, js = s * m;
-        const int wstep = (int)(((int64_t)wr * k) % N);
-        TC ar = 0, ai = 0;
-        int wi = 0;
-        for (int j = 0; j < r; ++j) {
-          const C xv = T[base + j * js];
-          const C wv = tw[wi];
-          ar += xv.x * wv.x - xv.y * wv.y;
-          ai += xv.x * wv.y + xv.y * wv.x;
-          wi += wstep;
-          if (wi >= N) wi -= N;
+    const C* Wr = Wt + off;
+    if constexpr (PP) {
+      if (r % 2 == 1) {
+        const int NB = N / r, items = NB * ((r + 1) / 2);
+        for (int it = tid; it < items; it += GEN_THREADS) {
+          C y0, y1;
+          int o0, o1;
+          odd_pair<TC>(X, Wr, tw, it, NB, r, s, m, wn, N, y0, y1, o0, o1);
+          Y[o0] = y0;
+          if (o1 >= 0) Y[o1] = y1;
         }
-        const C t2 = tw[(int)(((int64_t)wn * pp * k) % N)];
-        y[u] = mk<TC>(ar * t2.x - ai * t2.y, ar * t2.y + ai * t2.x);
+      } else {
+        for (int o = tid; o < N; o += GEN_THREADS) Y[o] = even_output<TC>(X, Wr, tw, o, r, s, m, wn, N);
       }
-    }
-    __syncthreads();
+      __syncthreads();
+      C* tmp = X;
+      X = Y;
+      Y = tmp;
+    } else {
+      if (r % 2 == 1) {
+        const int NB = N / r, items = NB * ((r + 1) / 2);
+        C y0[MAXI], y1[MAXI];
+        int o0[MAXI], o1[MAXI];
 #pragma unroll
-    for (int u = 0; u < MAXU; ++u) {
-      const int o = tid + u * GEN_THREADS;
-      if (o < N) T[o] = y[u];
+        for (int u = 0; u < MAXI; ++u) {
+          const int it = tid + u * GEN_THREADS;
+          o0[u] = -1;
+          if (it < items) odd_pair<TC>(X, Wr, tw, it, NB, r, s, m, wn, N, y0[u], y1[u], o0[u], o1[u]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < MAXI; ++u) {
+          if (o0[u] >= 0) {
+            X[o0[u]] = y0[u];
+            if (o1[u] >= 0) X[o1[u]] = y1[u];
+          }
+        }
+      } else {
+        C y[MAXU];
+#pragma unroll
+        for (int u = 0; u < MAXU; ++u) {
+          const int o = tid + u * GEN_THREADS;
+          if (o < N) y[u] = even_output<TC>(X, Wr, tw, o, r, s, m, wn, N);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < MAXU; ++u) {
+          const int o = tid + u * GEN_THREADS;
+          if (o < N) X[o] = y[u];
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
     n = m;
     s *= r;
+    off += r;
   }
 
   // two-for-one split: A = (Z_k + conj Z_{N-k}) / 2, C = (Z_k - conj Z_{N-k}) / 2i
+  const C* Z = X;
   const TC h = (TC)0.5 * kappa;
   const bool vec = two && (M % 2 == 0);        // 16-byte aligned pair (m0 even)
   for (int k = tid; k < K; k += GEN_THREADS) {
-    const C z = T[k], zc = T[k == 0 ? 0 : N - k];
+    const C z = Z[k], zc = Z[k == 0 ? 0 : N - k];
     const C a = mk<TC>(h * (z.x + zc.x), h * (z.y - zc.y));
     const C c = mk<TC>(h * (z.y + zc.y), h * (zc.x - z.x));
     C* dst = qhat + ((int64_t)k * L + l) * M + m0;
@@ -126,12 +244,11 @@ __global__ __launch_bounds__(GEN_THREADS) void blocks_dft_general_kernel(
   }
 }
 
-template <typename TC, typename TIN, int MAXU>
-spod_status launch_general_t(const Plan& p, const TIN* q, const double* mean, void* qhat,
-                             hipStream_t st) {
+template <typename TC, typename TIN, bool PP, int MAXU>
+spod_status launch_general_pp(const Plan& p, const TIN* q, const double* mean, void* qhat,
+                              size_t lds, hipStream_t st) {
   using C = cpx_t<TC>;
-  const size_t lds = sizeof(C) * (size_t)p.nfft;
-  const void* fn = reinterpret_cast<const void*>(&blocks_dft_general_kernel<TC, TIN, MAXU>);
+  const void* fn = reinterpret_cast<const void*>(&blocks_dft_general_kernel<TC, TIN, PP, MAXU>);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
   const int64_t P = (p.M + 1) / 2;
@@ -139,12 +256,27 @@ spod_status launch_general_t(const Plan& p, const TIN* q, const double* mean, vo
   const int64_t wgs = 8 * per_xcd * p.nblocks;
   if (wgs > 0x7fffffffLL) return fail(SPOD_ERR_UNSUPPORTED, "general transform grid too large");
   const C* tw = static_cast<const C*>(sizeof(TC) == 8 ? (const void*)p.d_tw64 : (const void*)p.d_tw32);
-  hipLaunchKernelGGL((blocks_dft_general_kernel<TC, TIN, MAXU>), dim3((unsigned)wgs),
+  hipLaunchKernelGGL((blocks_dft_general_kernel<TC, TIN, PP, MAXU>), dim3((unsigned)wgs),
                      dim3(GEN_THREADS), lds, st, q, mean, p.d_window, tw, static_cast<C*>(qhat),
                      (int64_t)p.M, (int64_t)p.nt, (int)p.nfft, (int)p.step, (int)p.nblocks,
                      (int)p.nfreq, (TC)p.kappa, p.radices, per_xcd);
   e = hipGetLastError();
   return e == hipSuccess ? SPOD_OK : hip_fail(e, "blocks_dft_general_kernel");
+}
+
+template <typename TC, typename TIN, int MAXU>
+spod_status launch_general_t(const Plan& p, const TIN* q, const double* mean, void* qhat,
+                             hipStream_t st) {
+  using C = cpx_t<TC>;
+  int sum_r = 0;
+  for (int i = 0; i < p.radices.n; ++i) sum_r += p.radices.r[i];
+  constexpr size_t LDS_MAX = 160 * 1024;
+  const size_t two_buf = sizeof(C) * (2 * (size_t)p.nfft + (size_t)sum_r);
+  if (two_buf <= LDS_MAX) return launch_general_pp<TC, TIN, true, 1>(p, q, mean, qhat, two_buf, st);
+  const size_t one_buf = sizeof(C) * ((size_t)p.nfft + (size_t)sum_r);
+  if (one_buf > LDS_MAX)
+    return fail(SPOD_ERR_UNSUPPORTED, "block and twiddles exceed the 160 KiB of LDS");
+  return launch_general_pp<TC, TIN, false, MAXU>(p, q, mean, qhat, one_buf, st);
 }
 
 }  // namespace
@@ -156,6 +288,9 @@ spod_status launch_blocks_dft_general(const Plan& p, const void* q, spod_dtype d
     return fail(SPOD_ERR_UNSUPPORTED, c128 ? "nfft above 10240 with complex128 blocks"
                                            : "nfft above 20480");
   if (p.radices.n <= 0) return fail(SPOD_ERR_UNSUPPORTED, "nfft has no radix factorisation");
+  for (int i = 0; i < p.radices.n; ++i)
+    if (p.radices.r[i] > 1024)
+      return fail(SPOD_ERR_UNSUPPORTED, "nfft has a prime factor above 1024");
   constexpr int UF = (SPOD_GENERAL_MAX_NFFT + GEN_THREADS - 1) / GEN_THREADS;
   constexpr int UD = (SPOD_GENERAL_MAX_NFFT / 2 + GEN_THREADS - 1) / GEN_THREADS;
   if (dtype == SPOD_F32)
