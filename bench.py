@@ -133,6 +133,7 @@ def run_path(p, precision, steps, warmup, n_modes=5):
         step()
     torch.cuda.synchronize()
     stage = [0.0, 0.0, 0.0, 0.0]
+    per_step = []
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -145,12 +146,14 @@ def run_path(p, precision, steps, warmup, n_modes=5):
         ev[4].synchronize()
         for i in range(4):
             stage[i] += ev[i].elapsed_time(ev[i + 1])
+        per_step.append(ev[0].elapsed_time(ev[4]))
     t1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     total_ms = t0.elapsed_time(t1)
     out = {
         "ms_per_step": total_ms / steps,
+        "median_ms_per_step": sorted(per_step)[len(per_step) // 2],
         "wall_s": wall,
         "stages_ms": {n: s / steps for n, s in zip(("blocks_fft", "csd", "eig", "modes"), stage)},
         "lam": lam.cpu(),
@@ -560,7 +563,18 @@ def main(argv=None):
                                                         a.precision == "bf16x4") else None,
                      "algorithmic_bytes_per_launch": fft_bytes},
         "checks": {"jacobi_info_min": mixed["info_min"], "n_valid_min": mixed["n_valid_min"]},
+        "median_ms_per_step": round(mixed["median_ms_per_step"], 4),
     }
+    # the whole path against the HBM floor of the materialised-Fourier-block
+    # design: q read once, qhat written once and read twice (Gram, modes),
+    # the modes written once
+    path_bytes = in_bytes + 3 * mixed["qhat_bytes"] + mixed["phi_bytes"]
+    ceiling = in_bytes / (path_bytes / (HBM_PEAK_GBS * 1e9)) / 1e9
+    result["path_roofline"] = {"bytes_per_step": path_bytes,
+                               "input_GBps_ceiling_at_8TBps": round(ceiling, 1),
+                               "frac": round(value / ceiling, 4),
+                               "achieved_GBps_of_path_bytes": round(path_bytes /
+                                                                    (mixed["ms_per_step"] * 1e-3) / 1e9, 1)}
     if fp64 is not None:
         lf, lm = fp64["lam"].numpy()[:, :5], mixed["lam"].numpy()[:, :5]
         err = float(np.max(np.abs(lm - lf) / np.maximum(np.abs(lf), 1e-300)))
