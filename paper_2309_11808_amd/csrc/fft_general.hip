@@ -3,8 +3,8 @@
 // not a power of two or is above the register-resident transform's 1024 (the
 // paper's hourly data use N_f = 8760 = 2^3 3 5 73).
 //
-// One workgroup of 1024 threads owns one pair of degrees of freedom and one
-// block: the two real rows are packed as a + i c, transformed once, and split
+// One workgroup of 1024 threads owns one pair of degrees of freedom: the two
+// real rows are packed as a + i c, transformed once, and split
 // with the two-for-one identity.  The transform is a self-sorting mixed-radix
 // one (decimation in frequency) held in LDS: for N = r_0 r_1 ... the stage of
 // radix r with current length n and stride s maps
@@ -16,9 +16,10 @@
 // of the symmetric sums, a quarter of the multiplications.  A thread
 // computes its outputs of a stage into registers, the workgroup synchronises,
 // and the outputs overwrite the inputs in LDS.  The mean comes from the FP64
-// mean pass.  Consecutive workgroups of one XCD take consecutive pairs of the
-// same block, so their 16-byte stores of neighbouring degrees of freedom
-// meet in that XCD's L2.
+// mean pass.  A workgroup takes the blocks of its pair in turn, loading the
+// next block while it transforms the current one.  Consecutive workgroups of
+// one XCD take consecutive pairs, so their 16-byte stores of neighbouring
+// degrees of freedom meet in that XCD's L2.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -36,6 +37,18 @@ __device__ __forceinline__ cpx_t<TC> mk(TC x, TC y) {
   c.x = x;
   c.y = y;
   return c;
+}
+
+// Workgroup barrier for LDS traffic only: every wave's LDS reads and writes
+// are complete, while its global loads (the next block's samples) may still
+// be in flight (__syncthreads would wait for those too).  The compiler fences
+// keep LDS accesses from moving across it.
+__device__ __forceinline__ void lds_barrier() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(15 | (3 << 14) | (7 << 4) | (0 << 8));   // lgkmcnt(0) only
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_sched_barrier(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
 // One output of an even-radix stage: y[o] = W_n^{p k} sum_j x[q + s(p + j m)] W_r^{j k}
@@ -118,23 +131,24 @@ __device__ __forceinline__ void odd_pair(const cpx_t<TC>* __restrict__ X,
 // staging registers).  Otherwise one buffer: a thread computes its outputs of
 // a stage into registers (MAXU outputs of an even-radix stage, MAXI pairs of
 // an odd one, (N / r)(r + 1) / 2 <= 2N / 3 items), the workgroup synchronises,
-// and the outputs overwrite the inputs.
-template <typename TC, typename TIN, bool PP, int MAXU, int MAXI = (2 * MAXU + 2) / 3>
+// and the outputs overwrite the inputs.  A workgroup takes every block of its
+// pair in turn; with PP the samples of the next block are loaded into
+// registers (MAXR per thread and row) while the current one is transformed.
+template <typename TC, typename TIN, bool PP, int MAXU, int MAXI = (2 * MAXU + 2) / 3,
+          int MAXR = PP ? MAXU : 1>
 __global__ __launch_bounds__(GEN_THREADS) void blocks_dft_general_kernel(
     const TIN* __restrict__ q, const double* __restrict__ mean, const double* __restrict__ window,
     const cpx_t<TC>* __restrict__ tw, cpx_t<TC>* __restrict__ qhat, int64_t M, int64_t nt, int N,
     int step, int L, int K, TC kappa, Radices rad, int64_t per_xcd) {
   using C = cpx_t<TC>;
   extern __shared__ unsigned char smem[];
-  C* X = reinterpret_cast<C*>(smem);
-  C* Y = PP ? X + N : X;
-  C* Wt = X + (PP ? 2 * N : N);  // per stage: W_r^t, t < r, stage after stage
+  C* const B0 = reinterpret_cast<C*>(smem);
+  C* const B1 = PP ? B0 + N : B0;
+  C* Wt = B0 + (PP ? 2 * N : N);  // per stage: W_r^t, t < r, stage after stage
   const int64_t b = blockIdx.x;
-  const int64_t x = b >> 3, xcd = b & 7;
-  const int64_t l = x / per_xcd;
-  const int64_t pair = xcd * per_xcd + x % per_xcd;
+  const int64_t pair = (b & 7) * per_xcd + (b >> 3);   // consecutive pairs on one XCD
   const int64_t P = (M + 1) / 2;
-  if (pair >= P || l >= L) return;             // the same for every thread
+  if (pair >= P) return;                       // the same for every thread
   const int64_t m0 = 2 * pair;
   const bool two = m0 + 1 < M;
   const int tid = threadIdx.x;
@@ -147,100 +161,140 @@ __global__ __launch_bounds__(GEN_THREADS) void blocks_dft_general_kernel(
       off += r;
     }
   }
-  // windowed, mean-free samples of both rows as one complex sequence
-  {
-    const double mu0 = mean[m0], mu1 = two ? mean[m0 + 1] : 0.0;
-    const TIN* r0 = q + m0 * nt + l * step;
-    const TIN* r1 = q + (two ? m0 + 1 : m0) * nt + l * step;
-    for (int n = tid; n < N; n += GEN_THREADS) {
-      const double w = window[n];
-      const double a = ((double)r0[n] - mu0) * w;
-      const double c = two ? ((double)r1[n] - mu1) * w : 0.0;
-      X[n] = mk<TC>((TC)a, (TC)c);
+  const double mu0 = mean[m0], mu1 = two ? mean[m0 + 1] : 0.0;
+  const TIN* r0 = q + m0 * nt;
+  const TIN* r1 = q + (two ? m0 + 1 : m0) * nt;
+  TIN pa[MAXR], pb[MAXR];                      // the next block's samples (PP)
+  if constexpr (PP) {
+#pragma unroll
+    for (int u = 0; u < MAXR; ++u) {
+      const int n = tid + u * GEN_THREADS;
+      pa[u] = n < N ? r0[n] : (TIN)0;
+      pb[u] = n < N ? r1[n] : (TIN)0;
     }
   }
-  __syncthreads();
-
-  int n = N, s = 1, off = 0;
-  for (int st = 0; st < rad.n; ++st) {
-    const int r = rad.r[st];
-    const int m = n / r;
-    const int wn = N / n;          // W_n = W_N^(N/n)
-    const C* Wr = Wt + off;
-    if constexpr (PP) {
-      if (r % 2 == 1) {
-        const int NB = N / r, items = NB * ((r + 1) / 2);
-        for (int it = tid; it < items; it += GEN_THREADS) {
-          C y0, y1;
-          int o0, o1;
-          odd_pair<TC>(X, Wr, tw, it, NB, r, s, m, wn, N, y0, y1, o0, o1);
-          Y[o0] = y0;
-          if (o1 >= 0) Y[o1] = y1;
-        }
-      } else {
-        for (int o = tid; o < N; o += GEN_THREADS) Y[o] = even_output<TC>(X, Wr, tw, o, r, s, m, wn, N);
-      }
-      __syncthreads();
-      C* tmp = X;
-      X = Y;
-      Y = tmp;
-    } else {
-      if (r % 2 == 1) {
-        const int NB = N / r, items = NB * ((r + 1) / 2);
-        C y0[MAXI], y1[MAXI];
-        int o0[MAXI], o1[MAXI];
-#pragma unroll
-        for (int u = 0; u < MAXI; ++u) {
-          const int it = tid + u * GEN_THREADS;
-          o0[u] = -1;
-          if (it < items) odd_pair<TC>(X, Wr, tw, it, NB, r, s, m, wn, N, y0[u], y1[u], o0[u], o1[u]);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < MAXI; ++u) {
-          if (o0[u] >= 0) {
-            X[o0[u]] = y0[u];
-            if (o1[u] >= 0) X[o1[u]] = y1[u];
-          }
-        }
-      } else {
-        C y[MAXU];
-#pragma unroll
-        for (int u = 0; u < MAXU; ++u) {
-          const int o = tid + u * GEN_THREADS;
-          if (o < N) y[u] = even_output<TC>(X, Wr, tw, o, r, s, m, wn, N);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < MAXU; ++u) {
-          const int o = tid + u * GEN_THREADS;
-          if (o < N) X[o] = y[u];
-        }
-      }
-      __syncthreads();
-    }
-    n = m;
-    s *= r;
-    off += r;
-  }
-
-  // two-for-one split: A = (Z_k + conj Z_{N-k}) / 2, C = (Z_k - conj Z_{N-k}) / 2i
-  const C* Z = X;
   const TC h = (TC)0.5 * kappa;
   const bool vec = two && (M % 2 == 0);        // 16-byte aligned pair (m0 even)
-  for (int k = tid; k < K; k += GEN_THREADS) {
-    const C z = Z[k], zc = Z[k == 0 ? 0 : N - k];
-    const C a = mk<TC>(h * (z.x + zc.x), h * (z.y - zc.y));
-    const C c = mk<TC>(h * (z.y + zc.y), h * (zc.x - z.x));
-    C* dst = qhat + ((int64_t)k * L + l) * M + m0;
-    if constexpr (sizeof(TC) == 4) {
-      if (vec) {
-        *reinterpret_cast<float4*>(dst) = make_float4(a.x, a.y, c.x, c.y);
-        continue;
+
+  for (int l = 0; l < L; ++l) {
+    C* X = B0;
+    C* Y = B1;
+    // windowed, mean-free samples of both rows as one complex sequence
+    if constexpr (PP) {
+#pragma unroll
+      for (int u = 0; u < MAXR; ++u) {
+        const int n = tid + u * GEN_THREADS;
+        if (n < N) {
+          const double w = window[n];
+          X[n] = mk<TC>((TC)(((double)pa[u] - mu0) * w),
+                        (TC)(two ? ((double)pb[u] - mu1) * w : 0.0));
+        }
+      }
+      if (l + 1 < L) {
+        const int64_t o = (int64_t)(l + 1) * step;
+#pragma unroll
+        for (int u = 0; u < MAXR; ++u) {
+          const int n = tid + u * GEN_THREADS;
+          pa[u] = n < N ? r0[o + n] : (TIN)0;
+          pb[u] = n < N ? r1[o + n] : (TIN)0;
+        }
+      }
+    } else {
+      const int64_t o = (int64_t)l * step;
+      for (int n = tid; n < N; n += GEN_THREADS) {
+        const double w = window[n];
+        const double a = ((double)r0[o + n] - mu0) * w;
+        const double c = two ? ((double)r1[o + n] - mu1) * w : 0.0;
+        X[n] = mk<TC>((TC)a, (TC)c);
       }
     }
-    dst[0] = a;
-    if (two) dst[1] = c;
+    if constexpr (PP) lds_barrier();
+    else __syncthreads();
+
+    int n = N, s = 1, off = 0;
+    for (int st = 0; st < rad.n; ++st) {
+      const int r = rad.r[st];
+      const int m = n / r;
+      const int wn = N / n;          // W_n = W_N^(N/n)
+      const C* Wr = Wt + off;
+      if constexpr (PP) {
+        if (r % 2 == 1) {
+          const int NB = N / r, items = NB * ((r + 1) / 2);
+          for (int it = tid; it < items; it += GEN_THREADS) {
+            C y0, y1;
+            int o0, o1;
+            odd_pair<TC>(X, Wr, tw, it, NB, r, s, m, wn, N, y0, y1, o0, o1);
+            Y[o0] = y0;
+            if (o1 >= 0) Y[o1] = y1;
+          }
+        } else {
+          for (int o = tid; o < N; o += GEN_THREADS)
+            Y[o] = even_output<TC>(X, Wr, tw, o, r, s, m, wn, N);
+        }
+        lds_barrier();
+        C* tmp = X;
+        X = Y;
+        Y = tmp;
+      } else {
+        if (r % 2 == 1) {
+          const int NB = N / r, items = NB * ((r + 1) / 2);
+          C y0[MAXI], y1[MAXI];
+          int o0[MAXI], o1[MAXI];
+#pragma unroll
+          for (int u = 0; u < MAXI; ++u) {
+            const int it = tid + u * GEN_THREADS;
+            o0[u] = -1;
+            if (it < items)
+              odd_pair<TC>(X, Wr, tw, it, NB, r, s, m, wn, N, y0[u], y1[u], o0[u], o1[u]);
+          }
+          __syncthreads();
+#pragma unroll
+          for (int u = 0; u < MAXI; ++u) {
+            if (o0[u] >= 0) {
+              X[o0[u]] = y0[u];
+              if (o1[u] >= 0) X[o1[u]] = y1[u];
+            }
+          }
+        } else {
+          C y[MAXU];
+#pragma unroll
+          for (int u = 0; u < MAXU; ++u) {
+            const int o = tid + u * GEN_THREADS;
+            if (o < N) y[u] = even_output<TC>(X, Wr, tw, o, r, s, m, wn, N);
+          }
+          __syncthreads();
+#pragma unroll
+          for (int u = 0; u < MAXU; ++u) {
+            const int o = tid + u * GEN_THREADS;
+            if (o < N) X[o] = y[u];
+          }
+        }
+        __syncthreads();
+      }
+      n = m;
+      s *= r;
+      off += r;
+    }
+
+    // two-for-one split: A = (Z_k + conj Z_{N-k}) / 2, C = (Z_k - conj Z_{N-k}) / 2i
+    const C* Z = X;
+    for (int k = tid; k < K; k += GEN_THREADS) {
+      const C z = Z[k], zc = Z[k == 0 ? 0 : N - k];
+      const C a = mk<TC>(h * (z.x + zc.x), h * (z.y - zc.y));
+      const C c = mk<TC>(h * (z.y + zc.y), h * (zc.x - z.x));
+      C* dst = qhat + ((int64_t)k * L + l) * M + m0;
+      if constexpr (sizeof(TC) == 4) {
+        if (vec) {
+          *reinterpret_cast<float4*>(dst) = make_float4(a.x, a.y, c.x, c.y);
+          continue;
+        }
+      }
+      dst[0] = a;
+      if (two) dst[1] = c;
+    }
+    // Z is read before the next block writes B0
+    if constexpr (PP) lds_barrier();
+    else __syncthreads();
   }
 }
 
@@ -253,7 +307,7 @@ spod_status launch_general_pp(const Plan& p, const TIN* q, const double* mean, v
   if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
   const int64_t P = (p.M + 1) / 2;
   const int64_t per_xcd = (P + 7) / 8;
-  const int64_t wgs = 8 * per_xcd * p.nblocks;
+  const int64_t wgs = 8 * per_xcd;
   if (wgs > 0x7fffffffLL) return fail(SPOD_ERR_UNSUPPORTED, "general transform grid too large");
   const C* tw = static_cast<const C*>(sizeof(TC) == 8 ? (const void*)p.d_tw64 : (const void*)p.d_tw32);
   hipLaunchKernelGGL((blocks_dft_general_kernel<TC, TIN, PP, MAXU>), dim3((unsigned)wgs),
@@ -272,7 +326,10 @@ spod_status launch_general_t(const Plan& p, const TIN* q, const double* mean, vo
   for (int i = 0; i < p.radices.n; ++i) sum_r += p.radices.r[i];
   constexpr size_t LDS_MAX = 160 * 1024;
   const size_t two_buf = sizeof(C) * (2 * (size_t)p.nfft + (size_t)sum_r);
-  if (two_buf <= LDS_MAX) return launch_general_pp<TC, TIN, true, 1>(p, q, mean, qhat, two_buf, st);
+  // two buffers: complex64 N <= ~10200, complex128 <= ~5100, so at most
+  // ceil(10240 / 1024) samples per thread and row to prefetch
+  if (two_buf <= LDS_MAX)
+    return launch_general_pp<TC, TIN, true, (sizeof(C) == 8 ? 10 : 5)>(p, q, mean, qhat, two_buf, st);
   const size_t one_buf = sizeof(C) * ((size_t)p.nfft + (size_t)sum_r);
   if (one_buf > LDS_MAX)
     return fail(SPOD_ERR_UNSUPPORTED, "block and twiddles exceed the 160 KiB of LDS");
