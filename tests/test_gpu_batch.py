@@ -206,3 +206,24 @@ def test_batch_rejects_bad_arguments():
     with pytest.raises(ValueError):
         b.forward([p.q.cuda()[:20]])
     b.close()
+
+
+def test_batch_with_general_block_lengths():
+    """Problems whose N_f is not a power of two run their own transform inside
+    the batch; everything else is the batch's grouped launches."""
+    from paper_2309_11808_amd import Batch
+    probs, descs = [], []
+    for i, (nfft, nov) in enumerate(((64, 32), (60, 30), (128, 64), (100, 50), (73, 0))):
+        p = fields.random_rows(150 + 37 * i, 10 * nfft, nfft, nov, seed=70 + i, dtype=torch.float64)
+        p.q = p.q.cuda()
+        probs.append(p)
+        descs.append(_desc(p))
+    b = Batch(descs, precision="fp64", n_modes=2)
+    res = b.forward([p.q for p in probs])
+    torch.cuda.synchronize()
+    for i, (p, r) in enumerate(zip(probs, res)):
+        _same(r, _single(p, "fp64", 2), f"problem {i} (N_f = {p.nfft})")
+        if p.nfft in (60, 73):
+            ref = O.spod(p.q.cpu().numpy(), p.nfft, p.noverlap, weights=p.weights, n_modes=2)
+            PT.check_eig(r["lam"], ref["lam"], rtol=1e-10, floor_rel=1e-13)
+    b.close()

@@ -208,3 +208,20 @@ def test_bad_arguments():
         o.forward(q=p.q[:100])
     o.close()
     plan.close()
+
+
+def test_chunks_with_a_general_block_length():
+    """Out-of-core with N_f = 60 (the mixed-radix transform) against the oracle."""
+    from paper_2309_11808_amd import OutOfCore
+    p = fields.random_rows(900, 9 * 30 + 60, 60, 30, seed=61, offset=0.4, dtype=torch.float64)
+    ref = O.spod(p.q.numpy(), 60, 30, weights=p.weights, n_modes=3)
+    plan = _plan(p, "fp64")
+    o = OutOfCore(plan, dtype=torch.float64, chunk_rows=256, n_modes=3, resident=1)
+    assert o.n_chunks == 4
+    out = o.forward(q=p.q.numpy())
+    PT.check_eig(out["lam"], ref["lam"], rtol=1e-10, floor_rel=1e-13)
+    s, n = PT.check_modes(out["phi"], ref["phi"], ref["lam"], p.weights, ref["n_valid"],
+                          sin_tol=1e-8, elem_tol=1e-6, rel_gap=1e-6)
+    assert n > 20
+    o.close()
+    plan.close()
