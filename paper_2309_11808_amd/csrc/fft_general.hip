@@ -51,16 +51,37 @@ __device__ __forceinline__ void lds_barrier() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
+// Quotient and remainder of a / d for 0 <= a < 2^24 and 1 <= d, from the
+// precomputed float reciprocal inv = 1/d: the product is within one of the
+// true quotient, and one correction step makes it exact.
+struct DivMod {
+  int q, r;
+};
+__device__ __forceinline__ DivMod divmod(int a, int d, float inv) {
+  int q = (int)((float)a * inv);
+  int r = a - q * d;
+  if (r < 0) {
+    --q;
+    r += d;
+  } else if (r >= d) {
+    ++q;
+    r -= d;
+  }
+  return {q, r};
+}
+
 // One output of an even-radix stage: y[o] = W_n^{p k} sum_j x[q + s(p + j m)] W_r^{j k}
 // (four independent partial sums, t = j k mod r).
 template <typename TC>
 __device__ __forceinline__ cpx_t<TC> even_output(const cpx_t<TC>* __restrict__ X,
                                                  const cpx_t<TC>* __restrict__ Wr,
                                                  const cpx_t<TC>* __restrict__ tw, int o, int r,
-                                                 int s, int m, int wn, int N) {
+                                                 int s, int m, int wn, int N, float inv_s,
+                                                 float inv_r) {
   using C = cpx_t<TC>;
-  const int qq = o % s, rest = o / s;
-  const int k = rest % r, pp = rest / r;
+  const DivMod a = divmod(o, s, inv_s);       // o = qq + s * rest
+  const DivMod b = divmod(a.q, r, inv_r);     // rest = k + r * pp
+  const int qq = a.r, k = b.r, pp = b.q;
   const int base = qq + s * pp, js = s * m;
   TC ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
   int j = 0, t = 0;
@@ -125,6 +146,60 @@ __device__ __forceinline__ void odd_pair(const cpx_t<TC>* __restrict__ X,
   y1 = mk<TC>(yrr * t1.x - yri * t1.y, yrr * t1.y + yri * t1.x);
   o0 = qq + s * (r * pp + kk);
   o1 = kk > 0 ? qq + s * (r * pp + r - kk) : -1;
+}
+
+// Two work items of an odd-radix stage in one pass: the outputs k1 = g and
+// k2 = g + hh (when k2 < h = (r + 1) / 2), with their partners r - k, for
+// butterfly bf.  The loads of x_j and x_{r-j} and their sum and difference are
+// shared by both; writes every output it owns straight to Y.
+template <typename TC>
+__device__ __forceinline__ void odd_two(const cpx_t<TC>* __restrict__ X, const cpx_t<TC>* __restrict__ Wr,
+                                        const cpx_t<TC>* __restrict__ tw, cpx_t<TC>* __restrict__ Y,
+                                        int it, int NB, int hh, int r, int s, int m, int wn, int N,
+                                        float inv_nb, float inv_s) {
+  using C = cpx_t<TC>;
+  const int h = (r + 1) / 2;
+  const DivMod a = divmod(it, NB, inv_nb);    // it = bf + NB * g
+  const int g = a.q, bf = a.r;
+  const int k1 = g, k2 = g + hh;
+  const DivMod b = divmod(bf, s, inv_s);      // bf = qq + s * pp
+  const int qq = b.r, pp = b.q;
+  const int base = qq + s * pp, js = s * m;
+  const C x0 = X[base];
+  TC a1r = 0, a1i = 0, b1r = 0, b1i = 0, a2r = 0, a2i = 0, b2r = 0, b2i = 0;
+  int t1 = 0, t2 = 0;
+  const C* pa = X + base + js;
+  const C* pb = X + base + (r - 1) * js;
+  for (int j = 1; 2 * j < r; ++j, pa += js, pb -= js) {
+    t1 += k1;
+    if (t1 >= r) t1 -= r;
+    t2 += k2;
+    if (t2 >= r) t2 -= r;
+    const C xa = *pa, xb = *pb;
+    const TC sr = xa.x + xb.x, si = xa.y + xb.y, dr = xa.x - xb.x, di = xa.y - xb.y;
+    const C w1 = Wr[t1], w2 = Wr[t2];
+    a1r += sr * w1.x;
+    a1i += si * w1.x;
+    b1r -= dr * w1.y;
+    b1i -= di * w1.y;
+    a2r += sr * w2.x;
+    a2i += si * w2.x;
+    b2r -= dr * w2.y;
+    b2i -= di * w2.y;
+  }
+  auto put = [&](int k, TC ar, TC ai, TC br, TC bi) {
+    // y_k = x0 + A - iB, y_{r-k} = x0 + A + iB, then W_n^{p k}, W_n^{p (r-k)}
+    const TC ykr = x0.x + ar + bi, yki = x0.y + ai - br;
+    const C t0 = tw[(int)(((int64_t)wn * pp * k) % N)];
+    Y[qq + s * (r * pp + k)] = mk<TC>(ykr * t0.x - yki * t0.y, ykr * t0.y + yki * t0.x);
+    if (k > 0) {
+      const TC yrr = x0.x + ar - bi, yri = x0.y + ai + br;
+      const C t1w = tw[(int)(((int64_t)wn * pp * (r - k)) % N)];
+      Y[qq + s * (r * pp + r - k)] = mk<TC>(yrr * t1w.x - yri * t1w.y, yrr * t1w.y + yri * t1w.x);
+    }
+  };
+  put(k1, a1r, a1i, b1r, b1i);
+  if (k2 < h) put(k2, a2r, a2i, b2r, b2i);
 }
 
 // PP: two LDS buffers, every stage reads one and writes the other (no
@@ -219,17 +294,14 @@ __global__ __launch_bounds__(GEN_THREADS) void blocks_dft_general_kernel(
       const C* Wr = Wt + off;
       if constexpr (PP) {
         if (r % 2 == 1) {
-          const int NB = N / r, items = NB * ((r + 1) / 2);
-          for (int it = tid; it < items; it += GEN_THREADS) {
-            C y0, y1;
-            int o0, o1;
-            odd_pair<TC>(X, Wr, tw, it, NB, r, s, m, wn, N, y0, y1, o0, o1);
-            Y[o0] = y0;
-            if (o1 >= 0) Y[o1] = y1;
-          }
+          const int NB = N / r, hh = ((r + 1) / 2 + 1) / 2;
+          const float inv_nb = 1.0f / (float)NB, inv_s = 1.0f / (float)s;
+          for (int it = tid; it < NB * hh; it += GEN_THREADS)
+            odd_two<TC>(X, Wr, tw, Y, it, NB, hh, r, s, m, wn, N, inv_nb, inv_s);
         } else {
+          const float inv_s = 1.0f / (float)s, inv_r = 1.0f / (float)r;
           for (int o = tid; o < N; o += GEN_THREADS)
-            Y[o] = even_output<TC>(X, Wr, tw, o, r, s, m, wn, N);
+            Y[o] = even_output<TC>(X, Wr, tw, o, r, s, m, wn, N, inv_s, inv_r);
         }
         lds_barrier();
         C* tmp = X;
@@ -260,7 +332,8 @@ __global__ __launch_bounds__(GEN_THREADS) void blocks_dft_general_kernel(
 #pragma unroll
           for (int u = 0; u < MAXU; ++u) {
             const int o = tid + u * GEN_THREADS;
-            if (o < N) y[u] = even_output<TC>(X, Wr, tw, o, r, s, m, wn, N);
+            if (o < N)
+              y[u] = even_output<TC>(X, Wr, tw, o, r, s, m, wn, N, 1.0f / (float)s, 1.0f / (float)r);
           }
           __syncthreads();
 #pragma unroll
