@@ -24,6 +24,7 @@
 
 #include <algorithm>
 
+#include "fft_core.h"
 #include "internal.h"
 
 namespace spod {
@@ -146,6 +147,35 @@ __device__ __forceinline__ void odd_pair(const cpx_t<TC>* __restrict__ X,
   y1 = mk<TC>(yrr * t1.x - yri * t1.y, yrr * t1.y + yri * t1.x);
   o0 = qq + s * (r * pp + kk);
   o1 = kk > 0 ? qq + s * (r * pp + r - kk) : -1;
+}
+
+// One butterfly of a radix-2, 4 or 8 stage: the RS inputs x[q + s(p + j m)]
+// through the in-register DFT, output k times W_n^{p k}, stored at
+// y[q + s(RS p + k)].
+template <int RS, typename TC>
+__device__ __forceinline__ void even_butterfly(const cpx_t<TC>* __restrict__ X,
+                                               const cpx_t<TC>* __restrict__ tw,
+                                               cpx_t<TC>* __restrict__ Y, int bf, int s, int m,
+                                               int wn, int N, float inv_s) {
+  using C = cpx_t<TC>;
+  const DivMod a = divmod(bf, s, inv_s);      // bf = qq + s * pp
+  const int qq = a.r, pp = a.q;
+  const int base = qq + s * pp, js = s * m;
+  C x[RS];
+#pragma unroll
+  for (int j = 0; j < RS; ++j) x[j] = X[base + j * js];
+  dft_r<RS>(x);
+  const int step = (int)(((int64_t)wn * pp) % N);   // W_n^{p k} = W_N^{k step}
+  int t = 0;
+  const int out = qq + s * RS * pp;
+  Y[out] = x[0];
+#pragma unroll
+  for (int k = 1; k < RS; ++k) {
+    t += step;
+    if (t >= N) t -= N;
+    const C w = tw[t];
+    Y[out + s * k] = mk<TC>(x[k].x * w.x - x[k].y * w.y, x[k].x * w.y + x[k].y * w.x);
+  }
 }
 
 // Two work items of an odd-radix stage in one pass: the outputs k1 = g and
@@ -298,6 +328,14 @@ __global__ __launch_bounds__(GEN_THREADS) void blocks_dft_general_kernel(
           const float inv_nb = 1.0f / (float)NB, inv_s = 1.0f / (float)s;
           for (int it = tid; it < NB * hh; it += GEN_THREADS)
             odd_two<TC>(X, Wr, tw, Y, it, NB, hh, r, s, m, wn, N, inv_nb, inv_s);
+        } else if (r == 8 || r == 4 || r == 2) {
+          const float inv_s = 1.0f / (float)s;
+          const int NB = N / r;
+          for (int bf = tid; bf < NB; bf += GEN_THREADS) {
+            if (r == 8) even_butterfly<8, TC>(X, tw, Y, bf, s, m, wn, N, inv_s);
+            else if (r == 4) even_butterfly<4, TC>(X, tw, Y, bf, s, m, wn, N, inv_s);
+            else even_butterfly<2, TC>(X, tw, Y, bf, s, m, wn, N, inv_s);
+          }
         } else {
           const float inv_s = 1.0f / (float)s, inv_r = 1.0f / (float)r;
           for (int o = tid; o < N; o += GEN_THREADS)
