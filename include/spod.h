@@ -70,7 +70,8 @@ typedef enum {
   SPOD_ERR_HIP = -4,         /* HIP runtime error (no device, launch failure, ...) */
   SPOD_ERR_NUMERIC = -5,     /* non-finite values where finite ones are required   */
   SPOD_ERR_WORKSPACE = -6,   /* workspace missing or smaller than required         */
-  SPOD_ERR_IO = -7           /* a reader callback reported a failure               */
+  SPOD_ERR_IO = -7,          /* a reader callback reported a failure               */
+  SPOD_ERR_INTERNAL = -8     /* unexpected host-side failure (e.g. no thread)      */
 } spod_status;
 
 typedef enum { SPOD_F32 = 0, SPOD_F64 = 1 } spod_dtype; /* stored type of q and g_q */

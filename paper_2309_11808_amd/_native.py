@@ -19,6 +19,7 @@ SPOD_ERR_HIP = -4
 SPOD_ERR_NUMERIC = -5
 SPOD_ERR_WORKSPACE = -6
 SPOD_ERR_IO = -7
+SPOD_ERR_INTERNAL = -8
 
 SPOD_F32 = 0
 SPOD_F64 = 1

@@ -108,6 +108,7 @@ const char* spod_status_string(spod_status s) {
     case SPOD_ERR_NUMERIC: return "SPOD_ERR_NUMERIC";
     case SPOD_ERR_WORKSPACE: return "SPOD_ERR_WORKSPACE";
     case SPOD_ERR_IO: return "SPOD_ERR_IO";
+    case SPOD_ERR_INTERNAL: return "SPOD_ERR_INTERNAL";
   }
   return "SPOD_ERR_UNKNOWN";
 }
@@ -136,152 +137,154 @@ void spod_plan_destroy(spod_plan plan) {
 spod_status spod_plan_create(int64_t nspace, int64_t nvar, int64_t nt, int64_t nfft,
                              int64_t noverlap, const double* window, const double* weights,
                              spod_plan* out) {
-  if (!out) return fail(SPOD_ERR_INVALID_ARG, "out is NULL");
-  *out = nullptr;
-  if (nspace < 1 || nvar < 1) return fail(SPOD_ERR_INVALID_ARG, "nspace and nvar must be >= 1");
-  if (nspace > (int64_t(1) << 40) / nvar) return fail(SPOD_ERR_INVALID_ARG, "M too large");
-  int64_t L = 0, K = 0;
-  spod_status st = validate_shape(nt, nfft, noverlap, &L, &K);
-  if (st != SPOD_OK) return st;
-  const int64_t M = nspace * nvar;
+  return guarded([&]() -> spod_status {
+    if (!out) return fail(SPOD_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (nspace < 1 || nvar < 1) return fail(SPOD_ERR_INVALID_ARG, "nspace and nvar must be >= 1");
+    if (nspace > (int64_t(1) << 40) / nvar) return fail(SPOD_ERR_INVALID_ARG, "M too large");
+    int64_t L = 0, K = 0;
+    spod_status st = validate_shape(nt, nfft, noverlap, &L, &K);
+    if (st != SPOD_OK) return st;
+    const int64_t M = nspace * nvar;
 
-  // host copies of window and weights, validated before any HIP call
-  std::vector<double> w(nfft), W(M);
-  double sw2 = 0.0;
-  for (int64_t n = 0; n < nfft; ++n) {
-    double v = window ? window[n]
-                      : (double)(0.5L - 0.5L * cosl(2.0L * 3.14159265358979323846264338327950288L *
-                                                    (long double)n / (long double)nfft));
-    if (!std::isfinite(v)) return fail(SPOD_ERR_INVALID_ARG, "window has a non-finite value");
-    w[n] = v;
-    sw2 += v * v;
-  }
-  if (!(sw2 > 0.0) || !std::isfinite(sw2)) return fail(SPOD_ERR_INVALID_ARG, "window energy is zero");
-  bool any = false;
-  for (int64_t m = 0; m < M; ++m) {
-    double v = weights ? weights[m] : 1.0 / (double)M;
-    if (!std::isfinite(v) || v < 0.0)
-      return fail(SPOD_ERR_INVALID_ARG, "weights must be finite and >= 0");
-    any |= v > 0.0;
-    W[m] = v;
-  }
-  if (!any) return fail(SPOD_ERR_INVALID_ARG, "weights are all zero");
-  if (nfft < 8 || nfft > SPOD_GENERAL_MAX_NFFT)
-    return fail(SPOD_ERR_UNSUPPORTED, "nfft must be in [8, 20480]");
+    // host copies of window and weights, validated before any HIP call
+    std::vector<double> w(nfft), W(M);
+    double sw2 = 0.0;
+    for (int64_t n = 0; n < nfft; ++n) {
+      double v = window ? window[n]
+                        : (double)(0.5L - 0.5L * cosl(2.0L * 3.14159265358979323846264338327950288L *
+                                                      (long double)n / (long double)nfft));
+      if (!std::isfinite(v)) return fail(SPOD_ERR_INVALID_ARG, "window has a non-finite value");
+      w[n] = v;
+      sw2 += v * v;
+    }
+    if (!(sw2 > 0.0) || !std::isfinite(sw2)) return fail(SPOD_ERR_INVALID_ARG, "window energy is zero");
+    bool any = false;
+    for (int64_t m = 0; m < M; ++m) {
+      double v = weights ? weights[m] : 1.0 / (double)M;
+      if (!std::isfinite(v) || v < 0.0)
+        return fail(SPOD_ERR_INVALID_ARG, "weights must be finite and >= 0");
+      any |= v > 0.0;
+      W[m] = v;
+    }
+    if (!any) return fail(SPOD_ERR_INVALID_ARG, "weights are all zero");
+    if (nfft < 8 || nfft > SPOD_GENERAL_MAX_NFFT)
+      return fail(SPOD_ERR_UNSUPPORTED, "nfft must be in [8, 20480]");
 
-  Plan* p = new (std::nothrow) Plan();
-  if (!p) return fail(SPOD_ERR_ALLOC, "plan");
-  p->nspace = nspace;
-  p->nvar = nvar;
-  p->M = M;
-  p->nt = nt;
-  p->nfft = nfft;
-  p->noverlap = noverlap;
-  p->step = nfft - noverlap;
-  p->nblocks = L;
-  p->nfreq = K;
-  p->general = !(is_pow2(nfft) && nfft <= 1024);
-  {
-    int64_t n = nfft;
-    for (int64_t f : {8, 4, 2, 3, 5, 7}) {
-      while (n % f == 0 && p->radices.n < 32) {
-        p->radices.r[p->radices.n++] = (int)f;
-        n /= f;
-      }
-    }
-    for (int64_t f = 11; n > 1 && p->radices.n < 32; f += 2) {
-      while (n % f == 0 && p->radices.n < 32) {
-        p->radices.r[p->radices.n++] = (int)f;
-        n /= f;
-      }
-    }
-    if (n != 1) p->radices.n = 0;   // not reachable for nfft <= 20480 (at most 15 factors)
-  }
-  p->kappa = 1.0 / std::sqrt((double)(L - 1) * sw2);
-  // DFT of the window at every one-sided bin, What_k = sum_n w[n] e^{-2 pi i k n / N},
-  // in long double with exact integer reduction of k*n mod N
-  std::vector<double2> what(K);
-  {
-    long double sabs = 0.0L;
-    for (int64_t n = 0; n < nfft; ++n) sabs += fabsl((long double)w[n]);
-    std::vector<long double> ct(nfft), st(nfft);
-    for (int64_t t = 0; t < nfft; ++t) {
-      const long double a =
-          2.0L * 3.14159265358979323846264338327950288L * (long double)t / (long double)nfft;
-      ct[t] = cosl(a);
-      st[t] = sinl(a);
-    }
-    int cnt = 0;
-    for (int64_t k = 0; k < K; ++k) {
-      long double re = 0.0L, im = 0.0L;
-      int64_t t = 0;                      // (k * n) mod nfft
-      for (int64_t n = 0; n < nfft; ++n) {
-        re += (long double)w[n] * ct[t];
-        im -= (long double)w[n] * st[t];
-        t += k;
-        if (t >= nfft) t -= nfft;
-      }
-      what[k] = make_double2((double)re, (double)im);
-      if (cnt >= 0 && sqrtl(re * re + im * im) > 1e-12L * sabs) {
-        if (cnt == Plan::SPOD_MAX_MEAN_BINS) {
-          cnt = -1;
-        } else {
-          p->mean_bin[cnt] = (int)k;
-          p->what_re[cnt] = (double)re;
-          p->what_im[cnt] = (double)im;
-          ++cnt;
+    Plan* p = new (std::nothrow) Plan();
+    if (!p) return fail(SPOD_ERR_ALLOC, "plan");
+    p->nspace = nspace;
+    p->nvar = nvar;
+    p->M = M;
+    p->nt = nt;
+    p->nfft = nfft;
+    p->noverlap = noverlap;
+    p->step = nfft - noverlap;
+    p->nblocks = L;
+    p->nfreq = K;
+    p->general = !(is_pow2(nfft) && nfft <= 1024);
+    {
+      int64_t n = nfft;
+      for (int64_t f : {8, 4, 2, 3, 5, 7}) {
+        while (n % f == 0 && p->radices.n < 32) {
+          p->radices.r[p->radices.n++] = (int)f;
+          n /= f;
         }
       }
+      for (int64_t f = 11; n > 1 && p->radices.n < 32; f += 2) {
+        while (n % f == 0 && p->radices.n < 32) {
+          p->radices.r[p->radices.n++] = (int)f;
+          n /= f;
+        }
+      }
+      if (n != 1) p->radices.n = 0;   // not reachable for nfft <= 20480 (at most 15 factors)
     }
-    p->n_mean_bins = cnt;
-  }
-  derive(*p);
+    p->kappa = 1.0 / std::sqrt((double)(L - 1) * sw2);
+    // DFT of the window at every one-sided bin, What_k = sum_n w[n] e^{-2 pi i k n / N},
+    // in long double with exact integer reduction of k*n mod N
+    std::vector<double2> what(K);
+    {
+      long double sabs = 0.0L;
+      for (int64_t n = 0; n < nfft; ++n) sabs += fabsl((long double)w[n]);
+      std::vector<long double> ct(nfft), st(nfft);
+      for (int64_t t = 0; t < nfft; ++t) {
+        const long double a =
+            2.0L * 3.14159265358979323846264338327950288L * (long double)t / (long double)nfft;
+        ct[t] = cosl(a);
+        st[t] = sinl(a);
+      }
+      int cnt = 0;
+      for (int64_t k = 0; k < K; ++k) {
+        long double re = 0.0L, im = 0.0L;
+        int64_t t = 0;                      // (k * n) mod nfft
+        for (int64_t n = 0; n < nfft; ++n) {
+          re += (long double)w[n] * ct[t];
+          im -= (long double)w[n] * st[t];
+          t += k;
+          if (t >= nfft) t -= nfft;
+        }
+        what[k] = make_double2((double)re, (double)im);
+        if (cnt >= 0 && sqrtl(re * re + im * im) > 1e-12L * sabs) {
+          if (cnt == Plan::SPOD_MAX_MEAN_BINS) {
+            cnt = -1;
+          } else {
+            p->mean_bin[cnt] = (int)k;
+            p->what_re[cnt] = (double)re;
+            p->what_im[cnt] = (double)im;
+            ++cnt;
+          }
+        }
+      }
+      p->n_mean_bins = cnt;
+    }
+    derive(*p);
 
-  hipError_t e = hipGetDevice(&p->device);
-  if (e != hipSuccess) {
-    delete p;
-    return hip_fail(e, "hipGetDevice");
-  }
-  // twiddles e^{-2 pi i j / N}, computed in long double and rounded once
-  std::vector<double2> tw(nfft);
-  std::vector<float2> tw32(nfft);
-  std::vector<float> w32(nfft), sq32(M);
-  std::vector<double> sq(M);
-  for (int64_t j = 0; j < nfft; ++j) {
-    long double a = 2.0L * 3.14159265358979323846264338327950288L * (long double)j / (long double)nfft;
-    tw[j] = make_double2((double)cosl(a), (double)-sinl(a));
-    tw32[j] = make_float2((float)cosl(a), (float)-sinl(a));
-    w32[j] = (float)w[j];
-  }
-  for (int64_t m = 0; m < M; ++m) {
-    sq[m] = std::sqrt(W[m]);
-    sq32[m] = (float)sq[m];
-  }
-  struct Up { void** dst; const void* src; size_t bytes; } ups[] = {
-      {(void**)&p->d_window, w.data(), sizeof(double) * nfft},
-      {(void**)&p->d_window32, w32.data(), sizeof(float) * nfft},
-      {(void**)&p->d_weights, W.data(), sizeof(double) * M},
-      {(void**)&p->d_sqrtw, sq.data(), sizeof(double) * M},
-      {(void**)&p->d_sqrtw32, sq32.data(), sizeof(float) * M},
-      {(void**)&p->d_tw64, tw.data(), sizeof(double2) * nfft},
-      {(void**)&p->d_tw32, tw32.data(), sizeof(float2) * nfft},
-      {(void**)&p->d_what, what.data(), sizeof(double2) * K},
-  };
-  for (auto& u : ups) {
-    e = hipMalloc(u.dst, u.bytes);
+    hipError_t e = hipGetDevice(&p->device);
     if (e != hipSuccess) {
-      spod_plan_destroy(reinterpret_cast<spod_plan>(p));
-      return e == hipErrorOutOfMemory ? fail(SPOD_ERR_ALLOC, "plan tables")
-                                      : hip_fail(e, "hipMalloc");
+      delete p;
+      return hip_fail(e, "hipGetDevice");
     }
-    e = hipMemcpy(*u.dst, u.src, u.bytes, hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-      spod_plan_destroy(reinterpret_cast<spod_plan>(p));
-      return hip_fail(e, "hipMemcpy");
+    // twiddles e^{-2 pi i j / N}, computed in long double and rounded once
+    std::vector<double2> tw(nfft);
+    std::vector<float2> tw32(nfft);
+    std::vector<float> w32(nfft), sq32(M);
+    std::vector<double> sq(M);
+    for (int64_t j = 0; j < nfft; ++j) {
+      long double a = 2.0L * 3.14159265358979323846264338327950288L * (long double)j / (long double)nfft;
+      tw[j] = make_double2((double)cosl(a), (double)-sinl(a));
+      tw32[j] = make_float2((float)cosl(a), (float)-sinl(a));
+      w32[j] = (float)w[j];
     }
-  }
-  *out = reinterpret_cast<spod_plan>(p);
-  return SPOD_OK;
+    for (int64_t m = 0; m < M; ++m) {
+      sq[m] = std::sqrt(W[m]);
+      sq32[m] = (float)sq[m];
+    }
+    struct Up { void** dst; const void* src; size_t bytes; } ups[] = {
+        {(void**)&p->d_window, w.data(), sizeof(double) * nfft},
+        {(void**)&p->d_window32, w32.data(), sizeof(float) * nfft},
+        {(void**)&p->d_weights, W.data(), sizeof(double) * M},
+        {(void**)&p->d_sqrtw, sq.data(), sizeof(double) * M},
+        {(void**)&p->d_sqrtw32, sq32.data(), sizeof(float) * M},
+        {(void**)&p->d_tw64, tw.data(), sizeof(double2) * nfft},
+        {(void**)&p->d_tw32, tw32.data(), sizeof(float2) * nfft},
+        {(void**)&p->d_what, what.data(), sizeof(double2) * K},
+    };
+    for (auto& u : ups) {
+      e = hipMalloc(u.dst, u.bytes);
+      if (e != hipSuccess) {
+        spod_plan_destroy(reinterpret_cast<spod_plan>(p));
+        return e == hipErrorOutOfMemory ? fail(SPOD_ERR_ALLOC, "plan tables")
+                                        : hip_fail(e, "hipMalloc");
+      }
+      e = hipMemcpy(*u.dst, u.src, u.bytes, hipMemcpyHostToDevice);
+      if (e != hipSuccess) {
+        spod_plan_destroy(reinterpret_cast<spod_plan>(p));
+        return hip_fail(e, "hipMemcpy");
+      }
+    }
+    *out = reinterpret_cast<spod_plan>(p);
+    return SPOD_OK;
+  });
 }
 
 spod_status spod_plan_set_precision(spod_plan plan, spod_precision prec) {
@@ -403,36 +406,38 @@ spod_status spod_backward(spod_plan plan, const void* q, spod_dtype dtype, const
                           const void* g_phi, int64_t n_modes, const int32_t* bins,
                           int64_t n_bins, void* g_qhat, void* g_q, void* ws, size_t ws_bytes,
                           spod_stream stream) {
-  Plan* p = reinterpret_cast<Plan*>(plan);
-  if (!p) return fail(SPOD_ERR_INVALID_ARG, "plan is NULL");
-  if (!lam || !psi || !g_qhat || !g_q)
-    return fail(SPOD_ERR_INVALID_ARG, "lam, psi, g_qhat and g_q are required");
-  if (!qhat && !q) return fail(SPOD_ERR_INVALID_ARG, "q is required when qhat is NULL");
-  if (dtype != SPOD_F32 && dtype != SPOD_F64) return fail(SPOD_ERR_INVALID_ARG, "dtype");
-  if (g_phi && (n_modes < 1 || n_modes > p->nblocks))
-    return fail(SPOD_ERR_INVALID_ARG, "n_modes must be in [1, nblocks]");
-  if (bins) {
-    if (n_bins < 1 || n_bins > p->nfreq)
-      return fail(SPOD_ERR_INVALID_ARG, "n_bins must be in [1, nfreq]");
-    for (int64_t i = 0; i < n_bins; ++i) {
-      if (bins[i] < 0 || bins[i] >= p->nfreq || (i > 0 && bins[i] <= bins[i - 1]))
-        return fail(SPOD_ERR_INVALID_ARG, "bins must be strictly increasing in [0, nfreq)");
+  return guarded([&]() -> spod_status {
+    Plan* p = reinterpret_cast<Plan*>(plan);
+    if (!p) return fail(SPOD_ERR_INVALID_ARG, "plan is NULL");
+    if (!lam || !psi || !g_qhat || !g_q)
+      return fail(SPOD_ERR_INVALID_ARG, "lam, psi, g_qhat and g_q are required");
+    if (!qhat && !q) return fail(SPOD_ERR_INVALID_ARG, "q is required when qhat is NULL");
+    if (dtype != SPOD_F32 && dtype != SPOD_F64) return fail(SPOD_ERR_INVALID_ARG, "dtype");
+    if (g_phi && (n_modes < 1 || n_modes > p->nblocks))
+      return fail(SPOD_ERR_INVALID_ARG, "n_modes must be in [1, nblocks]");
+    if (bins) {
+      if (n_bins < 1 || n_bins > p->nfreq)
+        return fail(SPOD_ERR_INVALID_ARG, "n_bins must be in [1, nfreq]");
+      for (int64_t i = 0; i < n_bins; ++i) {
+        if (bins[i] < 0 || bins[i] >= p->nfreq || (i > 0 && bins[i] <= bins[i - 1]))
+          return fail(SPOD_ERR_INVALID_ARG, "bins must be strictly increasing in [0, nfreq)");
+      }
+      if (qhat && qhat == g_qhat)
+        return fail(SPOD_ERR_INVALID_ARG, "g_qhat may alias qhat only without a bin selection");
     }
-    if (qhat && qhat == g_qhat)
-      return fail(SPOD_ERR_INVALID_ARG, "g_qhat may alias qhat only without a bin selection");
-  }
-  if (p->nfft < 16) return fail(SPOD_ERR_UNSUPPORTED, "backward needs nfft >= 16");
-  if (p->general) return fail(SPOD_ERR_UNSUPPORTED, "backward needs a power-of-two nfft <= 1024");
-  if (p->step != p->nfft && p->step != p->nfft / 2 && p->step != p->nfft / 4)
-    return fail(SPOD_ERR_UNSUPPORTED, "backward needs a hop of nfft/4, nfft/2 or nfft");
-  if (p->nblocks > 64) return fail(SPOD_ERR_UNSUPPORTED, "nblocks > 64");
-  spod_status st = enter(p);
-  if (st != SPOD_OK) return st;
-  st = check_ws(*p, ws, ws_bytes, backward_workspace(*p));
-  if (st != SPOD_OK) return st;
-  return launch_backward(*p, q, dtype, qhat, lam, psi, g_lam, g_phi, g_phi ? (int)n_modes : 0,
-                         bins, bins ? (int)n_bins : (int)p->nfreq, g_qhat, g_q, ws,
-                         (hipStream_t)stream);
+    if (p->nfft < 16) return fail(SPOD_ERR_UNSUPPORTED, "backward needs nfft >= 16");
+    if (p->general) return fail(SPOD_ERR_UNSUPPORTED, "backward needs a power-of-two nfft <= 1024");
+    if (p->step != p->nfft && p->step != p->nfft / 2 && p->step != p->nfft / 4)
+      return fail(SPOD_ERR_UNSUPPORTED, "backward needs a hop of nfft/4, nfft/2 or nfft");
+    if (p->nblocks > 64) return fail(SPOD_ERR_UNSUPPORTED, "nblocks > 64");
+    spod_status st = enter(p);
+    if (st != SPOD_OK) return st;
+    st = check_ws(*p, ws, ws_bytes, backward_workspace(*p));
+    if (st != SPOD_OK) return st;
+    return launch_backward(*p, q, dtype, qhat, lam, psi, g_lam, g_phi, g_phi ? (int)n_modes : 0,
+                           bins, bins ? (int)n_bins : (int)p->nfreq, g_qhat, g_q, ws,
+                           (hipStream_t)stream);
+  });
 }
 
 static spod_status coeff_sel(const Plan& p, int64_t n_modes, const int32_t* bins, int64_t n_bins,

@@ -475,47 +475,49 @@ extern "C" {
 
 spod_status spod_batch_create(const spod_problem* problems, int64_t n, spod_precision precision,
                               int64_t n_modes, spod_batch* out) {
-  if (!out) return fail(SPOD_ERR_INVALID_ARG, "out is NULL");
-  *out = nullptr;
-  if (!problems || n < 1) return fail(SPOD_ERR_INVALID_ARG, "need at least one problem");
-  if (n > 65536) return fail(SPOD_ERR_INVALID_ARG, "at most 65536 problems");
-  if (n_modes < 1) return fail(SPOD_ERR_INVALID_ARG, "n_modes must be >= 1");
-  if (precision != SPOD_PREC_FP64 && precision != SPOD_PREC_FP32 &&
-      precision != SPOD_PREC_BF16X4 && precision != SPOD_PREC_FP16X4)
-    return fail(SPOD_ERR_INVALID_ARG, "unknown precision");
-  Batch* b = new (std::nothrow) Batch();
-  if (!b) return fail(SPOD_ERR_ALLOC, "batch");
-  b->prec = precision;
-  b->pb.resize((size_t)n);
-  spod_status st = SPOD_OK;
-  for (int64_t i = 0; i < n && st == SPOD_OK; ++i) {
-    const spod_problem& d = problems[i];
-    spod_plan h = nullptr;
-    st = spod_plan_create(d.nspace, d.nvar, d.nt, d.nfft, d.noverlap, d.window, d.weights, &h);
-    if (st != SPOD_OK) {
-      fail(st, "problem " + std::to_string(i) + ": " + spod_last_error());
-      break;
+  return guarded([&]() -> spod_status {
+    if (!out) return fail(SPOD_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!problems || n < 1) return fail(SPOD_ERR_INVALID_ARG, "need at least one problem");
+    if (n > 65536) return fail(SPOD_ERR_INVALID_ARG, "at most 65536 problems");
+    if (n_modes < 1) return fail(SPOD_ERR_INVALID_ARG, "n_modes must be >= 1");
+    if (precision != SPOD_PREC_FP64 && precision != SPOD_PREC_FP32 &&
+        precision != SPOD_PREC_BF16X4 && precision != SPOD_PREC_FP16X4)
+      return fail(SPOD_ERR_INVALID_ARG, "unknown precision");
+    Batch* b = new (std::nothrow) Batch();
+    if (!b) return fail(SPOD_ERR_ALLOC, "batch");
+    b->prec = precision;
+    b->pb.resize((size_t)n);
+    spod_status st = SPOD_OK;
+    for (int64_t i = 0; i < n && st == SPOD_OK; ++i) {
+      const spod_problem& d = problems[i];
+      spod_plan h = nullptr;
+      st = spod_plan_create(d.nspace, d.nvar, d.nt, d.nfft, d.noverlap, d.window, d.weights, &h);
+      if (st != SPOD_OK) {
+        fail(st, "problem " + std::to_string(i) + ": " + spod_last_error());
+        break;
+      }
+      b->pb[i].plan = reinterpret_cast<Plan*>(h);
+      st = spod_plan_set_precision(h, precision);
+      if (b->pb[i].plan->nblocks > 64) st = fail(SPOD_ERR_UNSUPPORTED, "nblocks > 64");
+      b->pb[i].n_modes = (int)std::min<int64_t>(n_modes, b->pb[i].plan->nblocks);
     }
-    b->pb[i].plan = reinterpret_cast<Plan*>(h);
-    st = spod_plan_set_precision(h, precision);
-    if (b->pb[i].plan->nblocks > 64) st = fail(SPOD_ERR_UNSUPPORTED, "nblocks > 64");
-    b->pb[i].n_modes = (int)std::min<int64_t>(n_modes, b->pb[i].plan->nblocks);
-  }
-  if (st == SPOD_OK) {
-    hipError_t e = hipGetDevice(&b->device);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
-    if (e != hipSuccess) st = hip_fail(e, "batch stream");
-  }
-  if (st != SPOD_OK) {
-    const std::string msg = spod_last_error();
-    spod_batch_destroy(reinterpret_cast<spod_batch>(b));
-    fail(st, msg.substr(msg.find(": ") == std::string::npos ? 0 : msg.find(": ") + 2));
-    return st;
-  }
-  apply_target(*b);
-  layout(*b);
-  *out = reinterpret_cast<spod_batch>(b);
-  return SPOD_OK;
+    if (st == SPOD_OK) {
+      hipError_t e = hipGetDevice(&b->device);
+      if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+      if (e != hipSuccess) st = hip_fail(e, "batch stream");
+    }
+    if (st != SPOD_OK) {
+      const std::string msg = spod_last_error();
+      spod_batch_destroy(reinterpret_cast<spod_batch>(b));
+      fail(st, msg.substr(msg.find(": ") == std::string::npos ? 0 : msg.find(": ") + 2));
+      return st;
+    }
+    apply_target(*b);
+    layout(*b);
+    *out = reinterpret_cast<spod_batch>(b);
+    return SPOD_OK;
+  });
 }
 
 spod_status spod_batch_set_option(spod_batch batch, spod_batch_option opt, int64_t value) {
@@ -573,59 +575,63 @@ spod_status spod_batch_item_info(spod_batch batch, int64_t i, spod_batch_item* i
 
 spod_status spod_batch_forward(spod_batch batch, const void* const* q, spod_dtype dtype,
                                void* out, void* ws, size_t ws_bytes, spod_stream stream) {
-  Batch* b = reinterpret_cast<Batch*>(batch);
-  spod_status st = check_call(b, q, dtype, out, ws, ws_bytes);
-  if (st != SPOD_OK) return st;
-  return run(*b, q, dtype, out, ws, (hipStream_t)stream, b->use_graph);
+  return guarded([&]() -> spod_status {
+    Batch* b = reinterpret_cast<Batch*>(batch);
+    spod_status st = check_call(b, q, dtype, out, ws, ws_bytes);
+    if (st != SPOD_OK) return st;
+    return run(*b, q, dtype, out, ws, (hipStream_t)stream, b->use_graph);
+  });
 }
 
 spod_status spod_batch_autotune(spod_batch batch, const void* const* q, spod_dtype dtype,
                                 void* out, void* ws, size_t ws_bytes, spod_stream stream,
                                 const char* cache_path, int64_t* chosen) {
-  Batch* b = reinterpret_cast<Batch*>(batch);
-  spod_status st = check_call(b, q, dtype, out, ws, ws_bytes);
-  if (st != SPOD_OK) return st;
-  hipStream_t s = (hipStream_t)stream;
-  const std::string key = batch_key(*b);
-  int64_t best = cache_path ? cache_lookup(cache_path, key) : 0;
-  const int64_t cands[] = {2048, 4096, 8192, 16384};
-  float ms[4] = {0, 0, 0, 0};
-  if (best <= 0) {
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    hipError_t e = hipEventCreate(&e0);
-    if (e == hipSuccess) e = hipEventCreate(&e1);
-    if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
-    float best_ms = 0.0f;
-    for (int c = 0; c < 4 && st == SPOD_OK; ++c) {
-      b->gram_target = cands[c];
-      // one untimed pass (builds the tables), then one timed pass, without a graph
-      st = run(*b, q, dtype, out, ws, s, false);
-      if (st == SPOD_OK) e = hipEventRecord(e0, s);
-      if (st == SPOD_OK && e == hipSuccess) st = run(*b, q, dtype, out, ws, s, false);
-      if (st == SPOD_OK && e == hipSuccess) e = hipEventRecord(e1, s);
-      if (st == SPOD_OK && e == hipSuccess) e = hipEventSynchronize(e1);
-      if (st == SPOD_OK && e == hipSuccess) e = hipEventElapsedTime(&ms[c], e0, e1);
-      if (st == SPOD_OK && e != hipSuccess) st = hip_fail(e, "autotune timing");
-      if (st == SPOD_OK && (best <= 0 || ms[c] < best_ms)) {
-        best = cands[c];
-        best_ms = ms[c];
+  return guarded([&]() -> spod_status {
+    Batch* b = reinterpret_cast<Batch*>(batch);
+    spod_status st = check_call(b, q, dtype, out, ws, ws_bytes);
+    if (st != SPOD_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const std::string key = batch_key(*b);
+    int64_t best = cache_path ? cache_lookup(cache_path, key) : 0;
+    const int64_t cands[] = {2048, 4096, 8192, 16384};
+    float ms[4] = {0, 0, 0, 0};
+    if (best <= 0) {
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      hipError_t e = hipEventCreate(&e0);
+      if (e == hipSuccess) e = hipEventCreate(&e1);
+      if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+      float best_ms = 0.0f;
+      for (int c = 0; c < 4 && st == SPOD_OK; ++c) {
+        b->gram_target = cands[c];
+        // one untimed pass (builds the tables), then one timed pass, without a graph
+        st = run(*b, q, dtype, out, ws, s, false);
+        if (st == SPOD_OK) e = hipEventRecord(e0, s);
+        if (st == SPOD_OK && e == hipSuccess) st = run(*b, q, dtype, out, ws, s, false);
+        if (st == SPOD_OK && e == hipSuccess) e = hipEventRecord(e1, s);
+        if (st == SPOD_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+        if (st == SPOD_OK && e == hipSuccess) e = hipEventElapsedTime(&ms[c], e0, e1);
+        if (st == SPOD_OK && e != hipSuccess) st = hip_fail(e, "autotune timing");
+        if (st == SPOD_OK && (best <= 0 || ms[c] < best_ms)) {
+          best = cands[c];
+          best_ms = ms[c];
+        }
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      if (st != SPOD_OK) return st;
+      if (cache_path) {
+        std::ofstream f(cache_path, std::ios::app);
+        f << "{\"key\": \"" << key << "\", \"gram_target\": " << best << ", \"ms\": {";
+        for (int c = 0; c < 4; ++c) f << (c ? ", " : "") << "\"" << cands[c] << "\": " << ms[c];
+        f << "}}\n";
       }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (st != SPOD_OK) return st;
-    if (cache_path) {
-      std::ofstream f(cache_path, std::ios::app);
-      f << "{\"key\": \"" << key << "\", \"gram_target\": " << best << ", \"ms\": {";
-      for (int c = 0; c < 4; ++c) f << (c ? ", " : "") << "\"" << cands[c] << "\": " << ms[c];
-      f << "}}\n";
-    }
-  }
-  b->gram_target = best;
-  drop_graph(*b);
-  b->tables_ok = false;
-  if (chosen) *chosen = best;
-  return SPOD_OK;
+    b->gram_target = best;
+    drop_graph(*b);
+    b->tables_ok = false;
+    if (chosen) *chosen = best;
+    return SPOD_OK;
+  });
 }
 
 void spod_batch_destroy(spod_batch batch) {

@@ -5,6 +5,8 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <exception>
+#include <new>
 #include <string>
 
 #include "spod.h"
@@ -79,6 +81,21 @@ Plan plan_rows(const Plan& p, int64_t row0, int64_t rows);
 // error reporting (thread local message)
 spod_status fail(spod_status s, const std::string& msg);
 spod_status hip_fail(hipError_t e, const char* where);
+
+// Runs an entry point's body so that no exception crosses the C ABI: host
+// allocation failures become SPOD_ERR_ALLOC, anything else SPOD_ERR_INTERNAL.
+template <typename F>
+spod_status guarded(F&& body) noexcept {
+  try {
+    return body();
+  } catch (const std::bad_alloc&) {
+    return fail(SPOD_ERR_ALLOC, "host memory");
+  } catch (const std::exception& e) {
+    return fail(SPOD_ERR_INTERNAL, e.what());
+  } catch (...) {
+    return fail(SPOD_ERR_INTERNAL, "unexpected exception");
+  }
+}
 
 // --------------------------------------------------------------------------
 // stage launchers (each returns SPOD_OK or an error, never throws)

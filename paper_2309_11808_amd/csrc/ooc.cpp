@@ -16,6 +16,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <system_error>
 #include <thread>
 #include <vector>
 
@@ -66,40 +67,49 @@ char* mapped_range(void* p, size_t bytes) {
 
 size_t up256(size_t x) { return (x + 255) / 256 * 256; }
 
+// Runs part(0) .. part(t - 1), on threads where they can be started and on
+// this thread otherwise; returns once every part has finished.
+template <class F>
+void run_parts(unsigned t, F part) {
+  std::vector<std::thread> th;
+  th.reserve(t);
+  for (unsigned i = 0; i < t; ++i) {
+    try {
+      th.emplace_back(part, i);
+    } catch (const std::system_error&) {
+      part(i);
+    }
+  }
+  for (auto& x : th) x.join();
+}
+
 // Host copies of `n` rows of `width` bytes (strides in bytes), split over a
 // few threads once there is enough to copy.
 void copy_rows(char* dst, size_t dpitch, const char* src, size_t spitch, size_t width, size_t n) {
   const size_t total = width * n;
   unsigned t = std::min<unsigned>(8, std::max(1u, std::thread::hardware_concurrency()));
   if (total < (size_t(64) << 20) || t < 2) t = 1;
-  auto part = [&](size_t r0, size_t r1) {
+  if (t == 1) {
+    for (size_t r = 0; r < n; ++r) std::memcpy(dst + r * dpitch, src + r * spitch, width);
+    return;
+  }
+  if (n == 1) {   // one long row: split the bytes instead
+    const size_t step = (width + t - 1) / t;
+    run_parts(t, [=](unsigned i) {
+      const size_t b0 = std::min(width, i * step), b1 = std::min(width, b0 + step);
+      std::memcpy(dst + b0, src + b0, b1 - b0);
+    });
+    return;
+  }
+  const size_t step = (n + t - 1) / t;
+  run_parts(t, [=](unsigned i) {
+    const size_t r0 = std::min(n, i * step), r1 = std::min(n, r0 + step);
     if (dpitch == width && spitch == width) {
       std::memcpy(dst + r0 * width, src + r0 * width, (r1 - r0) * width);
     } else {
       for (size_t r = r0; r < r1; ++r) std::memcpy(dst + r * dpitch, src + r * spitch, width);
     }
-  };
-  if (t == 1 || n == 1) {
-    if (n == 1 && t > 1) {   // one long row: split the bytes instead
-      std::vector<std::thread> th;
-      const size_t step = (width + t - 1) / t;
-      for (unsigned i = 0; i < t; ++i) {
-        const size_t b0 = i * step, b1 = std::min(width, b0 + step);
-        if (b0 < b1) th.emplace_back([=] { std::memcpy(dst + b0, src + b0, b1 - b0); });
-      }
-      for (auto& x : th) x.join();
-    } else {
-      part(0, n);
-    }
-    return;
-  }
-  std::vector<std::thread> th;
-  const size_t step = (n + t - 1) / t;
-  for (unsigned i = 0; i < t; ++i) {
-    const size_t r0 = i * step, r1 = std::min(n, r0 + step);
-    if (r0 < r1) th.emplace_back(part, r0, r1);
-  }
-  for (auto& x : th) x.join();
+  });
 }
 
 }  // namespace
@@ -299,32 +309,10 @@ struct Run {
   }
 };
 
-}  // namespace
-}  // namespace spod
-
-using namespace spod;
-
-extern "C" {
-
-spod_status spod_ooc_create(spod_plan plan, spod_dtype dtype, int64_t chunk_rows, int64_t n_modes,
-                            int64_t resident, spod_ooc* out) {
-  if (!out) return fail(SPOD_ERR_INVALID_ARG, "out is NULL");
-  *out = nullptr;
-  Plan* p = reinterpret_cast<Plan*>(plan);
-  if (!p) return fail(SPOD_ERR_INVALID_ARG, "plan is NULL");
-  if (dtype != SPOD_F32 && dtype != SPOD_F64) return fail(SPOD_ERR_INVALID_ARG, "dtype");
-  if (chunk_rows < 1) return fail(SPOD_ERR_INVALID_ARG, "chunk_rows must be >= 1");
-  if (n_modes < 1 || n_modes > p->nblocks)
-    return fail(SPOD_ERR_INVALID_ARG, "n_modes must be in [1, nblocks]");
-  if (resident < 0) return fail(SPOD_ERR_INVALID_ARG, "resident must be >= 0");
-  if (p->nblocks > 64) return fail(SPOD_ERR_UNSUPPORTED, "nblocks > 64");
-  int cur = -1;
-  hipError_t e = hipGetDevice(&cur);
-  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-  if (cur != p->device) return fail(SPOD_ERR_INVALID_ARG, "plan belongs to another device");
-
-  Ooc* o = new (std::nothrow) Ooc();
-  if (!o) return fail(SPOD_ERR_ALLOC, "out-of-core object");
+// The allocations of spod_ooc_create (o is released on an error status).
+spod_status ooc_create_body(Ooc* o, Plan* p, spod_dtype dtype, int64_t chunk_rows,
+                            int64_t n_modes, int64_t resident, spod_ooc* out) {
+  hipError_t e;
   o->plan = p;
   o->dtype = dtype;
   o->n_modes = (int)n_modes;
@@ -387,6 +375,42 @@ spod_status spod_ooc_create(spod_plan plan, spod_dtype dtype, int64_t chunk_rows
   return SPOD_OK;
 }
 
+}  // namespace
+}  // namespace spod
+
+using namespace spod;
+
+extern "C" {
+
+spod_status spod_ooc_create(spod_plan plan, spod_dtype dtype, int64_t chunk_rows, int64_t n_modes,
+                            int64_t resident, spod_ooc* out) {
+  return guarded([&]() -> spod_status {
+    if (!out) return fail(SPOD_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    Plan* p = reinterpret_cast<Plan*>(plan);
+    if (!p) return fail(SPOD_ERR_INVALID_ARG, "plan is NULL");
+    if (dtype != SPOD_F32 && dtype != SPOD_F64) return fail(SPOD_ERR_INVALID_ARG, "dtype");
+    if (chunk_rows < 1) return fail(SPOD_ERR_INVALID_ARG, "chunk_rows must be >= 1");
+    if (n_modes < 1 || n_modes > p->nblocks)
+      return fail(SPOD_ERR_INVALID_ARG, "n_modes must be in [1, nblocks]");
+    if (resident < 0) return fail(SPOD_ERR_INVALID_ARG, "resident must be >= 0");
+    if (p->nblocks > 64) return fail(SPOD_ERR_UNSUPPORTED, "nblocks > 64");
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (cur != p->device) return fail(SPOD_ERR_INVALID_ARG, "plan belongs to another device");
+
+    Ooc* o = new (std::nothrow) Ooc();
+    if (!o) return fail(SPOD_ERR_ALLOC, "out-of-core object");
+    try {
+      return ooc_create_body(o, p, dtype, chunk_rows, n_modes, resident, out);
+    } catch (...) {
+      release(o);
+      throw;
+    }
+  });
+}
+
 spod_status spod_ooc_query(spod_ooc ooc, int64_t* chunk_rows, int64_t* n_chunks,
                            int64_t* n_resident, size_t* device_bytes, size_t* pinned_bytes) {
   Ooc* o = reinterpret_cast<Ooc*>(ooc);
@@ -402,64 +426,72 @@ spod_status spod_ooc_query(spod_ooc ooc, int64_t* chunk_rows, int64_t* n_chunks,
 spod_status spod_ooc_forward(spod_ooc ooc, const void* q, spod_read_fn read, void* user,
                              double* mean, double* lam, void* psi, int32_t* info, void* phi,
                              int32_t* n_valid, spod_stream stream) {
-  Ooc* o = reinterpret_cast<Ooc*>(ooc);
-  if (!o) return fail(SPOD_ERR_INVALID_ARG, "ooc is NULL");
-  if ((q == nullptr) == (read == nullptr))
-    return fail(SPOD_ERR_INVALID_ARG, "exactly one of q and read is required");
-  if (!mean || !lam || !psi || !phi)
-    return fail(SPOD_ERR_INVALID_ARG, "mean, lam, psi and phi are required");
-  const Plan& p = *o->plan;
-  int cur = -1;
-  hipError_t e = hipGetDevice(&cur);
-  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-  if (cur != p.device) return fail(SPOD_ERR_INVALID_ARG, "plan belongs to another device");
+  return guarded([&]() -> spod_status {
+    Ooc* o = reinterpret_cast<Ooc*>(ooc);
+    if (!o) return fail(SPOD_ERR_INVALID_ARG, "ooc is NULL");
+    if ((q == nullptr) == (read == nullptr))
+      return fail(SPOD_ERR_INVALID_ARG, "exactly one of q and read is required");
+    if (!mean || !lam || !psi || !phi)
+      return fail(SPOD_ERR_INVALID_ARG, "mean, lam, psi and phi are required");
+    const Plan& p = *o->plan;
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (cur != p.device) return fail(SPOD_ERR_INVALID_ARG, "plan belongs to another device");
 
-  const Mem q_mem = q ? classify(q) : Mem::Pageable;
-  const Mem phi_mem = classify(phi);
-  // pinned staging, kept for later calls
-  if (q_mem == Mem::Pageable && !o->pin_q[0]) {
-    const size_t b = (size_t)o->rows * (size_t)p.nt * o->esz;
-    for (auto& x : o->pin_q)
-      if ((e = hipHostMalloc(&x, b, hipHostMallocDefault)) != hipSuccess)
-        return e == hipErrorOutOfMemory ? fail(SPOD_ERR_ALLOC, "pinned staging")
-                                        : hip_fail(e, "hipHostMalloc");
-  }
-  if (phi_mem == Mem::Pageable && !o->pin_phi[0]) {
-    const size_t b = (size_t)p.nfreq * (size_t)o->n_modes * (size_t)o->rows * o->csz;
-    for (auto& x : o->pin_phi)
-      if ((e = hipHostMalloc(&x, b, hipHostMallocDefault)) != hipSuccess)
-        return e == hipErrorOutOfMemory ? fail(SPOD_ERR_ALLOC, "pinned staging")
-                                        : hip_fail(e, "hipHostMalloc");
-  }
+    const Mem q_mem = q ? classify(q) : Mem::Pageable;
+    const Mem phi_mem = classify(phi);
+    // pinned staging, kept for later calls
+    if (q_mem == Mem::Pageable && !o->pin_q[0]) {
+      const size_t b = (size_t)o->rows * (size_t)p.nt * o->esz;
+      for (auto& x : o->pin_q)
+        if ((e = hipHostMalloc(&x, b, hipHostMallocDefault)) != hipSuccess)
+          return e == hipErrorOutOfMemory ? fail(SPOD_ERR_ALLOC, "pinned staging")
+                                          : hip_fail(e, "hipHostMalloc");
+    }
+    if (phi_mem == Mem::Pageable && !o->pin_phi[0]) {
+      const size_t b = (size_t)p.nfreq * (size_t)o->n_modes * (size_t)o->rows * o->csz;
+      for (auto& x : o->pin_phi)
+        if ((e = hipHostMalloc(&x, b, hipHostMallocDefault)) != hipSuccess)
+          return e == hipErrorOutOfMemory ? fail(SPOD_ERR_ALLOC, "pinned staging")
+                                          : hip_fail(e, "hipHostMalloc");
+    }
 
-  hipStream_t st = (hipStream_t)stream;
-  // Modes going to pinned host memory while chunks are still coming in are
-  // stored by a kernel through the memory's device address: a DMA copy out
-  // was measured to wait for the DMA copies in (one engine), a kernel's
-  // stores run beside them.  With every chunk resident nothing comes in
-  // during the modes pass and the DMA copy is the faster one.
-  char* phi_mapped =
-      phi_mem == Mem::Pinned && o->nres < o->nchunks
-          ? mapped_range(phi, (size_t)p.nfreq * (size_t)o->n_modes * (size_t)p.M * o->csz)
-          : nullptr;
-  Run run{*o, static_cast<const char*>(q), q_mem, read, user, static_cast<char*>(phi), phi_mem,
-          phi_mapped, st};
-  spod_status r = run.hip(hipEventRecord(o->start, st), "hipEventRecord");
-  if (r == SPOD_OK) r = run.hip(hipStreamWaitEvent(o->cin, o->start, 0), "hipStreamWaitEvent");
-  if (r == SPOD_OK) r = run.hip(hipStreamWaitEvent(o->cout, o->start, 0), "hipStreamWaitEvent");
-  if (r == SPOD_OK) r = run.pass1();
-  if (r == SPOD_OK) r = launch_eig(p, o->gram, lam, psi, info, o->ws, st);
-  if (r == SPOD_OK) r = run.pass2(lam, psi, n_valid);
-  // nothing of this call may still run when it returns, error or not
-  hipError_t e1 = hipStreamSynchronize(st);
-  hipError_t e2 = hipStreamSynchronize(o->cin);
-  hipError_t e3 = hipStreamSynchronize(o->cout);
-  if (r != SPOD_OK) return r;
-  if (e1 != hipSuccess) return hip_fail(e1, "hipStreamSynchronize");
-  if (e2 != hipSuccess) return hip_fail(e2, "hipStreamSynchronize");
-  if (e3 != hipSuccess) return hip_fail(e3, "hipStreamSynchronize");
-  e = hipMemcpy(mean, o->mean, sizeof(double) * (size_t)p.M, hipMemcpyDefault);
-  return e == hipSuccess ? SPOD_OK : hip_fail(e, "hipMemcpy");
+    hipStream_t st = (hipStream_t)stream;
+    // Modes going to pinned host memory while chunks are still coming in are
+    // stored by a kernel through the memory's device address: a DMA copy out
+    // was measured to wait for the DMA copies in (one engine), a kernel's
+    // stores run beside them.  With every chunk resident nothing comes in
+    // during the modes pass and the DMA copy is the faster one.
+    char* phi_mapped =
+        phi_mem == Mem::Pinned && o->nres < o->nchunks
+            ? mapped_range(phi, (size_t)p.nfreq * (size_t)o->n_modes * (size_t)p.M * o->csz)
+            : nullptr;
+    Run run{*o, static_cast<const char*>(q), q_mem, read, user, static_cast<char*>(phi), phi_mem,
+            phi_mapped, st};
+    spod_status r = run.hip(hipEventRecord(o->start, st), "hipEventRecord");
+    if (r == SPOD_OK) r = run.hip(hipStreamWaitEvent(o->cin, o->start, 0), "hipStreamWaitEvent");
+    if (r == SPOD_OK) r = run.hip(hipStreamWaitEvent(o->cout, o->start, 0), "hipStreamWaitEvent");
+    try {
+      if (r == SPOD_OK) r = run.pass1();
+      if (r == SPOD_OK) r = launch_eig(p, o->gram, lam, psi, info, o->ws, st);
+      if (r == SPOD_OK) r = run.pass2(lam, psi, n_valid);
+    } catch (const std::bad_alloc&) {
+      r = fail(SPOD_ERR_ALLOC, "host memory");
+    } catch (...) {
+      r = fail(SPOD_ERR_INTERNAL, "unexpected exception");
+    }
+    // nothing of this call may still run when it returns, error or not
+    hipError_t e1 = hipStreamSynchronize(st);
+    hipError_t e2 = hipStreamSynchronize(o->cin);
+    hipError_t e3 = hipStreamSynchronize(o->cout);
+    if (r != SPOD_OK) return r;
+    if (e1 != hipSuccess) return hip_fail(e1, "hipStreamSynchronize");
+    if (e2 != hipSuccess) return hip_fail(e2, "hipStreamSynchronize");
+    if (e3 != hipSuccess) return hip_fail(e3, "hipStreamSynchronize");
+    e = hipMemcpy(mean, o->mean, sizeof(double) * (size_t)p.M, hipMemcpyDefault);
+    return e == hipSuccess ? SPOD_OK : hip_fail(e, "hipMemcpy");
+  });
 }
 
 void spod_ooc_destroy(spod_ooc ooc) {

@@ -49,7 +49,8 @@ def test_binding_signature_table_matches_header():
 def test_status_strings(lib):
     for code, name in [(0, b"SPOD_OK"), (-1, b"SPOD_ERR_INVALID_ARG"), (-2, b"SPOD_ERR_UNSUPPORTED"),
                        (-3, b"SPOD_ERR_ALLOC"), (-4, b"SPOD_ERR_HIP"), (-5, b"SPOD_ERR_NUMERIC"),
-                       (-6, b"SPOD_ERR_WORKSPACE"), (-7, b"SPOD_ERR_IO")]:
+                       (-6, b"SPOD_ERR_WORKSPACE"), (-7, b"SPOD_ERR_IO"),
+                       (-8, b"SPOD_ERR_INTERNAL")]:
         assert lib.spod_status_string(code) == name
     assert lib.spod_status_string(-99) == b"SPOD_ERR_UNKNOWN"
 
