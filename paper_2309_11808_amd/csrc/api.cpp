@@ -1,6 +1,7 @@
 // extern "C" entry points of libspod: validation, plan lifetime, dispatch.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -127,7 +128,7 @@ void spod_plan_destroy(spod_plan plan) {
   if (hipGetDevice(&cur) == hipSuccess && cur != p->device) (void)hipSetDevice(p->device);
   (void)hipDeviceSynchronize();
   void* bufs[] = {p->d_window, p->d_window32, p->d_weights, p->d_sqrtw,
-                  p->d_sqrtw32, p->d_tw64, p->d_tw32, p->d_what};
+                  p->d_sqrtw32, p->d_tw64, p->d_tw32, p->d_what, p->d_oddw64, p->d_oddw32};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (cur != p->device) (void)hipSetDevice(cur);
@@ -199,6 +200,14 @@ spod_status spod_plan_create(int64_t nspace, int64_t nvar, int64_t nt, int64_t n
       }
       if (n != 1) p->radices.n = 0;   // not reachable for nfft <= 20480 (at most 15 factors)
     }
+    int odd_entries = 0;
+    for (int i = 0; i < p->radices.n; ++i) {
+      const int r = p->radices.r[i];
+      if (r % 2 == 0) continue;
+      p->radices.kpt[i] = general_odd_kpt(r, (int)(nfft / r));
+      p->radices.toff[i] = odd_entries;
+      odd_entries += general_odd_entries(r, p->radices.kpt[i]);
+    }
     p->kappa = 1.0 / std::sqrt((double)(L - 1) * sw2);
     // DFT of the window at every one-sided bin, What_k = sum_n w[n] e^{-2 pi i k n / N},
     // in long double with exact integer reduction of k*n mod N
@@ -259,6 +268,23 @@ spod_status spod_plan_create(int64_t nspace, int64_t nvar, int64_t nt, int64_t n
       sq[m] = std::sqrt(W[m]);
       sq32[m] = (float)sq[m];
     }
+    // the odd stages' tables, from the same rounded twiddles
+    std::vector<double2> oddw(std::max(odd_entries, 1));
+    std::vector<float2> oddw32(oddw.size());
+    for (int i = 0; i < p->radices.n; ++i) {
+      const int r = p->radices.r[i], kpt = p->radices.kpt[i];
+      if (r % 2 == 0) continue;
+      const int hm = (r - 1) / 2, G = (hm + 1 + kpt - 1) / kpt;
+      size_t e = (size_t)p->radices.toff[i];
+      for (int g = 0; g < G; ++g)
+        for (int j = 1; j <= hm; ++j)
+          for (int c = 0; c < kpt; ++c, ++e) {
+            const int k = std::min(g + c * G, hm);
+            const int64_t t = (int64_t)(nfft / r) * ((int64_t)j * k % r);
+            oddw[e] = tw[t];
+            oddw32[e] = tw32[t];
+          }
+    }
     struct Up { void** dst; const void* src; size_t bytes; } ups[] = {
         {(void**)&p->d_window, w.data(), sizeof(double) * nfft},
         {(void**)&p->d_window32, w32.data(), sizeof(float) * nfft},
@@ -268,6 +294,8 @@ spod_status spod_plan_create(int64_t nspace, int64_t nvar, int64_t nt, int64_t n
         {(void**)&p->d_tw64, tw.data(), sizeof(double2) * nfft},
         {(void**)&p->d_tw32, tw32.data(), sizeof(float2) * nfft},
         {(void**)&p->d_what, what.data(), sizeof(double2) * K},
+        {(void**)&p->d_oddw64, oddw.data(), sizeof(double2) * oddw.size()},
+        {(void**)&p->d_oddw32, oddw32.data(), sizeof(float2) * oddw32.size()},
     };
     for (auto& u : ups) {
       e = hipMalloc(u.dst, u.bytes);

@@ -10,12 +10,15 @@
 // radix r with current length n and stride s maps
 //   y[q + s (r p + k)] = W_n^{p k} sum_j x[q + s (p + j n / r)] W_r^{j k},
 // every output a direct radix-r sum (so a prime factor such as 73 needs no
-// special case), the W_r^t of every stage copied from the plan's table W_N^t
-// into LDS (at most the sum of the radices, 89 values for 8760).  For an odd
-// radix one work item yields the outputs k and r - k from (r - 1) / 2 terms
-// of the symmetric sums, a quarter of the multiplications.  A thread
-// computes its outputs of a stage into registers, the workgroup synchronises,
-// and the outputs overwrite the inputs in LDS.  The mean comes from the FP64
+// special case).  W_n^{p k} = W_N^{(N / n) p k} is read from the plan's table
+// W_N^t (p k < n, so no reduction mod N).  For an odd radix the outputs k and
+// r - k come from (r - 1) / 2 terms of the symmetric sums, a quarter of the
+// multiplications; a work item takes up to 6 such pairs of one butterfly,
+// all lanes of a wavefront the same pairs, so their W_r^{jk} come from the
+// plan's per-stage table through scalar loads.  With two LDS buffers a stage
+// reads one and writes the other; with one, a thread computes its outputs of
+// a stage into registers, the workgroup synchronises, and the outputs
+// overwrite the inputs.  The mean comes from the FP64
 // mean pass.  A workgroup takes the blocks of its pair in turn, loading the
 // next block while it transforms the current one.  Consecutive workgroups of
 // one XCD take consecutive pairs, so their 16-byte stores of neighbouring
@@ -106,7 +109,7 @@ __device__ __forceinline__ cpx_t<TC> even_output(const cpx_t<TC>* __restrict__ X
     if (t >= r) t -= r;
   }
   const TC sr = (ar[0] + ar[1]) + (ar[2] + ar[3]), si = (ai[0] + ai[1]) + (ai[2] + ai[3]);
-  const C t2 = tw[(int)(((int64_t)wn * pp * k) % N)];
+  const C t2 = tw[wn * pp * k];
   return mk<TC>(sr * t2.x - si * t2.y, sr * t2.y + si * t2.x);
 }
 
@@ -141,8 +144,8 @@ __device__ __forceinline__ void odd_pair(const cpx_t<TC>* __restrict__ X,
   }
   const TC ykr = x0.x + Ar + Bi, yki = x0.y + Ai - Br;
   const TC yrr = x0.x + Ar - Bi, yri = x0.y + Ai + Br;
-  const C t0 = tw[(int)(((int64_t)wn * pp * kk) % N)];
-  const C t1 = tw[(int)(((int64_t)wn * pp * (r - kk)) % N)];
+  const C t0 = tw[wn * pp * kk];
+  const C t1 = tw[wn * pp * (r - kk)];
   y0 = mk<TC>(ykr * t0.x - yki * t0.y, ykr * t0.y + yki * t0.x);
   y1 = mk<TC>(yrr * t1.x - yri * t1.y, yrr * t1.y + yri * t1.x);
   o0 = qq + s * (r * pp + kk);
@@ -165,71 +168,128 @@ __device__ __forceinline__ void even_butterfly(const cpx_t<TC>* __restrict__ X,
 #pragma unroll
   for (int j = 0; j < RS; ++j) x[j] = X[base + j * js];
   dft_r<RS>(x);
-  const int step = (int)(((int64_t)wn * pp) % N);   // W_n^{p k} = W_N^{k step}
+  const int step = wn * pp;   // W_n^{p k} = W_N^{k step}, k step < N
   int t = 0;
   const int out = qq + s * RS * pp;
   Y[out] = x[0];
 #pragma unroll
   for (int k = 1; k < RS; ++k) {
     t += step;
-    if (t >= N) t -= N;
     const C w = tw[t];
     Y[out + s * k] = mk<TC>(x[k].x * w.x - x[k].y * w.y, x[k].x * w.y + x[k].y * w.x);
   }
 }
 
-// Two work items of an odd-radix stage in one pass: the outputs k1 = g and
-// k2 = g + hh (when k2 < h = (r + 1) / 2), with their partners r - k, for
-// butterfly bf.  The loads of x_j and x_{r-j} and their sum and difference are
-// shared by both; writes every output it owns straight to Y.
-template <typename TC>
-__device__ __forceinline__ void odd_two(const cpx_t<TC>* __restrict__ X, const cpx_t<TC>* __restrict__ Wr,
-                                        const cpx_t<TC>* __restrict__ tw, cpx_t<TC>* __restrict__ Y,
-                                        int it, int NB, int hh, int r, int s, int m, int wn, int N,
-                                        float inv_nb, float inv_s) {
+// Work item of an odd-radix stage: the output pairs k_c = g + c G, c < KPT,
+// of butterfly bf, with the symmetric sums of odd_pair.  The loads of x_j and
+// x_{r-j} and their sum and difference are shared by the KPT pairs.  g is
+// the same for every lane of the wavefront (the butterflies of one g are
+// padded to a multiple of 64 work items), so the stage's table Tg[j][c] =
+// W_r^{(j + 1) k_c} (row g of the plan's odd-stage table) is read at
+// wave-uniform addresses, into scalar registers, with no index arithmetic.
+// Pairs with k_c >= h = (r + 1) / 2 use the last pair's values and store
+// nothing.
+template <int KPT, typename TC>
+__device__ __forceinline__ void odd_uniform(const cpx_t<TC>* __restrict__ X,
+                                            const cpx_t<TC>* __restrict__ Tg,
+                                            const cpx_t<TC>* __restrict__ tw,
+                                            cpx_t<TC>* __restrict__ Y, int bf, int g, int G, int r,
+                                            int s, int m, int wn, float inv_s) {
   using C = cpx_t<TC>;
-  const int h = (r + 1) / 2;
-  const DivMod a = divmod(it, NB, inv_nb);    // it = bf + NB * g
-  const int g = a.q, bf = a.r;
-  const int k1 = g, k2 = g + hh;
+  const int h = (r + 1) / 2, hm = h - 1;
   const DivMod b = divmod(bf, s, inv_s);      // bf = qq + s * pp
   const int qq = b.r, pp = b.q;
   const int base = qq + s * pp, js = s * m;
   const C x0 = X[base];
-  TC a1r = 0, a1i = 0, b1r = 0, b1i = 0, a2r = 0, a2i = 0, b2r = 0, b2i = 0;
-  int t1 = 0, t2 = 0;
+  TC ar[KPT], ai[KPT], br[KPT], bi[KPT];
+#pragma unroll
+  for (int c = 0; c < KPT; ++c) ar[c] = ai[c] = br[c] = bi[c] = 0;
   const C* pa = X + base + js;
   const C* pb = X + base + (r - 1) * js;
-  for (int j = 1; 2 * j < r; ++j, pa += js, pb -= js) {
-    t1 += k1;
-    if (t1 >= r) t1 -= r;
-    t2 += k2;
-    if (t2 >= r) t2 -= r;
+  for (int j = 0; j < hm; ++j, pa += js, pb -= js) {
     const C xa = *pa, xb = *pb;
     const TC sr = xa.x + xb.x, si = xa.y + xb.y, dr = xa.x - xb.x, di = xa.y - xb.y;
-    const C w1 = Wr[t1], w2 = Wr[t2];
-    a1r += sr * w1.x;
-    a1i += si * w1.x;
-    b1r -= dr * w1.y;
-    b1i -= di * w1.y;
-    a2r += sr * w2.x;
-    a2i += si * w2.x;
-    b2r -= dr * w2.y;
-    b2i -= di * w2.y;
-  }
-  auto put = [&](int k, TC ar, TC ai, TC br, TC bi) {
-    // y_k = x0 + A - iB, y_{r-k} = x0 + A + iB, then W_n^{p k}, W_n^{p (r-k)}
-    const TC ykr = x0.x + ar + bi, yki = x0.y + ai - br;
-    const C t0 = tw[(int)(((int64_t)wn * pp * k) % N)];
-    Y[qq + s * (r * pp + k)] = mk<TC>(ykr * t0.x - yki * t0.y, ykr * t0.y + yki * t0.x);
-    if (k > 0) {
-      const TC yrr = x0.x + ar - bi, yri = x0.y + ai + br;
-      const C t1w = tw[(int)(((int64_t)wn * pp * (r - k)) % N)];
-      Y[qq + s * (r * pp + r - k)] = mk<TC>(yrr * t1w.x - yri * t1w.y, yrr * t1w.y + yri * t1w.x);
+    const C* w = Tg + j * KPT;
+#pragma unroll
+    for (int c = 0; c < KPT; ++c) {
+      const C wc = w[c];
+      ar[c] += sr * wc.x;
+      ai[c] += si * wc.x;
+      br[c] -= dr * wc.y;
+      bi[c] -= di * wc.y;
     }
-  };
-  put(k1, a1r, a1i, b1r, b1i);
-  if (k2 < h) put(k2, a2r, a2i, b2r, b2i);
+  }
+  // y_k = x0 + A - iB, y_{r-k} = x0 + A + iB, then W_n^{p k}, W_n^{p (r-k)}
+  const int wp = wn * pp;
+#pragma unroll
+  for (int c = 0; c < KPT; ++c) {
+    const int k = g + c * G;
+    if (k < h) {
+      const TC ykr = x0.x + ar[c] + bi[c], yki = x0.y + ai[c] - br[c];
+      const C t0 = tw[wp * k];
+      Y[qq + s * (r * pp + k)] = mk<TC>(ykr * t0.x - yki * t0.y, ykr * t0.y + yki * t0.x);
+      if (k > 0) {
+        const TC yrr = x0.x + ar[c] - bi[c], yri = x0.y + ai[c] + br[c];
+        const C t1 = tw[wp * (r - k)];
+        Y[qq + s * (r * pp + r - k)] = mk<TC>(yrr * t1.x - yri * t1.y, yrr * t1.y + yri * t1.x);
+      }
+    }
+  }
+}
+
+// An odd stage of the two-buffer kernel: work items (g, bf) with bf padded to
+// NBp, a multiple of 64, so every wavefront has one g.
+template <int KPT, typename TC>
+__device__ __forceinline__ void odd_stage(const cpx_t<TC>* __restrict__ X,
+                                          const cpx_t<TC>* __restrict__ T,
+                                          const cpx_t<TC>* __restrict__ tw,
+                                          cpx_t<TC>* __restrict__ Y, int tid, int NB, int r, int s,
+                                          int m, int wn) {
+  const int h = (r + 1) / 2, hm = h - 1, G = (h + KPT - 1) / KPT;
+  const int NBp = (NB + 63) & ~63;
+  const float inv_nbp = 1.0f / (float)NBp, inv_s = 1.0f / (float)s;
+  for (int it = tid; it < NBp * G; it += GEN_THREADS) {
+    // NBp G is a multiple of 64: whole wavefronts run this body
+    const int g = __builtin_amdgcn_readfirstlane(divmod(it, NBp, inv_nbp).q);
+    const int bf = it - g * NBp;
+    if (bf < NB)
+      odd_uniform<KPT, TC>(X, T + (size_t)g * hm * KPT, tw, Y, bf, g, G, r, s, m, wn, inv_s);
+  }
+}
+
+// One stage of the two-buffer kernel, X -> Y (W_n^{p k} = tw[wn p k], wn = N / n).
+template <typename TC>
+__device__ __forceinline__ void pp_stage(const cpx_t<TC>* __restrict__ X,
+                                         cpx_t<TC>* __restrict__ Y,
+                                         const cpx_t<TC>* __restrict__ tw,
+                                         const cpx_t<TC>* __restrict__ Wr,
+                                         const cpx_t<TC>* __restrict__ oddw, const Radices& rad,
+                                         int st, int tid, int N, int r, int s, int m, int wn) {
+  if (r % 2 == 1) {
+    const int NB = N / r;
+    const cpx_t<TC>* T = oddw + rad.toff[st];
+    switch (rad.kpt[st]) {
+      case 1: odd_stage<1, TC>(X, T, tw, Y, tid, NB, r, s, m, wn); break;
+      case 2: odd_stage<2, TC>(X, T, tw, Y, tid, NB, r, s, m, wn); break;
+      case 3: odd_stage<3, TC>(X, T, tw, Y, tid, NB, r, s, m, wn); break;
+      case 4: odd_stage<4, TC>(X, T, tw, Y, tid, NB, r, s, m, wn); break;
+      case 5: odd_stage<5, TC>(X, T, tw, Y, tid, NB, r, s, m, wn); break;
+      default: odd_stage<6, TC>(X, T, tw, Y, tid, NB, r, s, m, wn); break;
+    }
+    static_assert(GENERAL_MAX_KPT == 6, "one case per output-pair count");
+  } else if (r == 8 || r == 4 || r == 2) {
+    const float inv_s = 1.0f / (float)s;
+    const int NB = N / r;
+    for (int bf = tid; bf < NB; bf += GEN_THREADS) {
+      if (r == 8) even_butterfly<8, TC>(X, tw, Y, bf, s, m, wn, N, inv_s);
+      else if (r == 4) even_butterfly<4, TC>(X, tw, Y, bf, s, m, wn, N, inv_s);
+      else even_butterfly<2, TC>(X, tw, Y, bf, s, m, wn, N, inv_s);
+    }
+  } else {
+    const float inv_s = 1.0f / (float)s, inv_r = 1.0f / (float)r;
+    for (int o = tid; o < N; o += GEN_THREADS)
+      Y[o] = even_output<TC>(X, Wr, tw, o, r, s, m, wn, N, inv_s, inv_r);
+  }
 }
 
 // PP: two LDS buffers, every stage reads one and writes the other (no
@@ -244,7 +304,8 @@ template <typename TC, typename TIN, bool PP, int MAXU, int MAXI = (2 * MAXU + 2
 __global__ __launch_bounds__(GEN_THREADS) void blocks_dft_general_kernel(
     const TIN* __restrict__ q, const double* __restrict__ mean, const double* __restrict__ window,
     const cpx_t<TC>* __restrict__ tw, cpx_t<TC>* __restrict__ qhat, int64_t M, int64_t nt, int N,
-    int step, int L, int K, TC kappa, Radices rad, int64_t per_xcd) {
+    int step, int L, int K, TC kappa, Radices rad, int64_t per_xcd,
+    const cpx_t<TC>* __restrict__ oddw) {
   using C = cpx_t<TC>;
   extern __shared__ unsigned char smem[];
   C* const B0 = reinterpret_cast<C*>(smem);
@@ -323,24 +384,7 @@ __global__ __launch_bounds__(GEN_THREADS) void blocks_dft_general_kernel(
       const int wn = N / n;          // W_n = W_N^(N/n)
       const C* Wr = Wt + off;
       if constexpr (PP) {
-        if (r % 2 == 1) {
-          const int NB = N / r, hh = ((r + 1) / 2 + 1) / 2;
-          const float inv_nb = 1.0f / (float)NB, inv_s = 1.0f / (float)s;
-          for (int it = tid; it < NB * hh; it += GEN_THREADS)
-            odd_two<TC>(X, Wr, tw, Y, it, NB, hh, r, s, m, wn, N, inv_nb, inv_s);
-        } else if (r == 8 || r == 4 || r == 2) {
-          const float inv_s = 1.0f / (float)s;
-          const int NB = N / r;
-          for (int bf = tid; bf < NB; bf += GEN_THREADS) {
-            if (r == 8) even_butterfly<8, TC>(X, tw, Y, bf, s, m, wn, N, inv_s);
-            else if (r == 4) even_butterfly<4, TC>(X, tw, Y, bf, s, m, wn, N, inv_s);
-            else even_butterfly<2, TC>(X, tw, Y, bf, s, m, wn, N, inv_s);
-          }
-        } else {
-          const float inv_s = 1.0f / (float)s, inv_r = 1.0f / (float)r;
-          for (int o = tid; o < N; o += GEN_THREADS)
-            Y[o] = even_output<TC>(X, Wr, tw, o, r, s, m, wn, N, inv_s, inv_r);
-        }
+        pp_stage<TC>(X, Y, tw, Wr, oddw, rad, st, tid, N, r, s, m, wn);
         lds_barrier();
         C* tmp = X;
         X = Y;
@@ -424,7 +468,9 @@ spod_status launch_general_pp(const Plan& p, const TIN* q, const double* mean, v
   hipLaunchKernelGGL((blocks_dft_general_kernel<TC, TIN, PP, MAXU>), dim3((unsigned)wgs),
                      dim3(GEN_THREADS), lds, st, q, mean, p.d_window, tw, static_cast<C*>(qhat),
                      (int64_t)p.M, (int64_t)p.nt, (int)p.nfft, (int)p.step, (int)p.nblocks,
-                     (int)p.nfreq, (TC)p.kappa, p.radices, per_xcd);
+                     (int)p.nfreq, (TC)p.kappa, p.radices, per_xcd,
+                     static_cast<const C*>(sizeof(TC) == 8 ? (const void*)p.d_oddw64
+                                                           : (const void*)p.d_oddw32));
   e = hipGetLastError();
   return e == hipSuccess ? SPOD_OK : hip_fail(e, "blocks_dft_general_kernel");
 }
@@ -448,6 +494,32 @@ spod_status launch_general_t(const Plan& p, const TIN* q, const double* mean, vo
 }
 
 }  // namespace
+
+int general_odd_entries(int r, int kpt) {
+  const int hm = (r - 1) / 2, G = (hm + kpt) / kpt;
+  return G * hm * kpt;
+}
+
+int general_odd_kpt(int r, int nb) {
+  // instructions of one work item: per term a shared load, sum and difference
+  // (about 6) plus 4 multiply-adds per pair; per pair about 30 to finish and
+  // store.  A stage costs the work items of the busiest SIMD (the wavefronts
+  // of a workgroup spread over its 4 SIMDs).
+  const int hm = (r - 1) / 2, h = hm + 1;
+  const int64_t nbp = (nb + 63) / 64 * 64;
+  int best = 1;
+  int64_t best_cost = -1;
+  for (int kpt = 1; kpt <= GENERAL_MAX_KPT; ++kpt) {
+    const int64_t G = (h + kpt - 1) / kpt;
+    const int64_t waves = nbp / 64 * G;
+    const int64_t cost = (waves + 3) / 4 * ((int64_t)hm * (6 + 4 * kpt) + 30 * kpt);
+    if (best_cost < 0 || cost < best_cost) {
+      best = kpt;
+      best_cost = cost;
+    }
+  }
+  return best;
+}
 
 spod_status launch_blocks_dft_general(const Plan& p, const void* q, spod_dtype dtype,
                                       const double* mean, void* qhat, hipStream_t st) {

@@ -17,11 +17,23 @@ namespace spod {
 // plan
 // --------------------------------------------------------------------------
 // Radix factorisation of N_f for the general transform (radices 8, 4, 2, 3,
-// 5, 7, then any remaining primes in increasing order).
+// 5, 7, then any remaining primes in increasing order).  For an odd radix,
+// kpt is the number of output pairs one work item computes and toff the
+// offset of the stage's table of W_r^{jk} in the plan's d_oddw (entries);
+// both are 0 for the radices 2, 4 and 8.
 struct Radices {
   int n = 0;
   int r[32] = {};
+  int kpt[32] = {};
+  int toff[32] = {};
 };
+// Output pairs per work item of an odd stage of radix r with nb butterflies
+// (from a cost model of the stage's instructions per SIMD).
+int general_odd_kpt(int r, int nb);
+// Entries of the odd stage's table: G (h - 1) kpt with h = (r + 1) / 2 and
+// G = ceil(h / kpt).
+int general_odd_entries(int r, int kpt);
+constexpr int GENERAL_MAX_KPT = 6;
 constexpr int SPOD_GENERAL_MAX_NFFT = 20480;   // complex64 blocks of one transform fill 160 KiB LDS
 
 struct Plan {
@@ -66,6 +78,10 @@ struct Plan {
   float* d_sqrtw32 = nullptr;  // [M]
   double2* d_tw64 = nullptr;   // [nfft] e^{-2 pi i j / nfft}
   float2* d_tw32 = nullptr;    // [nfft]
+  // general transform: per odd stage, T[g][j][c] = W_r^{(j + 1) k}, k =
+  // min(g + c G, (r - 1) / 2), for g < G, j < (r - 1) / 2, c < kpt
+  double2* d_oddw64 = nullptr;
+  float2* d_oddw32 = nullptr;
 };
 
 bool is_complex128(const Plan& p);

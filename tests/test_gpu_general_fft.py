@@ -4,7 +4,11 @@ the FP64 oracle (whose DFT is pinned to numpy's rfft for any length).
 
 Lengths cover small primes, a large prime factor (73, as in the paper's
 8760 = 2^3 3 5 73 hourly blocks), odd N_f (K = (N_f + 1) / 2), powers of two
-above 1024, ragged M (odd: a last unpaired row) and several overlaps."""
+above 1024, ragged M (odd: a last unpaired row) and several overlaps.  Odd
+radices take 2, 4 or 8 output pairs per work item from a table of W_r^{jk}
+(1001 = 7 11 13 and 527 = 17 31 reach every count, with pairs beyond
+(r + 1) / 2 that store nothing); a prime whose table does not fit in LDS
+(1019) takes the sums with modular indices instead."""
 import numpy as np
 import pytest
 import torch
@@ -32,7 +36,9 @@ def _plan(p, precision):
 CASES = [  # nfft, noverlap, M, L
     (12, 6, 37, 6), (24, 12, 64, 5), (60, 30, 101, 4), (73, 0, 50, 3), (100, 50, 33, 4),
     (146, 73, 20, 3), (360, 180, 17, 3), (2048, 1024, 9, 3), (730, 365, 12, 3),
+    (1001, 500, 15, 3), (527, 263, 19, 3), (1019, 509, 11, 3),
 ]
+C64_CASES = CASES[:5] + CASES[-3:] + [(8760, 4380, 7, 2)]
 
 
 @pytest.mark.parametrize("nfft,nov,M,L", CASES, ids=[f"N{c[0]}" for c in CASES])
@@ -51,7 +57,7 @@ def test_fourier_blocks_match_oracle_fp64(nfft, nov, M, L):
     plan.close()
 
 
-@pytest.mark.parametrize("nfft,nov,M,L", CASES[:5], ids=[f"N{c[0]}" for c in CASES[:5]])
+@pytest.mark.parametrize("nfft,nov,M,L", C64_CASES, ids=[f"N{c[0]}" for c in C64_CASES])
 def test_fourier_blocks_match_oracle_complex64(nfft, nov, M, L):
     nt = (L - 1) * (nfft - nov) + nfft + 5
     p = fields.random_rows(M, nt, nfft, nov, seed=nfft + 1, offset=1.5, dtype=torch.float32)
