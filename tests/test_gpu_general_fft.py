@@ -5,10 +5,9 @@ the FP64 oracle (whose DFT is pinned to numpy's rfft for any length).
 Lengths cover small primes, a large prime factor (73, as in the paper's
 8760 = 2^3 3 5 73 hourly blocks), odd N_f (K = (N_f + 1) / 2), powers of two
 above 1024, ragged M (odd: a last unpaired row) and several overlaps.  Odd
-radices take 2, 4 or 8 output pairs per work item from a table of W_r^{jk}
-(1001 = 7 11 13 and 527 = 17 31 reach every count, with pairs beyond
-(r + 1) / 2 that store nothing); a prime whose table does not fit in LDS
-(1019) takes the sums with modular indices instead."""
+radices take 1 to 6 output pairs per work item, with W_r^{jk} from the plan's
+per-stage table (1001 = 7 11 13, 527 = 17 31 and the prime 1019 reach several
+counts, with table rows beyond (r + 1) / 2 pairs that store nothing)."""
 import numpy as np
 import pytest
 import torch
