@@ -89,7 +89,8 @@ typedef enum {
 typedef enum {
   SPOD_OPT_MAX_SWEEPS = 0, /* Jacobi sweep cap (default 40; 0 forces non-convergence)   */
   SPOD_OPT_GRAM_SPLIT = 1, /* slices of M per frequency in the Gram (0 = automatic)     */
-  SPOD_OPT_FFT_TILE = 2    /* degrees of freedom per transform workgroup (0 = automatic) */
+  SPOD_OPT_FFT_TILE = 2    /* degrees of freedom per transform workgroup: 16 or 32
+                              (0 = automatic: 32 for nfft <= 256, else 16)            */
 } spod_option;
 
 /* Create a plan.  Follows the problem statement of Sec. 2.3: Q is M x N_t with

@@ -341,8 +341,8 @@ spod_status spod_plan_set_option(spod_plan plan, spod_option opt, int64_t value)
       p->gram_split_opt = value;
       break;
     case SPOD_OPT_FFT_TILE:
-      if (value != 0 && value != 16 && value != 32 && value != 64)
-        return fail(SPOD_ERR_INVALID_ARG, "fft tile must be 0, 16, 32 or 64");
+      if (value != 0 && value != 16 && value != 32)
+        return fail(SPOD_ERR_INVALID_ARG, "fft tile must be 0, 16 or 32");
       p->fft_tile_opt = value;
       break;
     default:

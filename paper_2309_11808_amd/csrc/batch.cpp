@@ -164,6 +164,10 @@ spod_status build_tables(Batch& b, const void* const* q, spod_dtype dtype, char*
     Group g;
     g.key = kv.first;
     const int T = fft_group_tile(kv.first, b.prec);
+    // the longest workgroups (most blocks) first, so the short ones fill the
+    // end of the launch; a workgroup's result does not depend on its place
+    std::stable_sort(kv.second.begin(), kv.second.end(),
+                     [](const FftItem& x, const FftItem& y) { return x.L > y.L; });
     int64_t start = 0;
     for (auto& it : kv.second) {
       it.start = (int)start;
@@ -199,6 +203,10 @@ spod_status build_tables(Batch& b, const void* const* q, spod_dtype dtype, char*
   for (auto& kv : gram) {
     Group g;
     g.key = kv.first;
+    // the longest slices first (as for the transform)
+    std::stable_sort(kv.second.begin(), kv.second.end(), [](const GramItem& x, const GramItem& y) {
+      return (x.M + x.S - 1) / x.S > (y.M + y.S - 1) / y.S;
+    });
     int64_t start = 0;
     for (auto& it : kv.second) {
       it.start = (int)start;

@@ -309,3 +309,29 @@ def test_stage_errors_on_device():
     # precision and options are frozen after the first stage call
     assert lib().spod_plan_set_precision(plan._h, N.SPOD_PREC_FP32) == N.SPOD_ERR_INVALID_ARG
     assert math.isfinite(plan.workspace_bytes)
+
+
+@pytest.mark.parametrize("nfft", [64, 256, 512])
+@pytest.mark.parametrize("precision", ["fp64", "bf16x4"])
+def test_fft_tile_option(nfft, precision):
+    """The transform tile (16 or 32 DOFs per workgroup) only regroups DOFs:
+    every tile gives the same blocks bit for bit, and other values are
+    rejected."""
+    from paper_2309_11808_amd import SpodError
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    p = _rand_problem(333, 5 * nfft // 2 + 7, nfft, nfft // 2, seed=nfft + 7)
+    q = _dev(p.q.to(dt))
+    ref = None
+    for tile in (0, 16, 32):
+        plan = _plan(p, precision, fft_tile=tile)
+        qhat, mean = plan.blocks_fft(q)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = (qhat.clone(), mean.clone())
+        else:
+            assert torch.equal(qhat, ref[0]) and torch.equal(mean, ref[1]), tile
+        plan.close()
+    for bad in (8, 64, -1):
+        with pytest.raises(SpodError) as ei:
+            _plan(p, precision, fft_tile=bad)
+        assert ei.value.status == -1
