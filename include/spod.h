@@ -262,7 +262,10 @@ spod_status spod_batch_item_info(spod_batch batch, int64_t i, spod_batch_item* i
  * device buffers of the queried sizes, 256-byte aligned.  When q, out or ws
  * differ from the previous call the work tables are rebuilt (a synchronous
  * copy) and the graph is captured again.  Calls on one batch must not
- * overlap. */
+ * overlap.  With grouped launches, the problems with more than 32 blocks run
+ * on a second stream that the batch owns, forked from `stream` (after all
+ * work already queued on it) and joined back into it before the call's work
+ * ends, so the caller sees one stream either way. */
 spod_status spod_batch_forward(spod_batch batch, const void* const* q, spod_dtype dtype,
                                void* out, void* ws, size_t ws_bytes, spod_stream stream);
 

@@ -31,9 +31,18 @@ struct ProblemSlots {
 
 struct Group {
   int key = 0;               // nfft (transform) or ceil(L/16) (Gram)
+  int chain = 0;             // 0: problems with L <= 32, 1: L > 32
   size_t off = 0;            // byte offset of the item array in the table
   int n = 0, wgs = 0;
 };
+
+// Problems with more than 32 blocks form a second chain of launches: their
+// Gram (64 x 64 tiles) is bound by MFMA issue and their eigensolves by LDS
+// latency, while the other chain's transforms and modes are bound by HBM, so
+// the two run side by side (a fork onto a second stream, parallel branches of
+// the graph).
+constexpr int NCHAIN = 2;
+int chain_of(const Plan& p) { return p.nblocks > 32 ? 1 : 0; }
 
 }  // namespace
 
@@ -56,10 +65,12 @@ struct Batch {
   bool tables_ok = false;
   std::vector<Group> fft_groups, gram_groups, eig_groups;   // eig: by L bucket (16, 32, 64)
   std::vector<int> fft_fallback;                 // problems launched on their own
-  Group scale_g, comb_g, modes_g;
+  Group scale_g[NCHAIN], comb_g[NCHAIN], modes_g[NCHAIN];
   size_t modes_lds = 0;
 
   hipStream_t cap_stream = nullptr;
+  hipStream_t side = nullptr;                    // the second chain
+  hipEvent_t fork = nullptr, join = nullptr;
   hipGraphExec_t exec = nullptr;
 };
 
@@ -129,8 +140,8 @@ void put(std::vector<char>& host, Group& g, const std::vector<It>& items) {
 spod_status build_tables(Batch& b, const void* const* q, spod_dtype dtype, char* out, char* ws) {
   std::vector<char> host;
   const bool half = b.prec == SPOD_PREC_FP16X4;
-  // transform: grouped by nfft
-  std::map<int, std::vector<FftItem>> fft;
+  // transform: grouped by chain and nfft
+  std::map<std::pair<int, int>, std::vector<FftItem>> fft;
   b.fft_fallback.clear();
   for (size_t i = 0; i < b.pb.size(); ++i) {
     const ProblemSlots& s = b.pb[i];
@@ -157,13 +168,14 @@ spod_status build_tables(Batch& b, const void* const* q, spod_dtype dtype, char*
       it.mb.wr[j] = p.what_re[j];
       it.mb.wi[j] = p.what_im[j];
     }
-    fft[(int)p.nfft].push_back(it);
+    fft[{chain_of(p), (int)p.nfft}].push_back(it);
   }
   b.fft_groups.clear();
   for (auto& kv : fft) {
     Group g;
-    g.key = kv.first;
-    const int T = fft_group_tile(kv.first, b.prec);
+    g.chain = kv.first.first;
+    g.key = kv.first.second;
+    const int T = fft_group_tile(g.key, b.prec);
     // the longest workgroups (most blocks) first, so the short ones fill the
     // end of the launch; a workgroup's result does not depend on its place
     std::stable_sort(kv.second.begin(), kv.second.end(),
@@ -178,8 +190,8 @@ spod_status build_tables(Batch& b, const void* const* q, spod_dtype dtype, char*
     put(host, g, kv.second);
     b.fft_groups.push_back(g);
   }
-  // Gram: grouped by ceil(L / 16)
-  std::map<int, std::vector<GramItem>> gram;
+  // Gram: grouped by chain and ceil(L / 16)
+  std::map<std::pair<int, int>, std::vector<GramItem>> gram;
   for (auto& s : b.pb) {
     const Plan& p = *s.plan;
     GramItem it{};
@@ -197,12 +209,13 @@ spod_status build_tables(Batch& b, const void* const* q, spod_dtype dtype, char*
     it.K = (int)p.nfreq;
     const bool aligned = ((uintptr_t)it.qhat % 16 == 0) && ((uintptr_t)it.sqrtw % 16 == 0);
     it.vec = aligned && (c128(b) || s.ldq % 2 == 0);
-    gram[p.gram_dim / 16].push_back(it);
+    gram[{chain_of(p), p.gram_dim / 16}].push_back(it);
   }
   b.gram_groups.clear();
   for (auto& kv : gram) {
     Group g;
-    g.key = kv.first;
+    g.chain = kv.first.first;
+    g.key = kv.first.second;
     // the longest slices first (as for the transform)
     std::stable_sort(kv.second.begin(), kv.second.end(), [](const GramItem& x, const GramItem& y) {
       return (x.M + x.S - 1) / x.S > (y.M + y.S - 1) / y.S;
@@ -210,24 +223,26 @@ spod_status build_tables(Batch& b, const void* const* q, spod_dtype dtype, char*
     int64_t start = 0;
     for (auto& it : kv.second) {
       it.start = (int)start;
-      start += gram_group_wgs(kv.first, it.S, it.K);
+      start += gram_group_wgs(g.key, it.S, it.K);
     }
     if (start > 0x7fffffff) return fail(SPOD_ERR_UNSUPPORTED, "batch too large for one launch");
     g.wgs = (int)start;
     put(host, g, kv.second);
     b.gram_groups.push_back(g);
   }
-  // FP16 scales, combine, eigensolve, modes: one group each
-  std::vector<CombineItem> sc, cb;
-  std::map<int, std::vector<EigItem>> eg;
-  std::map<int, int64_t> s_eg;
-  std::vector<ModesItem> md;
-  int64_t s_sc = 0, s_cb = 0, s_md = 0;
+  // FP16 scales, combine, modes: one group per chain; eigensolve: by chain
+  // and L bucket
+  std::vector<CombineItem> sc[NCHAIN], cb[NCHAIN];
+  std::map<std::pair<int, int>, std::vector<EigItem>> eg;
+  std::map<std::pair<int, int>, int64_t> s_eg;
+  std::vector<ModesItem> md[NCHAIN];
+  int64_t s_sc[NCHAIN] = {}, s_cb[NCHAIN] = {}, s_md[NCHAIN] = {};
   b.modes_lds = 0;
   for (auto& s : b.pb) {
     const Plan& p = *s.plan;
     const size_t D = (size_t)p.gram_dim;
     const int K = (int)p.nfreq, L = (int)p.nblocks;
+    const int ch = chain_of(p);
     if (half) {
       CombineItem it{};
       it.part = ws + s.ws_qhat;
@@ -237,9 +252,9 @@ spod_status build_tables(Batch& b, const void* const* q, spod_dtype dtype, char*
       it.M = p.M;
       it.ldq = s.ldq;
       it.L = L;
-      it.start = (int)s_sc;
-      s_sc += (int64_t)K * gram_scale_parts();
-      sc.push_back(it);
+      it.start = (int)s_sc[ch];
+      s_sc[ch] += (int64_t)K * gram_scale_parts();
+      sc[ch].push_back(it);
     }
     CombineItem c{};
     c.part = ws + s.ws_part;
@@ -247,16 +262,16 @@ spod_status build_tables(Batch& b, const void* const* q, spod_dtype dtype, char*
     c.L = L;
     c.D = (int)D;
     c.S = p.gram_split;
-    c.start = (int)s_cb;
-    s_cb += K;
-    cb.push_back(c);
+    c.start = (int)s_cb[ch];
+    s_cb[ch] += K;
+    cb[ch].push_back(c);
     EigItem e{};
     e.gram = ws + s.ws_gram;
     e.lam = reinterpret_cast<double*>(out + s.o_lam);
     e.psi = out + s.o_psi;
     e.info = reinterpret_cast<int32_t*>(out + s.o_info);
     e.L = L;
-    const int lb = L <= 16 ? 16 : (L <= 32 ? 32 : 64);
+    const std::pair<int, int> lb{ch, L <= 16 ? 16 : (L <= 32 ? 32 : 64)};
     e.start = (int)s_eg[lb];
     s_eg[lb] += K;
     eg[lb].push_back(e);
@@ -275,29 +290,37 @@ spod_status build_tables(Batch& b, const void* const* q, spod_dtype dtype, char*
     m.pair = !c128(b) && p.M % 2 == 0 && (uintptr_t)m.qhat % 16 == 0 && (uintptr_t)m.phi % 16 == 0;
     m.tiles = (int)(((m.pair ? p.M / 2 : p.M) + 255) / 256);
     m.eps = c128(b) ? 1e-12 : 1e-6;
-    m.start = (int)s_md;
-    s_md += (int64_t)K * m.tiles;
-    md.push_back(m);
+    m.start = (int)s_md[ch];
+    s_md[ch] += (int64_t)K * m.tiles;
+    md[ch].push_back(m);
     b.modes_lds = std::max(b.modes_lds, csize(b) * (size_t)L * (size_t)s.n_modes);
   }
-  if (s_md > 0x7fffffff) return fail(SPOD_ERR_UNSUPPORTED, "batch too large for one launch");
-  b.scale_g = Group{};
-  if (half) {
-    put(host, b.scale_g, sc);
-    b.scale_g.wgs = (int)s_sc;
+  for (int ch = 0; ch < NCHAIN; ++ch) {
+    if (s_md[ch] > 0x7fffffff) return fail(SPOD_ERR_UNSUPPORTED, "batch too large for one launch");
+    b.scale_g[ch] = Group{};
+    b.scale_g[ch].chain = ch;
+    if (half) {
+      put(host, b.scale_g[ch], sc[ch]);
+      b.scale_g[ch].wgs = (int)s_sc[ch];
+    }
+    b.comb_g[ch] = Group{};
+    b.comb_g[ch].chain = ch;
+    put(host, b.comb_g[ch], cb[ch]);
+    b.comb_g[ch].wgs = (int)s_cb[ch];
+    b.modes_g[ch] = Group{};
+    b.modes_g[ch].chain = ch;
+    put(host, b.modes_g[ch], md[ch]);
+    b.modes_g[ch].wgs = (int)s_md[ch];
   }
-  put(host, b.comb_g, cb);
-  b.comb_g.wgs = (int)s_cb;
   b.eig_groups.clear();
   for (auto& kv : eg) {
     Group g;
-    g.key = kv.first;
+    g.chain = kv.first.first;
+    g.key = kv.first.second;
     put(host, g, kv.second);
     g.wgs = (int)s_eg[kv.first];
     b.eig_groups.push_back(g);
   }
-  put(host, b.modes_g, md);
-  b.modes_g.wgs = (int)s_md;
 
   if (host.size() > b.table_cap) {
     if (b.d_table) (void)hipFree(b.d_table);
@@ -346,27 +369,56 @@ spod_status record(Batch& b, const void* const* q, spod_dtype dtype, char* out, 
                           reinterpret_cast<double*>(out + s.o_mean), nullptr, st);
     if (r != SPOD_OK) return r;
   }
-  for (const Group& g : b.fft_groups) {
-    r = launch_fft_group(g.key, b.prec, dtype, 4, at<FftItem>(b, g), g.n, g.wgs, st);
-    if (r != SPOD_OK) return r;
+  // Chain 1 (L > 32) is forked onto the side stream after the per-problem
+  // transforms and joined at the end; nothing is forked when one chain is
+  // empty.  (Running chain 1's transforms alone before the fork was measured
+  // slower.)
+  const bool two = b.modes_g[0].n > 0 && b.modes_g[1].n > 0;
+  auto hip = [](hipError_t e, const char* what) { return e == hipSuccess ? SPOD_OK : hip_fail(e, what); };
+  auto transforms = [&](int ch, hipStream_t cs) {
+    for (const Group& g : b.fft_groups) {
+      if (g.chain != ch || r != SPOD_OK) continue;
+      r = launch_fft_group(g.key, b.prec, dtype, 4, at<FftItem>(b, g), g.n, g.wgs, cs);
+    }
+  };
+  auto rest = [&](int ch, hipStream_t cs) {
+    if (r == SPOD_OK && b.prec == SPOD_PREC_FP16X4)
+      r = launch_gram_scale_group(at<CombineItem>(b, b.scale_g[ch]), b.scale_g[ch].n,
+                                  b.scale_g[ch].wgs, cs);
+    for (const Group& g : b.gram_groups) {
+      if (g.chain != ch || r != SPOD_OK) continue;
+      r = launch_gram_group(b.prec, g.key, at<GramItem>(b, g), g.n, g.wgs, cs);
+    }
+    if (r == SPOD_OK)
+      r = launch_gram_combine_group(at<CombineItem>(b, b.comb_g[ch]), b.comb_g[ch].n,
+                                    b.comb_g[ch].wgs, cs);
+    for (const Group& g : b.eig_groups) {
+      if (g.chain != ch || r != SPOD_OK) continue;
+      r = launch_eig_group(at<EigItem>(b, g), g.n, g.wgs, b.pb[0].plan->max_sweeps,
+                           eig_group_lds(g.key), cs);
+    }
+    if (r == SPOD_OK)
+      r = launch_modes_group(c128(b), at<ModesItem>(b, b.modes_g[ch]), b.modes_g[ch].n,
+                             b.modes_g[ch].wgs, b.modes_lds, cs);
+  };
+  if (!two) {
+    const int ch = b.modes_g[1].n > 0 ? 1 : 0;
+    transforms(ch, st);
+    rest(ch, st);
+    return r;
   }
-  if (b.prec == SPOD_PREC_FP16X4) {
-    r = launch_gram_scale_group(at<CombineItem>(b, b.scale_g), b.scale_g.n, b.scale_g.wgs, st);
-    if (r != SPOD_OK) return r;
-  }
-  for (const Group& g : b.gram_groups) {
-    r = launch_gram_group(b.prec, g.key, at<GramItem>(b, g), g.n, g.wgs, st);
-    if (r != SPOD_OK) return r;
-  }
-  r = launch_gram_combine_group(at<CombineItem>(b, b.comb_g), b.comb_g.n, b.comb_g.wgs, st);
+  r = hip(hipEventRecord(b.fork, st), "hipEventRecord");
+  if (r == SPOD_OK) r = hip(hipStreamWaitEvent(b.side, b.fork, 0), "hipStreamWaitEvent");
   if (r != SPOD_OK) return r;
-  for (const Group& g : b.eig_groups) {
-    r = launch_eig_group(at<EigItem>(b, g), g.n, g.wgs, b.pb[0].plan->max_sweeps,
-                         eig_group_lds(g.key), st);
-    if (r != SPOD_OK) return r;
-  }
-  return launch_modes_group(c128(b), at<ModesItem>(b, b.modes_g), b.modes_g.n, b.modes_g.wgs,
-                            b.modes_lds, st);
+  transforms(0, st);
+  rest(0, st);
+  transforms(1, b.side);
+  rest(1, b.side);
+  // the join is recorded whatever happened, so a capture always ends whole
+  spod_status rj = hip(hipEventRecord(b.join, b.side), "hipEventRecord");
+  if (rj == SPOD_OK) rj = hip(hipStreamWaitEvent(st, b.join, 0), "hipStreamWaitEvent");
+  if (r == SPOD_OK) r = rj;
+  return r;
 }
 
 spod_status prepare(Batch& b, const void* const* q, spod_dtype dtype, void* out, void* ws) {
@@ -513,6 +565,9 @@ spod_status spod_batch_create(const spod_problem* problems, int64_t n, spod_prec
     if (st == SPOD_OK) {
       hipError_t e = hipGetDevice(&b->device);
       if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join, hipEventDisableTiming);
       if (e != hipSuccess) st = hip_fail(e, "batch stream");
     }
     if (st != SPOD_OK) {
@@ -651,6 +706,9 @@ void spod_batch_destroy(spod_batch batch) {
   (void)hipDeviceSynchronize();
   drop_graph(*b);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  if (b->side) (void)hipStreamDestroy(b->side);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  if (b->join) (void)hipEventDestroy(b->join);
   if (b->d_table) (void)hipFree(b->d_table);
   for (auto& s : b->pb)
     if (s.plan) spod_plan_destroy(reinterpret_cast<spod_plan>(s.plan));
