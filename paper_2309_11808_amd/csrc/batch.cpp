@@ -394,8 +394,7 @@ spod_status record(Batch& b, const void* const* q, spod_dtype dtype, char* out, 
                                     b.comb_g[ch].wgs, cs);
     for (const Group& g : b.eig_groups) {
       if (g.chain != ch || r != SPOD_OK) continue;
-      r = launch_eig_group(at<EigItem>(b, g), g.n, g.wgs, b.pb[0].plan->max_sweeps,
-                           eig_group_lds(g.key), cs);
+      r = launch_eig_group(at<EigItem>(b, g), g.n, g.wgs, b.pb[0].plan->max_sweeps, g.key, cs);
     }
     if (r == SPOD_OK)
       r = launch_modes_group(c128(b), at<ModesItem>(b, b.modes_g[ch]), b.modes_g[ch].n,

@@ -214,36 +214,49 @@ __device__ __forceinline__ void jacobi_body(const double2* __restrict__ gram,
   if (tid == 0 && info) info[k] = converged ? sweep : -(sweep - 1);
 }
 
-__global__ __launch_bounds__(256) void jacobi_kernel(const double2* __restrict__ gram,
-                                                     double* __restrict__ lam,
-                                                     double2* __restrict__ psi,
-                                                     int32_t* __restrict__ info, int L,
-                                                     int max_sweeps) {
+// NT threads per eigenproblem.  A round updates n/2 x n/2 blocks of A and
+// n x n/2 pairs of V between two barriers (3072 items at n = 64), so the large
+// problems take 1024 threads: the round's latency is spread over 16
+// wavefronts instead of 4 (one problem fills a CU's LDS either way).  Every
+// item is computed by one thread with the same arithmetic whatever NT is.
+template <int NT>
+__global__ __launch_bounds__(NT) void jacobi_kernel(const double2* __restrict__ gram,
+                                                    double* __restrict__ lam,
+                                                    double2* __restrict__ psi,
+                                                    int32_t* __restrict__ info, int L,
+                                                    int max_sweeps) {
   jacobi_body(gram, lam, psi, info, L, max_sweeps, blockIdx.x);
 }
 
-__global__ __launch_bounds__(256) void jacobi_batch_kernel(const EigItem* __restrict__ items, int n,
-                                                           int max_sweeps) {
+template <int NT>
+__global__ __launch_bounds__(NT) void jacobi_batch_kernel(const EigItem* __restrict__ items, int n,
+                                                          int max_sweeps) {
   const EigItem& it = items[find_item(items, n, (int)blockIdx.x)];
   jacobi_body(static_cast<const double2*>(it.gram), it.lam, static_cast<double2*>(it.psi), it.info,
               it.L, max_sweeps, (int)blockIdx.x - it.start);
 }
 
+constexpr int EIG_SMALL_NT = 256, EIG_LARGE_NT = 1024;
+// 1024 threads only above L = 32: at L = 31 they were measured slower (0.86
+// against 0.70 ms for 257 problems), the round's 768 items being too few.
+constexpr int eig_threads(int L) { return L > 32 ? EIG_LARGE_NT : EIG_SMALL_NT; }
+
 static bool eig_attr_done = false;
 
 static hipError_t eig_attr() {
   if (eig_attr_done) return hipSuccess;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_kernel),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)eig_lds_bytes(EIG_MAXN));
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_batch_kernel),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)eig_lds_bytes(EIG_MAXN));
-  if (e == hipSuccess) eig_attr_done = true;
-  return e;
+  const void* fns[] = {reinterpret_cast<const void*>(&jacobi_kernel<EIG_SMALL_NT>),
+                       reinterpret_cast<const void*>(&jacobi_kernel<EIG_LARGE_NT>),
+                       reinterpret_cast<const void*>(&jacobi_batch_kernel<EIG_SMALL_NT>),
+                       reinterpret_cast<const void*>(&jacobi_batch_kernel<EIG_LARGE_NT>)};
+  for (const void* f : fns) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)eig_lds_bytes(EIG_MAXN));
+    if (e != hipSuccess) return e;
+  }
+  eig_attr_done = true;
+  return hipSuccess;
 }
-
-size_t eig_group_lds(int L) { return eig_lds_bytes(L); }
 
 spod_status launch_eig(const Plan& p, const void* gram, double* lam, void* psi, int32_t* info,
                        void* ws, hipStream_t st) {
@@ -251,20 +264,30 @@ spod_status launch_eig(const Plan& p, const void* gram, double* lam, void* psi, 
   if (p.nblocks > EIG_MAXN) return fail(SPOD_ERR_UNSUPPORTED, "nblocks > 64");
   hipError_t ea = eig_attr();
   if (ea != hipSuccess) return hip_fail(ea, "hipFuncSetAttribute");
-  hipLaunchKernelGGL(jacobi_kernel, dim3((unsigned)p.nfreq), dim3(256),
-                     eig_lds_bytes((int)p.nblocks), st,
-                     static_cast<const double2*>(gram), lam, static_cast<double2*>(psi), info,
-                     (int)p.nblocks, p.max_sweeps);
+  const int L = (int)p.nblocks;
+  if (eig_threads(L) == EIG_LARGE_NT)
+    hipLaunchKernelGGL(jacobi_kernel<EIG_LARGE_NT>, dim3((unsigned)p.nfreq), dim3(EIG_LARGE_NT),
+                       eig_lds_bytes(L), st, static_cast<const double2*>(gram), lam,
+                       static_cast<double2*>(psi), info, L, p.max_sweeps);
+  else
+    hipLaunchKernelGGL(jacobi_kernel<EIG_SMALL_NT>, dim3((unsigned)p.nfreq), dim3(EIG_SMALL_NT),
+                       eig_lds_bytes(L), st, static_cast<const double2*>(gram), lam,
+                       static_cast<double2*>(psi), info, L, p.max_sweeps);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SPOD_OK : hip_fail(e, "jacobi_kernel");
 }
 
-spod_status launch_eig_group(const EigItem* d_items, int n, int wgs, int max_sweeps,
-                             size_t lds_bytes, hipStream_t st) {
+spod_status launch_eig_group(const EigItem* d_items, int n, int wgs, int max_sweeps, int lmax,
+                             hipStream_t st) {
   hipError_t ea = eig_attr();
   if (ea != hipSuccess) return hip_fail(ea, "hipFuncSetAttribute");
-  hipLaunchKernelGGL(jacobi_batch_kernel, dim3((unsigned)wgs), dim3(256), lds_bytes, st, d_items, n,
-                     max_sweeps);
+  const size_t lds_bytes = eig_lds_bytes(lmax);
+  if (eig_threads(lmax) == EIG_LARGE_NT)
+    hipLaunchKernelGGL(jacobi_batch_kernel<EIG_LARGE_NT>, dim3((unsigned)wgs), dim3(EIG_LARGE_NT),
+                       lds_bytes, st, d_items, n, max_sweeps);
+  else
+    hipLaunchKernelGGL(jacobi_batch_kernel<EIG_SMALL_NT>, dim3((unsigned)wgs), dim3(EIG_SMALL_NT),
+                       lds_bytes, st, d_items, n, max_sweeps);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SPOD_OK : hip_fail(e, "jacobi_batch_kernel");
 }

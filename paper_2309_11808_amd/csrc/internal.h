@@ -263,9 +263,8 @@ int64_t gram_group_wgs(int nt16, int64_t S, int64_t K);   // workgroups of one p
 spod_status launch_gram_scale_group(const CombineItem* d_items, int n, int wgs, hipStream_t st);
 int gram_scale_parts();                              // FP16 scale: partial maxima per frequency
 spod_status launch_gram_combine_group(const CombineItem* d_items, int n, int wgs, hipStream_t st);
-spod_status launch_eig_group(const EigItem* d_items, int n, int wgs, int max_sweeps,
-                             size_t lds_bytes, hipStream_t st);
-size_t eig_group_lds(int L);                         // dynamic LDS of one eigenproblem
+spod_status launch_eig_group(const EigItem* d_items, int n, int wgs, int max_sweeps, int lmax,
+                             hipStream_t st);   // lmax: the group's largest L (16, 32 or 64)
 spod_status launch_modes_group(bool c128, const ModesItem* d_items, int n, int wgs,
                                size_t lds_bytes, hipStream_t st);
 
