@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
@@ -14,13 +15,26 @@ namespace spod {
 
 static thread_local std::string g_last_error;
 
-spod_status fail(spod_status s, const std::string& msg) {
-  g_last_error = std::string(spod_status_string(s)) + ": " + msg;
+// The status is returned even when the message cannot be stored (no memory
+// for the string): nothing here throws.
+spod_status fail(spod_status s, const char* msg) noexcept {
+  try {
+    g_last_error = spod_status_string(s);
+    g_last_error += ": ";
+    g_last_error += msg;
+  } catch (...) {
+  }
   return s;
 }
 
-spod_status hip_fail(hipError_t e, const char* where) {
-  return fail(SPOD_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+spod_status fail(spod_status s, const std::string& msg) noexcept { return fail(s, msg.c_str()); }
+
+spod_status hip_fail(hipError_t e, const char* where) noexcept {
+  try {
+    return fail(SPOD_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+  } catch (...) {
+    return fail(SPOD_ERR_HIP, where);
+  }
 }
 
 bool is_complex128(const Plan& p) { return p.prec == SPOD_PREC_FP64; }
@@ -364,8 +378,11 @@ spod_status spod_plan_query(spod_plan plan, int64_t* nblocks, int64_t* nfreq,
 
 static spod_status check_ws(const Plan& p, void* ws, size_t ws_bytes, size_t need) {
   if (need == 0) return SPOD_OK;
-  if (!ws || ws_bytes < need)
-    return fail(SPOD_ERR_WORKSPACE, "workspace of " + std::to_string(need) + " bytes required");
+  if (!ws || ws_bytes < need) {
+    char msg[64];
+    std::snprintf(msg, sizeof msg, "workspace of %zu bytes required", need);
+    return fail(SPOD_ERR_WORKSPACE, msg);
+  }
   (void)p;
   return SPOD_OK;
 }

@@ -95,8 +95,10 @@ void freeze(Plan& p);
 Plan plan_rows(const Plan& p, int64_t row0, int64_t rows);
 
 // error reporting (thread local message)
-spod_status fail(spod_status s, const std::string& msg);
-spod_status hip_fail(hipError_t e, const char* where);
+// Record the message of a failing call (spod_last_error) and return s.
+spod_status fail(spod_status s, const char* msg) noexcept;
+spod_status fail(spod_status s, const std::string& msg) noexcept;
+spod_status hip_fail(hipError_t e, const char* where) noexcept;
 
 // Runs an entry point's body so that no exception crosses the C ABI: host
 // allocation failures become SPOD_ERR_ALLOC, anything else SPOD_ERR_INTERNAL.
