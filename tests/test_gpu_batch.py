@@ -227,3 +227,26 @@ def test_batch_with_general_block_lengths():
             ref = O.spod(p.q.cpu().numpy(), p.nfft, p.noverlap, weights=p.weights, n_modes=2)
             PT.check_eig(r["lam"], ref["lam"], rtol=1e-10, floor_rel=1e-13)
     b.close()
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_batch_of_long_problems_only(graph):
+    """Only problems with more than 32 blocks: their chain runs alone on the
+    caller's stream (no fork), with the same results as the single path."""
+    from paper_2309_11808_amd import Batch
+    probs = [fields.random_rows(200 + 61 * i, (40 + 7 * i) * 32 + 32, 64, 32, seed=90 + i,
+                                dtype=torch.float32) for i in range(3)]
+    for p in probs:
+        p.q = p.q.cuda()
+    b = Batch([_desc(p) for p in probs], precision="bf16x4", n_modes=4, graph=graph)
+    assert [it.nblocks for it in b.items] == [40, 47, 54]
+    for rep in range(2):
+        res = b.forward([p.q for p in probs])
+        torch.cuda.synchronize()
+        for i, (r, p) in enumerate(zip(res, probs)):
+            s = _single(p, "bf16x4", 4)
+            if p.M % 2 == 1:
+                _close(r, s, "bf16x4", p.M, f"graph={graph} rep {rep} problem {i}")
+            else:
+                _same(r, s, f"graph={graph} rep {rep} problem {i}")
+    b.close()
