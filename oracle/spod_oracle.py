@@ -114,12 +114,17 @@ def dft_matrix(nfft: int, bins=None) -> np.ndarray:
 
 
 def fourier_blocks(q: np.ndarray, nfft: int, noverlap: int, window=None,
-                   mean=None, bins=None) -> np.ndarray:
+                   mean=None, bins=None, dft: str = "matrix") -> np.ndarray:
     """Qhat[k, l, m] for the rows of q (eqs. (blocks), (blocks-ft), (blocks-k)).
 
     q        : [M, N_t] real snapshot rows (any float dtype; upcast to float64).
     mean     : [M] temporal mean to subtract; computed from q when None.
     bins     : frequency indices to return (default: all K one-sided bins).
+    dft      : "matrix" - the DFT sum of eq. (blocks-ft) as a product with the
+               exact twiddle table (the definition written out);
+               "fft"    - the same sum by numpy's FFT of the windowed block (a
+               library step; the two agree to rounding, which a pin checks).
+               Used where the full sum over every bin is too slow.
     Returns complex128 [len(bins), L, M], already scaled by kappa (R1, R3).
     """
     q = np.asarray(q)
@@ -132,6 +137,16 @@ def fourier_blocks(q: np.ndarray, nfft: int, noverlap: int, window=None,
     if mean is None:
         mean = temporal_mean(q)
     kappa = dft_scale(window, nb)
+    if dft == "fft":
+        sel = np.arange(nfreq(nfft)) if bins is None else np.asarray(bins, dtype=np.int64)
+        out = np.empty((len(sel), nb, m_rows), dtype=np.complex128)
+        for ell in range(nb):
+            seg = q[:, ell * s: ell * s + nfft].astype(np.float64) - mean[:, None]
+            seg *= window[None, :]
+            out[:, ell, :] = np.fft.rfft(seg, axis=1)[:, sel].T * kappa
+        return out
+    if dft != "matrix":
+        raise ValueError("dft must be 'matrix' or 'fft'")
     F = dft_matrix(nfft, bins)                      # [N_f, nbins]
     out = np.empty((F.shape[1], nb, m_rows), dtype=np.complex128)
     for ell in range(nb):
@@ -275,7 +290,8 @@ def spod(q, nfft: int, noverlap: int, window=None, weights=None, n_modes: int = 
 
 def spod_chunked(q, nfft: int, noverlap: int, window=None, weights=None,
                  n_modes: int = 5, eps: float = 1e-12, chunk: int = 8192,
-                 bins=None, want_modes: bool = True, mode_rows=None):
+                 bins=None, want_modes: bool = True, mode_rows=None, dft: str = "matrix",
+                 progress=None):
     """The same path streamed over chunks of degrees of freedom.
 
     This is the spatial split of Sec. 3.1 done sequentially: the Gram of every
@@ -283,7 +299,8 @@ def spod_chunked(q, nfft: int, noverlap: int, window=None, weights=None,
     are solved, and the modes come from a second pass that recomputes Qhat.
     `bins` restricts the work to selected frequencies; `mode_rows` restricts
     the second pass to selected degrees of freedom (the rest of phi is not
-    formed).
+    formed).  `dft` is passed to fourier_blocks; `progress(rows_done)` is
+    called after every chunk of the first pass (for long runs).
     """
     q = np.asarray(q)
     m_rows, nt = q.shape
@@ -300,8 +317,10 @@ def spod_chunked(q, nfft: int, noverlap: int, window=None, weights=None,
         c1 = min(m_rows, c0 + chunk)
         qc = q[c0:c1]
         mean[c0:c1] = temporal_mean(qc)
-        qh = fourier_blocks(qc, nfft, noverlap, window, mean[c0:c1], bins)
+        qh = fourier_blocks(qc, nfft, noverlap, window, mean[c0:c1], bins, dft=dft)
         G += gram(qh, weights[c0:c1])
+        if progress is not None:
+            progress(c1)
     lam, V, sweeps = jacobi_eigh(G)
     lam, psi = sort_and_phase(lam, V)
     out = {"mean": mean, "gram": G, "lam": lam, "psi": psi, "sweeps": sweeps}
@@ -312,7 +331,7 @@ def spod_chunked(q, nfft: int, noverlap: int, window=None, weights=None,
         n_valid = None
         for c0 in range(0, len(rows), chunk):
             r = rows[c0:c0 + chunk]
-            qh = fourier_blocks(q[r], nfft, noverlap, window, mean[r], bins)
+            qh = fourier_blocks(q[r], nfft, noverlap, window, mean[r], bins, dft=dft)
             phi[:, :, c0:c0 + len(r)], n_valid = modes(qh, lam, psi, n_modes, eps)
         out["phi"] = phi
         out["n_valid"] = n_valid

@@ -233,16 +233,22 @@ def test_modes_are_w_orthonormal():
         np.testing.assert_allclose(G, np.eye(P.shape[0]), atol=1e-11)
 
 
-def test_planted_modes_closed_form():
+@pytest.mark.parametrize("dft", ["matrix", "fft"])
+def test_planted_modes_closed_form(dft):
     """Noise-free planted field: with the periodic Hann, sum w = N/2 and
     sum w^2 = 3N/8, so a cosine of amplitude a on a W-unit mode at bin b gives
     lambda_1(b) = L/(L-1) * a^2 * N_f / 6, and the Hann leakage (-N/4 at +-1)
-    gives lambda_1(b +- 1) = lambda_1(b) / 4; everything else is zero."""
+    gives lambda_1(b +- 1) = lambda_1(b) / 4; everything else is zero.  Both
+    forms of the block transform (the DFT sum with the twiddle table, and the
+    library FFT step) are held to it."""
     p = fields.planted(sigma=0.0, seed=1)
     q = p.q.numpy()
     nfft, nov = 128, 64
     L = O.block_count(q.shape[1], nfft, nov)
-    out = O.spod(q, nfft, nov, weights=p.weights, n_modes=3)
+    if dft == "matrix":
+        out = O.spod(q, nfft, nov, weights=p.weights, n_modes=3)
+    else:
+        out = O.spod_chunked(q, nfft, nov, weights=p.weights, n_modes=3, chunk=300, dft="fft")
     lam = out["lam"]
     top = lam.max()
     seen = set()
@@ -314,6 +320,20 @@ def test_chunked_equals_whole():
     c = O.spod_chunked(q, 32, 16, weights=p.weights, n_modes=3, chunk=16, bins=sel, mode_rows=[5, 1])
     np.testing.assert_allclose(c["lam"], a["lam"][sel], rtol=1e-12, atol=1e-15 * a["lam"].max())
     np.testing.assert_allclose(c["phi"], a["phi"][sel][:, :, [5, 1]], atol=1e-10 * np.abs(a["phi"]).max())
+    # the library FFT form of the block transform gives the same path
+    done = []
+    d = O.spod_chunked(q, 32, 16, weights=p.weights, n_modes=3, chunk=16, dft="fft",
+                       progress=done.append)
+    assert done == list(range(16, 70, 16)) + [70]
+    np.testing.assert_allclose(d["gram"], a["gram"], atol=1e-13 * np.abs(a["gram"]).max())
+    np.testing.assert_allclose(d["lam"], a["lam"], rtol=1e-12, atol=1e-15 * a["lam"].max())
+    np.testing.assert_allclose(d["phi"], a["phi"], atol=1e-10 * np.abs(a["phi"]).max())
+    e = O.spod_chunked(q, 32, 16, weights=p.weights, n_modes=3, chunk=16, bins=sel, dft="fft")
+    np.testing.assert_allclose(e["lam"], a["lam"][sel], rtol=1e-12, atol=1e-15 * a["lam"].max())
+    for odd in (33, 35):       # odd block length: the one-sided set has no Nyquist bin
+        qo = q[:, :400]
+        np.testing.assert_allclose(O.fourier_blocks(qo, odd, 11, dft="fft"),
+                                   O.fourier_blocks(qo, odd, 11), atol=1e-12)
 
 
 def test_generator_is_seeded():
