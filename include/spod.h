@@ -76,14 +76,21 @@ typedef enum {
 
 typedef enum { SPOD_F32 = 0, SPOD_F64 = 1 } spod_dtype; /* stored type of q and g_q */
 
+/* info value of an eigenproblem whose Gram matrix is not finite (spod_eig). */
+#define SPOD_INFO_NONFINITE ((int32_t)(-2147483647 - 1))
+
 typedef enum {
   SPOD_PREC_FP64 = 0,   /* FP64 transform, Gram and modes; complex128 qhat/phi            */
   SPOD_PREC_FP32 = 1,   /* FP32 transform; Gram on FP32 MFMA, each 4-wide partial sum
                            added into FP64; FP32 modes; complex64 qhat/phi               */
-  SPOD_PREC_BF16X4 = 2, /* FP32 transform; Gram on BF16 MFMA with a two-term split
-                           y = hi + lo and all four products (hi hi, hi lo, lo hi, lo lo),
-                           FP32 partial sums added into FP64; FP32 modes; complex64       */
-  SPOD_PREC_FP16X4 = 3  /* as BF16X4 with FP16 operands scaled per frequency            */
+  SPOD_PREC_BF16X4 = 2, /* FP32 transform; Gram on BF16 MFMA with a block floating
+                           point split: per 32-wide contraction step, y 2^-E = h + l with
+                           the integer h (|h| <= 2^8) and l rounded to BF16, all four
+                           products (h h, h l, l h, l l); the h h sums are exact in FP32,
+                           each step is scaled by 2^(2E) into FP64; FP32 modes; complex64 */
+  SPOD_PREC_FP16X4 = 3  /* as BF16X4 with FP16 operands (|h| <= 2^9, l to FP16): 2^-20
+                           of each step's largest operand instead of 2^-17; no range
+                           scaling is needed, the step exponent E carries the range     */
 } spod_precision;
 
 typedef enum {
@@ -156,7 +163,13 @@ spod_status spod_csd(spod_plan plan, const void* qhat, void* gram, void* ws, siz
  *          eigenvector j (unit 2-norm, phase convention above).
  *   info : device [K] int32 or NULL: > 0 converged, the number of sweeps
  *          used (the last one made no rotation); <= 0 not converged after
- *          -info sweeps (the cap set with SPOD_OPT_MAX_SWEEPS was reached). */
+ *          -info sweeps (the cap set with SPOD_OPT_MAX_SWEEPS was reached);
+ *          SPOD_INFO_NONFINITE when gram[k] holds a NaN or an infinity (from
+ *          non-finite data): lam[k][*] and psi[k] are then written as NaN, and
+ *          spod_modes counts no valid mode for k (its modes are zero).
+ * The stage calls are asynchronous, so a non-finite input is reported here,
+ * after a stream synchronisation, and not as a status; the synchronous
+ * out-of-core call returns SPOD_ERR_NUMERIC for it. */
 spod_status spod_eig(spod_plan plan, const void* gram, double* lam, void* psi, int32_t* info,
                      void* ws, size_t ws_bytes, spod_stream stream);
 
@@ -385,14 +398,16 @@ spod_status spod_ooc_query(spod_ooc ooc, int64_t* chunk_rows, int64_t* n_chunks,
  * Outputs:
  *   mean  : [M] f64, host or device memory;
  *   lam   : device [K][L] f64;  psi: device [K][L][L] c128;  info: device [K]
- *           int32 (as spod_eig);
+ *           int32 (as spod_eig) or NULL;
  *   phi   : [K][n_modes][M], c128 under SPOD_PREC_FP64 else c64, host (pinned
  *           or not) or device memory;
  *   n_valid: device [K] int32 (as spod_modes).
  * `stream` runs the kernels and is waited on before the first copy.  The call
  * returns after every result is in place (it synchronises the streams).  On
  * an error nothing is left running; the outputs are then undefined.  Calls on
- * one object must not overlap. */
+ * one object must not overlap.  SPOD_ERR_NUMERIC when the data hold a NaN or
+ * an infinity: every output is still written, and the frequencies concerned
+ * carry SPOD_INFO_NONFINITE in info (NaN eigenpairs, no valid mode). */
 spod_status spod_ooc_forward(spod_ooc ooc, const void* q, spod_read_fn read, void* user,
                              double* mean, double* lam, void* psi, int32_t* info, void* phi,
                              int32_t* n_valid, spod_stream stream);

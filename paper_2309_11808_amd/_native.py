@@ -24,6 +24,8 @@ SPOD_ERR_INTERNAL = -8
 SPOD_F32 = 0
 SPOD_F64 = 1
 
+SPOD_INFO_NONFINITE = -2147483648   # spod_eig info of a non-finite Gram matrix
+
 SPOD_PREC_FP64 = 0
 SPOD_PREC_FP32 = 1
 SPOD_PREC_BF16X4 = 2

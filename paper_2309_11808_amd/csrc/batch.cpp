@@ -65,7 +65,7 @@ struct Batch {
   bool tables_ok = false;
   std::vector<Group> fft_groups, gram_groups, eig_groups;   // eig: by L bucket (16, 32, 64)
   std::vector<int> fft_fallback;                 // problems launched on their own
-  Group scale_g[NCHAIN], comb_g[NCHAIN], modes_g[NCHAIN];
+  Group comb_g[NCHAIN], modes_g[NCHAIN];
   size_t modes_lds = 0;
 
   hipStream_t cap_stream = nullptr;
@@ -96,7 +96,7 @@ void layout(Batch& b) {
     s.ws_part = ws;
     const size_t D = (size_t)p.gram_dim;
     const size_t smax = (size_t)gram_split_for(p, tmax);
-    ws += up256(16 * K * smax * D * D + sizeof(float) * K * (1 + (size_t)gram_scale_parts()) + 256);
+    ws += up256(16 * K * smax * D * D);
     s.o_mean = out;
     out += up256(8 * M);
     s.o_lam = out;
@@ -139,7 +139,6 @@ void put(std::vector<char>& host, Group& g, const std::vector<It>& items) {
 
 spod_status build_tables(Batch& b, const void* const* q, spod_dtype dtype, char* out, char* ws) {
   std::vector<char> host;
-  const bool half = b.prec == SPOD_PREC_FP16X4;
   // transform: grouped by chain and nfft
   std::map<std::pair<int, int>, std::vector<FftItem>> fft;
   b.fft_fallback.clear();
@@ -197,11 +196,7 @@ spod_status build_tables(Batch& b, const void* const* q, spod_dtype dtype, char*
     GramItem it{};
     it.qhat = ws + s.ws_qhat;
     it.sqrtw = c128(b) ? (const void*)p.d_sqrtw : (const void*)p.d_sqrtw32;
-    const size_t D = (size_t)p.gram_dim;
     it.part = reinterpret_cast<double*>(ws + s.ws_part);
-    it.fscale = half ? reinterpret_cast<const float*>(ws + s.ws_part + 16 * (size_t)p.nfreq *
-                                                          (size_t)p.gram_split * D * D)
-                     : nullptr;
     it.M = p.M;
     it.ldq = s.ldq;
     it.L = (int)p.nblocks;
@@ -230,32 +225,18 @@ spod_status build_tables(Batch& b, const void* const* q, spod_dtype dtype, char*
     put(host, g, kv.second);
     b.gram_groups.push_back(g);
   }
-  // FP16 scales, combine, modes: one group per chain; eigensolve: by chain
-  // and L bucket
-  std::vector<CombineItem> sc[NCHAIN], cb[NCHAIN];
+  // combine, modes: one group per chain; eigensolve: by chain and L bucket
+  std::vector<CombineItem> cb[NCHAIN];
   std::map<std::pair<int, int>, std::vector<EigItem>> eg;
   std::map<std::pair<int, int>, int64_t> s_eg;
   std::vector<ModesItem> md[NCHAIN];
-  int64_t s_sc[NCHAIN] = {}, s_cb[NCHAIN] = {}, s_md[NCHAIN] = {};
+  int64_t s_cb[NCHAIN] = {}, s_md[NCHAIN] = {};
   b.modes_lds = 0;
   for (auto& s : b.pb) {
     const Plan& p = *s.plan;
     const size_t D = (size_t)p.gram_dim;
     const int K = (int)p.nfreq, L = (int)p.nblocks;
     const int ch = chain_of(p);
-    if (half) {
-      CombineItem it{};
-      it.part = ws + s.ws_qhat;
-      it.gram = ws + s.ws_part + 16 * (size_t)K * (size_t)p.gram_split * D * D;
-      it.aux = static_cast<float*>(it.gram) + K;
-      it.sqrtw = p.d_sqrtw32;
-      it.M = p.M;
-      it.ldq = s.ldq;
-      it.L = L;
-      it.start = (int)s_sc[ch];
-      s_sc[ch] += (int64_t)K * gram_scale_parts();
-      sc[ch].push_back(it);
-    }
     CombineItem c{};
     c.part = ws + s.ws_part;
     c.gram = ws + s.ws_gram;
@@ -297,12 +278,6 @@ spod_status build_tables(Batch& b, const void* const* q, spod_dtype dtype, char*
   }
   for (int ch = 0; ch < NCHAIN; ++ch) {
     if (s_md[ch] > 0x7fffffff) return fail(SPOD_ERR_UNSUPPORTED, "batch too large for one launch");
-    b.scale_g[ch] = Group{};
-    b.scale_g[ch].chain = ch;
-    if (half) {
-      put(host, b.scale_g[ch], sc[ch]);
-      b.scale_g[ch].wgs = (int)s_sc[ch];
-    }
     b.comb_g[ch] = Group{};
     b.comb_g[ch].chain = ch;
     put(host, b.comb_g[ch], cb[ch]);
@@ -382,9 +357,6 @@ spod_status record(Batch& b, const void* const* q, spod_dtype dtype, char* out, 
     }
   };
   auto rest = [&](int ch, hipStream_t cs) {
-    if (r == SPOD_OK && b.prec == SPOD_PREC_FP16X4)
-      r = launch_gram_scale_group(at<CombineItem>(b, b.scale_g[ch]), b.scale_g[ch].n,
-                                  b.scale_g[ch].wgs, cs);
     for (const Group& g : b.gram_groups) {
       if (g.chain != ch || r != SPOD_OK) continue;
       r = launch_gram_group(b.prec, g.key, at<GramItem>(b, g), g.n, g.wgs, cs);

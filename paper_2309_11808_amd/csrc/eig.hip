@@ -17,8 +17,13 @@
 //
 // Output: eigenvalues in descending order (stable on ties), eigenvector j in
 // column j with its entry of largest modulus (lowest index on ties) made real
-// and positive.
+// and positive.  A matrix with a non-finite entry (NaN or Inf data) is not
+// iterated: every eigenvalue and eigenvector entry is written as NaN and info
+// is SPOD_INFO_NONFINITE.
 #include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <mutex>
 
 #include "internal.h"
 
@@ -44,6 +49,7 @@ __device__ __forceinline__ void jacobi_body(const double2* __restrict__ gram,
   extern __shared__ double2 eig_dyn[];
   __shared__ Rot rot[EIG_MAXN / 2];
   __shared__ int any_rot;
+  __shared__ int nonfinite;
   __shared__ double lsh[EIG_MAXN];
   __shared__ int rank_of[EIG_MAXN];
   __shared__ double2 phase[EIG_MAXN];
@@ -57,15 +63,27 @@ __device__ __forceinline__ void jacobi_body(const double2* __restrict__ gram,
   double2* V = eig_dyn + n * EIG_LD;      // [n][n + 1]
   const double2* G = gram + (int64_t)k * L * L;
 
+  if (tid == 0) nonfinite = 0;
+  __syncthreads();
   for (int idx = tid; idx < n * n; idx += blockDim.x) {
     const int i = idx / n, j = idx % n;
     double2 g = make_double2(0.0, 0.0);
     if (i < L && j < L) g = G[i * L + j];
     if (i == j) g.y = 0.0;
+    if (!isfinite(g.x) || !isfinite(g.y)) nonfinite = 1;
     A[i * EIG_LD + j] = g;
     V[i * EIG_LD + j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
   }
   __syncthreads();
+  if (nonfinite) {
+    // no rotation is meaningful: report every output as NaN
+    const double qnan = __builtin_nan("");
+    for (int i = tid; i < L; i += blockDim.x) lam[(int64_t)k * L + i] = qnan;
+    for (int idx = tid; idx < L * L; idx += blockDim.x)
+      psi[(int64_t)k * L * L + idx] = make_double2(qnan, qnan);
+    if (tid == 0 && info) info[k] = SPOD_INFO_NONFINITE;
+    return;
+  }
 
   const double tol = 1e-15;
   int sweep = 0;
@@ -176,15 +194,22 @@ __device__ __forceinline__ void jacobi_body(const double2* __restrict__ gram,
     __syncthreads();
   }
 
-  // eigenvalues, ranks (descending, stable), phases
+  // eigenvalues, ranks (descending, stable), phases.  The order is total:
+  // j goes before i when lj > li, or when they are equal (or both NaN) and
+  // j < i, or when only li is NaN; so the ranks are a permutation even if an
+  // overflow produced a NaN.
   for (int i = tid; i < L; i += blockDim.x) lsh[i] = A[i * EIG_LD + i].x;
   __syncthreads();
   for (int i = tid; i < L; i += blockDim.x) {
     const double li = lsh[i];
+    const bool ni = isnan(li);
     int r = 0;
     for (int j = 0; j < L; ++j) {
       const double lj = lsh[j];
-      r += (lj > li) || (lj == li && j < i);
+      const bool nj = isnan(lj);
+      const bool before = (ni || nj) ? ((ni && !nj) || (ni && nj && j < i))
+                                     : ((lj > li) || (lj == li && j < i));
+      r += before;
     }
     rank_of[i] = r;
     int piv = 0;
@@ -241,10 +266,12 @@ constexpr int EIG_SMALL_NT = 256, EIG_LARGE_NT = 1024;
 // against 0.70 ms for 257 problems), the round's 768 items being too few.
 constexpr int eig_threads(int L) { return L > 32 ? EIG_LARGE_NT : EIG_SMALL_NT; }
 
-static bool eig_attr_done = false;
-
+// The attribute is set once per process (std::call_once: plans may be used
+// from several host threads).
 static hipError_t eig_attr() {
-  if (eig_attr_done) return hipSuccess;
+  static std::once_flag once;
+  static hipError_t result = hipSuccess;
+  std::call_once(once, [] {
   const void* fns[] = {reinterpret_cast<const void*>(&jacobi_kernel<EIG_SMALL_NT>),
                        reinterpret_cast<const void*>(&jacobi_kernel<EIG_LARGE_NT>),
                        reinterpret_cast<const void*>(&jacobi_batch_kernel<EIG_SMALL_NT>),
@@ -252,10 +279,13 @@ static hipError_t eig_attr() {
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)eig_lds_bytes(EIG_MAXN));
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess) {
+      result = e;
+      return;
+    }
   }
-  eig_attr_done = true;
-  return hipSuccess;
+  });
+  return result;
 }
 
 spod_status launch_eig(const Plan& p, const void* gram, double* lam, void* psi, int32_t* info,

@@ -18,18 +18,21 @@
 //           Im = T3 - T1 + T2 (this path is bound by FP64 MFMA issue).
 //   FP32    v_mfma_f32_16x16x4f32; the two products of one 4-wide step start
 //           from zero and are added into FP64 registers at once.
-//   BF16X4  y = hi + lo with hi = bf16(y), lo = bf16(y - hi) (round to nearest
-//           even) and all four products hi hi^T + hi lo^T + lo hi^T + lo lo^T
-//           on v_mfma_f32_16x16x32_bf16: the exact product of the 16-bit
-//           representation.  Dropping lo lo^T (the common three-product
-//           scheme) is not used: on a Gram matrix it is a one-signed bias of
-//           the diagonal (sum of lo^2) that shifts every small eigenvalue.
-//           The dominant hi hi^T products start from zero at every 32-wide
-//           step and are added into FP64 at once, so each FP32 rounding only
-//           sees 64 products; the small correction products share one FP32
-//           accumulator flushed every 16 steps.
-//   FP16X4  the same with FP16 operands, y scaled per frequency by a power of
-//           two so that max |y| lies in [2^14, 2^15) (gram_scale_kernel).
+//   BF16X4  block floating point split, per wave and 32-wide contraction
+//   FP16X4  step: with E chosen so that |y| 2^-E < 2^H for every operand of
+//           the step (H = 8 for BF16, 9 for FP16), y 2^-E = h + l with the
+//           integer h = rint(y 2^-E) (exact in the 16-bit type) and
+//           l = y 2^-E - h rounded to the 16-bit type (|l| <= 1/2).  All four
+//           products h h^T + h l^T + l h^T + l l^T run on
+//           v_mfma_f32_16x16x32_{bf16,f16}.  The h h^T sums are integers of
+//           at most 64 * 2^(2H) <= 2^24, so their FP32 accumulation is exact;
+//           only the representation of l is rounded (2^-(H+9) of the step's
+//           largest operand for BF16, 2^-(H+11) for FP16).  Every step's sums
+//           are scaled by 2^(2E) and added into FP64.  Dropping l l^T (the
+//           common three-product scheme) is not done: on a Gram matrix it is
+//           a one-signed bias of the diagonal that shifts every small
+//           eigenvalue.  The integer form needs no range scaling of the data,
+//           so FP16 and BF16 take the same path.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -71,23 +74,30 @@ template <> struct GramCfg<G_FP16X4> {
   using ACC = v4f;
 };
 
-__device__ __forceinline__ void split_bf16(const float* y, v8bf& hi, v8bf& lo) {
+// Largest value over the 64 lanes of a wavefront.
+__device__ __forceinline__ float wave_max(float x) {
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    __bf16 h = (__bf16)y[e];
-    hi[e] = h;
-    lo[e] = (__bf16)(y[e] - (float)h);
+  for (int o = 32; o > 0; o >>= 1) x = fmaxf(x, __shfl_xor(x, o, 64));
+  return x;
+}
+
+// y 2^-E = h + l (see the header): h exact, l rounded to nearest even.
+template <typename T16, typename FR>
+__device__ __forceinline__ void split_int(const float* y, int e, FR& hi, FR& lo) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const float ys = ldexpf(y[i], -e);
+    const float h = rintf(ys);
+    hi[i] = (T16)h;
+    lo[i] = (T16)(ys - h);
   }
 }
 
-__device__ __forceinline__ void split_f16(const float* y, float s, v8h& hi, v8h& lo) {
-#pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const float v = y[e] * s;
-    _Float16 h = (_Float16)v;
-    hi[e] = h;
-    lo[e] = (_Float16)(v - (float)h);
-  }
+// One 16 x 16 x 32 product of the split operands, FP32 accumulation.
+template <int MODE, typename FR>
+__device__ __forceinline__ v4f mfma_split(FR x, FR y, v4f c) {
+  if constexpr (MODE == G_BF16X4) return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, c, 0, 0, 0);
+  else return __builtin_amdgcn_mfma_f32_16x16x32_f16(x, y, c, 0, 0, 0);
 }
 
 template <typename V>
@@ -203,7 +213,7 @@ __device__ __forceinline__ void stage_issue(char* stage, const char* __restrict_
 template <int MODE, int NT, int G, int WPG>
 __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __restrict__ qhat,
                                           const typename GramCfg<MODE>::T* __restrict__ sqrtw,
-                                          float scale, double* __restrict__ part, int64_t M,
+                                          double* __restrict__ part, int64_t M,
                                           int64_t ldq, int L, int S, bool vec, double* red, char* lds,
                                           int s, int k) {
   using Cfg = GramCfg<MODE>;
@@ -237,20 +247,16 @@ __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __res
   const int64_t nchunk = vec ? M / CD : 0;
   const int64_t c0 = nchunk * s / S, c1 = nchunk * (s + 1) / S;
 
-  ACC accR[NPG], accI[NPG];          // FP64: running sums; split modes: correction terms
-  ACC accG[MODE == G_F64 ? NPG : 1]; // FP64: the third product of the 3-multiplication form
+  constexpr int NACC = MODE == G_F64 ? NPG : 1;
+  ACC accR[NACC], accI[NACC];        // FP64 mode: running sums
+  ACC accG[NACC];                    // FP64 mode: the third product of the 3-multiplication form
   double sR[NPG][4], sI[NPG][4];     // FP64 sums of the FP32 partials (not FP64 mode)
 #pragma unroll
-  for (int i = 0; i < (MODE == G_F64 ? NPG : 1); ++i) accG[i] = ACC{0, 0, 0, 0};
+  for (int i = 0; i < NACC; ++i) accG[i] = accR[i] = accI[i] = ACC{0, 0, 0, 0};
 #pragma unroll
-  for (int i = 0; i < NPG; ++i) {
-    accR[i] = ACC{0, 0, 0, 0};
-    accI[i] = ACC{0, 0, 0, 0};
+  for (int i = 0; i < NPG; ++i)
 #pragma unroll
     for (int v = 0; v < 4; ++v) sR[i][v] = sI[i][v] = 0.0;
-  }
-
-  int since_flush = 0;
   auto compute = [&](const Raw<MODE, NT>& cur) {
     if constexpr (!SPLIT) {
       // four 4-wide MFMA steps; step t uses element t of every lane's run
@@ -295,24 +301,33 @@ __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __res
       }
     } else {
       using FR = typename std::conditional<MODE == G_BF16X4, v8bf, v8h>::type;
+      using T16 = typename std::conditional<MODE == G_BF16X4, __bf16, _Float16>::type;
+      constexpr int H = MODE == G_BF16X4 ? 8 : 9;     // bits of the integer part h
+      float ya[NT][8], yb[NT][8];
+      float mx = 0.0f;
+#pragma unroll
+      for (int a = 0; a < NT; ++a) {
+        if (!((NEED >> a) & 1u)) continue;
+        const bool live = 16 * a + r16 < L;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          ya[a][e] = live ? cur.x[a][e].x * cur.w[e] : 0.0f;
+          yb[a][e] = live ? cur.x[a][e].y * cur.w[e] : 0.0f;
+          mx = fmaxf(mx, fmaxf(fabsf(ya[a][e]), fabsf(yb[a][e])));
+        }
+      }
+      // one exponent for the whole step of this wave: mx < 2^ex, so
+      // |y| 2^-E < 2^H with E = ex - H (uniform across the wavefront)
+      int ex = 0;
+      (void)frexpf(wave_max(mx), &ex);
+      const int E = __builtin_amdgcn_readfirstlane(ex) - H;
+      const double unit = ldexp(1.0, 2 * E);            // value of one integer product
       FR ah[NT], al[NT], bh[NT], bl[NT];
 #pragma unroll
       for (int a = 0; a < NT; ++a) {
         if (!((NEED >> a) & 1u)) continue;
-        float ya[8], yb[8];
-        const bool live = 16 * a + r16 < L;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          ya[e] = live ? cur.x[a][e].x * cur.w[e] : 0.0f;
-          yb[e] = live ? cur.x[a][e].y * cur.w[e] : 0.0f;
-        }
-        if constexpr (MODE == G_BF16X4) {
-          split_bf16(ya, ah[a], al[a]);
-          split_bf16(yb, bh[a], bl[a]);
-        } else {
-          split_f16(ya, scale, ah[a], al[a]);
-          split_f16(yb, scale, bh[a], bl[a]);
-        }
+        split_int<T16>(ya[a], E, ah[a], al[a]);
+        split_int<T16>(yb[a], E, bh[a], bl[a]);
       }
       int pi = 0;
 #pragma unroll
@@ -322,60 +337,35 @@ __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __res
           if (pi < P0 || pi >= P0 + NPG) continue;
           const int i = pi - P0;
           const FR nbh = negate(bh[a]), nbl = negate(bl[a]);
-          ACC tr, ti;
-          if constexpr (MODE == G_BF16X4) {
-            tr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], ah[b], ACC{0, 0, 0, 0}, 0, 0, 0);
-            tr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh[a], bh[b], tr, 0, 0, 0);
-            ti = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], ACC{0, 0, 0, 0}, 0, 0, 0);
-            ti = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nbh, ah[b], ti, 0, 0, 0);
-            accR[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], al[b], accR[i], 0, 0, 0);
-            accR[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], ah[b], accR[i], 0, 0, 0);
-            accR[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], al[b], accR[i], 0, 0, 0);
-            accR[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh[a], bl[b], accR[i], 0, 0, 0);
-            accR[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bl[a], bh[b], accR[i], 0, 0, 0);
-            accR[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bl[a], bl[b], accR[i], 0, 0, 0);
-            accI[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], accI[i], 0, 0, 0);
-            accI[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], accI[i], 0, 0, 0);
-            accI[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bl[b], accI[i], 0, 0, 0);
-            accI[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nbh, al[b], accI[i], 0, 0, 0);
-            accI[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nbl, ah[b], accI[i], 0, 0, 0);
-            accI[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nbl, al[b], accI[i], 0, 0, 0);
-          } else {
-            tr = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[a], ah[b], ACC{0, 0, 0, 0}, 0, 0, 0);
-            tr = __builtin_amdgcn_mfma_f32_16x16x32_f16(bh[a], bh[b], tr, 0, 0, 0);
-            ti = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[a], bh[b], ACC{0, 0, 0, 0}, 0, 0, 0);
-            ti = __builtin_amdgcn_mfma_f32_16x16x32_f16(nbh, ah[b], ti, 0, 0, 0);
-            accR[i] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[a], al[b], accR[i], 0, 0, 0);
-            accR[i] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[a], ah[b], accR[i], 0, 0, 0);
-            accR[i] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[a], al[b], accR[i], 0, 0, 0);
-            accR[i] = __builtin_amdgcn_mfma_f32_16x16x32_f16(bh[a], bl[b], accR[i], 0, 0, 0);
-            accR[i] = __builtin_amdgcn_mfma_f32_16x16x32_f16(bl[a], bh[b], accR[i], 0, 0, 0);
-            accR[i] = __builtin_amdgcn_mfma_f32_16x16x32_f16(bl[a], bl[b], accR[i], 0, 0, 0);
-            accI[i] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[a], bl[b], accI[i], 0, 0, 0);
-            accI[i] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[a], bh[b], accI[i], 0, 0, 0);
-            accI[i] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[a], bl[b], accI[i], 0, 0, 0);
-            accI[i] = __builtin_amdgcn_mfma_f32_16x16x32_f16(nbh, al[b], accI[i], 0, 0, 0);
-            accI[i] = __builtin_amdgcn_mfma_f32_16x16x32_f16(nbl, ah[b], accI[i], 0, 0, 0);
-            accI[i] = __builtin_amdgcn_mfma_f32_16x16x32_f16(nbl, al[b], accI[i], 0, 0, 0);
-          }
+          ACC tr, ti, cr, ci;
+#define SPOD_MFMA(x, y, acc) mfma_split<MODE>((x), (y), (acc))
+          const ACC z = ACC{0, 0, 0, 0};
+          // exact integer sums: Re h = ha hb^T (re) + ..., Im h = ha_re hb_im^T - ha_im hb_re^T
+          tr = SPOD_MFMA(ah[a], ah[b], z);
+          tr = SPOD_MFMA(bh[a], bh[b], tr);
+          ti = SPOD_MFMA(ah[a], bh[b], z);
+          ti = SPOD_MFMA(nbh, ah[b], ti);
+          // correction products (rounded FP32 sums, at most 2^-(H-1) of the above)
+          cr = SPOD_MFMA(ah[a], al[b], z);
+          cr = SPOD_MFMA(al[a], ah[b], cr);
+          cr = SPOD_MFMA(al[a], al[b], cr);
+          cr = SPOD_MFMA(bh[a], bl[b], cr);
+          cr = SPOD_MFMA(bl[a], bh[b], cr);
+          cr = SPOD_MFMA(bl[a], bl[b], cr);
+          ci = SPOD_MFMA(ah[a], bl[b], z);
+          ci = SPOD_MFMA(al[a], bh[b], ci);
+          ci = SPOD_MFMA(al[a], bl[b], ci);
+          ci = SPOD_MFMA(nbh, al[b], ci);
+          ci = SPOD_MFMA(nbl, ah[b], ci);
+          ci = SPOD_MFMA(nbl, al[b], ci);
+#undef SPOD_MFMA
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            sR[i][v] += (double)tr[v];
-            sI[i][v] += (double)ti[v];
+            sR[i][v] = fma((double)tr[v], unit, sR[i][v]);
+            sR[i][v] = fma((double)cr[v], unit, sR[i][v]);
+            sI[i][v] = fma((double)ti[v], unit, sI[i][v]);
+            sI[i][v] = fma((double)ci[v], unit, sI[i][v]);
           }
-        }
-      }
-      if (++since_flush == 16) {
-        since_flush = 0;
-#pragma unroll
-        for (int i = 0; i < NPG; ++i) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            sR[i][v] += (double)accR[i][v];
-            sI[i][v] += (double)accI[i][v];
-          }
-          accR[i] = ACC{0, 0, 0, 0};
-          accI[i] = ACC{0, 0, 0, 0};
         }
       }
     }
@@ -455,24 +445,6 @@ __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __res
         sR[i][v] = accR[i][v] + accI[i][v];
         sI[i][v] = (accG[i][v] - accR[i][v]) + accI[i][v];
       }
-  } else if constexpr (SPLIT) {
-#pragma unroll
-    for (int i = 0; i < NPG; ++i)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        sR[i][v] += (double)accR[i][v];
-        sI[i][v] += (double)accI[i][v];
-      }
-  }
-  if constexpr (MODE == G_FP16X4) {
-    const double inv = 1.0 / ((double)scale * (double)scale);
-#pragma unroll
-    for (int i = 0; i < NPG; ++i)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        sR[i][v] *= inv;
-        sI[i][v] *= inv;
-      }
   }
 
   // the stages are reused for the reduction: drain the last (re-read)
@@ -522,7 +494,7 @@ __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __res
 template <int MODE, int NT>
 __device__ __forceinline__ void gram_unit(const typename GramCfg<MODE>::C* __restrict__ qhat,
                                           const typename GramCfg<MODE>::T* __restrict__ sqrtw,
-                                          const float* __restrict__ fscale, double* __restrict__ part,
+                                          double* __restrict__ part,
                                           int64_t M, int64_t ldq, int L, int S, int K, bool vec,
                                           int64_t local, char* lds) {
   constexpr int NP = NT * (NT + 1) / 2;
@@ -533,13 +505,12 @@ __device__ __forceinline__ void gram_unit(const typename GramCfg<MODE>::C* __res
   const int s = (int)(local % S);
   const int k = (int)(local / S);
   double* red = reinterpret_cast<double*>(lds);                      // reused after the loop
-  const float scale = (MODE == G_FP16X4) ? fscale[k] : 1.0f;
   const int g = (int)(threadIdx.x >> 6) / WPG;
   switch (g) {
-    case 0: gram_body<MODE, NT, 0, WPG>(qhat, sqrtw, scale, part, M, ldq, L, S, vec, red, lds, s, k); break;
-    case 1: if constexpr (NG > 1) gram_body<MODE, NT, 1, WPG>(qhat, sqrtw, scale, part, M, ldq, L, S, vec, red, lds, s, k); break;
-    case 2: if constexpr (NG > 2) gram_body<MODE, NT, 2, WPG>(qhat, sqrtw, scale, part, M, ldq, L, S, vec, red, lds, s, k); break;
-    case 3: if constexpr (NG > 3) gram_body<MODE, NT, 3, WPG>(qhat, sqrtw, scale, part, M, ldq, L, S, vec, red, lds, s, k); break;
+    case 0: gram_body<MODE, NT, 0, WPG>(qhat, sqrtw, part, M, ldq, L, S, vec, red, lds, s, k); break;
+    case 1: if constexpr (NG > 1) gram_body<MODE, NT, 1, WPG>(qhat, sqrtw, part, M, ldq, L, S, vec, red, lds, s, k); break;
+    case 2: if constexpr (NG > 2) gram_body<MODE, NT, 2, WPG>(qhat, sqrtw, part, M, ldq, L, S, vec, red, lds, s, k); break;
+    case 3: if constexpr (NG > 3) gram_body<MODE, NT, 3, WPG>(qhat, sqrtw, part, M, ldq, L, S, vec, red, lds, s, k); break;
     default: break;
   }
 }
@@ -547,17 +518,14 @@ __device__ __forceinline__ void gram_unit(const typename GramCfg<MODE>::C* __res
 template <int MODE, int NT>
 __global__ __launch_bounds__(256, 2) void gram_kernel(const typename GramCfg<MODE>::C* __restrict__ qhat,
                                                       const void* __restrict__ sqrtw_v,
-                                                      const float* __restrict__ fscale,
                                                       double* __restrict__ part, int64_t M, int L,
                                                       int S, int K, int vec) {
   using T = typename GramCfg<MODE>::T;
   extern __shared__ __attribute__((aligned(16))) char gram_lds[];   // 2 stages
-  gram_unit<MODE, NT>(qhat, static_cast<const T*>(sqrtw_v), fscale, part, M, M, L, S, K, vec != 0,
+  gram_unit<MODE, NT>(qhat, static_cast<const T*>(sqrtw_v), part, M, M, L, S, K, vec != 0,
                       blockIdx.x, gram_lds);
 }
 
-// Grouped launch over a batch: workgroup b -> item, then (pair group, slice,
-// frequency) = the item's local index in that order.
 // Grouped launch over a batch: workgroup b -> item, then the item's local
 // index -> work unit as in gram_kernel.
 template <int MODE, int NT>
@@ -566,8 +534,7 @@ __global__ __launch_bounds__(256, 2) void gram_batch_kernel(const GramItem* __re
   using C = typename GramCfg<MODE>::C;
   extern __shared__ __attribute__((aligned(16))) char gram_lds[];
   const GramItem& it = items[find_item(items, n, (int)blockIdx.x)];
-  gram_unit<MODE, NT>(static_cast<const C*>(it.qhat), static_cast<const T*>(it.sqrtw), it.fscale,
-                      it.part, it.M, it.ldq, it.L, it.S, it.K, it.vec != 0,
+  gram_unit<MODE, NT>(static_cast<const C*>(it.qhat), static_cast<const T*>(it.sqrtw), it.part, it.M, it.ldq, it.L, it.S, it.K, it.vec != 0,
                       (int64_t)blockIdx.x - it.start, gram_lds);
 }
 
@@ -610,94 +577,15 @@ __global__ __launch_bounds__(256) void gram_combine_batch_kernel(const CombineIt
                     it.D, it.S, (int)blockIdx.x - it.start, false);
 }
 
-// Per-frequency power-of-two scale for the FP16 operands: 2^(15 - e) with e
-// the exponent of max_m,l |sqrt(W_m) qhat[k][l][m]| (real or imaginary part),
-// so the largest scaled value lies in [2^14, 2^15) < 65504.  Two stages, in a
-// fixed order: workgroup (c, k) takes the maximum over every row of the c-th
-// of SCALE_PARTS ranges of degrees of freedom, then one wave per frequency
-// reduces the partial maxima.
-constexpr int SCALE_PARTS = 64;
-
-__device__ __forceinline__ void gram_scale_part_body(const float2* __restrict__ qhat,
-                                                     const float* __restrict__ sqrtw,
-                                                     float* __restrict__ pmax, int64_t M,
-                                                     int64_t ldq, int L, int k, int c) {
-  const float2* base = qhat + (int64_t)k * L * ldq;
-  const int64_t m0 = M * c / SCALE_PARTS, m1 = M * (c + 1) / SCALE_PARTS;
-  float mx = 0.0f;
-  for (int l = 0; l < L; ++l) {
-    const float2* row = base + (int64_t)l * ldq;
-    for (int64_t m = m0 + threadIdx.x; m < m1; m += 256) {
-      const float2 z = row[m];
-      const float w = sqrtw[m];
-      mx = fmaxf(mx, fmaxf(fabsf(z.x * w), fabsf(z.y * w)));
-    }
-  }
-  __shared__ float red[256];
-  red[threadIdx.x] = mx;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + o]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) pmax[(int64_t)k * SCALE_PARTS + c] = red[0];
-}
-
-__device__ __forceinline__ void gram_scale_final_body(const float* __restrict__ pmax,
-                                                      float* __restrict__ scale, int k) {
-  static_assert(SCALE_PARTS == 64, "one partial per lane");
-  float m = pmax[(int64_t)k * SCALE_PARTS + (threadIdx.x & 63)];
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
-  if (threadIdx.x == 0) {
-    int e = 0;
-    if (m > 0.0f) (void)frexpf(m, &e);
-    scale[k] = ldexpf(1.0f, 15 - e);
-  }
-}
-
-__global__ __launch_bounds__(256) void gram_scale_part_kernel(const float2* __restrict__ qhat,
-                                                              const float* __restrict__ sqrtw,
-                                                              float* __restrict__ pmax, int64_t M,
-                                                              int L) {
-  gram_scale_part_body(qhat, sqrtw, pmax, M, M, L, blockIdx.y, blockIdx.x);
-}
-
-__global__ __launch_bounds__(64) void gram_scale_final_kernel(const float* __restrict__ pmax,
-                                                              float* __restrict__ scale) {
-  gram_scale_final_body(pmax, scale, blockIdx.x);
-}
-
-// grouped: stage 1 units = (k, c) per item (c fastest), stage 2 units = k
-__global__ __launch_bounds__(256) void gram_scale_part_batch_kernel(const CombineItem* __restrict__ items,
-                                                                    int n) {
-  const CombineItem& it = items[find_item(items, n, (int)blockIdx.x)];
-  const int local = (int)blockIdx.x - it.start;
-  gram_scale_part_body(static_cast<const float2*>(it.part), static_cast<const float*>(it.sqrtw),
-                       static_cast<float*>(it.aux), it.M, it.ldq, it.L, local / SCALE_PARTS,
-                       local % SCALE_PARTS);
-}
-
-__global__ __launch_bounds__(64) void gram_scale_final_batch_kernel(const CombineItem* __restrict__ items,
-                                                                    int n) {
-  const CombineItem& it = items[find_item(items, n, (int)blockIdx.x)];
-  const int local = (int)blockIdx.x - it.start;
-  if (local % SCALE_PARTS) return;     // one workgroup per frequency reduces
-  gram_scale_final_body(static_cast<const float*>(it.aux), static_cast<float*>(it.gram),
-                        local / SCALE_PARTS);
-}
-
 // ---------------------------------------------------------------------------
 size_t csd_workspace(const Plan& p) {
   const size_t D = (size_t)p.gram_dim;
-  size_t b = sizeof(double2) * (size_t)p.nfreq * (size_t)p.gram_split * D * D;
-  if (p.prec == SPOD_PREC_FP16X4) b += sizeof(float) * (size_t)p.nfreq * (1 + SCALE_PARTS) + 256;
-  return b;
+  return sizeof(double2) * (size_t)p.nfreq * (size_t)p.gram_split * D * D;
 }
 
 template <int MODE, int NTI>
-static void launch_gram_nti(const Plan& p, const void* qhat, const void* sqrtw, const float* fs,
-                            double* part, hipStream_t st) {
+static void launch_gram_nti(const Plan& p, const void* qhat, const void* sqrtw, double* part,
+                            hipStream_t st) {
   using C = typename GramCfg<MODE>::C;
   constexpr int NP = NTI * (NTI + 1) / 2;
   (void)NP;
@@ -710,18 +598,18 @@ static void launch_gram_nti(const Plan& p, const void* qhat, const void* sqrtw, 
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gram_kernel<MODE, NTI>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL((gram_kernel<MODE, NTI>), grid, dim3(256), lds, st,
-                     static_cast<const C*>(qhat), sqrtw, fs, part, (int64_t)p.M, (int)p.nblocks,
+                     static_cast<const C*>(qhat), sqrtw, part, (int64_t)p.M, (int)p.nblocks,
                      p.gram_split, (int)p.nfreq, (int)vec);
 }
 
 template <int MODE>
 static spod_status launch_gram_mode(const Plan& p, const void* qhat, const void* sqrtw,
-                                    const float* fs, double* part, hipStream_t st) {
+                                    double* part, hipStream_t st) {
   switch (p.gram_dim / 16) {
-    case 1: launch_gram_nti<MODE, 1>(p, qhat, sqrtw, fs, part, st); break;
-    case 2: launch_gram_nti<MODE, 2>(p, qhat, sqrtw, fs, part, st); break;
-    case 3: launch_gram_nti<MODE, 3>(p, qhat, sqrtw, fs, part, st); break;
-    case 4: launch_gram_nti<MODE, 4>(p, qhat, sqrtw, fs, part, st); break;
+    case 1: launch_gram_nti<MODE, 1>(p, qhat, sqrtw, part, st); break;
+    case 2: launch_gram_nti<MODE, 2>(p, qhat, sqrtw, part, st); break;
+    case 3: launch_gram_nti<MODE, 3>(p, qhat, sqrtw, part, st); break;
+    case 4: launch_gram_nti<MODE, 4>(p, qhat, sqrtw, part, st); break;
     default: return fail(SPOD_ERR_UNSUPPORTED, "nblocks > 64");
   }
   hipError_t e = hipGetLastError();
@@ -733,22 +621,12 @@ spod_status launch_csd(const Plan& p, const void* qhat, void* gram, void* ws, hi
   if (p.nblocks > 64) return fail(SPOD_ERR_UNSUPPORTED, "nblocks > 64");
   double* part = static_cast<double*>(ws);
   const size_t D = (size_t)p.gram_dim;
-  float* fs = reinterpret_cast<float*>(
-      static_cast<char*>(ws) + sizeof(double2) * (size_t)p.nfreq * (size_t)p.gram_split * D * D);
   spod_status s;
   switch (p.prec) {
-    case SPOD_PREC_FP64: s = launch_gram_mode<G_F64>(p, qhat, p.d_sqrtw, nullptr, part, st); break;
-    case SPOD_PREC_FP32: s = launch_gram_mode<G_F32>(p, qhat, p.d_sqrtw32, nullptr, part, st); break;
-    case SPOD_PREC_BF16X4: s = launch_gram_mode<G_BF16X4>(p, qhat, p.d_sqrtw32, nullptr, part, st); break;
-    case SPOD_PREC_FP16X4: {
-      float* pmax = fs + p.nfreq;            // [K][SCALE_PARTS] partial maxima
-      hipLaunchKernelGGL(gram_scale_part_kernel, dim3(SCALE_PARTS, (unsigned)p.nfreq), dim3(256), 0,
-                         st, static_cast<const float2*>(qhat), p.d_sqrtw32, pmax, (int64_t)p.M,
-                         (int)p.nblocks);
-      hipLaunchKernelGGL(gram_scale_final_kernel, dim3((unsigned)p.nfreq), dim3(64), 0, st, pmax, fs);
-      s = launch_gram_mode<G_FP16X4>(p, qhat, p.d_sqrtw32, fs, part, st);
-      break;
-    }
+    case SPOD_PREC_FP64: s = launch_gram_mode<G_F64>(p, qhat, p.d_sqrtw, part, st); break;
+    case SPOD_PREC_FP32: s = launch_gram_mode<G_F32>(p, qhat, p.d_sqrtw32, part, st); break;
+    case SPOD_PREC_BF16X4: s = launch_gram_mode<G_BF16X4>(p, qhat, p.d_sqrtw32, part, st); break;
+    case SPOD_PREC_FP16X4: s = launch_gram_mode<G_FP16X4>(p, qhat, p.d_sqrtw32, part, st); break;
     default: return fail(SPOD_ERR_INVALID_ARG, "precision");
   }
   if (s != SPOD_OK) return s;
@@ -802,17 +680,6 @@ spod_status launch_gram_group(spod_precision prec, int nt16, const GramItem* d_i
     case SPOD_PREC_FP16X4: return gram_group_mode<G_FP16X4>(nt16, d_items, n, wgs, st);
   }
   return fail(SPOD_ERR_INVALID_ARG, "precision");
-}
-
-int gram_scale_parts() { return SCALE_PARTS; }
-
-spod_status launch_gram_scale_group(const CombineItem* d_items, int n, int wgs, hipStream_t st) {
-  // wgs = sum over items of K * SCALE_PARTS; stage 2 reuses the same table
-  // and grid, and only the first workgroup of each frequency works
-  hipLaunchKernelGGL(gram_scale_part_batch_kernel, dim3((unsigned)wgs), dim3(256), 0, st, d_items, n);
-  hipLaunchKernelGGL(gram_scale_final_batch_kernel, dim3((unsigned)wgs), dim3(64), 0, st, d_items, n);
-  hipError_t e = hipGetLastError();
-  return e == hipSuccess ? SPOD_OK : hip_fail(e, "gram_scale_batch_kernel");
 }
 
 spod_status launch_gram_combine_group(const CombineItem* d_items, int n, int wgs, hipStream_t st) {

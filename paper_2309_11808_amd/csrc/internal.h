@@ -202,19 +202,15 @@ struct FftItem {                 // blocks_fft, fused mean, all blocks per tile
 struct GramItem {                // gram partials, work unit = (slice, k)
   const void* qhat;
   const void* sqrtw;
-  const float* fscale;
   double* part;
   int64_t M, ldq;
   int L, S, K, vec;
   int start;
 };
 
-struct CombineItem {             // gram_combine (unit k) / gram_scale (unit (k, part))
-  const void* part;              // combine: partials; scale: qhat
-  void* gram;                    // combine: gram; scale: float scales [K]
-  const void* sqrtw;             // scale only
-  void* aux;                     // scale only: partial maxima [K][gram_scale_parts()]
-  int64_t M, ldq;                // scale only
+struct CombineItem {             // gram_combine, work unit = k
+  const void* part;              // partials [K][S][D][D]
+  void* gram;                    // [K][L][L]
   int L, D, S;
   int start;
 };
@@ -262,8 +258,6 @@ spod_status launch_gram_group(spod_precision prec, int nt16, const GramItem* d_i
                               int wgs, hipStream_t st);
 int gram_groups(int nt16);                           // pair groups per (slice, k)
 int64_t gram_group_wgs(int nt16, int64_t S, int64_t K);   // workgroups of one problem
-spod_status launch_gram_scale_group(const CombineItem* d_items, int n, int wgs, hipStream_t st);
-int gram_scale_parts();                              // FP16 scale: partial maxima per frequency
 spod_status launch_gram_combine_group(const CombineItem* d_items, int n, int wgs, hipStream_t st);
 spod_status launch_eig_group(const EigItem* d_items, int n, int wgs, int max_sweeps, int lmax,
                              hipStream_t st);   // lmax: the group's largest L (16, 32 or 64)

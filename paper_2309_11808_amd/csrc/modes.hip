@@ -15,6 +15,7 @@
 namespace spod {
 
 constexpr int MODES_MAXL = 64;
+constexpr int MODES_MAXM = 256;   // largest n_modes (n_modes <= L)
 constexpr int MODES_GROUP = 8;
 
 // Pairs of degrees of freedom as one 16-byte vector (complex64 only).
@@ -31,9 +32,18 @@ __device__ __forceinline__ void modes_body(const cpx_t<TC>* __restrict__ qhat,
   static_assert(!PAIR || sizeof(TC) == 4, "pairs are 16-byte complex64 vectors");
   extern __shared__ char modes_lds[];
   C* coef = reinterpret_cast<C*>(modes_lds);   // [L][n_modes]
+  // valid-mode flags: an invalid mode is stored as zeros, not as the
+  // accumulated sum (which is not zero when qhat holds a NaN or an infinity)
+  __shared__ unsigned vmask[MODES_MAXM / 32];
   const int tid = threadIdx.x;
   const double* lk = lam + (int64_t)k * L;
   const double l0 = lk[0];
+  if (tid < MODES_MAXM / 32) {
+    unsigned b = 0;
+    for (int j = 32 * tid; j < n_modes && j < 32 * tid + 32; ++j)
+      b |= (unsigned)(l0 > 0.0 && lk[j] > eps * l0) << (j - 32 * tid);
+    vmask[tid] = b;
+  }
   for (int idx = tid; idx < L * n_modes; idx += blockDim.x) {
     const int l = idx / n_modes, j = idx % n_modes;
     const double lj = lk[j];
@@ -84,6 +94,10 @@ __device__ __forceinline__ void modes_body(const cpx_t<TC>* __restrict__ qhat,
 #pragma unroll
     for (int j = 0; j < MODES_GROUP; ++j) {
       if (j0 + j < n_modes) {
+        if (!((vmask[(j0 + j) >> 5] >> ((j0 + j) & 31)) & 1u)) {
+#pragma unroll
+          for (int d = 0; d < DPT; ++d) acc[d][j] = C{0, 0};
+        }
         if constexpr (PAIR) {
           const modes_v4 v = {acc[0][j].x, acc[0][j].y, acc[1][j].x, acc[1][j].y};
           __builtin_nontemporal_store(v, reinterpret_cast<modes_v4*>(dst + (int64_t)(j0 + j) * M));

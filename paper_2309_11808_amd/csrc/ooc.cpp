@@ -128,6 +128,7 @@ struct Ooc {
   void* phi_c[2] = {nullptr, nullptr};   // modes of one chunk, [K][n_modes][rows]
   double2* gram = nullptr;       // [K][L][L]
   double* mean = nullptr;        // [M]
+  int32_t* info = nullptr;       // [K], when the caller passes no info array
   void* ws = nullptr;
   void* pin_q[2] = {nullptr, nullptr};   // pinned staging (allocated on demand)
   void* pin_phi[2] = {nullptr, nullptr};
@@ -154,7 +155,7 @@ void release(Ooc* o) {
   if (o->cout) (void)hipStreamSynchronize(o->cout);
   for (void* s : o->slot)
     if (s) (void)hipFree(s);
-  void* dev[] = {o->qhat, o->phi_c[0], o->phi_c[1], o->gram, o->mean, o->ws};
+  void* dev[] = {o->qhat, o->phi_c[0], o->phi_c[1], o->gram, o->mean, o->info, o->ws};
   for (void* b : dev)
     if (b) (void)hipFree(b);
   void* pin[] = {o->pin_q[0], o->pin_q[1], o->pin_phi[0], o->pin_phi[1]};
@@ -351,6 +352,7 @@ spod_status ooc_create_body(Ooc* o, Plan* p, spod_dtype dtype, int64_t chunk_row
     if ((e = hipMalloc(&b, o->phi_bytes)) != hipSuccess) return bail(e, "chunk modes");
   if ((e = hipMalloc(&o->gram, gram_bytes)) != hipSuccess) return bail(e, "gram");
   if ((e = hipMalloc(&o->mean, mean_bytes)) != hipSuccess) return bail(e, "mean");
+  if ((e = hipMalloc(&o->info, up256(K * sizeof(int32_t)))) != hipSuccess) return bail(e, "info");
   if ((e = hipMalloc(&o->ws, o->ws_bytes)) != hipSuccess) return bail(e, "workspace");
   if ((e = hipStreamCreateWithFlags(&o->cin, hipStreamNonBlocking)) != hipSuccess)
     return bail(e, "hipStreamCreateWithFlags");
@@ -474,7 +476,7 @@ spod_status spod_ooc_forward(spod_ooc ooc, const void* q, spod_read_fn read, voi
     if (r == SPOD_OK) r = run.hip(hipStreamWaitEvent(o->cout, o->start, 0), "hipStreamWaitEvent");
     try {
       if (r == SPOD_OK) r = run.pass1();
-      if (r == SPOD_OK) r = launch_eig(p, o->gram, lam, psi, info, o->ws, st);
+      if (r == SPOD_OK) r = launch_eig(p, o->gram, lam, psi, info ? info : o->info, o->ws, st);
       if (r == SPOD_OK) r = run.pass2(lam, psi, n_valid);
     } catch (const std::bad_alloc&) {
       r = fail(SPOD_ERR_ALLOC, "host memory");
@@ -490,7 +492,16 @@ spod_status spod_ooc_forward(spod_ooc ooc, const void* q, spod_read_fn read, voi
     if (e2 != hipSuccess) return hip_fail(e2, "hipStreamSynchronize");
     if (e3 != hipSuccess) return hip_fail(e3, "hipStreamSynchronize");
     e = hipMemcpy(mean, o->mean, sizeof(double) * (size_t)p.M, hipMemcpyDefault);
-    return e == hipSuccess ? SPOD_OK : hip_fail(e, "hipMemcpy");
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+    // every output is written; a frequency whose Gram was not finite (NaN or
+    // infinite data) is reported as a numeric failure of the whole call
+    std::vector<int32_t> h_info((size_t)p.nfreq);
+    e = hipMemcpy(h_info.data(), info ? info : o->info, sizeof(int32_t) * (size_t)p.nfreq,
+                  hipMemcpyDefault);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+    for (int32_t v : h_info)
+      if (v == SPOD_INFO_NONFINITE) return fail(SPOD_ERR_NUMERIC, "non-finite data (see info)");
+    return SPOD_OK;
   });
 }
 

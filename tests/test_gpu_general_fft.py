@@ -80,7 +80,7 @@ def test_hourly_year_blocks_end_to_end():
     plan = _plan(p, "fp64")
     out = plan.forward(p.q.cuda(), n_modes=3)
     torch.cuda.synchronize()
-    PT.check_eig(out["lam"], ref["lam"], rtol=1e-10, floor_rel=1e-13)
+    PT.check_eig(out["lam"], ref["lam"], rtol=1e-10)
     s, n = PT.check_modes(out["phi"], ref["phi"], ref["lam"], p.weights, ref["n_valid"],
                           sin_tol=1e-8, elem_tol=1e-6, rel_gap=1e-6)
     print(f"N=8760 end to end: modes compared {n}, worst sine {s:.2e}")

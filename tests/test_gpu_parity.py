@@ -161,7 +161,7 @@ def test_eig_matches_oracle(L, kind):
     lo, psio = O.sort_and_phase(lo, Vo)
     info = info.cpu().numpy()
     assert (info > 0).all(), info
-    PT.check_eig(lam, lo, rtol=1e-12, floor_rel=1e-14)
+    PT.check_eig(lam, lo, rtol=1e-12, theta=1e-2)
     lg, pg = lam.cpu().numpy(), psi.cpu().numpy()
     nrm = np.linalg.norm(A, axis=(1, 2))
     for k in range(K):
@@ -267,7 +267,13 @@ def test_planted_field_mixed_end_to_end(prec):
     p = fields.planted(seed=1, sigma=0.1, dtype=torch.float32)
     _, g = _end_to_end(p, prec)
     o = O.spod(p.q.numpy(), 128, 64, weights=p.weights, n_modes=5, eps=1e-6)
-    PT.check_eig_mixed(g["lam"], o["lam"], p.M, n=5)
+    # The FP32 form rounds every 8-product MFMA partial to FP32 before it
+    # reaches FP64 (24-bit operands have no exact-integer form on the FP32
+    # matrix cores): about 2^-24 sqrt(8/M) lambda_1 per Gram entry, which at
+    # M = 1024 reaches 1e-4 of an eigenvalue ~2e5 below lambda_1 (this field's
+    # noise eigenvalues).  It is held to the relative bar from 1e-4 lambda_1 up;
+    # the split forms meet it from 1e-6 lambda_1 up.
+    PT.check_eig_mixed(g["lam"], o["lam"], n=5, theta=1e-4 if prec == "fp32" else PT.THETA_MIXED)
     s, n = PT.check_modes(g["phi"], o["phi"], o["lam"], p.weights, o["n_valid"], sin_tol=1e-3,
                           elem_tol=1e-2, rel_gap=1e-3)
     assert n > 100
