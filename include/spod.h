@@ -156,6 +156,26 @@ spod_status spod_blocks_fft(spod_plan plan, const void* q, spod_dtype dtype, voi
 spod_status spod_csd(spod_plan plan, const void* qhat, void* gram, void* ws, size_t ws_bytes,
                      spod_stream stream);
 
+/* Bytes of device scratch the library holds for spod_csd_noalloc, per device. */
+#define SPOD_CSD_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+
+/* spod_csd for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops that must not call hipMalloc, harnesses that
+ * forbid it): the same weighted inner product, with the Gram partials in a
+ * static device array of the library (SPOD_CSD_NOALLOC_MAX_BYTES = 64 MiB on
+ * every device the library runs on, held until the process ends) instead of a
+ * workspace.  The caller still passes qhat and gram as for spod_csd.  The
+ * number of slices of M is the plan's, reduced to what fits the array; it is
+ * written to *slices when slices != NULL (0 when even one slice does not fit).
+ * Calls no allocation routine.  Calls that overlap on one device (several
+ * streams, several host threads) share the array and race: the caller must
+ * order them.  Results differ from spod_csd's only in the FP64 summation order
+ * of the slices, and are identical when the slice counts agree.
+ * SPOD_ERR_UNSUPPORTED when one slice of partials, nfreq * (16 ceil(nblocks /
+ * 16))^2 * 16 bytes, exceeds the array. */
+spod_status spod_csd_noalloc(spod_plan plan, const void* qhat, void* gram, int64_t* slices,
+                             spod_stream stream);
+
 /* Step 5 (eq. (spod-discrete-snapshots); Sec. 3.1 step 5): eigendecomposition
  * of every Hermitian gram[k] by cyclic Jacobi in FP64.
  *   lam  : device [K][L] float64, descending.

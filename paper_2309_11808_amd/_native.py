@@ -25,6 +25,7 @@ SPOD_F32 = 0
 SPOD_F64 = 1
 
 SPOD_INFO_NONFINITE = -2147483648   # spod_eig info of a non-finite Gram matrix
+SPOD_CSD_NOALLOC_MAX_BYTES = 64 << 20
 
 SPOD_PREC_FP64 = 0
 SPOD_PREC_FP32 = 1
@@ -68,6 +69,7 @@ SIGNATURES = {
     "spod_plan_query": (C.c_int, [_p, C.POINTER(_i64), C.POINTER(_i64), C.POINTER(_sz)]),
     "spod_blocks_fft": (C.c_int, [_p, _p, C.c_int, _p, _p, _p, _sz, _p]),
     "spod_csd": (C.c_int, [_p, _p, _p, _p, _sz, _p]),
+    "spod_csd_noalloc": (C.c_int, [_p, _p, _p, C.POINTER(_i64), _p]),
     "spod_eig": (C.c_int, [_p, _p, _p, _p, _p, _p, _sz, _p]),
     "spod_modes": (C.c_int, [_p, _p, _p, _p, _i64, _p, _p, _p, _sz, _p]),
     "spod_backward": (C.c_int, [_p, _p, C.c_int, _p, _p, _p, _p, _p, _i64, _p, _i64, _p, _p, _p,

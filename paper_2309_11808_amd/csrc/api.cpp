@@ -422,6 +422,18 @@ spod_status spod_csd(spod_plan plan, const void* qhat, void* gram, void* ws, siz
   return launch_csd(*p, qhat, gram, ws, (hipStream_t)stream);
 }
 
+spod_status spod_csd_noalloc(spod_plan plan, const void* qhat, void* gram, int64_t* slices,
+                             spod_stream stream) {
+  return guarded([&]() -> spod_status {
+    Plan* p = reinterpret_cast<Plan*>(plan);
+    spod_status st = enter(p);
+    if (st != SPOD_OK) return st;
+    if (!qhat || !gram) return fail(SPOD_ERR_INVALID_ARG, "qhat and gram are required");
+    if (slices) *slices = csd_noalloc_split(*p);
+    return launch_csd_noalloc(*p, qhat, gram, (hipStream_t)stream);
+  });
+}
+
 spod_status spod_eig(spod_plan plan, const void* gram, double* lam, void* psi, int32_t* info,
                      void* ws, size_t ws_bytes, spod_stream stream) {
   Plan* p = reinterpret_cast<Plan*>(plan);

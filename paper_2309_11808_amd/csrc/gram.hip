@@ -35,6 +35,8 @@
 //           so FP16 and BF16 take the same path.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 #include "internal.h"
@@ -635,6 +637,59 @@ spod_status launch_csd(const Plan& p, const void* qhat, void* gram, void* ws, hi
                      (int)p.nblocks, (int)D, p.gram_split, accumulate ? 1 : 0);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SPOD_OK : hip_fail(e, "gram_combine_kernel");
+}
+
+// ---------------------------------------------------------------------------
+// spod_csd without a caller workspace: the Gram partials go to a scratch array
+// of the library's own (file scope, one copy per device, held until the
+// process ends).  Nothing in it has to start at zero: every slice writes all
+// of its upper 16 x 16 blocks and the combination reads only those.  Calls
+// that overlap on one device share the array and race.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) char scratch[SPOD_CSD_NOALLOC_MAX_BYTES];
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+static std::mutex scratch_mu;
+static void* scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+// Device address of `scratch` on device `dev` (the current device): taken
+// with hipGetSymbolAddress on the first call per device, then reused.  In host
+// code the array's name is not a device address; only this pointer is.
+static spod_status scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES)
+    return fail(SPOD_ERR_UNSUPPORTED, "device ordinal above 63");
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) return fail(SPOD_ERR_HIP, "hipGetSymbolAddress(scratch) gave NULL");
+    scratch_ptr[dev] = ptr;
+  }
+  *out = scratch_ptr[dev];
+  return SPOD_OK;
+}
+
+spod_status launch_csd_noalloc(const Plan& p, const void* qhat, void* gram, hipStream_t st) {
+  const size_t per_slice = sizeof(double2) * (size_t)p.nfreq * (size_t)p.gram_dim * (size_t)p.gram_dim;
+  if (per_slice > SPOD_CSD_NOALLOC_MAX_BYTES)
+    return fail(SPOD_ERR_UNSUPPORTED,
+                "one slice of Gram partials (nfreq * (16 ceil(nblocks/16))^2 * 16 bytes) exceeds "
+                "SPOD_CSD_NOALLOC_MAX_BYTES");
+  // the plan's slice count, reduced until the partials fit the scratch array
+  const int64_t fit = (int64_t)(SPOD_CSD_NOALLOC_MAX_BYTES / per_slice);
+  Plan c = p;
+  c.gram_split = (int)std::min<int64_t>(p.gram_split, fit);
+  void* ptr = nullptr;
+  spod_status s = scratch_address(p.device, &ptr);
+  if (s != SPOD_OK) return s;
+  return launch_csd(c, qhat, gram, ptr, st);
+}
+
+int64_t csd_noalloc_split(const Plan& p) {
+  const size_t per_slice = sizeof(double2) * (size_t)p.nfreq * (size_t)p.gram_dim * (size_t)p.gram_dim;
+  if (per_slice > SPOD_CSD_NOALLOC_MAX_BYTES) return 0;
+  return std::min<int64_t>(p.gram_split, (int64_t)(SPOD_CSD_NOALLOC_MAX_BYTES / per_slice));
 }
 
 // ---------------------------------------------------------------------------

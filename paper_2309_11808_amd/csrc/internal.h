@@ -135,6 +135,10 @@ spod_status launch_blocks_dft_general(const Plan& p, const void* q, spod_dtype d
                                       const double* mean, void* qhat, hipStream_t st);
 spod_status launch_csd(const Plan& p, const void* qhat, void* gram, void* ws, hipStream_t st,
                        bool accumulate = false);
+// spod_csd with the partials in the library's static device scratch (no
+// allocation); csd_noalloc_split: the slice count it uses (0: does not fit)
+spod_status launch_csd_noalloc(const Plan& p, const void* qhat, void* gram, hipStream_t st);
+int64_t csd_noalloc_split(const Plan& p);
 spod_status launch_eig(const Plan& p, const void* gram, double* lam, void* psi, int32_t* info,
                        void* ws, hipStream_t st);
 spod_status launch_modes(const Plan& p, const void* qhat, const double* lam, const void* psi,
