@@ -96,9 +96,31 @@ typedef enum {
 typedef enum {
   SPOD_OPT_MAX_SWEEPS = 0, /* Jacobi sweep cap (default 40; 0 forces non-convergence)   */
   SPOD_OPT_GRAM_SPLIT = 1, /* slices of M per frequency in the Gram (0 = automatic)     */
-  SPOD_OPT_FFT_TILE = 2    /* degrees of freedom per transform workgroup: 16 or 32
+  SPOD_OPT_FFT_TILE = 2,   /* degrees of freedom per transform workgroup: 16 or 32
                               (0 = automatic: 32 for nfft <= 256, else 16)            */
+  SPOD_OPT_QHAT_FORMAT = 3 /* storage of qhat: SPOD_QHAT_COMPLEX (default) or
+                              SPOD_QHAT_BFP20 (complex64 forms, power-of-two nfft)    */
 } spod_option;
+
+/* Storage of the Fourier blocks qhat between the stages.
+ *   SPOD_QHAT_COMPLEX: [K][L][M] interleaved complex (complex128 under
+ *     SPOD_PREC_FP64, complex64 otherwise).
+ *   SPOD_QHAT_BFP20: 20-bit block floating point, 5 bytes per complex value
+ *     plus one exponent per 16 degrees of freedom (about 0.63 of complex64):
+ *     row r = k * L + l occupies ceil(M / 128) superblocks of 656 bytes at byte
+ *     (r * ceil(M / 128) + b) * 656.  Superblock b covers degrees of freedom
+ *     128 b .. 128 b + 127 as 8 groups of 16: bytes 0..7 hold the groups'
+ *     int8 exponents E (bytes 8..15 are zero); group g starts at byte
+ *     16 + 80 g with the 8 pairs p (degrees of freedom 16 g + 2 p, + 1) as four
+ *     int16 h at 8 p (re, im of the first, re, im of the second), then at
+ *     64 + 2 p one uint16 whose nibble i (bits 4 i .. 4 i + 3) is n of value i.
+ *     A value is (16 h + n) 2^E (a 20-bit two's complement mantissa, rounded to
+ *     nearest, below 2^19 in magnitude); E = 127 marks a group that holds a
+ *     NaN or an infinity (decoded as NaN); degrees of freedom past M are zero.
+ *     Byte size from spod_plan_qhat_bytes.  Rounding: 2^-19 to 2^-20 of the
+ *     group's largest value (the split forms' Gram operands carry 2^-20 of the
+ *     step's largest).  spod_backward then needs qhat = NULL. */
+typedef enum { SPOD_QHAT_COMPLEX = 0, SPOD_QHAT_BFP20 = 1 } spod_qhat_format;
 
 /* Create a plan.  Follows the problem statement of Sec. 2.3: Q is M x N_t with
  * M = nspace * nvar (eq. (data-matrix)); blocks of nfft snapshots overlapping by
@@ -131,6 +153,9 @@ spod_status spod_plan_set_precision(spod_plan plan, spod_precision prec);
 
 /* Tuning / test options (see spod_option); same timing rule as the precision. */
 spod_status spod_plan_set_option(spod_plan plan, spod_option opt, int64_t value);
+
+/* Bytes of one qhat buffer of this plan in its storage format. */
+spod_status spod_plan_qhat_bytes(spod_plan plan, size_t* bytes);
 
 /* nblocks L, nfreq K and the workspace size (bytes) that every stage call of
  * this plan accepts.  Any output pointer may be NULL. */

@@ -35,6 +35,10 @@ SPOD_PREC_FP16X4 = 3
 SPOD_OPT_MAX_SWEEPS = 0
 SPOD_OPT_GRAM_SPLIT = 1
 SPOD_OPT_FFT_TILE = 2
+SPOD_OPT_QHAT_FORMAT = 3
+
+SPOD_QHAT_COMPLEX = 0
+SPOD_QHAT_BFP20 = 1
 
 SPOD_BATCH_GROUPED = 0
 SPOD_BATCH_GRAPH = 1
@@ -67,6 +71,7 @@ SIGNATURES = {
     "spod_plan_set_precision": (C.c_int, [_p, C.c_int]),
     "spod_plan_set_option": (C.c_int, [_p, C.c_int, _i64]),
     "spod_plan_query": (C.c_int, [_p, C.POINTER(_i64), C.POINTER(_i64), C.POINTER(_sz)]),
+    "spod_plan_qhat_bytes": (C.c_int, [_p, C.POINTER(_sz)]),
     "spod_blocks_fft": (C.c_int, [_p, _p, C.c_int, _p, _p, _p, _sz, _p]),
     "spod_csd": (C.c_int, [_p, _p, _p, _p, _sz, _p]),
     "spod_csd_noalloc": (C.c_int, [_p, _p, _p, C.POINTER(_i64), _p]),

@@ -28,7 +28,8 @@ class SpodFunction(torch.autograd.Function):
         lam, phi = out["lam"], out["phi"]
         ctx.plan, ctx.n_modes, ctx.bins = plan, n_modes, bins
         ctx.set_materialize_grads(False)
-        ctx.save_for_backward(q, lam, out["psi"], out["qhat"] if keep_qhat else None)
+        ctx.save_for_backward(q, lam, out["psi"],
+                              out["qhat"] if keep_qhat and not plan.packed else None)
         if bins is not None:
             idx = torch.as_tensor(np.asarray(bins, dtype=np.int64), device=q.device)
             return lam.index_select(0, idx), phi.index_select(0, idx)

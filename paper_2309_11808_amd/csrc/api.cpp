@@ -39,6 +39,12 @@ spod_status hip_fail(hipError_t e, const char* where) noexcept {
 
 bool is_complex128(const Plan& p) { return p.prec == SPOD_PREC_FP64; }
 
+size_t qhat_bytes(const Plan& p) {
+  const size_t rows = (size_t)p.nfreq * (size_t)p.nblocks;
+  if (p.qhat_packed) return rows * (size_t)pk_row_bytes(p.M);
+  return rows * (size_t)p.M * (is_complex128(p) ? 16 : 8);
+}
+
 int64_t gram_split_for(const Plan& p, int64_t target) {
   // about `target` workgroups (one per slice and frequency; 8192 measured
   // best on the 1M-DOF workload: 32 slices x 257 frequencies), but keep at
@@ -270,7 +276,10 @@ spod_status spod_plan_create(int64_t nspace, int64_t nvar, int64_t nt, int64_t n
     // twiddles e^{-2 pi i j / N}, computed in long double and rounded once
     std::vector<double2> tw(nfft);
     std::vector<float2> tw32(nfft);
-    std::vector<float> w32(nfft), sq32(M);
+    // the FP32 weights are padded with zeros to a multiple of 128 (whole
+    // superblocks of packed Fourier blocks)
+    const int64_t Mpad = (M + PK_SB_DOFS - 1) / PK_SB_DOFS * PK_SB_DOFS;
+    std::vector<float> w32(nfft), sq32(Mpad, 0.0f);
     std::vector<double> sq(M);
     for (int64_t j = 0; j < nfft; ++j) {
       long double a = 2.0L * 3.14159265358979323846264338327950288L * (long double)j / (long double)nfft;
@@ -304,7 +313,7 @@ spod_status spod_plan_create(int64_t nspace, int64_t nvar, int64_t nt, int64_t n
         {(void**)&p->d_window32, w32.data(), sizeof(float) * nfft},
         {(void**)&p->d_weights, W.data(), sizeof(double) * M},
         {(void**)&p->d_sqrtw, sq.data(), sizeof(double) * M},
-        {(void**)&p->d_sqrtw32, sq32.data(), sizeof(float) * M},
+        {(void**)&p->d_sqrtw32, sq32.data(), sizeof(float) * Mpad},
         {(void**)&p->d_tw64, tw.data(), sizeof(double2) * nfft},
         {(void**)&p->d_tw32, tw32.data(), sizeof(float2) * nfft},
         {(void**)&p->d_what, what.data(), sizeof(double2) * K},
@@ -336,6 +345,8 @@ spod_status spod_plan_set_precision(spod_plan plan, spod_precision prec) {
   if (prec != SPOD_PREC_FP64 && prec != SPOD_PREC_FP32 && prec != SPOD_PREC_BF16X4 &&
       prec != SPOD_PREC_FP16X4)
     return fail(SPOD_ERR_INVALID_ARG, "unknown precision");
+  if (prec == SPOD_PREC_FP64 && p->qhat_packed)
+    return fail(SPOD_ERR_UNSUPPORTED, "packed Fourier blocks need a complex64 precision form");
   p->prec = prec;
   derive(*p);
   return SPOD_OK;
@@ -359,10 +370,27 @@ spod_status spod_plan_set_option(spod_plan plan, spod_option opt, int64_t value)
         return fail(SPOD_ERR_INVALID_ARG, "fft tile must be 0, 16 or 32");
       p->fft_tile_opt = value;
       break;
+    case SPOD_OPT_QHAT_FORMAT:
+      if (value != SPOD_QHAT_COMPLEX && value != SPOD_QHAT_BFP20)
+        return fail(SPOD_ERR_INVALID_ARG, "qhat format must be SPOD_QHAT_COMPLEX or SPOD_QHAT_BFP20");
+      if (value == SPOD_QHAT_BFP20 && (p->prec == SPOD_PREC_FP64 || p->general))
+        return fail(SPOD_ERR_UNSUPPORTED,
+                    "packed Fourier blocks need a complex64 precision form and a power-of-two "
+                    "nfft <= 1024");
+      p->qhat_packed = value == SPOD_QHAT_BFP20;
+      break;
     default:
       return fail(SPOD_ERR_INVALID_ARG, "unknown option");
   }
   derive(*p);
+  return SPOD_OK;
+}
+
+spod_status spod_plan_qhat_bytes(spod_plan plan, size_t* bytes) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p) return fail(SPOD_ERR_INVALID_ARG, "plan is NULL");
+  if (!bytes) return fail(SPOD_ERR_INVALID_ARG, "bytes is NULL");
+  *bytes = qhat_bytes(*p);
   return SPOD_OK;
 }
 
@@ -404,6 +432,8 @@ spod_status spod_blocks_fft(spod_plan plan, const void* q, spod_dtype dtype, voi
   if (st != SPOD_OK) return st;
   if (!q || !qhat) return fail(SPOD_ERR_INVALID_ARG, "q and qhat are required");
   if (dtype != SPOD_F32 && dtype != SPOD_F64) return fail(SPOD_ERR_INVALID_ARG, "dtype");
+  if (p->qhat_packed && (uintptr_t)qhat % 16 != 0)
+    return fail(SPOD_ERR_INVALID_ARG, "packed qhat must be 16-byte aligned");
   if (!mean) {
     st = check_ws(*p, ws, ws_bytes, fft_workspace(*p));
     if (st != SPOD_OK) return st;
@@ -417,6 +447,8 @@ spod_status spod_csd(spod_plan plan, const void* qhat, void* gram, void* ws, siz
   spod_status st = enter(p);
   if (st != SPOD_OK) return st;
   if (!qhat || !gram) return fail(SPOD_ERR_INVALID_ARG, "qhat and gram are required");
+  if (p->qhat_packed && (uintptr_t)qhat % 16 != 0)
+    return fail(SPOD_ERR_INVALID_ARG, "packed qhat must be 16-byte aligned");
   st = check_ws(*p, ws, ws_bytes, csd_workspace(*p));
   if (st != SPOD_OK) return st;
   return launch_csd(*p, qhat, gram, ws, (hipStream_t)stream);
@@ -429,6 +461,8 @@ spod_status spod_csd_noalloc(spod_plan plan, const void* qhat, void* gram, int64
     spod_status st = enter(p);
     if (st != SPOD_OK) return st;
     if (!qhat || !gram) return fail(SPOD_ERR_INVALID_ARG, "qhat and gram are required");
+    if (p->qhat_packed && (uintptr_t)qhat % 16 != 0)
+      return fail(SPOD_ERR_INVALID_ARG, "packed qhat must be 16-byte aligned");
     if (slices) *slices = csd_noalloc_split(*p);
     return launch_csd_noalloc(*p, qhat, gram, (hipStream_t)stream);
   });
@@ -454,6 +488,8 @@ spod_status spod_modes(spod_plan plan, const void* qhat, const double* lam, cons
     return fail(SPOD_ERR_INVALID_ARG, "qhat, lam, psi and phi are required");
   if (n_modes < 1 || n_modes > p->nblocks)
     return fail(SPOD_ERR_INVALID_ARG, "n_modes must be in [1, nblocks]");
+  if (p->qhat_packed && (uintptr_t)qhat % 16 != 0)
+    return fail(SPOD_ERR_INVALID_ARG, "packed qhat must be 16-byte aligned");
   (void)ws_bytes;
   return launch_modes(*p, qhat, lam, psi, (int)n_modes, phi, n_valid, ws, (hipStream_t)stream);
 }
@@ -487,11 +523,17 @@ spod_status spod_backward(spod_plan plan, const void* q, spod_dtype dtype, const
     if (p->step != p->nfft && p->step != p->nfft / 2 && p->step != p->nfft / 4)
       return fail(SPOD_ERR_UNSUPPORTED, "backward needs a hop of nfft/4, nfft/2 or nfft");
     if (p->nblocks > 64) return fail(SPOD_ERR_UNSUPPORTED, "nblocks > 64");
+    if (p->qhat_packed && qhat)
+      return fail(SPOD_ERR_UNSUPPORTED,
+                  "packed Fourier blocks: pass qhat = NULL (the blocks are recomputed)");
     spod_status st = enter(p);
     if (st != SPOD_OK) return st;
     st = check_ws(*p, ws, ws_bytes, backward_workspace(*p));
     if (st != SPOD_OK) return st;
-    return launch_backward(*p, q, dtype, qhat, lam, psi, g_lam, g_phi, g_phi ? (int)n_modes : 0,
+    // the adjoint works on complex blocks (g_qhat), whatever the plan stores
+    Plan c = *p;
+    c.qhat_packed = false;
+    return launch_backward(c, q, dtype, qhat, lam, psi, g_lam, g_phi, g_phi ? (int)n_modes : 0,
                            bins, bins ? (int)n_bins : (int)p->nfreq, g_qhat, g_q, ws,
                            (hipStream_t)stream);
   });

@@ -81,7 +81,7 @@ __device__ __forceinline__ double group_sum(double x) {
 // (mu - mu0) What).  mu0 keeps the transform's input of the order of the
 // fluctuations, so the FP32 transform does not lose the precision a large
 // mean would cost.  Not FUSED: mean[] was computed by mean_kernel.
-template <int NF, typename TC, typename TIN, int NPAIR, int SHIFT, bool FUSED>
+template <int NF, typename TC, typename TIN, int NPAIR, int SHIFT, bool FUSED, bool PACK = false>
 __device__ __forceinline__ void blocks_fft_body(
     const TIN* __restrict__ q, double* __restrict__ mean, const double* __restrict__ window,
     const cpx_t<TC>* __restrict__ tw, cpx_t<TC>* __restrict__ qhat, int64_t M, int64_t ldq,
@@ -212,26 +212,58 @@ __device__ __forceinline__ void blocks_fft_body(
     // output row s holds frequency k = s (or ksel[s] for a bin selection).
     // One thread per (row, pair): X_a = (A + conj B) / 2 and
     // X_b = (A - conj B) / (2i) come from the same two LDS reads, and the two
-    // adjacent degrees of freedom are written with one 16-byte streaming store.
-    C* out = qhat + (int64_t)l * ldq;
+    // adjacent degrees of freedom are written with one 16-byte streaming store
+    // (or, packed, as their 20-bit mantissas: 8 consecutive threads form a
+    // group of 16 degrees of freedom and share its exponent).
     const TC sc = (TC)0.5 * kappa;
-    for (int idx = tid; idx < nsel * NPAIR; idx += NTH) {
-      const int f2 = idx % NPAIR;
-      const int s = idx / NPAIR;
-      const int k = sel ? ksel[s] : s;
-      const C* row = lds + f2 * LDP;
-      const C A = row[pad8(k)];
-      const C Bc = row[pad8((NF - k) & (NF - 1))];
-      const C Xa = C{(A.x + Bc.x) * sc, (A.y - Bc.y) * sc};
-      const TC dx = A.x - Bc.x, dy = A.y + Bc.y;
-      const C Xb = C{dy * sc, -(dx * sc)};
-      const int64_t m = m0 + 2 * f2;
-      C* o = out + (int64_t)s * L * ldq + m;
-      if (pair_ok && m + 1 < M) {
-        store_pair(o, Xa, Xb);
-      } else {
-        if (m < M) o[0] = Xa;
-        if (m + 1 < M) o[1] = Xb;
+    if constexpr (PACK) {
+      // one thread per quarter group (two pairs, 4 degrees of freedom); the
+      // 4 quarters of a group are an aligned quad of lanes.  Degrees of
+      // freedom past M are stored as zeros (the separation of a pair with one
+      // real row leaves rounding noise in the other).
+      constexpr int NQ = NPAIR / 2;
+      for (int idx = tid; idx < nsel * NQ; idx += NTH) {
+        const int fq = idx % NQ;
+        const int s = idx / NQ;
+        const int k = sel ? ksel[s] : s;
+        float v[8];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const C* row = lds + (2 * fq + h) * LDP;
+          const C A = row[pad8(k)];
+          const C Bc = row[pad8((NF - k) & (NF - 1))];
+          const int64_t m = m0 + 4 * fq + 2 * h;
+          const bool ka = m < M, kb = m + 1 < M;
+          v[4 * h] = ka ? (float)((A.x + Bc.x) * sc) : 0.0f;
+          v[4 * h + 1] = ka ? (float)((A.y - Bc.y) * sc) : 0.0f;
+          v[4 * h + 2] = kb ? (float)((A.y + Bc.y) * sc) : 0.0f;
+          v[4 * h + 3] = kb ? (float)(-((A.x - Bc.x) * sc)) : 0.0f;
+        }
+        // ldq is the packed row length in bytes; tiles cover whole superblocks
+        const int64_t m = m0 + 4 * fq;
+        char* sb = reinterpret_cast<char*>(qhat) + ((int64_t)s * L + l) * ldq +
+                   (m / PK_SB_DOFS) * PK_SB_BYTES;
+        pk_store_quarter(sb, (int)((m % PK_SB_DOFS) >> 4), (int)((m & 15) >> 2), v);
+      }
+    } else {
+      for (int idx = tid; idx < nsel * NPAIR; idx += NTH) {
+        const int f2 = idx % NPAIR;
+        const int s = idx / NPAIR;
+        const int k = sel ? ksel[s] : s;
+        const C* row = lds + f2 * LDP;
+        const C A = row[pad8(k)];
+        const C Bc = row[pad8((NF - k) & (NF - 1))];
+        const C Xa = C{(A.x + Bc.x) * sc, (A.y - Bc.y) * sc};
+        const TC dx = A.x - Bc.x, dy = A.y + Bc.y;
+        const C Xb = C{dy * sc, -(dx * sc)};
+        const int64_t m = m0 + 2 * f2;
+        C* o = qhat + (int64_t)l * ldq + (int64_t)s * L * ldq + m;
+        if (pair_ok && m + 1 < M) {
+          store_pair(o, Xa, Xb);
+        } else {
+          if (m < M) o[0] = Xa;
+          if (m + 1 < M) o[1] = Xb;
+        }
       }
     }
     __syncthreads();
@@ -254,27 +286,66 @@ __device__ __forceinline__ void blocks_fft_body(
       corr[2 * f + 1] = db * (double)kappa;
     }
     __syncthreads();
-    for (int idx = tid; idx < mb.n * L * T; idx += NTH) {
-      const int d = idx % T;
-      const int l = (idx / T) % L;
-      const int s = idx / (T * L);
-      const int64_t m = m0 + d;
-      if (m >= M) continue;
-      C* o = qhat + ((int64_t)mb.k[s] * L + l) * ldq + m;
-      const C raw = *o;
-      const double c = corr[d];
-      *o = C{(TC)((double)raw.x - c * mb.wr[s]), (TC)((double)raw.y - c * mb.wi[s])};
+    if constexpr (PACK) {
+      // decode, correct and re-encode the groups of the mean bins' rows (the
+      // group exponent may change); one thread per quarter group as in the
+      // stores
+      constexpr int NQ = NPAIR / 2;
+      for (int idx = tid; idx < mb.n * L * NQ; idx += NTH) {
+        const int fq = idx % NQ;
+        const int l = (idx / NQ) % L;
+        const int s = idx / (NQ * L);
+        const int64_t m = m0 + 4 * fq;
+        char* sb = reinterpret_cast<char*>(qhat) + ((int64_t)mb.k[s] * L + l) * ldq +
+                   (m / PK_SB_DOFS) * PK_SB_BYTES;
+        const int g = (int)((m % PK_SB_DOFS) >> 4), c = (int)((m & 15) >> 2);
+        const char* grp = sb + PK_HDR_BYTES + PK_GROUP_BYTES * g;
+        typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+        const v4u hw = *reinterpret_cast<const v4u*>(grp + 16 * c);
+        const uint32_t nib = *reinterpret_cast<const uint32_t*>(grp + 64 + 4 * c);
+        const float scale = pk_scale((int)(signed char)sb[g]);
+        float v[8];
+        pk_decode4(hw[0], hw[1], nib & 0xffffu, scale, v);
+        pk_decode4(hw[2], hw[3], nib >> 16, scale, v + 4);
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+          const double cd = corr[4 * fq + d];
+          const bool live = m + d < M;
+          v[2 * d] = live ? (float)((double)v[2 * d] - cd * mb.wr[s]) : 0.0f;
+          v[2 * d + 1] = live ? (float)((double)v[2 * d + 1] - cd * mb.wi[s]) : 0.0f;
+        }
+        // every lane of the group has read its quarter (and the exponent)
+        // before any lane overwrites them (the quad runs in lockstep)
+        __builtin_amdgcn_wave_barrier();
+        pk_store_quarter(sb, g, c, v);
+      }
+    } else {
+      for (int idx = tid; idx < mb.n * L * T; idx += NTH) {
+        const int d = idx % T;
+        const int l = (idx / T) % L;
+        const int s = idx / (T * L);
+        const int64_t m = m0 + d;
+        if (m >= M) continue;
+        C* o = qhat + ((int64_t)mb.k[s] * L + l) * ldq + m;
+        const C raw = *o;
+        const double c = corr[d];
+        *o = C{(TC)((double)raw.x - c * mb.wr[s]), (TC)((double)raw.y - c * mb.wi[s])};
+      }
     }
   }
 }
 
-template <int NF, typename TC, typename TIN, int NPAIR, int SHIFT, bool FUSED>
+// PACK: qhat in the packed 20-bit layout (ldq = bytes of a packed row).
+template <int NF, typename TC, typename TIN, int NPAIR, int SHIFT, bool FUSED, bool PACK>
 __global__ __launch_bounds__(NPAIR*(NF / 8)) void blocks_fft_kernel(
     const TIN* __restrict__ q, double* __restrict__ mean, const double* __restrict__ window,
-    const cpx_t<TC>* __restrict__ tw, cpx_t<TC>* __restrict__ qhat, int64_t M, int64_t nt,
-    int step, int L, int bpw, TC kappa, MeanBins mb, const int* __restrict__ sel, int nsel) {
-  blocks_fft_body<NF, TC, TIN, NPAIR, SHIFT, FUSED>(q, mean, window, tw, qhat, M, M, nt, step, L, bpw,
-                                                    kappa, mb, sel, nsel, blockIdx.x, blockIdx.y);
+    const cpx_t<TC>* __restrict__ tw, cpx_t<TC>* __restrict__ qhat, int64_t M, int64_t ldq,
+    int64_t nt, int step, int L, int bpw, TC kappa, MeanBins mb, const int* __restrict__ sel,
+    int nsel) {
+  const int64_t tile = PACK ? xcd_tile(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+  blocks_fft_body<NF, TC, TIN, NPAIR, SHIFT, FUSED, PACK>(q, mean, window, tw, qhat, M, ldq, nt, step,
+                                                          L, bpw, kappa, mb, sel, nsel, tile,
+                                                          blockIdx.y);
 }
 
 // Grouped launch over the problems of a batch that share N_f, precision, input
@@ -299,10 +370,20 @@ static void launch_fft_kernel(const Plan& p, dim3 grid, const TIN* q, double* me
                               hipStream_t st) {
   using C = cpx_t<TC>;
   constexpr int P = NF / 8;
-  hipLaunchKernelGGL((blocks_fft_kernel<NF, TC, TIN, NPAIR, SHIFT, FUSED>), grid, dim3(NPAIR * P), 0,
-                     st, q, mean, p.d_window, static_cast<const C*>(tw), static_cast<C*>(qhat),
-                     (int64_t)p.M, (int64_t)p.nt, (int)p.step, (int)p.nblocks, bpw, (TC)p.kappa, mb,
-                     fs.d_sel, fs.d_sel ? fs.nsel : (int)p.nfreq);
+  const int nsel = fs.d_sel ? fs.nsel : (int)p.nfreq;
+  if constexpr (sizeof(TC) == 4) {
+    if (p.qhat_packed) {
+      hipLaunchKernelGGL((blocks_fft_kernel<NF, TC, TIN, NPAIR, SHIFT, FUSED, true>), grid,
+                         dim3(NPAIR * P), 0, st, q, mean, p.d_window, static_cast<const C*>(tw),
+                         static_cast<C*>(qhat), (int64_t)p.M, pk_row_bytes(p.M), (int64_t)p.nt,
+                         (int)p.step, (int)p.nblocks, bpw, (TC)p.kappa, mb, fs.d_sel, nsel);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((blocks_fft_kernel<NF, TC, TIN, NPAIR, SHIFT, FUSED, false>), grid,
+                     dim3(NPAIR * P), 0, st, q, mean, p.d_window, static_cast<const C*>(tw),
+                     static_cast<C*>(qhat), (int64_t)p.M, (int64_t)p.M, (int64_t)p.nt, (int)p.step,
+                     (int)p.nblocks, bpw, (TC)p.kappa, mb, fs.d_sel, nsel);
 }
 
 template <int NF, typename TC, typename TIN, int BASE>
@@ -310,7 +391,9 @@ static spod_status launch_fft_shape(const Plan& p, const TIN* q, double* mean, v
                                     hipStream_t st, bool fused, const FftSel& fs) {
   using S = FftShape<NF, BASE>;
   constexpr int P = S::P, NPAIR = S::NPAIR, T = S::T;
-  const int64_t ntiles = (p.M + T - 1) / T;
+  static_assert(PK_SB_DOFS % T == 0, "tiles must tile the packed superblocks");
+  // packed blocks: the tiles cover whole superblocks (their padding is written as zeros)
+  const int64_t ntiles = p.qhat_packed ? pk_superblocks(p.M) * (PK_SB_DOFS / T) : (p.M + T - 1) / T;
   if (ntiles > 0x7fffffff) return fail(SPOD_ERR_UNSUPPORTED, "too many tiles");
   const int L = (int)p.nblocks;
   const void* tw = sizeof(TC) == 4 ? (const void*)p.d_tw32 : (const void*)p.d_tw64;
@@ -445,6 +528,8 @@ spod_status launch_blocks_fft(const Plan& p, const void* q, spod_dtype dtype, vo
                               double* mean, void* ws, hipStream_t st, const FftSel& fs) {
   // the mean goes to the caller's buffer, or to the start of the workspace
   double* mu = mean ? mean : static_cast<double*>(ws);
+  if (p.qhat_packed && (p.general || fs.d_sel || is_complex128(p)))
+    return fail(SPOD_ERR_UNSUPPORTED, "packed Fourier blocks: complex64, power-of-two nfft, all bins");
   if (p.general) {
     if (fs.d_sel) return fail(SPOD_ERR_UNSUPPORTED, "frequency selection needs a power-of-two nfft");
     const int64_t mgrid = (p.M + 3) / 4;

@@ -76,11 +76,29 @@ template <> struct GramCfg<G_FP16X4> {
   using ACC = v4f;
 };
 
-// Largest value over the 64 lanes of a wavefront.
-__device__ __forceinline__ float wave_max(float x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x = fmaxf(x, __shfl_xor(x, o, 64));
-  return x;
+// ex with max_lanes x < 2^ex (x >= 0 in every lane; 0 when all are zero; a
+// NaN or an infinity gives 129, which keeps them non-finite downstream).  The
+// maximum is taken on the bit patterns, which order like non-negative floats:
+// within each row of 16 lanes by DPP (quad swaps, half-row and row mirrors),
+// then across the 4 rows on the scalar unit.
+__device__ __forceinline__ int wave_max_exp(float x) {
+  uint32_t u = __float_as_uint(x), v;
+  v = (uint32_t)__builtin_amdgcn_mov_dpp((int)u, 0xb1, 0xf, 0xf, false);   // quad_perm [1,0,3,2]
+  u = u > v ? u : v;
+  v = (uint32_t)__builtin_amdgcn_mov_dpp((int)u, 0x4e, 0xf, 0xf, false);   // quad_perm [2,3,0,1]
+  u = u > v ? u : v;
+  v = (uint32_t)__builtin_amdgcn_mov_dpp((int)u, 0x141, 0xf, 0xf, false);  // row_half_mirror
+  u = u > v ? u : v;
+  v = (uint32_t)__builtin_amdgcn_mov_dpp((int)u, 0x140, 0xf, 0xf, false);  // row_mirror
+  u = u > v ? u : v;
+  uint32_t m = (uint32_t)__builtin_amdgcn_readlane((int)u, 0);
+  uint32_t r = (uint32_t)__builtin_amdgcn_readlane((int)u, 16);
+  m = m > r ? m : r;
+  r = (uint32_t)__builtin_amdgcn_readlane((int)u, 32);
+  m = m > r ? m : r;
+  r = (uint32_t)__builtin_amdgcn_readlane((int)u, 48);
+  m = m > r ? m : r;
+  return m == 0 ? 0 : (int)(m >> 23) - 126;
 }
 
 // y 2^-E = h + l (see the header): h exact, l rounded to nearest even.
@@ -178,7 +196,10 @@ struct GramStage {
   static constexpr int NI = (16 * NT + 1 + 3) / 4;  // load instructions per wave per chunk
 };
 
-template <int NT>
+// CHUNKB: bytes of one row per chunk (1024, or one 656-byte packed
+// superblock: lanes past it re-read the superblock's first 16 bytes into the
+// unused end of the row's slot, so no load leaves the row).
+template <int NT, int CHUNKB = 1024>
 __device__ __forceinline__ void stage_issue(char* stage, const char* __restrict__ qrows, int64_t rowb,
                                             const char* __restrict__ wrow, int L, int wave, int lane) {
   using GS = GramStage<NT>;
@@ -199,7 +220,7 @@ __device__ __forceinline__ void stage_issue(char* stage, const char* __restrict_
       dst = 16 * NT + 1;
     }
     // the weight row holds 512 bytes: lanes 32..63 re-read the first half
-    const int off = (slot >= 16 * NT) ? 16 * (lane & 31) : 16 * lane;
+    const int off = (slot >= 16 * NT) ? 16 * (lane & 31) : (16 * lane < CHUNKB ? 16 * lane : 0);
     __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)(src + off),
                                      (void __attribute__((address_space(3)))*)(stage + dst * GS::RSB),
                                      16, 0, 0);
@@ -212,7 +233,10 @@ __device__ __forceinline__ void stage_issue(char* stage, const char* __restrict_
 // wave runs its group's instantiation over the chunk that all four waves
 // loaded, so the rows are read from HBM once per workgroup.  Every
 // instantiation executes the same barriers, in the same order.
-template <int MODE, int NT, int G, int WPG>
+// PK: qhat in the packed 20-bit layout (one chunk = one superblock of 128
+// degrees of freedom per row; ldq = bytes of a packed row; the rows are padded
+// with zeros to whole superblocks and the weights to a multiple of 128).
+template <int MODE, int NT, int G, int WPG, bool PK = false>
 __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __restrict__ qhat,
                                           const typename GramCfg<MODE>::T* __restrict__ sqrtw,
                                           double* __restrict__ part, int64_t M,
@@ -242,11 +266,12 @@ __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __res
   const int lane = tid & 63;
   const int r16 = lane & 15;
   const int g4 = lane >> 4;
-  const C* qk = qhat + (int64_t)k * L * ldq;
+  static_assert(!PK || (MODE != G_F64 && CD == PK_SB_DOFS), "packed blocks are complex64 superblocks");
+  const C* qk = PK ? nullptr : qhat + (int64_t)k * L * ldq;
 
   // full chunks are split over the S slices; the ragged remainder (or all of
   // it, when 16-byte loads are not possible) goes to the last slice
-  const int64_t nchunk = vec ? M / CD : 0;
+  const int64_t nchunk = PK ? pk_superblocks(M) : (vec ? M / CD : 0);
   const int64_t c0 = nchunk * s / S, c1 = nchunk * (s + 1) / S;
 
   constexpr int NACC = MODE == G_F64 ? NPG : 1;
@@ -305,24 +330,25 @@ __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __res
       using FR = typename std::conditional<MODE == G_BF16X4, v8bf, v8h>::type;
       using T16 = typename std::conditional<MODE == G_BF16X4, __bf16, _Float16>::type;
       constexpr int H = MODE == G_BF16X4 ? 8 : 9;     // bits of the integer part h
+      // Rows past L hold a copy of row L - 1 (the staging re-reads it): they
+      // only reach rows and columns of the partial Gram past L, which the
+      // combination never reads, and they leave the step's maximum unchanged,
+      // so they need no masking here.
       float ya[NT][8], yb[NT][8];
       float mx = 0.0f;
 #pragma unroll
       for (int a = 0; a < NT; ++a) {
         if (!((NEED >> a) & 1u)) continue;
-        const bool live = 16 * a + r16 < L;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          ya[a][e] = live ? cur.x[a][e].x * cur.w[e] : 0.0f;
-          yb[a][e] = live ? cur.x[a][e].y * cur.w[e] : 0.0f;
+          ya[a][e] = cur.x[a][e].x * cur.w[e];
+          yb[a][e] = cur.x[a][e].y * cur.w[e];
           mx = fmaxf(mx, fmaxf(fabsf(ya[a][e]), fabsf(yb[a][e])));
         }
       }
       // one exponent for the whole step of this wave: mx < 2^ex, so
       // |y| 2^-E < 2^H with E = ex - H (uniform across the wavefront)
-      int ex = 0;
-      (void)frexpf(wave_max(mx), &ex);
-      const int E = __builtin_amdgcn_readfirstlane(ex) - H;
+      const int E = wave_max_exp(mx) - H;
       const double unit = ldexp(1.0, 2 * E);            // value of one integer product
       FR ah[NT], al[NT], bh[NT], bl[NT];
 #pragma unroll
@@ -373,17 +399,20 @@ __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __res
     }
   };
 
-  const char* qb = reinterpret_cast<const char*>(qk);
+  constexpr int CHUNKB = PK ? PK_SB_BYTES : 1024;
+  const char* qb = PK ? reinterpret_cast<const char*>(qhat) + (int64_t)k * L * ldq
+                      : reinterpret_cast<const char*>(qk);
   const char* wb = reinterpret_cast<const char*>(sqrtw);
-  const int64_t rowb = ldq * (int64_t)sizeof(C);
-  if (c0 < c1) stage_issue<NT>(lds, qb + c0 * 1024, rowb, wb + c0 * CD * (int64_t)sizeof(T), L, wave, lane);
+  const int64_t rowb = PK ? ldq : ldq * (int64_t)sizeof(C);
+  if (c0 < c1)
+    stage_issue<NT, CHUNKB>(lds, qb + c0 * CHUNKB, rowb, wb + c0 * CD * (int64_t)sizeof(T), L, wave, lane);
 #pragma unroll 1
   for (int64_t c = c0; c < c1; ++c) {
     char* cur = lds + ((c - c0) & 1) * GS::BYTES;
     char* nxt = lds + (((c - c0) & 1) ^ 1) * GS::BYTES;
     // prefetch the next chunk (the last one re-reads itself into the free stage)
     const int64_t cn = c + 1 < c1 ? c + 1 : c;
-    stage_issue<NT>(nxt, qb + cn * 1024, rowb, wb + cn * CD * (int64_t)sizeof(T), L, wave, lane);
+    stage_issue<NT, CHUNKB>(nxt, qb + cn * CHUNKB, rowb, wb + cn * CD * (int64_t)sizeof(T), L, wave, lane);
     // wait for this wave's loads of chunk c (the NI of chunk c+1 stay in
     // flight), then for everybody's.  A bare s_barrier: __syncthreads() would
     // add a release fence that drains the prefetch as well.
@@ -397,6 +426,40 @@ __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __res
 #pragma unroll
       for (int a = 0; a < NT; ++a) {
         if (!((NEED >> a) & 1u)) continue;
+        if constexpr (PK) {
+          // decode this lane's DPL degrees of freedom (DPL / 2 pairs of one
+          // group): int16 high parts, low nibbles, the group's exponent
+          typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+          typedef unsigned int v2u __attribute__((ext_vector_type(2)));
+          const char* rowp = cur + (16 * a + r16) * GS::RSB;
+          const int g = base >> 4, p0 = (base & 15) >> 1;
+          const float scale = pk_scale((int)(signed char)rowp[g]);
+          const char* grp = rowp + PK_HDR_BYTES + PK_GROUP_BYTES * g;
+          uint32_t hw[DPL], nw[DPL / 4 > 0 ? DPL / 4 : 1];
+#pragma unroll
+          for (int v = 0; v < DPL / 4; ++v) {
+            const v4u h = *reinterpret_cast<const v4u*>(grp + 8 * p0 + 16 * v);
+            hw[4 * v] = h[0];
+            hw[4 * v + 1] = h[1];
+            hw[4 * v + 2] = h[2];
+            hw[4 * v + 3] = h[3];
+          }
+          if constexpr (DPL == 8) {
+            const v2u n = *reinterpret_cast<const v2u*>(grp + 64 + 2 * p0);
+            nw[0] = n[0];
+            nw[1] = n[1];
+          } else {
+            nw[0] = *reinterpret_cast<const uint32_t*>(grp + 64 + 2 * p0);
+          }
+#pragma unroll
+          for (int i = 0; i < DPL / 2; ++i) {
+            float v[4];
+            pk_decode4(hw[2 * i], hw[2 * i + 1], (nw[i >> 1] >> (16 * (i & 1))) & 0xffffu, scale, v);
+            r.x[a][2 * i] = C{v[0], v[1]};
+            r.x[a][2 * i + 1] = C{v[2], v[3]};
+          }
+          continue;
+        }
         const v4f* src = reinterpret_cast<const v4f*>(cur + (16 * a + r16) * GS::RSB + base * (int)sizeof(C));
         constexpr int NV = (int)(sizeof(C) * DPL / 16);
 #pragma unroll
@@ -427,8 +490,9 @@ __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __res
     __builtin_amdgcn_sched_barrier(0);
   }
   // remaining degrees of freedom (ragged end, or everything when rows are not
-  // 16-byte aligned), split over the S slices like the chunks
-  {
+  // 16-byte aligned), split over the S slices like the chunks; packed rows are
+  // whole superblocks
+  if constexpr (!PK) {
     const int64_t m_rem = nchunk * CD;
     const int64_t ng = (M - m_rem + GDOF - 1) / GDOF;
     const int64_t g0 = ng * s / S, g1 = ng * (s + 1) / S;
@@ -493,7 +557,7 @@ __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __res
 
 // Work unit = (slice s, frequency k), one workgroup each; the pair groups of
 // a unit are spread over the workgroup's waves (see gram_body).
-template <int MODE, int NT>
+template <int MODE, int NT, bool PK = false>
 __device__ __forceinline__ void gram_unit(const typename GramCfg<MODE>::C* __restrict__ qhat,
                                           const typename GramCfg<MODE>::T* __restrict__ sqrtw,
                                           double* __restrict__ part,
@@ -509,23 +573,23 @@ __device__ __forceinline__ void gram_unit(const typename GramCfg<MODE>::C* __res
   double* red = reinterpret_cast<double*>(lds);                      // reused after the loop
   const int g = (int)(threadIdx.x >> 6) / WPG;
   switch (g) {
-    case 0: gram_body<MODE, NT, 0, WPG>(qhat, sqrtw, part, M, ldq, L, S, vec, red, lds, s, k); break;
-    case 1: if constexpr (NG > 1) gram_body<MODE, NT, 1, WPG>(qhat, sqrtw, part, M, ldq, L, S, vec, red, lds, s, k); break;
-    case 2: if constexpr (NG > 2) gram_body<MODE, NT, 2, WPG>(qhat, sqrtw, part, M, ldq, L, S, vec, red, lds, s, k); break;
-    case 3: if constexpr (NG > 3) gram_body<MODE, NT, 3, WPG>(qhat, sqrtw, part, M, ldq, L, S, vec, red, lds, s, k); break;
+    case 0: gram_body<MODE, NT, 0, WPG, PK>(qhat, sqrtw, part, M, ldq, L, S, vec, red, lds, s, k); break;
+    case 1: if constexpr (NG > 1) gram_body<MODE, NT, 1, WPG, PK>(qhat, sqrtw, part, M, ldq, L, S, vec, red, lds, s, k); break;
+    case 2: if constexpr (NG > 2) gram_body<MODE, NT, 2, WPG, PK>(qhat, sqrtw, part, M, ldq, L, S, vec, red, lds, s, k); break;
+    case 3: if constexpr (NG > 3) gram_body<MODE, NT, 3, WPG, PK>(qhat, sqrtw, part, M, ldq, L, S, vec, red, lds, s, k); break;
     default: break;
   }
 }
 
-template <int MODE, int NT>
+template <int MODE, int NT, bool PK>
 __global__ __launch_bounds__(256, 2) void gram_kernel(const typename GramCfg<MODE>::C* __restrict__ qhat,
                                                       const void* __restrict__ sqrtw_v,
-                                                      double* __restrict__ part, int64_t M, int L,
-                                                      int S, int K, int vec) {
+                                                      double* __restrict__ part, int64_t M,
+                                                      int64_t ldq, int L, int S, int K, int vec) {
   using T = typename GramCfg<MODE>::T;
   extern __shared__ __attribute__((aligned(16))) char gram_lds[];   // 2 stages
-  gram_unit<MODE, NT>(qhat, static_cast<const T*>(sqrtw_v), part, M, M, L, S, K, vec != 0,
-                      blockIdx.x, gram_lds);
+  gram_unit<MODE, NT, PK>(qhat, static_cast<const T*>(sqrtw_v), part, M, ldq, L, S, K, vec != 0,
+                          blockIdx.x, gram_lds);
 }
 
 // Grouped launch over a batch: workgroup b -> item, then the item's local
@@ -589,19 +653,27 @@ template <int MODE, int NTI>
 static void launch_gram_nti(const Plan& p, const void* qhat, const void* sqrtw, double* part,
                             hipStream_t st) {
   using C = typename GramCfg<MODE>::C;
-  constexpr int NP = NTI * (NTI + 1) / 2;
-  (void)NP;
   dim3 grid((unsigned)((int64_t)p.gram_split * p.nfreq));
+  const size_t lds = 2 * (size_t)GramStage<NTI>::BYTES;
+  if constexpr (MODE != G_F64) {
+    if (p.qhat_packed) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gram_kernel<MODE, NTI, true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      hipLaunchKernelGGL((gram_kernel<MODE, NTI, true>), grid, dim3(256), lds, st,
+                         static_cast<const C*>(qhat), sqrtw, part, (int64_t)p.M, pk_row_bytes(p.M),
+                         (int)p.nblocks, p.gram_split, (int)p.nfreq, 1);
+      return;
+    }
+  }
   // 16-byte loads need 16-byte aligned rows (an aligned base and, for
   // complex64, an even M) and 16-byte aligned weights
   const bool vec = ((uintptr_t)qhat % 16 == 0) && (sizeof(C) == 16 || p.M % 2 == 0) &&
                    ((uintptr_t)sqrtw % 16 == 0);
-  const size_t lds = 2 * (size_t)GramStage<NTI>::BYTES;
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gram_kernel<MODE, NTI>),
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gram_kernel<MODE, NTI, false>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((gram_kernel<MODE, NTI>), grid, dim3(256), lds, st,
-                     static_cast<const C*>(qhat), sqrtw, part, (int64_t)p.M, (int)p.nblocks,
-                     p.gram_split, (int)p.nfreq, (int)vec);
+  hipLaunchKernelGGL((gram_kernel<MODE, NTI, false>), grid, dim3(256), lds, st,
+                     static_cast<const C*>(qhat), sqrtw, part, (int64_t)p.M, (int64_t)p.M,
+                     (int)p.nblocks, p.gram_split, (int)p.nfreq, (int)vec);
 }
 
 template <int MODE>

@@ -63,6 +63,7 @@ struct Plan {
   int max_sweeps = 40;
   int64_t gram_split_opt = 0;
   int64_t fft_tile_opt = 0;
+  bool qhat_packed = false;   // SPOD_QHAT_BFP20: qhat in the packed layout below
 
   // derived launch shapes (fixed when frozen)
   int gram_split = 1;       // slices of M per frequency
@@ -85,6 +86,7 @@ struct Plan {
 };
 
 bool is_complex128(const Plan& p);
+size_t qhat_bytes(const Plan& p);   // bytes of one plan's qhat in its format
 int64_t gram_split_for(const Plan& p, int64_t target);   // slices for ~target workgroups
 void plan_set_gram_split(Plan& p, int64_t s);            // internal: owner of the plan only
 size_t workspace_bytes(const Plan& p);
@@ -267,6 +269,102 @@ spod_status launch_eig_group(const EigItem* d_items, int n, int wgs, int max_swe
                              hipStream_t st);   // lmax: the group's largest L (16, 32 or 64)
 spod_status launch_modes_group(bool c128, const ModesItem* d_items, int n, int wgs,
                                size_t lds_bytes, hipStream_t st);
+
+// --------------------------------------------------------------------------
+// packed Fourier blocks (SPOD_QHAT_BFP20): every row (k, l) of M degrees of
+// freedom is stored as ceil(M / 128) superblocks of 656 bytes.  A superblock
+// holds 8 groups of 16 degrees of freedom: bytes 0..7 are the groups' int8
+// exponents E (8..15 are zero), then group g at byte 16 + 80 g: the 8 pairs p
+// (degrees of freedom 16 g + 2 p, + 1) as four int16 h at 8 p (re a, im a,
+// re b, im b), then at 64 + 2 p one uint16 of the four low nibbles n (value i
+// in bits 4 i .. 4 i + 3).  A value is (16 h + n) 2^E: a 20-bit two's
+// complement mantissa with the group's shared exponent, |16 h + n| < 2^19.
+// E = 127 marks a group with a non-finite value (decoded as NaN); an all-zero
+// group has E = -128.  Degrees of freedom past M are zero.
+// --------------------------------------------------------------------------
+constexpr int PK_SB_DOFS = 128;
+constexpr int PK_SB_BYTES = 656;
+constexpr int PK_HDR_BYTES = 16;
+constexpr int PK_GROUP_BYTES = 80;
+constexpr int PK_EXP_NONFINITE = 127;
+constexpr int PK_MANT_BITS = 20;
+__host__ __device__ inline int64_t pk_superblocks(int64_t M) { return (M + PK_SB_DOFS - 1) / PK_SB_DOFS; }
+__host__ __device__ inline int64_t pk_row_bytes(int64_t M) { return pk_superblocks(M) * PK_SB_BYTES; }
+
+// Scale of a group's mantissas: 2^E, or NaN for the non-finite marker.
+__device__ __forceinline__ float pk_scale(int e) {
+  return e == PK_EXP_NONFINITE ? __builtin_nanf("") : ldexpf(1.0f, e);
+}
+
+// Decode four values from their int16 high parts (two packed per word) and
+// the uint16 of low nibbles.
+__device__ __forceinline__ void pk_decode4(uint32_t h01, uint32_t h23, uint32_t nib, float scale,
+                                           float* v) {
+  const int32_t h[4] = {(int32_t)(int16_t)(h01 & 0xffffu), (int32_t)h01 >> 16,
+                        (int32_t)(int16_t)(h23 & 0xffffu), (int32_t)h23 >> 16};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int32_t mant = h[i] * 16 + (int32_t)((nib >> (4 * i)) & 15u);
+    v[i] = (float)mant * scale;
+  }
+}
+
+// Largest of x over the 4 lanes of an aligned quad (DPP quad swaps).
+__device__ __forceinline__ uint32_t max4_u32(uint32_t x) {
+  uint32_t y = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4e, 0xf, 0xf, false);   // quad_perm [2,3,0,1]
+  x = x > y ? x : y;
+  y = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xb1, 0xf, 0xf, false);            // quad_perm [1,0,3,2]
+  return x > y ? x : y;
+}
+
+// Encode the eight values v (re, im of degrees of freedom 16 g + 4 c .. + 3)
+// of quarter c of group g of the superblock at `sb`: two pairs, one 16-byte
+// store of their int16 high parts and one 4-byte store of their nibbles.  The
+// 4 lanes of a group (an aligned quad, all active) call it together and share
+// the group's exponent.  The largest magnitude is taken on the bit patterns
+// (|v| as unsigned integers order like the values, and infinities and NaNs
+// lie above every finite value).  Plain (cached) stores: the 81 bytes of a
+// group share cache lines with the neighbouring tiles, which the caller keeps
+// on the same XCD.
+__device__ __forceinline__ void pk_store_quarter(char* sb, int g, int c, const float* v) {
+  uint32_t mb = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const uint32_t u = __float_as_uint(v[i]) & 0x7fffffffu;
+    mb = mb > u ? mb : u;
+  }
+  mb = max4_u32(mb);
+  const bool bad = mb >= 0x7f800000u;
+  // mx < 2^ex with ex = biased exponent - 126; e = ex - 19 (|v| 2^-e < 2^19)
+  int e = (int)(mb >> 23) - 145;
+  e = e < -128 ? -128 : e;
+  if (mb == 0) e = -128;
+  uint32_t h[4] = {0, 0, 0, 0}, nib = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    // round to nearest even through the 1.5 2^23 offset (|v 2^-e| < 2^19)
+    const float t = bad ? 0.0f : ldexpf(v[i], -e) + 12582912.0f;
+    int32_t mant = (int32_t)(__float_as_uint(t) - 0x4b400000u);
+    mant = mant > 524287 ? 524287 : mant;
+    h[i >> 1] |= (((uint32_t)mant >> 4) & 0xffffu) << (16 * (i & 1));
+    nib |= ((uint32_t)mant & 15u) << (4 * i);
+  }
+  char* grp = sb + PK_HDR_BYTES + PK_GROUP_BYTES * g;
+  typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+  typedef unsigned int v2u __attribute__((ext_vector_type(2)));
+  *reinterpret_cast<v4u*>(grp + 16 * c) = v4u{h[0], h[1], h[2], h[3]};
+  *reinterpret_cast<uint32_t*>(grp + 64 + 4 * c) = nib;
+  if (c == 0) sb[g] = (char)(signed char)(bad ? PK_EXP_NONFINITE : e);
+  if (c == 0 && g == 0) *reinterpret_cast<v2u*>(sb + 8) = v2u{0u, 0u};   // unused header bytes
+}
+
+// Workgroup b of n -> tile, so that each XCD (workgroups are dealt to the 8
+// XCDs in turn) takes a contiguous run of tiles: neighbouring tiles share
+// cache lines of the packed rows, which then meet in one L2.
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t n) {
+  const int64_t x = b & 7, i = b >> 3, q = n >> 3, r = n & 7;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
+}
 
 // --------------------------------------------------------------------------
 // small device helpers

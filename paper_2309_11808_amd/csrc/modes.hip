@@ -109,6 +109,109 @@ __device__ __forceinline__ void modes_body(const cpx_t<TC>* __restrict__ qhat,
   }
 }
 
+// Packed Fourier blocks (complex64 modes): one thread per 4 degrees of
+// freedom, 2 pairs of one group, decoded from their int16 high parts, low
+// nibbles and the group's exponent at every block.
+__device__ __forceinline__ void modes_pk_body(const char* __restrict__ qhat, int64_t rowb,
+                                              const double* __restrict__ lam,
+                                              const double2* __restrict__ psi,
+                                              float2* __restrict__ phi, int32_t* __restrict__ n_valid,
+                                              int64_t M, int L, int n_modes, double eps, int64_t bx,
+                                              int k) {
+  using C = float2;
+  extern __shared__ char modes_lds[];
+  C* coef = reinterpret_cast<C*>(modes_lds);   // [L][n_modes]
+  __shared__ unsigned vmask[MODES_MAXM / 32];
+  const int tid = threadIdx.x;
+  const double* lk = lam + (int64_t)k * L;
+  const double l0 = lk[0];
+  if (tid < MODES_MAXM / 32) {
+    unsigned b = 0;
+    for (int j = 32 * tid; j < n_modes && j < 32 * tid + 32; ++j)
+      b |= (unsigned)(l0 > 0.0 && lk[j] > eps * l0) << (j - 32 * tid);
+    vmask[tid] = b;
+  }
+  for (int idx = tid; idx < L * n_modes; idx += blockDim.x) {
+    const int l = idx / n_modes, j = idx % n_modes;
+    const double lj = lk[j];
+    const bool valid = l0 > 0.0 && lj > eps * l0;
+    const double s = valid ? 1.0 / sqrt(lj) : 0.0;
+    const double2 ps = psi[((int64_t)k * L + l) * L + j];
+    coef[idx] = C{(float)(ps.x * s), (float)(ps.y * s)};
+  }
+  if (bx == 0 && tid == 0 && n_valid) {
+    int c = 0;
+    for (int j = 0; j < n_modes; ++j) c += (l0 > 0.0 && lk[j] > eps * l0);
+    n_valid[k] = c;
+  }
+  __syncthreads();
+  const int64_t m = (bx * blockDim.x + tid) * 4;
+  if (m >= M) return;
+  typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+  const int g = (int)((m % PK_SB_DOFS) >> 4), p0 = (int)((m & 15) >> 1);
+  const char* src = qhat + (int64_t)k * L * rowb + (m / PK_SB_DOFS) * PK_SB_BYTES;
+  const char* grp = src + PK_HDR_BYTES + PK_GROUP_BYTES * g;
+  C* dst = phi + (int64_t)k * n_modes * M + m;
+  const bool vec = (M % 2 == 0) && (m + 3 < M) && ((uintptr_t)phi % 16 == 0);
+  for (int j0 = 0; j0 < n_modes; j0 += MODES_GROUP) {
+    C acc[4][MODES_GROUP];
+#pragma unroll
+    for (int d = 0; d < 4; ++d)
+#pragma unroll
+      for (int j = 0; j < MODES_GROUP; ++j) acc[d][j] = C{0, 0};
+    for (int l = 0; l < L; ++l) {
+      const int64_t ro = (int64_t)l * rowb;
+      const v4u h = __builtin_nontemporal_load(reinterpret_cast<const v4u*>(grp + ro + 8 * p0));
+      const uint32_t nib = *reinterpret_cast<const uint32_t*>(grp + ro + 64 + 2 * p0);
+      const float scale = pk_scale((int)(signed char)src[ro + g]);
+      float v[8];
+      pk_decode4(h[0], h[1], nib & 0xffffu, scale, v);
+      pk_decode4(h[2], h[3], nib >> 16, scale, v + 4);
+      const C* cl = coef + l * n_modes + j0;
+#pragma unroll
+      for (int j = 0; j < MODES_GROUP; ++j) {
+        if (j0 + j < n_modes) {
+          const C c = cl[j];
+#pragma unroll
+          for (int d = 0; d < 4; ++d) {
+            acc[d][j].x += v[2 * d] * c.x - v[2 * d + 1] * c.y;
+            acc[d][j].y += v[2 * d] * c.y + v[2 * d + 1] * c.x;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < MODES_GROUP; ++j) {
+      if (j0 + j < n_modes) {
+        if (!((vmask[(j0 + j) >> 5] >> ((j0 + j) & 31)) & 1u)) {
+#pragma unroll
+          for (int d = 0; d < 4; ++d) acc[d][j] = C{0, 0};
+        }
+        C* o = dst + (int64_t)(j0 + j) * M;
+        if (vec) {
+          const modes_v4 a = {acc[0][j].x, acc[0][j].y, acc[1][j].x, acc[1][j].y};
+          const modes_v4 b = {acc[2][j].x, acc[2][j].y, acc[3][j].x, acc[3][j].y};
+          __builtin_nontemporal_store(a, reinterpret_cast<modes_v4*>(o));
+          __builtin_nontemporal_store(b, reinterpret_cast<modes_v4*>(o) + 1);
+        } else {
+#pragma unroll
+          for (int d = 0; d < 4; ++d)
+            if (m + d < M) o[d] = acc[d][j];
+        }
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void modes_pk_kernel(const char* __restrict__ qhat, int64_t rowb,
+                                                       const double* __restrict__ lam,
+                                                       const double2* __restrict__ psi,
+                                                       float2* __restrict__ phi,
+                                                       int32_t* __restrict__ n_valid, int64_t M, int L,
+                                                       int n_modes, double eps) {
+  modes_pk_body(qhat, rowb, lam, psi, phi, n_valid, M, L, n_modes, eps, blockIdx.x, blockIdx.y);
+}
+
 template <typename TC, bool PAIR>
 __global__ __launch_bounds__(256) void modes_kernel(const cpx_t<TC>* __restrict__ qhat,
                                                     const double* __restrict__ lam,
@@ -143,7 +246,13 @@ spod_status launch_modes(const Plan& p, const void* qhat, const double* lam, con
   (void)ws;
   if (p.nblocks > MODES_MAXL) return fail(SPOD_ERR_UNSUPPORTED, "nblocks > 64");
   const size_t lds = (is_complex128(p) ? 16 : 8) * (size_t)p.nblocks * (size_t)n_modes;
-  if (is_complex128(p)) {
+  if (p.qhat_packed) {
+    dim3 grid((unsigned)(((p.M + 3) / 4 + 255) / 256), (unsigned)p.nfreq);
+    hipLaunchKernelGGL(modes_pk_kernel, grid, dim3(256), lds, st, static_cast<const char*>(qhat),
+                       pk_row_bytes(p.M), lam, static_cast<const double2*>(psi),
+                       static_cast<float2*>(phi), n_valid, (int64_t)p.M, (int)p.nblocks, n_modes,
+                       1e-6);
+  } else if (is_complex128(p)) {
     dim3 grid((unsigned)((p.M + 255) / 256), (unsigned)p.nfreq);
     hipLaunchKernelGGL((modes_kernel<double, false>), grid, dim3(256), lds, st,
                        static_cast<const double2*>(qhat), lam, static_cast<const double2*>(psi),

@@ -329,7 +329,7 @@ spod_status ooc_create_body(Ooc* o, Plan* p, spod_dtype dtype, int64_t chunk_row
   o->csz = is_complex128(*p) ? 16 : 8;
   const size_t K = (size_t)p->nfreq, L = (size_t)p->nblocks;
   o->slot_bytes = up256((size_t)rows * (size_t)p->nt * o->esz);
-  o->qhat_bytes = up256(K * L * (size_t)rows * o->csz);
+  o->qhat_bytes = up256(qhat_bytes(plan_rows(*p, 0, rows)));
   o->phi_bytes = up256(K * (size_t)n_modes * (size_t)rows * o->csz);
   o->ws_bytes = std::max<size_t>(256, plan_rows(*p, 0, rows).ws_bytes);
   const size_t gram_bytes = up256(K * L * L * sizeof(double2));

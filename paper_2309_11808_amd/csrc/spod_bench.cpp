@@ -1,8 +1,8 @@
 // spod_bench: a plain C-ABI caller of libspod, with nothing else in the
 // process (no Python, no framework), for hardware-counter runs.
 //
-//   spod_bench [nspace nvar nt nfft noverlap reps precision path]
-//   defaults:   524288  2   8192 512  256      3    2 (bf16x4)  0
+//   spod_bench [nspace nvar nt nfft noverlap reps precision path qhat_format]
+//   defaults:   524288  2   8192 512  256      3    2 (bf16x4)  0    0 (complex)
 //
 // Fills q [M][nt] float32 on the device with hashed values in [-1, 1).
 // path 0: runs spod_blocks_fft `reps` times, then copies 1 GiB device to
@@ -135,19 +135,21 @@ static int run_rates() {
 }
 
 static int run_path(int64_t nspace, int64_t nvar, int64_t nt, int64_t nfft, int64_t nov,
-                    int64_t reps, spod_precision prec, const float* q) {
+                    int64_t reps, spod_precision prec, const float* q, int64_t fmt) {
   const int64_t M = nspace * nvar, n_modes = 5;
   spod_plan plan = nullptr;
   CHECK_SPOD(spod_plan_create(nspace, nvar, nt, nfft, nov, nullptr, nullptr, &plan));
   CHECK_SPOD(spod_plan_set_precision(plan, prec));
+  CHECK_SPOD(spod_plan_set_option(plan, SPOD_OPT_QHAT_FORMAT, fmt));
   int64_t L = 0, K = 0;
-  size_t wsb = 0;
+  size_t wsb = 0, qhb = 0;
   CHECK_SPOD(spod_plan_query(plan, &L, &K, &wsb));
+  CHECK_SPOD(spod_plan_qhat_bytes(plan, &qhb));
   const size_t csz = prec == SPOD_PREC_FP64 ? 16 : 8;
   void *qhat = nullptr, *gram = nullptr, *psi = nullptr, *phi = nullptr, *ws = nullptr;
   double *mean = nullptr, *lam = nullptr;
   int32_t *info = nullptr, *nval = nullptr;
-  CHECK_HIP(hipMalloc(&qhat, csz * (size_t)(K * L * M)));
+  CHECK_HIP(hipMalloc(&qhat, qhb));
   CHECK_HIP(hipMalloc(&phi, csz * (size_t)(K * n_modes * M)));
   CHECK_HIP(hipMalloc(&gram, 16 * (size_t)(K * L * L)));
   CHECK_HIP(hipMalloc(&psi, 16 * (size_t)(K * L * L)));
@@ -237,9 +239,10 @@ static int run_ooc(int64_t nspace, int64_t nvar, int64_t nt, int64_t nfft, int64
 }
 
 int main(int argc, char** argv) {
-  int64_t nspace = 524288, nvar = 2, nt = 8192, nfft = 512, nov = 256, reps = 3, prec = 2, path = 0;
-  int64_t* args[] = {&nspace, &nvar, &nt, &nfft, &nov, &reps, &prec, &path};
-  for (int i = 1; i < argc && i <= 8; ++i) *args[i - 1] = std::atoll(argv[i]);
+  int64_t nspace = 524288, nvar = 2, nt = 8192, nfft = 512, nov = 256, reps = 3, prec = 2, path = 0,
+          fmt = 0;
+  int64_t* args[] = {&nspace, &nvar, &nt, &nfft, &nov, &reps, &prec, &path, &fmt};
+  for (int i = 1; i < argc && i <= 9; ++i) *args[i - 1] = std::atoll(argv[i]);
   const int64_t M = nspace * nvar;
   if (path == 3) {
     if (run_rates()) return 1;
@@ -258,8 +261,8 @@ int main(int argc, char** argv) {
     hipLaunchKernelGGL(fill_kernel, dim3(8192), dim3(256), 0, 0, q, (int64_t)(qbytes / 4), 12345u);
     CHECK_HIP(hipGetLastError());
     CHECK_HIP(hipDeviceSynchronize());
-    if (run_path(nspace, nvar, nt, nfft, nov, reps, (spod_precision)prec, q)) return 1;
-    if (run_path(nspace, nvar, nt, nfft, nov, reps, SPOD_PREC_FP64, q)) return 1;
+    if (run_path(nspace, nvar, nt, nfft, nov, reps, (spod_precision)prec, q, fmt)) return 1;
+    if (run_path(nspace, nvar, nt, nfft, nov, reps, SPOD_PREC_FP64, q, 0)) return 1;
     CHECK_HIP(hipFree(q));
     std::printf("done\n");
     return 0;
@@ -268,12 +271,12 @@ int main(int argc, char** argv) {
   spod_plan plan = nullptr;
   CHECK_SPOD(spod_plan_create(nspace, nvar, nt, nfft, nov, nullptr, nullptr, &plan));
   CHECK_SPOD(spod_plan_set_precision(plan, (spod_precision)prec));
+  CHECK_SPOD(spod_plan_set_option(plan, SPOD_OPT_QHAT_FORMAT, fmt));
   int64_t L = 0, K = 0;
-  size_t wsb = 0;
+  size_t wsb = 0, hbytes = 0;
   CHECK_SPOD(spod_plan_query(plan, &L, &K, &wsb));
-  const size_t csz = prec == SPOD_PREC_FP64 ? 16 : 8;
+  CHECK_SPOD(spod_plan_qhat_bytes(plan, &hbytes));
   const size_t qbytes = sizeof(float) * (size_t)M * (size_t)nt;
-  const size_t hbytes = csz * (size_t)K * (size_t)L * (size_t)M;
   std::printf("M=%lld nt=%lld nfft=%lld L=%lld K=%lld q=%.3f GB qhat=%.3f GB\n", (long long)M,
               (long long)nt, (long long)nfft, (long long)L, (long long)K, qbytes / 1e9, hbytes / 1e9);
   std::fflush(stdout);

@@ -75,13 +75,20 @@ class Plan:
         self._h = h
         self.precision = precision
         _check(lib().spod_plan_set_precision(self._h, PRECISIONS[precision]))
+        self.packed = False
         for k, v in (options or {}).items():
+            if k == "qhat_format":
+                v = {"complex": N.SPOD_QHAT_COMPLEX, "bfp20": N.SPOD_QHAT_BFP20}[v]
+                self.packed = v == N.SPOD_QHAT_BFP20
             opt = {"max_sweeps": N.SPOD_OPT_MAX_SWEEPS, "gram_split": N.SPOD_OPT_GRAM_SPLIT,
-                   "fft_tile": N.SPOD_OPT_FFT_TILE}[k]
+                   "fft_tile": N.SPOD_OPT_FFT_TILE, "qhat_format": N.SPOD_OPT_QHAT_FORMAT}[k]
             _check(lib().spod_plan_set_option(self._h, opt, int(v)))
         L, K, ws = C.c_int64(), C.c_int64(), C.c_size_t()
         _check(lib().spod_plan_query(self._h, C.byref(L), C.byref(K), C.byref(ws)))
         self.nblocks, self.nfreq, self.workspace_bytes = L.value, K.value, ws.value
+        qb = C.c_size_t()
+        _check(lib().spod_plan_qhat_bytes(self._h, C.byref(qb)))
+        self.qhat_bytes = qb.value
         self.cdtype = torch.complex128 if precision == "fp64" else torch.complex64
         self._ws = None
 
@@ -125,10 +132,17 @@ class Plan:
         self._dev(q, "q", q.dtype, (self.M, self.nt))
         return N.SPOD_F32 if q.dtype == torch.float32 else N.SPOD_F64
 
+    def _qhat(self, qhat, name="qhat"):
+        """qhat as the plan stores it: complex [K, L, M], or the packed
+        20-bit layout as a uint8 tensor of qhat_bytes (SPOD_QHAT_BFP20)."""
+        if self.packed:
+            return self._out(qhat, name, torch.uint8, (self.qhat_bytes,))
+        return self._out(qhat, name, self.cdtype, (self.nfreq, self.nblocks, self.M))
+
     # -- stages -------------------------------------------------------------
     def blocks_fft(self, q, qhat=None, mean=None, want_mean: bool = True):
         dt = self._q(q)
-        qhat = self._out(qhat, "qhat", self.cdtype, (self.nfreq, self.nblocks, self.M))
+        qhat = self._qhat(qhat)
         if want_mean or mean is not None:
             mean = self._out(mean, "mean", torch.float64, (self.M,))
         ws = self.workspace()
@@ -137,7 +151,7 @@ class Plan:
         return qhat, mean
 
     def csd(self, qhat, gram=None):
-        self._dev(qhat, "qhat", self.cdtype, (self.nfreq, self.nblocks, self.M))
+        self._qhat(qhat)
         gram = self._out(gram, "gram", torch.complex128, (self.nfreq, self.nblocks, self.nblocks))
         ws = self.workspace()
         _check(lib().spod_csd(self._h, _ptr(qhat), _ptr(gram), _ptr(ws), ws.numel(),
@@ -157,7 +171,7 @@ class Plan:
 
     def modes(self, qhat, lam, psi, n_modes: int, phi=None, n_valid=None):
         L, K = self.nblocks, self.nfreq
-        self._dev(qhat, "qhat", self.cdtype, (K, L, self.M))
+        self._qhat(qhat)
         self._dev(lam, "lam", torch.float64, (K, L))
         self._dev(psi, "psi", torch.complex128, (K, L, L))
         phi = self._out(phi, "phi", self.cdtype, (K, n_modes, self.M))

@@ -190,3 +190,76 @@ def check_invalid_modes_zero(phi_gpu, n_valid):
     pg = as_np(phi_gpu)
     for k in range(pg.shape[0]):
         assert np.all(pg[k, int(n_valid[k]):] == 0), f"invalid modes at k={k} are not zero"
+
+
+# ---------------------------------------------------------------------------
+# packed Fourier blocks (SPOD_QHAT_BFP20), written here from the layout that
+# include/spod.h documents, independently of the library's kernels
+# ---------------------------------------------------------------------------
+PK_SB_DOFS, PK_SB_BYTES = 128, 656
+
+
+def pk_row_bytes(M):
+    return -(-M // PK_SB_DOFS) * PK_SB_BYTES
+
+
+def unpack_qhat(buf, K, L, M):
+    """Decode a packed qhat (bytes or uint8 array) to complex128 [K, L, M]."""
+    b = np.frombuffer(as_np(buf).tobytes(), dtype=np.uint8)
+    nsb = -(-M // PK_SB_DOFS)
+    assert b.size == K * L * nsb * PK_SB_BYTES, (b.size, K, L, M)
+    sb = b.reshape(K * L, nsb, PK_SB_BYTES)
+    e = sb[:, :, :8].view(np.int8).astype(np.int64)                    # [rows, nsb, 8]
+    grp = sb[:, :, 16:].reshape(K * L, nsb, 8, 80)
+    h = grp[:, :, :, :64].copy().view("<i2").astype(np.int64)           # [rows, nsb, 8, 32]
+    nib16 = grp[:, :, :, 64:].copy().view("<u2").astype(np.int64)       # [rows, nsb, 8, 8]
+    nib = np.stack([(nib16 >> (4 * i)) & 15 for i in range(4)], axis=-1).reshape(h.shape)
+    mant = h * 16 + nib
+    scale = np.where(e == 127, np.nan, np.ldexp(1.0, np.clip(e, -1074, 1023)))
+    v = mant * scale[..., None]                                          # [rows, nsb, 8, 32]
+    v = v.reshape(K * L, nsb * 128, 2)
+    out = (v[:, :, 0] + 1j * v[:, :, 1]).reshape(K, L, nsb * 128)
+    return out[:, :, :M], out[:, :, M:], sb
+
+
+def pack_qhat(qh):
+    """Encode complex [K, L, M] values into the packed layout (round to nearest,
+    exponent E with |v| 2^-E < 2^19 per group of 16 degrees of freedom)."""
+    K, L, M = qh.shape
+    nsb = -(-M // PK_SB_DOFS)
+    pad = nsb * 128 - M
+    z = np.pad(np.asarray(qh, np.complex128), ((0, 0), (0, 0), (0, pad))).reshape(K * L, nsb, 8, 16)
+    v = np.stack([z.real, z.imag], axis=-1).reshape(K * L, nsb, 8, 32)
+    mx = np.abs(v).max(axis=-1)
+    ex = np.frexp(mx)[1]
+    e = np.where(mx > 0, np.maximum(ex - 19, -128), -128).astype(np.int64)
+    mant = np.clip(np.rint(np.ldexp(v, -e[..., None])), -524288, 524287).astype(np.int64)
+    h = (mant >> 4).astype("<i2")
+    nib = (mant & 15).reshape(K * L, nsb, 8, 8, 4)
+    nib16 = (nib[..., 0] | (nib[..., 1] << 4) | (nib[..., 2] << 8) | (nib[..., 3] << 12)).astype("<u2")
+    out = np.zeros((K * L, nsb, PK_SB_BYTES), dtype=np.uint8)
+    out[:, :, :8] = e.astype(np.int8).view(np.uint8)
+    grp = np.concatenate([h.view(np.uint8).reshape(K * L, nsb, 8, 64),
+                          nib16.view(np.uint8).reshape(K * L, nsb, 8, 16)], axis=-1)
+    out[:, :, 16:] = grp.reshape(K * L, nsb, 640)
+    return out.reshape(-1)
+
+
+def check_packed_format(sb, M):
+    """Layout invariants of a packed qhat (the sb view from unpack_qhat):
+    header bytes 8..15 zero, mantissas of every non-zero group normalised
+    (largest magnitude in [2^18, 2^19]), degrees of freedom past M zero."""
+    rows, nsb, _ = sb.shape
+    assert not sb[:, :, 8:16].any(), "header bytes 8..15 must be zero"
+    e = sb[:, :, :8].view(np.int8).astype(np.int64)
+    grp = sb[:, :, 16:].reshape(rows, nsb, 8, 80)
+    h = grp[:, :, :, :64].copy().view("<i2").astype(np.int64)
+    nib16 = grp[:, :, :, 64:].copy().view("<u2").astype(np.int64)
+    nib = np.stack([(nib16 >> (4 * i)) & 15 for i in range(4)], axis=-1).reshape(h.shape)
+    mant = h * 16 + nib
+    amax = np.abs(mant).max(axis=-1)
+    live = (amax > 0) & (e != 127)
+    assert np.all(amax[live] >= 2 ** 18) and np.all(amax[live] <= 2 ** 19), "mantissas not normalised"
+    assert np.all(e[amax == 0] == -128), "zero groups must carry exponent -128"
+    dofs = mant.reshape(rows, nsb * 128, 2)
+    assert not dofs[:, M:].any(), "degrees of freedom past M must be zero"

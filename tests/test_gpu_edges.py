@@ -107,7 +107,7 @@ def test_batch_of_one_with_clamped_modes():
     b.close()
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp16x4"])
+@pytest.mark.parametrize("precision", ["fp64", "fp16x4", "fp16x4+bfp20"])
 @pytest.mark.parametrize("bad", ["nan", "inf"])
 def test_non_finite_data_is_reported(precision, bad):
     """One NaN row or one infinite sample: every frequency's Gram is then not
@@ -122,7 +122,11 @@ def test_non_finite_data_is_reported(precision, bad):
         q[7, :] = float("nan")
     else:
         q[11, 100] = float("inf")
-    plan = _plan(p, precision)
+    from paper_2309_11808_amd import Plan
+    packed = precision.endswith("+bfp20")
+    precision = precision.split("+")[0]
+    plan = Plan(p.nspace, p.nvar, p.nt, p.nfft, p.noverlap, weights=p.weights, precision=precision,
+                options={"qhat_format": "bfp20"} if packed else None)
     qdev = q.to(torch.float64 if precision == "fp64" else torch.float32).cuda()
     K, L = plan.nfreq, plan.nblocks
     qhat, mean = plan.blocks_fft(qdev)

@@ -341,3 +341,122 @@ def test_fft_tile_option(nfft, precision):
         with pytest.raises(SpodError) as ei:
             _plan(p, precision, fft_tile=bad)
         assert ei.value.status == -1
+
+
+# ---------------------------------------------------------------------------
+# packed Fourier blocks (20-bit block floating point, SPOD_QHAT_BFP20)
+# ---------------------------------------------------------------------------
+PACKED_FFT_CASES = [
+    (8, 4, 37, 3, torch.float64, 0.0, "hann"),
+    (16, 8, 65, 0, torch.float64, 5.0, "random"),
+    (64, 32, 129, 11, torch.float64, 100.0, "hann"),
+    (128, 64, 70, 0, torch.float32, 3.0, "random"),
+    (256, 128, 97, 13, torch.float32, 0.0, "hann"),
+    (256, 0, 40, 1, torch.float64, 0.0, "hann"),
+    (512, 256, 300, 3, torch.float32, 10.0, "hann"),
+    (512, 128, 33, 0, torch.float64, 0.0, "hann"),
+    (1024, 512, 35, 17, torch.float64, 1.0, "hamming"),
+]
+
+
+def _packed_plan(p, prec="fp16x4", window=None, **opt):
+    return _plan(p, prec, window=window, qhat_format="bfp20", **opt)
+
+
+@pytest.mark.parametrize("nfft,nov,M,extra,dtype,offset,wkind", PACKED_FFT_CASES)
+def test_blocks_fft_packed_matches_oracle(nfft, nov, M, extra, dtype, offset, wkind):
+    """Packed blocks decode to the oracle's within the FP32 transform's error
+    (4e-6 of the block norm) plus the 20-bit rounding (2^-19 of the largest
+    real or imaginary part in the group of 16 degrees of freedom), and keep the
+    layout's invariants (normalised mantissas, zero padding)."""
+    L = 3 + (nfft % 5)
+    nt = (L - 1) * (nfft - nov) + nfft + extra
+    p = _rand_problem(M, nt, nfft, nov, seed=nfft + M, dtype=dtype, offset=offset)
+    window = _window(wkind, nfft, nfft)
+    plan = _packed_plan(p, window=window)
+    q = p.q.to(torch.float32).cuda()
+    qhat, mean = plan.blocks_fft(q)
+    torch.cuda.synchronize()
+    K = plan.nfreq
+    dec, _, sb = PT.unpack_qhat(qhat.cpu().numpy(), K, L, M)
+    PT.check_packed_format(sb, M)
+    q64 = q.cpu().numpy().astype(np.float64)
+    ora = O.fourier_blocks(q64, nfft, nov, window)
+    np.testing.assert_allclose(mean.cpu().numpy(), O.temporal_mean(q64), rtol=1e-14,
+                               atol=1e-15 * (1 + abs(offset)))
+    norm = np.sqrt(np.sum(np.abs(ora) ** 2, axis=0, keepdims=True))
+    pad = (-M) % 16
+    parts = np.stack([ora.real, ora.imag], axis=-1)
+    gmax = np.abs(np.pad(parts, ((0, 0), (0, 0), (0, pad), (0, 0)))).reshape(K, L, -1, 32).max(-1)
+    gmax = np.repeat(gmax, 16, axis=2)[:, :, :M]
+    err = np.abs(dec - ora) - (4e-6 * norm + 2.0 ** -19 * np.sqrt(2.0) * gmax)
+    assert err.max() <= 0.0, f"packed blocks beyond the bound by {err.max():.3e}"
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x4", "fp16x4"])
+@pytest.mark.parametrize("L,M", [(2, 1), (7, 300), (15, 1024), (16, 77), (31, 5000), (33, 130),
+                                 (47, 700), (64, 200)])
+def test_csd_packed_matches_oracle(prec, L, M):
+    """The Gram of packed blocks (encoded on the host from the layout's
+    definition) against the oracle's Gram of the same decoded values."""
+    nfft, nov = 16, 8
+    nt = (L - 1) * 8 + 16
+    p = _rand_problem(M, nt, nfft, nov, seed=L * 7 + M)
+    plan = _packed_plan(p, prec, gram_split=3 if M > 1000 else 0)
+    qh = O.fourier_blocks(p.q.numpy(), nfft, nov)
+    buf = PT.pack_qhat(qh)
+    dec, _, _ = PT.unpack_qhat(buf, plan.nfreq, L, M)
+    assert buf.size == plan.qhat_bytes
+    gram = plan.csd(torch.as_tensor(buf).cuda())
+    torch.cuda.synchronize()
+    PT.check_gram(gram, O.gram(dec, p.weights), GRAM_TOL[prec])
+    plan.close()
+
+
+def test_modes_packed_matches_oracle():
+    L, M, nfft, nov = 15, 1031, 32, 16
+    nt = (L - 1) * 16 + 32
+    p = _rand_problem(M, nt, nfft, nov, seed=77)
+    plan = _packed_plan(p, "fp16x4")
+    qh = O.fourier_blocks(p.q.numpy(), nfft, nov)
+    buf = PT.pack_qhat(qh)
+    dec, _, _ = PT.unpack_qhat(buf, plan.nfreq, L, M)
+    lam, V, _ = O.jacobi_eigh(O.gram(dec, p.weights))
+    lam, psi = O.sort_and_phase(lam, V)
+    phi, n_valid = plan.modes(torch.as_tensor(buf).cuda(), _dev(lam), _dev(psi), 5)
+    torch.cuda.synchronize()
+    ref, nv = O.modes(dec, lam, psi, 5, eps=1e-6)
+    np.testing.assert_array_equal(n_valid.cpu().numpy(), nv)
+    g = phi.cpu().numpy()
+    scale = np.abs(ref).max(axis=2, keepdims=True) + 1e-300
+    assert (np.abs(g - ref) / scale).max() < 2e-6
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["fp16x4", "bf16x4"])
+def test_planted_field_packed_end_to_end(prec):
+    """The planted field (lambda_1 / lambda_5 ~ 2e5 at the planted bins) through
+    packed blocks meets the mixed-path bars; the backward of a packed plan
+    recomputes complex blocks and gives the complex plan's gradient."""
+    p = fields.planted(seed=1, sigma=0.1, dtype=torch.float32)
+    plan = _packed_plan(p, prec)
+    out = plan.forward(p.q.cuda(), n_modes=5)
+    torch.cuda.synchronize()
+    o = O.spod(p.q.numpy(), 128, 64, weights=p.weights, n_modes=5, eps=1e-6)
+    err = PT.check_eig_mixed(out["lam"], o["lam"], n=5)
+    s, n = PT.check_modes(out["phi"], o["phi"], o["lam"], p.weights, o["n_valid"], sin_tol=1e-3,
+                          elem_tol=1e-2, rel_gap=1e-3)
+    assert n > 100 and int(out["info"].min()) > 0
+    print(f"packed {prec}: eigenvalue rel err {err:.2e}, mode sine {s:.2e}")
+    bins = list(p.meta["bins"])
+    g_lam = torch.zeros(len(bins), plan.nblocks, dtype=torch.float64, device="cuda")
+    g_lam[:, :3] = 1.0
+    lam_b, psi_b = out["lam"][bins].contiguous(), out["psi"]
+    g1 = plan.backward(p.q.cuda(), out["lam"], psi_b, g_lam=g_lam, bins=bins)
+    cplan = _plan(p, prec)
+    g2 = cplan.backward(p.q.cuda(), out["lam"], psi_b, g_lam=g_lam, bins=bins)
+    torch.cuda.synchronize()
+    assert torch.equal(g1, g2)
+    cplan.close()
+    plan.close()
