@@ -105,11 +105,24 @@ def workload(name, device):
     return p, desc
 
 
+def form_options(form):
+    """(precision, plan options) of a form name: "+bfp20" selects packed
+    Fourier blocks, "+mfma" the matrix-core modes kernel."""
+    prec, *mods = form.split("+")
+    opts = {}
+    for m in mods:
+        if m == "bfp20":
+            opts["qhat_format"] = "bfp20"
+        elif m == "mfma":
+            opts["modes_kernel"] = "mfma"
+        else:
+            raise SystemExit(f"unknown form modifier {m}")
+    return prec, opts or None
+
+
 def make_plan(p, form, **kw):
-    """A plan for a precision form name; "+bfp20" selects packed Fourier blocks."""
     from paper_2309_11808_amd import Plan
-    prec, _, fmt = form.partition("+")
-    opts = {"qhat_format": fmt} if fmt else None
+    prec, opts = form_options(form)
     return Plan(p.nspace, p.nvar, p.nt, p.nfft, p.noverlap, weights=p.weights, precision=prec,
                 options=opts, **kw)
 
@@ -268,9 +281,8 @@ def cpu_baseline(p, precisions, seconds_target=20.0, single_thread=True):
     sel = np.unique(np.linspace(1, ref["lam"].shape[0] - 1, 8).round().astype(int))
     w = p.weights[:S]
     for prec in precisions:
-        base, _, fmt = prec.partition("+")
-        plan = Plan(S, 1, p.nt, p.nfft, p.noverlap, weights=w, precision=base,
-                    options={"qhat_format": fmt} if fmt else None)
+        base, opts = form_options(prec)
+        plan = Plan(S, 1, p.nt, p.nfft, p.noverlap, weights=w, precision=base, options=opts)
         qs = p.q[:S].contiguous()
         if base == "fp64":
             qs = qs.double()
@@ -746,7 +758,7 @@ def main(argv=None):
         # every precision form's time and eigenvalue error against the FP64 path
         forms = {a.precision: {"ms_per_step": result["ms_per_step"],
                                "eig_rel_err_vs_fp64": err, "eig_bar_met": ok}}
-        for prec in ("fp16x4+bfp20", "fp16x4", "bf16x4", "fp32"):
+        for prec in ("fp16x4+mfma", "fp16x4+bfp20", "fp16x4", "bf16x4", "fp32"):
             if prec in forms:
                 continue
             r = run_path(p, prec, max(2, a.steps // 3), 1)

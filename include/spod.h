@@ -98,8 +98,10 @@ typedef enum {
   SPOD_OPT_GRAM_SPLIT = 1, /* slices of M per frequency in the Gram (0 = automatic)     */
   SPOD_OPT_FFT_TILE = 2,   /* degrees of freedom per transform workgroup: 16 or 32
                               (0 = automatic: 32 for nfft <= 256, else 16)            */
-  SPOD_OPT_QHAT_FORMAT = 3 /* storage of qhat: SPOD_QHAT_COMPLEX (default) or
+  SPOD_OPT_QHAT_FORMAT = 3, /* storage of qhat: SPOD_QHAT_COMPLEX (default) or
                               SPOD_QHAT_BFP20 (complex64 forms, power-of-two nfft)    */
+  SPOD_OPT_MODES_KERNEL = 4  /* complex64 modes of complex qhat: 0 = vector ALU (default),
+                              1 = v_mfma_f32_16x16x4f32 (FP32 products and sums)      */
 } spod_option;
 
 /* Storage of the Fourier blocks qhat between the stages.

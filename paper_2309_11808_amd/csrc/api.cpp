@@ -370,6 +370,11 @@ spod_status spod_plan_set_option(spod_plan plan, spod_option opt, int64_t value)
         return fail(SPOD_ERR_INVALID_ARG, "fft tile must be 0, 16 or 32");
       p->fft_tile_opt = value;
       break;
+    case SPOD_OPT_MODES_KERNEL:
+      if (value != 0 && value != 1)
+        return fail(SPOD_ERR_INVALID_ARG, "modes kernel must be 0 (vector ALU) or 1 (matrix cores)");
+      p->modes_mfma = value == 1;
+      break;
     case SPOD_OPT_QHAT_FORMAT:
       if (value != SPOD_QHAT_COMPLEX && value != SPOD_QHAT_BFP20)
         return fail(SPOD_ERR_INVALID_ARG, "qhat format must be SPOD_QHAT_COMPLEX or SPOD_QHAT_BFP20");

@@ -64,6 +64,7 @@ struct Plan {
   int64_t gram_split_opt = 0;
   int64_t fft_tile_opt = 0;
   bool qhat_packed = false;   // SPOD_QHAT_BFP20: qhat in the packed layout below
+  bool modes_mfma = false;    // complex64 modes on the matrix cores (SPOD_OPT_MODES_KERNEL)
 
   // derived launch shapes (fixed when frozen)
   int gram_split = 1;       // slices of M per frequency

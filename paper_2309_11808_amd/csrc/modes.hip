@@ -203,6 +203,123 @@ __device__ __forceinline__ void modes_pk_body(const char* __restrict__ qhat, int
   }
 }
 
+// Complex64 modes on the matrix cores.  Per 16-DOF tile and 4 blocks, with
+// A = qhat rows (Re, Im) and B = the coefficients (Re, Im, -Im) of up to 16
+// modes, v_mfma_f32_16x16x4f32 accumulates
+//   Re Phi += A_re B_re + A_im (-B_im),   Im Phi += A_re B_im + A_im B_re
+// in FP32.  Lane (i = lane % 16, t = lane / 16) holds the A element of DOF i
+// and block 4 s + t; the B element of block 4 s + t and mode i; the result
+// element of DOF 4 (lane / 16) + v and mode lane % 16.  Each wave owns
+// MODES_TW tiles (8: 128 consecutive DOFs), so every block row is read as
+// 128 contiguous complex values.  Blocks past L and modes past n_modes are
+// zero in the coefficient table.
+constexpr int MODES_TW = 8;
+
+__device__ __forceinline__ void modes_mfma_body(const float2* __restrict__ qhat,
+                                                const double* __restrict__ lam,
+                                                const double2* __restrict__ psi,
+                                                float2* __restrict__ phi,
+                                                int32_t* __restrict__ n_valid, int64_t M, int64_t ldq,
+                                                int L, int n_modes, double eps, int64_t bx, int k) {
+  typedef float v4f_m __attribute__((ext_vector_type(4)));
+  extern __shared__ char modes_lds[];
+  const int Lp = (L + 3) & ~3;
+  float* cre = reinterpret_cast<float*>(modes_lds);   // [Lp][16]: Re of psi / sqrt(lam), one mode group
+  float* cim = cre + Lp * 16;                         // [Lp][16]: Im
+  __shared__ unsigned vmask[MODES_MAXM / 32];
+  const int tid = threadIdx.x;
+  const double* lk = lam + (int64_t)k * L;
+  const double l0 = lk[0];
+  if (tid < MODES_MAXM / 32) {
+    unsigned b = 0;
+    for (int j = 32 * tid; j < n_modes && j < 32 * tid + 32; ++j)
+      b |= (unsigned)(l0 > 0.0 && lk[j] > eps * l0) << (j - 32 * tid);
+    vmask[tid] = b;
+  }
+  if (bx == 0 && tid == 0 && n_valid) {
+    int c = 0;
+    for (int j = 0; j < n_modes; ++j) c += (l0 > 0.0 && lk[j] > eps * l0);
+    n_valid[k] = c;
+  }
+  const int wave = tid >> 6, lane = tid & 63;
+  const int i16 = lane & 15, t4 = lane >> 4;
+  const int64_t mw = (bx * 4 + wave) * (16 * MODES_TW);      // this wave's first DOF
+  const float2* qk = qhat + (int64_t)k * L * ldq;
+  const bool vec = (M % 2 == 0) && ((uintptr_t)phi % 16 == 0);
+  for (int j0 = 0; j0 < n_modes; j0 += 16) {
+    __syncthreads();                                          // the previous group's table is free
+    for (int idx = tid; idx < Lp * 16; idx += blockDim.x) {
+      const int l = idx >> 4, j = j0 + (idx & 15);
+      float re = 0.0f, im = 0.0f;
+      if (l < L && j < n_modes) {
+        const double lj = lk[j];
+        const bool valid = l0 > 0.0 && lj > eps * l0;
+        const double sc = valid ? 1.0 / sqrt(lj) : 0.0;
+        const double2 ps = psi[((int64_t)k * L + l) * L + j];
+        re = (float)(ps.x * sc);
+        im = (float)(ps.y * sc);
+      }
+      cre[idx] = re;
+      cim[idx] = im;
+    }
+    __syncthreads();
+    v4f_m accR[MODES_TW], accI[MODES_TW];
+#pragma unroll
+    for (int w = 0; w < MODES_TW; ++w) accR[w] = accI[w] = v4f_m{0, 0, 0, 0};
+    for (int l0s = 0; l0s < Lp; l0s += 4) {
+      const int l = l0s + t4;
+      const float br = cre[l * 16 + i16], bi = cim[l * 16 + i16];
+      float2 a[MODES_TW];
+#pragma unroll
+      for (int w = 0; w < MODES_TW; ++w) {
+        const int64_t m = mw + 16 * w + i16;
+        a[w] = (l < L && m < M) ? qk[(int64_t)l * ldq + m] : float2{0.0f, 0.0f};
+      }
+#pragma unroll
+      for (int w = 0; w < MODES_TW; ++w) {
+        accR[w] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[w].x, br, accR[w], 0, 0, 0);
+        accR[w] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[w].y, -bi, accR[w], 0, 0, 0);
+        accI[w] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[w].x, bi, accI[w], 0, 0, 0);
+        accI[w] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[w].y, br, accI[w], 0, 0, 0);
+      }
+    }
+    // lane holds DOFs 4 t4 + v of each tile for mode j0 + i16
+    const int j = j0 + i16;
+    if (j < n_modes) {
+      const bool valid = (vmask[j >> 5] >> (j & 31)) & 1u;
+      float2* o = phi + ((int64_t)k * n_modes + j) * M;
+#pragma unroll
+      for (int w = 0; w < MODES_TW; ++w) {
+        const int64_t m = mw + 16 * w + 4 * t4;
+        float v[8];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          v[2 * e] = valid ? accR[w][e] : 0.0f;
+          v[2 * e + 1] = valid ? accI[w][e] : 0.0f;
+        }
+        if (vec && m + 3 < M) {
+          const modes_v4 x = {v[0], v[1], v[2], v[3]}, y = {v[4], v[5], v[6], v[7]};
+          __builtin_nontemporal_store(x, reinterpret_cast<modes_v4*>(o + m));
+          __builtin_nontemporal_store(y, reinterpret_cast<modes_v4*>(o + m) + 1);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (m + e < M) o[m + e] = float2{v[2 * e], v[2 * e + 1]};
+        }
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void modes_mfma_kernel(const float2* __restrict__ qhat,
+                                                         const double* __restrict__ lam,
+                                                         const double2* __restrict__ psi,
+                                                         float2* __restrict__ phi,
+                                                         int32_t* __restrict__ n_valid, int64_t M,
+                                                         int L, int n_modes, double eps) {
+  modes_mfma_body(qhat, lam, psi, phi, n_valid, M, M, L, n_modes, eps, blockIdx.x, blockIdx.y);
+}
+
 __global__ __launch_bounds__(256) void modes_pk_kernel(const char* __restrict__ qhat, int64_t rowb,
                                                        const double* __restrict__ lam,
                                                        const double2* __restrict__ psi,
@@ -258,6 +375,14 @@ spod_status launch_modes(const Plan& p, const void* qhat, const double* lam, con
                        static_cast<const double2*>(qhat), lam, static_cast<const double2*>(psi),
                        static_cast<double2*>(phi), n_valid, (int64_t)p.M, (int)p.nblocks, n_modes,
                        1e-12);
+  } else if (p.modes_mfma) {
+    // the complex64 modes on the matrix cores: 512 DOFs per workgroup
+    const size_t lds_m = 2 * sizeof(float) * 16 * (size_t)((p.nblocks + 3) & ~3);
+    dim3 grid((unsigned)((p.M + 4 * 16 * MODES_TW - 1) / (4 * 16 * MODES_TW)), (unsigned)p.nfreq);
+    hipLaunchKernelGGL(modes_mfma_kernel, grid, dim3(256), lds_m, st,
+                       static_cast<const float2*>(qhat), lam, static_cast<const double2*>(psi),
+                       static_cast<float2*>(phi), n_valid, (int64_t)p.M, (int)p.nblocks, n_modes,
+                       1e-6);
   } else if (p.M % 2 == 0 && (uintptr_t)qhat % 16 == 0 && (uintptr_t)phi % 16 == 0) {
     // two degrees of freedom per thread, 16-byte loads and stores
     dim3 grid((unsigned)((p.M / 2 + 255) / 256), (unsigned)p.nfreq);

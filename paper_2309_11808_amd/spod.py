@@ -81,7 +81,10 @@ class Plan:
                 v = {"complex": N.SPOD_QHAT_COMPLEX, "bfp20": N.SPOD_QHAT_BFP20}[v]
                 self.packed = v == N.SPOD_QHAT_BFP20
             opt = {"max_sweeps": N.SPOD_OPT_MAX_SWEEPS, "gram_split": N.SPOD_OPT_GRAM_SPLIT,
-                   "fft_tile": N.SPOD_OPT_FFT_TILE, "qhat_format": N.SPOD_OPT_QHAT_FORMAT}[k]
+                   "fft_tile": N.SPOD_OPT_FFT_TILE, "qhat_format": N.SPOD_OPT_QHAT_FORMAT,
+                   "modes_kernel": N.SPOD_OPT_MODES_KERNEL}[k]
+            if k == "modes_kernel":
+                v = {"valu": 0, "mfma": 1}.get(v, v)
             _check(lib().spod_plan_set_option(self._h, opt, int(v)))
         L, K, ws = C.c_int64(), C.c_int64(), C.c_size_t()
         _check(lib().spod_plan_query(self._h, C.byref(L), C.byref(K), C.byref(ws)))

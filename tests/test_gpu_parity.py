@@ -460,3 +460,35 @@ def test_planted_field_packed_end_to_end(prec):
     assert torch.equal(g1, g2)
     cplan.close()
     plan.close()
+
+
+@pytest.mark.parametrize("L,M,n_modes", [(15, 1031, 5), (31, 4096, 5), (40, 777, 20), (64, 300, 17),
+                                         (3, 50, 3)])
+def test_modes_mfma_matches_oracle(L, M, n_modes):
+    """The matrix-core modes kernel (FP32 products and sums on
+    v_mfma_f32_16x16x4f32) against the oracle's modes of the same complex64
+    blocks, and against the vector-ALU kernel, with more than 16 modes (two
+    mode groups), odd M, and a near-null eigenvalue (a zero mode)."""
+    nfft, nov = 16, 8
+    nt = (L - 1) * 8 + 16
+    p = _rand_problem(M, nt, nfft, nov, seed=L + M)
+    plan = _plan(p, "fp16x4", modes_kernel="mfma")
+    vplan = _plan(p, "fp16x4")
+    qh = O.fourier_blocks(p.q.numpy(), nfft, nov).astype(np.complex64)
+    lam, V, _ = O.jacobi_eigh(O.gram(qh.astype(np.complex128), p.weights))
+    lam, psi = O.sort_and_phase(lam, V)
+    lam[:, n_modes - 1] = 1e-9 * lam[:, :1].ravel()          # below the valid-mode threshold
+    qd = _dev(qh)
+    phi, n_valid = plan.modes(qd, _dev(lam), _dev(psi), n_modes)
+    phv, nvv = vplan.modes(qd, _dev(lam), _dev(psi), n_modes)
+    torch.cuda.synchronize()
+    ref, nv = O.modes(qh.astype(np.complex128), lam, psi, n_modes, eps=1e-6)
+    np.testing.assert_array_equal(n_valid.cpu().numpy(), nv)
+    np.testing.assert_array_equal(nvv.cpu().numpy(), nv)
+    g = phi.cpu().numpy()
+    assert np.all(g[:, n_modes - 1] == 0)
+    scale = np.abs(ref).max(axis=2, keepdims=True) + 1e-300
+    assert (np.abs(g - ref) / scale).max() < 2e-6
+    assert (np.abs(g - phv.cpu().numpy()) / scale).max() < 2e-6
+    plan.close()
+    vplan.close()
