@@ -179,7 +179,12 @@ spod_status spod_blocks_fft(spod_plan plan, const void* q, spod_dtype dtype, voi
  * inner product of the method of snapshots for every frequency,
  *   gram[k][i][j] = sum_m conj(qhat[k][i][m]) W_m qhat[k][j][m]
  * (complex128 [K][L][L], Hermitian).  The sum over m, which the paper reduces
- * across MPI ranks, is split across workgroups and combined in FP64. */
+ * across MPI ranks, is split across workgroups and combined in FP64.
+ * Up to 64 blocks a workgroup computes every 16 x 16 block pair of its
+ * frequency and slice; up to 160 blocks (the paper's jet analysis has 155) the
+ * pairs are spread over several workgroups (SPOD_PREC_FP64, BF16X4, FP16X4 with
+ * complex qhat; SPOD_ERR_UNSUPPORTED for FP32 or packed qhat there, and for
+ * nblocks > 160). */
 spod_status spod_csd(spod_plan plan, const void* qhat, void* gram, void* ws, size_t ws_bytes,
                      spod_stream stream);
 
@@ -204,7 +209,9 @@ spod_status spod_csd_noalloc(spod_plan plan, const void* qhat, void* gram, int64
                              spod_stream stream);
 
 /* Step 5 (eq. (spod-discrete-snapshots); Sec. 3.1 step 5): eigendecomposition
- * of every Hermitian gram[k] by cyclic Jacobi in FP64.
+ * of every Hermitian gram[k] by cyclic Jacobi in FP64.  One workgroup per
+ * frequency; A and V live in LDS up to 64 blocks and in the workspace (size
+ * from spod_plan_query; required then) up to 160.
  *   lam  : device [K][L] float64, descending.
  *   psi  : device [K][L][L] complex128; psi[k][i][j] = component i of
  *          eigenvector j (unit 2-norm, phase convention above).
@@ -426,7 +433,7 @@ typedef int (*spod_read_fn)(void* user, int64_t row0, int64_t nrows, void* dst);
  * chunks kept on the device between the passes.  Allocates every device
  * buffer and the streams now (on the plan's device, which must be current);
  * pinned host staging buffers are allocated on the first forward pass that
- * needs them.  SPOD_ERR_UNSUPPORTED when nblocks > 64. */
+ * needs them.  SPOD_ERR_UNSUPPORTED when nblocks > 160. */
 spod_status spod_ooc_create(spod_plan plan, spod_dtype dtype, int64_t chunk_rows,
                             int64_t n_modes, int64_t resident, spod_ooc* out);
 

@@ -60,6 +60,13 @@ int64_t gram_split_for(const Plan& p, int64_t target) {
 
 static int64_t auto_gram_split(const Plan& p) {
   if (p.gram_split_opt > 0) return p.gram_split_opt;
+  if (p.nblocks > SPOD_SMALL_NBLOCKS) {
+    // L > 64: the block pairs of a frequency take several workgroups already
+    // (four groups of 6 pairs each); about 4096 workgroups in all
+    const int64_t nt16 = (p.nblocks + 15) / 16, np = nt16 * (nt16 + 1) / 2;
+    const int64_t z = ((np + 5) / 6 + 3) / 4;
+    return gram_split_for(p, std::max<int64_t>(1, 4096 / z));
+  }
   return gram_split_for(p, 8192);
 }
 
@@ -79,8 +86,10 @@ size_t workspace_bytes(const Plan& p) {
   size_t w = fft_workspace(p);
   size_t a = csd_workspace(p);
   size_t b = backward_workspace(p);
+  size_t e = eig_workspace(p);
   if (a > w) w = a;
   if (b > w) w = b;
+  if (e > w) w = e;
   return (w + 255) / 256 * 256;
 }
 
@@ -479,7 +488,8 @@ spod_status spod_eig(spod_plan plan, const void* gram, double* lam, void* psi, i
   spod_status st = enter(p);
   if (st != SPOD_OK) return st;
   if (!gram || !lam || !psi) return fail(SPOD_ERR_INVALID_ARG, "gram, lam and psi are required");
-  (void)ws_bytes;
+  st = check_ws(*p, ws, ws_bytes, eig_workspace(*p));
+  if (st != SPOD_OK) return st;
   return launch_eig(*p, gram, lam, psi, info, ws, (hipStream_t)stream);
 }
 

@@ -29,10 +29,12 @@
 
 namespace spod {
 
-constexpr int EIG_MAXN = 64;
+constexpr int EIG_MAXN = 64;      // A and V in LDS up to here
+constexpr int EIG_BIGN = 160;     // above: A and V in the workspace (L2 and HBM)
 
 // LDS of one eigenproblem: A and V with rows of n + 1 entries (n = L rounded
-// up to even), sized at launch so that small problems share a CU.
+// up to even), sized at launch so that small problems share a CU.  The same
+// layout, per frequency, in the workspace for L > 64.
 __host__ __device__ constexpr size_t eig_lds_bytes(int L) {
   return 2 * sizeof(double2) * (size_t)((L + 1) & ~1) * (size_t)(((L + 1) & ~1) + 1);
 }
@@ -42,25 +44,29 @@ struct Rot {
   int p, q, on;
 };
 
+// MAXN: the largest n of the instantiation; GMEM: A and V live in `work`
+// (this frequency's slice of the workspace) instead of LDS.  Within the
+// workgroup the barriers order the global accesses as they order the LDS ones.
+template <int MAXN, bool GMEM>
 __device__ __forceinline__ void jacobi_body(const double2* __restrict__ gram,
                                             double* __restrict__ lam, double2* __restrict__ psi,
                                             int32_t* __restrict__ info, int L, int max_sweeps,
-                                            int k) {
+                                            int k, double2* __restrict__ work) {
   extern __shared__ double2 eig_dyn[];
-  __shared__ Rot rot[EIG_MAXN / 2];
+  __shared__ Rot rot[MAXN / 2];
   __shared__ int any_rot;
   __shared__ int nonfinite;
-  __shared__ double lsh[EIG_MAXN];
-  __shared__ int rank_of[EIG_MAXN];
-  __shared__ double2 phase[EIG_MAXN];
-  __shared__ int pivot[EIG_MAXN];
+  __shared__ double lsh[MAXN];
+  __shared__ int rank_of[MAXN];
+  __shared__ double2 phase[MAXN];
+  __shared__ int pivot[MAXN];
 
   const int tid = threadIdx.x;
   const int n = (L + 1) & ~1;             // even, includes a dummy index when L is odd
   const int half = n / 2;
   const int EIG_LD = n + 1;
-  double2* A = eig_dyn;                   // [n][n + 1]
-  double2* V = eig_dyn + n * EIG_LD;      // [n][n + 1]
+  double2* A = GMEM ? work + (int64_t)k * 2 * n * EIG_LD : eig_dyn;   // [n][n + 1]
+  double2* V = A + n * EIG_LD;                                          // [n][n + 1]
   const double2* G = gram + (int64_t)k * L * L;
 
   if (tid == 0) nonfinite = 0;
@@ -250,15 +256,25 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const double2* __restrict__ 
                                                     double2* __restrict__ psi,
                                                     int32_t* __restrict__ info, int L,
                                                     int max_sweeps) {
-  jacobi_body(gram, lam, psi, info, L, max_sweeps, blockIdx.x);
+  jacobi_body<EIG_MAXN, false>(gram, lam, psi, info, L, max_sweeps, blockIdx.x, nullptr);
+}
+
+// L > 64: A and V of frequency k in work [K][2][n][n + 1] complex.
+__global__ __launch_bounds__(1024) void jacobi_big_kernel(const double2* __restrict__ gram,
+                                                          double* __restrict__ lam,
+                                                          double2* __restrict__ psi,
+                                                          int32_t* __restrict__ info, int L,
+                                                          int max_sweeps, double2* __restrict__ work) {
+  jacobi_body<EIG_BIGN, true>(gram, lam, psi, info, L, max_sweeps, blockIdx.x, work);
 }
 
 template <int NT>
 __global__ __launch_bounds__(NT) void jacobi_batch_kernel(const EigItem* __restrict__ items, int n,
                                                           int max_sweeps) {
   const EigItem& it = items[find_item(items, n, (int)blockIdx.x)];
-  jacobi_body(static_cast<const double2*>(it.gram), it.lam, static_cast<double2*>(it.psi), it.info,
-              it.L, max_sweeps, (int)blockIdx.x - it.start);
+  jacobi_body<EIG_MAXN, false>(static_cast<const double2*>(it.gram), it.lam,
+                               static_cast<double2*>(it.psi), it.info, it.L, max_sweeps,
+                               (int)blockIdx.x - it.start, nullptr);
 }
 
 constexpr int EIG_SMALL_NT = 256, EIG_LARGE_NT = 1024;
@@ -288,13 +304,23 @@ static hipError_t eig_attr() {
   return result;
 }
 
+size_t eig_workspace(const Plan& p) {
+  return p.nblocks > EIG_MAXN ? (size_t)p.nfreq * eig_lds_bytes((int)p.nblocks) : 0;
+}
+
 spod_status launch_eig(const Plan& p, const void* gram, double* lam, void* psi, int32_t* info,
                        void* ws, hipStream_t st) {
-  (void)ws;
-  if (p.nblocks > EIG_MAXN) return fail(SPOD_ERR_UNSUPPORTED, "nblocks > 64");
+  if (p.nblocks > EIG_BIGN) return fail(SPOD_ERR_UNSUPPORTED, "nblocks > 160");
+  const int L = (int)p.nblocks;
+  if (L > EIG_MAXN) {
+    hipLaunchKernelGGL(jacobi_big_kernel, dim3((unsigned)p.nfreq), dim3(1024), 0, st,
+                       static_cast<const double2*>(gram), lam, static_cast<double2*>(psi), info, L,
+                       p.max_sweeps, static_cast<double2*>(ws));
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SPOD_OK : hip_fail(e, "jacobi_big_kernel");
+  }
   hipError_t ea = eig_attr();
   if (ea != hipSuccess) return hip_fail(ea, "hipFuncSetAttribute");
-  const int L = (int)p.nblocks;
   if (eig_threads(L) == EIG_LARGE_NT)
     hipLaunchKernelGGL(jacobi_kernel<EIG_LARGE_NT>, dim3((unsigned)p.nfreq), dim3(EIG_LARGE_NT),
                        eig_lds_bytes(L), st, static_cast<const double2*>(gram), lam,

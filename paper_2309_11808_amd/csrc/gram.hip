@@ -188,9 +188,11 @@ __device__ __forceinline__ void gram_load_any(Raw<MODE, NT>& r, const typename G
 // rows, same column) fall in distinct banks.  Each wave issues exactly NI load
 // instructions per chunk (slots past the real rows re-read a valid row into a
 // spare LDS slot), so the wait for a chunk is the constant vmcnt(NI).
-template <int NT>
+template <int NT, int CHUNKB = 1024>
 struct GramStage {
-  static constexpr int RSB = 1040;                  // LDS row stride (bytes)
+  // LDS row stride (bytes): 1040 for chunks of 1 KB (or a 656-byte packed
+  // superblock), the chunk plus 16 bytes for the short chunks of L > 64
+  static constexpr int RSB = CHUNKB >= 512 ? 1040 : CHUNKB + 16;
   static constexpr int ROWS = 16 * NT + 2;          // tile rows, weight row, spare row
   static constexpr int BYTES = ROWS * RSB;          // one stage
   static constexpr int NI = (16 * NT + 1 + 3) / 4;  // load instructions per wave per chunk
@@ -199,17 +201,24 @@ struct GramStage {
 // CHUNKB: bytes of one row per chunk (1024, or one 656-byte packed
 // superblock: lanes past it re-read the superblock's first 16 bytes into the
 // unused end of the row's slot, so no load leaves the row).
-template <int NT, int CHUNKB = 1024>
+// Short chunks (CHUNKB < 512, L > 64): one row per instruction, only the
+// lanes that cover the row load (so the rows can be padded in LDS), and WB
+// bytes of weights; rows of tiles outside `need` re-read the chunk's first row
+// (a cached duplicate) so that every wave still issues NI loads per chunk.
+template <int NT, int CHUNKB = 1024, int WB = 512>
 __device__ __forceinline__ void stage_issue(char* stage, const char* __restrict__ qrows, int64_t rowb,
-                                            const char* __restrict__ wrow, int L, int wave, int lane) {
-  using GS = GramStage<NT>;
+                                            const char* __restrict__ wrow, int L, int wave, int lane,
+                                            unsigned need = ~0u) {
+  using GS = GramStage<NT, CHUNKB>;
+  constexpr bool SHORT = CHUNKB < 512;
 #pragma unroll
   for (int i = 0; i < GS::NI; ++i) {
     const int slot = wave + 4 * i;                   // 0 .. 16 NT  (16 NT = weights)
     const char* src;
     int dst;
     if (slot < 16 * NT) {
-      const int row = slot < L ? slot : L - 1;        // padded rows re-read a real row
+      int row = slot < L ? slot : L - 1;              // padded rows re-read a real row
+      if (!((need >> (slot >> 4)) & 1u)) row = 0;     // tile not needed here
       src = qrows + (int64_t)row * rowb;
       dst = slot;
     } else if (slot == 16 * NT) {
@@ -219,11 +228,19 @@ __device__ __forceinline__ void stage_issue(char* stage, const char* __restrict_
       src = wrow;                                     // spare slot: harmless duplicate
       dst = 16 * NT + 1;
     }
-    // the weight row holds 512 bytes: lanes 32..63 re-read the first half
-    const int off = (slot >= 16 * NT) ? 16 * (lane & 31) : (16 * lane < CHUNKB ? 16 * lane : 0);
-    __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)(src + off),
-                                     (void __attribute__((address_space(3)))*)(stage + dst * GS::RSB),
-                                     16, 0, 0);
+    if constexpr (SHORT) {
+      const int nl = slot >= 16 * NT ? WB / 16 : CHUNKB / 16;
+      if (lane < nl)
+        __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)(src + 16 * lane),
+                                         (void __attribute__((address_space(3)))*)(stage + dst * GS::RSB),
+                                         16, 0, 0);
+    } else {
+      // the weight row holds 512 bytes: lanes 32..63 re-read the first half
+      const int off = (slot >= 16 * NT) ? 16 * (lane & 31) : (16 * lane < CHUNKB ? 16 * lane : 0);
+      __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)(src + off),
+                                       (void __attribute__((address_space(3)))*)(stage + dst * GS::RSB),
+                                       16, 0, 0);
+    }
   }
 }
 
@@ -236,25 +253,35 @@ __device__ __forceinline__ void stage_issue(char* stage, const char* __restrict_
 // PK: qhat in the packed 20-bit layout (one chunk = one superblock of 128
 // degrees of freedom per row; ldq = bytes of a packed row; the rows are padded
 // with zeros to whole superblocks and the weights to a multiple of 128).
-template <int MODE, int NT, int G, int WPG, bool PK = false>
+// BIG (L > 64): one contraction step per chunk (GDOF degrees of freedom), one
+// wave per pair group (WPG = 1), PGB pairs per group, the groups of a frequency
+// spread over several workgroups (grid z); only the tiles in `need` (the
+// workgroup's groups) are read.  `write`: false for a wave with no group of its
+// own (it repeats another group's work for the barriers and stores nothing).
+constexpr int PGB = 6;
+
+template <int MODE, int NT, int G, int WPG, bool PK = false, bool BIG = false>
 __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __restrict__ qhat,
                                           const typename GramCfg<MODE>::T* __restrict__ sqrtw,
                                           double* __restrict__ part, int64_t M,
                                           int64_t ldq, int L, int S, bool vec, double* red, char* lds,
-                                          int s, int k) {
+                                          int s, int k, unsigned need = ~0u, bool write = true) {
   using Cfg = GramCfg<MODE>;
   using T = typename Cfg::T;
   using C = typename Cfg::C;
   using ACC = typename Cfg::ACC;
-  using GS = GramStage<NT>;
   constexpr int DPL = Cfg::DPL;
   constexpr int GDOF = 4 * DPL;                             // degrees of freedom per group
-  constexpr int CD = 1024 / (int)sizeof(C);                 // degrees of freedom per chunk
+  constexpr int CD = BIG ? GDOF : 1024 / (int)sizeof(C);    // degrees of freedom per chunk
+  constexpr int CHUNKB = PK ? PK_SB_BYTES : CD * (int)sizeof(C);
+  using GS = GramStage<NT, CHUNKB>;
   constexpr int GPW = CD / GDOF / WPG;                      // DOF groups per wave per chunk
   constexpr int D = 16 * NT;
   constexpr int NP = NT * (NT + 1) / 2;
-  constexpr int P0 = G * PG;
-  constexpr int NPG = (NP - P0) < PG ? (NP - P0) : PG;
+  constexpr int PGX = BIG ? PGB : PG;                       // pairs per group
+  constexpr int P0 = G * PGX;
+  constexpr int NPG = (NP - P0) < PGX ? (NP - P0) : PGX;
+  static_assert(!BIG || (WPG == 1 && !PK), "L > 64: one wave per group, complex blocks");
   constexpr unsigned NEED = tiles_needed<NT, P0, NPG>();
   constexpr bool SPLIT = MODE == G_BF16X4 || MODE == G_FP16X4;
   static_assert(CD * (int)sizeof(T) <= 512, "weights of a chunk must fit the 512-byte weight row");
@@ -399,20 +426,22 @@ __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __res
     }
   };
 
-  constexpr int CHUNKB = PK ? PK_SB_BYTES : 1024;
+  constexpr int WB = BIG ? CD * (int)sizeof(T) : 512;        // weight bytes per chunk
   const char* qb = PK ? reinterpret_cast<const char*>(qhat) + (int64_t)k * L * ldq
                       : reinterpret_cast<const char*>(qk);
   const char* wb = reinterpret_cast<const char*>(sqrtw);
   const int64_t rowb = PK ? ldq : ldq * (int64_t)sizeof(C);
   if (c0 < c1)
-    stage_issue<NT, CHUNKB>(lds, qb + c0 * CHUNKB, rowb, wb + c0 * CD * (int64_t)sizeof(T), L, wave, lane);
+    stage_issue<NT, CHUNKB, WB>(lds, qb + c0 * CHUNKB, rowb, wb + c0 * CD * (int64_t)sizeof(T), L,
+                                wave, lane, need);
 #pragma unroll 1
   for (int64_t c = c0; c < c1; ++c) {
     char* cur = lds + ((c - c0) & 1) * GS::BYTES;
     char* nxt = lds + (((c - c0) & 1) ^ 1) * GS::BYTES;
     // prefetch the next chunk (the last one re-reads itself into the free stage)
     const int64_t cn = c + 1 < c1 ? c + 1 : c;
-    stage_issue<NT, CHUNKB>(nxt, qb + cn * CHUNKB, rowb, wb + cn * CD * (int64_t)sizeof(T), L, wave, lane);
+    stage_issue<NT, CHUNKB, WB>(nxt, qb + cn * CHUNKB, rowb, wb + cn * CD * (int64_t)sizeof(T), L,
+                                wave, lane, need);
     // wait for this wave's loads of chunk c (the NI of chunk c+1 stay in
     // flight), then for everybody's.  A bare s_barrier: __syncthreads() would
     // add a release fence that drains the prefetch as well.
@@ -513,6 +542,31 @@ __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __res
       }
   }
 
+  // element (lane, v) of a 16x16 result tile sits in column lane%16 and row
+  // 4*(lane/16)+v for the FP32-accumulating instructions, but row lane/16+4*v
+  // for v_mfma_f64_16x16x4f64.  Partials are stored as complex [D][D].
+  double2* out = reinterpret_cast<double2*>(part) + ((int64_t)k * S + s) * D * D;
+  if constexpr (WPG == 1) {
+    // the wave is its group's only contributor: store from the registers
+    __builtin_amdgcn_s_waitcnt(0);
+    if (write) {
+#pragma unroll
+      for (int i = 0; i < NPG; ++i) {
+        int a = 0, rem = P0 + i;
+        while (rem >= NT - a) {
+          rem -= NT - a;
+          ++a;
+        }
+        const int b = a + rem;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = (MODE == G_F64) ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v;
+          out[(16 * a + r) * D + 16 * b + (lane & 15)] = make_double2(sR[i][v], sI[i][v]);
+        }
+      }
+    }
+    return;
+  }
   // the stages are reused for the reduction: drain the last (re-read)
   // prefetch of every wave first
   __builtin_amdgcn_s_waitcnt(0);
@@ -535,10 +589,6 @@ __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __res
     }
     __syncthreads();
   }
-  // element (lane, v) of a 16x16 result tile sits in column lane%16 and row
-  // 4*(lane/16)+v for the FP32-accumulating instructions, but row lane/16+4*v
-  // for v_mfma_f64_16x16x4f64.  Partials are stored as complex [D][D].
-  double2* out = reinterpret_cast<double2*>(part) + ((int64_t)k * S + s) * D * D;
   for (int idx = wsub * 64 + lane; idx < NPG * 4 * 64; idx += 64 * WPG) {
     const int ln = idx & 63;
     const int v = (idx >> 6) & 3;
@@ -590,6 +640,57 @@ __global__ __launch_bounds__(256, 2) void gram_kernel(const typename GramCfg<MOD
   extern __shared__ __attribute__((aligned(16))) char gram_lds[];   // 2 stages
   gram_unit<MODE, NT, PK>(qhat, static_cast<const T*>(sqrtw_v), part, M, ldq, L, S, K, vec != 0,
                           blockIdx.x, gram_lds);
+}
+
+// ---------------------------------------------------------------------------
+// L > 64: the block pairs in groups of PGB, four groups (one per wave) per
+// workgroup; work unit = (group set z, slice s, frequency k)
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int big_groups(int nt) { return (nt * (nt + 1) / 2 + PGB - 1) / PGB; }
+
+// tiles used by pair group g (pairs g PGB .. g PGB + PGB - 1 in (a, b >= a) order)
+__host__ __device__ constexpr unsigned big_need(int nt, int g) {
+  unsigned mask = 0;
+  int pi = 0;
+  for (int a = 0; a < nt; ++a)
+    for (int b = a; b < nt; ++b, ++pi)
+      if (pi >= g * PGB && pi < (g + 1) * PGB) mask |= (1u << a) | (1u << b);
+  return mask;
+}
+
+template <int MODE, int NT, int G>
+__device__ __forceinline__ void gram_big_dispatch(int g, bool write, unsigned need,
+                                                  const typename GramCfg<MODE>::C* __restrict__ qhat,
+                                                  const typename GramCfg<MODE>::T* __restrict__ sqrtw,
+                                                  double* __restrict__ part, int64_t M, int L, int S,
+                                                  bool vec, char* lds, int s, int k) {
+  if constexpr (G < big_groups(NT)) {
+    if (g == G)
+      gram_body<MODE, NT, G, 1, false, true>(qhat, sqrtw, part, M, M, L, S, vec, nullptr, lds, s, k,
+                                             need, write);
+    else
+      gram_big_dispatch<MODE, NT, G + 1>(g, write, need, qhat, sqrtw, part, M, L, S, vec, lds, s, k);
+  }
+}
+
+template <int MODE, int NT>
+__global__ __launch_bounds__(256, 1) void gram_big_kernel(const typename GramCfg<MODE>::C* __restrict__ qhat,
+                                                          const void* __restrict__ sqrtw_v,
+                                                          double* __restrict__ part, int64_t M, int L,
+                                                          int S, int K, int vec) {
+  using T = typename GramCfg<MODE>::T;
+  extern __shared__ __attribute__((aligned(16))) char gram_lds[];
+  constexpr int NG = big_groups(NT);
+  const int64_t local = blockIdx.x;
+  const int z = (int)(local / ((int64_t)S * K));
+  const int64_t rem = local - (int64_t)z * S * K;
+  const int s = (int)(rem % S), k = (int)(rem / S);
+  const int g = 4 * z + (int)(threadIdx.x >> 6);
+  const bool write = g < NG;
+  unsigned need = 0;
+  for (int i = 4 * z; i < 4 * z + 4 && i < NG; ++i) need |= big_need(NT, i);
+  gram_big_dispatch<MODE, NT, 0>(write ? g : NG - 1, write, need, qhat, static_cast<const T*>(sqrtw_v),
+                                 part, M, L, S, vec != 0, gram_lds, s, k);
 }
 
 // Grouped launch over a batch: workgroup b -> item, then the item's local
@@ -676,23 +777,54 @@ static void launch_gram_nti(const Plan& p, const void* qhat, const void* sqrtw, 
                      (int)p.nblocks, p.gram_split, (int)p.nfreq, (int)vec);
 }
 
+template <int MODE, int NTI>
+static spod_status launch_gram_big(const Plan& p, const void* qhat, const void* sqrtw, double* part,
+                                   hipStream_t st) {
+  using C = typename GramCfg<MODE>::C;
+  if constexpr (MODE == G_F32) {
+    return fail(SPOD_ERR_UNSUPPORTED, "nblocks > 64 needs the fp64, bf16x4 or fp16x4 form");
+  } else {
+    if (p.qhat_packed) return fail(SPOD_ERR_UNSUPPORTED, "nblocks > 64 needs complex Fourier blocks");
+    constexpr int CHUNKB = 4 * GramCfg<MODE>::DPL * (int)sizeof(C);
+    const int Z = (big_groups(NTI) + 3) / 4;
+    dim3 grid((unsigned)((int64_t)p.gram_split * p.nfreq * Z));
+    const bool vec = ((uintptr_t)qhat % 16 == 0) && (sizeof(C) == 16 || p.M % 2 == 0) &&
+                     ((uintptr_t)sqrtw % 16 == 0);
+    const size_t lds = 2 * (size_t)GramStage<NTI, CHUNKB>::BYTES;
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gram_big_kernel<MODE, NTI>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((gram_big_kernel<MODE, NTI>), grid, dim3(256), lds, st,
+                       static_cast<const C*>(qhat), sqrtw, part, (int64_t)p.M, (int)p.nblocks,
+                       p.gram_split, (int)p.nfreq, (int)vec);
+    return SPOD_OK;
+  }
+}
+
 template <int MODE>
 static spod_status launch_gram_mode(const Plan& p, const void* qhat, const void* sqrtw,
                                     double* part, hipStream_t st) {
+  spod_status r = SPOD_OK;
   switch (p.gram_dim / 16) {
     case 1: launch_gram_nti<MODE, 1>(p, qhat, sqrtw, part, st); break;
     case 2: launch_gram_nti<MODE, 2>(p, qhat, sqrtw, part, st); break;
     case 3: launch_gram_nti<MODE, 3>(p, qhat, sqrtw, part, st); break;
     case 4: launch_gram_nti<MODE, 4>(p, qhat, sqrtw, part, st); break;
-    default: return fail(SPOD_ERR_UNSUPPORTED, "nblocks > 64");
+    case 5: r = launch_gram_big<MODE, 5>(p, qhat, sqrtw, part, st); break;
+    case 6: r = launch_gram_big<MODE, 6>(p, qhat, sqrtw, part, st); break;
+    case 7: r = launch_gram_big<MODE, 7>(p, qhat, sqrtw, part, st); break;
+    case 8: r = launch_gram_big<MODE, 8>(p, qhat, sqrtw, part, st); break;
+    case 9: r = launch_gram_big<MODE, 9>(p, qhat, sqrtw, part, st); break;
+    case 10: r = launch_gram_big<MODE, 10>(p, qhat, sqrtw, part, st); break;
+    default: return fail(SPOD_ERR_UNSUPPORTED, "nblocks > 160");
   }
+  if (r != SPOD_OK) return r;
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SPOD_OK : hip_fail(e, "gram_kernel");
 }
 
 spod_status launch_csd(const Plan& p, const void* qhat, void* gram, void* ws, hipStream_t st,
                        bool accumulate) {
-  if (p.nblocks > 64) return fail(SPOD_ERR_UNSUPPORTED, "nblocks > 64");
+  if (p.nblocks > SPOD_MAX_NBLOCKS) return fail(SPOD_ERR_UNSUPPORTED, "nblocks > 160");
   double* part = static_cast<double*>(ws);
   const size_t D = (size_t)p.gram_dim;
   spod_status s;

@@ -34,6 +34,8 @@ int general_odd_kpt(int r, int nb);
 // G = ceil(h / kpt).
 int general_odd_entries(int r, int kpt);
 constexpr int GENERAL_MAX_KPT = 6;
+constexpr int SPOD_MAX_NBLOCKS = 160;          // Gram, eigensolve and modes (backward, batch: 64)
+constexpr int SPOD_SMALL_NBLOCKS = 64;         // above this: the L > 64 kernels
 constexpr int SPOD_GENERAL_MAX_NFFT = 20480;   // complex64 blocks of one transform fill 160 KiB LDS
 
 struct Plan {
@@ -181,6 +183,7 @@ spod_status launch_reconstruct(const Plan& p, const void* phi, const CoeffSel& c
 size_t fft_workspace(const Plan& p);  // only used when the caller passes no mean buffer
 size_t csd_workspace(const Plan& p);
 size_t backward_workspace(const Plan& p);
+size_t eig_workspace(const Plan& p);  // A and V of every frequency for L > 64
 
 // --------------------------------------------------------------------------
 // grouped (batched) launches: one launch covers the workgroups of several

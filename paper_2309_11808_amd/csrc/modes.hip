@@ -14,7 +14,8 @@
 
 namespace spod {
 
-constexpr int MODES_MAXL = 64;
+constexpr int MODES_MAXL = SPOD_MAX_NBLOCKS;
+constexpr size_t MODES_MAX_TABLE = 64 * 1024;   // LDS of the coefficient table
 constexpr int MODES_MAXM = 256;   // largest n_modes (n_modes <= L)
 constexpr int MODES_GROUP = 8;
 
@@ -361,8 +362,10 @@ __global__ __launch_bounds__(256) void modes_batch_kernel(const ModesItem* __res
 spod_status launch_modes(const Plan& p, const void* qhat, const double* lam, const void* psi,
                          int n_modes, void* phi, int32_t* n_valid, void* ws, hipStream_t st) {
   (void)ws;
-  if (p.nblocks > MODES_MAXL) return fail(SPOD_ERR_UNSUPPORTED, "nblocks > 64");
+  if (p.nblocks > MODES_MAXL) return fail(SPOD_ERR_UNSUPPORTED, "nblocks > 160");
   const size_t lds = (is_complex128(p) ? 16 : 8) * (size_t)p.nblocks * (size_t)n_modes;
+  if (lds > MODES_MAX_TABLE)
+    return fail(SPOD_ERR_UNSUPPORTED, "nblocks * n_modes coefficients exceed 64 KiB of LDS");
   if (p.qhat_packed) {
     dim3 grid((unsigned)(((p.M + 3) / 4 + 255) / 256), (unsigned)p.nfreq);
     hipLaunchKernelGGL(modes_pk_kernel, grid, dim3(256), lds, st, static_cast<const char*>(qhat),

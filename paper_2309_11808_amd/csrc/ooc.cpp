@@ -396,7 +396,7 @@ spod_status spod_ooc_create(spod_plan plan, spod_dtype dtype, int64_t chunk_rows
     if (n_modes < 1 || n_modes > p->nblocks)
       return fail(SPOD_ERR_INVALID_ARG, "n_modes must be in [1, nblocks]");
     if (resident < 0) return fail(SPOD_ERR_INVALID_ARG, "resident must be >= 0");
-    if (p->nblocks > 64) return fail(SPOD_ERR_UNSUPPORTED, "nblocks > 64");
+    if (p->nblocks > SPOD_MAX_NBLOCKS) return fail(SPOD_ERR_UNSUPPORTED, "nblocks > 160");
     int cur = -1;
     hipError_t e = hipGetDevice(&cur);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");

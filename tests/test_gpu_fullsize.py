@@ -261,3 +261,41 @@ def test_era_field_coefficients_and_reconstruction(era, era_modes):
     del a, rec, phi
     plan.close()
     torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------------------
+# the paper's jet analysis block structure: N_f = 256, 50% overlap, L = 155
+# blocks, on the jet-like field (256 x 128 x 3, N_t = 19,968 float32)
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def jet155():
+    p = fields.jet_like(seed=2, nt=19968, device="cuda", dtype=torch.float32)
+    assert fields.block_count_of(p.nt, p.nfft, p.noverlap) == 155
+    q_host = p.q.cpu().numpy()
+    bins = [0, 10, 20, 35, 50, 77, 100, 128]
+    t = time.perf_counter()
+    ref = O.spod_chunked(q_host, p.nfft, p.noverlap, weights=p.weights, n_modes=5,
+                         chunk=8192, bins=bins, want_modes=False)
+    print(f"[jet155 fixture] oracle Gram and Jacobi at 8 bins: {time.perf_counter() - t:.0f} s",
+          flush=True)
+    del q_host
+    return p, bins, ref
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp16x4"])
+def test_jet_155_blocks_full_size(jet155, precision):
+    p, bins, ref = jet155
+    plan = _plan(p, precision)
+    assert plan.nblocks == 155
+    out = plan.forward(p.q, n_modes=5)
+    torch.cuda.synchronize()
+    lam = out["lam"].index_select(0, torch.as_tensor(bins, device="cuda")).cpu().numpy()
+    if precision == "fp64":
+        err = PT.check_eig(lam, ref["lam"], rtol=1e-10, n=5)
+    else:
+        err = PT.check_eig_mixed(lam, ref["lam"], n=5, rtol=1e-4)
+    assert int(out["info"].min()) > 0
+    print(f"jet L = 155 {precision}: leading-5 eigenvalue rel err {err:.2e} at 8 bins", flush=True)
+    del out
+    plan.close()
+    torch.cuda.empty_cache()

@@ -101,8 +101,11 @@ GRAM_TOL = {"fp64": 1e-13, "fp32": 3e-6, "bf16x4": 3e-5, "fp16x4": 2e-6}
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x4", "fp16x4"])
 @pytest.mark.parametrize("L,M", [(2, 1), (7, 300), (15, 1024), (16, 77), (31, 5000), (32, 2049),
-                                 (33, 130), (47, 700), (63, 257), (64, 64)])
+                                 (33, 130), (47, 700), (63, 257), (64, 64), (65, 500), (80, 3001),
+                                 (100, 257), (155, 2000), (160, 64)])
 def test_csd_matches_oracle(prec, L, M):
+    if L > 64 and prec == "fp32":
+        pytest.skip("the FP32 form is limited to 64 blocks (test_large_nblocks_fp32_is_refused)")
     nfft, nov = 16, 8
     nt = (L - 1) * 8 + 16
     p = _rand_problem(M, nt, nfft, nov, seed=L * 7 + M)
@@ -145,9 +148,13 @@ def _herm_batch(L, K, seed, kind):
     return 0.5 * (A + np.conj(np.transpose(A, (0, 2, 1))))
 
 
-@pytest.mark.parametrize("L", [2, 3, 8, 15, 31, 32, 33, 63, 64])
+@pytest.mark.parametrize("L", [2, 3, 8, 15, 31, 32, 33, 63, 64, 65, 96, 155, 160])
 @pytest.mark.parametrize("kind", ["psd", "lowrank", "graded", "degenerate", "diagonal", "zero"])
 def test_eig_matches_oracle(L, kind):
+    """Up to 64 blocks against the oracle's Jacobi; above (A and V in the
+    workspace) against LAPACK's eigh with the oracle's ordering and phase
+    convention (the oracle's Python Jacobi takes about 20 s per batch at
+    L = 160; test_many_blocks_end_to_end runs it at L = 155)."""
     nfft = 16
     nt = (L - 1) * 8 + 16
     p = _rand_problem(4, nt, nfft, 8, seed=1)
@@ -157,7 +164,10 @@ def test_eig_matches_oracle(L, kind):
     A = _herm_batch(L, K, seed=L, kind=kind)
     lam, psi, info = plan.eig(_dev(A))
     torch.cuda.synchronize()
-    lo, Vo, sw = O.jacobi_eigh(A)
+    if L <= 64:
+        lo, Vo, sw = O.jacobi_eigh(A)
+    else:
+        lo, Vo = np.linalg.eigh(A)
     lo, psio = O.sort_and_phase(lo, Vo)
     info = info.cpu().numpy()
     assert (info > 0).all(), info
@@ -492,3 +502,41 @@ def test_modes_mfma_matches_oracle(L, M, n_modes):
     assert (np.abs(g - phv.cpu().numpy()) / scale).max() < 2e-6
     plan.close()
     vplan.close()
+
+
+def test_large_nblocks_fp32_is_refused():
+    from paper_2309_11808_amd import SpodError, _native as N
+    p = _rand_problem(100, 64 * 8 + 16, 16, 8, seed=3)
+    plan = _plan(p, "fp32")
+    assert plan.nblocks == 65
+    qh = torch.zeros(plan.nfreq, 65, 100, dtype=torch.complex64, device="cuda")
+    with pytest.raises(SpodError) as ei:
+        plan.csd(qh)
+    assert ei.value.status == N.SPOD_ERR_UNSUPPORTED
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp16x4", "bf16x4"])
+def test_many_blocks_end_to_end(prec):
+    """155 blocks (the paper's jet analysis uses N_f = 256 at 50% overlap and
+    L = 155), here with N_f = 32 so the oracle's Jacobi stays fast: the
+    L > 64 Gram, eigensolver (A and V in the workspace) and modes."""
+    nfft, nov, L = 32, 16, 155
+    nt = (L - 1) * 16 + 32 + 5
+    p = _rand_problem(1500, nt, nfft, nov, seed=155,
+                      dtype=torch.float64 if prec == "fp64" else torch.float32, offset=2.0)
+    plan = _plan(p, prec)
+    assert plan.nblocks == L
+    out = plan.forward(p.q.cuda(), n_modes=8)
+    torch.cuda.synchronize()
+    eps = 1e-12 if prec == "fp64" else 1e-6
+    o = O.spod(p.q.numpy(), nfft, nov, weights=p.weights, n_modes=8, eps=eps)
+    assert int(out["info"].min()) > 0
+    if prec == "fp64":
+        err = PT.check_eig(out["lam"], o["lam"], rtol=1e-10)
+        PT.check_modes(out["phi"], o["phi"], o["lam"], p.weights, o["n_valid"], 1e-8, 1e-6, 1e-6)
+    else:
+        err = PT.check_eig_mixed(out["lam"], o["lam"], n=8)
+        PT.check_modes(out["phi"], o["phi"], o["lam"], p.weights, o["n_valid"], 1e-3, 1e-2, 1e-3)
+    print(f"L = 155 {prec}: eigenvalue rel err {err:.2e}")
+    plan.close()
