@@ -13,7 +13,8 @@
 // separated with X_a[k] = (Z[k] + conj Z[N-k]) / 2 and
 // X_b[k] = (Z[k] - conj Z[N-k]) / (2i) while the spectra are read back from
 // LDS in [k][m] order, so every frequency row is written as one contiguous run
-// of T complex values.
+// of T complex values.  The factor 1/2 and the DFT scale kappa ride on the
+// window.
 #include <hip/hip_runtime.h>
 
 #include "fft_core.h"
@@ -109,8 +110,11 @@ __device__ __forceinline__ void blocks_fft_body(
   const int64_t m0 = tile * T;
   const int64_t ma = m0 + 2 * f, mb_ = ma + 1;
   const bool va = ma < M, vb = mb_ < M;
-  const TIN* ra = q + (va ? ma : 0) * nt;
-  const TIN* rb = q + (vb ? mb_ : 0) * nt;
+  // a row past M reads a real row instead (row a of its pair, else the last
+  // row): its transform is never stored, and it cannot carry another row's
+  // NaN or infinity into a stored spectrum of its pair
+  const TIN* ra = q + (va ? ma : M - 1) * nt;
+  const TIN* rb = q + (vb ? mb_ : (va ? ma : M - 1)) * nt;
   C* buf = lds + f * LDP;
   // two adjacent complex values per 16-byte aligned store (complex64 needs an
   // even row stride ldq)
@@ -118,9 +122,11 @@ __device__ __forceinline__ void blocks_fft_body(
   if (sel)
     for (int i = tid; i < nsel; i += NTH) ksel[i] = sel[i];
 
+  // the window carries kappa / 2 (the DFT scale and the 1/2 of the
+  // two-for-one separation), so the separated spectra need no scaling
   TC w[8];
 #pragma unroll
-  for (int r = 0; r < 8; ++r) w[r] = (TC)window[j + r * P];
+  for (int r = 0; r < 8; ++r) w[r] = (TC)(window[j + r * P] * (0.5 * (double)kappa));
   const C* twp = tw;
   if constexpr (TWL) {
     for (int i = tid; i < NF; i += NTH) twl[i] = tw[i];
@@ -134,8 +140,8 @@ __device__ __forceinline__ void blocks_fft_body(
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     const int64_t t = (int64_t)l0 * step + j + r * P;
-    xa[r] = va ? ra[t] : (TIN)0;
-    xb[r] = vb ? rb[t] : (TIN)0;
+    xa[r] = ra[t];
+    xb[r] = rb[t];
   }
   double mua, mub;
   double sa = 0.0, sb = 0.0;             // FUSED: sums of (x - mu0) over this lane's samples
@@ -148,6 +154,13 @@ __device__ __forceinline__ void blocks_fft_body(
     }
     mua = group_sum<P>(pa) / NF;
     mub = group_sum<P>(pb) / NF;
+    if constexpr (sizeof(TC) == 4 && sizeof(TIN) == 4) {
+      // mu0 is any constant close to the mean: rounded to float, x - mu0 is
+      // a single float subtraction with the same (correctly rounded) result
+      // as the FP64 difference rounded to float
+      mua = (double)(float)mua;
+      mub = (double)(float)mub;
+    }
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       sa += (double)xa[r] - mua;
@@ -174,13 +187,20 @@ __device__ __forceinline__ void blocks_fft_body(
     C v[8];
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
-      const TC a = (TC)((double)xa[r] - mua);
-      const TC b = (TC)((double)xb[r] - mub);
+      TC a, b;
+      if constexpr (FUSED && sizeof(TC) == 4 && sizeof(TIN) == 4) {
+        a = xa[r] - (float)mua;
+        b = xb[r] - (float)mub;
+      } else {
+        a = (TC)((double)xa[r] - mua);
+        b = (TC)((double)xb[r] - mub);
+      }
       v[r] = C{a * w[r], b * w[r]};
     }
     stockham<NF, 1>(v, buf, j, twp);
 #pragma unroll
     for (int r = 0; r < 8; ++r) buf[pad8(j + r * P)] = v[r];
+    if (j == 0) buf[pad8(NF)] = v[0];      // Z[N] = Z[0]: the partner of k = 0 is pad8(N - 0)
     __syncthreads();
 
     // take in the prefetched samples of block l+1 now, before this block's
@@ -195,11 +215,16 @@ __device__ __forceinline__ void blocks_fft_body(
         xa[r] = xa[r + NEWR];
         xb[r] = xb[r + NEWR];
       } else {
-        xa[r] = va ? na[r] : (TIN)0;
-        xb[r] = vb ? nb[r] : (TIN)0;
-        if constexpr (FUSED) {
-          sa += more ? (double)xa[r] - mua : 0.0;
-          sb += more ? (double)xb[r] - mub : 0.0;
+        xa[r] = na[r];
+        xb[r] = nb[r];
+      }
+    }
+    if constexpr (FUSED) {
+      if (more) {            // uniform: the last block's re-read samples are not new
+#pragma unroll
+        for (int r = 8 - NEWR; r < 8; ++r) {
+          sa += (double)xa[r] - mua;
+          sb += (double)xb[r] - mub;
         }
       }
     }
@@ -215,7 +240,6 @@ __device__ __forceinline__ void blocks_fft_body(
     // adjacent degrees of freedom are written with one 16-byte streaming store
     // (or, packed, as their 20-bit mantissas: 8 consecutive threads form a
     // group of 16 degrees of freedom and share its exponent).
-    const TC sc = (TC)0.5 * kappa;
     if constexpr (PACK) {
       // one thread per quarter group (two pairs, 4 degrees of freedom); the
       // 4 quarters of a group are an aligned quad of lanes.  Degrees of
@@ -234,16 +258,38 @@ __device__ __forceinline__ void blocks_fft_body(
           const C Bc = row[pad8((NF - k) & (NF - 1))];
           const int64_t m = m0 + 4 * fq + 2 * h;
           const bool ka = m < M, kb = m + 1 < M;
-          v[4 * h] = ka ? (float)((A.x + Bc.x) * sc) : 0.0f;
-          v[4 * h + 1] = ka ? (float)((A.y - Bc.y) * sc) : 0.0f;
-          v[4 * h + 2] = kb ? (float)((A.y + Bc.y) * sc) : 0.0f;
-          v[4 * h + 3] = kb ? (float)(-((A.x - Bc.x) * sc)) : 0.0f;
+          v[4 * h] = ka ? (float)(A.x + Bc.x) : 0.0f;
+          v[4 * h + 1] = ka ? (float)(A.y - Bc.y) : 0.0f;
+          v[4 * h + 2] = kb ? (float)(A.y + Bc.y) : 0.0f;
+          v[4 * h + 3] = kb ? (float)(Bc.x - A.x) : 0.0f;
         }
         // ldq is the packed row length in bytes; tiles cover whole superblocks
         const int64_t m = m0 + 4 * fq;
         char* sb = reinterpret_cast<char*>(qhat) + ((int64_t)s * L + l) * ldq +
                    (m / PK_SB_DOFS) * PK_SB_BYTES;
         pk_store_quarter(sb, (int)((m % PK_SB_DOFS) >> 4), (int)((m & 15) >> 2), v);
+      }
+    } else if (!sel && pair_ok && m0 + T <= M) {
+      // every frequency, a whole tile with 16-byte stores: thread tid keeps
+      // its pair (tid % NPAIR) and steps over the rows s = tid / NPAIR + i SR
+      constexpr int SR = NTH / NPAIR;
+      const int f2 = tid % NPAIR;
+      const C* row = lds + f2 * LDP;
+      int s = tid / NPAIR;
+      int ia = pad8(s), ib = pad8(NF - s);
+      C* o = qhat + ((int64_t)s * L + l) * ldq + m0 + 2 * f2;
+      const int64_t ostep = (int64_t)SR * L * ldq;
+      for (; s < nsel; s += SR, o += ostep) {
+        const C A = row[ia];
+        const C Bc = row[ib];
+        store_pair(o, C{A.x + Bc.x, A.y - Bc.y}, C{A.y + Bc.y, Bc.x - A.x});
+        if constexpr (SR % 8 == 0) {         // pad8 is linear in steps of 8
+          ia += SR + SR / 8;
+          ib -= SR + SR / 8;
+        } else {
+          ia = pad8(s + SR);
+          ib = pad8(NF - s - SR);
+        }
       }
     } else {
       for (int idx = tid; idx < nsel * NPAIR; idx += NTH) {
@@ -253,9 +299,8 @@ __device__ __forceinline__ void blocks_fft_body(
         const C* row = lds + f2 * LDP;
         const C A = row[pad8(k)];
         const C Bc = row[pad8((NF - k) & (NF - 1))];
-        const C Xa = C{(A.x + Bc.x) * sc, (A.y - Bc.y) * sc};
-        const TC dx = A.x - Bc.x, dy = A.y + Bc.y;
-        const C Xb = C{dy * sc, -(dx * sc)};
+        const C Xa = C{A.x + Bc.x, A.y - Bc.y};
+        const C Xb = C{A.y + Bc.y, Bc.x - A.x};
         const int64_t m = m0 + 2 * f2;
         C* o = qhat + (int64_t)l * ldq + (int64_t)s * L * ldq + m;
         if (pair_ok && m + 1 < M) {
@@ -342,7 +387,7 @@ __global__ __launch_bounds__(NPAIR*(NF / 8)) void blocks_fft_kernel(
     const cpx_t<TC>* __restrict__ tw, cpx_t<TC>* __restrict__ qhat, int64_t M, int64_t ldq,
     int64_t nt, int step, int L, int bpw, TC kappa, MeanBins mb, const int* __restrict__ sel,
     int nsel) {
-  const int64_t tile = PACK ? xcd_tile(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+  const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
   blocks_fft_body<NF, TC, TIN, NPAIR, SHIFT, FUSED, PACK>(q, mean, window, tw, qhat, M, ldq, nt, step,
                                                           L, bpw, kappa, mb, sel, nsel, tile,
                                                           blockIdx.y);

@@ -364,7 +364,8 @@ __device__ __forceinline__ void pk_store_quarter(char* sb, int g, int c, const f
 
 // Workgroup b of n -> tile, so that each XCD (workgroups are dealt to the 8
 // XCDs in turn) takes a contiguous run of tiles: neighbouring tiles share
-// cache lines of the packed rows, which then meet in one L2.
+// cache lines of the packed rows, which then meet in one L2, and each XCD
+// writes long runs of every frequency row.
 __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t n) {
   const int64_t x = b & 7, i = b >> 3, q = n >> 3, r = n & 7;
   return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;

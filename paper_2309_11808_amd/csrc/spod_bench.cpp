@@ -15,10 +15,14 @@
 //         with chunks of 32768 rows, `reps` times with no chunk resident and
 //         `reps` times with every chunk resident (plan of `precision`, 5
 //         modes to pinned host memory).
-// path 3: HBM reference rates of plain streaming kernels with 16-byte accesses
-//         over 16 GiB in / 32 GiB out: write only, read only, copy 1:1, and
+// path 3: HBM reference rates of streaming kernels with 16-byte accesses over
+//         16 GiB in / 32 GiB out: write only, read only, copy 1:1, and
 //         read 1 : write 2 (the transform's mix: q in, twice the bytes out)
-//         as two output streams; grids of 16384 and 65536 workgroups.
+//         as two output streams; a sweep over grids (2048-65536 workgroups),
+//         accesses in flight per thread (1, 4, 8), plain or non-temporal
+//         accesses, and grid-stride or one contiguous range per workgroup;
+//         the best of three launches per configuration, then the best
+//         configuration per mix.
 // Prints the event timings.
 #include <hip/hip_runtime.h>
 
@@ -67,31 +71,86 @@ __global__ void copy_kernel(const float4* __restrict__ src, float4* __restrict__
     dst[i] = src[i];
 }
 
-__global__ void write_kernel(float4* __restrict__ o, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    o[i] = make_float4((float)i, 1.f, 2.f, 3.f);
-}
+// Streaming kernels for the HBM reference rates.  KIND 0: write 2n float4;
+// 1: read n; 2: copy n; 3: read n, write 2n as two streams o[i] and o[n + i]
+// (the transform's mix).  Each thread keeps U 16-byte accesses in flight per
+// stream; NT: non-temporal loads and stores; BLOCKED: workgroup b streams one
+// contiguous range (else a grid-stride loop over the whole array).
+typedef float v4f __attribute__((ext_vector_type(4)));
 
-__global__ void read_kernel(const float4* __restrict__ a, int64_t n, float* __restrict__ sink) {
+template <int KIND, int U, bool NT, bool BLOCKED>
+__global__ __launch_bounds__(256) void stream_kernel(const v4f* __restrict__ a,
+                                                     v4f* __restrict__ o, int64_t n,
+                                                     float* __restrict__ sink) {
+  const int64_t N = KIND == 0 ? 2 * n : n;              // units of the index space
+  const int64_t span = (int64_t)U * blockDim.x;
+  int64_t b0, b1, step;
+  if (BLOCKED) {
+    const int64_t per = (N + gridDim.x - 1) / gridDim.x;
+    const int64_t chunk = (per + span - 1) / span * span;
+    b0 = (int64_t)blockIdx.x * chunk;
+    b1 = b0 + chunk < N ? b0 + chunk : N;
+    step = span;
+  } else {
+    b0 = (int64_t)blockIdx.x * span;
+    b1 = N;
+    step = (int64_t)gridDim.x * span;
+  }
   float s = 0.f;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const float4 v = a[i];
-    s += v.x + v.y + v.z + v.w;
+  for (int64_t base = b0 + threadIdx.x; base - threadIdx.x < b1; base += step) {
+    v4f v[U];
+    if (KIND != 0) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t i = base + (int64_t)u * blockDim.x;
+        if (i < b1) v[u] = NT ? __builtin_nontemporal_load(a + i) : a[i];
+        else v[u] = v4f{0.f, 0.f, 0.f, 0.f};
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = v4f{(float)(base + u), 1.f, 2.f, 3.f};
+    }
+    if (KIND == 1) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) s += v[u].x + v[u].y + v[u].z + v[u].w;
+      continue;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = base + (int64_t)u * blockDim.x;
+      if (i >= b1) continue;
+      if (NT) __builtin_nontemporal_store(v[u], o + i);
+      else o[i] = v[u];
+      if (KIND == 3) {
+        const v4f w = v4f{v[u].y, v[u].x, v[u].w, v[u].z};
+        if (NT) __builtin_nontemporal_store(w, o + n + i);
+        else o[n + i] = w;
+      }
+    }
   }
-  if (s == 123.456f) sink[0] = s;   // keeps the loads
+  if (KIND == 1 && s == 123.456f) sink[0] = s;   // keeps the loads
 }
 
-// n float4 in, 2n float4 out as two streams: o[i] and o[n + i]
-__global__ void read1_write2_kernel(const float4* __restrict__ a, float4* __restrict__ o,
-                                    int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const float4 v = a[i];
-    o[i] = v;
-    o[n + i] = make_float4(v.y, v.x, v.w, v.z);
+template <int KIND, int U, bool NT, bool BLOCKED>
+static void launch_stream(int grid, const float4* a, float4* o, int64_t n, float* sink) {
+  hipLaunchKernelGGL((stream_kernel<KIND, U, NT, BLOCKED>), dim3(grid), dim3(256), 0, 0,
+                     reinterpret_cast<const v4f*>(a), reinterpret_cast<v4f*>(o), n, sink);
+}
+
+template <int KIND>
+static void launch_stream_cfg(int u, bool nt, bool blocked, int grid, const float4* a, float4* o,
+                              int64_t n, float* sink) {
+#define SPOD_STREAM(U_)                                                                    \
+  if (u == U_) {                                                                           \
+    if (nt && blocked) launch_stream<KIND, U_, true, true>(grid, a, o, n, sink);           \
+    if (nt && !blocked) launch_stream<KIND, U_, true, false>(grid, a, o, n, sink);         \
+    if (!nt && blocked) launch_stream<KIND, U_, false, true>(grid, a, o, n, sink);         \
+    if (!nt && !blocked) launch_stream<KIND, U_, false, false>(grid, a, o, n, sink);       \
   }
+  SPOD_STREAM(1)
+  SPOD_STREAM(4)
+  SPOD_STREAM(8)
+#undef SPOD_STREAM
 }
 
 static int run_rates() {
@@ -109,26 +168,42 @@ static int run_rates() {
   CHECK_HIP(hipEventCreate(&e1));
   const char* names[] = {"write only", "read only", "copy 1:1", "read 1 : write 2"};
   const double bytes[] = {32.0 * n, 16.0 * n, 32.0 * n, 48.0 * n};
-  for (int grid : {16384, 65536}) {
-    for (int k = 0; k < 4; ++k) {
-      float ms = 0.0f;
-      for (int r = 0; r < 3; ++r) {
-        CHECK_HIP(hipEventRecord(e0, 0));
-        if (k == 0) hipLaunchKernelGGL(write_kernel, dim3(grid), dim3(256), 0, 0, o, 2 * n);
-        if (k == 1) hipLaunchKernelGGL(read_kernel, dim3(grid), dim3(256), 0, 0, a, n, sink);
-        if (k == 2)
-          hipLaunchKernelGGL(copy_kernel, dim3(grid), dim3(256), 0, 0, a, o, n);
-        if (k == 3) hipLaunchKernelGGL(read1_write2_kernel, dim3(grid), dim3(256), 0, 0, a, o, n);
-        CHECK_HIP(hipGetLastError());
-        CHECK_HIP(hipEventRecord(e1, 0));
-        CHECK_HIP(hipEventSynchronize(e1));
-        CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
+  double best[4] = {0, 0, 0, 0};
+  char best_cfg[4][96] = {};
+  for (int k = 0; k < 4; ++k) {
+    for (int grid : {2048, 16384, 65536}) {
+      for (int u : {1, 4, 8}) {
+        for (int nt = 0; nt < 2; ++nt) {
+          for (int blocked = 0; blocked < 2; ++blocked) {
+            float ms = 0.0f, best_ms = 1e30f;
+            for (int r = 0; r < 3; ++r) {
+              CHECK_HIP(hipEventRecord(e0, 0));
+              if (k == 0) launch_stream_cfg<0>(u, nt, blocked, grid, a, o, n, sink);
+              if (k == 1) launch_stream_cfg<1>(u, nt, blocked, grid, a, o, n, sink);
+              if (k == 2) launch_stream_cfg<2>(u, nt, blocked, grid, a, o, n, sink);
+              if (k == 3) launch_stream_cfg<3>(u, nt, blocked, grid, a, o, n, sink);
+              CHECK_HIP(hipGetLastError());
+              CHECK_HIP(hipEventRecord(e1, 0));
+              CHECK_HIP(hipEventSynchronize(e1));
+              CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
+              if (ms < best_ms) best_ms = ms;
+            }
+            const double tbs = bytes[k] / (best_ms * 1e-3) / 1e12;
+            std::printf("%-18s grid %6d U %d %-9s %-11s %8.3f ms %6.2f TB/s\n", names[k], grid, u,
+                        nt ? "nt" : "plain", blocked ? "blocked" : "gridstride", best_ms, tbs);
+            std::fflush(stdout);
+            if (tbs > best[k]) {
+              best[k] = tbs;
+              std::snprintf(best_cfg[k], sizeof(best_cfg[k]), "grid %d U %d %s %s", grid, u,
+                            nt ? "nt" : "plain", blocked ? "blocked" : "gridstride");
+            }
+          }
+        }
       }
-      std::printf("grid %6d %-18s %8.3f ms %6.2f TB/s\n", grid, names[k], ms,
-                  bytes[k] / (ms * 1e-3) / 1e12);
-      std::fflush(stdout);
     }
   }
+  for (int k = 0; k < 4; ++k)
+    std::printf("best %-18s %6.2f TB/s  (%s)\n", names[k], best[k], best_cfg[k]);
   void* bufs[] = {a, o, sink};
   for (void* b : bufs) CHECK_HIP(hipFree(b));
   return 0;
