@@ -179,8 +179,8 @@ __device__ __forceinline__ void blocks_fft_body(
     const int64_t tn = (int64_t)(more ? l + 1 : l) * step + j;
 #pragma unroll
     for (int r = 8 - NEWR; r < 8; ++r) {
-      na[r] = ra[tn + r * P];
-      nb[r] = rb[tn + r * P];
+      na[r] = __builtin_nontemporal_load(ra + tn + r * P);     // q is read once
+      nb[r] = __builtin_nontemporal_load(rb + tn + r * P);
     }
     __builtin_amdgcn_sched_barrier(0);
 

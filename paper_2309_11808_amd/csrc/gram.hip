@@ -205,6 +205,8 @@ struct GramStage {
 // lanes that cover the row load (so the rows can be padded in LDS), and WB
 // bytes of weights; rows of tiles outside `need` re-read the chunk's first row
 // (a cached duplicate) so that every wave still issues NI loads per chunk.
+constexpr int CPOL_NT = 2;   // the non-temporal bit of a load's cache-policy operand (gfx950)
+
 template <int NT, int CHUNKB = 1024, int WB = 512>
 __device__ __forceinline__ void stage_issue(char* stage, const char* __restrict__ qrows, int64_t rowb,
                                             const char* __restrict__ wrow, int L, int wave, int lane,
@@ -228,18 +230,24 @@ __device__ __forceinline__ void stage_issue(char* stage, const char* __restrict_
       src = wrow;                                     // spare slot: harmless duplicate
       dst = 16 * NT + 1;
     }
+    // blocks are read once: non-temporal (cache policy NT); the weights are
+    // read again for every frequency and keep the default policy
+    typedef const void __attribute__((address_space(1)))* gptr;
+    typedef void __attribute__((address_space(3)))* lptr;
+    const lptr ldst = (lptr)(stage + dst * GS::RSB);
     if constexpr (SHORT) {
       const int nl = slot >= 16 * NT ? WB / 16 : CHUNKB / 16;
-      if (lane < nl)
-        __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)(src + 16 * lane),
-                                         (void __attribute__((address_space(3)))*)(stage + dst * GS::RSB),
-                                         16, 0, 0);
+      if (lane < nl) {
+        if (slot < 16 * NT) __builtin_amdgcn_global_load_lds((gptr)(src + 16 * lane), ldst, 16, 0, CPOL_NT);
+        else __builtin_amdgcn_global_load_lds((gptr)(src + 16 * lane), ldst, 16, 0, 0);
+      }
     } else {
       // the weight row holds 512 bytes: lanes 32..63 re-read the first half
-      const int off = (slot >= 16 * NT) ? 16 * (lane & 31) : (16 * lane < CHUNKB ? 16 * lane : 0);
-      __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)(src + off),
-                                       (void __attribute__((address_space(3)))*)(stage + dst * GS::RSB),
-                                       16, 0, 0);
+      if (slot < 16 * NT)
+        __builtin_amdgcn_global_load_lds((gptr)(src + (16 * lane < CHUNKB ? 16 * lane : 0)), ldst, 16, 0,
+                                         CPOL_NT);
+      else
+        __builtin_amdgcn_global_load_lds((gptr)(src + 16 * (lane & 31)), ldst, 16, 0, 0);
     }
   }
 }
