@@ -191,8 +191,9 @@ __device__ __forceinline__ void gram_load_any(Raw<MODE, NT>& r, const typename G
 template <int NT, int CHUNKB = 1024>
 struct GramStage {
   // LDS row stride (bytes): 1040 for chunks of 1 KB (or a 656-byte packed
-  // superblock), the chunk plus 16 bytes for the short chunks of L > 64
-  static constexpr int RSB = CHUNKB >= 512 ? 1040 : CHUNKB + 16;
+  // superblock), the chunk plus 16 bytes for chunks of 512 bytes or less
+  // (rows stay 4 banks apart)
+  static constexpr int RSB = CHUNKB > 512 ? 1040 : CHUNKB + 16;
   static constexpr int ROWS = 16 * NT + 2;          // tile rows, weight row, spare row
   static constexpr int BYTES = ROWS * RSB;          // one stage
   static constexpr int NI = (16 * NT + 1 + 3) / 4;  // load instructions per wave per chunk
@@ -201,10 +202,11 @@ struct GramStage {
 // CHUNKB: bytes of one row per chunk (1024, or one 656-byte packed
 // superblock: lanes past it re-read the superblock's first 16 bytes into the
 // unused end of the row's slot, so no load leaves the row).
-// Short chunks (CHUNKB < 512, L > 64): one row per instruction, only the
-// lanes that cover the row load (so the rows can be padded in LDS), and WB
-// bytes of weights; rows of tiles outside `need` re-read the chunk's first row
-// (a cached duplicate) so that every wave still issues NI loads per chunk.
+// Short chunks (CHUNKB <= 512: three or more 16-row tiles, or L > 64): one row
+// per instruction, only the lanes that cover the row load (so the rows can be
+// padded in LDS), and WB bytes of weights; rows of tiles outside `need`
+// re-read the chunk's first row (a cached duplicate) so that every wave still
+// issues NI loads per chunk.
 constexpr int CPOL_NT = 2;   // the non-temporal bit of a load's cache-policy operand (gfx950)
 
 template <int NT, int CHUNKB = 1024, int WB = 512>
@@ -212,7 +214,7 @@ __device__ __forceinline__ void stage_issue(char* stage, const char* __restrict_
                                             const char* __restrict__ wrow, int L, int wave, int lane,
                                             unsigned need = ~0u) {
   using GS = GramStage<NT, CHUNKB>;
-  constexpr bool SHORT = CHUNKB < 512;
+  constexpr bool SHORT = CHUNKB <= 512;
 #pragma unroll
   for (int i = 0; i < GS::NI; ++i) {
     const int slot = wave + 4 * i;                   // 0 .. 16 NT  (16 NT = weights)
@@ -268,6 +270,15 @@ __device__ __forceinline__ void stage_issue(char* stage, const char* __restrict_
 // own (it repeats another group's work for the barriers and stores nothing).
 constexpr int PGB = 6;
 
+// Bytes of one row per LDS chunk (L <= 64): 1 KB for up to two 16-row tiles;
+// 512 bytes for three or four, so that the two stages take half the LDS and
+// two workgroups share a CU (with 1 KB chunks one workgroup filled it, one
+// wavefront per SIMD); one superblock for packed blocks.
+template <int NT, bool PK>
+__host__ __device__ constexpr int gram_chunk_bytes() {
+  return PK ? PK_SB_BYTES : (NT >= 3 ? 512 : 1024);
+}
+
 template <int MODE, int NT, int G, int WPG, bool PK = false, bool BIG = false>
 __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __restrict__ qhat,
                                           const typename GramCfg<MODE>::T* __restrict__ sqrtw,
@@ -280,8 +291,8 @@ __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __res
   using ACC = typename Cfg::ACC;
   constexpr int DPL = Cfg::DPL;
   constexpr int GDOF = 4 * DPL;                             // degrees of freedom per group
-  constexpr int CD = BIG ? GDOF : 1024 / (int)sizeof(C);    // degrees of freedom per chunk
-  constexpr int CHUNKB = PK ? PK_SB_BYTES : CD * (int)sizeof(C);
+  constexpr int CD = BIG ? GDOF : (PK ? PK_SB_DOFS : gram_chunk_bytes<NT, false>() / (int)sizeof(C));
+  constexpr int CHUNKB = PK ? PK_SB_BYTES : CD * (int)sizeof(C);   // degrees of freedom, bytes per chunk
   using GS = GramStage<NT, CHUNKB>;
   constexpr int GPW = CD / GDOF / WPG;                      // DOF groups per wave per chunk
   constexpr int D = 16 * NT;
@@ -434,7 +445,7 @@ __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __res
     }
   };
 
-  constexpr int WB = BIG ? CD * (int)sizeof(T) : 512;        // weight bytes per chunk
+  constexpr int WB = CHUNKB <= 512 ? CD * (int)sizeof(T) : 512;   // weight bytes per chunk
   const char* qb = PK ? reinterpret_cast<const char*>(qhat) + (int64_t)k * L * ldq
                       : reinterpret_cast<const char*>(qk);
   const char* wb = reinterpret_cast<const char*>(sqrtw);
@@ -763,12 +774,13 @@ static void launch_gram_nti(const Plan& p, const void* qhat, const void* sqrtw, 
                             hipStream_t st) {
   using C = typename GramCfg<MODE>::C;
   dim3 grid((unsigned)((int64_t)p.gram_split * p.nfreq));
-  const size_t lds = 2 * (size_t)GramStage<NTI>::BYTES;
+  const size_t lds = 2 * (size_t)GramStage<NTI, gram_chunk_bytes<NTI, false>()>::BYTES;
   if constexpr (MODE != G_F64) {
     if (p.qhat_packed) {
+      const size_t lds_pk = 2 * (size_t)GramStage<NTI, PK_SB_BYTES>::BYTES;
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gram_kernel<MODE, NTI, true>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      hipLaunchKernelGGL((gram_kernel<MODE, NTI, true>), grid, dim3(256), lds, st,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_pk);
+      hipLaunchKernelGGL((gram_kernel<MODE, NTI, true>), grid, dim3(256), lds_pk, st,
                          static_cast<const C*>(qhat), sqrtw, part, (int64_t)p.M, pk_row_bytes(p.M),
                          (int)p.nblocks, p.gram_split, (int)p.nfreq, 1);
       return;
@@ -919,7 +931,7 @@ int64_t gram_group_wgs(int nt16, int64_t S, int64_t K) {
 
 template <int MODE, int NTI>
 static spod_status gram_group_nti(const GramItem* d, int n, int wgs, hipStream_t st) {
-  const size_t lds = 2 * (size_t)GramStage<NTI>::BYTES;
+  const size_t lds = 2 * (size_t)GramStage<NTI, gram_chunk_bytes<NTI, false>()>::BYTES;
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gram_batch_kernel<MODE, NTI>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL((gram_batch_kernel<MODE, NTI>), dim3((unsigned)wgs), dim3(256), lds, st, d, n);
