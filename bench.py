@@ -453,9 +453,31 @@ def bench_batching(steps, warmup, precision="fp16x4", n_modes=5):
     for name, grouped in (("grouped_graph", True), ("per_problem", False)):
         b = Batch(descs, precision=precision, n_modes=n_modes, grouped=grouped, graph=grouped)
         if grouped:
-            res["gram_target"] = b.autotune(qs)
+            # the autotuner's launch shapes and every candidate's time (ms),
+            # read back from a fresh JSON-lines cache
+            import tempfile
+            with tempfile.TemporaryDirectory() as td:
+                cache = os.path.join(td, "tune.jsonl")
+                res["gram_target"] = b.autotune(qs, cache_path=cache)
+                with open(cache) as f:
+                    res["autotune_ms"] = json.loads(f.readline())["ms"]
+            res["shapes"] = b.shapes()
+            # algorithmic HBM bytes of one pass, summed over the problems: q
+            # read, the blocks written once and read twice (Gram, modes), the
+            # modes written
+            csz = 16 if precision == "fp64" else 8
+            path_bytes = 0
+            for q, it in zip(qs, b.items):
+                blocks = it.nfreq * it.nblocks * it.M * csz
+                path_bytes += q.numel() * q.element_size() + 3 * blocks + \
+                    it.nfreq * it.n_modes * it.M * csz
         t = _time(lambda: b.forward(qs), steps, warmup)
         res[name] = {"ms": round(t, 3), "input_GBps": round(in_bytes / (t * 1e-3) / 1e9, 2)}
+        if grouped:
+            achieved = path_bytes / (t * 1e-3) / 1e9
+            res["path_roofline"] = {"bound": "hbm", "bytes_per_pass": int(path_bytes),
+                                    "achieved_GBps": round(achieved, 1), "peak_GBps": 8000.0,
+                                    "frac": round(achieved / 8000.0, 4)}
         b.close()
         del b
         torch.cuda.empty_cache()

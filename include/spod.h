@@ -303,9 +303,17 @@ typedef struct {
 } spod_batch_item;
 
 typedef enum {
-  SPOD_BATCH_GROUPED = 0,    /* 1 (default): grouped launches; 0: one launch per problem and step */
-  SPOD_BATCH_GRAPH = 1,      /* 1 (default): capture into a hipGraph on first use and replay      */
-  SPOD_BATCH_GRAM_TARGET = 2 /* Gram workgroups aimed at per problem (default 8192, >= 64)       */
+  SPOD_BATCH_GROUPED = 0,     /* 1 (default): grouped launches; 0: one launch per problem and step */
+  SPOD_BATCH_GRAPH = 1,       /* 1 (default): capture into a hipGraph on first use and replay      */
+  SPOD_BATCH_GRAM_TARGET = 2, /* Gram workgroups aimed at per problem (default 8192, >= 64)       */
+  SPOD_BATCH_FFT_TILE = 3,    /* DOFs per transform workgroup: 0 (default: 32 up to nfft 256,
+                                 else 16), 16 or 32; results do not depend on it              */
+  SPOD_BATCH_EIG_THREADS = 4, /* threads per eigenproblem: 0 (default: 1024 above 32 blocks,
+                                 else 256), 256 or 1024; results do not depend on it          */
+  SPOD_BATCH_PERSISTENT = 5   /* 1: persistent workgroups (as many as the device holds) take the
+                                 work units of every grouped stage from a device queue, zeroed
+                                 by a kernel at the start of each pass; 0 (default): one
+                                 workgroup per unit.  Results do not depend on it            */
 } spod_batch_option;
 
 /* Create plans for problems[0..n) on the current device (n >= 1).  Every
@@ -316,6 +324,9 @@ spod_status spod_batch_create(const spod_problem* problems, int64_t n, spod_prec
 
 /* Options, before the first forward pass or autotune. */
 spod_status spod_batch_set_option(spod_batch batch, spod_batch_option opt, int64_t value);
+
+/* The current value of an option (after spod_batch_autotune: its choice). */
+spod_status spod_batch_get_option(spod_batch batch, spod_batch_option opt, int64_t* value);
 
 /* Bytes of the device workspace (Fourier blocks, Gram partials and Grams of
  * every problem) and of the output buffer. */
@@ -336,12 +347,16 @@ spod_status spod_batch_item_info(spod_batch batch, int64_t i, spod_batch_item* i
 spod_status spod_batch_forward(spod_batch batch, const void* const* q, spod_dtype dtype,
                                void* out, void* ws, size_t ws_bytes, spod_stream stream);
 
-/* Choose SPOD_BATCH_GRAM_TARGET by timing one grouped forward pass per
- * candidate (2048, 4096, 8192, 16384 workgroups per problem) on these
- * buffers.  With cache_path != NULL the choice is read from (when its key,
- * a hash of the problem shapes and precision, is present) or appended to that
- * JSON-lines file.  Synchronises the stream.  *chosen (nullable) receives the
- * target. */
+/* Choose the launch shapes by timing grouped forward passes (no graph; the
+ * best of two timed passes per candidate) on these buffers, one shape at a
+ * time from the defaults: SPOD_BATCH_GRAM_TARGET over 2048, 4096, 8192 and
+ * 16384 workgroups per problem, then SPOD_BATCH_FFT_TILE over 16 and 32, then
+ * SPOD_BATCH_EIG_THREADS over 256 and 1024, then SPOD_BATCH_PERSISTENT = 1;
+ * each is kept when it is faster.  With cache_path != NULL the choice is read
+ * from (when its key, a hash of the problem shapes and precision, is present)
+ * or appended to that JSON-lines file, one line with the chosen shapes and
+ * every candidate's time in ms.  Synchronises the stream.  *chosen (nullable)
+ * receives the Gram target; spod_batch_get_option reads the others. */
 spod_status spod_batch_autotune(spod_batch batch, const void* const* q, spod_dtype dtype,
                                 void* out, void* ws, size_t ws_bytes, spod_stream stream,
                                 const char* cache_path, int64_t* chosen);

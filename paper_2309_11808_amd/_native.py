@@ -44,6 +44,9 @@ SPOD_QHAT_BFP20 = 1
 SPOD_BATCH_GROUPED = 0
 SPOD_BATCH_GRAPH = 1
 SPOD_BATCH_GRAM_TARGET = 2
+SPOD_BATCH_FFT_TILE = 3
+SPOD_BATCH_EIG_THREADS = 4
+SPOD_BATCH_PERSISTENT = 5
 
 
 class SpodProblem(C.Structure):
@@ -83,6 +86,7 @@ SIGNATURES = {
     "spod_plan_destroy": (None, [_p]),
     "spod_batch_create": (C.c_int, [C.POINTER(SpodProblem), _i64, C.c_int, _i64, C.POINTER(_p)]),
     "spod_batch_set_option": (C.c_int, [_p, C.c_int, _i64]),
+    "spod_batch_get_option": (C.c_int, [_p, C.c_int, C.POINTER(_i64)]),
     "spod_batch_query": (C.c_int, [_p, C.POINTER(_sz), C.POINTER(_sz)]),
     "spod_batch_item_info": (C.c_int, [_p, _i64, C.POINTER(SpodBatchItem)]),
     "spod_batch_forward": (C.c_int, [_p, C.POINTER(_p), C.c_int, _p, _p, _sz, _p]),

@@ -1,6 +1,8 @@
-// Batches of independent SPOD problems: grouped launches, hipGraph replay and
-// a Gram-split autotuner.  The per-problem arithmetic is the single-problem
-// path's; only the mapping of workgroups to problems differs.
+// Batches of independent SPOD problems: grouped launches (one workgroup per
+// work unit, or persistent workgroups that take units from a device queue),
+// hipGraph replay and an autotuner over the launch shapes.  The per-problem
+// arithmetic is the single-problem path's; only the mapping of workgroups to
+// problems differs.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,7 +36,10 @@ struct Group {
   int chain = 0;             // 0: problems with L <= 32, 1: L > 32
   size_t off = 0;            // byte offset of the item array in the table
   int n = 0, wgs = 0;
+  int queue = 0;             // its counter in the batch's queue array (persistent launches)
 };
+
+constexpr int NQUEUE = 256;   // work-queue counters (one per grouped launch)
 
 // Problems with more than 32 blocks form a second chain of launches: their
 // Gram (64 x 64 tiles) is bound by MFMA issue and their eigensolves by LDS
@@ -52,6 +57,12 @@ struct Batch {
   int device = 0;
   bool grouped = true, use_graph = true, started = false;
   int64_t gram_target = 8192;
+  // launch shapes (options, or the autotuner's choice): transform tile (0 =
+  // the single-problem default, 16, 32), eigensolver threads (0 = the
+  // single-problem rule, 256, 1024), persistent workgroups (0 or 1)
+  int fft_tile = 0, eig_threads = 0, persistent = 0;
+  int* d_queue = nullptr;    // [NQUEUE] work-queue counters
+  int n_queue = 0;           // counters in use
   size_t ws_bytes = 0, out_bytes = 0;
 
   // work tables (device) and the pointers they were built for
@@ -62,6 +73,7 @@ struct Batch {
   void* ws_built = nullptr;
   spod_dtype dtype_built = SPOD_F32;
   int64_t target_built = -1;
+  int tile_built = -1;
   bool tables_ok = false;
   std::vector<Group> fft_groups, gram_groups, eig_groups;   // eig: by L bucket (16, 32, 64)
   std::vector<int> fft_fallback;                 // problems launched on their own
@@ -174,7 +186,7 @@ spod_status build_tables(Batch& b, const void* const* q, spod_dtype dtype, char*
     Group g;
     g.chain = kv.first.first;
     g.key = kv.first.second;
-    const int T = fft_group_tile(g.key, b.prec);
+    const int T = fft_group_tile(g.key, b.prec, b.fft_tile);
     // the longest workgroups (most blocks) first, so the short ones fill the
     // end of the launch; a workgroup's result does not depend on its place
     std::stable_sort(kv.second.begin(), kv.second.end(),
@@ -297,6 +309,14 @@ spod_status build_tables(Batch& b, const void* const* q, spod_dtype dtype, char*
     b.eig_groups.push_back(g);
   }
 
+  // one work-queue counter per grouped launch
+  int nq = 0;
+  for (auto* gs : {&b.fft_groups, &b.gram_groups, &b.eig_groups})
+    for (Group& g : *gs) g.queue = nq++;
+  for (int ch = 0; ch < NCHAIN; ++ch) b.modes_g[ch].queue = nq++;
+  if (nq > NQUEUE) return fail(SPOD_ERR_UNSUPPORTED, "too many grouped launches");
+  b.n_queue = nq;
+
   if (host.size() > b.table_cap) {
     if (b.d_table) (void)hipFree(b.d_table);
     b.d_table = nullptr;
@@ -350,27 +370,35 @@ spod_status record(Batch& b, const void* const* q, spod_dtype dtype, char* out, 
   // slower.)
   const bool two = b.modes_g[0].n > 0 && b.modes_g[1].n > 0;
   auto hip = [](hipError_t e, const char* what) { return e == hipSuccess ? SPOD_OK : hip_fail(e, what); };
+  // persistent launches: every counter is zeroed before the fork, on `st`
+  auto queue = [&](const Group& g) -> int* { return b.persistent ? b.d_queue + g.queue : nullptr; };
+  if (b.persistent) {
+    r = launch_queue_reset(b.d_queue, b.n_queue, st);
+    if (r != SPOD_OK) return r;
+  }
   auto transforms = [&](int ch, hipStream_t cs) {
     for (const Group& g : b.fft_groups) {
       if (g.chain != ch || r != SPOD_OK) continue;
-      r = launch_fft_group(g.key, b.prec, dtype, 4, at<FftItem>(b, g), g.n, g.wgs, cs);
+      r = launch_fft_group(g.key, b.prec, dtype, 4, b.fft_tile, at<FftItem>(b, g), g.n, g.wgs,
+                           queue(g), cs);
     }
   };
   auto rest = [&](int ch, hipStream_t cs) {
     for (const Group& g : b.gram_groups) {
       if (g.chain != ch || r != SPOD_OK) continue;
-      r = launch_gram_group(b.prec, g.key, at<GramItem>(b, g), g.n, g.wgs, cs);
+      r = launch_gram_group(b.prec, g.key, at<GramItem>(b, g), g.n, g.wgs, queue(g), cs);
     }
     if (r == SPOD_OK)
       r = launch_gram_combine_group(at<CombineItem>(b, b.comb_g[ch]), b.comb_g[ch].n,
                                     b.comb_g[ch].wgs, cs);
     for (const Group& g : b.eig_groups) {
       if (g.chain != ch || r != SPOD_OK) continue;
-      r = launch_eig_group(at<EigItem>(b, g), g.n, g.wgs, b.pb[0].plan->max_sweeps, g.key, cs);
+      r = launch_eig_group(at<EigItem>(b, g), g.n, g.wgs, b.pb[0].plan->max_sweeps, g.key,
+                           b.eig_threads, queue(g), cs);
     }
     if (r == SPOD_OK)
       r = launch_modes_group(c128(b), at<ModesItem>(b, b.modes_g[ch]), b.modes_g[ch].n,
-                             b.modes_g[ch].wgs, b.modes_lds, cs);
+                             b.modes_g[ch].wgs, b.modes_lds, queue(b.modes_g[ch]), cs);
   };
   if (!two) {
     const int ch = b.modes_g[1].n > 0 ? 1 : 0;
@@ -394,7 +422,7 @@ spod_status record(Batch& b, const void* const* q, spod_dtype dtype, char* out, 
 
 spod_status prepare(Batch& b, const void* const* q, spod_dtype dtype, void* out, void* ws) {
   bool same = b.tables_ok && out == b.out_built && ws == b.ws_built && dtype == b.dtype_built &&
-              b.target_built == b.gram_target;
+              b.target_built == b.gram_target && b.tile_built == b.fft_tile;
   for (size_t i = 0; same && i < b.pb.size(); ++i) same = q[i] == b.q_built[i];
   if (same) return SPOD_OK;
   drop_graph(b);
@@ -407,6 +435,7 @@ spod_status prepare(Batch& b, const void* const* q, spod_dtype dtype, void* out,
   b.ws_built = ws;
   b.dtype_built = dtype;
   b.target_built = b.gram_target;
+  b.tile_built = b.fft_tile;
   b.tables_ok = true;
   return SPOD_OK;
 }
@@ -484,17 +513,44 @@ std::string batch_key(const Batch& b) {
   return buf;
 }
 
-int64_t cache_lookup(const char* path, const std::string& key) {
+// The launch shapes the autotuner chooses.
+struct Shapes {
+  int64_t gram_target = 0;   // 0: not found
+  int fft_tile = 0, eig_threads = 0, persistent = 0;
+};
+
+int64_t json_int(const std::string& line, const char* name, int64_t dflt) {
+  const std::string k = std::string("\"") + name + "\": ";
+  const size_t p = line.find(k);
+  return p == std::string::npos ? dflt : std::strtoll(line.c_str() + p + k.size(), nullptr, 10);
+}
+
+// The last line of the JSON-lines cache with this key.
+Shapes cache_lookup(const char* path, const std::string& key) {
   std::ifstream f(path);
   std::string line;
-  int64_t found = 0;
+  Shapes found;
   const std::string kk = "\"key\": \"" + key + "\"";
   while (std::getline(f, line)) {
     if (line.find(kk) == std::string::npos) continue;
-    const size_t p = line.find("\"gram_target\": ");
-    if (p != std::string::npos) found = std::strtoll(line.c_str() + p + 15, nullptr, 10);
+    Shapes s;
+    s.gram_target = json_int(line, "gram_target", 0);
+    s.fft_tile = (int)json_int(line, "fft_tile", 0);
+    s.eig_threads = (int)json_int(line, "eig_threads", 0);
+    s.persistent = (int)json_int(line, "persistent", 0);
+    const bool ok = s.gram_target >= 64 && (s.fft_tile == 0 || s.fft_tile == 16 || s.fft_tile == 32) &&
+                    (s.eig_threads == 0 || s.eig_threads == 256 || s.eig_threads == 1024) &&
+                    (s.persistent == 0 || s.persistent == 1);
+    if (ok) found = s;
   }
   return found;
+}
+
+void set_shapes(Batch& b, const Shapes& s) {
+  b.gram_target = s.gram_target;
+  b.fft_tile = s.fft_tile;
+  b.eig_threads = s.eig_threads;
+  b.persistent = s.persistent;
 }
 
 }  // namespace
@@ -539,6 +595,7 @@ spod_status spod_batch_create(const spod_problem* problems, int64_t n, spod_prec
       if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking);
       if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
       if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join, hipEventDisableTiming);
+      if (e == hipSuccess) e = hipMalloc(&b->d_queue, sizeof(int) * NQUEUE);
       if (e != hipSuccess) st = hip_fail(e, "batch stream");
     }
     if (st != SPOD_OK) {
@@ -574,8 +631,37 @@ spod_status spod_batch_set_option(spod_batch batch, spod_batch_option opt, int64
       apply_target(*b);
       layout(*b);
       break;
+    case SPOD_BATCH_FFT_TILE:
+      if (value != 0 && value != 16 && value != 32)
+        return fail(SPOD_ERR_INVALID_ARG, "transform tile is 0, 16 or 32");
+      b->fft_tile = (int)value;
+      break;
+    case SPOD_BATCH_EIG_THREADS:
+      if (value != 0 && value != 256 && value != 1024)
+        return fail(SPOD_ERR_INVALID_ARG, "eigensolver threads are 0, 256 or 1024");
+      b->eig_threads = (int)value;
+      break;
+    case SPOD_BATCH_PERSISTENT:
+      if (value != 0 && value != 1) return fail(SPOD_ERR_INVALID_ARG, "persistent is 0 or 1");
+      b->persistent = (int)value;
+      break;
     default:
       return fail(SPOD_ERR_INVALID_ARG, "unknown option");
+  }
+  return SPOD_OK;
+}
+
+spod_status spod_batch_get_option(spod_batch batch, spod_batch_option opt, int64_t* value) {
+  Batch* b = reinterpret_cast<Batch*>(batch);
+  if (!b || !value) return fail(SPOD_ERR_INVALID_ARG, "batch and value are required");
+  switch (opt) {
+    case SPOD_BATCH_GROUPED: *value = b->grouped; break;
+    case SPOD_BATCH_GRAPH: *value = b->use_graph; break;
+    case SPOD_BATCH_GRAM_TARGET: *value = b->gram_target; break;
+    case SPOD_BATCH_FFT_TILE: *value = b->fft_tile; break;
+    case SPOD_BATCH_EIG_THREADS: *value = b->eig_threads; break;
+    case SPOD_BATCH_PERSISTENT: *value = b->persistent; break;
+    default: return fail(SPOD_ERR_INVALID_ARG, "unknown option");
   }
   return SPOD_OK;
 }
@@ -626,44 +712,104 @@ spod_status spod_batch_autotune(spod_batch batch, const void* const* q, spod_dty
     if (st != SPOD_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     const std::string key = batch_key(*b);
-    int64_t best = cache_path ? cache_lookup(cache_path, key) : 0;
-    const int64_t cands[] = {2048, 4096, 8192, 16384};
-    float ms[4] = {0, 0, 0, 0};
-    if (best <= 0) {
+    Shapes best = cache_path ? cache_lookup(cache_path, key) : Shapes{};
+    if (best.gram_target <= 0) {
       hipEvent_t e0 = nullptr, e1 = nullptr;
       hipError_t e = hipEventCreate(&e0);
       if (e == hipSuccess) e = hipEventCreate(&e1);
       if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
-      float best_ms = 0.0f;
-      for (int c = 0; c < 4 && st == SPOD_OK; ++c) {
-        b->gram_target = cands[c];
-        // one untimed pass (builds the tables), then one timed pass, without a graph
-        st = run(*b, q, dtype, out, ws, s, false);
-        if (st == SPOD_OK) e = hipEventRecord(e0, s);
-        if (st == SPOD_OK && e == hipSuccess) st = run(*b, q, dtype, out, ws, s, false);
-        if (st == SPOD_OK && e == hipSuccess) e = hipEventRecord(e1, s);
-        if (st == SPOD_OK && e == hipSuccess) e = hipEventSynchronize(e1);
-        if (st == SPOD_OK && e == hipSuccess) e = hipEventElapsedTime(&ms[c], e0, e1);
-        if (st == SPOD_OK && e != hipSuccess) st = hip_fail(e, "autotune timing");
-        if (st == SPOD_OK && (best <= 0 || ms[c] < best_ms)) {
-          best = cands[c];
-          best_ms = ms[c];
+      std::ostringstream log;
+      // one untimed pass (it builds the tables), then the best of two timed
+      // passes, without a graph
+      auto time_shapes = [&](const Shapes& c, float* best_ms) -> spod_status {
+        set_shapes(*b, c);
+        spod_status r = run(*b, q, dtype, out, ws, s, false);
+        *best_ms = 0.0f;
+        for (int rep = 0; rep < 2 && r == SPOD_OK; ++rep) {
+          float ms = 0.0f;
+          hipError_t x = hipEventRecord(e0, s);
+          if (x == hipSuccess) r = run(*b, q, dtype, out, ws, s, false);
+          if (r != SPOD_OK) break;
+          if (x == hipSuccess) x = hipEventRecord(e1, s);
+          if (x == hipSuccess) x = hipEventSynchronize(e1);
+          if (x == hipSuccess) x = hipEventElapsedTime(&ms, e0, e1);
+          if (x != hipSuccess) r = hip_fail(x, "autotune timing");
+          if (r == SPOD_OK && (rep == 0 || ms < *best_ms)) *best_ms = ms;
+        }
+        return r;
+      };
+      // coordinate search from the defaults, one launch shape at a time:
+      // the Gram split target, the transform tile, the eigensolver threads,
+      // then one workgroup per unit against persistent workgroups
+      Shapes cur;
+      cur.gram_target = 8192;
+      float cur_ms = 0.0f;
+      bool have = false;
+      const int64_t targets[] = {2048, 4096, 8192, 16384};
+      for (int64_t t : targets) {
+        Shapes c = cur;
+        c.gram_target = t;
+        float ms = 0.0f;
+        if ((st = time_shapes(c, &ms)) != SPOD_OK) break;
+        log << (have ? ", " : "") << "\"gram_target=" << t << "\": " << ms;
+        if (!have || ms < cur_ms) {
+          cur = c;
+          cur_ms = ms;
+        }
+        have = true;
+      }
+      for (int tile : {16, 32}) {
+        if (st != SPOD_OK) break;
+        Shapes c = cur;
+        c.fft_tile = tile;
+        float ms = 0.0f;
+        if ((st = time_shapes(c, &ms)) != SPOD_OK) break;
+        log << ", \"fft_tile=" << tile << "\": " << ms;
+        if (ms < cur_ms) {
+          cur = c;
+          cur_ms = ms;
+        }
+      }
+      for (int nt : {256, 1024}) {
+        if (st != SPOD_OK) break;
+        Shapes c = cur;
+        c.eig_threads = nt;
+        float ms = 0.0f;
+        if ((st = time_shapes(c, &ms)) != SPOD_OK) break;
+        log << ", \"eig_threads=" << nt << "\": " << ms;
+        if (ms < cur_ms) {
+          cur = c;
+          cur_ms = ms;
+        }
+      }
+      if (st == SPOD_OK) {
+        Shapes c = cur;
+        c.persistent = 1;
+        float ms = 0.0f;
+        st = time_shapes(c, &ms);
+        if (st == SPOD_OK) {
+          log << ", \"persistent=1\": " << ms;
+          if (ms < cur_ms) {
+            cur = c;
+            cur_ms = ms;
+          }
         }
       }
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);
       if (st != SPOD_OK) return st;
+      best = cur;
       if (cache_path) {
         std::ofstream f(cache_path, std::ios::app);
-        f << "{\"key\": \"" << key << "\", \"gram_target\": " << best << ", \"ms\": {";
-        for (int c = 0; c < 4; ++c) f << (c ? ", " : "") << "\"" << cands[c] << "\": " << ms[c];
-        f << "}}\n";
+        f << "{\"key\": \"" << key << "\", \"gram_target\": " << best.gram_target
+          << ", \"fft_tile\": " << best.fft_tile << ", \"eig_threads\": " << best.eig_threads
+          << ", \"persistent\": " << best.persistent << ", \"ms\": {" << log.str() << "}}\n";
       }
     }
-    b->gram_target = best;
+    set_shapes(*b, best);
     drop_graph(*b);
     b->tables_ok = false;
-    if (chosen) *chosen = best;
+    if (chosen) *chosen = best.gram_target;
     return SPOD_OK;
   });
 }
@@ -681,6 +827,7 @@ void spod_batch_destroy(spod_batch batch) {
   if (b->fork) (void)hipEventDestroy(b->fork);
   if (b->join) (void)hipEventDestroy(b->join);
   if (b->d_table) (void)hipFree(b->d_table);
+  if (b->d_queue) (void)hipFree(b->d_queue);
   for (auto& s : b->pb)
     if (s.plan) spod_plan_destroy(reinterpret_cast<spod_plan>(s.plan));
   if (have && cur != b->device) (void)hipSetDevice(cur);

@@ -268,13 +268,18 @@ __global__ __launch_bounds__(1024) void jacobi_big_kernel(const double2* __restr
   jacobi_body<EIG_BIGN, true>(gram, lam, psi, info, L, max_sweeps, blockIdx.x, work);
 }
 
-template <int NT>
+template <int NT, bool PERSIST>
 __global__ __launch_bounds__(NT) void jacobi_batch_kernel(const EigItem* __restrict__ items, int n,
-                                                          int max_sweeps) {
-  const EigItem& it = items[find_item(items, n, (int)blockIdx.x)];
-  jacobi_body<EIG_MAXN, false>(static_cast<const double2*>(it.gram), it.lam,
-                               static_cast<double2*>(it.psi), it.info, it.L, max_sweeps,
-                               (int)blockIdx.x - it.start, nullptr);
+                                                          int max_sweeps, int units, int* queue) {
+  __shared__ int slot;
+  for (int b = next_unit(PERSIST ? queue : nullptr, &slot, true); b < units;
+       b = next_unit(PERSIST ? queue : nullptr, &slot, false)) {
+    const EigItem& it = items[find_item(items, n, b)];
+    jacobi_body<EIG_MAXN, false>(static_cast<const double2*>(it.gram), it.lam,
+                                 static_cast<double2*>(it.psi), it.info, it.L, max_sweeps,
+                                 b - it.start, nullptr);
+    if constexpr (!PERSIST) break;
+  }
 }
 
 constexpr int EIG_SMALL_NT = 256, EIG_LARGE_NT = 1024;
@@ -290,8 +295,10 @@ static hipError_t eig_attr() {
   std::call_once(once, [] {
   const void* fns[] = {reinterpret_cast<const void*>(&jacobi_kernel<EIG_SMALL_NT>),
                        reinterpret_cast<const void*>(&jacobi_kernel<EIG_LARGE_NT>),
-                       reinterpret_cast<const void*>(&jacobi_batch_kernel<EIG_SMALL_NT>),
-                       reinterpret_cast<const void*>(&jacobi_batch_kernel<EIG_LARGE_NT>)};
+                       reinterpret_cast<const void*>(&jacobi_batch_kernel<EIG_SMALL_NT, false>),
+                       reinterpret_cast<const void*>(&jacobi_batch_kernel<EIG_LARGE_NT, false>),
+                       reinterpret_cast<const void*>(&jacobi_batch_kernel<EIG_SMALL_NT, true>),
+                       reinterpret_cast<const void*>(&jacobi_batch_kernel<EIG_LARGE_NT, true>)};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)eig_lds_bytes(EIG_MAXN));
@@ -334,16 +341,28 @@ spod_status launch_eig(const Plan& p, const void* gram, double* lam, void* psi, 
 }
 
 spod_status launch_eig_group(const EigItem* d_items, int n, int wgs, int max_sweeps, int lmax,
-                             hipStream_t st) {
+                             int threads, int* queue, hipStream_t st) {
   hipError_t ea = eig_attr();
   if (ea != hipSuccess) return hip_fail(ea, "hipFuncSetAttribute");
   const size_t lds_bytes = eig_lds_bytes(lmax);
-  if (eig_threads(lmax) == EIG_LARGE_NT)
-    hipLaunchKernelGGL(jacobi_batch_kernel<EIG_LARGE_NT>, dim3((unsigned)wgs), dim3(EIG_LARGE_NT),
-                       lds_bytes, st, d_items, n, max_sweeps);
-  else
-    hipLaunchKernelGGL(jacobi_batch_kernel<EIG_SMALL_NT>, dim3((unsigned)wgs), dim3(EIG_SMALL_NT),
-                       lds_bytes, st, d_items, n, max_sweeps);
+  const int nt = threads ? threads : eig_threads(lmax);
+  if (nt != EIG_LARGE_NT && nt != EIG_SMALL_NT) return fail(SPOD_ERR_INVALID_ARG, "eigensolver threads");
+#define SPOD_EIG_GROUP(NTH)                                                                      \
+  if (queue) {                                                                                   \
+    const void* k = reinterpret_cast<const void*>(&jacobi_batch_kernel<NTH, true>);              \
+    hipLaunchKernelGGL((jacobi_batch_kernel<NTH, true>),                                         \
+                       dim3((unsigned)persistent_grid(k, NTH, lds_bytes, wgs)), dim3(NTH),       \
+                       lds_bytes, st, d_items, n, max_sweeps, wgs, queue);                       \
+  } else {                                                                                       \
+    hipLaunchKernelGGL((jacobi_batch_kernel<NTH, false>), dim3((unsigned)wgs), dim3(NTH),        \
+                       lds_bytes, st, d_items, n, max_sweeps, wgs, queue);                       \
+  }
+  if (nt == EIG_LARGE_NT) {
+    SPOD_EIG_GROUP(EIG_LARGE_NT)
+  } else {
+    SPOD_EIG_GROUP(EIG_SMALL_NT)
+  }
+#undef SPOD_EIG_GROUP
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SPOD_OK : hip_fail(e, "jacobi_batch_kernel");
 }

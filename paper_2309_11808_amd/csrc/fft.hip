@@ -396,14 +396,22 @@ __global__ __launch_bounds__(NPAIR*(NF / 8)) void blocks_fft_kernel(
 // Grouped launch over the problems of a batch that share N_f, precision, input
 // type and hop: workgroup b belongs to the last item whose first workgroup is
 // <= b, and transforms that item's tile b - start (all blocks, fused mean).
-template <int NF, typename TC, typename TIN, int NPAIR, int SHIFT>
+// PERSIST: persistent workgroups that take units (tiles) from the queue; a
+// separate instantiation, so the loop's register needs do not reach the
+// one-unit-per-workgroup kernel.
+template <int NF, typename TC, typename TIN, int NPAIR, int SHIFT, bool PERSIST>
 __global__ __launch_bounds__(NPAIR*(NF / 8)) void blocks_fft_batch_kernel(const FftItem* __restrict__ items,
-                                                                          int n) {
-  const FftItem& it = items[find_item(items, n, (int)blockIdx.x)];
-  blocks_fft_body<NF, TC, TIN, NPAIR, SHIFT, true>(
-      static_cast<const TIN*>(it.q), it.mean, it.window, static_cast<const cpx_t<TC>*>(it.tw),
-      static_cast<cpx_t<TC>*>(it.qhat), it.M, it.ldq, it.nt, it.step, it.L, it.L, (TC)it.kappa, it.mb,
-      nullptr, NF / 2 + 1, (int64_t)blockIdx.x - it.start, 0);
+                                                                          int n, int units, int* queue) {
+  __shared__ int slot;
+  for (int b = next_unit(PERSIST ? queue : nullptr, &slot, true); b < units;
+       b = next_unit(PERSIST ? queue : nullptr, &slot, false)) {
+    const FftItem& it = items[find_item(items, n, b)];
+    blocks_fft_body<NF, TC, TIN, NPAIR, SHIFT, true>(
+        static_cast<const TIN*>(it.q), it.mean, it.window, static_cast<const cpx_t<TC>*>(it.tw),
+        static_cast<cpx_t<TC>*>(it.qhat), it.M, it.ldq, it.nt, it.step, it.L, it.L, (TC)it.kappa,
+        it.mb, nullptr, NF / 2 + 1, (int64_t)b - it.start, 0);
+    if constexpr (!PERSIST) break;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -515,56 +523,73 @@ static spod_status launch_fft_t(const Plan& p, const TIN* q, double* mean, void*
 }
 
 // ---------------------------------------------------------------------------
-// grouped launch for a batch: fused mean, hop N/2, nfft <= 512, the default
-// tile of the single-problem path (so results are bit-identical to it)
+// grouped launch for a batch: fused mean, hop N/2, nfft <= 512.  Tile: 16 or
+// 32 degrees of freedom, or 0 for the single-problem default (32 up to
+// N = 256, else 16).  A tile's results do not depend on the tile size (the
+// pairs are the same adjacent DOFs), so every choice is bit-identical to the
+// single-problem path.
 // ---------------------------------------------------------------------------
-template <int NF, typename TC>
-struct GroupShape {
-  using S = FftShape<NF, (NF <= 256) ? 16 : 8>;   // the single-problem default tile
-};
+template <int NF, int BASE>
+using GroupShape = FftShape<NF, BASE>;
 
-template <int NF, typename TC, typename TIN>
-static spod_status fft_group_nf(const FftItem* d, int n, int wgs, hipStream_t st) {
-  using S = typename GroupShape<NF, TC>::S;
-  hipLaunchKernelGGL((blocks_fft_batch_kernel<NF, TC, TIN, S::NPAIR, 4>), dim3((unsigned)wgs),
-                     dim3(S::NPAIR * S::P), 0, st, d, n);
+constexpr int group_base(int nf, int tile) { return tile == 32 ? 16 : (tile == 16 ? 8 : (nf <= 256 ? 16 : 8)); }
+
+template <int NF, typename TC, typename TIN, int BASE>
+static spod_status fft_group_shape(const FftItem* d, int n, int wgs, int* queue, hipStream_t st) {
+  using S = GroupShape<NF, BASE>;
+  if (queue) {
+    const void* k = reinterpret_cast<const void*>(&blocks_fft_batch_kernel<NF, TC, TIN, S::NPAIR, 4, true>);
+    hipLaunchKernelGGL((blocks_fft_batch_kernel<NF, TC, TIN, S::NPAIR, 4, true>),
+                       dim3((unsigned)persistent_grid(k, S::NPAIR * S::P, 0, wgs)),
+                       dim3(S::NPAIR * S::P), 0, st, d, n, wgs, queue);
+  } else {
+    hipLaunchKernelGGL((blocks_fft_batch_kernel<NF, TC, TIN, S::NPAIR, 4, false>), dim3((unsigned)wgs),
+                       dim3(S::NPAIR * S::P), 0, st, d, n, wgs, queue);
+  }
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SPOD_OK : hip_fail(e, "blocks_fft_batch_kernel");
 }
 
+template <int NF, typename TC, typename TIN>
+static spod_status fft_group_nf(int tile, const FftItem* d, int n, int wgs, int* queue, hipStream_t st) {
+  if (group_base(NF, tile) == 16) return fft_group_shape<NF, TC, TIN, 16>(d, n, wgs, queue, st);
+  return fft_group_shape<NF, TC, TIN, 8>(d, n, wgs, queue, st);
+}
+
 template <typename TC, typename TIN>
-static spod_status fft_group_t(int nfft, const FftItem* d, int n, int wgs, hipStream_t st) {
+static spod_status fft_group_t(int nfft, int tile, const FftItem* d, int n, int wgs, int* queue,
+                               hipStream_t st) {
   switch (nfft) {
-    case 16: return fft_group_nf<16, TC, TIN>(d, n, wgs, st);
-    case 32: return fft_group_nf<32, TC, TIN>(d, n, wgs, st);
-    case 64: return fft_group_nf<64, TC, TIN>(d, n, wgs, st);
-    case 128: return fft_group_nf<128, TC, TIN>(d, n, wgs, st);
-    case 256: return fft_group_nf<256, TC, TIN>(d, n, wgs, st);
-    case 512: return fft_group_nf<512, TC, TIN>(d, n, wgs, st);
+    case 16: return fft_group_nf<16, TC, TIN>(tile, d, n, wgs, queue, st);
+    case 32: return fft_group_nf<32, TC, TIN>(tile, d, n, wgs, queue, st);
+    case 64: return fft_group_nf<64, TC, TIN>(tile, d, n, wgs, queue, st);
+    case 128: return fft_group_nf<128, TC, TIN>(tile, d, n, wgs, queue, st);
+    case 256: return fft_group_nf<256, TC, TIN>(tile, d, n, wgs, queue, st);
+    case 512: return fft_group_nf<512, TC, TIN>(tile, d, n, wgs, queue, st);
   }
   return fail(SPOD_ERR_UNSUPPORTED, "grouped transform: nfft");
 }
 
-int fft_group_tile(int nfft, spod_precision prec) {
-  const bool c128 = prec == SPOD_PREC_FP64;
+int fft_group_tile(int nfft, spod_precision prec, int tile) {
+  (void)prec;
   switch (nfft) {
 #define SPOD_TILE(NF) \
-    case NF: return c128 ? GroupShape<NF, double>::S::T : GroupShape<NF, float>::S::T;
+    case NF: return group_base(NF, tile) == 16 ? GroupShape<NF, 16>::T : GroupShape<NF, 8>::T;
     SPOD_TILE(16) SPOD_TILE(32) SPOD_TILE(64) SPOD_TILE(128) SPOD_TILE(256) SPOD_TILE(512)
 #undef SPOD_TILE
   }
   return 0;
 }
 
-spod_status launch_fft_group(int nfft, spod_precision prec, spod_dtype dtype, int shift,
-                             const FftItem* d_items, int n, int wgs, hipStream_t st) {
+spod_status launch_fft_group(int nfft, spod_precision prec, spod_dtype dtype, int shift, int tile,
+                             const FftItem* d_items, int n, int wgs, int* queue, hipStream_t st) {
   if (shift != 4) return fail(SPOD_ERR_UNSUPPORTED, "grouped transform: hop must be nfft/2");
   const bool c128 = prec == SPOD_PREC_FP64;
   if (dtype == SPOD_F32)
-    return c128 ? fft_group_t<double, float>(nfft, d_items, n, wgs, st)
-                : fft_group_t<float, float>(nfft, d_items, n, wgs, st);
-  return c128 ? fft_group_t<double, double>(nfft, d_items, n, wgs, st)
-              : fft_group_t<float, double>(nfft, d_items, n, wgs, st);
+    return c128 ? fft_group_t<double, float>(nfft, tile, d_items, n, wgs, queue, st)
+                : fft_group_t<float, float>(nfft, tile, d_items, n, wgs, queue, st);
+  return c128 ? fft_group_t<double, double>(nfft, tile, d_items, n, wgs, queue, st)
+              : fft_group_t<float, double>(nfft, tile, d_items, n, wgs, queue, st);
 }
 
 size_t fft_workspace(const Plan& p) { return sizeof(double) * (size_t)p.M; }

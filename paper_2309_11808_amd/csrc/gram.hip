@@ -450,6 +450,9 @@ __device__ __forceinline__ void gram_body(const typename GramCfg<MODE>::C* __res
                       : reinterpret_cast<const char*>(qk);
   const char* wb = reinterpret_cast<const char*>(sqrtw);
   const int64_t rowb = PK ? ldq : ldq * (int64_t)sizeof(C);
+  // the explicit counts below assume that only this unit's loads are in
+  // flight (a persistent workgroup may still have its previous unit's stores)
+  __builtin_amdgcn_s_waitcnt(0);
   if (c0 < c1)
     stage_issue<NT, CHUNKB, WB>(lds, qb + c0 * CHUNKB, rowb, wb + c0 * CD * (int64_t)sizeof(T), L,
                                 wave, lane, need);
@@ -714,14 +717,20 @@ __global__ __launch_bounds__(256, 1) void gram_big_kernel(const typename GramCfg
 
 // Grouped launch over a batch: workgroup b -> item, then the item's local
 // index -> work unit as in gram_kernel.
-template <int MODE, int NT>
-__global__ __launch_bounds__(256, 2) void gram_batch_kernel(const GramItem* __restrict__ items, int n) {
+template <int MODE, int NT, bool PERSIST>
+__global__ __launch_bounds__(256, 2) void gram_batch_kernel(const GramItem* __restrict__ items, int n,
+                                                             int units, int* queue) {
   using T = typename GramCfg<MODE>::T;
   using C = typename GramCfg<MODE>::C;
   extern __shared__ __attribute__((aligned(16))) char gram_lds[];
-  const GramItem& it = items[find_item(items, n, (int)blockIdx.x)];
-  gram_unit<MODE, NT>(static_cast<const C*>(it.qhat), static_cast<const T*>(it.sqrtw), it.part, it.M, it.ldq, it.L, it.S, it.K, it.vec != 0,
-                      (int64_t)blockIdx.x - it.start, gram_lds);
+  __shared__ int slot;
+  for (int b = next_unit(PERSIST ? queue : nullptr, &slot, true); b < units;
+       b = next_unit(PERSIST ? queue : nullptr, &slot, false)) {
+    const GramItem& it = items[find_item(items, n, b)];
+    gram_unit<MODE, NT>(static_cast<const C*>(it.qhat), static_cast<const T*>(it.sqrtw), it.part,
+                        it.M, it.ldq, it.L, it.S, it.K, it.vec != 0, (int64_t)b - it.start, gram_lds);
+    if constexpr (!PERSIST) break;
+  }
 }
 
 // Sum the S partial Grams in FP64.  Each partial holds the 16 x 16 blocks
@@ -930,33 +939,42 @@ int64_t gram_group_wgs(int nt16, int64_t S, int64_t K) {
 }
 
 template <int MODE, int NTI>
-static spod_status gram_group_nti(const GramItem* d, int n, int wgs, hipStream_t st) {
+static spod_status gram_group_nti(const GramItem* d, int n, int wgs, int* queue, hipStream_t st) {
   const size_t lds = 2 * (size_t)GramStage<NTI, gram_chunk_bytes<NTI, false>()>::BYTES;
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gram_batch_kernel<MODE, NTI>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((gram_batch_kernel<MODE, NTI>), dim3((unsigned)wgs), dim3(256), lds, st, d, n);
+  if (queue) {
+    const void* k = reinterpret_cast<const void*>(&gram_batch_kernel<MODE, NTI, true>);
+    (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((gram_batch_kernel<MODE, NTI, true>), dim3((unsigned)persistent_grid(k, 256, lds, wgs)),
+                       dim3(256), lds, st, d, n, wgs, queue);
+  } else {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gram_batch_kernel<MODE, NTI, false>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((gram_batch_kernel<MODE, NTI, false>), dim3((unsigned)wgs), dim3(256), lds, st,
+                       d, n, wgs, queue);
+  }
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SPOD_OK : hip_fail(e, "gram_batch_kernel");
 }
 
 template <int MODE>
-static spod_status gram_group_mode(int nt16, const GramItem* d, int n, int wgs, hipStream_t st) {
+static spod_status gram_group_mode(int nt16, const GramItem* d, int n, int wgs, int* queue,
+                                   hipStream_t st) {
   switch (nt16) {
-    case 1: return gram_group_nti<MODE, 1>(d, n, wgs, st);
-    case 2: return gram_group_nti<MODE, 2>(d, n, wgs, st);
-    case 3: return gram_group_nti<MODE, 3>(d, n, wgs, st);
-    case 4: return gram_group_nti<MODE, 4>(d, n, wgs, st);
+    case 1: return gram_group_nti<MODE, 1>(d, n, wgs, queue, st);
+    case 2: return gram_group_nti<MODE, 2>(d, n, wgs, queue, st);
+    case 3: return gram_group_nti<MODE, 3>(d, n, wgs, queue, st);
+    case 4: return gram_group_nti<MODE, 4>(d, n, wgs, queue, st);
   }
   return fail(SPOD_ERR_UNSUPPORTED, "nblocks > 64");
 }
 
 spod_status launch_gram_group(spod_precision prec, int nt16, const GramItem* d_items, int n,
-                              int wgs, hipStream_t st) {
+                              int wgs, int* queue, hipStream_t st) {
   switch (prec) {
-    case SPOD_PREC_FP64: return gram_group_mode<G_F64>(nt16, d_items, n, wgs, st);
-    case SPOD_PREC_FP32: return gram_group_mode<G_F32>(nt16, d_items, n, wgs, st);
-    case SPOD_PREC_BF16X4: return gram_group_mode<G_BF16X4>(nt16, d_items, n, wgs, st);
-    case SPOD_PREC_FP16X4: return gram_group_mode<G_FP16X4>(nt16, d_items, n, wgs, st);
+    case SPOD_PREC_FP64: return gram_group_mode<G_F64>(nt16, d_items, n, wgs, queue, st);
+    case SPOD_PREC_FP32: return gram_group_mode<G_F32>(nt16, d_items, n, wgs, queue, st);
+    case SPOD_PREC_BF16X4: return gram_group_mode<G_BF16X4>(nt16, d_items, n, wgs, queue, st);
+    case SPOD_PREC_FP16X4: return gram_group_mode<G_FP16X4>(nt16, d_items, n, wgs, queue, st);
   }
   return fail(SPOD_ERR_INVALID_ARG, "precision");
 }

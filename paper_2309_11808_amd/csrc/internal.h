@@ -259,20 +259,42 @@ __device__ __forceinline__ int find_item(const It* __restrict__ items, int n, in
   return lo;
 }
 
+// Next work unit of a grouped launch.  queue == NULL: one workgroup per unit,
+// unit blockIdx.x (first call), then none (INT_MAX).  Otherwise persistent
+// workgroups: each takes the next value of the device counter *queue (zeroed
+// before the launch) until the units run out; a workgroup barrier on either
+// side keeps the previous unit's LDS in use until every thread is done with
+// it.  Every thread of the workgroup gets the same value.
+__device__ __forceinline__ int next_unit(int* queue, int* slot, bool first) {
+  if (!queue) return first ? (int)blockIdx.x : 0x7fffffff;
+  __syncthreads();
+  if (threadIdx.x == 0) *slot = atomicAdd(queue, 1);
+  __syncthreads();
+  return *slot;
+}
+
 // grouped stage launchers (items already in device memory; `wgs` = total
-// workgroups).  Each returns SPOD_OK or an error.
-spod_status launch_fft_group(int nfft, spod_precision prec, spod_dtype dtype, int shift,
-                             const FftItem* d_items, int n, int wgs, hipStream_t st);
-int fft_group_tile(int nfft, spod_precision prec);   // degrees of freedom per tile
+// work units).  queue: NULL (one workgroup per unit) or a zeroed device
+// counter (persistent workgroups, as many as fit the device at once).  Each
+// returns SPOD_OK or an error.
+spod_status launch_fft_group(int nfft, spod_precision prec, spod_dtype dtype, int shift, int tile,
+                             const FftItem* d_items, int n, int wgs, int* queue, hipStream_t st);
+int fft_group_tile(int nfft, spod_precision prec, int tile);   // degrees of freedom per tile
 spod_status launch_gram_group(spod_precision prec, int nt16, const GramItem* d_items, int n,
-                              int wgs, hipStream_t st);
+                              int wgs, int* queue, hipStream_t st);
 int gram_groups(int nt16);                           // pair groups per (slice, k)
 int64_t gram_group_wgs(int nt16, int64_t S, int64_t K);   // workgroups of one problem
 spod_status launch_gram_combine_group(const CombineItem* d_items, int n, int wgs, hipStream_t st);
 spod_status launch_eig_group(const EigItem* d_items, int n, int wgs, int max_sweeps, int lmax,
-                             hipStream_t st);   // lmax: the group's largest L (16, 32 or 64)
+                             int threads, int* queue, hipStream_t st);
+// (lmax: the group's largest L (16, 32 or 64); threads: 256, 1024, or 0 for the
+// single-problem rule)
 spod_status launch_modes_group(bool c128, const ModesItem* d_items, int n, int wgs,
-                               size_t lds_bytes, hipStream_t st);
+                               size_t lds_bytes, int* queue, hipStream_t st);
+spod_status launch_queue_reset(int* queue, int n, hipStream_t st);   // n counters to zero
+// workgroups of a persistent launch: as many as the device holds at once (at
+// most `units`)
+int persistent_grid(const void* kernel, int threads, size_t lds_bytes, int units);
 
 // --------------------------------------------------------------------------
 // packed Fourier blocks (SPOD_QHAT_BFP20): every row (k, l) of M degrees of

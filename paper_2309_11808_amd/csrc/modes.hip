@@ -343,23 +343,30 @@ __global__ __launch_bounds__(256) void modes_kernel(const cpx_t<TC>* __restrict_
   modes_body<TC, PAIR>(qhat, lam, psi, phi, n_valid, M, M, L, n_modes, eps, xcd_tile(blockIdx.x, gridDim.x), blockIdx.y);
 }
 
-template <typename TC>
-__global__ __launch_bounds__(256) void modes_batch_kernel(const ModesItem* __restrict__ items, int n) {
-  const ModesItem& it = items[find_item(items, n, (int)blockIdx.x)];
-  const int local = (int)blockIdx.x - it.start;
-  if constexpr (sizeof(TC) == 4) {
-    if (it.pair) {
-      modes_body<TC, true>(static_cast<const cpx_t<TC>*>(it.qhat), it.lam,
-                           static_cast<const double2*>(it.psi), static_cast<cpx_t<TC>*>(it.phi),
-                           it.n_valid, it.M, it.ldq, it.L, it.n_modes, it.eps, local % it.tiles,
-                           local / it.tiles);
-      return;
+template <typename TC, bool PERSIST>
+__global__ __launch_bounds__(256) void modes_batch_kernel(const ModesItem* __restrict__ items, int n,
+                                                          int units, int* queue) {
+  __shared__ int slot;
+  for (int b = next_unit(PERSIST ? queue : nullptr, &slot, true); b < units;
+       b = next_unit(PERSIST ? queue : nullptr, &slot, false)) {
+    const ModesItem& it = items[find_item(items, n, b)];
+    const int local = b - it.start;
+    if constexpr (sizeof(TC) == 4) {
+      if (it.pair) {
+        modes_body<TC, true>(static_cast<const cpx_t<TC>*>(it.qhat), it.lam,
+                             static_cast<const double2*>(it.psi), static_cast<cpx_t<TC>*>(it.phi),
+                             it.n_valid, it.M, it.ldq, it.L, it.n_modes, it.eps, local % it.tiles,
+                             local / it.tiles);
+        if constexpr (!PERSIST) break;
+        continue;
+      }
     }
+    modes_body<TC, false>(static_cast<const cpx_t<TC>*>(it.qhat), it.lam,
+                          static_cast<const double2*>(it.psi), static_cast<cpx_t<TC>*>(it.phi),
+                          it.n_valid, it.M, it.ldq, it.L, it.n_modes, it.eps, local % it.tiles,
+                          local / it.tiles);
+    if constexpr (!PERSIST) break;
   }
-  modes_body<TC, false>(static_cast<const cpx_t<TC>*>(it.qhat), it.lam,
-                        static_cast<const double2*>(it.psi), static_cast<cpx_t<TC>*>(it.phi),
-                        it.n_valid, it.M, it.ldq, it.L, it.n_modes, it.eps, local % it.tiles,
-                        local / it.tiles);
 }
 
 spod_status launch_modes(const Plan& p, const void* qhat, const double* lam, const void* psi,
@@ -408,15 +415,49 @@ spod_status launch_modes(const Plan& p, const void* qhat, const double* lam, con
 }
 
 spod_status launch_modes_group(bool c128, const ModesItem* d_items, int n, int wgs,
-                               size_t lds_bytes, hipStream_t st) {
-  if (c128)
-    hipLaunchKernelGGL(modes_batch_kernel<double>, dim3((unsigned)wgs), dim3(256), lds_bytes, st,
-                       d_items, n);
-  else
-    hipLaunchKernelGGL(modes_batch_kernel<float>, dim3((unsigned)wgs), dim3(256), lds_bytes, st,
-                       d_items, n);
+                               size_t lds_bytes, int* queue, hipStream_t st) {
+  if (queue) {
+    const void* k = c128 ? reinterpret_cast<const void*>(&modes_batch_kernel<double, true>)
+                         : reinterpret_cast<const void*>(&modes_batch_kernel<float, true>);
+    const dim3 grid((unsigned)persistent_grid(k, 256, lds_bytes, wgs));
+    if (c128)
+      hipLaunchKernelGGL((modes_batch_kernel<double, true>), grid, dim3(256), lds_bytes, st, d_items,
+                         n, wgs, queue);
+    else
+      hipLaunchKernelGGL((modes_batch_kernel<float, true>), grid, dim3(256), lds_bytes, st, d_items,
+                         n, wgs, queue);
+  } else if (c128) {
+    hipLaunchKernelGGL((modes_batch_kernel<double, false>), dim3((unsigned)wgs), dim3(256), lds_bytes,
+                       st, d_items, n, wgs, queue);
+  } else {
+    hipLaunchKernelGGL((modes_batch_kernel<float, false>), dim3((unsigned)wgs), dim3(256), lds_bytes,
+                       st, d_items, n, wgs, queue);
+  }
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SPOD_OK : hip_fail(e, "modes_batch_kernel");
+}
+
+// Work-queue counters of the persistent grouped launches, zeroed by a kernel
+// (not a memset node) so that a captured graph clears them on every replay.
+__global__ __launch_bounds__(256) void queue_reset_kernel(int* __restrict__ q, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) q[i] = 0;
+}
+
+spod_status launch_queue_reset(int* queue, int n, hipStream_t st) {
+  hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(256), 0, st, queue, n);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SPOD_OK : hip_fail(e, "queue_reset_kernel");
+}
+
+int persistent_grid(const void* kernel, int threads, size_t lds_bytes, int units) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, lds_bytes) != hipSuccess ||
+      cus < 1 || per < 1)
+    return units;   // fall back to one workgroup per unit (the loop still works)
+  const int64_t g = (int64_t)cus * per;
+  return (int)(g < units ? g : units);
 }
 
 // Rows of a packed buffer [nrow][width] to a destination with row stride

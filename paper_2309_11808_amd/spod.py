@@ -276,7 +276,9 @@ class Batch:
     n_valid); they are overwritten by the next forward call."""
 
     def __init__(self, problems, precision: str = "fp64", n_modes: int = 5, grouped: bool = True,
-                 graph: bool = True, gram_target: Optional[int] = None, device=None):
+                 graph: bool = True, gram_target: Optional[int] = None,
+                 fft_tile: Optional[int] = None, eig_threads: Optional[int] = None,
+                 persistent: Optional[bool] = None, device=None):
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
             else torch.device(device)
         self.precision = precision
@@ -298,7 +300,9 @@ class Batch:
                                            C.byref(h)))
         self._h = h
         for opt, v in ((N.SPOD_BATCH_GROUPED, grouped), (N.SPOD_BATCH_GRAPH, graph),
-                       (N.SPOD_BATCH_GRAM_TARGET, gram_target)):
+                       (N.SPOD_BATCH_GRAM_TARGET, gram_target), (N.SPOD_BATCH_FFT_TILE, fft_tile),
+                       (N.SPOD_BATCH_EIG_THREADS, eig_threads),
+                       (N.SPOD_BATCH_PERSISTENT, persistent)):
             if v is not None:
                 _check(lib().spod_batch_set_option(self._h, opt, int(v)))
         ws, out = C.c_size_t(), C.c_size_t()
@@ -365,6 +369,8 @@ class Batch:
         return self.results()
 
     def autotune(self, qs, cache_path: Optional[str] = None) -> int:
+        """Choose the launch shapes (spod_batch_autotune); returns the Gram
+        target, and shapes() gives every choice."""
         ptrs, dt = self._qptrs(qs)
         ws, out = self.buffers()
         chosen = C.c_int64()
@@ -373,6 +379,18 @@ class Batch:
                                          None if cache_path is None else cache_path.encode(),
                                          C.byref(chosen)))
         return chosen.value
+
+    def shapes(self) -> dict:
+        """The launch shapes in use (options or the autotuner's choice)."""
+        out = {}
+        for name, opt in (("gram_target", N.SPOD_BATCH_GRAM_TARGET),
+                          ("fft_tile", N.SPOD_BATCH_FFT_TILE),
+                          ("eig_threads", N.SPOD_BATCH_EIG_THREADS),
+                          ("persistent", N.SPOD_BATCH_PERSISTENT)):
+            v = C.c_int64()
+            _check(lib().spod_batch_get_option(self._h, opt, C.byref(v)))
+            out[name] = v.value
+        return out
 
 
 def _host_or_device_ptr(t, name: str):

@@ -99,6 +99,32 @@ def test_batch_bit_identical_to_single_path(precision):
         b.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp16x4"])
+def test_batch_launch_shapes_bit_identical(precision):
+    """The transform tile, the eigensolver's thread count and persistent
+    workgroups change how the work is mapped, not the arithmetic."""
+    from paper_2309_11808_amd import Batch
+    specs = _small_specs(12, seed=9)
+    probs = _problems(specs)
+    descs = [_desc(p) for p in probs]
+    base = Batch(descs, precision=precision, n_modes=4)
+    ref = [{k: v.clone() for k, v in r.items()} for r in base.forward([p.q for p in probs])]
+    torch.cuda.synchronize()
+    base.close()
+    for tile, nt, pers, graph in ((16, 256, True, True), (32, 1024, True, False),
+                                  (32, 256, False, True), (16, 1024, True, True)):
+        b = Batch(descs, precision=precision, n_modes=4, fft_tile=tile, eig_threads=nt,
+                  persistent=pers, graph=graph)
+        assert b.shapes()["fft_tile"] == tile and b.shapes()["persistent"] == int(pers)
+        for rep in range(2):
+            res = b.forward([p.q for p in probs])
+            torch.cuda.synchronize()
+            for i, (r, f) in enumerate(zip(res, ref)):
+                _same(r, f, f"tile {tile} threads {nt} persistent {pers} graph {graph} "
+                            f"pass {rep} problem {i}")
+        b.close()
+
+
 def test_batch_small_problems_match_oracle():
     from paper_2309_11808_amd import Batch
     specs = _small_specs(8, seed=11, max_space=400)
@@ -116,11 +142,14 @@ def test_batch_small_problems_match_oracle():
     b.close()
 
 
-def test_batch_graph_replays_and_new_buffers():
+@pytest.mark.parametrize("persistent", [False, True])
+def test_batch_graph_replays_and_new_buffers(persistent):
+    """Replays see new values and stay equal; with persistent workgroups the
+    queue counters are zeroed by a kernel inside the graph on every replay."""
     from paper_2309_11808_amd import Batch
     specs = _small_specs(10, seed=5)
     probs = _problems(specs)
-    b = Batch([_desc(p) for p in probs], precision="bf16x4", n_modes=4)
+    b = Batch([_desc(p) for p in probs], precision="bf16x4", n_modes=4, persistent=persistent)
     first = [{k: v.clone() for k, v in r.items()} for r in b.forward([p.q for p in probs])]
     torch.cuda.synchronize()
     for rep in range(3):
@@ -177,7 +206,13 @@ def test_batch_autotune_and_cache(tmp_path):
     t = b.autotune([p.q for p in probs], cache_path=cache)
     assert t in (2048, 4096, 8192, 16384)
     lines = open(cache).read().strip().splitlines()
-    assert len(lines) == 1 and json.loads(lines[0])["gram_target"] == t
+    rec = json.loads(lines[0])
+    assert len(lines) == 1 and rec["gram_target"] == t
+    shapes = b.shapes()
+    assert shapes == {k: rec[k] for k in ("gram_target", "fft_tile", "eig_threads", "persistent")}
+    assert shapes["fft_tile"] in (0, 16, 32) and shapes["eig_threads"] in (0, 256, 1024)
+    # every candidate was timed: 4 targets, 2 tiles, 2 thread counts, persistent
+    assert len(rec["ms"]) == 9 and all(v > 0 for v in rec["ms"].values())
     res = b.forward([p.q for p in probs])
     torch.cuda.synchronize()
     # the tuned split only changes the order of the Gram sums
@@ -188,6 +223,7 @@ def test_batch_autotune_and_cache(tmp_path):
     # a second batch of the same shapes takes the cached choice without timing
     b2 = Batch([_desc(p) for p in probs], precision="bf16x4", n_modes=3)
     assert b2.autotune([p.q for p in probs], cache_path=cache) == t
+    assert b2.shapes() == shapes
     assert len(open(cache).read().strip().splitlines()) == 1
     b2.close()
     os.remove(cache)
