@@ -267,9 +267,12 @@ spod_status spod_modes(spod_plan plan, const void* qhat, const double* lam, cons
  * than 1e-12 of the largest eigenvalue contribute nothing); Gram adjoint
  * 2 W Qhat G; then the adjoint of the windowed one-sided DFT, the overlap-add
  * of the blocks and the mean removal.  Modes that spod_modes zero-fills are
- * constants here.  Returns SPOD_ERR_UNSUPPORTED when nfft is not a power of
- * two in [16, 1024], when the hop nfft - noverlap is not nfft/4, nfft/2 or
- * nfft, or when nblocks > 64. */
+ * constants here.  Power-of-two nfft in [16, 1024] needs a hop nfft - noverlap
+ * of nfft/4, nfft/2 or nfft.  Any other nfft the forward supports (the
+ * mixed-radix transform, any hop) runs the adjoint of that transform and
+ * needs qhat (no recomputation) and at most 513 bins (bins may be NULL only
+ * when nfreq <= 513).  Returns SPOD_ERR_UNSUPPORTED otherwise, for nfft < 16,
+ * or when nblocks > 64. */
 spod_status spod_backward(spod_plan plan, const void* q, spod_dtype dtype, const void* qhat,
                           const double* lam, const void* psi, const double* g_lam,
                           const void* g_phi, int64_t n_modes, const int32_t* bins,

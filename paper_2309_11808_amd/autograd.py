@@ -4,7 +4,9 @@
 
 The forward runs spod_blocks_fft, spod_csd, spod_eig and spod_modes; the
 backward runs spod_backward, which recomputes the Fourier blocks (at the
-selected bins only) unless keep_qhat=True kept them from the forward.  With
+selected bins only) unless keep_qhat=True kept them from the forward.  A block
+length other than a power of two up to 1024 always keeps them (its transform
+has no bin selection to recompute from).  With
 `bins`, lam and phi are returned for those frequencies only ([nb, L] and
 [nb, n_modes, M]), and the backward touches only those frequencies.
 
@@ -28,8 +30,10 @@ class SpodFunction(torch.autograd.Function):
         lam, phi = out["lam"], out["phi"]
         ctx.plan, ctx.n_modes, ctx.bins = plan, n_modes, bins
         ctx.set_materialize_grads(False)
-        ctx.save_for_backward(q, lam, out["psi"],
-                              out["qhat"] if keep_qhat and not plan.packed else None)
+        nf = plan.nfft
+        general = not (nf & (nf - 1) == 0 and nf <= 1024)
+        keep = (keep_qhat or general) and not plan.packed
+        ctx.save_for_backward(q, lam, out["psi"], out["qhat"] if keep else None)
         if bins is not None:
             idx = torch.as_tensor(np.asarray(bins, dtype=np.int64), device=q.device)
             return lam.index_select(0, idx), phi.index_select(0, idx)

@@ -534,8 +534,7 @@ spod_status spod_backward(spod_plan plan, const void* q, spod_dtype dtype, const
         return fail(SPOD_ERR_INVALID_ARG, "g_qhat may alias qhat only without a bin selection");
     }
     if (p->nfft < 16) return fail(SPOD_ERR_UNSUPPORTED, "backward needs nfft >= 16");
-    if (p->general) return fail(SPOD_ERR_UNSUPPORTED, "backward needs a power-of-two nfft <= 1024");
-    if (p->step != p->nfft && p->step != p->nfft / 2 && p->step != p->nfft / 4)
+    if (!p->general && p->step != p->nfft && p->step != p->nfft / 2 && p->step != p->nfft / 4)
       return fail(SPOD_ERR_UNSUPPORTED, "backward needs a hop of nfft/4, nfft/2 or nfft");
     if (p->nblocks > 64) return fail(SPOD_ERR_UNSUPPORTED, "nblocks > 64");
     if (p->qhat_packed && qhat)

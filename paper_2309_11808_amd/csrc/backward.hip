@@ -642,6 +642,20 @@ spod_status launch_bwd_t(const Plan& p, spod_dtype dtype, const void* qrows, int
     if (r != SPOD_OK) return r;
   }
   // D
+  if (p.general) {
+    // any block length: the adjoint of the mixed-radix transform
+    GenAdjBins gb;
+    gb.n = bt.n;
+    for (int i = 0; i < bt.n; ++i) gb.k[i] = bt.k[i];
+    GenAdjMean gm{};
+    gm.n = ml.n;
+    for (int i = 0; i < ml.n; ++i) {
+      gm.slot[i] = ml.slot[i];
+      gm.wr[i] = ml.wr[i];
+      gm.wi[i] = ml.wi[i];
+    }
+    return launch_general_adjoint(p, g_qhat, dtype, g_q, gb, gm, st);
+  }
   return dtype == SPOD_F32 ? launch_bwd_fft<TC, float>(p, g_qhat, g_q, bt, ml, st)
                            : launch_bwd_fft<TC, double>(p, g_qhat, g_q, bt, ml, st);
 }
@@ -655,20 +669,34 @@ spod_status launch_backward(const Plan& p, const void* q, spod_dtype dtype, cons
                             const void* g_phi, int n_modes, const int32_t* bins, int n_bins,
                             void* g_qhat, void* g_q, void* ws, hipStream_t st) {
   const int K = (int)p.nfreq;
-  if (K > BWD_MAXK || p.nblocks > BWD_MAXL) return fail(SPOD_ERR_UNSUPPORTED, "shape");
+  // a power-of-two transform keeps its K <= 513 bins in the table's inverse
+  // map; any other block length takes at most 513 selected bins (the inverse
+  // map is then not used)
+  if ((!p.general && K > BWD_MAXK) || p.nblocks > BWD_MAXL) return fail(SPOD_ERR_UNSUPPORTED, "shape");
+  if (n_bins > BWD_MAXK)
+    return fail(SPOD_ERR_UNSUPPORTED, "at most 513 bins: pass a selection (bins) for nfft above 1024");
+  if (p.general && !qhat)
+    return fail(SPOD_ERR_UNSUPPORTED,
+                "pass the Fourier blocks (qhat) for a block length other than a power of two <= 1024");
   BinTable bt;
   bt.n = n_bins;
   for (int k = 0; k < BWD_MAXK; ++k) bt.slot[k] = -1;
   for (int s = 0; s < n_bins; ++s) {
     const int k = bins ? bins[s] : s;
     bt.k[s] = (int16_t)k;
-    bt.slot[k] = (int16_t)s;
+    if (k < BWD_MAXK) bt.slot[k] = (int16_t)s;
   }
+  // the selected bins where the window's DFT is not zero
+  auto slot_of = [&](int k) {
+    for (int s = 0; s < n_bins; ++s)
+      if (bt.k[s] == k) return s;
+    return -1;
+  };
   MeanList ml{};
   if (p.n_mean_bins >= 0) {
     ml.n = 0;
     for (int i = 0; i < p.n_mean_bins; ++i) {
-      const int s = bt.slot[p.mean_bin[i]];
+      const int s = slot_of(p.mean_bin[i]);
       if (s < 0) continue;
       ml.slot[ml.n] = s;
       ml.wr[ml.n] = p.what_re[i];

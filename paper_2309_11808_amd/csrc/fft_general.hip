@@ -292,6 +292,72 @@ __device__ __forceinline__ void pp_stage(const cpx_t<TC>* __restrict__ X,
   }
 }
 
+// The stages of the transform on X (in LDS, natural order in and out); with
+// PP the stages alternate between X and Y.  Returns the buffer that holds the
+// result.  The caller has synchronised the workgroup after writing X.
+template <typename TC, bool PP, int MAXU, int MAXI>
+__device__ __forceinline__ cpx_t<TC>* dft_stages(cpx_t<TC>* X, cpx_t<TC>* Y,
+                                                 const cpx_t<TC>* __restrict__ Wt,
+                                                 const cpx_t<TC>* __restrict__ tw,
+                                                 const cpx_t<TC>* __restrict__ oddw,
+                                                 const Radices& rad, int tid, int N) {
+  using C = cpx_t<TC>;
+  int n = N, s = 1, off = 0;
+  for (int st = 0; st < rad.n; ++st) {
+    const int r = rad.r[st];
+    const int m = n / r;
+    const int wn = N / n;          // W_n = W_N^(N/n)
+    const C* Wr = Wt + off;
+    if constexpr (PP) {
+      pp_stage<TC>(X, Y, tw, Wr, oddw, rad, st, tid, N, r, s, m, wn);
+      lds_barrier();
+      C* tmp = X;
+      X = Y;
+      Y = tmp;
+    } else {
+      if (r % 2 == 1) {
+        const int NB = N / r, items = NB * ((r + 1) / 2);
+        C y0[MAXI], y1[MAXI];
+        int o0[MAXI], o1[MAXI];
+#pragma unroll
+        for (int u = 0; u < MAXI; ++u) {
+          const int it = tid + u * GEN_THREADS;
+          o0[u] = -1;
+          if (it < items)
+            odd_pair<TC>(X, Wr, tw, it, NB, r, s, m, wn, N, y0[u], y1[u], o0[u], o1[u]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < MAXI; ++u) {
+          if (o0[u] >= 0) {
+            X[o0[u]] = y0[u];
+            if (o1[u] >= 0) X[o1[u]] = y1[u];
+          }
+        }
+      } else {
+        C y[MAXU];
+#pragma unroll
+        for (int u = 0; u < MAXU; ++u) {
+          const int o = tid + u * GEN_THREADS;
+          if (o < N)
+            y[u] = even_output<TC>(X, Wr, tw, o, r, s, m, wn, N, 1.0f / (float)s, 1.0f / (float)r);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < MAXU; ++u) {
+          const int o = tid + u * GEN_THREADS;
+          if (o < N) X[o] = y[u];
+        }
+      }
+      __syncthreads();
+    }
+    n = m;
+    s *= r;
+    off += r;
+  }
+  return X;
+}
+
 // PP: two LDS buffers, every stage reads one and writes the other (no
 // staging registers).  Otherwise one buffer: a thread computes its outputs of
 // a stage into registers (MAXU outputs of an even-radix stage, MAXI pairs of
@@ -377,59 +443,7 @@ __global__ __launch_bounds__(GEN_THREADS) void blocks_dft_general_kernel(
     if constexpr (PP) lds_barrier();
     else __syncthreads();
 
-    int n = N, s = 1, off = 0;
-    for (int st = 0; st < rad.n; ++st) {
-      const int r = rad.r[st];
-      const int m = n / r;
-      const int wn = N / n;          // W_n = W_N^(N/n)
-      const C* Wr = Wt + off;
-      if constexpr (PP) {
-        pp_stage<TC>(X, Y, tw, Wr, oddw, rad, st, tid, N, r, s, m, wn);
-        lds_barrier();
-        C* tmp = X;
-        X = Y;
-        Y = tmp;
-      } else {
-        if (r % 2 == 1) {
-          const int NB = N / r, items = NB * ((r + 1) / 2);
-          C y0[MAXI], y1[MAXI];
-          int o0[MAXI], o1[MAXI];
-#pragma unroll
-          for (int u = 0; u < MAXI; ++u) {
-            const int it = tid + u * GEN_THREADS;
-            o0[u] = -1;
-            if (it < items)
-              odd_pair<TC>(X, Wr, tw, it, NB, r, s, m, wn, N, y0[u], y1[u], o0[u], o1[u]);
-          }
-          __syncthreads();
-#pragma unroll
-          for (int u = 0; u < MAXI; ++u) {
-            if (o0[u] >= 0) {
-              X[o0[u]] = y0[u];
-              if (o1[u] >= 0) X[o1[u]] = y1[u];
-            }
-          }
-        } else {
-          C y[MAXU];
-#pragma unroll
-          for (int u = 0; u < MAXU; ++u) {
-            const int o = tid + u * GEN_THREADS;
-            if (o < N)
-              y[u] = even_output<TC>(X, Wr, tw, o, r, s, m, wn, N, 1.0f / (float)s, 1.0f / (float)r);
-          }
-          __syncthreads();
-#pragma unroll
-          for (int u = 0; u < MAXU; ++u) {
-            const int o = tid + u * GEN_THREADS;
-            if (o < N) X[o] = y[u];
-          }
-        }
-        __syncthreads();
-      }
-      n = m;
-      s *= r;
-      off += r;
-    }
+    X = dft_stages<TC, PP, MAXU, MAXI>(X, Y, Wt, tw, oddw, rad, tid, N);
 
     // two-for-one split: A = (Z_k + conj Z_{N-k}) / 2, C = (Z_k - conj Z_{N-k}) / 2i
     const C* Z = X;
@@ -493,6 +507,170 @@ spod_status launch_general_t(const Plan& p, const TIN* q, const double* mean, vo
   return launch_general_pp<TC, TIN, false, MAXU>(p, q, mean, qhat, one_buf, st);
 }
 
+// Adjoint of the general transform for the selected bins (not in the paper;
+// the reverse of eq. (blocks-ft) and of the mean removal).  With
+// Qhat_k = kappa sum_n w[n] x[n] W_N^{kn} on the one-sided bins, and
+// g = dE/dRe + i dE/dIm,
+//   dE/dx[n] = kappa w[n] Re sum_k g_k W_N^{-kn} = kappa w[n] (1/2) sum_k H_k W_N^{-kn}
+// over all N bins with H_0 = 2 Re g_0, H_{N/2} = 2 Re g_{N/2} (N even),
+// H_k = g_k and H_{N-k} = conj g_k.  Two rows a, c are packed as
+// Z = H_a + i H_c; the same forward stages give D = DFT(conj Z), and
+// (1/2) conj D carries row a in its real part and row c in its imaginary part.
+// The blocks are added into g_q in turn (the workgroup owns both rows, so no
+// other workgroup writes them).  The mean removal x - mean(x) adds
+// -(1/nt) sum_t dE/dx[t] to every sample; that sum is
+// kappa sum_l Re sum_k g_{k,l} conj(What_k), taken from the bins where the
+// window's DFT is not zero before the blocks, so every row starts at that
+// constant and the blocks accumulate onto it.
+template <typename TC, typename TOUT, bool PP, int MAXU, int MAXI = (2 * MAXU + 2) / 3>
+__global__ __launch_bounds__(GEN_THREADS) void general_adjoint_kernel(
+    const cpx_t<TC>* __restrict__ gqh, TOUT* __restrict__ g_q, const double* __restrict__ window,
+    const cpx_t<TC>* __restrict__ tw, const double2* __restrict__ what, int64_t M, int64_t nt,
+    int N, int step, int L, double kappa, Radices rad, int64_t per_xcd,
+    const cpx_t<TC>* __restrict__ oddw, GenAdjBins bins, GenAdjMean gm) {
+  using C = cpx_t<TC>;
+  extern __shared__ unsigned char smem[];
+  C* const B0 = reinterpret_cast<C*>(smem);
+  C* const B1 = PP ? B0 + N : B0;
+  C* Wt = B0 + (PP ? 2 * N : N);
+  const int64_t b = blockIdx.x;
+  const int64_t pair = (b & 7) * per_xcd + (b >> 3);
+  const int64_t P = (M + 1) / 2;
+  if (pair >= P) return;                       // the same for every thread
+  const int64_t m0 = 2 * pair;
+  const bool two = m0 + 1 < M;
+  const int tid = threadIdx.x;
+
+  // sum_t dE/dx[t] of both rows, in FP64 (reduced in the first 16 KiB of LDS,
+  // before the twiddles and the blocks take it)
+  double sa = 0.0, sc = 0.0;
+  const int nmb = gm.n >= 0 ? gm.n : bins.n;
+  for (int it = tid; it < nmb * L; it += GEN_THREADS) {
+    const int i = it / L, l = it - i * L;
+    const int slot = gm.n >= 0 ? gm.slot[i] : i;
+    double wr, wi;
+    if (gm.n >= 0) {
+      wr = gm.wr[i];
+      wi = gm.wi[i];
+    } else {
+      const double2 wv = what[bins.k[i]];
+      wr = wv.x;
+      wi = wv.y;
+    }
+    const C* src = gqh + ((int64_t)slot * L + l) * M + m0;
+    const C ga = src[0];
+    sa += (double)ga.x * wr + (double)ga.y * wi;
+    if (two) {
+      const C gc = src[1];
+      sc += (double)gc.x * wr + (double)gc.y * wi;
+    }
+  }
+  double* red = reinterpret_cast<double*>(B0);   // before the first block uses B0
+  red[tid] = sa;
+  red[GEN_THREADS + tid] = sc;
+  __syncthreads();
+  for (int h = GEN_THREADS / 2; h > 0; h >>= 1) {
+    if (tid < h) {
+      red[tid] += red[tid + h];
+      red[GEN_THREADS + tid] += red[GEN_THREADS + tid + h];
+    }
+    __syncthreads();
+  }
+  const double ca = -kappa * red[0] / (double)nt, cc = -kappa * red[GEN_THREADS] / (double)nt;
+  __syncthreads();
+  {
+    int off = 0;
+    for (int st = 0; st < rad.n; ++st) {
+      const int r = rad.r[st];
+      for (int t = tid; t < r; t += GEN_THREADS) Wt[off + t] = tw[(N / r) * t];
+      off += r;
+    }
+  }
+  TOUT* ra = g_q + m0 * nt;
+  TOUT* rc = g_q + (two ? m0 + 1 : m0) * nt;
+  for (int64_t t = tid; t < nt; t += GEN_THREADS) {
+    ra[t] = (TOUT)ca;
+    if (two) rc[t] = (TOUT)cc;
+  }
+  __syncthreads();
+
+  const TC hk = (TC)(0.5 * kappa);
+  for (int l = 0; l < L; ++l) {
+    C* X = B0;
+    C* Y = B1;
+    // conj Z: zero, then the selected bins and their mirrors
+    for (int n = tid; n < N; n += GEN_THREADS) X[n] = mk<TC>((TC)0, (TC)0);
+    __syncthreads();
+    for (int i = tid; i < bins.n; i += GEN_THREADS) {
+      const int k = bins.k[i];
+      const C* src = gqh + ((int64_t)i * L + l) * M + m0;
+      const C ga = src[0];
+      const C gc = two ? src[1] : mk<TC>((TC)0, (TC)0);
+      if (k == 0 || 2 * k == N) {
+        X[k] = mk<TC>((TC)2 * ga.x, (TC)-2 * gc.x);
+      } else {
+        X[k] = mk<TC>(ga.x - gc.y, -ga.y - gc.x);
+        X[N - k] = mk<TC>(ga.x + gc.y, ga.y - gc.x);
+      }
+    }
+    __syncthreads();
+    const C* D = dft_stages<TC, PP, MAXU, MAXI>(X, Y, Wt, tw, oddw, rad, tid, N);
+    // (1/2) conj D, times kappa w[n], added into the block's samples
+    const int64_t o = (int64_t)l * step;
+    for (int n = tid; n < N; n += GEN_THREADS) {
+      const TC w = (TC)window[n] * hk;
+      const C d = D[n];
+      ra[o + n] = (TOUT)((TC)ra[o + n] + w * d.x);
+      if (two) rc[o + n] = (TOUT)((TC)rc[o + n] - w * d.y);
+    }
+    // the next block reads these samples and rewrites the buffers
+    __syncthreads();
+  }
+}
+
+template <typename TC, typename TOUT, bool PP, int MAXU>
+spod_status launch_adjoint_pp(const Plan& p, const void* g_qhat, void* g_q, const GenAdjBins& bins,
+                              const GenAdjMean& gm, size_t lds, hipStream_t st) {
+  using C = cpx_t<TC>;
+  const void* fn = reinterpret_cast<const void*>(&general_adjoint_kernel<TC, TOUT, PP, MAXU>);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
+  const int64_t P = (p.M + 1) / 2;
+  const int64_t per_xcd = (P + 7) / 8;
+  const int64_t wgs = 8 * per_xcd;
+  if (wgs > 0x7fffffffLL) return fail(SPOD_ERR_UNSUPPORTED, "general transform grid too large");
+  const C* tw = static_cast<const C*>(sizeof(TC) == 8 ? (const void*)p.d_tw64 : (const void*)p.d_tw32);
+  hipLaunchKernelGGL((general_adjoint_kernel<TC, TOUT, PP, MAXU>), dim3((unsigned)wgs),
+                     dim3(GEN_THREADS), lds, st, static_cast<const C*>(g_qhat),
+                     static_cast<TOUT*>(g_q), p.d_window, tw, p.d_what, (int64_t)p.M, (int64_t)p.nt,
+                     (int)p.nfft, (int)p.step, (int)p.nblocks, p.kappa, p.radices, per_xcd,
+                     static_cast<const C*>(sizeof(TC) == 8 ? (const void*)p.d_oddw64
+                                                           : (const void*)p.d_oddw32),
+                     bins, gm);
+  e = hipGetLastError();
+  return e == hipSuccess ? SPOD_OK : hip_fail(e, "general_adjoint_kernel");
+}
+
+template <typename TC, typename TOUT, int MAXU>
+spod_status launch_adjoint_t(const Plan& p, const void* g_qhat, void* g_q, const GenAdjBins& bins,
+                             const GenAdjMean& gm, hipStream_t st) {
+  using C = cpx_t<TC>;
+  int sum_r = 0;
+  for (int i = 0; i < p.radices.n; ++i) sum_r += p.radices.r[i];
+  constexpr size_t LDS_MAX = 160 * 1024;
+  // at least 16 KiB: the FP64 reduction of the mean term comes first
+  const size_t two_buf = std::max<size_t>(sizeof(C) * (2 * (size_t)p.nfft + (size_t)sum_r),
+                                          2 * GEN_THREADS * sizeof(double));
+  if (two_buf <= LDS_MAX)
+    return launch_adjoint_pp<TC, TOUT, true, (sizeof(C) == 8 ? 10 : 5)>(p, g_qhat, g_q, bins, gm,
+                                                                          two_buf, st);
+  const size_t one_buf = std::max<size_t>(sizeof(C) * ((size_t)p.nfft + (size_t)sum_r),
+                                          2 * GEN_THREADS * sizeof(double));
+  if (one_buf > LDS_MAX)
+    return fail(SPOD_ERR_UNSUPPORTED, "block and twiddles exceed the 160 KiB of LDS");
+  return launch_adjoint_pp<TC, TOUT, false, MAXU>(p, g_qhat, g_q, bins, gm, one_buf, st);
+}
+
 }  // namespace
 
 int general_odd_entries(int r, int kpt) {
@@ -538,6 +716,25 @@ spod_status launch_blocks_dft_general(const Plan& p, const void* q, spod_dtype d
                 : launch_general_t<float, float, UF>(p, static_cast<const float*>(q), mean, qhat, st);
   return c128 ? launch_general_t<double, double, UD>(p, static_cast<const double*>(q), mean, qhat, st)
               : launch_general_t<float, double, UF>(p, static_cast<const double*>(q), mean, qhat, st);
+}
+
+}  // namespace spod
+
+namespace spod {
+
+spod_status launch_general_adjoint(const Plan& p, const void* g_qhat, spod_dtype dtype, void* g_q,
+                                   const GenAdjBins& bins, const GenAdjMean& mean, hipStream_t st) {
+  const bool c128 = is_complex128(p);
+  if (p.nfft > (c128 ? SPOD_GENERAL_MAX_NFFT / 2 : SPOD_GENERAL_MAX_NFFT))
+    return fail(SPOD_ERR_UNSUPPORTED, "nfft too large for the general transform");
+  if (p.radices.n <= 0) return fail(SPOD_ERR_UNSUPPORTED, "nfft has no radix factorisation");
+  constexpr int UF = (SPOD_GENERAL_MAX_NFFT + GEN_THREADS - 1) / GEN_THREADS;
+  constexpr int UD = (SPOD_GENERAL_MAX_NFFT / 2 + GEN_THREADS - 1) / GEN_THREADS;
+  if (dtype == SPOD_F32)
+    return c128 ? launch_adjoint_t<double, float, UD>(p, g_qhat, g_q, bins, mean, st)
+                : launch_adjoint_t<float, float, UF>(p, g_qhat, g_q, bins, mean, st);
+  return c128 ? launch_adjoint_t<double, double, UD>(p, g_qhat, g_q, bins, mean, st)
+              : launch_adjoint_t<float, double, UF>(p, g_qhat, g_q, bins, mean, st);
 }
 
 }  // namespace spod

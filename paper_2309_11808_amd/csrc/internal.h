@@ -138,6 +138,23 @@ spod_status launch_blocks_fft(const Plan& p, const void* q, spod_dtype dtype, vo
 // the transform of steps 1-2 for any N_f (mean from the FP64 mean pass)
 spod_status launch_blocks_dft_general(const Plan& p, const void* q, spod_dtype dtype,
                                       const double* mean, void* qhat, hipStream_t st);
+// Adjoint of that transform (and of the mean removal) for the selected bins:
+// g_q = dE/dq from g_qhat = dE/dqhat [bins.n][L][M].  bins: strictly
+// increasing frequencies; mean: the selected bins whose window DFT is not
+// zero (slot into the selection and What_k), or n < 0 for every selected bin
+// with the plan's What table.
+constexpr int GEN_ADJ_MAXB = 513;
+struct GenAdjBins {
+  int n;
+  int16_t k[GEN_ADJ_MAXB];
+};
+struct GenAdjMean {
+  int n;
+  int slot[Plan::SPOD_MAX_MEAN_BINS];
+  double wr[Plan::SPOD_MAX_MEAN_BINS], wi[Plan::SPOD_MAX_MEAN_BINS];
+};
+spod_status launch_general_adjoint(const Plan& p, const void* g_qhat, spod_dtype dtype, void* g_q,
+                                   const GenAdjBins& bins, const GenAdjMean& mean, hipStream_t st);
 spod_status launch_csd(const Plan& p, const void* qhat, void* gram, void* ws, hipStream_t st,
                        bool accumulate = false);
 // spod_csd with the partials in the library's static device scratch (no

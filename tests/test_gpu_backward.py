@@ -189,6 +189,64 @@ def test_gradient_variants_fp64(nfft, nov, M, extra, dtype, wkind):
     assert err <= tol, f"gradient error {err:.2e}"
 
 
+# block lengths other than a power of two up to 1024 (the mixed-radix
+# transform and its adjoint; the forward's blocks are kept): radices 2, 3, 5
+# and the paper's 73, a power of two above 1024, hops of 1/2, 1/4 and 2/3 of N_f
+GEN_CASES = [
+    # nfft, noverlap, M, extra samples, input dtype, window, all bins
+    (24, 12, 37, 5, torch.float64, "hann", False),
+    (100, 25, 29, 3, torch.float64, "random", True),
+    (146, 73, 41, 0, torch.float32, "hann", False),
+    (150, 50, 23, 9, torch.float64, "hamming", True),
+    (1536, 768, 13, 11, torch.float64, "hann", False),
+    (2190, 1095, 9, 4, torch.float64, "hamming", False),
+    (8760, 4380, 6, 7, torch.float64, "hann", False),       # the paper's one-year hourly block
+]
+
+
+@pytest.mark.parametrize("nfft,nov,M,extra,dtype,wkind,all_bins", GEN_CASES)
+def test_gradient_general_lengths_fp64(nfft, nov, M, extra, dtype, wkind, all_bins):
+    L = 4 + (nfft % 3)
+    nt = (L - 1) * (nfft - nov) + nfft + extra
+    p = fields.random_rows(M, nt, nfft, nov, seed=nfft + M, dtype=dtype, offset=2.0)
+    window = _window(wkind, nfft, nfft)
+    q64 = p.q.numpy().astype(np.float64)
+    lam = O.spod(q64, nfft, nov, window=window, weights=p.weights, n_modes=1)["lam"]
+    bins = None if all_bins else _separated_bins(lam, 4)
+    n_modes = 2
+    nb = lam.shape[0] if all_bins else len(bins)
+    loss = _make_loss(p.weights, _probes(nb, M, p.weights, seed=5), n_lam=2)
+    ref = _reference(p, loss, bins, window, n_modes)
+    g = _gpu_grad(p, loss, bins, window, n_modes)
+    tol = TOL_FP64 if dtype == torch.float64 else 2e-7
+    err = _rel(g, ref)
+    print(f"general nfft={nfft} nov={nov} M={M} {wkind} all_bins={all_bins}: {err:.2e}")
+    assert err <= tol, f"gradient error {err:.2e}"
+
+
+def test_backward_general_length_needs_blocks_and_a_selection():
+    from paper_2309_11808_amd import SpodError
+    p = fields.random_rows(12, 3 * 1536 + 5, 1536, 768, seed=2)   # K = 769 > 513
+    plan = _plan(p)
+    q = p.q.cuda()
+    out = _forward(plan, q, 1)
+    g_lam = torch.ones(2, plan.nblocks, dtype=torch.float64, device="cuda")
+    # no stored blocks: the mixed-radix transform has no bin selection to recompute from
+    with pytest.raises(SpodError) as ei:
+        plan.backward(q, out["lam"], out["psi"], g_lam=g_lam, bins=[3, 9])
+    assert ei.value.status == -2
+    # every bin (769 > 513)
+    with pytest.raises(SpodError) as ei:
+        plan.backward(q, out["lam"], out["psi"], g_lam=torch.ones_like(out["lam"]),
+                      qhat=out["qhat"])
+    assert ei.value.status == -2
+    # a selection with the stored blocks works
+    g = plan.backward(q, out["lam"], out["psi"], g_lam=g_lam, bins=[3, 9], qhat=out["qhat"])
+    torch.cuda.synchronize()
+    assert torch.isfinite(g).all()
+    plan.close()
+
+
 # ---------------------------------------------------------------------------
 # mixed-precision plans (complex64 blocks, FP32 transforms)
 # ---------------------------------------------------------------------------

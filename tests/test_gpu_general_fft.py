@@ -107,7 +107,10 @@ def test_general_transform_limits():
     plan.close()
 
 
-def test_backward_rejects_general_lengths():
+def test_backward_general_length_without_blocks_is_refused():
+    """Any block length other than a power of two up to 1024 needs the
+    forward's blocks: the mixed-radix transform has no bin selection to
+    recompute them from (the gradients themselves: test_gpu_backward.py)."""
     from paper_2309_11808_amd import SpodError
     p = fields.random_rows(16, 4 * 30 + 60, 60, 30, seed=2, dtype=torch.float64)
     plan = _plan(p, "fp64")
