@@ -134,13 +134,18 @@ typedef enum { SPOD_QHAT_COMPLEX = 0, SPOD_QHAT_BFP20 = 1 } spod_qhat_format;
  *             finite, >= 0, not all zero.
  * Returns SPOD_ERR_INVALID_ARG for nspace, nvar < 1; nfft < 2; noverlap outside
  * [0, nfft); nt < nfft; L < 2; a bad window or weights; out == NULL.
- * Returns SPOD_ERR_UNSUPPORTED for nfft outside [8, 20480].  Powers of two up
+ * Returns SPOD_ERR_UNSUPPORTED for nfft outside [8, 2^20].  Powers of two up
  * to 1024 take the register-resident radix-8 transform; every other nfft (the
  * paper's hourly records use 8760 = 2^3 3 5 73) takes a mixed-radix transform
- * held in LDS, limited to nfft <= 10240 under SPOD_PREC_FP64 (complex128
- * blocks) and about 20400 otherwise (the block and its stage twiddles share
- * 160 KiB of LDS), and to prime factors up to 1024 (SPOD_ERR_UNSUPPORTED from
- * spod_blocks_fft).  Validation happens before any HIP call. */
+ * held in LDS, up to nfft = 10240 under SPOD_PREC_FP64 (complex128 blocks)
+ * and about 20400 otherwise (the block and its stage twiddles share 160 KiB
+ * of LDS), with prime factors up to 1024 (SPOD_ERR_UNSUPPORTED from
+ * spod_blocks_fft).  Longer blocks (the paper's ten-year blocks: 87600) take a
+ * two-pass transform nfft = A B (A-point DFTs of the B columns, twiddles, then
+ * B-point DFTs of the A rows; A the largest divisor <= sqrt(nfft), A and B at
+ * most 4096, prime factors up to 1024; otherwise SPOD_ERR_UNSUPPORTED here)
+ * whose intermediate lives in the workspace.  Validation happens before any
+ * HIP call. */
 spod_status spod_plan_create(int64_t nspace, int64_t nvar, int64_t nt, int64_t nfft,
                              int64_t noverlap, const double* window, const double* weights,
                              spod_plan* out);

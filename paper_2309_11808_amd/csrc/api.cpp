@@ -109,6 +109,113 @@ Plan plan_rows(const Plan& p, int64_t row0, int64_t rows) {
 
 static bool is_pow2(int64_t n) { return n > 0 && (n & (n - 1)) == 0; }
 
+// Radices of n (8, 4, 2, 3, 5, 7, then the remaining primes in increasing
+// order) with the odd stages' work-item shapes and table offsets; returns
+// the odd stages' table entries, or -1 when n has more than 32 factors.
+static int factor_radices(int64_t n, Radices& rad) {
+  rad = Radices{};
+  const int64_t n0 = n;
+  for (int64_t f : {8, 4, 2, 3, 5, 7}) {
+    while (n % f == 0 && rad.n < 32) {
+      rad.r[rad.n++] = (int)f;
+      n /= f;
+    }
+  }
+  for (int64_t f = 11; n > 1 && rad.n < 32; f += 2) {
+    while (n % f == 0 && rad.n < 32) {
+      rad.r[rad.n++] = (int)f;
+      n /= f;
+    }
+  }
+  if (n != 1) {
+    rad.n = 0;
+    return -1;
+  }
+  int odd_entries = 0;
+  for (int i = 0; i < rad.n; ++i) {
+    const int r = rad.r[i];
+    if (r % 2 == 0) continue;
+    rad.kpt[i] = general_odd_kpt(r, (int)(n0 / r));
+    rad.toff[i] = odd_entries;
+    odd_entries += general_odd_entries(r, rad.kpt[i]);
+  }
+  return odd_entries;
+}
+
+// The odd stages' tables T[g][j][c] = W_r^{(j + 1) k}, k = min(g + c G, (r-1)/2),
+// from a twiddle table W_n^t of the transform length n.
+static void odd_tables(const Radices& rad, int64_t n, const std::vector<double2>& tw,
+                       const std::vector<float2>& tw32, std::vector<double2>& oddw,
+                       std::vector<float2>& oddw32) {
+  for (int i = 0; i < rad.n; ++i) {
+    const int r = rad.r[i], kpt = rad.kpt[i];
+    if (r % 2 == 0) continue;
+    const int hm = (r - 1) / 2, G = (hm + 1 + kpt - 1) / kpt;
+    size_t e = (size_t)rad.toff[i];
+    for (int g = 0; g < G; ++g)
+      for (int j = 1; j <= hm; ++j)
+        for (int c = 0; c < kpt; ++c, ++e) {
+          const int k = std::min(g + c * G, hm);
+          const int64_t t = (n / r) * ((int64_t)j * k % r);
+          oddw[e] = tw[t];
+          oddw32[e] = tw32[t];
+        }
+  }
+}
+
+// Twiddles e^{-2 pi i j / n}, in long double and rounded once.
+static void twiddles(int64_t n, std::vector<double2>& tw, std::vector<float2>& tw32) {
+  tw.resize(n);
+  tw32.resize(n);
+  for (int64_t j = 0; j < n; ++j) {
+    const long double a = 2.0L * 3.14159265358979323846264338327950288L * (long double)j / (long double)n;
+    tw[j] = make_double2((double)cosl(a), (double)-sinl(a));
+    tw32[j] = make_float2((float)cosl(a), (float)-sinl(a));
+  }
+}
+
+// DFT of a real sequence, X[k] = sum_n x[n] e^{-2 pi i k n / N} for k < K, in
+// long double: the same self-sorting mixed-radix stages as the device
+// transform (decimation in frequency), N * (sum of the radices) operations.
+static void host_dft(const std::vector<double>& x, const Radices& rad, int64_t K,
+                     std::vector<double2>& out) {
+  const int64_t N = (int64_t)x.size();
+  std::vector<long double> ct(N), st(N);
+  for (int64_t t = 0; t < N; ++t) {
+    const long double a = 2.0L * 3.14159265358979323846264338327950288L * (long double)t / (long double)N;
+    ct[t] = cosl(a);
+    st[t] = -sinl(a);
+  }
+  std::vector<long double> xr(N), xi(N, 0.0L), yr(N), yi(N);
+  for (int64_t i = 0; i < N; ++i) xr[i] = x[i];
+  int64_t n = N, s = 1;
+  for (int stg = 0; stg < rad.n; ++stg) {
+    const int64_t r = rad.r[stg], m = n / r, wn = N / n;
+    // y[q + s (r p + k)] = W_n^{p k} sum_j x[q + s (p + j m)] W_r^{j k}
+    for (int64_t pp = 0; pp < m; ++pp)
+      for (int64_t qq = 0; qq < s; ++qq)
+        for (int64_t k = 0; k < r; ++k) {
+          long double ar = 0.0L, ai = 0.0L;
+          for (int64_t j = 0; j < r; ++j) {
+            const int64_t t = (N / r) * ((j * k) % r);
+            const int64_t idx = qq + s * (pp + j * m);
+            ar += xr[idx] * ct[t] - xi[idx] * st[t];
+            ai += xr[idx] * st[t] + xi[idx] * ct[t];
+          }
+          const int64_t t2 = (wn * pp * k) % N;
+          const int64_t o = qq + s * (r * pp + k);
+          yr[o] = ar * ct[t2] - ai * st[t2];
+          yi[o] = ar * st[t2] + ai * ct[t2];
+        }
+    xr.swap(yr);
+    xi.swap(yi);
+    n = m;
+    s *= r;
+  }
+  out.resize(K);
+  for (int64_t k = 0; k < K; ++k) out[k] = make_double2((double)xr[k], (double)xi[k]);
+}
+
 static spod_status validate_shape(int64_t nt, int64_t nfft, int64_t noverlap, int64_t* L,
                                   int64_t* K) {
   if (nfft < 2) return fail(SPOD_ERR_INVALID_ARG, "nfft must be >= 2");
@@ -157,7 +264,9 @@ void spod_plan_destroy(spod_plan plan) {
   if (hipGetDevice(&cur) == hipSuccess && cur != p->device) (void)hipSetDevice(p->device);
   (void)hipDeviceSynchronize();
   void* bufs[] = {p->d_window, p->d_window32, p->d_weights, p->d_sqrtw,
-                  p->d_sqrtw32, p->d_tw64, p->d_tw32, p->d_what, p->d_oddw64, p->d_oddw32};
+                  p->d_sqrtw32, p->d_tw64, p->d_tw32, p->d_what, p->d_oddw64, p->d_oddw32,
+                  p->d_tw_a64, p->d_tw_a32, p->d_tw_b64, p->d_tw_b32, p->d_oddw_a64,
+                  p->d_oddw_a32, p->d_oddw_b64, p->d_oddw_b32};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (cur != p->device) (void)hipSetDevice(cur);
@@ -198,8 +307,8 @@ spod_status spod_plan_create(int64_t nspace, int64_t nvar, int64_t nt, int64_t n
       W[m] = v;
     }
     if (!any) return fail(SPOD_ERR_INVALID_ARG, "weights are all zero");
-    if (nfft < 8 || nfft > SPOD_GENERAL_MAX_NFFT)
-      return fail(SPOD_ERR_UNSUPPORTED, "nfft must be in [8, 20480]");
+    if (nfft < 8 || nfft > SPOD_LONG_MAX_NFFT)
+      return fail(SPOD_ERR_UNSUPPORTED, "nfft must be in [8, 2^20]");
 
     Plan* p = new (std::nothrow) Plan();
     if (!p) return fail(SPOD_ERR_ALLOC, "plan");
@@ -213,29 +322,45 @@ spod_status spod_plan_create(int64_t nspace, int64_t nvar, int64_t nt, int64_t n
     p->nblocks = L;
     p->nfreq = K;
     p->general = !(is_pow2(nfft) && nfft <= 1024);
-    {
-      int64_t n = nfft;
-      for (int64_t f : {8, 4, 2, 3, 5, 7}) {
-        while (n % f == 0 && p->radices.n < 32) {
-          p->radices.r[p->radices.n++] = (int)f;
-          n /= f;
-        }
+    const int odd_entries = std::max(0, factor_radices(nfft, p->radices));
+    // above what one workgroup's LDS holds (complex64 above 20480, complex128
+    // above 10240): the two-pass transform N = A B, A the largest divisor
+    // <= sqrt(N) (both at most SPOD_LONG_MAX_FACTOR).  Its tables are built
+    // from N > 10240 on; the precision picks the path at launch.
+    int odd_a = 0, odd_b = 0;
+    if (nfft > SPOD_GENERAL_MAX_NFFT / 2) {
+      int64_t a = 1;
+      for (int64_t d = 2; d * d <= nfft; ++d)
+        if (nfft % d == 0) a = d;
+      const int64_t b = nfft / a;
+      bool ok = a >= 2 && b <= SPOD_LONG_MAX_FACTOR;
+      if (ok) {
+        odd_a = factor_radices(a, p->rad_a);
+        odd_b = factor_radices(b, p->rad_b);
+        for (const Radices* rr : {&p->rad_a, &p->rad_b})
+          for (int i = 0; i < rr->n; ++i) ok = ok && rr->r[i] <= 1024;
       }
-      for (int64_t f = 11; n > 1 && p->radices.n < 32; f += 2) {
-        while (n % f == 0 && p->radices.n < 32) {
-          p->radices.r[p->radices.n++] = (int)f;
-          n /= f;
-        }
+      if (!ok && nfft > SPOD_GENERAL_MAX_NFFT) {
+        delete p;
+        return fail(SPOD_ERR_UNSUPPORTED,
+                    "nfft above 20480 must be a product A B of two factors <= 4096 "
+                    "with prime factors <= 1024");
       }
-      if (n != 1) p->radices.n = 0;   // not reachable for nfft <= 20480 (at most 15 factors)
-    }
-    int odd_entries = 0;
-    for (int i = 0; i < p->radices.n; ++i) {
-      const int r = p->radices.r[i];
-      if (r % 2 == 0) continue;
-      p->radices.kpt[i] = general_odd_kpt(r, (int)(nfft / r));
-      p->radices.toff[i] = odd_entries;
-      odd_entries += general_odd_entries(r, p->radices.kpt[i]);
+      if (ok) {
+        p->long_dft = true;
+        p->long_a = (int)a;
+        p->long_b = (int)b;
+        // one workgroup per CU (each takes most of a CU's LDS), each with its
+        // own slot of the intermediate in the workspace
+        int dev = 0, cus = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess || cus < 1) {
+          delete p;
+          return e != hipSuccess ? hip_fail(e, "hipDeviceGetAttribute") : fail(SPOD_ERR_HIP, "no CUs");
+        }
+        p->long_grid = cus;
+      }
     }
     p->kappa = 1.0 / std::sqrt((double)(L - 1) * sw2);
     // DFT of the window at every one-sided bin, What_k = sum_n w[n] e^{-2 pi i k n / N},
@@ -252,14 +377,24 @@ spod_status spod_plan_create(int64_t nspace, int64_t nvar, int64_t nt, int64_t n
         st[t] = sinl(a);
       }
       int cnt = 0;
+      // long blocks: the window's DFT by the host's mixed-radix transform
+      // (N sum(r) operations instead of N K)
+      std::vector<double2> what_fast;
+      const bool fast = nfft > SPOD_GENERAL_MAX_NFFT;
+      if (fast) host_dft(w, p->radices, K, what_fast);
       for (int64_t k = 0; k < K; ++k) {
         long double re = 0.0L, im = 0.0L;
-        int64_t t = 0;                      // (k * n) mod nfft
-        for (int64_t n = 0; n < nfft; ++n) {
-          re += (long double)w[n] * ct[t];
-          im -= (long double)w[n] * st[t];
-          t += k;
-          if (t >= nfft) t -= nfft;
+        if (fast) {
+          re = what_fast[k].x;
+          im = what_fast[k].y;
+        } else {
+          int64_t t = 0;                    // (k * n) mod nfft
+          for (int64_t n = 0; n < nfft; ++n) {
+            re += (long double)w[n] * ct[t];
+            im -= (long double)w[n] * st[t];
+            t += k;
+            if (t >= nfft) t -= nfft;
+          }
         }
         what[k] = make_double2((double)re, (double)im);
         if (cnt >= 0 && sqrtl(re * re + im * im) > 1e-12L * sabs) {
@@ -329,6 +464,40 @@ spod_status spod_plan_create(int64_t nspace, int64_t nvar, int64_t nt, int64_t n
         {(void**)&p->d_oddw64, oddw.data(), sizeof(double2) * oddw.size()},
         {(void**)&p->d_oddw32, oddw32.data(), sizeof(float2) * oddw32.size()},
     };
+    // the two-pass transform's tables of A and B
+    std::vector<double2> tw_a, tw_b, oddw_a(std::max(odd_a, 1)), oddw_b(std::max(odd_b, 1));
+    std::vector<float2> tw_a32, tw_b32, oddw_a32(oddw_a.size()), oddw_b32(oddw_b.size());
+    if (p->long_dft) {
+      twiddles(p->long_a, tw_a, tw_a32);
+      twiddles(p->long_b, tw_b, tw_b32);
+      odd_tables(p->rad_a, p->long_a, tw_a, tw_a32, oddw_a, oddw_a32);
+      odd_tables(p->rad_b, p->long_b, tw_b, tw_b32, oddw_b, oddw_b32);
+    }
+    const size_t la = p->long_dft ? (size_t)p->long_a : 0, lb = p->long_dft ? (size_t)p->long_b : 0;
+    Up ups_long[] = {
+        {(void**)&p->d_tw_a64, tw_a.data(), sizeof(double2) * la},
+        {(void**)&p->d_tw_a32, tw_a32.data(), sizeof(float2) * la},
+        {(void**)&p->d_tw_b64, tw_b.data(), sizeof(double2) * lb},
+        {(void**)&p->d_tw_b32, tw_b32.data(), sizeof(float2) * lb},
+        {(void**)&p->d_oddw_a64, oddw_a.data(), p->long_dft ? sizeof(double2) * oddw_a.size() : 0},
+        {(void**)&p->d_oddw_a32, oddw_a32.data(), p->long_dft ? sizeof(float2) * oddw_a32.size() : 0},
+        {(void**)&p->d_oddw_b64, oddw_b.data(), p->long_dft ? sizeof(double2) * oddw_b.size() : 0},
+        {(void**)&p->d_oddw_b32, oddw_b32.data(), p->long_dft ? sizeof(float2) * oddw_b32.size() : 0},
+    };
+    for (auto& u : ups_long) {
+      if (u.bytes == 0) continue;
+      e = hipMalloc(u.dst, u.bytes);
+      if (e != hipSuccess) {
+        spod_plan_destroy(reinterpret_cast<spod_plan>(p));
+        return e == hipErrorOutOfMemory ? fail(SPOD_ERR_ALLOC, "plan tables")
+                                        : hip_fail(e, "hipMalloc");
+      }
+      e = hipMemcpy(*u.dst, u.src, u.bytes, hipMemcpyHostToDevice);
+      if (e != hipSuccess) {
+        spod_plan_destroy(reinterpret_cast<spod_plan>(p));
+        return hip_fail(e, "hipMemcpy");
+      }
+    }
     for (auto& u : ups) {
       e = hipMalloc(u.dst, u.bytes);
       if (e != hipSuccess) {

@@ -587,6 +587,8 @@ spod_status spod_batch_create(const spod_problem* problems, int64_t n, spod_prec
       b->pb[i].plan = reinterpret_cast<Plan*>(h);
       st = spod_plan_set_precision(h, precision);
       if (b->pb[i].plan->nblocks > 64) st = fail(SPOD_ERR_UNSUPPORTED, "nblocks > 64");
+      if (st == SPOD_OK && long_scratch_bytes(*b->pb[i].plan) > 0)
+        st = fail(SPOD_ERR_UNSUPPORTED, "a batch takes blocks that fit one workgroup's LDS");
       b->pb[i].n_modes = (int)std::min<int64_t>(n_modes, b->pb[i].plan->nblocks);
     }
     if (st == SPOD_OK) {

@@ -592,7 +592,12 @@ spod_status launch_fft_group(int nfft, spod_precision prec, spod_dtype dtype, in
               : fft_group_t<float, double>(nfft, tile, d_items, n, wgs, queue, st);
 }
 
-size_t fft_workspace(const Plan& p) { return sizeof(double) * (size_t)p.M; }
+// the mean (when the caller passes no buffer for it), then, for the two-pass
+// transform, its scratch
+size_t fft_workspace(const Plan& p) {
+  const size_t mean = (sizeof(double) * (size_t)p.M + 255) / 256 * 256;
+  return mean + long_scratch_bytes(p);
+}
 
 spod_status launch_blocks_fft(const Plan& p, const void* q, spod_dtype dtype, void* qhat,
                               double* mean, void* ws, hipStream_t st, const FftSel& fs) {
@@ -611,6 +616,11 @@ spod_status launch_blocks_fft(const Plan& p, const void* q, spod_dtype dtype, vo
                          (const double*)q, mu, (int64_t)p.M, (int64_t)p.nt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "mean_kernel");
+    if (long_scratch_bytes(p) > 0) {
+      if (!ws) return fail(SPOD_ERR_WORKSPACE, "the two-pass transform needs the plan's workspace");
+      char* scratch = static_cast<char*>(ws) + (sizeof(double) * (size_t)p.M + 255) / 256 * 256;
+      return launch_blocks_dft_long(p, q, dtype, mu, qhat, scratch, st);
+    }
     return launch_blocks_dft_general(p, q, dtype, mu, qhat, st);
   }
   // single pass when the window's DFT has few non-zero bins and the hop is a

@@ -671,6 +671,218 @@ spod_status launch_adjoint_t(const Plan& p, const void* g_qhat, void* g_q, const
   return launch_adjoint_pp<TC, TOUT, false, MAXU>(p, g_qhat, g_q, bins, gm, one_buf, st);
 }
 
+// ---------------------------------------------------------------------------
+// two-pass transform for blocks beyond one workgroup's LDS: N = A B
+// ---------------------------------------------------------------------------
+// A stage over G sequences of length n stored one after another in X (and
+// Y): the butterflies of every sequence in one loop.  Odd stages keep the
+// wavefront-uniform (sequence, output-pair group) of odd_stage.
+template <int KPT, typename TC>
+__device__ __forceinline__ void odd_stage_batched(const cpx_t<TC>* __restrict__ X,
+                                                  const cpx_t<TC>* __restrict__ T,
+                                                  const cpx_t<TC>* __restrict__ tw,
+                                                  cpx_t<TC>* __restrict__ Y, int tid, int n, int G,
+                                                  int r, int s, int m, int wn) {
+  const int NB = n / r;
+  const int h = (r + 1) / 2, hm = h - 1, GG = (h + KPT - 1) / KPT;
+  const int NBp = (NB + 63) & ~63;
+  const int per = NBp * GG;                   // a multiple of 64
+  const float inv_per = 1.0f / (float)per, inv_nbp = 1.0f / (float)NBp, inv_s = 1.0f / (float)s;
+  for (int it = tid; it < G * per; it += GEN_THREADS) {
+    const DivMod a = divmod(it, per, inv_per);
+    const int seq = __builtin_amdgcn_readfirstlane(a.q);
+    const int g = __builtin_amdgcn_readfirstlane(divmod(a.r, NBp, inv_nbp).q);
+    const int bf = a.r - g * NBp;
+    if (bf < NB)
+      odd_uniform<KPT, TC>(X + (size_t)seq * n, T + (size_t)g * hm * KPT, tw, Y + (size_t)seq * n, bf,
+                           g, GG, r, s, m, wn, inv_s);
+  }
+}
+
+template <typename TC>
+__device__ __forceinline__ void stage_batched(const cpx_t<TC>* __restrict__ X, cpx_t<TC>* __restrict__ Y,
+                                              const cpx_t<TC>* __restrict__ tw,
+                                              const cpx_t<TC>* __restrict__ oddw, const Radices& rad,
+                                              int st, int tid, int n, int G, int r, int s, int m, int wn) {
+  if (r % 2 == 1) {
+    const cpx_t<TC>* T = oddw + rad.toff[st];
+    switch (rad.kpt[st]) {
+      case 1: odd_stage_batched<1, TC>(X, T, tw, Y, tid, n, G, r, s, m, wn); break;
+      case 2: odd_stage_batched<2, TC>(X, T, tw, Y, tid, n, G, r, s, m, wn); break;
+      case 3: odd_stage_batched<3, TC>(X, T, tw, Y, tid, n, G, r, s, m, wn); break;
+      case 4: odd_stage_batched<4, TC>(X, T, tw, Y, tid, n, G, r, s, m, wn); break;
+      case 5: odd_stage_batched<5, TC>(X, T, tw, Y, tid, n, G, r, s, m, wn); break;
+      default: odd_stage_batched<6, TC>(X, T, tw, Y, tid, n, G, r, s, m, wn); break;
+    }
+  } else {
+    // the factorisation gives even radices 8, 4 and 2 only
+    const int NB = n / r;
+    const float inv_nb = 1.0f / (float)NB, inv_s = 1.0f / (float)s;
+    for (int it = tid; it < G * NB; it += GEN_THREADS) {
+      const DivMod a = divmod(it, NB, inv_nb);
+      const cpx_t<TC>* x = X + (size_t)a.q * n;
+      cpx_t<TC>* y = Y + (size_t)a.q * n;
+      if (r == 8) even_butterfly<8, TC>(x, tw, y, a.r, s, m, wn, n, inv_s);
+      else if (r == 4) even_butterfly<4, TC>(x, tw, y, a.r, s, m, wn, n, inv_s);
+      else even_butterfly<2, TC>(x, tw, y, a.r, s, m, wn, n, inv_s);
+    }
+  }
+}
+
+// G transforms of length n (tw = W_n^t), ping-pong between X and Y; returns
+// the buffer with the results.  The caller has synchronised after writing X.
+template <typename TC>
+__device__ __forceinline__ cpx_t<TC>* dft_batched(cpx_t<TC>* X, cpx_t<TC>* Y,
+                                                  const cpx_t<TC>* __restrict__ tw,
+                                                  const cpx_t<TC>* __restrict__ oddw,
+                                                  const Radices& rad, int tid, int n, int G) {
+  int nn = n, s = 1;
+  for (int st = 0; st < rad.n; ++st) {
+    const int r = rad.r[st];
+    const int m = nn / r;
+    stage_batched<TC>(X, Y, tw, oddw, rad, st, tid, n, G, r, s, m, n / nn);
+    __syncthreads();
+    cpx_t<TC>* tmp = X;
+    X = Y;
+    Y = tmp;
+    nn = m;
+    s *= r;
+  }
+  return X;
+}
+
+// One workgroup per CU, taking (pair of DOFs, block) items in turn.  With
+// n = B j + c (j < A, c < B) and k = k1 + A k2:
+//   pass 1: for the columns c, Y[k1][c] = W_N^{c k1} sum_j x[B j + c] W_A^{j k1}
+//           (GA columns per LDS batch; Y in this workgroup's workspace slot);
+//   pass 2: for the rows k1, X[k1 + A k2] = sum_c Y[k1][c] W_B^{c k2}, the
+//           rows k1 and (A - k1) mod A together (GB rows per batch), so that
+//           Z_k and Z_{N-k} of the two-for-one split are both in LDS.
+// The two rows of a pair are packed as a + i c; the window carries kappa.
+template <typename TC, typename TIN>
+__global__ __launch_bounds__(GEN_THREADS) void blocks_dft_long_kernel(
+    const TIN* __restrict__ q, const double* __restrict__ mean, const double* __restrict__ window,
+    const cpx_t<TC>* __restrict__ tw_n, const cpx_t<TC>* __restrict__ tw_a,
+    const cpx_t<TC>* __restrict__ oddw_a, Radices rad_a, const cpx_t<TC>* __restrict__ tw_b,
+    const cpx_t<TC>* __restrict__ oddw_b, Radices rad_b, int A, int B, int GA, int GB,
+    cpx_t<TC>* __restrict__ scratch, cpx_t<TC>* __restrict__ qhat, int64_t M, int64_t nt, int step,
+    int L, int K, double kappa) {
+  using C = cpx_t<TC>;
+  extern __shared__ unsigned char smem[];
+  const int cap = max(GA * A, GB * B);
+  C* const B0 = reinterpret_cast<C*>(smem);
+  C* const B1 = B0 + cap;
+  const int N = A * B;
+  C* const Yg = scratch + (size_t)blockIdx.x * N;          // [A][B]
+  const int64_t P = (M + 1) / 2;
+  const int tid = threadIdx.x;
+  const TC h = (TC)0.5;
+  const bool aligned = (M % 2 == 0);
+  for (int64_t item = blockIdx.x; item < P * L; item += gridDim.x) {
+    const int64_t pair = item / L;
+    const int l = (int)(item - pair * L);
+    const int64_t m0 = 2 * pair;
+    const bool two = m0 + 1 < M;
+    const double mu0 = mean[m0], mu1 = two ? mean[m0 + 1] : 0.0;
+    const TIN* r0 = q + m0 * nt + (int64_t)l * step;
+    const TIN* r1 = q + (two ? m0 + 1 : m0) * nt + (int64_t)l * step;
+
+    // pass 1
+    for (int c0 = 0; c0 < B; c0 += GA) {
+      const int gc = min(GA, B - c0);
+      for (int idx = tid; idx < gc * A; idx += GEN_THREADS) {
+        const int j = idx / gc, g = idx - j * gc;          // g fastest: consecutive samples
+        const int n = B * j + c0 + g;
+        const double w = window[n] * kappa;
+        B0[g * A + j] = mk<TC>((TC)(((double)r0[n] - mu0) * w),
+                               (TC)(two ? ((double)r1[n] - mu1) * w : 0.0));
+      }
+      __syncthreads();
+      const C* R = dft_batched<TC>(B0, B1, tw_a, oddw_a, rad_a, tid, A, gc);
+      for (int idx = tid; idx < gc * A; idx += GEN_THREADS) {
+        const int k1 = idx / gc, g = idx - k1 * gc;
+        const int c = c0 + g;
+        const C v = R[g * A + k1];
+        const C t = tw_n[c * k1];                            // c k1 < N
+        Yg[(size_t)k1 * B + c] = mk<TC>(v.x * t.x - v.y * t.y, v.x * t.y + v.y * t.x);
+      }
+      // Y written (global, this workgroup only) and the LDS free again
+      __syncthreads();
+    }
+
+    // pass 2: units u = 0 .. A/2, rows u and (A - u) mod A in slots 2i, 2i + 1
+    const int U = A / 2 + 1, upb = GB / 2;
+    for (int u0 = 0; u0 < U; u0 += upb) {
+      const int nu = min(upb, U - u0);
+      for (int idx = tid; idx < 2 * nu * B; idx += GEN_THREADS) {
+        const int slot = idx / B, c = idx - slot * B;
+        const int u = u0 + (slot >> 1);
+        const int row = (slot & 1) ? (A - u) % A : u;
+        B0[idx] = Yg[(size_t)row * B + c];
+      }
+      __syncthreads();
+      const C* R = dft_batched<TC>(B0, B1, tw_b, oddw_b, rad_b, tid, B, 2 * nu);
+      // split and store: row u (slot 2i) and, when it is another row, row A - u
+      for (int idx = tid; idx < 2 * nu * B; idx += GEN_THREADS) {
+        const int slot = idx / B, k2 = idx - slot * B;
+        const int u = u0 + (slot >> 1);
+        const bool second = slot & 1;
+        if (second && (u == 0 || 2 * u == A)) continue;     // the same row as slot 2i
+        const int k1 = second ? A - u : u;
+        const int64_t k = (int64_t)k1 + (int64_t)A * k2;
+        if (k >= K) continue;
+        // Z_{N-k}: row (A - k1) mod A = the other slot of this unit (the same
+        // slot for u = 0 and u = A/2), column (B - k2) mod B for k1 = 0, else
+        // B - 1 - k2
+        const int pslot = (u == 0 || 2 * u == A) ? slot : (slot ^ 1);
+        const int pk2 = (k1 == 0) ? (B - k2) % B : B - 1 - k2;
+        const C z = R[slot * B + k2], zc = R[pslot * B + pk2];
+        const C a = mk<TC>(h * (z.x + zc.x), h * (z.y - zc.y));
+        const C cc = mk<TC>(h * (z.y + zc.y), h * (zc.x - z.x));
+        C* dst = qhat + (k * L + l) * M + m0;
+        if constexpr (sizeof(TC) == 4) {
+          if (two && aligned) {
+            *reinterpret_cast<float4*>(dst) = make_float4(a.x, a.y, cc.x, cc.y);
+            continue;
+          }
+        }
+        dst[0] = a;
+        if (two) dst[1] = cc;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <typename TC, typename TIN>
+spod_status launch_long_t(const Plan& p, const TIN* q, const double* mean, void* qhat, void* scratch,
+                          hipStream_t st) {
+  using C = cpx_t<TC>;
+  constexpr size_t LDS_MAX = 160 * 1024;
+  const int A = p.long_a, B = p.long_b;
+  const int GA = (int)std::min<size_t>((size_t)B, LDS_MAX / (2 * sizeof(C) * (size_t)A));
+  const int GB = (int)(LDS_MAX / (2 * sizeof(C) * (size_t)B)) & ~1;
+  if (GA < 1 || GB < 2)
+    return fail(SPOD_ERR_UNSUPPORTED, "two-pass transform: a factor does not fit the LDS");
+  const size_t lds = 2 * sizeof(C) * (size_t)std::max(GA * A, GB * B);
+  const void* fn = reinterpret_cast<const void*>(&blocks_dft_long_kernel<TC, TIN>);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
+  const bool c8 = sizeof(TC) == 8;
+  hipLaunchKernelGGL((blocks_dft_long_kernel<TC, TIN>), dim3((unsigned)p.long_grid), dim3(GEN_THREADS),
+                     lds, st, q, mean, p.d_window,
+                     static_cast<const C*>(c8 ? (const void*)p.d_tw64 : (const void*)p.d_tw32),
+                     static_cast<const C*>(c8 ? (const void*)p.d_tw_a64 : (const void*)p.d_tw_a32),
+                     static_cast<const C*>(c8 ? (const void*)p.d_oddw_a64 : (const void*)p.d_oddw_a32),
+                     p.rad_a,
+                     static_cast<const C*>(c8 ? (const void*)p.d_tw_b64 : (const void*)p.d_tw_b32),
+                     static_cast<const C*>(c8 ? (const void*)p.d_oddw_b64 : (const void*)p.d_oddw_b32),
+                     p.rad_b, A, B, GA, GB, static_cast<C*>(scratch), static_cast<C*>(qhat),
+                     (int64_t)p.M, (int64_t)p.nt, (int)p.step, (int)p.nblocks, (int)p.nfreq, p.kappa);
+  e = hipGetLastError();
+  return e == hipSuccess ? SPOD_OK : hip_fail(e, "blocks_dft_long_kernel");
+}
+
 }  // namespace
 
 int general_odd_entries(int r, int kpt) {
@@ -735,6 +947,30 @@ spod_status launch_general_adjoint(const Plan& p, const void* g_qhat, spod_dtype
                 : launch_adjoint_t<float, float, UF>(p, g_qhat, g_q, bins, mean, st);
   return c128 ? launch_adjoint_t<double, double, UD>(p, g_qhat, g_q, bins, mean, st)
               : launch_adjoint_t<float, double, UF>(p, g_qhat, g_q, bins, mean, st);
+}
+
+}  // namespace spod
+
+namespace spod {
+
+// whether a plan's transform takes the two-pass path (precision dependent)
+static bool use_long(const Plan& p) {
+  return p.long_dft && p.nfft > (is_complex128(p) ? SPOD_GENERAL_MAX_NFFT / 2 : SPOD_GENERAL_MAX_NFFT);
+}
+
+size_t long_scratch_bytes(const Plan& p) {
+  if (!use_long(p)) return 0;
+  return (is_complex128(p) ? 16 : 8) * (size_t)p.long_grid * (size_t)p.nfft;
+}
+
+spod_status launch_blocks_dft_long(const Plan& p, const void* q, spod_dtype dtype,
+                                   const double* mean, void* qhat, void* scratch, hipStream_t st) {
+  const bool c128 = is_complex128(p);
+  if (dtype == SPOD_F32)
+    return c128 ? launch_long_t<double, float>(p, static_cast<const float*>(q), mean, qhat, scratch, st)
+                : launch_long_t<float, float>(p, static_cast<const float*>(q), mean, qhat, scratch, st);
+  return c128 ? launch_long_t<double, double>(p, static_cast<const double*>(q), mean, qhat, scratch, st)
+              : launch_long_t<float, double>(p, static_cast<const double*>(q), mean, qhat, scratch, st);
 }
 
 }  // namespace spod

@@ -37,6 +37,8 @@ constexpr int GENERAL_MAX_KPT = 6;
 constexpr int SPOD_MAX_NBLOCKS = 160;          // Gram, eigensolve and modes (backward, batch: 64)
 constexpr int SPOD_SMALL_NBLOCKS = 64;         // above this: the L > 64 kernels
 constexpr int SPOD_GENERAL_MAX_NFFT = 20480;   // complex64 blocks of one transform fill 160 KiB LDS
+constexpr int64_t SPOD_LONG_MAX_NFFT = int64_t(1) << 20;   // two-pass transform (N = A B) above that
+constexpr int SPOD_LONG_MAX_FACTOR = 4096;     // A, B: the sub-transform lengths
 
 struct Plan {
   int64_t nspace = 0, nvar = 0, M = 0, nt = 0, nfft = 0, noverlap = 0, step = 0;
@@ -60,6 +62,15 @@ struct Plan {
   // N_f not a power of two in [8, 1024]: the general transform and its radices
   bool general = false;
   Radices radices;
+  // N_f above SPOD_GENERAL_MAX_NFFT (complex128: half): the two-pass
+  // transform N = A B (four-step: A-point DFTs of the B columns, twiddles
+  // W_N^{c k1}, B-point DFTs of the A rows), with the rows and columns in LDS
+  // and the intermediate [A][B] in a workspace slot per workgroup
+  bool long_dft = false;
+  int long_a = 0, long_b = 0;       // A <= B
+  int long_ga = 0, long_gb = 0;     // columns, rows per LDS batch
+  int long_grid = 0;                // workgroups (one per CU)
+  Radices rad_a, rad_b;
 
   // options
   int max_sweeps = 40;
@@ -86,6 +97,15 @@ struct Plan {
   // min(g + c G, (r - 1) / 2), for g < G, j < (r - 1) / 2, c < kpt
   double2* d_oddw64 = nullptr;
   float2* d_oddw32 = nullptr;
+  // two-pass transform: W_A^t, W_B^t and the odd stages' tables of A and B
+  double2* d_tw_a64 = nullptr;
+  float2* d_tw_a32 = nullptr;
+  double2* d_tw_b64 = nullptr;
+  float2* d_tw_b32 = nullptr;
+  double2* d_oddw_a64 = nullptr;
+  float2* d_oddw_a32 = nullptr;
+  double2* d_oddw_b64 = nullptr;
+  float2* d_oddw_b32 = nullptr;
 };
 
 bool is_complex128(const Plan& p);
@@ -138,6 +158,10 @@ spod_status launch_blocks_fft(const Plan& p, const void* q, spod_dtype dtype, vo
 // the transform of steps 1-2 for any N_f (mean from the FP64 mean pass)
 spod_status launch_blocks_dft_general(const Plan& p, const void* q, spod_dtype dtype,
                                       const double* mean, void* qhat, hipStream_t st);
+// the two-pass transform (p.long_dft); scratch: p.long_grid * N complex
+spod_status launch_blocks_dft_long(const Plan& p, const void* q, spod_dtype dtype,
+                                   const double* mean, void* qhat, void* scratch, hipStream_t st);
+size_t long_scratch_bytes(const Plan& p);
 // Adjoint of that transform (and of the mean removal) for the selected bins:
 // g_q = dE/dq from g_qhat = dE/dqhat [bins.n][L][M].  bins: strictly
 // increasing frequencies; mean: the selected bins whose window DFT is not

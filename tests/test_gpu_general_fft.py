@@ -89,13 +89,20 @@ def test_hourly_year_blocks_end_to_end():
 
 
 def test_general_transform_limits():
-    from paper_2309_11808_amd import SpodError
+    from paper_2309_11808_amd import Plan, SpodError
     p = fields.random_rows(4, 3 * 12000, 12000, 0, seed=1, dtype=torch.float64)
-    plan = _plan(p, "fp64")                     # complex128 blocks: at most 10240
-    with pytest.raises(SpodError) as ei:
-        plan.blocks_fft(p.q.cuda())
-    assert ei.value.status == -2
+    plan = _plan(p, "fp64")                     # complex128 above 10240: the two-pass transform
+    qhat, _ = plan.blocks_fft(p.q.cuda())
+    torch.cuda.synchronize()
+    ref = O.fourier_blocks(p.q.numpy(), 12000, 0, O.hann_periodic(12000),
+                           O.temporal_mean(p.q.numpy()), None, dft="fft")
+    err = PT.check_qhat(qhat.cpu().numpy(), ref, 1e-12)
+    print(f"N=12000 (two passes, 100 x 120): complex128 qhat rel err {err:.2e}")
     plan.close()
+    # above 20480 the length must split into two factors <= 4096 (a prime cannot)
+    with pytest.raises(SpodError) as ei:
+        Plan(4, 1, 3 * 20483, 20483, 0)
+    assert ei.value.status == -2
     plan = _plan(p, "fp32")                     # complex64 blocks: one LDS buffer above ~10200
     q32 = p.q.float()
     qhat, _ = plan.blocks_fft(q32.cuda())
@@ -118,4 +125,60 @@ def test_backward_general_length_without_blocks_is_refused():
     with pytest.raises(SpodError) as ei:
         plan.backward(p.q.cuda(), out["lam"], out["psi"], g_lam=torch.ones_like(out["lam"]))
     assert ei.value.status == -2
+    plan.close()
+
+
+# ---------------------------------------------------------------------------
+# blocks beyond one workgroup's LDS: the two-pass transform N = A B (A the
+# largest divisor <= sqrt(N)); the oracle's library-FFT form of the transform
+# ---------------------------------------------------------------------------
+LONG_CASES = [  # nfft, noverlap, M, L
+    (30030, 15015, 5, 2),      # 2 3 5 7 11 13: A = 165, B = 182
+    (40960, 20480, 4, 2),      # 2^13 5: A = 160, B = 256
+    (65536, 0, 3, 2),          # 2^16: A = B = 256
+    (87600, 43800, 6, 3),      # the paper's ten-year hourly blocks: A = 292, B = 300
+]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16x4"])
+@pytest.mark.parametrize("nfft,nov,M,L", LONG_CASES, ids=[f"N{c[0]}" for c in LONG_CASES])
+def test_long_blocks_match_oracle(nfft, nov, M, L, precision):
+    nt = (L - 1) * (nfft - nov) + nfft + 5
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    p = fields.random_rows(M, nt, nfft, nov, seed=nfft % 1000, offset=1.5, dtype=dt)
+    plan = _plan(p, precision)
+    assert plan.nblocks == L
+    qhat, mean = plan.blocks_fft(p.q.cuda())
+    torch.cuda.synchronize()
+    q64 = p.q.double().numpy()
+    ref_mean = O.temporal_mean(q64)
+    ref = O.fourier_blocks(q64, nfft, nov, O.hann_periodic(nfft), ref_mean, None, dft="fft")
+    np.testing.assert_allclose(mean.cpu().numpy(), ref_mean, rtol=0, atol=1e-13 * 3)
+    err = PT.check_qhat(qhat.cpu().numpy(), ref, 1e-12 if precision == "fp64" else 2e-6)
+    print(f"N={nfft} two passes: {precision} qhat rel err {err:.2e}")
+    plan.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp16x4"])
+def test_ten_year_blocks_end_to_end(precision):
+    """N_f = 87,600 hourly samples (ten years), 50% overlap, L = 8 blocks as in
+    the paper's ERA5 analysis: eigenvalues at 8 frequencies against the
+    oracle (library-FFT form of the transform)."""
+    nfft, nov, M, L = 87600, 43800, 96, 8
+    nt = (L - 1) * (nfft - nov) + nfft
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    p = fields.random_rows(M, nt, nfft, nov, seed=876, offset=0.5, dtype=dt)
+    bins = [0, 1, 2, 10, 365, 1000, 20000, nfft // 2]
+    ref = O.spod_chunked(p.q.double().numpy(), nfft, nov, weights=p.weights, n_modes=3,
+                         chunk=32, bins=bins, want_modes=False, dft="fft")
+    plan = _plan(p, precision)
+    out = plan.forward(p.q.cuda(), n_modes=3)
+    torch.cuda.synchronize()
+    lam = out["lam"].index_select(0, torch.as_tensor(bins, device="cuda")).cpu().numpy()
+    if precision == "fp64":
+        err = PT.check_eig(lam, ref["lam"], rtol=1e-10, n=3)
+    else:
+        err = PT.check_eig_mixed(lam, ref["lam"], n=3)
+    assert int(out["info"].min()) > 0
+    print(f"N=87600, L=8 end to end ({precision}): leading eigenvalue rel err {err:.2e}")
     plan.close()
