@@ -100,8 +100,13 @@ typedef enum {
                               (0 = automatic: 32 for nfft <= 256, else 16)            */
   SPOD_OPT_QHAT_FORMAT = 3, /* storage of qhat: SPOD_QHAT_COMPLEX (default) or
                               SPOD_QHAT_BFP20 (complex64 forms, power-of-two nfft)    */
-  SPOD_OPT_MODES_KERNEL = 4  /* complex64 modes of complex qhat: 0 = vector ALU (default),
+  SPOD_OPT_MODES_KERNEL = 4, /* complex64 modes of complex qhat: 0 = vector ALU (default),
                               1 = v_mfma_f32_16x16x4f32 (FP32 products and sums)      */
+  SPOD_OPT_GENERAL_PASSES = 5 /* transform of an nfft other than a power of two <= 1024:
+                              0 = automatic (one pass while the block fits one
+                              workgroup's LDS, else two), 1 = one pass, 2 = two passes
+                              (nfft > 1024 with two factors <= 4096, else
+                              SPOD_ERR_UNSUPPORTED here)                                 */
 } spod_option;
 
 /* Storage of the Fourier blocks qhat between the stages.

@@ -37,6 +37,7 @@ SPOD_OPT_GRAM_SPLIT = 1
 SPOD_OPT_FFT_TILE = 2
 SPOD_OPT_QHAT_FORMAT = 3
 SPOD_OPT_MODES_KERNEL = 4
+SPOD_OPT_GENERAL_PASSES = 5
 
 SPOD_QHAT_COMPLEX = 0
 SPOD_QHAT_BFP20 = 1

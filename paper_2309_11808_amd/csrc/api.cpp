@@ -326,9 +326,10 @@ spod_status spod_plan_create(int64_t nspace, int64_t nvar, int64_t nt, int64_t n
     // above what one workgroup's LDS holds (complex64 above 20480, complex128
     // above 10240): the two-pass transform N = A B, A the largest divisor
     // <= sqrt(N) (both at most SPOD_LONG_MAX_FACTOR).  Its tables are built
-    // from N > 10240 on; the precision picks the path at launch.
+    // for every general N above 1024; the precision and SPOD_OPT_GENERAL_PASSES
+    // pick the path at launch.
     int odd_a = 0, odd_b = 0;
-    if (nfft > SPOD_GENERAL_MAX_NFFT / 2) {
+    if (p->general && nfft > 1024) {
       int64_t a = 1;
       for (int64_t d = 2; d * d <= nfft; ++d)
         if (nfft % d == 0) a = d;
@@ -552,6 +553,14 @@ spod_status spod_plan_set_option(spod_plan plan, spod_option opt, int64_t value)
       if (value != 0 && value != 1)
         return fail(SPOD_ERR_INVALID_ARG, "modes kernel must be 0 (vector ALU) or 1 (matrix cores)");
       p->modes_mfma = value == 1;
+      break;
+    case SPOD_OPT_GENERAL_PASSES:
+      if (value != 0 && value != 1 && value != 2)
+        return fail(SPOD_ERR_INVALID_ARG, "general passes must be 0, 1 or 2");
+      if (value == 2 && !p->long_dft)
+        return fail(SPOD_ERR_UNSUPPORTED,
+                    "two passes need nfft > 1024, not a power of two, with two factors <= 4096");
+      p->general_passes = (int)value;
       break;
     case SPOD_OPT_QHAT_FORMAT:
       if (value != SPOD_QHAT_COMPLEX && value != SPOD_QHAT_BFP20)

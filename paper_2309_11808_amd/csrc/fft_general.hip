@@ -675,8 +675,11 @@ spod_status launch_adjoint_t(const Plan& p, const void* g_qhat, void* g_q, const
 // two-pass transform for blocks beyond one workgroup's LDS: N = A B
 // ---------------------------------------------------------------------------
 // A stage over G sequences of length n stored one after another in X (and
-// Y): the butterflies of every sequence in one loop.  Odd stages keep the
-// wavefront-uniform (sequence, output-pair group) of odd_stage.
+// Y): the butterflies of every sequence in one loop.  In an odd stage the
+// work items are ordered by output-pair group g first, then by sequence and
+// butterfly (padded to a multiple of 64 once per g, not per sequence, since
+// a short sequence has few butterflies), so g stays wavefront-uniform and
+// its row of the stage's table is read through scalar loads as in odd_stage.
 template <int KPT, typename TC>
 __device__ __forceinline__ void odd_stage_batched(const cpx_t<TC>* __restrict__ X,
                                                   const cpx_t<TC>* __restrict__ T,
@@ -685,17 +688,17 @@ __device__ __forceinline__ void odd_stage_batched(const cpx_t<TC>* __restrict__ 
                                                   int r, int s, int m, int wn) {
   const int NB = n / r;
   const int h = (r + 1) / 2, hm = h - 1, GG = (h + KPT - 1) / KPT;
-  const int NBp = (NB + 63) & ~63;
-  const int per = NBp * GG;                   // a multiple of 64
-  const float inv_per = 1.0f / (float)per, inv_nbp = 1.0f / (float)NBp, inv_s = 1.0f / (float)s;
-  for (int it = tid; it < G * per; it += GEN_THREADS) {
-    const DivMod a = divmod(it, per, inv_per);
-    const int seq = __builtin_amdgcn_readfirstlane(a.q);
-    const int g = __builtin_amdgcn_readfirstlane(divmod(a.r, NBp, inv_nbp).q);
-    const int bf = a.r - g * NBp;
-    if (bf < NB)
-      odd_uniform<KPT, TC>(X + (size_t)seq * n, T + (size_t)g * hm * KPT, tw, Y + (size_t)seq * n, bf,
-                           g, GG, r, s, m, wn, inv_s);
+  const int per = G * NB;                     // butterflies of all sequences
+  const int perp = (per + 63) & ~63;
+  const float inv_perp = 1.0f / (float)perp, inv_nb = 1.0f / (float)NB, inv_s = 1.0f / (float)s;
+  for (int it = tid; it < GG * perp; it += GEN_THREADS) {
+    const DivMod a = divmod(it, perp, inv_perp);
+    const int g = __builtin_amdgcn_readfirstlane(a.q);
+    if (a.r < per) {
+      const DivMod b = divmod(a.r, NB, inv_nb);      // (sequence, butterfly)
+      odd_uniform<KPT, TC>(X + (size_t)b.q * n, T + (size_t)g * hm * KPT, tw, Y + (size_t)b.q * n,
+                           b.r, g, GG, r, s, m, wn, inv_s);
+    }
   }
 }
 
@@ -751,80 +754,128 @@ __device__ __forceinline__ cpx_t<TC>* dft_batched(cpx_t<TC>* X, cpx_t<TC>* Y,
   return X;
 }
 
-// One workgroup per CU, taking (pair of DOFs, block) items in turn.  With
-// n = B j + c (j < A, c < B) and k = k1 + A k2:
-//   pass 1: for the columns c, Y[k1][c] = W_N^{c k1} sum_j x[B j + c] W_A^{j k1}
-//           (GA columns per LDS batch; Y in this workgroup's workspace slot);
-//   pass 2: for the rows k1, X[k1 + A k2] = sum_c Y[k1][c] W_B^{c k2}, the
-//           rows k1 and (A - k1) mod A together (GB rows per batch), so that
-//           Z_k and Z_{N-k} of the two-for-one split are both in LDS.
+// Loads per thread issued together when a batch is brought into LDS.
+constexpr int LONG_U = 4;
+
+// One workgroup per CU, taking (tile of up to P pairs of DOFs, block) items in
+// turn.  With n = B j + c (j < A, c < B) and k = k1 + A k2:
+//   pass 1: for every pair p and column c, Y_p[k1][c] = W_N^{c k1}
+//           sum_j x_p[B j + c] W_A^{j k1} (GA sequences of length A per LDS
+//           batch; Y in this workgroup's workspace slot, [P][A][B]);
+//   pass 2: for the rows k1, X_p[k1 + A k2] = sum_c Y_p[k1][c] W_B^{c k2}, the
+//           rows k1 and (A - k1) mod A of every pair side by side (NU of
+//           these units per batch), so that Z_k and Z_{N-k} of the
+//           two-for-one split are both in LDS, and the P pairs' values of one
+//           frequency row are stored by neighbouring lanes: P * 16 bytes
+//           contiguous (a whole 128-byte line at P = 8) instead of 16.
 // The two rows of a pair are packed as a + i c; the window carries kappa.
 template <typename TC, typename TIN>
 __global__ __launch_bounds__(GEN_THREADS) void blocks_dft_long_kernel(
     const TIN* __restrict__ q, const double* __restrict__ mean, const double* __restrict__ window,
     const cpx_t<TC>* __restrict__ tw_n, const cpx_t<TC>* __restrict__ tw_a,
     const cpx_t<TC>* __restrict__ oddw_a, Radices rad_a, const cpx_t<TC>* __restrict__ tw_b,
-    const cpx_t<TC>* __restrict__ oddw_b, Radices rad_b, int A, int B, int GA, int GB,
+    const cpx_t<TC>* __restrict__ oddw_b, Radices rad_b, int A, int B, int GA, int NU, int P,
     cpx_t<TC>* __restrict__ scratch, cpx_t<TC>* __restrict__ qhat, int64_t M, int64_t nt, int step,
     int L, int K, double kappa) {
   using C = cpx_t<TC>;
   extern __shared__ unsigned char smem[];
-  const int cap = max(GA * A, GB * B);
+  const int N = A * B;
+  const int cap = max(GA * A, 2 * NU * P * B);
   C* const B0 = reinterpret_cast<C*>(smem);
   C* const B1 = B0 + cap;
-  const int N = A * B;
-  C* const Yg = scratch + (size_t)blockIdx.x * N;          // [A][B]
-  const int64_t P = (M + 1) / 2;
+  C* const Yg = scratch + (size_t)blockIdx.x * P * N;       // [P][A][B]
+  const int64_t npair = (M + 1) / 2;
+  const int64_t ntile = (npair + P - 1) / P;
   const int tid = threadIdx.x;
   const TC h = (TC)0.5;
   const bool aligned = (M % 2 == 0);
-  for (int64_t item = blockIdx.x; item < P * L; item += gridDim.x) {
-    const int64_t pair = item / L;
-    const int l = (int)(item - pair * L);
-    const int64_t m0 = 2 * pair;
-    const bool two = m0 + 1 < M;
-    const double mu0 = mean[m0], mu1 = two ? mean[m0 + 1] : 0.0;
-    const TIN* r0 = q + m0 * nt + (int64_t)l * step;
-    const TIN* r1 = q + (two ? m0 + 1 : m0) * nt + (int64_t)l * step;
+  for (int64_t item = blockIdx.x; item < ntile * L; item += gridDim.x) {
+    const int64_t tile = item / L;
+    const int l = (int)(item - tile * L);
+    const int64_t pair0 = tile * P;
+    const int np = (int)min((int64_t)P, npair - pair0);
 
-    // pass 1
-    for (int c0 = 0; c0 < B; c0 += GA) {
-      const int gc = min(GA, B - c0);
-      for (int idx = tid; idx < gc * A; idx += GEN_THREADS) {
-        const int j = idx / gc, g = idx - j * gc;          // g fastest: consecutive samples
-        const int n = B * j + c0 + g;
-        const double w = window[n] * kappa;
-        B0[g * A + j] = mk<TC>((TC)(((double)r0[n] - mu0) * w),
-                               (TC)(two ? ((double)r1[n] - mu1) * w : 0.0));
+    // pass 1: sequences s = p B + c of length A, GA per batch
+    for (int s0 = 0; s0 < np * B; s0 += GA) {
+      const int gs = min(GA, np * B - s0);
+      // LONG_U loads per thread in flight, then their LDS writes
+      for (int i0 = tid; i0 < gs * A; i0 += LONG_U * GEN_THREADS) {
+        TIN va[LONG_U], vc[LONG_U];
+        double vw[LONG_U], mu[LONG_U], mc[LONG_U];
+        bool tw2[LONG_U];
+#pragma unroll
+        for (int u = 0; u < LONG_U; ++u) {
+          const int idx = i0 + u * GEN_THREADS;
+          if (idx < gs * A) {
+            const int j = idx / gs, g = idx - j * gs;      // g fastest: consecutive samples
+            const int sq = s0 + g, pp = sq / B, c = sq - pp * B;
+            const int64_t m0 = 2 * (pair0 + pp);
+            const bool two = m0 + 1 < M;
+            const int64_t n = (int64_t)l * step + B * j + c;
+            va[u] = q[m0 * nt + n];
+            vc[u] = q[(two ? m0 + 1 : m0) * nt + n];
+            vw[u] = window[B * j + c];
+            mu[u] = mean[m0];
+            mc[u] = two ? mean[m0 + 1] : 0.0;
+            tw2[u] = two;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < LONG_U; ++u) {
+          const int idx = i0 + u * GEN_THREADS;
+          if (idx < gs * A) {
+            const int j = idx / gs, g = idx - j * gs;
+            const double w = vw[u] * kappa;
+            B0[g * A + j] = mk<TC>((TC)(((double)va[u] - mu[u]) * w),
+                                   (TC)(tw2[u] ? ((double)vc[u] - mc[u]) * w : 0.0));
+          }
+        }
       }
       __syncthreads();
-      const C* R = dft_batched<TC>(B0, B1, tw_a, oddw_a, rad_a, tid, A, gc);
-      for (int idx = tid; idx < gc * A; idx += GEN_THREADS) {
-        const int k1 = idx / gc, g = idx - k1 * gc;
-        const int c = c0 + g;
+      const C* R = dft_batched<TC>(B0, B1, tw_a, oddw_a, rad_a, tid, A, gs);
+      for (int idx = tid; idx < gs * A; idx += GEN_THREADS) {
+        const int k1 = idx / gs, g = idx - k1 * gs;
+        const int sq = s0 + g, pp = sq / B, c = sq - pp * B;
         const C v = R[g * A + k1];
         const C t = tw_n[c * k1];                            // c k1 < N
-        Yg[(size_t)k1 * B + c] = mk<TC>(v.x * t.x - v.y * t.y, v.x * t.y + v.y * t.x);
+        Yg[(size_t)pp * N + (size_t)k1 * B + c] = mk<TC>(v.x * t.x - v.y * t.y, v.x * t.y + v.y * t.x);
       }
       // Y written (global, this workgroup only) and the LDS free again
       __syncthreads();
     }
 
-    // pass 2: units u = 0 .. A/2, rows u and (A - u) mod A in slots 2i, 2i + 1
-    const int U = A / 2 + 1, upb = GB / 2;
-    for (int u0 = 0; u0 < U; u0 += upb) {
-      const int nu = min(upb, U - u0);
-      for (int idx = tid; idx < 2 * nu * B; idx += GEN_THREADS) {
-        const int slot = idx / B, c = idx - slot * B;
-        const int u = u0 + (slot >> 1);
-        const int row = (slot & 1) ? (A - u) % A : u;
-        B0[idx] = Yg[(size_t)row * B + c];
+    // pass 2: units u = 0 .. A/2, rows u and (A - u) mod A; sequence
+    // (slot, pair) = slot np + p, slot 2i the row u of unit u0 + i, slot 2i + 1
+    // its partner
+    const int U = A / 2 + 1;
+    for (int u0 = 0; u0 < U; u0 += NU) {
+      const int nu = min(NU, U - u0), nseq = 2 * nu * np;
+      for (int i0 = tid; i0 < nseq * B; i0 += LONG_U * GEN_THREADS) {
+        C vy[LONG_U];
+#pragma unroll
+        for (int v = 0; v < LONG_U; ++v) {
+          const int idx = i0 + v * GEN_THREADS;
+          if (idx < nseq * B) {
+            const int sq = idx / B, c = idx - sq * B;
+            const int slot = sq / np, pp = sq - slot * np;
+            const int u = u0 + (slot >> 1);
+            const int row = (slot & 1) ? (A - u) % A : u;
+            vy[v] = Yg[(size_t)pp * N + (size_t)row * B + c];
+          }
+        }
+#pragma unroll
+        for (int v = 0; v < LONG_U; ++v) {
+          const int idx = i0 + v * GEN_THREADS;
+          if (idx < nseq * B) B0[idx] = vy[v];
+        }
       }
       __syncthreads();
-      const C* R = dft_batched<TC>(B0, B1, tw_b, oddw_b, rad_b, tid, B, 2 * nu);
-      // split and store: row u (slot 2i) and, when it is another row, row A - u
-      for (int idx = tid; idx < 2 * nu * B; idx += GEN_THREADS) {
-        const int slot = idx / B, k2 = idx - slot * B;
+      const C* R = dft_batched<TC>(B0, B1, tw_b, oddw_b, rad_b, tid, B, nseq);
+      // split and store: pairs fastest, so neighbouring lanes write one
+      // frequency row's consecutive DOFs
+      for (int idx = tid; idx < 2 * nu * B * np; idx += GEN_THREADS) {
+        const int pp = idx % np, rest = idx / np;
+        const int k2 = rest % B, slot = rest / B;
         const int u = u0 + (slot >> 1);
         const bool second = slot & 1;
         if (second && (u == 0 || 2 * u == A)) continue;     // the same row as slot 2i
@@ -836,9 +887,11 @@ __global__ __launch_bounds__(GEN_THREADS) void blocks_dft_long_kernel(
         // B - 1 - k2
         const int pslot = (u == 0 || 2 * u == A) ? slot : (slot ^ 1);
         const int pk2 = (k1 == 0) ? (B - k2) % B : B - 1 - k2;
-        const C z = R[slot * B + k2], zc = R[pslot * B + pk2];
+        const C z = R[(slot * np + pp) * B + k2], zc = R[(pslot * np + pp) * B + pk2];
         const C a = mk<TC>(h * (z.x + zc.x), h * (z.y - zc.y));
         const C cc = mk<TC>(h * (z.y + zc.y), h * (zc.x - z.x));
+        const int64_t m0 = 2 * (pair0 + pp);
+        const bool two = m0 + 1 < M;
         C* dst = qhat + (k * L + l) * M + m0;
         if constexpr (sizeof(TC) == 4) {
           if (two && aligned) {
@@ -854,31 +907,57 @@ __global__ __launch_bounds__(GEN_THREADS) void blocks_dft_long_kernel(
   }
 }
 
+// Workgroups per CU of the two-pass transform (measured with one pair per
+// item: one with all the LDS, 184 ms on the ten-year workload, against 212
+// ms for two with half).
+constexpr int LONG_WG_PER_CU = 1;
+
+// Launch shape of the two-pass transform: P pairs per item (8, fewer when
+// the pass-2 batch or the scratch, at most 2 GiB, does not allow it), GA
+// sequences per pass-1 batch, NU units per pass-2 batch.
+struct LongShape {
+  int P = 0, GA = 0, NU = 0;
+  size_t lds = 0, scratch = 0;
+};
+
+LongShape long_shape(const Plan& p) {
+  LongShape sh;
+  const size_t csz = is_complex128(p) ? 16 : 8;
+  const int64_t cap = (int64_t)(160 * 1024 / LONG_WG_PER_CU / 2 / csz);   // elements per buffer
+  const int A = p.long_a, B = p.long_b;
+  const int64_t grid = (int64_t)p.long_grid * LONG_WG_PER_CU;
+  int P = (int)std::min<int64_t>(8, cap / B / 2);
+  while (P > 1 && grid * P * p.nfft * (int64_t)csz > (int64_t(2) << 30)) --P;
+  if (P < 1 || cap / A < 1) return sh;
+  sh.P = P;
+  sh.GA = (int)std::min<int64_t>((int64_t)P * B, cap / A);
+  sh.NU = (int)std::max<int64_t>(1, cap / B / (2 * P));
+  sh.lds = 2 * csz * (size_t)std::max<int64_t>((int64_t)sh.GA * A, 2LL * sh.NU * P * B);
+  sh.scratch = csz * (size_t)grid * (size_t)P * (size_t)p.nfft;
+  return sh;
+}
+
 template <typename TC, typename TIN>
 spod_status launch_long_t(const Plan& p, const TIN* q, const double* mean, void* qhat, void* scratch,
                           hipStream_t st) {
   using C = cpx_t<TC>;
-  constexpr size_t LDS_MAX = 160 * 1024;
-  const int A = p.long_a, B = p.long_b;
-  const int GA = (int)std::min<size_t>((size_t)B, LDS_MAX / (2 * sizeof(C) * (size_t)A));
-  const int GB = (int)(LDS_MAX / (2 * sizeof(C) * (size_t)B)) & ~1;
-  if (GA < 1 || GB < 2)
-    return fail(SPOD_ERR_UNSUPPORTED, "two-pass transform: a factor does not fit the LDS");
-  const size_t lds = 2 * sizeof(C) * (size_t)std::max(GA * A, GB * B);
+  const LongShape sh = long_shape(p);
+  if (sh.P < 1) return fail(SPOD_ERR_UNSUPPORTED, "two-pass transform: a factor does not fit the LDS");
   const void* fn = reinterpret_cast<const void*>(&blocks_dft_long_kernel<TC, TIN>);
-  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds);
   if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
   const bool c8 = sizeof(TC) == 8;
-  hipLaunchKernelGGL((blocks_dft_long_kernel<TC, TIN>), dim3((unsigned)p.long_grid), dim3(GEN_THREADS),
-                     lds, st, q, mean, p.d_window,
+  hipLaunchKernelGGL((blocks_dft_long_kernel<TC, TIN>), dim3((unsigned)(p.long_grid * LONG_WG_PER_CU)),
+                     dim3(GEN_THREADS), sh.lds, st, q, mean, p.d_window,
                      static_cast<const C*>(c8 ? (const void*)p.d_tw64 : (const void*)p.d_tw32),
                      static_cast<const C*>(c8 ? (const void*)p.d_tw_a64 : (const void*)p.d_tw_a32),
                      static_cast<const C*>(c8 ? (const void*)p.d_oddw_a64 : (const void*)p.d_oddw_a32),
                      p.rad_a,
                      static_cast<const C*>(c8 ? (const void*)p.d_tw_b64 : (const void*)p.d_tw_b32),
                      static_cast<const C*>(c8 ? (const void*)p.d_oddw_b64 : (const void*)p.d_oddw_b32),
-                     p.rad_b, A, B, GA, GB, static_cast<C*>(scratch), static_cast<C*>(qhat),
-                     (int64_t)p.M, (int64_t)p.nt, (int)p.step, (int)p.nblocks, (int)p.nfreq, p.kappa);
+                     p.rad_b, p.long_a, p.long_b, sh.GA, sh.NU, sh.P, static_cast<C*>(scratch),
+                     static_cast<C*>(qhat), (int64_t)p.M, (int64_t)p.nt, (int)p.step, (int)p.nblocks,
+                     (int)p.nfreq, p.kappa);
   e = hipGetLastError();
   return e == hipSuccess ? SPOD_OK : hip_fail(e, "blocks_dft_long_kernel");
 }
@@ -955,12 +1034,14 @@ namespace spod {
 
 // whether a plan's transform takes the two-pass path (precision dependent)
 static bool use_long(const Plan& p) {
-  return p.long_dft && p.nfft > (is_complex128(p) ? SPOD_GENERAL_MAX_NFFT / 2 : SPOD_GENERAL_MAX_NFFT);
+  if (!p.long_dft || p.general_passes == 1) return false;
+  return p.general_passes == 2 ||
+         p.nfft > (is_complex128(p) ? SPOD_GENERAL_MAX_NFFT / 2 : SPOD_GENERAL_MAX_NFFT);
 }
 
 size_t long_scratch_bytes(const Plan& p) {
   if (!use_long(p)) return 0;
-  return (is_complex128(p) ? 16 : 8) * (size_t)p.long_grid * (size_t)p.nfft;
+  return long_shape(p).scratch;
 }
 
 spod_status launch_blocks_dft_long(const Plan& p, const void* q, spod_dtype dtype,

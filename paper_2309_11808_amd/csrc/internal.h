@@ -78,6 +78,7 @@ struct Plan {
   int64_t fft_tile_opt = 0;
   bool qhat_packed = false;   // SPOD_QHAT_BFP20: qhat in the packed layout below
   bool modes_mfma = false;    // complex64 modes on the matrix cores (SPOD_OPT_MODES_KERNEL)
+  int general_passes = 0;     // SPOD_OPT_GENERAL_PASSES: 0 automatic, 1 or 2
 
   // derived launch shapes (fixed when frozen)
   int gram_split = 1;       // slices of M per frequency

@@ -82,7 +82,8 @@ class Plan:
                 self.packed = v == N.SPOD_QHAT_BFP20
             opt = {"max_sweeps": N.SPOD_OPT_MAX_SWEEPS, "gram_split": N.SPOD_OPT_GRAM_SPLIT,
                    "fft_tile": N.SPOD_OPT_FFT_TILE, "qhat_format": N.SPOD_OPT_QHAT_FORMAT,
-                   "modes_kernel": N.SPOD_OPT_MODES_KERNEL}[k]
+                   "modes_kernel": N.SPOD_OPT_MODES_KERNEL,
+                   "general_passes": N.SPOD_OPT_GENERAL_PASSES}[k]
             if k == "modes_kernel":
                 v = {"valu": 0, "mfma": 1}.get(v, v)
             _check(lib().spod_plan_set_option(self._h, opt, int(v)))
