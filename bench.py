@@ -60,13 +60,13 @@ METRIC = "SPOD input GB/s (FFT+CSD+eig+modes), mixed vs FP64 at eig rel err ≤1
 HBM_PEAK_GBS = 8000.0
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spod_blocks_fft_era_1024x512x2_nt8192_bf16x4_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spod_blocks_fft_era_1024x512x2_nt8192_complex64_traffic.txt")
 
 
 def committed_traffic():
     """HBM bytes per spod_blocks_fft launch from the committed FETCH_SIZE /
-    WRITE_SIZE counter runs, or None once the transform's source differs from
-    the one the counters were taken on."""
+    WRITE_SIZE counter runs, or None once the transform's sources (fft.hip,
+    fft_core.h, internal.h) differ from the ones the counters were taken on."""
     import hashlib
     import re
     try:
@@ -78,7 +78,7 @@ def committed_traffic():
     if not t or not h:
         return None
     d = hashlib.sha256()
-    for f in ("fft.hip", "fft_core.h"):
+    for f in ("fft.hip", "fft_core.h", "internal.h"):
         with open(os.path.join(ROOT, "paper_2309_11808_amd", "csrc", f), "rb") as fh:
             d.update(fh.read())
     return int(t.group(1)) if d.hexdigest() == h.group(1) else None
