@@ -3,7 +3,7 @@
     python bench.py [--gpus 1] [--steps 10] [--warmup 3] [--precision fp16x4]
                     [--workload era|jet] [--no-fp64] [--no-cpu] [--no-diff] [--no-batch]
                     [--no-ooc] [--ooc-only] [--no-coeffs] [--coeffs-only]
-                    [--no-hourly] [--hourly-only]
+                    [--no-hourly] [--hourly-only] [--no-ten-year] [--ten-year-only]
 
 A step is one pass of the whole path over the resident input: temporal mean +
 windowed block FFT (spod_blocks_fft), weighted Gram (spod_csd), batched
@@ -24,10 +24,13 @@ frequencies), cos(latitude) weights; red noise plus 6 planted modes, generated
 on the device from a seed.  Prints one JSON line on stdout; progress goes to
 stderr.
 
-More measurements ride on the same line (skipped with --no-hourly, --no-coeffs,
---no-ooc, --no-diff and --no-batch):
+More measurements ride on the same line (skipped with --no-hourly,
+--no-ten-year, --no-coeffs, --no-ooc, --no-diff and --no-batch):
   * hourly: a block length that is not a power of two (N_f = 8760, one year of
     hourly records, 256 x 256 grid, N_t = 39,420, L = 8), whole path;
+  * ten_year: blocks beyond one workgroup's LDS (N_f = 87,600, ten years of
+    hourly records, 128 x 128 grid, N_t = 394,200, L = 8; the two-pass
+    transform), whole path;
   * coefficients: expansion coefficients (spod_coeffs) of the same field over
     the 5 leading modes of its 64 lowest frequencies (R = 320) and the
     reconstruction from them (spod_reconstruct), against FP64 MFMA peak;
@@ -41,8 +44,9 @@ More measurements ride on the same line (skipped with --no-hourly, --no-coeffs,
     recomputed; reported as forward ms, backward ms and (fwd + bwd) / fwd, on
     the FP64 and the mixed path;
   * batching: 64 uneven problems from the batch generator (seed 4), the mixed
-    path, grouped launches replayed from a hipGraph with the autotuned Gram
-    split, against one launch per problem and stage.
+    path, grouped launches replayed from a hipGraph with the autotuned launch
+    shapes (recorded with every candidate's time), against one launch per
+    problem and stage, with a summed per-problem HBM roofline.
 """
 from __future__ import annotations
 
@@ -678,6 +682,7 @@ def main(argv=None):
     ap.add_argument("--no-ooc", action="store_true")
     ap.add_argument("--no-coeffs", action="store_true")
     ap.add_argument("--no-hourly", action="store_true")
+    ap.add_argument("--no-ten-year", action="store_true")
     ap.add_argument("--ten-year-only", action="store_true",
                     help="time the ten-year block length (N_f = 87,600) alone")
     ap.add_argument("--hourly-only", action="store_true",
@@ -844,6 +849,10 @@ def main(argv=None):
         log("hourly workload (N_f = 8760)")
         result["hourly"] = bench_hourly(base_prec)
         log(f"hourly {result['hourly']}")
+    if not a.no_ten_year:
+        log("ten-year blocks (N_f = 87,600)")
+        result["ten_year"] = bench_ten_year(base_prec)
+        log(f"ten-year {result['ten_year']}")
     if not a.no_diff:
         log("differentiation workload")
         result["differentiation"] = bench_differentiation(max(3, a.steps // 2), 1)
