@@ -55,6 +55,21 @@ __device__ __forceinline__ void lds_barrier() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
+// W_N^t from two tables in LDS, t = 64 a + b: hi[a] = W_N^{64 a} and
+// lo[b] = W_N^b, so one complex product (a rounding of the working precision)
+// replaces a load from the N-entry table in global memory.  Stages that read
+// their twiddles this way wait on no global memory operation, so the stores of
+// the previous block stay in flight under them.
+template <typename TC>
+struct TwSplit {
+  const cpx_t<TC>* hi;
+  const cpx_t<TC>* lo;
+  __device__ __forceinline__ cpx_t<TC> operator[](int t) const {
+    const cpx_t<TC> a = hi[t >> 6], b = lo[t & 63];
+    return mk<TC>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  }
+};
+
 // Quotient and remainder of a / d for 0 <= a < 2^24 and 1 <= d, from the
 // precomputed float reciprocal inv = 1/d: the product is within one of the
 // true quotient, and one correction step makes it exact.
@@ -76,10 +91,10 @@ __device__ __forceinline__ DivMod divmod(int a, int d, float inv) {
 
 // One output of an even-radix stage: y[o] = W_n^{p k} sum_j x[q + s(p + j m)] W_r^{j k}
 // (four independent partial sums, t = j k mod r).
-template <typename TC>
+template <typename TC, typename TW>
 __device__ __forceinline__ cpx_t<TC> even_output(const cpx_t<TC>* __restrict__ X,
                                                  const cpx_t<TC>* __restrict__ Wr,
-                                                 const cpx_t<TC>* __restrict__ tw, int o, int r,
+                                                 const TW tw, int o, int r,
                                                  int s, int m, int wn, int N, float inv_s,
                                                  float inv_r) {
   using C = cpx_t<TC>;
@@ -118,10 +133,10 @@ __device__ __forceinline__ cpx_t<TC> even_output(const cpx_t<TC>* __restrict__ X
 // A = sum_{j <= (r-1)/2} a_j c and B = sum b_j s:  y_k = x_0 + A - i B,
 // y_{r-k} = x_0 + A + i B (then W_n^{p k}, W_n^{p(r-k)}).  kk = it / NB in
 // [0, (r-1)/2]; consecutive items are consecutive butterflies.
-template <typename TC>
+template <typename TC, typename TW>
 __device__ __forceinline__ void odd_pair(const cpx_t<TC>* __restrict__ X,
                                          const cpx_t<TC>* __restrict__ Wr,
-                                         const cpx_t<TC>* __restrict__ tw, int it, int NB, int r,
+                                         const TW tw, int it, int NB, int r,
                                          int s, int m, int wn, int N, cpx_t<TC>& y0,
                                          cpx_t<TC>& y1, int& o0, int& o1) {
   using C = cpx_t<TC>;
@@ -155,9 +170,9 @@ __device__ __forceinline__ void odd_pair(const cpx_t<TC>* __restrict__ X,
 // One butterfly of a radix-2, 4 or 8 stage: the RS inputs x[q + s(p + j m)]
 // through the in-register DFT, output k times W_n^{p k}, stored at
 // y[q + s(RS p + k)].
-template <int RS, typename TC>
+template <int RS, typename TC, typename TW>
 __device__ __forceinline__ void even_butterfly(const cpx_t<TC>* __restrict__ X,
-                                               const cpx_t<TC>* __restrict__ tw,
+                                               const TW tw,
                                                cpx_t<TC>* __restrict__ Y, int bf, int s, int m,
                                                int wn, int N, float inv_s) {
   using C = cpx_t<TC>;
@@ -189,10 +204,10 @@ __device__ __forceinline__ void even_butterfly(const cpx_t<TC>* __restrict__ X,
 // wave-uniform addresses, into scalar registers, with no index arithmetic.
 // Pairs with k_c >= h = (r + 1) / 2 use the last pair's values and store
 // nothing.
-template <int KPT, typename TC>
+template <int KPT, typename TC, typename TW>
 __device__ __forceinline__ void odd_uniform(const cpx_t<TC>* __restrict__ X,
                                             const cpx_t<TC>* __restrict__ Tg,
-                                            const cpx_t<TC>* __restrict__ tw,
+                                            const TW tw,
                                             cpx_t<TC>* __restrict__ Y, int bf, int g, int G, int r,
                                             int s, int m, int wn, float inv_s) {
   using C = cpx_t<TC>;
@@ -239,10 +254,10 @@ __device__ __forceinline__ void odd_uniform(const cpx_t<TC>* __restrict__ X,
 
 // An odd stage of the two-buffer kernel: work items (g, bf) with bf padded to
 // NBp, a multiple of 64, so every wavefront has one g.
-template <int KPT, typename TC>
+template <int KPT, typename TC, typename TW>
 __device__ __forceinline__ void odd_stage(const cpx_t<TC>* __restrict__ X,
                                           const cpx_t<TC>* __restrict__ T,
-                                          const cpx_t<TC>* __restrict__ tw,
+                                          const TW tw,
                                           cpx_t<TC>* __restrict__ Y, int tid, int NB, int r, int s,
                                           int m, int wn) {
   const int h = (r + 1) / 2, hm = h - 1, G = (h + KPT - 1) / KPT;
@@ -258,10 +273,10 @@ __device__ __forceinline__ void odd_stage(const cpx_t<TC>* __restrict__ X,
 }
 
 // One stage of the two-buffer kernel, X -> Y (W_n^{p k} = tw[wn p k], wn = N / n).
-template <typename TC>
+template <typename TC, typename TW>
 __device__ __forceinline__ void pp_stage(const cpx_t<TC>* __restrict__ X,
                                          cpx_t<TC>* __restrict__ Y,
-                                         const cpx_t<TC>* __restrict__ tw,
+                                         const TW tw,
                                          const cpx_t<TC>* __restrict__ Wr,
                                          const cpx_t<TC>* __restrict__ oddw, const Radices& rad,
                                          int st, int tid, int N, int r, int s, int m, int wn) {
@@ -295,10 +310,10 @@ __device__ __forceinline__ void pp_stage(const cpx_t<TC>* __restrict__ X,
 // The stages of the transform on X (in LDS, natural order in and out); with
 // PP the stages alternate between X and Y.  Returns the buffer that holds the
 // result.  The caller has synchronised the workgroup after writing X.
-template <typename TC, bool PP, int MAXU, int MAXI>
+template <typename TC, bool PP, int MAXU, int MAXI, typename TW>
 __device__ __forceinline__ cpx_t<TC>* dft_stages(cpx_t<TC>* X, cpx_t<TC>* Y,
                                                  const cpx_t<TC>* __restrict__ Wt,
-                                                 const cpx_t<TC>* __restrict__ tw,
+                                                 const TW tw,
                                                  const cpx_t<TC>* __restrict__ oddw,
                                                  const Radices& rad, int tid, int N) {
   using C = cpx_t<TC>;
@@ -385,24 +400,31 @@ __global__ __launch_bounds__(GEN_THREADS) void blocks_dft_general_kernel(
   const bool two = m0 + 1 < M;
   const int tid = threadIdx.x;
 
-  {
-    int off = 0;
-    for (int st = 0; st < rad.n; ++st) {
-      const int r = rad.r[st];
-      for (int t = tid; t < r; t += GEN_THREADS) Wt[off + t] = tw[(N / r) * t];
-      off += r;
-    }
+  int woff = 0;
+  for (int st = 0; st < rad.n; ++st) {
+    const int r = rad.r[st];
+    for (int t = tid; t < r; t += GEN_THREADS) Wt[woff + t] = tw[(N / r) * t];
+    woff += r;
+  }
+  // PP: W_N^t as the product of two short tables after the per-stage ones
+  C* const Th = Wt + woff;
+  C* const Tl = Th + ((N + 63) >> 6);
+  if constexpr (PP) {
+    for (int a = tid; 64 * a < N; a += GEN_THREADS) Th[a] = tw[64 * a];
+    for (int b = tid; b < 64 && b < N; b += GEN_THREADS) Tl[b] = tw[b];
   }
   const double mu0 = mean[m0], mu1 = two ? mean[m0 + 1] : 0.0;
   const TIN* r0 = q + m0 * nt;
   const TIN* r1 = q + (two ? m0 + 1 : m0) * nt;
   TIN pa[MAXR], pb[MAXR];                      // the next block's samples (PP)
+  double wr[MAXR];                             // this thread's window samples (PP)
   if constexpr (PP) {
 #pragma unroll
     for (int u = 0; u < MAXR; ++u) {
       const int n = tid + u * GEN_THREADS;
       pa[u] = n < N ? r0[n] : (TIN)0;
       pb[u] = n < N ? r1[n] : (TIN)0;
+      wr[u] = n < N ? window[n] : 0.0;
     }
   }
   const TC h = (TC)0.5 * kappa;
@@ -417,7 +439,7 @@ __global__ __launch_bounds__(GEN_THREADS) void blocks_dft_general_kernel(
       for (int u = 0; u < MAXR; ++u) {
         const int n = tid + u * GEN_THREADS;
         if (n < N) {
-          const double w = window[n];
+          const double w = wr[u];
           X[n] = mk<TC>((TC)(((double)pa[u] - mu0) * w),
                         (TC)(two ? ((double)pb[u] - mu1) * w : 0.0));
         }
@@ -443,7 +465,18 @@ __global__ __launch_bounds__(GEN_THREADS) void blocks_dft_general_kernel(
     if constexpr (PP) lds_barrier();
     else __syncthreads();
 
-    X = dft_stages<TC, PP, MAXU, MAXI>(X, Y, Wt, tw, oddw, rad, tid, N);
+    if constexpr (PP) {
+      X = dft_stages<TC, PP, MAXU, MAXI>(X, Y, Wt, TwSplit<TC>{Th, Tl}, oddw, rad, tid, N);
+      // an empty asm that reads the next block's samples takes the wait for
+      // them (and for this thread's earlier stores) here, after the stages,
+      // so the stores of the previous block drain under the window and stages
+      if (l + 1 < L) {
+#pragma unroll
+        for (int u = 0; u < MAXR; ++u) asm volatile("" ::"v"(pa[u]), "v"(pb[u]));
+      }
+    } else {
+      X = dft_stages<TC, PP, MAXU, MAXI>(X, Y, Wt, tw, oddw, rad, tid, N);
+    }
 
     // two-for-one split: A = (Z_k + conj Z_{N-k}) / 2, C = (Z_k - conj Z_{N-k}) / 2i
     const C* Z = X;
@@ -496,7 +529,8 @@ spod_status launch_general_t(const Plan& p, const TIN* q, const double* mean, vo
   int sum_r = 0;
   for (int i = 0; i < p.radices.n; ++i) sum_r += p.radices.r[i];
   constexpr size_t LDS_MAX = 160 * 1024;
-  const size_t two_buf = sizeof(C) * (2 * (size_t)p.nfft + (size_t)sum_r);
+  const size_t two_buf =
+      sizeof(C) * (2 * (size_t)p.nfft + (size_t)sum_r + ((size_t)p.nfft + 63) / 64 + 64);
   // two buffers: complex64 N <= ~10200, complex128 <= ~5100, so at most
   // ceil(10240 / 1024) samples per thread and row to prefetch
   if (two_buf <= LDS_MAX)
