@@ -25,15 +25,51 @@ namespace spod {
 // ---------------------------------------------------------------------------
 // temporal mean, accumulated in FP64: one 64-lane wavefront per row
 // ---------------------------------------------------------------------------
+// A 16-byte-aligned row is read as 16-byte non-temporal vectors, four per
+// lane in flight, into four FP64 partial sums (the row is read once here and once
+// more by the transform, far beyond any cache); the rest of the row, or a
+// whole unaligned row, element by element.
 template <typename TIN>
 __global__ __launch_bounds__(256) void mean_kernel(const TIN* __restrict__ q, double* __restrict__ mean,
                                                    int64_t M, int64_t nt) {
+  typedef TIN vec_t __attribute__((ext_vector_type(16 / sizeof(TIN))));
+  constexpr int V = 16 / (int)sizeof(TIN);
   const int lane = threadIdx.x & 63;
   const int64_t m = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (m >= M) return;
   const TIN* row = q + m * nt;
-  double s = 0.0;
-  for (int64_t t = lane; t < nt; t += 64) s += (double)row[t];
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int64_t t0 = 0;
+  if ((reinterpret_cast<uintptr_t>(row) & 15) == 0) {   // the same for the whole wavefront
+    const vec_t* rv = reinterpret_cast<const vec_t*>(row);
+    const int64_t nv = nt / V;
+    int64_t i = lane;
+    for (; i + 192 < nv; i += 256) {
+      vec_t a[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u] = __builtin_nontemporal_load(rv + i + 64 * u);
+#pragma unroll
+      for (int u = 0; u < 4; u += 2)
+#pragma unroll
+        for (int e = 0; e < V; e += 2) {
+          s0 += (double)a[u][e];
+          s1 += (double)a[u][e + 1];
+          s2 += (double)a[u + 1][e];
+          s3 += (double)a[u + 1][e + 1];
+        }
+    }
+    for (; i < nv; i += 64) {
+      const vec_t a = __builtin_nontemporal_load(rv + i);
+#pragma unroll
+      for (int e = 0; e < V; e += 2) {
+        s0 += (double)a[e];
+        s1 += (double)a[e + 1];
+      }
+    }
+    t0 = nv * V;
+  }
+  for (int64_t t = t0 + lane; t < nt; t += 64) s0 += (double)row[t];
+  double s = (s0 + s1) + (s2 + s3);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
   if (lane == 0) mean[m] = s / (double)nt;
