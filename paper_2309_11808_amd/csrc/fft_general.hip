@@ -823,26 +823,34 @@ __global__ __launch_bounds__(GEN_THREADS) void blocks_dft_long_kernel(
   const int tid = threadIdx.x;
   const TC h = (TC)0.5;
   const bool aligned = (M % 2 == 0);
+  // quotients by the batch shapes through float reciprocals (every dividend
+  // here is below 2^24: a batch holds at most 160 KiB of LDS)
+  const float inv_b = 1.0f / (float)B;
   for (int64_t item = blockIdx.x; item < ntile * L; item += gridDim.x) {
     const int64_t tile = item / L;
     const int l = (int)(item - tile * L);
     const int64_t pair0 = tile * P;
     const int np = (int)min((int64_t)P, npair - pair0);
+    const float inv_np = 1.0f / (float)np;
 
     // pass 1: sequences s = p B + c of length A, GA per batch
     for (int s0 = 0; s0 < np * B; s0 += GA) {
       const int gs = min(GA, np * B - s0);
+      const float inv_gs = 1.0f / (float)gs;
       // LONG_U loads per thread in flight, then their LDS writes
       for (int i0 = tid; i0 < gs * A; i0 += LONG_U * GEN_THREADS) {
         TIN va[LONG_U], vc[LONG_U];
         double vw[LONG_U], mu[LONG_U], mc[LONG_U];
         bool tw2[LONG_U];
+        int dst[LONG_U];
 #pragma unroll
         for (int u = 0; u < LONG_U; ++u) {
           const int idx = i0 + u * GEN_THREADS;
           if (idx < gs * A) {
-            const int j = idx / gs, g = idx - j * gs;      // g fastest: consecutive samples
-            const int sq = s0 + g, pp = sq / B, c = sq - pp * B;
+            const DivMod jg = divmod(idx, gs, inv_gs);     // g fastest: consecutive samples
+            const int j = jg.q, g = jg.r;
+            const DivMod pc = divmod(s0 + g, B, inv_b);
+            const int pp = pc.q, c = pc.r;
             const int64_t m0 = 2 * (pair0 + pp);
             const bool two = m0 + 1 < M;
             const int64_t n = (int64_t)l * step + B * j + c;
@@ -852,24 +860,26 @@ __global__ __launch_bounds__(GEN_THREADS) void blocks_dft_long_kernel(
             mu[u] = mean[m0];
             mc[u] = two ? mean[m0 + 1] : 0.0;
             tw2[u] = two;
+            dst[u] = g * A + j;
           }
         }
 #pragma unroll
         for (int u = 0; u < LONG_U; ++u) {
           const int idx = i0 + u * GEN_THREADS;
           if (idx < gs * A) {
-            const int j = idx / gs, g = idx - j * gs;
             const double w = vw[u] * kappa;
-            B0[g * A + j] = mk<TC>((TC)(((double)va[u] - mu[u]) * w),
-                                   (TC)(tw2[u] ? ((double)vc[u] - mc[u]) * w : 0.0));
+            B0[dst[u]] = mk<TC>((TC)(((double)va[u] - mu[u]) * w),
+                                (TC)(tw2[u] ? ((double)vc[u] - mc[u]) * w : 0.0));
           }
         }
       }
       __syncthreads();
       const C* R = dft_batched<TC>(B0, B1, tw_a, oddw_a, rad_a, tid, A, gs);
       for (int idx = tid; idx < gs * A; idx += GEN_THREADS) {
-        const int k1 = idx / gs, g = idx - k1 * gs;
-        const int sq = s0 + g, pp = sq / B, c = sq - pp * B;
+        const DivMod kg = divmod(idx, gs, inv_gs);
+        const int k1 = kg.q, g = kg.r;
+        const DivMod pc = divmod(s0 + g, B, inv_b);
+        const int pp = pc.q, c = pc.r;
         const C v = R[g * A + k1];
         const C t = tw_n[c * k1];                            // c k1 < N
         Yg[(size_t)pp * N + (size_t)k1 * B + c] = mk<TC>(v.x * t.x - v.y * t.y, v.x * t.y + v.y * t.x);
@@ -890,10 +900,12 @@ __global__ __launch_bounds__(GEN_THREADS) void blocks_dft_long_kernel(
         for (int v = 0; v < LONG_U; ++v) {
           const int idx = i0 + v * GEN_THREADS;
           if (idx < nseq * B) {
-            const int sq = idx / B, c = idx - sq * B;
-            const int slot = sq / np, pp = sq - slot * np;
+            const DivMod sc = divmod(idx, B, inv_b);
+            const int sq = sc.q, c = sc.r;
+            const DivMod sp = divmod(sq, np, inv_np);
+            const int slot = sp.q, pp = sp.r;
             const int u = u0 + (slot >> 1);
-            const int row = (slot & 1) ? (A - u) % A : u;
+            const int row = ((slot & 1) && u > 0) ? A - u : u;    // (A - u) mod A
             vy[v] = Yg[(size_t)pp * N + (size_t)row * B + c];
           }
         }
@@ -908,8 +920,10 @@ __global__ __launch_bounds__(GEN_THREADS) void blocks_dft_long_kernel(
       // split and store: pairs fastest, so neighbouring lanes write one
       // frequency row's consecutive DOFs
       for (int idx = tid; idx < 2 * nu * B * np; idx += GEN_THREADS) {
-        const int pp = idx % np, rest = idx / np;
-        const int k2 = rest % B, slot = rest / B;
+        const DivMod rp = divmod(idx, np, inv_np);
+        const int pp = rp.r, rest = rp.q;
+        const DivMod sk = divmod(rest, B, inv_b);
+        const int k2 = sk.r, slot = sk.q;
         const int u = u0 + (slot >> 1);
         const bool second = slot & 1;
         if (second && (u == 0 || 2 * u == A)) continue;     // the same row as slot 2i
@@ -920,7 +934,7 @@ __global__ __launch_bounds__(GEN_THREADS) void blocks_dft_long_kernel(
         // slot for u = 0 and u = A/2), column (B - k2) mod B for k1 = 0, else
         // B - 1 - k2
         const int pslot = (u == 0 || 2 * u == A) ? slot : (slot ^ 1);
-        const int pk2 = (k1 == 0) ? (B - k2) % B : B - 1 - k2;
+        const int pk2 = (k1 == 0) ? (k2 == 0 ? 0 : B - k2) : B - 1 - k2;
         const C z = R[(slot * np + pp) * B + k2], zc = R[(pslot * np + pp) * B + pk2];
         const C a = mk<TC>(h * (z.x + zc.x), h * (z.y - zc.y));
         const C cc = mk<TC>(h * (z.y + zc.y), h * (zc.x - z.x));
