@@ -25,6 +25,8 @@
 // degrees of freedom meet in that XCD's L2.
 #include <hip/hip_runtime.h>
 
+#include <numeric>
+
 #include <algorithm>
 
 #include "fft_core.h"
@@ -979,6 +981,17 @@ LongShape long_shape(const Plan& p) {
   if (P < 1 || cap / A < 1) return sh;
   sh.P = P;
   sh.GA = (int)std::min<int64_t>((int64_t)P * B, cap / A);
+  // an odd stage pads the butterflies of a batch to whole wavefronts: a batch
+  // of GA sequences with GA (A / r) a multiple of 64 for every odd radix r of
+  // A idles none of its lanes (A = 292 = 4 73: 32 sequences of 4 butterflies
+  // instead of 35, whose 140 fill 192 lanes)
+  int align = 1;
+  for (int i = 0; i < p.rad_a.n; ++i) {
+    const int r = p.rad_a.r[i];
+    if (r % 2 == 0) continue;
+    align = std::lcm(align, 64 / std::gcd(64, A / r));
+  }
+  if (align <= sh.GA) sh.GA -= sh.GA % align;
   sh.NU = (int)std::max<int64_t>(1, cap / B / (2 * P));
   sh.lds = 2 * csz * (size_t)std::max<int64_t>((int64_t)sh.GA * A, 2LL * sh.NU * P * B);
   sh.scratch = csz * (size_t)grid * (size_t)P * (size_t)p.nfft;
