@@ -811,14 +811,21 @@ __global__ __launch_bounds__(GEN_THREADS) void blocks_dft_long_kernel(
     const cpx_t<TC>* __restrict__ tw_n, const cpx_t<TC>* __restrict__ tw_a,
     const cpx_t<TC>* __restrict__ oddw_a, Radices rad_a, const cpx_t<TC>* __restrict__ tw_b,
     const cpx_t<TC>* __restrict__ oddw_b, Radices rad_b, int A, int B, int GA, int NU, int P,
-    cpx_t<TC>* __restrict__ scratch, cpx_t<TC>* __restrict__ qhat, int64_t M, int64_t nt, int step,
-    int L, int K, double kappa) {
+    int SB, cpx_t<TC>* __restrict__ scratch, cpx_t<TC>* __restrict__ qhat, int64_t M, int64_t nt,
+    int step, int L, int K, double kappa) {
   using C = cpx_t<TC>;
   extern __shared__ unsigned char smem[];
   const int N = A * B;
   const int cap = max(GA * A, 2 * NU * P * B);
   C* const B0 = reinterpret_cast<C*>(smem);
   C* const B1 = B0 + cap;
+  // W_N^t = hi[t / SB] lo[t % SB] (SB about sqrt N): the pass-1 twiddles from
+  // LDS instead of a gather from the N-entry table
+  C* const Thi = B1 + cap;
+  C* const Tlo = Thi + (N + SB - 1) / SB;
+  for (int a = (int)threadIdx.x; a * SB < N; a += GEN_THREADS) Thi[a] = tw_n[a * SB];
+  for (int b = (int)threadIdx.x; b < SB; b += GEN_THREADS) Tlo[b] = tw_n[b];
+  const float inv_sb = 1.0f / (float)SB;
   C* const Yg = scratch + (size_t)blockIdx.x * P * N;       // [P][A][B]
   const int64_t npair = (M + 1) / 2;
   const int64_t ntile = (npair + P - 1) / P;
@@ -883,7 +890,9 @@ __global__ __launch_bounds__(GEN_THREADS) void blocks_dft_long_kernel(
         const DivMod pc = divmod(s0 + g, B, inv_b);
         const int pp = pc.q, c = pc.r;
         const C v = R[g * A + k1];
-        const C t = tw_n[c * k1];                            // c k1 < N
+        const DivMod tt = divmod(c * k1, SB, inv_sb);         // c k1 < N
+        const C th = Thi[tt.q], tl = Tlo[tt.r];
+        const C t = mk<TC>(th.x * tl.x - th.y * tl.y, th.x * tl.y + th.y * tl.x);
         Yg[(size_t)pp * N + (size_t)k1 * B + c] = mk<TC>(v.x * t.x - v.y * t.y, v.x * t.y + v.y * t.x);
       }
       // Y written (global, this workgroup only) and the LDS free again
@@ -966,14 +975,19 @@ constexpr int LONG_WG_PER_CU = 1;
 // the pass-2 batch or the scratch, at most 2 GiB, does not allow it), GA
 // sequences per pass-1 batch, NU units per pass-2 batch.
 struct LongShape {
-  int P = 0, GA = 0, NU = 0;
+  int P = 0, GA = 0, NU = 0, SB = 0;
   size_t lds = 0, scratch = 0;
 };
 
 LongShape long_shape(const Plan& p) {
   LongShape sh;
   const size_t csz = is_complex128(p) ? 16 : 8;
-  const int64_t cap = (int64_t)(160 * 1024 / LONG_WG_PER_CU / 2 / csz);   // elements per buffer
+  // the split twiddle table W_N^{SB a}, W_N^b (SB = ceil(sqrt N)) after the two buffers
+  int sb = 1;
+  while ((int64_t)sb * sb < p.nfft) ++sb;
+  const int64_t ntab = (p.nfft + sb - 1) / sb + sb;
+  const int64_t cap =
+      (int64_t)(160 * 1024 / LONG_WG_PER_CU - ntab * (int64_t)csz) / 2 / (int64_t)csz;   // per buffer
   const int A = p.long_a, B = p.long_b;
   const int64_t grid = (int64_t)p.long_grid * LONG_WG_PER_CU;
   int P = (int)std::min<int64_t>(8, cap / B / 2);
@@ -993,7 +1007,8 @@ LongShape long_shape(const Plan& p) {
   }
   if (align <= sh.GA) sh.GA -= sh.GA % align;
   sh.NU = (int)std::max<int64_t>(1, cap / B / (2 * P));
-  sh.lds = 2 * csz * (size_t)std::max<int64_t>((int64_t)sh.GA * A, 2LL * sh.NU * P * B);
+  sh.SB = sb;
+  sh.lds = csz * (2 * (size_t)std::max<int64_t>((int64_t)sh.GA * A, 2LL * sh.NU * P * B) + (size_t)ntab);
   sh.scratch = csz * (size_t)grid * (size_t)P * (size_t)p.nfft;
   return sh;
 }
@@ -1016,7 +1031,7 @@ spod_status launch_long_t(const Plan& p, const TIN* q, const double* mean, void*
                      p.rad_a,
                      static_cast<const C*>(c8 ? (const void*)p.d_tw_b64 : (const void*)p.d_tw_b32),
                      static_cast<const C*>(c8 ? (const void*)p.d_oddw_b64 : (const void*)p.d_oddw_b32),
-                     p.rad_b, p.long_a, p.long_b, sh.GA, sh.NU, sh.P, static_cast<C*>(scratch),
+                     p.rad_b, p.long_a, p.long_b, sh.GA, sh.NU, sh.P, sh.SB, static_cast<C*>(scratch),
                      static_cast<C*>(qhat), (int64_t)p.M, (int64_t)p.nt, (int)p.step, (int)p.nblocks,
                      (int)p.nfreq, p.kappa);
   e = hipGetLastError();
