@@ -826,6 +826,11 @@ __global__ __launch_bounds__(GEN_THREADS) void blocks_dft_long_kernel(
   for (int a = (int)threadIdx.x; a * SB < N; a += GEN_THREADS) Thi[a] = tw_n[a * SB];
   for (int b = (int)threadIdx.x; b < SB; b += GEN_THREADS) Tlo[b] = tw_n[b];
   const float inv_sb = 1.0f / (float)SB;
+  // the stages' W_A^t and W_B^t tables, also in LDS
+  C* const Ta = Tlo + SB;
+  C* const Tb = Ta + A;
+  for (int t = (int)threadIdx.x; t < A; t += GEN_THREADS) Ta[t] = tw_a[t];
+  for (int t = (int)threadIdx.x; t < B; t += GEN_THREADS) Tb[t] = tw_b[t];
   C* const Yg = scratch + (size_t)blockIdx.x * P * N;       // [P][A][B]
   const int64_t npair = (M + 1) / 2;
   const int64_t ntile = (npair + P - 1) / P;
@@ -883,7 +888,7 @@ __global__ __launch_bounds__(GEN_THREADS) void blocks_dft_long_kernel(
         }
       }
       __syncthreads();
-      const C* R = dft_batched<TC>(B0, B1, tw_a, oddw_a, rad_a, tid, A, gs);
+      const C* R = dft_batched<TC>(B0, B1, Ta, oddw_a, rad_a, tid, A, gs);
       for (int idx = tid; idx < gs * A; idx += GEN_THREADS) {
         const DivMod kg = divmod(idx, gs, inv_gs);
         const int k1 = kg.q, g = kg.r;
@@ -927,7 +932,7 @@ __global__ __launch_bounds__(GEN_THREADS) void blocks_dft_long_kernel(
         }
       }
       __syncthreads();
-      const C* R = dft_batched<TC>(B0, B1, tw_b, oddw_b, rad_b, tid, B, nseq);
+      const C* R = dft_batched<TC>(B0, B1, Tb, oddw_b, rad_b, tid, B, nseq);
       // split and store: pairs fastest, so neighbouring lanes write one
       // frequency row's consecutive DOFs
       for (int idx = tid; idx < 2 * nu * B * np; idx += GEN_THREADS) {
@@ -982,10 +987,11 @@ struct LongShape {
 LongShape long_shape(const Plan& p) {
   LongShape sh;
   const size_t csz = is_complex128(p) ? 16 : 8;
-  // the split twiddle table W_N^{SB a}, W_N^b (SB = ceil(sqrt N)) after the two buffers
+  // after the two buffers: the split twiddle table W_N^{SB a}, W_N^b (SB =
+  // ceil(sqrt N)) and the stages' W_A^t, W_B^t
   int sb = 1;
   while ((int64_t)sb * sb < p.nfft) ++sb;
-  const int64_t ntab = (p.nfft + sb - 1) / sb + sb;
+  const int64_t ntab = (p.nfft + sb - 1) / sb + sb + p.long_a + p.long_b;
   const int64_t cap =
       (int64_t)(160 * 1024 / LONG_WG_PER_CU - ntab * (int64_t)csz) / 2 / (int64_t)csz;   // per buffer
   const int A = p.long_a, B = p.long_b;
