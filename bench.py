@@ -252,8 +252,9 @@ def cpu_baseline(p, precisions, seconds_target=20.0, single_thread=True):
     freedom of the workload (S sized for about `seconds_target` of work).  The
     same sample then runs through the HIP path in every precision form, and
     its eigenvalues (every bin) and modes (8 bins) are compared with the
-    oracle's.  With single_thread, the parity configurations 1 (whole) and 2
-    (a sample) are also timed with one BLAS thread, as the paper's ranks ran."""
+    oracle's.  With single_thread, the planted 32 x 32 field (whole) and the
+    jet-like field (a sample) are also timed with one BLAS thread, as the
+    paper's ranks ran."""
     import numpy as np
     import torch
     import oracle as O
@@ -320,8 +321,9 @@ def cpu_baseline(p, precisions, seconds_target=20.0, single_thread=True):
 
 
 def single_thread_baseline():
-    """The oracle with one BLAS thread on the parity workloads (configuration
-    1 whole; configuration 2 on its first 2048 degrees of freedom)."""
+    """The oracle with one BLAS thread on two smaller workloads: the planted
+    32 x 32 field whole, and the jet-like 256 x 128 x 3 field on its first 2048
+    degrees of freedom."""
     import numpy as np
     import torch
     import oracle as O
@@ -336,19 +338,19 @@ def single_thread_baseline():
         q1 = p1.q.numpy()
         _, sec = _oracle_stages(O, q1, p1.nfft, p1.noverlap, p1.weights)
         nb = q1.size * 8
-        res["config1"] = {"workload": "planted 32x32, nt=1024 float64, nfft=128 (15 blocks)",
-                          "stages_s": {k: round(v, 4) for k, v in sec.items()},
-                          "value_GBps": round(nb / sum(sec.values()) / 1e9, 5)}
+        res["planted_32x32"] = {"workload": "planted 32x32, nt=1024 float64, nfft=128 (15 blocks)",
+                                "stages_s": {k: round(v, 4) for k, v in sec.items()},
+                                "value_GBps": round(nb / sum(sec.values()) / 1e9, 5)}
         p2 = fields.jet_like(seed=2, device="cuda", dtype=torch.float32)
         S = 2048
         q2 = p2.q[:S].cpu().numpy()
         w2 = p2.weights[:S]
         _, sec = _oracle_stages(O, q2, p2.nfft, p2.noverlap, w2)
         nb = q2.size * 4
-        res["config2_sample"] = {"workload": f"jet-like 256x128x3, nt=4096 float32, nfft=256 "
-                                             f"(31 blocks), first {S} of {p2.M} degrees of freedom",
-                                 "stages_s": {k: round(v, 4) for k, v in sec.items()},
-                                 "value_GBps": round(nb / sum(sec.values()) / 1e9, 5)}
+        res["jet_256x128x3_sample"] = {"workload": f"jet-like 256x128x3, nt=4096 float32, nfft=256 "
+                                                   f"(31 blocks), first {S} of {p2.M} degrees of freedom",
+                                       "stages_s": {k: round(v, 4) for k, v in sec.items()},
+                                       "value_GBps": round(nb / sum(sec.values()) / 1e9, 5)}
         del p2
     return res
 
