@@ -149,6 +149,17 @@ static int factor_radices(int64_t n, Radices& rad) {
       --rad.n;
     }
   }
+  // odd stages first, then the even ones (each group in its order): a first
+  // stage of radix 8 over the whole length measured slower than the same
+  // stage later (8760: 8 15 73 in 28.5 ms, 15 73 8 in 27.5 ms)
+  {
+    int rr[32], k = 0;
+    for (int i = 0; i < rad.n; ++i)
+      if (rad.r[i] % 2 == 1) rr[k++] = rad.r[i];
+    for (int i = 0; i < rad.n; ++i)
+      if (rad.r[i] % 2 == 0) rr[k++] = rad.r[i];
+    for (int i = 0; i < rad.n; ++i) rad.r[i] = rr[i];
+  }
   int odd_entries = 0;
   for (int i = 0; i < rad.n; ++i) {
     const int r = rad.r[i];
