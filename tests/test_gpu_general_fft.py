@@ -4,7 +4,10 @@ the FP64 oracle (whose DFT is pinned to numpy's rfft for any length).
 
 Lengths cover small primes, a large prime factor (73, as in the paper's
 8760 = 2^3 3 5 73 hourly blocks), odd N_f (K = (N_f + 1) / 2), powers of two
-above 1024, ragged M (odd: a last unpaired row) and several overlaps.  Odd
+above 1024, ragged M (odd: a last unpaired row) and several overlaps.  The
+plan merges a 3 with a 5 into one radix-15 stage and two 3s into a radix-9
+stage, and runs the odd stages first: 60 = 15 4, 360 = 15 3 8, 504 = 9 7 8
+and 675 = 15 15 3 take those paths.  Odd
 radices take 1 to 6 output pairs per work item, with W_r^{jk} from the plan's
 per-stage table (1001 = 7 11 13, 527 = 17 31 and the prime 1019 reach several
 counts, with table rows beyond (r + 1) / 2 pairs that store nothing)."""
@@ -36,8 +39,9 @@ CASES = [  # nfft, noverlap, M, L
     (12, 6, 37, 6), (24, 12, 64, 5), (60, 30, 101, 4), (73, 0, 50, 3), (100, 50, 33, 4),
     (146, 73, 20, 3), (360, 180, 17, 3), (2048, 1024, 9, 3), (730, 365, 12, 3),
     (1001, 500, 15, 3), (527, 263, 19, 3), (1019, 509, 11, 3),
+    (504, 252, 23, 3), (675, 300, 10, 3),
 ]
-C64_CASES = CASES[:5] + CASES[-3:] + [(8760, 4380, 7, 2)]
+C64_CASES = CASES[:5] + CASES[-5:] + [(8760, 4380, 7, 2)]
 
 
 @pytest.mark.parametrize("nfft,nov,M,L", CASES, ids=[f"N{c[0]}" for c in CASES])
