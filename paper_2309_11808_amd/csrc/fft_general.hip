@@ -533,8 +533,9 @@ spod_status launch_general_t(const Plan& p, const TIN* q, const double* mean, vo
   constexpr size_t LDS_MAX = 160 * 1024;
   const size_t two_buf =
       sizeof(C) * (2 * (size_t)p.nfft + (size_t)sum_r + ((size_t)p.nfft + 63) / 64 + 64);
-  // two buffers: complex64 N <= ~10200, complex128 <= ~5100, so at most
-  // ceil(10240 / 1024) samples per thread and row to prefetch
+  // two buffers and the twiddle tables: complex64 N <= ~10080, complex128
+  // <= ~5000, so at most ceil(10240 / 1024) samples per thread and row to
+  // prefetch
   if (two_buf <= LDS_MAX)
     return launch_general_pp<TC, TIN, true, (sizeof(C) == 8 ? 10 : 5)>(p, q, mean, qhat, two_buf, st);
   const size_t one_buf = sizeof(C) * ((size_t)p.nfft + (size_t)sum_r);

@@ -107,7 +107,7 @@ def test_general_transform_limits():
     with pytest.raises(SpodError) as ei:
         Plan(4, 1, 3 * 20483, 20483, 0)
     assert ei.value.status == -2
-    plan = _plan(p, "fp32")                     # complex64 blocks: one LDS buffer above ~10200
+    plan = _plan(p, "fp32")                     # complex64 blocks: one LDS buffer above ~10080
     q32 = p.q.float()
     qhat, _ = plan.blocks_fft(q32.cuda())
     torch.cuda.synchronize()
